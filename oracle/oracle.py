@@ -1,0 +1,175 @@
+"""ctypes wrapper of the CPU oracle (``orc_mg.c``).
+
+TEST INFRASTRUCTURE ONLY.  The oracle is the plain double-precision CPU
+reference of the diagonally oriented multigrid V-cycle (Roberts, Sections 1-3)
+that the GPU library is checked against.  Only ``tests/``, the smoke check and
+the CPU-baseline leg of the benchmark import this module; the GPU package never
+does, and the two share no code.
+
+Arrays are numpy float64 in natural order, shape ``(n+1, n+1)`` or
+``(n+1, n+1, n+1)`` indexed ``[y, x]`` / ``[z, y, x]`` (x fastest), zero
+Dirichlet boundary.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liborc.so")
+_lib = None
+
+OK, ERR_ARG, ERR_SIZE, ERR_ALLOC, ERR_NONFINITE, ERR_DIVERGED, ERR_NOT_CONVERGED = 0, -1, -2, -4, -6, -7, -8
+
+# over-relaxation parameters the paper tunes: 2D p (Section 2.5, Table tbl:2d);
+# 3D (p_m, p_r1, p_r2, p_g) (Section 3.5, Table tbl:3dopt)
+P2D_TUNED = (1.052,)
+P3D_TUNED = (1.11, 1.42, 1.08, 0.99)
+
+
+def build(force=True):
+    """Compile ``liborc.so`` with gcc (plain -O2, no FP contraction)."""
+    src = os.path.join(_HERE, "orc_mg.c")
+    if not force and os.path.exists(_SO) and os.path.getmtime(_SO) >= max(
+            os.path.getmtime(src), os.path.getmtime(os.path.join(_HERE, "orc_mg_body.h"))):
+        return _SO
+    tmp = _SO + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+                           "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, src, "-lm"])
+    os.replace(tmp, _SO)
+    return _SO
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build()
+        L = ctypes.CDLL(_SO)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        i, d = ctypes.c_int, ctypes.c_double
+        L.orc_residual.argtypes = [i, i, dp, dp, dp]
+        L.orc_relres.argtypes = [i, i, dp, dp, dp]
+        L.orc_vcycle.argtypes = [i, i, dp, i, dp, dp]
+        L.orc_vcycle_trace.argtypes = [i, i, dp, i, dp, dp, dp, dp]
+        L.orc_solve.argtypes = [i, i, dp, i, dp, dp, d, i, ip, dp, dp]
+        L.orc_step_restrict.argtypes = [i, i, i, dp, dp]
+        L.orc_step_jacobi.argtypes = [i, i, i, dp, dp, dp, dp]
+        for fn in ("orc_residual", "orc_relres", "orc_vcycle", "orc_vcycle_trace", "orc_solve",
+                   "orc_step_restrict", "orc_step_jacobi"):
+            getattr(L, fn).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _dimn(a):
+    return a.ndim, a.shape[0] - 1
+
+
+def _params(dim, p):
+    if p is None:
+        p = P2D_TUNED if dim == 2 else P3D_TUNED
+    p = np.ascontiguousarray(np.atleast_1d(np.asarray(p, dtype=np.float64)))
+    assert p.size == (1 if dim == 2 else 4)
+    return p
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__("%s failed with code %d" % (what, code))
+        self.code = code
+
+
+def _chk(code, what):
+    if code != OK:
+        raise OracleError(code, what)
+
+
+def level_sides(dim, n):
+    """Side m of each level's array, in depth order (finest first)."""
+    K = int(round(np.log2(n)))
+    D = (2 if dim == 2 else 3) * (K - 1)
+    return [n >> (d // dim) for d in range(D + 1)]
+
+
+def residual(u, f):
+    dim, n = _dimn(u)
+    r = np.zeros_like(u)
+    _chk(lib().orc_residual(dim, n, _ptr(u), _ptr(f), _ptr(r)), "orc_residual")
+    return r
+
+
+def relres(u, f):
+    dim, n = _dimn(u)
+    out = ctypes.c_double()
+    _chk(lib().orc_relres(dim, n, _ptr(u), _ptr(f), ctypes.byref(out)), "orc_relres")
+    return out.value
+
+
+def vcycle(u, f, p=None, prec=0):
+    """One V-cycle; returns the new u (the input is not modified)."""
+    dim, n = _dimn(u)
+    u = np.array(u, dtype=np.float64, order="C")
+    _chk(lib().orc_vcycle(dim, n, _ptr(_params(dim, p)), prec, _ptr(u), _ptr(f)), "orc_vcycle")
+    return u
+
+
+def vcycle_trace(u, f, p=None, prec=0):
+    """One V-cycle; returns (u_new, [r per level], [v per level])."""
+    dim, n = _dimn(u)
+    sides = level_sides(dim, n)
+    sizes = [(m + 1) ** dim for m in sides]
+    rt = np.zeros(sum(sizes))
+    vt = np.zeros(sum(sizes))
+    u = np.array(u, dtype=np.float64, order="C")
+    _chk(lib().orc_vcycle_trace(dim, n, _ptr(_params(dim, p)), prec, _ptr(u), _ptr(f), _ptr(rt), _ptr(vt)),
+         "orc_vcycle_trace")
+    rs, vs, off = [], [], 0
+    for m, s in zip(sides, sizes):
+        rs.append(rt[off:off + s].reshape((m + 1,) * dim))
+        vs.append(vt[off:off + s].reshape((m + 1,) * dim))
+        off += s
+    return u, rs, vs
+
+
+def solve(u, f, p=None, prec=0, rtol=1e-10, max_cycles=50, check=True):
+    """Returns (u, cycles, relres, history, status)."""
+    dim, n = _dimn(u)
+    u = np.array(u, dtype=np.float64, order="C")
+    hist = np.zeros(max_cycles + 1)
+    cyc = ctypes.c_int()
+    rr = ctypes.c_double()
+    st = lib().orc_solve(dim, n, _ptr(_params(dim, p)), prec, _ptr(u), _ptr(f), rtol, max_cycles,
+                         ctypes.byref(cyc), ctypes.byref(rr), _ptr(hist))
+    if check and st not in (OK, ERR_NOT_CONVERGED):
+        raise OracleError(st, "orc_solve")
+    return u, cyc.value, rr.value, hist[:cyc.value + 1], st
+
+
+def step_restrict(dim, kind, fine):
+    m = fine.shape[0] - 1
+    mc = m // 2 if (dim == 2 and kind == 1) or (dim == 3 and kind == 2) else m
+    out = np.zeros((mc + 1,) * dim)
+    _chk(lib().orc_step_restrict(dim, kind, m, _ptr(np.ascontiguousarray(fine, dtype=np.float64)), _ptr(out)),
+         "orc_step_restrict")
+    return out
+
+
+def step_jacobi(dim, kind, c, r, vc):
+    m = r.shape[0] - 1
+    c = np.ascontiguousarray(np.atleast_1d(np.asarray(c, dtype=np.float64)))
+    if c.size < 2:
+        c = np.concatenate([c, [0.0]])
+    out = np.zeros_like(r)
+    _chk(lib().orc_step_jacobi(dim, kind, m, _ptr(c), _ptr(np.ascontiguousarray(r)),
+                               _ptr(np.ascontiguousarray(vc)), _ptr(out)), "orc_step_jacobi")
+    return out

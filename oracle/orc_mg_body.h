@@ -1,0 +1,361 @@
+/*
+ * Oracle body: one V-cycle of the diagonally oriented multigrid for the
+ * discrete Poisson equation, written as plainly as possible.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the CPU reference that the GPU
+ * path is checked against; nothing in the product links it.
+ *
+ * Included twice by orc_mg.c: with R = double (SFX adds nothing) and with
+ * R = float (SFX appends "_f32").  R is the type every level residual and
+ * correction is held in; the finest residual r = f - Lap(u) and the update
+ * u += v are always computed in double (the f32 instance is the
+ * mixed-precision iterative refinement: the cycle in single, the outer
+ * residual and the update in double).
+ *
+ * Storage: every level is a full array of its own stride sigma, natural
+ * order with x fastest, indices in units of sigma (the paper indexes every
+ * level of a group with the subscripts of that group's finest grid,
+ * Section 3.1).  Points of the array that are not on the level, and
+ * boundary points, hold 0 (zero Dirichlet data for the correction).
+ *
+ * 2D (Section 2): n = 2^K, depth d = 0 .. 2(K-1).  Even d: axis grid,
+ * sigma = 2^(d/2), spacing sigma*h.  Odd d: diagonal grid of the points
+ * with (a+b) even, sigma = 2^((d-1)/2), spacing sqrt2*sigma*h.  Array side
+ * m+1 with m = n/sigma.
+ *
+ * 3D (Section 3): depth d = 3q+t, sigma = 2^q.  t=0 green (cubic), t=1 red
+ * (points with a+b+c even: cube corners and face centres), t=2 magenta
+ * (points with a,b,c all even or all odd: corners and cube centres).  The
+ * blue grid that ends a group is the next group's green grid.
+ *
+ * Every sum below is evaluated left to right in the order the paper prints
+ * its terms; the build uses -ffp-contract=off.
+ */
+
+/* ------------------------------------------------------------------ 2D */
+
+#define I2(m, a, b) ((size_t)(b) * (size_t)((m) + 1) + (size_t)(a))
+
+/* Eq. (Erest2r): restriction from an axis grid to the diagonal grid of the
+ * same stride; the weights are 1/2 on the point and 1/8 on each of its four
+ * axis neighbours (Fig. Erest2).  Coarse side is m as well. */
+static void SFX(rs2_axis_to_diag)(int m, const R *r, R *rc)
+{
+    memset(rc, 0, sizeof(R) * (size_t)(m + 1) * (size_t)(m + 1));
+    for (int b = 1; b < m; b++)
+        for (int a = 1; a < m; a++) {
+            if ((a + b) % 2 != 0) continue;
+            rc[I2(m, a, b)] = (R)((4 * r[I2(m, a, b)] + r[I2(m, a - 1, b)] + r[I2(m, a, b - 1)]
+                                   + r[I2(m, a + 1, b)] + r[I2(m, a, b + 1)]) / 8);
+        }
+}
+
+/* Eq. (Erest2b): restriction from a diagonal grid (side m) onto the axis
+ * grid of twice the stride (side m/2), weights 1/2 and 1/8 on the four
+ * diagonal neighbours. */
+static void SFX(rs2_diag_to_axis)(int m, const R *r, R *rc)
+{
+    int mc = m / 2;
+    memset(rc, 0, sizeof(R) * (size_t)(mc + 1) * (size_t)(mc + 1));
+    for (int B = 1; B < mc; B++)
+        for (int A = 1; A < mc; A++) {
+            int a = 2 * A, b = 2 * B;
+            rc[I2(mc, A, B)] = (R)((4 * r[I2(m, a, b)] + r[I2(m, a - 1, b - 1)] + r[I2(m, a + 1, b - 1)]
+                                    + r[I2(m, a + 1, b + 1)] + r[I2(m, a - 1, b + 1)]) / 8);
+        }
+}
+
+/* Jacobi prolongation onto an axis grid of side m (Section 2.2, "similarly
+ * for a green grid"; over-relaxed form Section 2.5).  c = p*(sigma*h)^2.
+ * First the points with (a+b) odd, which are not on the coarser diagonal
+ * grid, from the four axis neighbours of vd (the coarser diagonal level,
+ * same side m); then the points with (a+b) even from the new odd values. */
+static void SFX(jac2_axis)(int m, R c, const R *r, const R *vd, R *v)
+{
+    memset(v, 0, sizeof(R) * (size_t)(m + 1) * (size_t)(m + 1));
+    for (int b = 1; b < m; b++)
+        for (int a = 1; a < m; a++) {
+            if ((a + b) % 2 != 1) continue;
+            v[I2(m, a, b)] = (R)((-c * r[I2(m, a, b)] + vd[I2(m, a - 1, b)] + vd[I2(m, a, b - 1)]
+                                  + vd[I2(m, a + 1, b)] + vd[I2(m, a, b + 1)]) / 4);
+        }
+    for (int b = 1; b < m; b++)
+        for (int a = 1; a < m; a++) {
+            if ((a + b) % 2 != 0) continue;
+            v[I2(m, a, b)] = (R)((-c * r[I2(m, a, b)] + v[I2(m, a - 1, b)] + v[I2(m, a, b - 1)]
+                                  + v[I2(m, a + 1, b)] + v[I2(m, a, b + 1)]) / 4);
+        }
+}
+
+/* Eq. (Eajacr) then Eq. (Eajacb): Jacobi prolongation onto a diagonal grid
+ * of side m from the axis grid va of twice the stride (side m/2).
+ * c = 2*p*(sigma*h)^2 (the diagonal spacing is sqrt2*sigma*h).  First the
+ * points with a,b odd (not on the coarser grid), then the points with a,b
+ * even from the new odd values. */
+static void SFX(jac2_diag)(int m, R c, const R *r, const R *va, R *v)
+{
+    int mc = m / 2;
+    memset(v, 0, sizeof(R) * (size_t)(m + 1) * (size_t)(m + 1));
+    for (int b = 1; b < m; b += 2)
+        for (int a = 1; a < m; a += 2) {
+            int A0 = (a - 1) / 2, A1 = (a + 1) / 2, B0 = (b - 1) / 2, B1 = (b + 1) / 2;
+            v[I2(m, a, b)] = (R)((-c * r[I2(m, a, b)] + va[I2(mc, A0, B0)] + va[I2(mc, A1, B0)]
+                                  + va[I2(mc, A1, B1)] + va[I2(mc, A0, B1)]) / 4);
+        }
+    for (int b = 2; b < m; b += 2)
+        for (int a = 2; a < m; a += 2)
+            v[I2(m, a, b)] = (R)((-c * r[I2(m, a, b)] + v[I2(m, a - 1, b - 1)] + v[I2(m, a + 1, b - 1)]
+                                  + v[I2(m, a + 1, b + 1)] + v[I2(m, a - 1, b + 1)]) / 4);
+}
+
+/* ------------------------------------------------------------------ 3D */
+
+#define I3(m, a, b, c) (((size_t)(c) * (size_t)((m) + 1) + (size_t)(b)) * (size_t)((m) + 1) + (size_t)(a))
+
+static size_t SFX(vol3)(int m) { return (size_t)(m + 1) * (size_t)(m + 1) * (size_t)(m + 1); }
+
+/* Eq. (Erred): green -> red (same side m), at the points with a+b+c even. */
+static void SFX(rs3_green_to_red)(int m, const R *r, R *rc)
+{
+    memset(rc, 0, sizeof(R) * SFX(vol3)(m));
+    for (int k = 1; k < m; k++)
+        for (int j = 1; j < m; j++)
+            for (int i = 1; i < m; i++) {
+                if ((i + j + k) % 2 != 0) continue;
+                rc[I3(m, i, j, k)] = (R)((6 * r[I3(m, i, j, k)]
+                    + r[I3(m, i + 1, j, k)] + r[I3(m, i - 1, j, k)] + r[I3(m, i, j + 1, k)] + r[I3(m, i, j - 1, k)]
+                    + r[I3(m, i, j, k + 1)] + r[I3(m, i, j, k - 1)]) / 12);
+            }
+}
+
+/* Eq. (Ermagc) at the magenta corners (all indices even) and Eq. (Ermagm)
+ * at the magenta cube centres (all odd, no centre term). */
+static void SFX(rs3_red_to_magenta)(int m, const R *r, R *rc)
+{
+    memset(rc, 0, sizeof(R) * SFX(vol3)(m));
+    for (int k = 1; k < m; k++)
+        for (int j = 1; j < m; j++)
+            for (int i = 1; i < m; i++) {
+                int odd = (i & 1) + (j & 1) + (k & 1);
+                if (odd == 0)
+                    rc[I3(m, i, j, k)] = (R)((12 * r[I3(m, i, j, k)]
+                        + r[I3(m, i + 1, j + 1, k)] + r[I3(m, i + 1, j - 1, k)]
+                        + r[I3(m, i - 1, j - 1, k)] + r[I3(m, i - 1, j + 1, k)]
+                        + r[I3(m, i + 1, j, k + 1)] + r[I3(m, i + 1, j, k - 1)]
+                        + r[I3(m, i - 1, j, k - 1)] + r[I3(m, i - 1, j, k + 1)]
+                        + r[I3(m, i, j + 1, k + 1)] + r[I3(m, i, j + 1, k - 1)]
+                        + r[I3(m, i, j - 1, k - 1)] + r[I3(m, i, j - 1, k + 1)]) / 24);
+                else if (odd == 3)
+                    rc[I3(m, i, j, k)] = (R)((r[I3(m, i + 1, j, k)] + r[I3(m, i - 1, j, k)]
+                        + r[I3(m, i, j + 1, k)] + r[I3(m, i, j - 1, k)]
+                        + r[I3(m, i, j, k + 1)] + r[I3(m, i, j, k - 1)]) / 6);
+            }
+}
+
+/* Eq. (Erblu): magenta (side m) -> blue = green grid of twice the stride
+ * (side m/2), at the blue points (all indices even). */
+static void SFX(rs3_magenta_to_blue)(int m, const R *r, R *rc)
+{
+    int mc = m / 2;
+    memset(rc, 0, sizeof(R) * SFX(vol3)(mc));
+    for (int C = 1; C < mc; C++)
+        for (int B = 1; B < mc; B++)
+            for (int A = 1; A < mc; A++) {
+                int i = 2 * A, j = 2 * B, k = 2 * C;
+                rc[I3(mc, A, B, C)] = (R)((8 * r[I3(m, i, j, k)]
+                    + r[I3(m, i + 1, j + 1, k + 1)] + r[I3(m, i + 1, j + 1, k - 1)]
+                    + r[I3(m, i + 1, j - 1, k + 1)] + r[I3(m, i + 1, j - 1, k - 1)]
+                    + r[I3(m, i - 1, j + 1, k + 1)] + r[I3(m, i - 1, j + 1, k - 1)]
+                    + r[I3(m, i - 1, j - 1, k + 1)] + r[I3(m, i - 1, j - 1, k - 1)]) / 16);
+            }
+}
+
+/* Eq. (Emprolm) then Eq. (Emprolb): magenta-blue Jacobi on the magenta grid
+ * (side m) from the blue grid vb (side m/2).  c = 4*p_m*(sigma*h)^2.
+ * Cube centres (all odd) from their eight blue neighbours, then the corners
+ * (all even) from the new centre values. */
+static void SFX(jac3_magenta)(int m, R c, const R *r, const R *vb, R *v)
+{
+    int mc = m / 2;
+    memset(v, 0, sizeof(R) * SFX(vol3)(m));
+    for (int k = 1; k < m; k += 2)
+        for (int j = 1; j < m; j += 2)
+            for (int i = 1; i < m; i += 2) {
+                int i0 = (i - 1) / 2, i1 = (i + 1) / 2, j0 = (j - 1) / 2, j1 = (j + 1) / 2;
+                int k0 = (k - 1) / 2, k1 = (k + 1) / 2;
+                v[I3(m, i, j, k)] = (R)((-c * r[I3(m, i, j, k)]
+                    + vb[I3(mc, i1, j1, k1)] + vb[I3(mc, i1, j1, k0)]
+                    + vb[I3(mc, i1, j0, k1)] + vb[I3(mc, i1, j0, k0)]
+                    + vb[I3(mc, i0, j1, k1)] + vb[I3(mc, i0, j1, k0)]
+                    + vb[I3(mc, i0, j0, k1)] + vb[I3(mc, i0, j0, k0)]) / 8);
+            }
+    for (int k = 2; k < m; k += 2)
+        for (int j = 2; j < m; j += 2)
+            for (int i = 2; i < m; i += 2)
+                v[I3(m, i, j, k)] = (R)((-c * r[I3(m, i, j, k)]
+                    + v[I3(m, i + 1, j + 1, k + 1)] + v[I3(m, i + 1, j + 1, k - 1)]
+                    + v[I3(m, i + 1, j - 1, k + 1)] + v[I3(m, i + 1, j - 1, k - 1)]
+                    + v[I3(m, i - 1, j + 1, k + 1)] + v[I3(m, i - 1, j + 1, k - 1)]
+                    + v[I3(m, i - 1, j - 1, k + 1)] + v[I3(m, i - 1, j - 1, k - 1)]) / 8);
+}
+
+/* Eq. (Erprolr) then Eq. (Erprolm): red-magenta Jacobi on the red grid (side
+ * m) from the magenta grid vm (same side).  c1 = 2*p_r1*(sigma*h)^2,
+ * c2 = 4*p_r2*(sigma*h)^2.
+ * Face centres (two indices odd): the two magenta cube centres along the
+ * even axis count twice, plus the four magenta corners in the plane normal
+ * to that axis; the paper prints the z-normal case and the x- and y-normal
+ * cases are its cyclic permutations (k->i->j).  Then the corners (all even)
+ * from their twelve new face-centre neighbours.  The magenta cube centres
+ * are not on the red grid and are not carried. */
+static void SFX(jac3_red)(int m, R c1, R c2, const R *r, const R *vm, R *v)
+{
+    memset(v, 0, sizeof(R) * SFX(vol3)(m));
+    for (int k = 1; k < m; k++)
+        for (int j = 1; j < m; j++)
+            for (int i = 1; i < m; i++) {
+                int oi = i & 1, oj = j & 1, ok = k & 1;
+                if (oi + oj + ok != 2) continue;
+                R s;
+                if (!ok)        /* face normal to z: i, j odd */
+                    s = 2 * (vm[I3(m, i, j, k + 1)] + vm[I3(m, i, j, k - 1)])
+                        + vm[I3(m, i + 1, j + 1, k)] + vm[I3(m, i + 1, j - 1, k)]
+                        + vm[I3(m, i - 1, j - 1, k)] + vm[I3(m, i - 1, j + 1, k)];
+                else if (!oi)   /* face normal to x: j, k odd (z->x, x->y, y->z) */
+                    s = 2 * (vm[I3(m, i + 1, j, k)] + vm[I3(m, i - 1, j, k)])
+                        + vm[I3(m, i, j + 1, k + 1)] + vm[I3(m, i, j + 1, k - 1)]
+                        + vm[I3(m, i, j - 1, k - 1)] + vm[I3(m, i, j - 1, k + 1)];
+                else            /* face normal to y: k, i odd */
+                    s = 2 * (vm[I3(m, i, j + 1, k)] + vm[I3(m, i, j - 1, k)])
+                        + vm[I3(m, i + 1, j, k + 1)] + vm[I3(m, i - 1, j, k + 1)]
+                        + vm[I3(m, i - 1, j, k - 1)] + vm[I3(m, i + 1, j, k - 1)];
+                v[I3(m, i, j, k)] = (R)((-c1 * r[I3(m, i, j, k)] + s) / 8);
+            }
+    for (int k = 2; k < m; k += 2)
+        for (int j = 2; j < m; j += 2)
+            for (int i = 2; i < m; i += 2)
+                v[I3(m, i, j, k)] = (R)((-c2 * r[I3(m, i, j, k)]
+                    + v[I3(m, i + 1, j + 1, k)] + v[I3(m, i + 1, j - 1, k)]
+                    + v[I3(m, i - 1, j - 1, k)] + v[I3(m, i - 1, j + 1, k)]
+                    + v[I3(m, i + 1, j, k + 1)] + v[I3(m, i + 1, j, k - 1)]
+                    + v[I3(m, i - 1, j, k - 1)] + v[I3(m, i - 1, j, k + 1)]
+                    + v[I3(m, i, j + 1, k + 1)] + v[I3(m, i, j + 1, k - 1)]
+                    + v[I3(m, i, j - 1, k - 1)] + v[I3(m, i, j - 1, k + 1)]) / 12);
+}
+
+/* Eq. (Egprolg) then Eq. (Egprolr): green-red Jacobi on the green grid
+ * (side m) from the red grid vr (same side).  c = p_g*(sigma*h)^2.  Points
+ * with a+b+c odd (edge midpoints and cube centres) first, then the red
+ * points from the new values. */
+static void SFX(jac3_green)(int m, R c, const R *r, const R *vr, R *v)
+{
+    memset(v, 0, sizeof(R) * SFX(vol3)(m));
+    for (int k = 1; k < m; k++)
+        for (int j = 1; j < m; j++)
+            for (int i = 1; i < m; i++) {
+                if ((i + j + k) % 2 != 1) continue;
+                v[I3(m, i, j, k)] = (R)((-c * r[I3(m, i, j, k)]
+                    + vr[I3(m, i + 1, j, k)] + vr[I3(m, i - 1, j, k)] + vr[I3(m, i, j + 1, k)]
+                    + vr[I3(m, i, j - 1, k)] + vr[I3(m, i, j, k + 1)] + vr[I3(m, i, j, k - 1)]) / 6);
+            }
+    for (int k = 1; k < m; k++)
+        for (int j = 1; j < m; j++)
+            for (int i = 1; i < m; i++) {
+                if ((i + j + k) % 2 != 0) continue;
+                v[I3(m, i, j, k)] = (R)((-c * r[I3(m, i, j, k)]
+                    + v[I3(m, i + 1, j, k)] + v[I3(m, i - 1, j, k)] + v[I3(m, i, j + 1, k)]
+                    + v[I3(m, i, j - 1, k)] + v[I3(m, i, j, k + 1)] + v[I3(m, i, j, k - 1)]) / 6);
+            }
+}
+
+/* ------------------------------------------------------------ V-cycle */
+
+/* One V-cycle (Section 1, Eq. Evpois): r = f - Lap_h(u) on the finest grid,
+ * restrict down to the coarsest grid (3x3 or 3x3x3, one interior node),
+ * one Jacobi iteration on each grid going back up, the coarsest one starting
+ * from zero, then u <- u + v.
+ * p: 2D {p}; 3D {p_m, p_r1, p_r2, p_g}.
+ * rtrace / vtrace (nullable): every level's residual and correction, in
+ * depth order, each level as its full (m+1)^dim array, converted to double. */
+static int SFX(vcycle)(int dim, int n, const double *p, double *u, const double *f,
+                       double *rtrace, double *vtrace)
+{
+    int K = orc_log2(n);
+    if (K < 1 || (dim != 2 && dim != 3)) return ORC_ERR_SIZE;
+    int D = (dim == 2) ? 2 * (K - 1) : 3 * (K - 1);
+    double h = 1.0 / n;
+    R **rl = (R **)calloc((size_t)D + 1, sizeof(R *));
+    R **vl = (R **)calloc((size_t)D + 1, sizeof(R *));
+    int *ml = (int *)calloc((size_t)D + 1, sizeof(int));
+    if (!rl || !vl || !ml) { free(rl); free(vl); free(ml); return ORC_ERR_ALLOC; }
+    int rc = ORC_OK;
+    for (int d = 0; d <= D; d++) {
+        int sig = (dim == 2) ? (1 << (d / 2)) : (1 << (d / 3));
+        ml[d] = n / sig;
+        size_t cnt = (dim == 2) ? (size_t)(ml[d] + 1) * (size_t)(ml[d] + 1) : SFX(vol3)(ml[d]);
+        rl[d] = (R *)calloc(cnt, sizeof(R));
+        vl[d] = (R *)calloc(cnt, sizeof(R));
+        if (!rl[d] || !vl[d]) { rc = ORC_ERR_ALLOC; goto done; }
+    }
+    /* finest residual, computed in double (Eq. Evpois) */
+    {
+        size_t cnt = (dim == 2) ? (size_t)(n + 1) * (size_t)(n + 1) : SFX(vol3)(n);
+        double *r0 = (double *)malloc(cnt * sizeof(double));
+        if (!r0) { rc = ORC_ERR_ALLOC; goto done; }
+        orc_residual_core(dim, n, u, f, r0);
+        for (size_t q = 0; q < cnt; q++) rl[0][q] = (R)r0[q];
+        free(r0);
+    }
+    /* restriction down the hierarchy */
+    for (int d = 1; d <= D; d++) {
+        if (dim == 2) {
+            if (d % 2 == 1) SFX(rs2_axis_to_diag)(ml[d - 1], rl[d - 1], rl[d]);
+            else            SFX(rs2_diag_to_axis)(ml[d - 1], rl[d - 1], rl[d]);
+        } else {
+            if (d % 3 == 1)      SFX(rs3_green_to_red)(ml[d - 1], rl[d - 1], rl[d]);
+            else if (d % 3 == 2) SFX(rs3_red_to_magenta)(ml[d - 1], rl[d - 1], rl[d]);
+            else                 SFX(rs3_magenta_to_blue)(ml[d - 1], rl[d - 1], rl[d]);
+        }
+    }
+    /* Jacobi back up; the coarsest grid runs its own Jacobi from a zero
+     * coarser correction (the zero array vz). */
+    {
+        size_t cz = (dim == 2) ? 9 : 27;
+        R *vz = (R *)calloc(cz, sizeof(R));
+        if (!vz) { rc = ORC_ERR_ALLOC; goto done; }
+        for (int d = D; d >= 0; d--) {
+            const R *vc = (d == D) ? vz : vl[d + 1];
+            int m = ml[d];
+            if (dim == 2) {
+                double sh = (double)(n / m) * h;          /* sigma * h */
+                if (d % 2 == 0) SFX(jac2_axis)(m, (R)(p[0] * sh * sh), rl[d], (d == D) ? vz : vc, vl[d]);
+                else            SFX(jac2_diag)(m, (R)(2 * p[0] * sh * sh), rl[d], vc, vl[d]);
+            } else {
+                double sh = (double)(n / m) * h;
+                if (d % 3 == 0)      SFX(jac3_green)(m, (R)(p[3] * sh * sh), rl[d], vc, vl[d]);
+                else if (d % 3 == 1) SFX(jac3_red)(m, (R)(2 * p[1] * sh * sh), (R)(4 * p[2] * sh * sh), rl[d], vc, vl[d]);
+                else                 SFX(jac3_magenta)(m, (R)(4 * p[0] * sh * sh), rl[d], vc, vl[d]);
+            }
+        }
+        free(vz);
+    }
+    {
+        size_t cnt = (dim == 2) ? (size_t)(n + 1) * (size_t)(n + 1) : SFX(vol3)(n);
+        for (size_t q = 0; q < cnt; q++) u[q] = u[q] + (double)vl[0][q];
+    }
+    if (rtrace || vtrace) {
+        size_t off = 0;
+        for (int d = 0; d <= D; d++) {
+            size_t cnt = (dim == 2) ? (size_t)(ml[d] + 1) * (size_t)(ml[d] + 1) : SFX(vol3)(ml[d]);
+            for (size_t q = 0; q < cnt; q++) {
+                if (rtrace) rtrace[off + q] = (double)rl[d][q];
+                if (vtrace) vtrace[off + q] = (double)vl[d][q];
+            }
+            off += cnt;
+        }
+    }
+done:
+    for (int d = 0; d <= D; d++) { free(rl[d]); free(vl[d]); }
+    free(rl); free(vl); free(ml);
+    return rc;
+}
