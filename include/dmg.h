@@ -1,0 +1,110 @@
+/*
+ * dmg.h -- C ABI of libdmg, a diagonally oriented multigrid V-cycle for the
+ * discrete Poisson equation on MI355X (gfx950).
+ *
+ * Method: A.J. Roberts, "Fast and accurate multigrid solution of Poissons
+ * equation using diagonally oriented grids" (arXiv math/9907190).
+ *   2D (Section 2): grids alternate between axis-aligned and 45-degree
+ *   rotated (spacings h, sqrt2 h, 2h, ...); restriction Eqs. (Erest2r),
+ *   (Erest2b); red-black Jacobi prolongation with over-relaxation p,
+ *   Eqs. (Eajacr), (Eajacb) (Section 2.5).
+ *   3D (Section 3): cubic -> FCC -> BCC -> cubic of twice the spacing;
+ *   restrictions Eqs. (Erred), (Ermagc), (Ermagm), (Erblu); Jacobi steps
+ *   Eqs. (Emprolm)-(Egprolr) with parameters p_m, p_r1, p_r2, p_g.
+ *   One V-cycle (Section 1, Eq. Evpois): r = f - Lap_h(u) with the 5-point or
+ *   7-point Laplacian, restrict down to the coarsest grid (3^dim nodes, one
+ *   interior node), one Jacobi iteration per level back up (the coarsest one
+ *   from a zero correction), u <- u + v.
+ *
+ * Problem: Lap_h u = f on the unit square / cube, n intervals per side
+ * (h = 1/n, n = 2^K, 2 <= n <= 2^15 in 2D, 2^11 in 3D), zero Dirichlet data.
+ *
+ * Memory: u and f are DEVICE pointers to (n+1)^dim doubles in natural order,
+ * x fastest (index ((z*(n+1) + y)*(n+1) + x)).  Boundary entries of u are
+ * read and never written (the iteration keeps them); boundary entries of f
+ * are ignored.  The caller owns u, f and the device workspace; the library
+ * allocates no device memory.  An mg_plan is host memory owned by the
+ * library (mg_setup allocates it, mg_destroy frees it).
+ *
+ * Streams: every call enqueues its work on the HIP stream given to
+ * mg_setup (NULL = the default stream) and returns once that work is
+ * enqueued, except mg_solve, which synchronises that stream to read the
+ * residual history.  A plan is bound to one stream and one device and is
+ * not thread-safe; distinct plans with distinct workspaces are independent.
+ *
+ * Errors: every function returns MG_OK (0) or a negative MG_ERR_* code;
+ * mg_strerror names it.  On an argument error nothing is enqueued.
+ */
+#ifndef DMG_H
+#define DMG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MG_OK = 0,
+    MG_ERR_ARG = -1,            /* null pointer, bad dim / precision / parameter count */
+    MG_ERR_SIZE = -2,           /* n not a power of two in the supported range */
+    MG_ERR_WS = -3,             /* workspace null, misaligned (256 B) or too small */
+    MG_ERR_ALLOC = -4,          /* host allocation failed */
+    MG_ERR_HIP = -5,            /* a HIP runtime call failed */
+    MG_ERR_NONFINITE = -6,      /* residual norm became NaN or Inf */
+    MG_ERR_DIVERGED = -7,       /* residual grew 3 cycles in a row and exceeds the initial one */
+    MG_ERR_NOT_CONVERGED = -8   /* max_cycles reached; cycles and residual still returned */
+};
+
+enum {
+    MG_FP64 = 0,          /* every level in double */
+    MG_FP32_REFINED = 1   /* levels in single; r = f - Lap_h(u) and u += v in double
+                             (iterative refinement, u and f stay double) */
+};
+
+typedef struct mg_plan mg_plan;
+
+/* Bytes of device workspace mg_setup needs for (dim, n, precision). */
+int mg_workspace_bytes(int dim, int n, int precision, size_t *bytes);
+
+/* Build a plan.  p: over-relaxation parameters, np = 1 in 2D (p, Section
+ * 2.5; the paper's tuned value is 1.052) and np = 4 in 3D (p_m, p_r1, p_r2,
+ * p_g, Section 3.5; tuned 1.11, 1.42, 1.08, 0.99).  workspace: device
+ * memory of at least mg_workspace_bytes bytes, 256-byte aligned, used only
+ * by this plan until mg_destroy.  hip_stream: a hipStream_t or NULL.
+ * Enqueues the zeroing of the workspace on the stream. */
+int mg_setup(mg_plan **out, int dim, int n, int precision, const double *p, int np,
+             void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* One V-cycle in place on u (Section 1).  rel_res_before (host, nullable):
+ * receives ||f - Lap_h u||_2 / ||f||_2 over interior nodes for the u on
+ * entry (||r||_2 if f = 0); passing it synchronises the stream. */
+int mg_vcycle(mg_plan *plan, double *u, const double *f, double *rel_res_before);
+
+/* Outer iteration u <- u + v until the relative residual is <= rtol or
+ * max_cycles (0 .. 1000) cycles have run; the residual is checked before
+ * every cycle.  cycles_out, rel_res_out (host, nullable).  history (host,
+ * nullable, max_cycles+1 doubles): relative residual after 0, 1, ...
+ * cycles.  Returns MG_OK, MG_ERR_NOT_CONVERGED, MG_ERR_NONFINITE or
+ * MG_ERR_DIVERGED (the last three still fill the outputs).  Synchronises
+ * the stream. */
+int mg_solve(mg_plan *plan, double *u, const double *f, double rtol, int max_cycles,
+             int *cycles_out, double *rel_res_out, double *history);
+
+/* Copy level `depth` of the last cycle into dst (device, (m+1)^dim doubles,
+ * natural order, m = the level's side in units of its stride; points not on
+ * the level and boundary points read 0).  which = 0: restricted residual
+ * r (depth 0 .. D); which = 1: correction v (depth 1 .. D; the finest
+ * correction is added to u and not kept).  For parity tests. */
+int mg_level_get(mg_plan *plan, int depth, int which, double *dst);
+
+/* Number of levels D+1 and the side m of level `depth` (host-only). */
+int mg_level_info(int dim, int n, int depth, int *num_levels, int *side);
+
+int mg_destroy(mg_plan *plan);
+const char *mg_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DMG_H */

@@ -1,0 +1,197 @@
+// Residual, norms and the on-device stopping decision of libdmg.
+//
+// r = f - Lap_h(u) (Eq. Evpois) with the 5-point (2D) or 7-point (3D)
+// second-order Laplacian, computed in double from double u and f and stored
+// as T (double, or float for the single-precision cycle).  The squared norm
+// is accumulated from the double residual: per block by a wavefront
+// shuffle reduction, then across blocks in one fixed-order pass, so the
+// result is deterministic for a given n.
+#include "dmg_launch.hpp"
+
+#include <math.h>
+
+namespace dmg {
+
+constexpr int kMaxParts = 16384;
+constexpr int kRowThreads = 256;
+
+__device__ inline double block_sum(double x)
+{
+    __shared__ double red[kRowThreads / 64];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) red[wv] = x;
+    __syncthreads();
+    double s = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); i++) s += red[i];
+    return s;  // valid in thread 0
+}
+
+static void row_grid(int dim, int n, dim3& g)
+{
+    long rows = (dim == 2) ? (long)(n - 1) : (long)(n - 1) * (n - 1);
+    int gx = (n - 1 + kRowThreads - 1) / kRowThreads;
+    long gy = rows;
+    long cap = kMaxParts / gx;
+    if (gy > cap) gy = cap;
+    if (gy < 1) gy = 1;
+    g = dim3(gx, (unsigned)gy);
+}
+
+int residual_parts(int dim, int n)
+{
+    dim3 g;
+    row_grid(dim, n, g);
+    return (int)(g.x * g.y);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRowThreads) k_residual(int dim, int n, double inv_h2,
+                                                          const double* __restrict__ u,
+                                                          const double* __restrict__ f, T* __restrict__ r0,
+                                                          double* __restrict__ partial, const Ctl* ctl)
+{
+    if (ctl && ctl->done) return;
+    int a = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    long rows = (dim == 2) ? (long)(n - 1) : (long)(n - 1) * (n - 1);
+    size_t s = (size_t)n + 1, s2 = s * s;
+    double acc = 0;
+    for (long q = blockIdx.y; q < rows; q += gridDim.y) {
+        if (a >= n) continue;
+        if (dim == 2) {
+            size_t c = (size_t)(q + 1) * s + a;
+            double lap = (u[c - 1] + u[c - s] + u[c + 1] + u[c + s] - 4 * u[c]) * inv_h2;
+            double r = f[c] - lap;
+            r0[c] = (T)r;
+            acc += r * r;
+        } else {
+            long b = q % (n - 1) + 1, cz = q / (n - 1) + 1;
+            size_t c = (size_t)cz * s2 + (size_t)b * s + a;
+            double lap = (u[c + 1] + u[c - 1] + u[c + s] + u[c - s] + u[c + s2] + u[c - s2] - 6 * u[c]) * inv_h2;
+            double r = f[c] - lap;
+            r0[c] = (T)r;
+            acc += r * r;
+        }
+    }
+    double t = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = t;
+}
+
+template <typename T>
+void launch_residual(int dim, int n, const double* u, const double* f, T* r0, double* partial, int nparts,
+                     const Ctl* ctl, hipStream_t s)
+{
+    dim3 g;
+    row_grid(dim, n, g);
+    (void)nparts;
+    double inv_h2 = (double)n * (double)n;
+    hipLaunchKernelGGL(k_residual<T>, g, dim3(kRowThreads), 0, s, dim, n, inv_h2, u, f, r0, partial, ctl);
+}
+
+__global__ void __launch_bounds__(kRowThreads) k_sumsq(int dim, int n, const double* __restrict__ a_,
+                                                       double* __restrict__ partial, const Ctl* ctl)
+{
+    if (ctl && ctl->done) return;
+    int a = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    long rows = (dim == 2) ? (long)(n - 1) : (long)(n - 1) * (n - 1);
+    size_t s = (size_t)n + 1, s2 = s * s;
+    double acc = 0;
+    for (long q = blockIdx.y; q < rows; q += gridDim.y) {
+        if (a >= n) continue;
+        size_t c = (dim == 2) ? (size_t)(q + 1) * s + a
+                              : (size_t)(q / (n - 1) + 1) * s2 + (size_t)(q % (n - 1) + 1) * s + a;
+        double x = a_[c];
+        acc += x * x;
+    }
+    double t = block_sum(acc);
+    if (threadIdx.x == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = t;
+}
+
+void launch_sumsq(int dim, int n, const double* a, double* partial, int nparts, const Ctl* ctl, hipStream_t s)
+{
+    dim3 g;
+    row_grid(dim, n, g);
+    (void)nparts;
+    hipLaunchKernelGGL(k_sumsq, g, dim3(kRowThreads), 0, s, dim, n, a, partial, ctl);
+}
+
+// kind 0: ctl->fnorm = sqrt(sum).  kind 1: relative residual after k cycles
+// and the outer iteration's decision (Section 1): stop when it is <= rtol,
+// when it is not finite, when it grew three cycles in a row above the
+// starting value, or after max_cycles cycles.
+__global__ void __launch_bounds__(1024) k_finalize(int kind, int k, const double* __restrict__ partial,
+                                                   int nparts, Ctl* ctl)
+{
+    if (ctl->done) return;
+    __shared__ double red[1024];
+    double s = 0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += partial[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    double tot = red[0];
+    if (kind == 0) {
+        ctl->fnorm = sqrt(tot);
+        return;
+    }
+    double rn = sqrt(tot);
+    double rr = ctl->fnorm > 0 ? rn / ctl->fnorm : rn;
+    ctl->last = rr;
+    if (k <= kMaxCycles) ctl->hist[k] = rr;
+    if (ctl->mode == 0) return;
+    int finite = isfinite(rr);
+    if (k == 0) {
+        ctl->rr0 = rr;
+        ctl->prev = rr;
+        ctl->grow = 0;
+        if (rr <= ctl->rtol) { ctl->status = 0; ctl->done = 1; }
+        else if (ctl->max_cycles == 0) { ctl->status = -8; ctl->done = 1; }
+        else if (!finite) { ctl->status = -6; ctl->done = 1; }
+    } else {
+        if (!finite) { ctl->status = -6; ctl->done = 1; }
+        else {
+            ctl->grow = (rr > ctl->prev) ? ctl->grow + 1 : 0;
+            ctl->prev = rr;
+            if (ctl->grow >= 3 && rr > ctl->rr0) { ctl->status = -7; ctl->done = 1; }
+            else if (rr <= ctl->rtol) { ctl->status = 0; ctl->done = 1; }
+            else if (k >= ctl->max_cycles) { ctl->status = -8; ctl->done = 1; }
+        }
+    }
+    if (ctl->done) ctl->cycles = k;
+}
+
+void launch_finalize(int kind, int k, const double* partial, int nparts, Ctl* ctl, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, kind, k, partial, nparts, ctl);
+}
+
+__global__ void k_ctl_reset(Ctl* ctl, int mode, int max_cycles, double rtol)
+{
+    if (threadIdx.x != 0) return;
+    ctl->done = 0;
+    ctl->status = 0;
+    ctl->cycles = 0;
+    ctl->grow = 0;
+    ctl->mode = mode;
+    ctl->max_cycles = max_cycles;
+    ctl->rtol = rtol;
+    ctl->fnorm = 0;
+    ctl->rr0 = ctl->prev = ctl->last = 0;
+}
+
+void launch_ctl_reset(Ctl* ctl, int mode, int max_cycles, double rtol, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, ctl, mode, max_cycles, rtol);
+}
+
+template void launch_residual<double>(int, int, const double*, const double*, double*, double*, int, const Ctl*,
+                                      hipStream_t);
+template void launch_residual<float>(int, int, const double*, const double*, float*, double*, int, const Ctl*,
+                                     hipStream_t);
+
+}  // namespace dmg

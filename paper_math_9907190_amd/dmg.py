@@ -1,0 +1,165 @@
+"""Python binding of libdmg (include/dmg.h): argument marshalling only.
+
+Every function of the C ABI is exposed under the same name; ``Solver`` adds
+the plumbing a PyTorch user needs (workspace from the caching allocator,
+torch's current stream).  All arithmetic of the V-cycle runs in the HIP
+kernels of libdmg.so; there is no CPU path and no fallback: if the library
+is missing this module raises on import.
+"""
+import ctypes
+import os
+
+import torch  # loads the HIP runtime libdmg.so binds to (same soname), so it must come first
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdmg.so")
+
+MG_OK, MG_ERR_ARG, MG_ERR_SIZE, MG_ERR_WS, MG_ERR_ALLOC, MG_ERR_HIP = 0, -1, -2, -3, -4, -5
+MG_ERR_NONFINITE, MG_ERR_DIVERGED, MG_ERR_NOT_CONVERGED = -6, -7, -8
+MG_FP64, MG_FP32_REFINED = 0, 1
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libdmg.so is not built (%s); run __graft_entry__.build() or "
+                      "python paper_math_9907190_amd/build.py" % LIB_PATH)
+_lib = ctypes.CDLL(LIB_PATH)
+
+_vp, _dp, _ip, _sz = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int), ctypes.c_size_t
+_lib.mg_workspace_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_sz)]
+_lib.mg_setup.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int,
+                          _vp, _sz, _vp]
+_lib.mg_vcycle.argtypes = [_vp, _vp, _vp, _dp]
+_lib.mg_solve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _ip, _dp, _dp]
+_lib.mg_level_get.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp]
+_lib.mg_level_info.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _ip]
+_lib.mg_destroy.argtypes = [_vp]
+_lib.mg_strerror.argtypes = [ctypes.c_int]
+_lib.mg_strerror.restype = ctypes.c_char_p
+for _f in ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_level_get", "mg_level_info",
+           "mg_destroy"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+EXPORTS = ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_level_get", "mg_level_info",
+           "mg_destroy", "mg_strerror")
+
+
+class MGError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__("%s: %s (%d)" % (what, mg_strerror(code), code))
+        self.code = code
+
+
+def _check(code, what):
+    if code != MG_OK:
+        raise MGError(code, what)
+    return code
+
+
+# ---------------------------------------------------------------- raw C ABI
+
+def mg_strerror(code):
+    return _lib.mg_strerror(int(code)).decode()
+
+
+def mg_workspace_bytes(dim, n, precision):
+    out = _sz()
+    _check(_lib.mg_workspace_bytes(dim, n, precision, ctypes.byref(out)), "mg_workspace_bytes")
+    return out.value
+
+
+def mg_level_info(dim, n, depth=0):
+    nl, side = ctypes.c_int(), ctypes.c_int()
+    _check(_lib.mg_level_info(dim, n, depth, ctypes.byref(nl), ctypes.byref(side)), "mg_level_info")
+    return nl.value, side.value
+
+
+def mg_setup(dim, n, precision, p, workspace_ptr, ws_bytes, stream_ptr):
+    plan = _vp()
+    arr = (ctypes.c_double * len(p))(*[float(x) for x in p])
+    _check(_lib.mg_setup(ctypes.byref(plan), dim, n, precision, arr, len(p), _vp(workspace_ptr), ws_bytes,
+                         _vp(stream_ptr)), "mg_setup")
+    return plan
+
+
+def mg_vcycle(plan, u_ptr, f_ptr, want_relres=False):
+    rr = ctypes.c_double()
+    _check(_lib.mg_vcycle(plan, _vp(u_ptr), _vp(f_ptr), ctypes.byref(rr) if want_relres else None), "mg_vcycle")
+    return rr.value if want_relres else None
+
+
+def mg_solve(plan, u_ptr, f_ptr, rtol, max_cycles):
+    """Returns (status, cycles, relres, history list)."""
+    cyc, rr = ctypes.c_int(), ctypes.c_double()
+    hist = (ctypes.c_double * (max_cycles + 1))()
+    st = _lib.mg_solve(plan, _vp(u_ptr), _vp(f_ptr), float(rtol), int(max_cycles), ctypes.byref(cyc),
+                       ctypes.byref(rr), hist)
+    if st not in (MG_OK, MG_ERR_NOT_CONVERGED, MG_ERR_NONFINITE, MG_ERR_DIVERGED):
+        raise MGError(st, "mg_solve")
+    return st, cyc.value, rr.value, list(hist[:cyc.value + 1])
+
+
+def mg_level_get(plan, depth, which, dst_ptr):
+    _check(_lib.mg_level_get(plan, depth, which, _vp(dst_ptr)), "mg_level_get")
+
+
+def mg_destroy(plan):
+    _check(_lib.mg_destroy(plan), "mg_destroy")
+
+
+# ------------------------------------------------------------ torch plumbing
+
+P2D_TUNED = (1.052,)                    # Section 2.5
+P3D_TUNED = (1.11, 1.42, 1.08, 0.99)    # Section 3.5, Table tbl:3dopt
+
+
+class Solver:
+    """A plan plus its workspace on one device / stream.
+
+    u, f: float64 CUDA tensors of shape (n+1,)*dim, contiguous (x fastest).
+    """
+
+    def __init__(self, dim, n, precision=MG_FP64, p=None, device=None, stream=None):
+        if p is None:
+            p = P2D_TUNED if dim == 2 else P3D_TUNED
+        self.dim, self.n, self.precision, self.p = dim, n, precision, tuple(float(x) for x in p)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.ws_bytes = mg_workspace_bytes(dim, n, precision)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.ws.data_ptr()
+            self._ws_ptr = (base + 255) // 256 * 256
+            self.plan = mg_setup(dim, n, precision, self.p, self._ws_ptr, self.ws_bytes, self.stream.cuda_stream)
+        self.num_levels = mg_level_info(dim, n)[0]
+
+    def _chk(self, t, name):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+                and tuple(t.shape) == (self.n + 1,) * self.dim and t.device == self.device):
+            raise ValueError("%s must be a contiguous float64 tensor of shape %s on %s"
+                             % (name, (self.n + 1,) * self.dim, self.device))
+
+    def vcycle(self, u, f, want_relres=False):
+        self._chk(u, "u")
+        self._chk(f, "f")
+        return mg_vcycle(self.plan, u.data_ptr(), f.data_ptr(), want_relres)
+
+    def solve(self, u, f, rtol=1e-10, max_cycles=50):
+        self._chk(u, "u")
+        self._chk(f, "f")
+        return mg_solve(self.plan, u.data_ptr(), f.data_ptr(), rtol, max_cycles)
+
+    def level(self, depth, which=0):
+        side = mg_level_info(self.dim, self.n, depth)[1]
+        out = torch.empty((side + 1,) * self.dim, dtype=torch.float64, device=self.device)
+        mg_level_get(self.plan, depth, which, out.data_ptr())
+        return out
+
+    def close(self):
+        if getattr(self, "plan", None) is not None:
+            mg_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,71 @@
+"""CPU checks of the C ABI: libdmg.so loads, exports every function
+include/dmg.h declares, and the host-only parts (sizes, level plan, argument
+errors raised before any GPU call) behave as documented."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    txt = open(os.path.join(ROOT, "include", "dmg.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\s*\*)\s*(mg_\w+)\s*\(", txt, re.M)))
+
+
+@pytest.fixture(scope="module")
+def D():
+    from paper_math_9907190_amd import dmg
+    return dmg
+
+
+def test_every_declared_symbol_is_exported(D):
+    names = declared()
+    assert len(names) >= 8
+    for nm in names:
+        assert hasattr(D._lib, nm), nm
+    assert sorted(D.EXPORTS) == names
+
+
+def test_level_info(D):
+    assert D.mg_level_info(2, 64) == (11, 64)        # 2(K-1)+1 levels for n = 2^K
+    assert D.mg_level_info(2, 4096) == (23, 4096)
+    assert D.mg_level_info(3, 256) == (22, 256)      # 3(K-1)+1
+    assert D.mg_level_info(2, 64, 10)[1] == 2        # coarsest: 3x3
+    assert D.mg_level_info(3, 16, 9)[1] == 2         # coarsest: 3x3x3
+    assert D.mg_level_info(2, 2) == (1, 2)
+
+
+def test_workspace_bytes(D):
+    b64 = D.mg_workspace_bytes(2, 4096, D.MG_FP64)
+    b32 = D.mg_workspace_bytes(2, 4096, D.MG_FP32_REFINED)
+    n2 = 4097 ** 2
+    # finest residual plus r and v on every coarser level: about 3 arrays of the finest size
+    assert 2.9 * 8 * n2 < b64 < 3.2 * 8 * n2
+    assert 0.45 < b32 / b64 < 0.55
+    b3 = D.mg_workspace_bytes(3, 256, D.MG_FP64)
+    assert 2.9 * 8 * 257 ** 3 < b3 < 3.4 * 8 * 257 ** 3
+
+
+@pytest.mark.parametrize("dim,n,code", [(2, 3, -2), (2, 1, -2), (2, 1 << 16, -2), (3, 1 << 12, -2), (4, 8, -1)])
+def test_size_errors(D, dim, n, code):
+    out = ctypes.c_size_t()
+    assert D._lib.mg_workspace_bytes(dim, n, 0, ctypes.byref(out)) == code
+
+
+def test_setup_argument_errors_before_any_gpu_call(D):
+    plan = ctypes.c_void_p()
+    p1 = (ctypes.c_double * 1)(1.052)
+    p4 = (ctypes.c_double * 4)(1.11, 1.42, 1.08, 0.99)
+    # wrong parameter count, bad parameter, bad precision, bad size, null / small workspace
+    assert D._lib.mg_setup(ctypes.byref(plan), 2, 64, 0, p4, 4, None, 0, None) == D.MG_ERR_ARG
+    bad = (ctypes.c_double * 1)(-1.0)
+    assert D._lib.mg_setup(ctypes.byref(plan), 2, 64, 0, bad, 1, None, 0, None) == D.MG_ERR_ARG
+    assert D._lib.mg_setup(ctypes.byref(plan), 2, 64, 7, p1, 1, None, 0, None) == D.MG_ERR_ARG
+    assert D._lib.mg_setup(ctypes.byref(plan), 2, 48, 0, p1, 1, None, 0, None) == D.MG_ERR_SIZE
+    assert D._lib.mg_setup(ctypes.byref(plan), 3, 16, 0, p4, 4, None, 0, None) == D.MG_ERR_WS
+    assert D._lib.mg_setup(ctypes.byref(plan), 2, 64, 0, p1, 1, ctypes.c_void_p(4096), 16, None) == D.MG_ERR_WS
+    assert D._lib.mg_setup(ctypes.byref(plan), 2, 64, 0, p1, 1, ctypes.c_void_p(4097), 1 << 30, None) == D.MG_ERR_WS
+    assert D.mg_strerror(D.MG_ERR_WS).startswith("workspace")
