@@ -101,6 +101,24 @@ int mg_level_get(mg_plan *plan, int depth, int which, double *dst);
 /* Number of levels D+1 and the side m of level `depth` (host-only). */
 int mg_level_info(int dim, int n, int depth, int *num_levels, int *side);
 
+/* Measurement.  Kernel families of one cycle: */
+enum {
+    MG_K_RESIDUAL = 0,  /* finest residual r = f - Lap_h(u) and its norm partials */
+    MG_K_RESTRICT = 1,  /* one restriction step per launch (all levels above the coarse part) */
+    MG_K_JACOBI = 2,    /* one Jacobi step per launch (levels between the finest and the coarse part) */
+    MG_K_FINEST = 3,    /* finest Jacobi step fused with u += v */
+    MG_K_COARSE = 4,    /* persistent kernel running every coarse level */
+    MG_K_NORM = 5,      /* norm finalisation and the stopping decision */
+    MG_K_FAMILIES = 6
+};
+/* Bracket every later launch of kernel family `family` (-1: none) on the
+ * plan's stream with HIP events.  mg_timing_read synchronises those events
+ * and returns, since the previous read: the summed kernel duration in ms,
+ * the number of launches, and their summed algorithmic HBM bytes (each
+ * array element a launch must read or write, counted once). */
+int mg_timing_enable(mg_plan *plan, int family);
+int mg_timing_read(mg_plan *plan, double *ms, long long *launches, double *bytes);
+
 int mg_destroy(mg_plan *plan);
 const char *mg_strerror(int code);
 

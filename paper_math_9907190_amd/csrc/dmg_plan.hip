@@ -9,6 +9,7 @@
 #include "../../include/dmg.h"
 #include "dmg_launch.hpp"
 #include "dmg_launch3.hpp"
+#include "dmg_rows.hpp"
 
 #include <new>
 #include <stdlib.h>
@@ -21,6 +22,9 @@ namespace {
 // levels with side <= kCoarseSide (2D) / kCoarseSide3 (3D) go to the persistent kernel
 constexpr int kCoarseSide = 32;
 constexpr int kCoarseSide3 = 8;
+// 2D levels of at least this side use the row-marching kernels; smaller ones
+// are latency-bound and use one thread per point (a single round of loads)
+constexpr int kRowsMinSide = 512;
 
 int ilog2(int n)
 {
@@ -41,7 +45,9 @@ struct Level {
 struct Layout {
     int dim = 0, n = 0, prec = 0, D = 0, dc = 0;
     size_t ctl = 0, partial = 0, zero = 0, r0 = 0, total = 0;
-    int nparts = 0;
+    int nparts_f = 0;   // partial sums written by the norm of f
+    int nparts_r = 0;   // partial sums written by the residual kernel
+    bool fused_rs1 = false;  // 2D: the residual kernel also restricts to level 1
     Level lev[kMaxLev];
 };
 
@@ -80,8 +86,10 @@ int make_layout(int dim, int n, int prec, const double* p, Layout& L)
         return o;
     };
     L.ctl = take(sizeof(Ctl));
-    L.nparts = residual_parts(dim, n);
-    L.partial = take(sizeof(double) * (size_t)L.nparts);
+    L.fused_rs1 = (dim == 2 && L.D >= 1);
+    L.nparts_f = residual_parts(dim, n);
+    L.nparts_r = L.fused_rs1 ? rows_resid_parts(n) : L.nparts_f;
+    L.partial = take(sizeof(double) * (size_t)(L.nparts_f > L.nparts_r ? L.nparts_f : L.nparts_r));
     L.zero = take(sizeof(double) * 64);
     L.r0 = take(es * (dim == 2 ? sizeA(n) : sizeG(n)));
     double h = 1.0 / n;
@@ -130,6 +138,8 @@ int make_layout(int dim, int n, int prec, const double* p, Layout& L)
 
 }  // namespace
 
+constexpr int kTimedMax = 64;
+
 struct mg_plan {
     Layout L;
     double p[4];
@@ -138,12 +148,96 @@ struct mg_plan {
     char* ws;
     size_t ws_bytes;
     Ctl* hctl;  // pinned host copy of the control block
+    // measurement of one kernel family (mg_timing_enable)
+    int tfam = -1;
+    int tpend = 0;
+    bool tev = false;
+    hipEvent_t tbeg[kTimedMax], tend[kTimedMax];
+    double tms = 0, tbytes = 0;
+    long long tcount = 0;
 };
 
 namespace {
 
 template <typename T>
 T* at(mg_plan* P, size_t off) { return reinterpret_cast<T*>(P->ws + off); }
+
+void timing_flush(mg_plan* P)
+{
+    for (int i = 0; i < P->tpend; i++) {
+        float ms = 0;
+        if (hipEventSynchronize(P->tend[i]) == hipSuccess && hipEventElapsedTime(&ms, P->tbeg[i], P->tend[i]) == hipSuccess)
+            P->tms += ms;
+    }
+    P->tpend = 0;
+}
+
+// Brackets one launch with events when its family is the measured one.
+struct Timed {
+    mg_plan* P;
+    bool on;
+    Timed(mg_plan* p, int fam, double bytes) : P(p), on(p->tev && p->tfam == fam)
+    {
+        if (!on) return;
+        if (P->tpend == kTimedMax) timing_flush(P);
+        (void)hipEventRecord(P->tbeg[P->tpend], P->stream);
+        P->tbytes += bytes;
+        P->tcount++;
+    }
+    ~Timed()
+    {
+        if (on) (void)hipEventRecord(P->tend[P->tpend++], P->stream);
+    }
+};
+
+// Algorithmic HBM bytes of one launch: every element of an input array the
+// launch reads, and every element it writes, counted once.
+double bytes_rs2(int diag_in, int m, size_t es)
+{
+    int M = m / 2;
+    if (!diag_in) return (double)es * (sizeA(m) + (double)M * M + (double)(M - 1) * (M - 1));
+    return (double)es * (sizeD(m) + (double)(M - 1) * (M - 1));
+}
+double bytes_jac2(int diag, int m, size_t es)
+{
+    int M = m / 2;
+    if (diag) {
+        double pts = (double)M * M + (double)(M - 1) * (M - 1);
+        return (double)es * (2 * pts + sizeA(M));
+    }
+    return (double)es * (2.0 * (m - 1) * (m - 1) + sizeD(m));
+}
+double bytes_rs3(int coarse_kind, int m, size_t es)
+{
+    double M = m / 2;
+    if (coarse_kind == 1) return (double)es * (sizeG(m) + (double)(m - 1) * (m - 1) * (m - 1) / 2);
+    if (coarse_kind == 2) return (double)es * (sizeR(m) + (M - 1) * (M - 1) * (M - 1) + M * M * M);
+    return (double)es * (sizeME(m) + sizeMO(m) + (M - 1) * (M - 1) * (M - 1));
+}
+double bytes_jac3(int kind, int m, size_t es)
+{
+    double M = m / 2, c = (double)(m - 1) * (m - 1) * (m - 1);
+    if (kind == 2) return (double)es * (2 * ((M - 1) * (M - 1) * (M - 1) + M * M * M) + sizeG(m / 2));
+    if (kind == 1) return (double)es * (2 * ((M - 1) * (M - 1) * (M - 1) + 3 * M * M * (M - 1)) + sizeME(m) + sizeMO(m));
+    return (double)es * (2 * c + sizeR(m));
+}
+double bytes_residual(int dim, int n, size_t es, bool fused_rs1)
+{
+    double inter = dim == 2 ? (double)(n - 1) * (n - 1) : (double)(n - 1) * (n - 1) * (n - 1);
+    double all = dim == 2 ? (double)sizeA(n) : (double)sizeG(n);
+    double b = 8 * all + 8 * inter + es * inter;
+    if (fused_rs1) {
+        double M = n / 2;
+        b += es * (M * M + (M - 1) * (M - 1));  // the level-1 residual it also writes
+    }
+    return b;
+}
+double bytes_finest(int dim, int n, size_t es)
+{
+    double inter = dim == 2 ? (double)(n - 1) * (n - 1) : (double)(n - 1) * (n - 1) * (n - 1);
+    double vc = dim == 2 ? (double)sizeD(n) : (double)sizeR(n);
+    return es * (inter + vc) + 16 * inter;
+}
 
 struct DevGuard {
     int old = -1;
@@ -168,9 +262,18 @@ void enqueue_cycle_2d(mg_plan* P, double* u, const Ctl* ctl)
     T* r0 = at<T>(P, L.r0);
     auto R = [&](int d) -> T* { return d == 0 ? r0 : at<T>(P, L.lev[d].r); };
     auto V = [&](int d) -> T* { return at<T>(P, L.lev[d].v); };
+    const size_t es = sizeof(T);
     int last_rs = dc ? dc : D;
-    for (int d = 1; d <= last_rs; d++) launch_rs2<T>((d - 1) % 2, L.lev[d - 1].m, R(d - 1), R(d), ctl, s);
+    for (int d = L.fused_rs1 ? 2 : 1; d <= last_rs; d++) {
+        Timed t(P, MG_K_RESTRICT, bytes_rs2((d - 1) % 2, L.lev[d - 1].m, es));
+        if (L.lev[d - 1].m >= kRowsMinSide) launch_rs2_rows<T>((d - 1) % 2, L.lev[d - 1].m, R(d - 1), R(d), ctl, s);
+        else launch_rs2<T>((d - 1) % 2, L.lev[d - 1].m, R(d - 1), R(d), ctl, s);
+    }
     if (dc) {
+        double cb = 0;
+        for (int d = dc + 1; d <= D; d++) cb += bytes_rs2((d - 1) % 2, L.lev[d - 1].m, es);
+        for (int d = dc; d <= D; d++) cb += bytes_jac2(L.lev[d].kind, L.lev[d].m, es);
+        Timed t(P, MG_K_COARSE, cb);
         Coarse2<T> a;
         a.first = dc;
         a.last = D;
@@ -186,20 +289,49 @@ void enqueue_cycle_2d(mg_plan* P, double* u, const Ctl* ctl)
     }
     for (int d = (dc ? dc - 1 : D); d >= 1; d--) {
         const T* vc = (d == D) ? at<T>(P, L.zero) : V(d + 1);
-        launch_jac2<T>(L.lev[d].kind, L.lev[d].m, (T)L.lev[d].c, R(d), vc, V(d), ctl, s);
+        Timed t(P, MG_K_JACOBI, bytes_jac2(L.lev[d].kind, L.lev[d].m, es));
+        if (L.lev[d].m >= kRowsMinSide) launch_jac2_rows<T>(L.lev[d].kind, L.lev[d].m, (T)L.lev[d].c, R(d), vc, V(d), ctl, s);
+        else launch_jac2<T>(L.lev[d].kind, L.lev[d].m, (T)L.lev[d].c, R(d), vc, V(d), ctl, s);
     }
     const T* v1 = D >= 1 ? V(1) : at<T>(P, L.zero);
-    launch_jac2_finest<T>(L.n, (T)L.lev[0].c, r0, v1, u, ctl, s);
+    Timed t(P, MG_K_FINEST, bytes_finest(2, L.n, es));
+    launch_jac2_finest_rows<T>(L.n, (T)L.lev[0].c, r0, v1, u, ctl, s);
 }
 
 template <typename T>
-void enqueue_cycle(mg_plan* P, double* u, const double* f, const Ctl* ctl, bool resid)
+void enqueue_cycle(mg_plan* P, double* u, const Ctl* ctl)
+{
+    if (P->L.dim == 2) enqueue_cycle_2d<T>(P, u, ctl);
+    else enqueue_cycle_3d<T>(P, u, ctl);
+}
+
+void enqueue_residual(mg_plan* P, const double* u, const double* f, const Ctl* ctl)
 {
     Layout& L = P->L;
-    if (resid)
-        launch_residual<T>(L.dim, L.n, u, f, at<T>(P, L.r0), at<double>(P, L.partial), L.nparts, ctl, P->stream);
-    if (L.dim == 2) enqueue_cycle_2d<T>(P, u, ctl);
-    else enqueue_cycle_3d<T>(P, u, ctl);
+    bool dbl = L.prec == MG_FP64;
+    double* part = at<double>(P, L.partial);
+    Timed t(P, MG_K_RESIDUAL, bytes_residual(L.dim, L.n, dbl ? 8 : 4, L.fused_rs1));
+    if (L.fused_rs1) {
+        if (dbl) launch_resid_a2d<double>(L.n, u, f, at<double>(P, L.r0), at<double>(P, L.lev[1].r), part, ctl, P->stream);
+        else launch_resid_a2d<float>(L.n, u, f, at<float>(P, L.r0), at<float>(P, L.lev[1].r), part, ctl, P->stream);
+    } else {
+        if (dbl) launch_residual<double>(L.dim, L.n, u, f, at<double>(P, L.r0), part, L.nparts_r, ctl, P->stream);
+        else launch_residual<float>(L.dim, L.n, u, f, at<float>(P, L.r0), part, L.nparts_r, ctl, P->stream);
+    }
+}
+
+// kind 0: norm of f (partials of the sumsq kernel); kind 1: residual norm
+void enqueue_finalize(mg_plan* P, int kind, int k, Ctl* ctl)
+{
+    int np = kind == 0 ? P->L.nparts_f : P->L.nparts_r;
+    Timed t(P, MG_K_NORM, 8.0 * np);
+    launch_finalize(kind, k, at<double>(P, P->L.partial), np, ctl, P->stream);
+}
+
+void enqueue_cycle_any(mg_plan* P, double* u, const Ctl* ctl)
+{
+    if (P->L.prec == MG_FP64) enqueue_cycle<double>(P, u, ctl);
+    else enqueue_cycle<float>(P, u, ctl);
 }
 
 int hip_status(hipError_t e) { return e == hipSuccess ? MG_OK : MG_ERR_HIP; }
@@ -230,9 +362,17 @@ void enqueue_cycle_3d_impl(mg_plan* P, double* u, const Ctl* ctl)
         x.c2 = (T)q.c2;
         return x;
     };
+    const size_t es = sizeof(T);
     int last_rs = dc ? dc : D;
-    for (int d = 1; d <= last_rs; d++) launch_rs3<T>(lv(d - 1), lv(d), ctl, s);
+    for (int d = 1; d <= last_rs; d++) {
+        Timed t(P, MG_K_RESTRICT, bytes_rs3(L.lev[d].kind, L.lev[d - 1].m, es));
+        launch_rs3<T>(lv(d - 1), lv(d), ctl, s);
+    }
     if (dc) {
+        double cb = 0;
+        for (int d = dc + 1; d <= D; d++) cb += bytes_rs3(L.lev[d].kind, L.lev[d - 1].m, es);
+        for (int d = dc; d <= D; d++) cb += bytes_jac3(L.lev[d].kind, L.lev[d].m, es);
+        Timed t(P, MG_K_COARSE, cb);
         Coarse3<T> a;
         a.first = dc;
         a.last = D;
@@ -242,9 +382,11 @@ void enqueue_cycle_3d_impl(mg_plan* P, double* u, const Ctl* ctl)
     }
     for (int d = (dc ? dc - 1 : D); d >= 1; d--) {
         Lev3<T> c = (d == D) ? Lev3<T>{} : lv(d + 1);
+        Timed t(P, MG_K_JACOBI, bytes_jac3(L.lev[d].kind, L.lev[d].m, es));
         launch_jac3<T>(lv(d), c, at<T>(P, L.zero), ctl, s);
     }
     Lev3<T> c1 = D >= 1 ? lv(1) : Lev3<T>{};
+    Timed t(P, MG_K_FINEST, bytes_finest(3, L.n, es));
     launch_jac3_finest<T>(L.n, (T)L.lev[0].c, r0, D >= 1 ? c1.v : at<T>(P, L.zero), u, ctl, s);
 }
 }  // namespace
@@ -329,6 +471,13 @@ int mg_setup(mg_plan** out, int dim, int n, int precision, const double* p, int 
 int mg_destroy(mg_plan* P)
 {
     if (!P) return MG_ERR_ARG;
+    if (P->tev) {
+        timing_flush(P);
+        for (int i = 0; i < kTimedMax; i++) {
+            (void)hipEventDestroy(P->tbeg[i]);
+            (void)hipEventDestroy(P->tend[i]);
+        }
+    }
     if (P->hctl) (void)hipHostFree(P->hctl);
     delete P;
     return MG_OK;
@@ -344,15 +493,12 @@ int mg_vcycle(mg_plan* P, double* u, const double* f, double* rel_res_before)
     double* part = at<double>(P, L.partial);
     launch_ctl_reset(ctl, 0, 0, 0.0, P->stream);
     if (rel_res_before) {
-        launch_sumsq(L.dim, L.n, f, part, L.nparts, ctl, P->stream);
-        launch_finalize(0, 0, part, L.nparts, ctl, P->stream);
+        launch_sumsq(L.dim, L.n, f, part, L.nparts_f, ctl, P->stream);
+        enqueue_finalize(P, 0, 0, ctl);
     }
-    bool dbl = L.prec == MG_FP64;
-    if (dbl) launch_residual<double>(L.dim, L.n, u, f, at<double>(P, L.r0), part, L.nparts, ctl, P->stream);
-    else launch_residual<float>(L.dim, L.n, u, f, at<float>(P, L.r0), part, L.nparts, ctl, P->stream);
-    if (rel_res_before) launch_finalize(1, 0, part, L.nparts, ctl, P->stream);
-    if (dbl) enqueue_cycle<double>(P, u, f, ctl, false);
-    else enqueue_cycle<float>(P, u, f, ctl, false);
+    enqueue_residual(P, u, f, ctl);
+    if (rel_res_before) enqueue_finalize(P, 1, 0, ctl);
+    enqueue_cycle_any(P, u, ctl);
     int e = last_launch();
     if (e) return e;
     if (rel_res_before) {
@@ -374,24 +520,24 @@ int mg_solve(mg_plan* P, double* u, const double* f, double rtol, int max_cycles
     Ctl* ctl = at<Ctl>(P, L.ctl);
     double* part = at<double>(P, L.partial);
     hipStream_t s = P->stream;
-    bool dbl = L.prec == MG_FP64;
     launch_ctl_reset(ctl, 1, max_cycles, rtol, s);
-    launch_sumsq(L.dim, L.n, f, part, L.nparts, ctl, s);
-    launch_finalize(0, 0, part, L.nparts, ctl, s);
+    launch_sumsq(L.dim, L.n, f, part, L.nparts_f, ctl, s);
+    enqueue_finalize(P, 0, 0, ctl);
+    enqueue_residual(P, u, f, ctl);
+    enqueue_finalize(P, 1, 0, ctl);
     size_t head = offsetof(Ctl, rtol);
-    for (int k = 0; k <= max_cycles; k++) {
-        if (dbl) launch_residual<double>(L.dim, L.n, u, f, at<double>(P, L.r0), part, L.nparts, ctl, s);
-        else launch_residual<float>(L.dim, L.n, u, f, at<float>(P, L.r0), part, L.nparts, ctl, s);
-        launch_finalize(1, k, part, L.nparts, ctl, s);
-        if (k == max_cycles) break;
-        if (dbl) enqueue_cycle<double>(P, u, f, ctl, false);
-        else enqueue_cycle<float>(P, u, f, ctl, false);
-        int e = last_launch();
-        if (e) return e;
-        // the device decides; the host only stops enqueueing once it sees `done`
+    // The device takes the decision after every residual evaluation; the
+    // host launches the next cycle only once it has seen that the last
+    // evaluation did not stop the solve, so no launch is wasted.
+    for (int k = 0;; k++) {
         if (hipMemcpyAsync(P->hctl, ctl, head, hipMemcpyDeviceToHost, s) != hipSuccess) return MG_ERR_HIP;
         if (hipStreamSynchronize(s) != hipSuccess) return MG_ERR_HIP;
-        if (P->hctl->done) break;
+        if (P->hctl->done || k >= max_cycles) break;
+        enqueue_cycle_any(P, u, ctl);
+        enqueue_residual(P, u, f, ctl);
+        enqueue_finalize(P, 1, k + 1, ctl);
+        int e = last_launch();
+        if (e) return e;
     }
     if (hipMemcpyAsync(P->hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s) != hipSuccess) return MG_ERR_HIP;
     if (hipStreamSynchronize(s) != hipSuccess) return MG_ERR_HIP;
@@ -402,6 +548,38 @@ int mg_solve(mg_plan* P, double* u, const double* f, double rtol, int max_cycles
     if (history)
         for (int k = 0; k <= cyc; k++) history[k] = H.hist[k];
     return H.done ? H.status : MG_ERR_NOT_CONVERGED;
+}
+
+int mg_timing_enable(mg_plan* P, int family)
+{
+    if (!P || family < -1 || family >= MG_K_FAMILIES) return MG_ERR_ARG;
+    DevGuard g(P->device);
+    if (!g.ok) return MG_ERR_HIP;
+    if (family >= 0 && !P->tev) {
+        for (int i = 0; i < kTimedMax; i++)
+            if (hipEventCreate(&P->tbeg[i]) != hipSuccess || hipEventCreate(&P->tend[i]) != hipSuccess)
+                return MG_ERR_HIP;
+        P->tev = true;
+    }
+    if (P->tev) timing_flush(P);
+    P->tfam = family;
+    P->tms = P->tbytes = 0;
+    P->tcount = 0;
+    return MG_OK;
+}
+
+int mg_timing_read(mg_plan* P, double* ms, long long* launches, double* bytes)
+{
+    if (!P) return MG_ERR_ARG;
+    DevGuard g(P->device);
+    if (!g.ok) return MG_ERR_HIP;
+    if (P->tev) timing_flush(P);
+    if (ms) *ms = P->tms;
+    if (launches) *launches = P->tcount;
+    if (bytes) *bytes = P->tbytes;
+    P->tms = P->tbytes = 0;
+    P->tcount = 0;
+    return MG_OK;
 }
 
 int mg_level_get(mg_plan* P, int depth, int which, double* dst)

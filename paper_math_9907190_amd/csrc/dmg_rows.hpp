@@ -1,0 +1,84 @@
+// Shared launch geometry of the row-marching kernels.
+#pragma once
+#include "dmg_common.hpp"
+
+namespace dmg {
+
+constexpr int kMaxRows = 32;         // longest strip a wave marches through
+constexpr int kChunk = 2;            // default depth: rows whose loads are issued together
+constexpr int kTargetWaves = 4096;   // ~16 waves per CU on 256 CUs
+constexpr int kWavesPerBlock = 4;
+constexpr int kRowBlock = 64 * kWavesPerBlock;
+constexpr int kPairsPerWave = 62;    // lanes 1..62 write; lanes 0 and 63 are halo
+constexpr int kColsPerWave = 63;     // one-sided halo (lane 0 only)
+constexpr int kXcds = 8;             // MI355X: 8 accelerator dies, one L2 each
+
+// Blocks are dispatched to the XCDs round-robin (block b runs on XCD b % 8).
+// Renumber them so that each XCD gets a contiguous range of logical blocks:
+// consecutive waves march neighbouring column bands of the same strip, so
+// the halo rows they share stay in one L2.
+__device__ inline int rows_wave_id(int nwaves)
+{
+    int nb = gridDim.x;
+    int b = blockIdx.x;
+    int per = nb / kXcds, rem = nb % kXcds;
+    int x = b % kXcds;
+    int logical = x * per + (x < rem ? x : rem) + b / kXcds;
+    (void)nwaves;
+    return logical * kWavesPerBlock + (threadIdx.x >> 6);
+}
+
+// Two adjacent elements (columns 2t, 2t+1 of a row) moved as one access.
+// Rows of odd length leave every other pair 8-byte (not 16-byte) aligned;
+// gfx950 global loads and stores only need dword alignment.
+template <typename T>
+struct alignas(sizeof(T)) P2 {
+    T x, y;
+};
+
+// Sum over the block (fixed order: wave shuffle tree, then waves in order).
+__device__ inline double rows_block_sum(double x)
+{
+    __shared__ double red[kWavesPerBlock];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    double s = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kWavesPerBlock; i++) s += red[i];
+    return s;
+}
+
+// Double-buffered march over rows jbeg, jbeg+CH, ... <= jlast: the loads of
+// the next CH rows are in flight while the current CH rows are computed.
+template <int CH, typename Ck, typename Load, typename Proc>
+__device__ inline void rows_march(int jbeg, int jlast, Load&& load, Proc&& proc)
+{
+    Ck A, B;
+    int jb = jbeg;
+    load(jb, A);
+    while (true) {
+        load(jb + CH, B);
+        proc(jb, A);
+        jb += CH;
+        if (jb > jlast) break;
+        load(jb + CH, A);
+        proc(jb, B);
+        jb += CH;
+        if (jb > jlast) break;
+    }
+}
+
+int rows_resid_parts(int n);
+
+template <typename T>
+void launch_resid_a2d(int n, const double* u, const double* f, T* r0, T* rD, double* partial, const Ctl* ctl,
+                      hipStream_t s);
+template <typename T>
+void launch_rs2_rows(int diag_in, int m, const T* in, T* out, const Ctl* ctl, hipStream_t s);
+template <typename T>
+void launch_jac2_rows(int diag, int m, T c, const T* r, const T* vc, T* v, const Ctl* ctl, hipStream_t s);
+template <typename T>
+void launch_jac2_finest_rows(int n, T c, const T* r0, const T* vD, double* u, const Ctl* ctl, hipStream_t s);
+
+}  // namespace dmg

@@ -32,14 +32,19 @@ _lib.mg_solve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _ip, _dp
 _lib.mg_level_get.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp]
 _lib.mg_level_info.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _ip]
 _lib.mg_destroy.argtypes = [_vp]
+_lib.mg_timing_enable.argtypes = [_vp, ctypes.c_int]
+_lib.mg_timing_read.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_longlong), _dp]
 _lib.mg_strerror.argtypes = [ctypes.c_int]
 _lib.mg_strerror.restype = ctypes.c_char_p
 for _f in ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_level_get", "mg_level_info",
-           "mg_destroy"):
+           "mg_destroy", "mg_timing_enable", "mg_timing_read"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_level_get", "mg_level_info",
-           "mg_destroy", "mg_strerror")
+           "mg_destroy", "mg_strerror", "mg_timing_enable", "mg_timing_read")
+
+# kernel families for mg_timing_enable
+MG_K_RESIDUAL, MG_K_RESTRICT, MG_K_JACOBI, MG_K_FINEST, MG_K_COARSE, MG_K_NORM = range(6)
 
 
 class MGError(RuntimeError):
@@ -105,6 +110,17 @@ def mg_destroy(plan):
     _check(_lib.mg_destroy(plan), "mg_destroy")
 
 
+def mg_timing_enable(plan, family):
+    _check(_lib.mg_timing_enable(plan, int(family)), "mg_timing_enable")
+
+
+def mg_timing_read(plan):
+    """Returns (summed ms, launches, summed algorithmic bytes) since the last read."""
+    ms, cnt, by = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
+    _check(_lib.mg_timing_read(plan, ctypes.byref(ms), ctypes.byref(cnt), ctypes.byref(by)), "mg_timing_read")
+    return ms.value, cnt.value, by.value
+
+
 # ------------------------------------------------------------ torch plumbing
 
 P2D_TUNED = (1.052,)                    # Section 2.5
@@ -152,6 +168,12 @@ class Solver:
         out = torch.empty((side + 1,) * self.dim, dtype=torch.float64, device=self.device)
         mg_level_get(self.plan, depth, which, out.data_ptr())
         return out
+
+    def timing(self, family):
+        mg_timing_enable(self.plan, family)
+
+    def timing_read(self):
+        return mg_timing_read(self.plan)
 
     def close(self):
         if getattr(self, "plan", None) is not None:
