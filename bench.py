@@ -62,6 +62,72 @@ def timed_solves(S, f, steps, warmup, rtol, family, torch):
     return dt, cycles, kern, us[-1], hist
 
 
+def bench_batched(dmg, workloads, dev, torch, args):
+    """512 independent 2D problems, sides drawn from {129, 257, 513, 1025}
+    (seed 4), smooth-mode f per problem (seed 4+b); single-precision cycles with
+    FP64 refinement to 1e-10; one launch per aligned level for the whole
+    batch, iteration replayed from a hipGraph; launch shapes autotuned at
+    setup (outside the timed region)."""
+    ns = workloads.batch_sizes(512, seed=4)
+    log("batched: generating %d problems" % len(ns))
+    fs = [torch.from_numpy(workloads.batch_problem(n, b)).to(dev) for b, n in enumerate(ns)]
+    B = dmg.BatchSolver(ns, precision=dmg.MG_FP32_REFINED, device=dev)
+    B.autotune()
+    unknowns = sum((n - 1) ** 2 for n in ns)
+    us = [[torch.zeros_like(f) for f in fs] for _ in range(args.steps + args.warmup)]
+    for k in range(args.warmup):
+        st, cyc, rr, sts = B.solve(us[k], fs, rtol=args.rtol, max_cycles=60)
+        assert st == 0, st
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ucs = 0
+    for k in range(args.warmup, args.warmup + args.steps):
+        st, cyc, rr, sts = B.solve(us[k], fs, rtol=args.rtol, max_cycles=60)
+        assert st == 0 and max(rr) <= args.rtol, (st, max(rr))
+        ucs += sum((n - 1) ** 2 * c for n, c in zip(ns, cyc))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res = {"workload": "512 problems, sides from {129,257,513,1025} (seed 4), 4 smooth modes each, "
+                       "FP32 cycles + FP64 refinement to %.0e" % args.rtol,
+           "unknowns": unknowns, "ms_to_rtol": round(1e3 * dt / args.steps, 3),
+           "unknowns_cycles_per_s": ucs / dt, "cycles_max": max(cyc), "cycles_min": min(cyc),
+           "max_final_rel_res": max(rr)}
+    log("  batched: %.3f ms per batch solve, cycles %d..%d, %.3e unknowns*cycles/s"
+        % (res["ms_to_rtol"], min(cyc), max(cyc), res["unknowns_cycles_per_s"]))
+    B.close()
+    del us, fs, B
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_cube(dmg, workloads, dev, torch, args):
+    """3D unit cube 257^3 (h = 1/256), f ~ U(-1,1) (seed 3), tuned 3D
+    parameters; FP64 against single-precision cycles, both to 1e-10."""
+    n = 256
+    f = torch.from_numpy(workloads.cube_uniform(n, seed=3)).to(dev)
+    res = {"workload": "3D unit cube 257^3, f ~ U(-1,1) (seed 3), p = (1.11, 1.42, 1.08, 0.99), to %.0e" % args.rtol,
+           "unknowns": (n - 1) ** 3}
+    for name, prec in (("fp64", dmg.MG_FP64), ("fp32_refined", dmg.MG_FP32_REFINED)):
+        S = dmg.Solver(3, n, precision=prec, device=dev)
+        us = [torch.zeros_like(f) for _ in range(args.steps + args.warmup)]
+        for k in range(args.warmup):
+            S.solve(us[k], f, rtol=args.rtol, max_cycles=60)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.warmup, args.warmup + args.steps):
+            st, cyc, rr, hist = S.solve(us[k], f, rtol=args.rtol, max_cycles=60)
+            assert st == 0 and rr <= args.rtol, (st, rr)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[name] = {"ms_to_rtol": round(1e3 * dt / args.steps, 3), "cycles": cyc,
+                     "unknowns_cycles_per_s": (n - 1) ** 3 * cyc * args.steps / dt, "final_rel_res": rr}
+        log("  cube257 %s: %.3f ms, %d cycles" % (name, res[name]["ms_to_rtol"], cyc))
+        S.close()
+        del S, us
+        torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +137,7 @@ def main():
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--family", type=int, default=3, help="kernel family for the roofline (3: finest Jacobi)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the batched and 3D workloads")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this solver has no multi-GPU path (a single grid is "
@@ -119,6 +186,11 @@ def main():
         torch.cuda.empty_cache()
     modes["fp32_refined"]["speedup_vs_fp64"] = round(modes["fp64"]["ms_to_rtol"] / modes["fp32_refined"]["ms_to_rtol"], 3)
 
+    extra = {}
+    if not args.no_extra:
+        extra["batched512"] = bench_batched(dmg, workloads, dev, torch, args)
+        extra["cube257"] = bench_cube(dmg, workloads, dev, torch, args)
+
     cpu = None
     if not args.no_cpu:
         from oracle import oracle as O
@@ -138,6 +210,7 @@ def main():
                                   "p=1.052, solve from u=0 to %.0e rel. residual" % (n + 1, n + 1, n, args.rtol),
                       "unknowns": unknowns, "grid": n + 1, "rtol": args.rtol},
            "modes": modes, "roofline": roof, "cpu_baseline": cpu}
+    out.update(extra)
     print(json.dumps(out), flush=True)
 
 

@@ -101,6 +101,36 @@ int mg_level_get(mg_plan *plan, int depth, int which, double *dst);
 /* Number of levels D+1 and the side m of level `depth` (host-only). */
 int mg_level_info(int dim, int n, int depth, int *num_levels, int *side);
 
+/* Batched 2D solve.  nprob independent problems on the unit square, problem
+ * i with n[i] intervals per side (a power of two, 2 .. 2^15), all with the
+ * same over-relaxation p (Section 2.5).  The hierarchies are aligned from the
+ * coarsest grid, where every level of the same aligned index has the same
+ * side whatever the problem's size, so one kernel launch per level serves the
+ * whole batch; a converged problem's work returns at once.  One outer
+ * iteration is captured in a hipGraph and replayed.  u and f are HOST arrays
+ * of nprob DEVICE pointers, each to (n[i]+1)^2 doubles laid out as for
+ * mg_solve.  The plan is used with mg_solve_batched / mg_vcycle_batched (and
+ * with mg_solve / mg_vcycle when nprob = 1), mg_autotune, mg_destroy. */
+int mg_batch_workspace_bytes(int nprob, const int *n, int precision, size_t *bytes);
+int mg_setup_batched(mg_plan **out, int nprob, const int *n, int precision, double p,
+                     void *workspace, size_t ws_bytes, void *hip_stream);
+/* Per problem (host arrays of nprob, nullable): cycles run, final relative
+ * residual, status (MG_OK / MG_ERR_NOT_CONVERGED / MG_ERR_NONFINITE /
+ * MG_ERR_DIVERGED).  Returns MG_OK when every problem converged, else the
+ * most negative per-problem status.  Synchronises the stream. */
+int mg_solve_batched(mg_plan *plan, double *const *u, const double *const *f, double rtol,
+                     int max_cycles, int *cycles, double *rel_res, int *status);
+/* One V-cycle of every problem; rel_res_before (host, nprob, nullable). */
+int mg_vcycle_batched(mg_plan *plan, double *const *u, const double *const *f, double *rel_res_before);
+
+/* Tile autotuner (2D plans): times every candidate launch shape (one thread
+ * per point, or row strips of 4..32 rows per wavefront) of every level
+ * launch of the cycle on the plan's own arrays and keeps the fastest.  If
+ * the environment variable DMG_TUNE_CACHE names a file, results are appended
+ * to it and later plans read them at setup.  Enqueues and synchronises work
+ * on the plan's stream; the workspace's level arrays are overwritten. */
+int mg_autotune(mg_plan *plan);
+
 /* Measurement.  Kernel families of one cycle: */
 enum {
     MG_K_RESIDUAL = 0,  /* finest residual r = f - Lap_h(u) and its norm partials */

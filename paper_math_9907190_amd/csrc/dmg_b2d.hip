@@ -1,0 +1,843 @@
+// 2D kernels of libdmg (Roberts, Section 2), driven by work items so that a
+// single launch per level serves a batch of independent problems.
+//
+// Large levels (side >= 512) use row-marching kernels: a wavefront owns a
+// band of columns and marches down a strip of rows holding a three-row
+// register window; on an axis grid each lane owns the column pair (2t, 2t+1)
+// (one point of each colour per row), so both half-sweeps of the red-black
+// Jacobi run in one launch, the value needed from the neighbouring pair
+// comes across lanes by shuffle, and lanes 0 and 63 are halo lanes so no
+// value crosses a wave.  Loads are double-buffered (rows_march) and pairs
+// move as one 16-byte access.  Small levels (latency-bound) use one thread
+// per point.  Levels of side <= 32 run in one workgroup per problem.
+//
+// Per point the arithmetic is the paper's: Eqs. (Erest2r), (Erest2b),
+// (Eajacr), (Eajacb) and the axis-grid Jacobi, terms in the printed order.
+#include "dmg_b2d.hpp"
+#include "dmg_rows.hpp"
+
+namespace dmg {
+
+#define ITEM_GATE(ctls, prob) \
+    if ((ctls)[(prob)].done) return
+
+// ====================================================================== finest
+
+// r = f - Lap_h(u) on rows [y0, y1) (stored as T, squared norm accumulated
+// in double), then Eq. (Erest2r) onto the first diagonal level at those rows.
+template <typename T, int CH>
+__global__ void __launch_bounds__(kRowBlock) kb_resid(int m, double inv_h2, const Fin2<T>* __restrict__ items,
+                                                      int nwx, int nwaves, int rows, const Ctl* __restrict__ ctls)
+{
+    const Fin2<T> it = items[blockIdx.y];
+    ITEM_GATE(ctls, it.prob);
+    const double* __restrict__ u = it.u;
+    const double* __restrict__ f = it.f;
+    T* __restrict__ r0 = it.r0;
+    T* __restrict__ rD = it.r1;
+    const int lane = threadIdx.x & 63;
+    const int wv = rows_wave_id(nwaves);
+    const bool live = wv < nwaves;
+    const int wx = wv % nwx, sy = wv / nwx;
+    const int t = wx * kPairsPerWave - 1 + lane;
+    const int y0 = 1 + sy * rows;
+    const int y1 = min(y0 + rows, m);
+    const bool useful = lane >= 1 && lane <= kPairsPerWave && t >= 0 && t <= m / 2;
+    const size_t w = (size_t)(m + 1);
+    const int W = m / 2 + 1;
+    const bool c0 = t >= 1 && 2 * t <= m - 1, c1 = t >= 0 && 2 * t + 1 <= m - 1;  // columns 2t, 2t+1 interior
+    const bool colok = live && t >= 0 && t <= m / 2;
+    // u at columns 2t, 2t+1 of row j (column m+1 does not exist)
+    auto ldu = [&](int j, double& x, double& y) {
+        x = y = 0;
+        if (!colok || j < 0 || j > m) return;
+        const double* p = u + (size_t)j * w + 2 * t;
+        if (t < m / 2) { P2<double> v = *reinterpret_cast<const P2<double>*>(p); x = v.x; y = v.y; }
+        else x = p[0];
+    };
+    auto ldf = [&](int j, double& x, double& y) {
+        x = y = 0;
+        if (!colok || j < 1 || j > m - 1) return;
+        P2<double> v = *reinterpret_cast<const P2<double>*>(f + (size_t)j * w + 2 * t);
+        x = v.x; y = v.y;
+    };
+    struct Ck { double ux[CH], uy[CH], fx[CH], fy[CH]; };
+    auto load = [&](int jb, Ck& c) {
+#pragma unroll
+        for (int i = 0; i < CH; i++) {
+            int j = jb + i;
+            c.ux[i] = c.uy[i] = c.fx[i] = c.fy[i] = 0;
+            if (j <= y1) { ldu(j + 2, c.ux[i], c.uy[i]); ldf(j, c.fx[i], c.fy[i]); }
+        }
+    };
+    double acc = 0;
+    double um0, um1, uc0, uc1, up0, up1;  // u rows j-1, j, j+1 of the lane's pair
+    ldu(y0 - 2, um0, um1);
+    ldu(y0 - 1, uc0, uc1);
+    ldu(y0, up0, up1);
+    T rm2_0 = 0, rm2_1 = 0, rm1_0 = 0, rm1_1 = 0;  // r rows j-2, j-1 (as stored)
+    auto proc = [&](int jb, const Ck& c) {
+#pragma unroll
+        for (int i = 0; i < CH; i++) {
+            int j = jb + i;
+            if (j > y1) break;
+            bool rowin = j >= 1 && j <= m - 1;
+            double uW = __shfl_up(uc1, 1);   // u(2t-1, j)
+            double uE = __shfl_down(uc0, 1); // u(2t+2, j)
+            double x0 = c.fx[i] - (uW + um0 + uc1 + up0 - 4 * uc0) * inv_h2;
+            double x1 = c.fy[i] - (uc0 + um1 + uE + up1 - 4 * uc1) * inv_h2;
+            T r0j = (rowin && c0) ? (T)x0 : T(0);
+            T r1j = (rowin && c1) ? (T)x1 : T(0);
+            if (j >= y0 && j < y1 && useful) {
+                T* p = r0 + (size_t)j * w + 2 * t;
+                if (c0 && c1) { *reinterpret_cast<P2<T>*>(p) = P2<T>{r0j, r1j}; acc += x0 * x0 + x1 * x1; }
+                else if (c1) { p[1] = r1j; acc += x1 * x1; }
+                else if (c0) { p[0] = r0j; acc += x0 * x0; }
+            }
+            if (j - 1 >= y0) {
+                // Eq. Erest2r at the diagonal point of row j-1 (a + j-1 even)
+                int q = (j - 1) & 1;
+                T sh = q ? __shfl_down(rm1_0, 1) : __shfl_up(rm1_1, 1);
+                T rc = q ? rm1_1 : rm1_0;
+                T rw = q ? rm1_0 : sh;
+                T re = q ? sh : rm1_1;
+                T rs = q ? rm2_1 : rm2_0;
+                T rn = q ? r1j : r0j;
+                int a = 2 * t + q;
+                if (useful && a >= 1 && a <= m - 1)
+                    rD[(size_t)(j - 1) * W + t] = (4 * rc + rw + rs + re + rn) * T(0.125);
+            }
+            rm2_0 = rm1_0; rm2_1 = rm1_1; rm1_0 = r0j; rm1_1 = r1j;
+            um0 = uc0; um1 = uc1; uc0 = up0; uc1 = up1; up0 = c.ux[i]; up1 = c.uy[i];
+        }
+    };
+    rows_march<CH, Ck>(y0 - 1, y1, load, proc);
+    double sum = rows_block_sum(acc);
+    if (threadIdx.x == 0) it.part[blockIdx.x] = sum;
+}
+
+// One-thread-per-point residual for tiny grids (side < 4: no diagonal level).
+template <typename T>
+__global__ void kb_resid_small(int n, double inv_h2, const Fin2<T>* __restrict__ items, const Ctl* __restrict__ ctls)
+{
+    const Fin2<T> it = items[blockIdx.y];
+    ITEM_GATE(ctls, it.prob);
+    double acc = 0;
+    size_t s = (size_t)n + 1;
+    for (int q = threadIdx.x; q < (n - 1) * (n - 1); q += blockDim.x) {
+        int a = q % (n - 1) + 1, b = q / (n - 1) + 1;
+        size_t c = (size_t)b * s + a;
+        double lap = (it.u[c - 1] + it.u[c - s] + it.u[c + 1] + it.u[c + s] - 4 * it.u[c]) * inv_h2;
+        double r = it.f[c] - lap;
+        it.r0[c] = (T)r;
+        acc += r * r;
+    }
+    double sum = rows_block_sum(acc);
+    if (threadIdx.x == 0) it.part[0] = sum;
+}
+
+// sum of f^2 over interior nodes, per problem (same partial count as kb_resid)
+template <typename T>
+__global__ void __launch_bounds__(kRowBlock) kb_sumsq(int n, const Fin2<T>* __restrict__ items,
+                                                      const Ctl* __restrict__ ctls)
+{
+    const Fin2<T> it = items[blockIdx.y];
+    ITEM_GATE(ctls, it.prob);
+    size_t s = (size_t)n + 1;
+    long tot = (long)(n - 1) * (n - 1);
+    double acc = 0;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += (long)gridDim.x * blockDim.x) {
+        long a = q % (n - 1) + 1, b = q / (n - 1) + 1;
+        double x = it.f[(size_t)b * s + a];
+        acc += x * x;
+    }
+    double sum = rows_block_sum(acc);
+    if (threadIdx.x == 0) it.part[blockIdx.x] = sum;
+}
+
+// finest axis-grid Jacobi fused with u <- u + v (Section 1), row-marching
+template <typename T, bool FINEST, int CH>
+__device__ inline void jaxis_body(int m, T cc, const T* __restrict__ rA, const T* __restrict__ vD,
+                                  T* __restrict__ vA, double* __restrict__ u, int nwx, int nwaves, int rows)
+{
+    const int lane = threadIdx.x & 63;
+    const int wv = rows_wave_id(nwaves);
+    if (wv >= nwaves) return;
+    const int wx = wv % nwx, sy = wv / nwx;
+    const int t = wx * kPairsPerWave - 1 + lane;
+    const int y0 = 1 + sy * rows;
+    const int y1 = min(y0 + rows, m);
+    const bool useful = lane >= 1 && lane <= kPairsPerWave && t >= 0 && t <= m / 2;
+    const bool colok = t >= 0 && t <= m / 2;
+    const bool c0 = t >= 1 && 2 * t <= m - 1, c1 = t >= 0 && 2 * t + 1 <= m - 1;
+    const size_t w = (size_t)(m + 1);
+    const int W = m / 2 + 1;
+    auto ldD = [&](int j) -> T { return (colok && j >= 0 && j <= m) ? vD[(size_t)j * W + t] : T(0); };
+    // pair of an interior row: column m+1 is the next row's column 0 and never used
+    auto ldR = [&](int j, T& x, T& y) {
+        x = y = 0;
+        if (!colok || j < 1 || j > m - 1) return;
+        P2<T> v = *reinterpret_cast<const P2<T>*>(rA + (size_t)j * w + 2 * t);
+        x = c0 ? v.x : T(0);
+        y = c1 ? v.y : T(0);
+    };
+    struct Ck { T d[CH], rx[CH], ry[CH]; double ux[CH], uy[CH]; };
+    auto load = [&](int jb, Ck& c) {
+#pragma unroll
+        for (int i = 0; i < CH; i++) {
+            int j = jb + i;
+            c.d[i] = c.rx[i] = c.ry[i] = 0;
+            c.ux[i] = c.uy[i] = 0;
+            if (j <= y1) {
+                c.d[i] = ldD(j + 1);
+                ldR(j, c.rx[i], c.ry[i]);
+                if (FINEST && useful && j >= y0 && j < y1 && (c0 || c1)) {
+                    P2<double> v = *reinterpret_cast<const P2<double>*>(u + (size_t)j * w + 2 * t);
+                    c.ux[i] = v.x;
+                    c.uy[i] = v.y;
+                }
+            }
+        }
+    };
+    // window entering row j: vD rows j-1, j; F rows j-2, j-1; r at the C point of row j-1; u of row j-1
+    T dm = ldD(y0 - 2), d0 = ldD(y0 - 1);
+    T Fm2 = 0, Fm1 = 0, rCm1 = 0;
+    double uxm1 = 0, uym1 = 0;
+    auto proc = [&](int jb, const Ck& c) {
+#pragma unroll
+        for (int i = 0; i < CH; i++) {
+            int j = jb + i;
+            if (j > y1) break;
+            T dp = c.d[i];
+            int q = j & 1;
+            T rF = q ? c.rx[i] : c.ry[i];  // F at column 2t+1-q
+            T rC = q ? c.ry[i] : c.rx[i];  // C at column 2t+q
+            // F at row j: vd[a-1,b] + vd[a,b-1] + vd[a+1,b] + vd[a,b+1]
+            T nb = q ? __shfl_up(d0, 1) : __shfl_down(d0, 1);
+            T vw = q ? nb : d0;
+            T ve = q ? d0 : nb;
+            int aF = 2 * t + 1 - q;
+            T Fj = (aF >= 1 && aF <= m - 1 && j >= 1 && j <= m - 1) ? (-cc * rF + vw + dm + ve + dp) * T(0.25) : T(0);
+            if (j - 1 >= y0) {
+                int qq = (j - 1) & 1;
+                T sb = qq ? __shfl_down(Fm1, 1) : __shfl_up(Fm1, 1);
+                T cw = qq ? Fm1 : sb;
+                T ce = qq ? sb : Fm1;
+                T C = (-cc * rCm1 + cw + Fm2 + ce + Fj) * T(0.25);
+                T vx = qq ? Fm1 : C;  // column 2t
+                T vy = qq ? C : Fm1;  // column 2t+1
+                size_t o = (size_t)(j - 1) * w + 2 * t;
+                if (useful) {
+                    if (FINEST) {
+                        if (c0 && c1) *reinterpret_cast<P2<double>*>(u + o) = P2<double>{uxm1 + (double)vx, uym1 + (double)vy};
+                        else if (c1) u[o + 1] = uym1 + (double)vy;
+                        else if (c0) u[o] = uxm1 + (double)vx;
+                    } else {
+                        if (c0 && c1) *reinterpret_cast<P2<T>*>(vA + o) = P2<T>{vx, vy};
+                        else if (c1) vA[o + 1] = vy;
+                        else if (c0) vA[o] = vx;
+                    }
+                }
+            }
+            Fm2 = Fm1; Fm1 = Fj; rCm1 = rC;
+            dm = d0; d0 = dp;
+            uxm1 = c.ux[i]; uym1 = c.uy[i];
+        }
+    };
+    rows_march<CH, Ck>(y0 - 1, y1, load, proc);
+}
+
+template <typename T, int CH>
+__global__ void __launch_bounds__(kRowBlock) kb_finest(int m, T cc, const Fin2<T>* __restrict__ items, int nwx,
+                                                       int nwaves, int rows, const Ctl* __restrict__ ctls)
+{
+    const Fin2<T> it = items[blockIdx.y];
+    ITEM_GATE(ctls, it.prob);
+    jaxis_body<T, true, CH>(m, cc, it.r0, it.v1, nullptr, it.u, nwx, nwaves, rows);
+}
+
+// tiny finest grids: one thread per point (both half-sweeps recomputed)
+template <typename T>
+__global__ void kb_finest_small(int n, T cc, const Fin2<T>* __restrict__ items, const Ctl* __restrict__ ctls)
+{
+    const Fin2<T> it = items[blockIdx.y];
+    ITEM_GATE(ctls, it.prob);
+    for (int q = threadIdx.x; q < (n / 2 + 1) * (n - 1); q += blockDim.x) {
+        int tt = q % (n / 2 + 1), b = q / (n / 2 + 1) + 1;
+        int aC = 2 * tt + (b & 1), aF = 2 * tt + 1 - (b & 1);
+        if (aF >= 1 && aF < n) { size_t o = idxA(n, aF, b); it.u[o] = it.u[o] + (double)jac2_axisF(it.r0, it.v1, n, cc, aF, b); }
+        if (aC >= 1 && aC < n) { size_t o = idxA(n, aC, b); it.u[o] = it.u[o] + (double)jac2_axisC(it.r0, it.v1, n, cc, aC, b); }
+    }
+}
+
+// ============================================================= level kernels
+
+// Eq. (Erest2r): axis grid (side m) -> diagonal grid (side m), row-marching
+template <typename T, int CH>
+__global__ void __launch_bounds__(kRowBlock) kb_a2d_rows(int m, const Item2<T>* __restrict__ items, int nwx,
+                                                         int nwaves, int rows, const Ctl* __restrict__ ctls)
+{
+    const Item2<T> it = items[blockIdx.y];
+    ITEM_GATE(ctls, it.prob);
+    const T* __restrict__ rA = it.in;
+    T* __restrict__ rD = it.r;
+    const int lane = threadIdx.x & 63;
+    const int wv = rows_wave_id(nwaves);
+    if (wv >= nwaves) return;
+    const int wx = wv % nwx, sy = wv / nwx;
+    const int t = wx * kPairsPerWave - 1 + lane;
+    const int y0 = 1 + sy * rows;
+    const int y1 = min(y0 + rows, m);
+    const bool useful = lane >= 1 && lane <= kPairsPerWave && t >= 0 && t <= m / 2;
+    const bool colok = t >= 0 && t <= m / 2;
+    const bool c0 = t >= 1 && 2 * t <= m - 1, c1 = t >= 0 && 2 * t + 1 <= m - 1;
+    const size_t w = (size_t)(m + 1);
+    const int W = m / 2 + 1;
+    auto ldr = [&](int j, T& x, T& y) {
+        x = y = 0;
+        if (!colok || j < 1 || j > m - 1) return;
+        P2<T> v = *reinterpret_cast<const P2<T>*>(rA + (size_t)j * w + 2 * t);
+        x = c0 ? v.x : T(0);
+        y = c1 ? v.y : T(0);
+    };
+    struct Ck { T x[CH], y[CH]; };
+    auto load = [&](int jb, Ck& c) {
+#pragma unroll
+        for (int i = 0; i < CH; i++) {
+            c.x[i] = c.y[i] = 0;
+            if (jb + i < y1) ldr(jb + i + 1, c.x[i], c.y[i]);
+        }
+    };
+    T rm0, rm1, rc0, rc1;
+    ldr(y0 - 1, rm0, rm1);
+    ldr(y0, rc0, rc1);
+    auto proc = [&](int jb, const Ck& c) {
+#pragma unroll
+        for (int i = 0; i < CH; i++) {
+            int j = jb + i;
+            if (j >= y1) break;
+            int q = j & 1;
+            T sh = q ? __shfl_down(rc0, 1) : __shfl_up(rc1, 1);
+            T rc = q ? rc1 : rc0;
+            T rw = q ? rc0 : sh;
+            T re = q ? sh : rc1;
+            T rs = q ? rm1 : rm0;
+            T rn = q ? c.y[i] : c.x[i];
+            int a = 2 * t + q;
+            if (useful && a >= 1 && a <= m - 1) rD[(size_t)j * W + t] = (4 * rc + rw + rs + re + rn) * T(0.125);
+            rm0 = rc0; rm1 = rc1; rc0 = c.x[i]; rc1 = c.y[i];
+        }
+    };
+    rows_march<CH, Ck>(y0, y1 - 1, load, proc);
+}
+
+// Eq. (Erest2b): diagonal grid (side m) -> axis grid (side m/2), row-marching.
+// Lane owns coarse column A (lane 0 is a halo lane) and marches over coarse rows B.
+template <typename T, int CH>
+__global__ void __launch_bounds__(kRowBlock) kb_d2a_rows(int m, const Item2<T>* __restrict__ items, int nwx,
+                                                         int nwaves, int rows, const Ctl* __restrict__ ctls)
+{
+    const Item2<T> it = items[blockIdx.y];
+    ITEM_GATE(ctls, it.prob);
+    const T* __restrict__ rD = it.in;
+    T* __restrict__ rA2 = it.r;
+    const int lane = threadIdx.x & 63;
+    const int wv = rows_wave_id(nwaves);
+    if (wv >= nwaves) return;
+    const int mc = m / 2;
+    const int wx = wv % nwx, sy = wv / nwx;
+    const int A = wx * kColsPerWave - 1 + lane;
+    const int B0 = 1 + sy * rows;
+    const int B1 = min(B0 + rows, mc);
+    const bool useful = lane >= 1 && A >= 1 && A <= mc - 1;
+    const bool colok = A >= 0 && A <= mc;
+    const int W = m / 2 + 1;
+    auto ld = [&](int row, bool ok) -> T { return (ok && colok && row >= 0 && row <= m) ? rD[(size_t)row * W + A] : T(0); };
+    struct Ck { T c[CH], h[CH]; };
+    auto load = [&](int Bb, Ck& q) {
+#pragma unroll
+        for (int i = 0; i < CH; i++) {
+            int B = Bb + i;
+            q.c[i] = ld(2 * B, B < B1);
+            q.h[i] = ld(2 * B + 1, B < B1);
+        }
+    };
+    T lo = ld(2 * B0 - 1, true);
+    auto proc = [&](int Bb, const Ck& q) {
+#pragma unroll
+        for (int i = 0; i < CH; i++) {
+            int B = Bb + i;
+            if (B >= B1) break;
+            T hi = q.h[i];
+            T lo_w = __shfl_up(lo, 1), hi_w = __shfl_up(hi, 1);
+            // 4 r(2A,2B) + r(2A-1,2B-1) + r(2A+1,2B-1) + r(2A+1,2B+1) + r(2A-1,2B+1)
+            if (useful) rA2[(size_t)B * (mc + 1) + A] = (4 * q.c[i] + lo_w + lo + hi + hi_w) * T(0.125);
+            lo = hi;
+        }
+    };
+    rows_march<CH, Ck>(B0, B1 - 1, load, proc);
+}
+
+// Eqs. (Eajacr), (Eajacb): Jacobi on a diagonal grid (side m) from the axis
+// grid of side m/2.  Lane owns column A of the compacted rows: F = (2A+1, 2B+1)
+// and C = (2A, 2B).
+template <typename T, int CH>
+__global__ void __launch_bounds__(kRowBlock) kb_jdiag_rows(int m, T cc, const Item2<T>* __restrict__ items, int nwx,
+                                                           int nwaves, int rows, const Ctl* __restrict__ ctls)
+{
+    const Item2<T> it = items[blockIdx.y];
+    ITEM_GATE(ctls, it.prob);
+    const T* __restrict__ rD = it.r;
+    const T* __restrict__ vA2 = it.in;
+    T* __restrict__ vD = it.v;
+    const int lane = threadIdx.x & 63;
+    const int wv = rows_wave_id(nwaves);
+    if (wv >= nwaves) return;
+    const int h = m / 2;
+    const int wx = wv % nwx, sy = wv / nwx;
+    const int A = wx * kPairsPerWave - 1 + lane;
+    const int B0 = sy * rows;  // coarse rows B: F row 2B+1 (B in [0,h-1]), C row 2B (B in [1,h-1])
+    const int B1 = min(B0 + rows, h);
+    const bool useful = lane >= 1 && lane <= kPairsPerWave && A >= 0 && A <= h - 1;
+    const bool colok = A >= 0 && A <= h;
+    const int W = m / 2 + 1;
+    const size_t wc = (size_t)(h + 1);
+    auto ldv = [&](int B, bool ok) -> T { return (ok && colok && B >= 0 && B <= h) ? vA2[(size_t)B * wc + A] : T(0); };
+    auto ldr = [&](int row, bool ok) -> T {
+        return (ok && colok && A <= h - 1 + ((row & 1) ? 0 : 1) && row >= 0 && row <= m) ? rD[(size_t)row * W + A] : T(0);
+    };
+    T vb = ldv(B0 >= 1 ? B0 - 1 : 0, true);
+    T Fprev = 0;  // F of the odd row 2B-1
+    if (B0 >= 1) {
+        T vn = ldv(B0, true);
+        T rf = ldr(2 * B0 - 1, true);
+        T vb_e = __shfl_down(vb, 1), vn_e = __shfl_down(vn, 1);
+        Fprev = (-cc * rf + vb + vb_e + vn_e + vn) * T(0.25);
+        vb = vn;
+    }
+    struct Ck { T v[CH], rf[CH], rc[CH]; };
+    auto load = [&](int Bb, Ck& q) {
+#pragma unroll
+        for (int i = 0; i < CH; i++) {
+            int B = Bb + i;
+            bool in = B < B1;
+            q.v[i] = ldv(B + 1, in);
+            q.rf[i] = ldr(2 * B + 1, in);
+            q.rc[i] = ldr(2 * B, in);
+        }
+    };
+    auto proc = [&](int Bb, const Ck& q) {
+#pragma unroll
+        for (int i = 0; i < CH; i++) {
+            int B = Bb + i;
+            if (B >= B1) break;
+            T vn = q.v[i];
+            T vb_e = __shfl_down(vb, 1), vn_e = __shfl_down(vn, 1);
+            // v_{i-1,j-1} + v_{i+1,j-1} + v_{i+1,j+1} + v_{i-1,j+1} on the coarse grid
+            T F = (-cc * q.rf[i] + vb + vb_e + vn_e + vn) * T(0.25);
+            T Fw = __shfl_up(F, 1), Fpw = __shfl_up(Fprev, 1);
+            if (useful) {
+                vD[(size_t)(2 * B + 1) * W + A] = F;
+                if (B >= 1 && A >= 1) vD[(size_t)(2 * B) * W + A] = (-cc * q.rc[i] + Fpw + Fprev + F + Fw) * T(0.25);
+            }
+            Fprev = F;
+            vb = vn;
+        }
+    };
+    rows_march<CH, Ck>(B0, B1 - 1, load, proc);
+}
+
+// axis-grid Jacobi of a coarser level (stores v)
+template <typename T, int CH>
+__global__ void __launch_bounds__(kRowBlock) kb_jaxis_rows(int m, T cc, const Item2<T>* __restrict__ items, int nwx,
+                                                           int nwaves, int rows, const Ctl* __restrict__ ctls)
+{
+    const Item2<T> it = items[blockIdx.y];
+    ITEM_GATE(ctls, it.prob);
+    jaxis_body<T, false, CH>(m, cc, it.r, it.in, it.v, nullptr, nwx, nwaves, rows);
+}
+
+// ------------------------------------------------------ one thread per point
+template <typename T>
+__global__ void __launch_bounds__(256) kb_rs_a2d(int m, const Item2<T>* __restrict__ items, const Ctl* __restrict__ ctls)
+{
+    const Item2<T> it = items[blockIdx.z];
+    ITEM_GATE(ctls, it.prob);
+    int col = blockIdx.x * blockDim.x + threadIdx.x;
+    int b = blockIdx.y + 1;
+    if (col > m / 2 || b >= m) return;
+    int a = 2 * col + (b & 1);
+    if (a < 1 || a >= m) return;
+    it.r[idxD(m, a, b)] = rs2_a2d(it.in, m, a, b);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) kb_rs_d2a(int m, const Item2<T>* __restrict__ items, const Ctl* __restrict__ ctls)
+{
+    const Item2<T> it = items[blockIdx.z];
+    ITEM_GATE(ctls, it.prob);
+    int mc = m / 2;
+    int A = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    int B = blockIdx.y + 1;
+    if (A >= mc || B >= mc) return;
+    it.r[idxA(mc, A, B)] = rs2_d2a(it.in, m, A, B);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) kb_jac_diag(int m, T cc, const Item2<T>* __restrict__ items,
+                                                   const Ctl* __restrict__ ctls)
+{
+    const Item2<T> it = items[blockIdx.z];
+    ITEM_GATE(ctls, it.prob);
+    int A = blockIdx.x * blockDim.x + threadIdx.x;
+    int B = blockIdx.y;
+    int h = m / 2;
+    if (A >= h || B >= h) return;
+    int a = 2 * A + 1, b = 2 * B + 1;
+    it.v[idxD(m, a, b)] = jac2_diagF(it.r, it.in, m, cc, a, b);
+    if (A >= 1 && B >= 1) it.v[idxD(m, 2 * A, 2 * B)] = jac2_diagC(it.r, it.in, m, cc, 2 * A, 2 * B);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) kb_jac_axis(int m, T cc, const Item2<T>* __restrict__ items,
+                                                   const Ctl* __restrict__ ctls)
+{
+    const Item2<T> it = items[blockIdx.z];
+    ITEM_GATE(ctls, it.prob);
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int b = blockIdx.y + 1;
+    if (t > m / 2 || b >= m) return;
+    int aC = 2 * t + (b & 1), aF = 2 * t + 1 - (b & 1);
+    if (aF >= 1 && aF < m) it.v[idxA(m, aF, b)] = jac2_axisF(it.r, it.in, m, cc, aF, b);
+    if (aC >= 1 && aC < m) it.v[idxA(m, aC, b)] = jac2_axisC(it.r, it.in, m, cc, aC, b);
+}
+
+// ------------------------------------------------------------ coarse levels
+// Aligned levels top .. 0 of one problem per workgroup: restriction down to
+// the 3x3 grid, its Jacobi from a zero correction, Jacobi back up to top.
+template <typename T>
+struct CoarseLev {
+    LevInfo<T> l[kCoarseLevels];
+};
+constexpr int kCoarseThreadsB = 1024;
+
+template <typename T>
+__global__ void __launch_bounds__(kCoarseThreadsB) kb_coarse(CoarseLev<T> L, const Coarse2B<T>* __restrict__ items,
+                                                             const T* __restrict__ zero, const Ctl* __restrict__ ctls)
+{
+    const Coarse2B<T>& it = items[blockIdx.x];
+    ITEM_GATE(ctls, it.prob);
+    const int top = it.top;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int lam = top - 1; lam >= 0; lam--) {   // restriction into lam from lam+1
+        const LevInfo<T>& Fi = L.l[lam + 1];
+        const T* rf = it.r[lam + 1];
+        T* rc = it.r[lam];
+        int m = Fi.m;
+        if (!Fi.diag) {  // axis -> diagonal, same side
+            int w = m / 2 + 1;
+            for (int q = tid; q < w * (m - 1); q += nt) {
+                int col = q % w, b = q / w + 1;
+                int a = 2 * col + (b & 1);
+                if (a >= 1 && a < m) rc[idxD(m, a, b)] = rs2_a2d(rf, m, a, b);
+            }
+        } else {         // diagonal -> axis of side m/2
+            int mc = m / 2;
+            for (int q = tid; q < (mc - 1) * (mc - 1); q += nt) {
+                int A = q % (mc - 1) + 1, B = q / (mc - 1) + 1;
+                rc[idxA(mc, A, B)] = rs2_d2a(rf, m, A, B);
+            }
+        }
+        __syncthreads();
+    }
+    for (int lam = 0; lam <= top; lam++) {
+        const LevInfo<T>& Li = L.l[lam];
+        const T* vc = lam == 0 ? zero : it.v[lam - 1];
+        const T* r = it.r[lam];
+        T* v = it.v[lam];
+        int m = Li.m;
+        T cc = Li.c;
+        if (Li.diag) {
+            int h = m / 2;
+            for (int q = tid; q < h * h; q += nt) {
+                int A = q % h, B = q / h;
+                v[idxD(m, 2 * A + 1, 2 * B + 1)] = jac2_diagF(r, vc, m, cc, 2 * A + 1, 2 * B + 1);
+                if (A >= 1 && B >= 1) v[idxD(m, 2 * A, 2 * B)] = jac2_diagC(r, vc, m, cc, 2 * A, 2 * B);
+            }
+        } else {
+            int w = m / 2 + 1;
+            for (int q = tid; q < w * (m - 1); q += nt) {
+                int t = q % w, b = q / w + 1;
+                int aC = 2 * t + (b & 1), aF = 2 * t + 1 - (b & 1);
+                if (aF >= 1 && aF < m) v[idxA(m, aF, b)] = jac2_axisF(r, vc, m, cc, aF, b);
+                if (aC >= 1 && aC < m) v[idxA(m, aC, b)] = jac2_axisC(r, vc, m, cc, aC, b);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ================================================================ decisions
+// Per-problem norm and stopping decision (Section 1): one workgroup per
+// problem sums its partials in a fixed order.  kind 0: ||f|| into fnorm;
+// kind 1: relative residual of evaluation ctl.k, then stop when it is <= rtol,
+// not finite, grew three times in a row above the start, or after
+// max_cycles cycles.  A problem that stops decrements *nactive.
+template <typename T>
+__global__ void __launch_bounds__(256) kb_finalize(int kind, const Fin2<T>* __restrict__ items, int nparts,
+                                                   Ctl* __restrict__ ctls, int* __restrict__ nactive)
+{
+    const Fin2<T> it = items[blockIdx.x];
+    Ctl* c = &ctls[it.prob];
+    if (c->done) return;
+    __shared__ double red[256];
+    double s = 0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += it.part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    double tot = red[0];
+    if (kind == 0) {
+        c->fnorm = sqrt(tot);
+        return;
+    }
+    int k = c->k;  // evaluation index = cycles run so far
+    double rn = sqrt(tot);
+    double rr = c->fnorm > 0 ? rn / c->fnorm : rn;
+    c->last = rr;
+    if (k <= kMaxCycles) c->hist[k] = rr;
+    c->k = k + 1;
+    if (c->mode == 0) return;
+    int finite = isfinite(rr);
+    if (k == 0) {
+        c->rr0 = rr;
+        c->prev = rr;
+        c->grow = 0;
+        if (rr <= c->rtol) { c->status = 0; c->done = 1; }
+        else if (c->max_cycles == 0) { c->status = -8; c->done = 1; }
+        else if (!finite) { c->status = -6; c->done = 1; }
+    } else {
+        if (!finite) { c->status = -6; c->done = 1; }
+        else {
+            c->grow = (rr > c->prev) ? c->grow + 1 : 0;
+            c->prev = rr;
+            if (c->grow >= 3 && rr > c->rr0) { c->status = -7; c->done = 1; }
+            else if (rr <= c->rtol) { c->status = 0; c->done = 1; }
+            else if (k >= c->max_cycles) { c->status = -8; c->done = 1; }
+        }
+    }
+    if (c->done) {
+        c->cycles = k;
+        atomicSub(nactive, 1);
+    }
+}
+
+__global__ void kb_ctl_reset(Ctl* ctls, int nprob, int mode, int max_cycles, double rtol, int* nactive)
+{
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p == 0) *nactive = nprob;
+    if (p >= nprob) return;
+    Ctl* c = &ctls[p];
+    c->done = 0;
+    c->status = 0;
+    c->cycles = 0;
+    c->grow = 0;
+    c->mode = mode;
+    c->max_cycles = max_cycles;
+    c->k = 0;
+    c->rtol = rtol;
+    c->fnorm = 0;
+    c->rr0 = c->prev = c->last = 0;
+}
+
+template <typename T>
+void launch_b_finalize(int kind, const Fin2<T>* items, int nitems, int nparts, Ctl* ctls, int* nactive, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_finalize<T>, dim3(nitems), dim3(256), 0, s, kind, items, nparts, ctls, nactive);
+}
+
+void launch_b_ctl_reset(Ctl* ctls, int nprob, int mode, int max_cycles, double rtol, int* nactive, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_ctl_reset, dim3((nprob + 255) / 256), dim3(256), 0, s, ctls, nprob, mode, max_cycles, rtol,
+                       nactive);
+}
+
+// level -> natural double array (parity tests)
+template <typename T>
+__global__ void kb_level_get(int diag, int m, const T* __restrict__ src, double* __restrict__ dst)
+{
+    int a = blockIdx.x * blockDim.x + threadIdx.x;
+    int b = blockIdx.y;
+    if (a > m || b > m) return;
+    double x = 0;
+    if (!diag) x = (double)src[idxA(m, a, b)];
+    else if (((a + b) & 1) == 0) x = (double)src[idxD(m, a, b)];
+    dst[idxA(m, a, b)] = x;
+}
+
+template <typename T>
+void launch_b_level_get(int diag, int m, const T* src, double* dst, hipStream_t s)
+{
+    dim3 g((m + 1 + 255) / 256, m + 1);
+    hipLaunchKernelGGL(kb_level_get<T>, g, dim3(256), 0, s, diag, m, src, dst);
+}
+
+// ================================================================= launchers
+constexpr int kChunkResid = 2, kChunkA2D = 1, kChunkD2A = 4, kChunkJDiag = 2, kChunkJAxis = 1;
+constexpr int kTargetWavesResid = 8192;  // ~120 VGPRs: 16 waves per CU
+constexpr int kRowsMinSide = 512;        // smaller levels: one thread per point
+
+// Strip length: the longest (fewest halo rows) that still gives the grid
+// about `target` waves, so every wave is resident in one round.
+static inline int pick_rows(int ncols_units, int per_wave, int nrows, int target = kTargetWaves)
+{
+    int nwx = (ncols_units + per_wave - 1) / per_wave;
+    int r = kMaxRows;
+    while (r > 4 && (long)nwx * ((nrows + r - 1) / r) < target) r >>= 1;
+    return r;
+}
+
+static inline void rows_grid(int ncols_units, int per_wave, int nrows, int rows, int& nwx, int& nwaves, int& nblocks)
+{
+    nwx = (ncols_units + per_wave - 1) / per_wave;
+    int nsy = (nrows + rows - 1) / rows;
+    nwaves = nwx * nsy;
+    nblocks = (nwaves + kWavesPerBlock - 1) / kWavesPerBlock;
+}
+
+// kind: 0 a2d restriction, 1 d2a restriction, 2 diagonal Jacobi, 3 axis Jacobi
+int b_default_rows(int kind, int m)
+{
+    if (m < kRowsMinSide) return 0;
+    switch (kind) {
+    case 0: return pick_rows(m / 2 + 1, kPairsPerWave, m - 1);
+    case 1: return pick_rows(m / 2 + 1, kColsPerWave, m / 2 - 1);
+    case 2: return pick_rows(m / 2, kPairsPerWave, m / 2);
+    default: return pick_rows(m / 2 + 1, kPairsPerWave, m - 1);
+    }
+}
+
+int b_resid_parts(int n)
+{
+    if (n < 4) return 1;
+    int nwx, nw, nb;
+    rows_grid(n / 2 + 1, kPairsPerWave, n - 1, pick_rows(n / 2 + 1, kPairsPerWave, n - 1, kTargetWavesResid), nwx,
+              nw, nb);
+    return nb;
+}
+
+template <typename T>
+void launch_b_resid(int n, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s)
+{
+    double inv_h2 = (double)n * (double)n;
+    if (n < 4) {
+        hipLaunchKernelGGL(kb_resid_small<T>, dim3(1, nitems), dim3(kRowBlock), 0, s, n, inv_h2, items, ctls);
+        return;
+    }
+    int nwx, nw, nb;
+    int rows = pick_rows(n / 2 + 1, kPairsPerWave, n - 1, kTargetWavesResid);
+    rows_grid(n / 2 + 1, kPairsPerWave, n - 1, rows, nwx, nw, nb);
+    hipLaunchKernelGGL((kb_resid<T, kChunkResid>), dim3(nb, nitems), dim3(kRowBlock), 0, s, n, inv_h2, items, nwx,
+                       nw, rows, ctls);
+}
+
+template <typename T>
+void launch_b_sumsq(int n, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_sumsq<T>, dim3(b_resid_parts(n), nitems), dim3(kRowBlock), 0, s, n, items, ctls);
+}
+
+template <typename T>
+void launch_b_finest(int n, T c, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s)
+{
+    if (n < 8) {
+        hipLaunchKernelGGL(kb_finest_small<T>, dim3(1, nitems), dim3(kRowBlock), 0, s, n, c, items, ctls);
+        return;
+    }
+    int nwx, nw, nb;
+    int rows = pick_rows(n / 2 + 1, kPairsPerWave, n - 1);
+    rows_grid(n / 2 + 1, kPairsPerWave, n - 1, rows, nwx, nw, nb);
+    hipLaunchKernelGGL((kb_finest<T, kChunkJAxis>), dim3(nb, nitems), dim3(kRowBlock), 0, s, n, c, items, nwx, nw,
+                       rows, ctls);
+}
+
+template <typename T>
+void launch_b_restrict(int diag_in, int m, int rows, const Item2<T>* items, int nitems, const Ctl* ctls,
+                       hipStream_t s)
+{
+    int nwx, nw, nb;
+    if (!diag_in) {
+        if (rows <= 0) {
+            dim3 g((m / 2 + 1 + 255) / 256, m - 1, nitems);
+            hipLaunchKernelGGL(kb_rs_a2d<T>, g, dim3(256), 0, s, m, items, ctls);
+            return;
+        }
+        rows_grid(m / 2 + 1, kPairsPerWave, m - 1, rows, nwx, nw, nb);
+        hipLaunchKernelGGL((kb_a2d_rows<T, kChunkA2D>), dim3(nb, nitems), dim3(kRowBlock), 0, s, m, items, nwx, nw,
+                           rows, ctls);
+    } else {
+        int mc = m / 2;
+        if (mc < 2) return;
+        if (rows <= 0) {
+            dim3 g((mc - 1 + 255) / 256, mc - 1, nitems);
+            hipLaunchKernelGGL(kb_rs_d2a<T>, g, dim3(256), 0, s, m, items, ctls);
+            return;
+        }
+        rows_grid(m / 2 + 1, kColsPerWave, m / 2 - 1, rows, nwx, nw, nb);
+        hipLaunchKernelGGL((kb_d2a_rows<T, kChunkD2A>), dim3(nb, nitems), dim3(kRowBlock), 0, s, m, items, nwx, nw,
+                           rows, ctls);
+    }
+}
+
+template <typename T>
+void launch_b_jacobi(int diag, int m, int rows, T c, const Item2<T>* items, int nitems, const Ctl* ctls,
+                     hipStream_t s)
+{
+    int nwx, nw, nb;
+    if (diag) {
+        if (rows <= 0) {
+            dim3 g((m / 2 + 255) / 256, m / 2, nitems);
+            hipLaunchKernelGGL(kb_jac_diag<T>, g, dim3(256), 0, s, m, c, items, ctls);
+            return;
+        }
+        rows_grid(m / 2, kPairsPerWave, m / 2, rows, nwx, nw, nb);
+        hipLaunchKernelGGL((kb_jdiag_rows<T, kChunkJDiag>), dim3(nb, nitems), dim3(kRowBlock), 0, s, m, c, items, nwx,
+                           nw, rows, ctls);
+    } else {
+        if (rows <= 0) {
+            dim3 g((m / 2 + 1 + 255) / 256, m - 1, nitems);
+            hipLaunchKernelGGL(kb_jac_axis<T>, g, dim3(256), 0, s, m, c, items, ctls);
+            return;
+        }
+        rows_grid(m / 2 + 1, kPairsPerWave, m - 1, rows, nwx, nw, nb);
+        hipLaunchKernelGGL((kb_jaxis_rows<T, kChunkJAxis>), dim3(nb, nitems), dim3(kRowBlock), 0, s, m, c, items, nwx,
+                           nw, rows, ctls);
+    }
+}
+
+template <typename T>
+void launch_b_coarse(const LevInfo<T>* lev, const Coarse2B<T>* items, int nitems, const T* zero, const Ctl* ctls,
+                     hipStream_t s)
+{
+    CoarseLev<T> L;
+    for (int i = 0; i < kCoarseLevels; i++) L.l[i] = lev[i];
+    hipLaunchKernelGGL(kb_coarse<T>, dim3(nitems), dim3(kCoarseThreadsB), 0, s, L, items, zero, ctls);
+}
+
+#define DMG_INSTB(T)                                                                                            \
+    template void launch_b_resid<T>(int, const Fin2<T>*, int, const Ctl*, hipStream_t);                        \
+    template void launch_b_sumsq<T>(int, const Fin2<T>*, int, const Ctl*, hipStream_t);                        \
+    template void launch_b_finest<T>(int, T, const Fin2<T>*, int, const Ctl*, hipStream_t);                    \
+    template void launch_b_restrict<T>(int, int, int, const Item2<T>*, int, const Ctl*, hipStream_t);          \
+    template void launch_b_jacobi<T>(int, int, int, T, const Item2<T>*, int, const Ctl*, hipStream_t);         \
+    template void launch_b_coarse<T>(const LevInfo<T>*, const Coarse2B<T>*, int, const T*, const Ctl*, hipStream_t); \
+    template void launch_b_finalize<T>(int, const Fin2<T>*, int, int, Ctl*, int*, hipStream_t);                \
+    template void launch_b_level_get<T>(int, int, const T*, double*, hipStream_t);
+DMG_INSTB(double)
+DMG_INSTB(float)
+
+}  // namespace dmg

@@ -1,0 +1,79 @@
+// Work items of the 2D kernels.  Every 2D launch processes a list of
+// independent problems: blockIdx.y (point kernels: blockIdx.z) selects the
+// item, so one launch per level serves a whole batch, and a single problem
+// is a batch of one.  Levels are aligned from the coarsest grid: at aligned
+// level lambda every problem's grid has the same side and kind, whatever its
+// finest size.
+#pragma once
+#include "dmg_common.hpp"
+
+namespace dmg {
+
+// one problem's arrays at one level
+template <typename T>
+struct Item2 {
+    T* r;          // residual of this level (restriction output, Jacobi input)
+    T* v;          // correction of this level (Jacobi output)
+    const T* in;   // restriction: residual of the finer level; Jacobi: correction of the coarser level
+    int prob;      // problem index: ctl[prob].done skips the item
+    int pad;
+};
+
+// one problem's finest-level arrays
+template <typename T>
+struct Fin2 {
+    double* u;
+    const double* f;
+    T* r0;         // finest residual (natural layout)
+    T* r1;         // residual of the first diagonal level (written by the fused residual)
+    const T* v1;   // correction of the first diagonal level (or a zero array)
+    double* part;  // norm partial sums of this problem
+    int prob;
+    int pad;
+};
+
+// one problem's coarse levels (aligned levels 0 .. top, side <= the coarse limit)
+constexpr int kCoarseLevels = 10;
+template <typename T>
+struct Coarse2B {
+    T* r[kCoarseLevels];
+    T* v[kCoarseLevels];
+    int top;       // highest aligned level run by the coarse kernel (-1: none)
+    int prob;
+};
+
+// per aligned level (the same for every problem at that level)
+template <typename T>
+struct LevInfo {
+    int m;
+    int diag;
+    T c;
+};
+
+template <typename T>
+void launch_b_resid(int n, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s);
+int b_resid_parts(int n);
+template <typename T>
+void launch_b_finest(int n, T c, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s);
+template <typename T>
+void launch_b_restrict(int diag_in, int m, int rows, const Item2<T>* items, int nitems, const Ctl* ctls,
+                       hipStream_t s);
+template <typename T>
+void launch_b_jacobi(int diag, int m, int rows, T c, const Item2<T>* items, int nitems, const Ctl* ctls,
+                     hipStream_t s);
+template <typename T>
+void launch_b_coarse(const LevInfo<T>* lev, const Coarse2B<T>* items, int nitems, const T* zero, const Ctl* ctls,
+                     hipStream_t s);
+// sum of f^2 over interior nodes per problem, into the problem's partials (b_resid_parts(n) of them)
+template <typename T>
+void launch_b_sumsq(int n, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s);
+template <typename T>
+void launch_b_finalize(int kind, const Fin2<T>* items, int nitems, int nparts, Ctl* ctls, int* nactive,
+                       hipStream_t s);
+void launch_b_ctl_reset(Ctl* ctls, int nprob, int mode, int max_cycles, double rtol, int* nactive, hipStream_t s);
+template <typename T>
+void launch_b_level_get(int diag, int m, const T* src, double* dst, hipStream_t s);
+// default strip length of a row-marching launch (0: use the one-thread-per-point kernel)
+int b_default_rows(int kind, int m);
+
+}  // namespace dmg

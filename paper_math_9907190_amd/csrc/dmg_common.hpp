@@ -71,7 +71,8 @@ struct Ctl {
     int grow;        // consecutive cycles with a growing residual
     int mode;        // 0: single cycle (never sets done); 1: solve
     int max_cycles;
-    int pad0, pad1;
+    int k;           // evaluations done so far (batched path)
+    int pad1;
     double rtol;
     double fnorm;    // ||f||_2 over interior nodes
     double rr0, prev;

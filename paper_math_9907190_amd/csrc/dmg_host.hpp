@@ -1,0 +1,111 @@
+// Host-side helpers shared by the 2D and 3D plans of libdmg: device guard,
+// HIP-event timing of one kernel family, error mapping.
+#pragma once
+#include "../../include/dmg.h"
+#include "dmg_common.hpp"
+
+namespace dmg {
+
+constexpr int kTimedMax = 64;
+
+// Timing of one kernel family (mg_timing_enable / mg_timing_read): every
+// launch of that family is bracketed by two events on the plan's stream.
+struct Timing {
+    int fam = -1;
+    int pend = 0;
+    bool ev = false;
+    hipEvent_t beg[kTimedMax], end[kTimedMax];
+    double ms = 0, bytes = 0;
+    long long count = 0;
+    hipStream_t stream = nullptr;
+
+    void flush()
+    {
+        for (int i = 0; i < pend; i++) {
+            float t = 0;
+            if (hipEventSynchronize(end[i]) == hipSuccess && hipEventElapsedTime(&t, beg[i], end[i]) == hipSuccess)
+                ms += t;
+        }
+        pend = 0;
+    }
+    int enable(int family)
+    {
+        if (family >= 0 && !ev) {
+            for (int i = 0; i < kTimedMax; i++)
+                if (hipEventCreate(&beg[i]) != hipSuccess || hipEventCreate(&end[i]) != hipSuccess) return MG_ERR_HIP;
+            ev = true;
+        }
+        if (ev) flush();
+        fam = family;
+        ms = bytes = 0;
+        count = 0;
+        return MG_OK;
+    }
+    void read(double* oms, long long* ocount, double* obytes)
+    {
+        if (ev) flush();
+        if (oms) *oms = ms;
+        if (ocount) *ocount = count;
+        if (obytes) *obytes = bytes;
+        ms = bytes = 0;
+        count = 0;
+    }
+    void destroy()
+    {
+        if (!ev) return;
+        flush();
+        for (int i = 0; i < kTimedMax; i++) {
+            (void)hipEventDestroy(beg[i]);
+            (void)hipEventDestroy(end[i]);
+        }
+        ev = false;
+    }
+};
+
+// Brackets one launch with events when its family is the measured one.
+struct Timed {
+    Timing* T;
+    bool on;
+    Timed(Timing* t, int fam, double bytes) : T(t), on(t->ev && t->fam == fam)
+    {
+        if (!on) return;
+        if (T->pend == kTimedMax) T->flush();
+        (void)hipEventRecord(T->beg[T->pend], T->stream);
+        T->bytes += bytes;
+        T->count++;
+    }
+    ~Timed()
+    {
+        if (on) (void)hipEventRecord(T->end[T->pend++], T->stream);
+    }
+};
+
+struct DevGuard {
+    int old = -1;
+    bool ok = true;
+    explicit DevGuard(int dev)
+    {
+        if (hipGetDevice(&old) != hipSuccess) { ok = false; return; }
+        if (old != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DevGuard()
+    {
+        if (old >= 0) {
+            int cur;
+            if (hipGetDevice(&cur) == hipSuccess && cur != old) (void)hipSetDevice(old);
+        }
+    }
+};
+
+inline int hip_status(hipError_t e) { return e == hipSuccess ? MG_OK : MG_ERR_HIP; }
+inline int last_launch() { return hip_status(hipGetLastError()); }
+
+inline int ilog2(int n)
+{
+    if (n < 2) return -1;
+    int k = 0;
+    while ((1 << k) < n) k++;
+    return ((1 << k) == n) ? k : -1;
+}
+
+}  // namespace dmg

@@ -168,7 +168,3 @@ template <typename T>
 void launch_level_get3(int kind, int m, const T* src, const T* src2, double* dst, hipStream_t s);
 
 }  // namespace dmg
-
-struct mg_plan;
-template <typename T>
-void enqueue_cycle_3d(mg_plan* P, double* u, const dmg::Ctl* ctl);

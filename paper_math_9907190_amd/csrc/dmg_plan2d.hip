@@ -1,0 +1,607 @@
+// Host runtime of the 2D solver (Roberts, Section 2): a plan for a batch of
+// independent problems (a single problem is a batch of one).
+//
+// Levels are aligned from the coarsest grid: at aligned level lambda every
+// problem's grid has side 2^(1+ceil(lambda/2)) (axis grid for even lambda,
+// diagonal grid for odd) and the same Jacobi coefficient, so one launch per
+// level serves every problem that has that level.  The launches read their
+// arrays from item tables in the workspace; a per-problem done flag makes a
+// converged problem's items return at once.
+//
+// One outer iteration (cycle + next residual + stopping decision) is captured
+// once in a hipGraph and replayed; its kernel arguments never change (the u and
+// f pointers are read from a table updated before each solve).  The host
+// launches iteration k+1 before it reads the number of active problems left
+// by iteration k, so the GPU never waits for the host round trip; the one
+// iteration launched after the last problem stops runs as gated no-ops.
+#include "dmg_b2d.hpp"
+#include "dmg_host.hpp"
+#include "dmg_plan2d.hpp"
+
+#include <algorithm>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+namespace dmg {
+
+namespace {
+
+constexpr int kCoarseSide2 = 32;  // aligned levels of side <= this run in the coarse kernel
+constexpr int kMaxSide2 = 1 << 15;
+
+int side_of(int lam) { return 1 << (1 + (lam + 1) / 2); }
+
+}  // namespace
+
+int plan2_layout(Plan2& P, int nprob, const int* n, int prec, double p)
+{
+    if (nprob < 1 || !n) return MG_ERR_ARG;
+    if (prec != MG_FP64 && prec != MG_FP32_REFINED) return MG_ERR_ARG;
+    P.nprob = nprob;
+    P.prec = prec;
+    P.p = p;
+    P.n.assign(n, n + nprob);
+    P.D.resize(nprob);
+    P.Dmax = 0;
+    for (int i = 0; i < nprob; i++) {
+        int K = ilog2(n[i]);
+        if (K < 1 || n[i] > kMaxSide2) return MG_ERR_SIZE;
+        P.D[i] = 2 * (K - 1);
+        P.Dmax = std::max(P.Dmax, P.D[i]);
+    }
+    P.lamc = 0;
+    while (side_of(P.lamc + 1) <= kCoarseSide2) P.lamc++;
+    size_t es = prec == MG_FP64 ? 8 : 4;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = alignUp(off + bytes);
+        return o;
+    };
+    // size classes (distinct n, ascending); fin-table slots grouped by class
+    std::vector<int> ord(nprob);
+    for (int i = 0; i < nprob; i++) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return n[a] < n[b]; });
+    P.order = ord;
+    P.cls_n.clear(); P.cls_first.clear(); P.cls_count.clear(); P.nparts.clear();
+    for (int s = 0; s < nprob; s++) {
+        int nn = n[ord[s]];
+        if (P.cls_n.empty() || P.cls_n.back() != nn) {
+            P.cls_n.push_back(nn);
+            P.cls_first.push_back(s);
+            P.cls_count.push_back(0);
+            P.nparts.push_back(b_resid_parts(nn));
+        }
+        P.cls_count.back()++;
+    }
+    P.off_ctl = take(sizeof(Ctl) * (size_t)nprob);
+    P.off_nactive = take(sizeof(int) * 4);
+    P.off_zero = take(sizeof(double) * 64);
+    P.off_fin = take(sizeof(Fin2<double>) * (size_t)nprob);
+    P.off_coarse = take(sizeof(Coarse2B<double>) * (size_t)nprob);
+    P.off_rs_items.assign(P.Dmax + 1, 0);
+    P.off_jac_items.assign(P.Dmax + 1, 0);
+    P.n_rs_items.assign(P.Dmax + 1, 0);
+    P.n_jac_items.assign(P.Dmax + 1, 0);
+    for (int lam = 0; lam <= P.Dmax; lam++) {
+        for (int i = 0; i < nprob; i++) {
+            int Dp = P.D[i];
+            int top = std::min(P.lamc, Dp - 1);
+            if (Dp >= 1 && lam >= top && lam <= Dp - 2) P.n_rs_items[lam]++;   // restriction into lam
+            if (Dp >= 1 && lam >= top + 1 && lam <= Dp - 1) P.n_jac_items[lam]++;  // Jacobi at lam
+        }
+        if (P.n_rs_items[lam]) P.off_rs_items[lam] = take(sizeof(Item2<double>) * (size_t)P.n_rs_items[lam]);
+        if (P.n_jac_items[lam]) P.off_jac_items[lam] = take(sizeof(Item2<double>) * (size_t)P.n_jac_items[lam]);
+    }
+    P.n_coarse_items = 0;
+    for (int i = 0; i < nprob; i++)
+        if (P.D[i] >= 1) P.n_coarse_items++;
+    P.off_r0.resize(nprob);
+    P.off_part.resize(nprob);
+    P.off_r.assign(nprob, {});
+    P.off_v.assign(nprob, {});
+    for (int s = 0; s < nprob; s++) {
+        int i = ord[s];
+        int m = n[i];
+        size_t cnt = sizeA(m);
+        P.off_r0[i] = take(es * cnt);
+        int cls = (int)(std::lower_bound(P.cls_n.begin(), P.cls_n.end(), m) - P.cls_n.begin());
+        P.off_part[i] = take(sizeof(double) * (size_t)P.nparts[cls]);
+        P.off_r[i].assign(std::max(P.D[i], 1), 0);
+        P.off_v[i].assign(std::max(P.D[i], 1), 0);
+        for (int lam = P.D[i] - 1; lam >= 0; lam--) {
+            int ms = side_of(lam);
+            size_t c = (lam & 1) ? sizeD(ms) : sizeA(ms);
+            P.off_r[i][lam] = take(es * c);
+            P.off_v[i][lam] = take(es * c);
+        }
+    }
+    P.rows_rs.assign(P.Dmax + 1, 0);
+    P.rows_jac.assign(P.Dmax + 1, 0);
+    for (int lam = 0; lam <= P.Dmax; lam++) {
+        // restriction into lam reads level lam+1
+        int mf = side_of(lam + 1);
+        P.rows_rs[lam] = b_default_rows(((lam + 1) & 1) ? 1 : 0, mf);
+        P.rows_jac[lam] = b_default_rows((lam & 1) ? 2 : 3, side_of(lam));
+    }
+    P.total = off;
+    return MG_OK;
+}
+
+namespace {
+
+template <typename T>
+T* at(Plan2& P, size_t off) { return reinterpret_cast<T*>(P.ws + off); }
+
+double coef(const Plan2& P, int lam)
+{
+    double sh = 1.0 / side_of(lam);   // sigma * h
+    return (lam & 1) ? 2 * P.p * sh * sh : P.p * sh * sh;
+}
+
+// host images of the item tables (pointers into the workspace)
+template <typename T>
+int write_tables(Plan2& P)
+{
+    std::vector<Item2<T>> items;
+    T* zero = at<T>(P, P.off_zero);
+    for (int lam = 0; lam <= P.Dmax; lam++) {
+        items.clear();
+        for (int i = 0; i < P.nprob; i++) {
+            int Dp = P.D[i];
+            int top = std::min(P.lamc, Dp - 1);
+            if (Dp >= 1 && lam >= top && lam <= Dp - 2)
+                items.push_back(Item2<T>{at<T>(P, P.off_r[i][lam]), at<T>(P, P.off_v[i][lam]),
+                                         at<T>(P, P.off_r[i][lam + 1]), i, 0});
+        }
+        if (!items.empty() &&
+            hipMemcpy(P.ws + P.off_rs_items[lam], items.data(), items.size() * sizeof(Item2<T>), hipMemcpyHostToDevice) != hipSuccess)
+            return MG_ERR_HIP;
+        items.clear();
+        for (int i = 0; i < P.nprob; i++) {
+            int Dp = P.D[i];
+            int top = std::min(P.lamc, Dp - 1);
+            if (Dp >= 1 && lam >= top + 1 && lam <= Dp - 1)
+                items.push_back(Item2<T>{at<T>(P, P.off_r[i][lam]), at<T>(P, P.off_v[i][lam]),
+                                         lam >= 1 ? at<T>(P, P.off_v[i][lam - 1]) : zero, i, 0});
+        }
+        if (!items.empty() &&
+            hipMemcpy(P.ws + P.off_jac_items[lam], items.data(), items.size() * sizeof(Item2<T>), hipMemcpyHostToDevice) != hipSuccess)
+            return MG_ERR_HIP;
+    }
+    std::vector<Coarse2B<T>> co;
+    for (int i = 0; i < P.nprob; i++) {
+        if (P.D[i] < 1) continue;
+        Coarse2B<T> c;
+        memset(&c, 0, sizeof(c));
+        c.top = std::min(P.lamc, P.D[i] - 1);
+        c.prob = i;
+        for (int lam = 0; lam <= c.top; lam++) {
+            c.r[lam] = at<T>(P, P.off_r[i][lam]);
+            c.v[lam] = at<T>(P, P.off_v[i][lam]);
+        }
+        co.push_back(c);
+    }
+    if (!co.empty() && hipMemcpy(P.ws + P.off_coarse, co.data(), co.size() * sizeof(Coarse2B<T>), hipMemcpyHostToDevice) != hipSuccess)
+        return MG_ERR_HIP;
+    // finest items (u, f filled per call), in class order
+    Fin2<T>* hf = reinterpret_cast<Fin2<T>*>(P.hfin);
+    for (int s = 0; s < P.nprob; s++) {
+        int i = P.order[s];
+        Fin2<T> x;
+        memset(&x, 0, sizeof(x));
+        x.r0 = at<T>(P, P.off_r0[i]);
+        x.r1 = P.D[i] >= 1 ? at<T>(P, P.off_r[i][P.D[i] - 1]) : nullptr;
+        x.v1 = P.D[i] >= 1 ? at<T>(P, P.off_v[i][P.D[i] - 1]) : zero;
+        x.part = at<double>(P, P.off_part[i]);
+        x.prob = i;
+        hf[s] = x;
+    }
+    return MG_OK;
+}
+
+template <typename T>
+const Fin2<T>* fin_items(Plan2& P, int cls) { return at<Fin2<T>>(P, P.off_fin) + P.cls_first[cls]; }
+
+template <typename T>
+void enq_norm_f(Plan2& P, Ctl* ctls, int* nact)
+{
+    for (size_t c = 0; c < P.cls_n.size(); c++) {
+        launch_b_sumsq<T>(P.cls_n[c], fin_items<T>(P, (int)c), P.cls_count[c], ctls, P.stream);
+        launch_b_finalize<T>(0, fin_items<T>(P, (int)c), P.cls_count[c], P.nparts[c], ctls, nact, P.stream);
+    }
+}
+
+double bytes_resid(int n, size_t es)
+{
+    double inter = (double)(n - 1) * (n - 1), M = n / 2;
+    return 8 * (double)sizeA(n) + 8 * inter + es * inter + (n >= 4 ? es * (M * M + (M - 1) * (M - 1)) : 0);
+}
+double bytes_finest(int n, size_t es)
+{
+    double inter = (double)(n - 1) * (n - 1);
+    return es * (inter + (double)sizeD(n)) + 16 * inter;
+}
+double bytes_rs(int diag_in, int m, size_t es)
+{
+    double M = m / 2;
+    if (!diag_in) return es * ((double)sizeA(m) + M * M + (M - 1) * (M - 1));
+    return es * ((double)sizeD(m) + (M - 1) * (M - 1));
+}
+double bytes_jac(int diag, int m, size_t es)
+{
+    double M = m / 2;
+    if (diag) return es * (2 * (M * M + (M - 1) * (M - 1)) + (double)sizeA(m / 2));
+    return es * (2.0 * (m - 1) * (m - 1) + (double)sizeD(m));
+}
+
+template <typename T>
+void enq_resid(Plan2& P, Ctl* ctls, int* nact)
+{
+    size_t es = sizeof(T);
+    for (size_t c = 0; c < P.cls_n.size(); c++) {
+        {
+            Timed t(&P.tm, MG_K_RESIDUAL, bytes_resid(P.cls_n[c], es) * P.cls_count[c]);
+            launch_b_resid<T>(P.cls_n[c], fin_items<T>(P, (int)c), P.cls_count[c], ctls, P.stream);
+        }
+        Timed t(&P.tm, MG_K_NORM, 8.0 * P.nparts[c] * P.cls_count[c]);
+        launch_b_finalize<T>(1, fin_items<T>(P, (int)c), P.cls_count[c], P.nparts[c], ctls, nact, P.stream);
+    }
+}
+
+template <typename T>
+void enq_cycle(Plan2& P, Ctl* ctls)
+{
+    size_t es = sizeof(T);
+    for (int lam = P.Dmax - 2; lam >= 0; lam--) {
+        int k = P.n_rs_items[lam];
+        if (!k) continue;
+        int diag_in = (lam + 1) & 1;
+        Timed t(&P.tm, MG_K_RESTRICT, bytes_rs(diag_in, side_of(lam + 1), es) * k);
+        launch_b_restrict<T>(diag_in, side_of(lam + 1), P.rows_rs[lam], at<Item2<T>>(P, P.off_rs_items[lam]), k, ctls,
+                             P.stream);
+    }
+    if (P.n_coarse_items) {
+        LevInfo<T> lev[kCoarseLevels];
+        double cb = 0;
+        for (int lam = 0; lam < kCoarseLevels; lam++) {
+            lev[lam].m = side_of(lam);
+            lev[lam].diag = lam & 1;
+            lev[lam].c = (T)coef(P, lam);
+            if (lam <= P.lamc) {
+                cb += bytes_jac(lam & 1, side_of(lam), es);
+                if (lam < P.lamc) cb += bytes_rs((lam + 1) & 1, side_of(lam + 1), es);
+            }
+        }
+        Timed t(&P.tm, MG_K_COARSE, cb * P.n_coarse_items);
+        launch_b_coarse<T>(lev, at<Coarse2B<T>>(P, P.off_coarse), P.n_coarse_items, at<T>(P, P.off_zero), ctls,
+                           P.stream);
+    }
+    for (int lam = 0; lam <= P.Dmax; lam++) {
+        int k = P.n_jac_items[lam];
+        if (!k) continue;
+        Timed t(&P.tm, MG_K_JACOBI, bytes_jac(lam & 1, side_of(lam), es) * k);
+        launch_b_jacobi<T>(lam & 1, side_of(lam), P.rows_jac[lam], (T)coef(P, lam), at<Item2<T>>(P, P.off_jac_items[lam]),
+                           k, ctls, P.stream);
+    }
+    for (size_t c = 0; c < P.cls_n.size(); c++) {
+        int n = P.cls_n[c];
+        Timed t(&P.tm, MG_K_FINEST, bytes_finest(n, es) * P.cls_count[c]);
+        double sh = 1.0 / n;
+        launch_b_finest<T>(n, (T)(P.p * sh * sh), fin_items<T>(P, (int)c), P.cls_count[c], ctls, P.stream);
+    }
+}
+
+// one outer iteration: cycle, the next residual, the stopping decision
+void enq_iteration(Plan2& P)
+{
+    Ctl* ctls = at<Ctl>(P, P.off_ctl);
+    int* nact = at<int>(P, P.off_nactive);
+    if (P.prec == MG_FP64) { enq_cycle<double>(P, ctls); enq_resid<double>(P, ctls, nact); }
+    else { enq_cycle<float>(P, ctls); enq_resid<float>(P, ctls, nact); }
+}
+
+int build_graph(Plan2& P)
+{
+    if (P.gready) return MG_OK;
+    if (!P.cap && hipStreamCreateWithFlags(&P.cap, hipStreamNonBlocking) != hipSuccess) return MG_ERR_HIP;
+    hipStream_t keep = P.stream;
+    P.stream = P.cap;
+    if (hipStreamBeginCapture(P.cap, hipStreamCaptureModeThreadLocal) != hipSuccess) { P.stream = keep; return MG_ERR_HIP; }
+    enq_iteration(P);
+    hipGraph_t g;
+    hipError_t e = hipStreamEndCapture(P.cap, &g);
+    P.stream = keep;
+    if (e != hipSuccess) return MG_ERR_HIP;
+    e = hipGraphInstantiate(&P.gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return MG_ERR_HIP;
+    P.gready = true;
+    return MG_OK;
+}
+
+int run_iteration(Plan2& P)
+{
+    // graphs replay the captured launches; with timing on, launch eagerly so
+    // the events bracket each kernel
+    if (P.use_graph && P.tm.fam < 0) {
+        int e = build_graph(P);
+        if (e) return e;
+        return hip_status(hipGraphLaunch(P.gexec, P.stream));
+    }
+    enq_iteration(P);
+    return last_launch();
+}
+
+// Point the finest-item table at this call's u and f.  The pinned host image
+// is only rewritten after the previous upload from it has completed, and only
+// uploaded when a pointer changed.
+int bind_uf(Plan2& P, double* const* u, const double* const* f)
+{
+    bool same = P.fin_valid;
+    for (int i = 0; same && i < P.nprob; i++) same = P.last_u[i] == u[i] && P.last_f[i] == f[i];
+    if (same) return MG_OK;
+    if (P.fin_valid && hipEventSynchronize(P.evu) != hipSuccess) return MG_ERR_HIP;
+    for (int s = 0; s < P.nprob; s++) {
+        int i = P.order[s];
+        if (P.prec == MG_FP64) {
+            Fin2<double>* hf = reinterpret_cast<Fin2<double>*>(P.hfin);
+            hf[s].u = u[i];
+            hf[s].f = f[i];
+        } else {
+            Fin2<float>* hf = reinterpret_cast<Fin2<float>*>(P.hfin);
+            hf[s].u = u[i];
+            hf[s].f = f[i];
+        }
+    }
+    size_t bytes = (P.prec == MG_FP64 ? sizeof(Fin2<double>) : sizeof(Fin2<float>)) * (size_t)P.nprob;
+    if (hipMemcpyAsync(P.ws + P.off_fin, P.hfin, bytes, hipMemcpyHostToDevice, P.stream) != hipSuccess) return MG_ERR_HIP;
+    if (hipEventRecord(P.evu, P.stream) != hipSuccess) return MG_ERR_HIP;
+    P.last_u.assign(u, u + P.nprob);
+    P.last_f.assign(f, f + P.nprob);
+    P.fin_valid = true;
+    return MG_OK;
+}
+
+}  // namespace
+
+int plan2_setup(Plan2& P, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!ws || ((uintptr_t)ws % kAlign) != 0 || ws_bytes < P.total) return MG_ERR_WS;
+    P.ws = (char*)ws;
+    P.stream = stream;
+    P.tm.stream = stream;
+    if (hipGetDevice(&P.device) != hipSuccess) return MG_ERR_HIP;
+    size_t fb = sizeof(Fin2<double>) * (size_t)P.nprob;
+    if (hipHostMalloc(&P.hfin, fb, hipHostMallocDefault) != hipSuccess) return MG_ERR_HIP;
+    if (hipHostMalloc((void**)&P.hctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) return MG_ERR_HIP;
+    if (hipHostMalloc((void**)&P.hact, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) return MG_ERR_HIP;
+    if (hipHostMalloc((void**)&P.hres, sizeof(double) * 9 * (size_t)P.nprob, hipHostMallocDefault) != hipSuccess)
+        return MG_ERR_HIP;
+    memset(P.hfin, 0, fb);
+    if (hipMemsetAsync(P.ws, 0, P.total, stream) != hipSuccess) return MG_ERR_HIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return MG_ERR_HIP;
+    int e = P.prec == MG_FP64 ? write_tables<double>(P) : write_tables<float>(P);
+    if (e) return e;
+    const char* ng = getenv("DMG_NO_GRAPH");
+    P.use_graph = !(ng && ng[0] == '1');
+    for (int k = 0; k < 2; k++)
+        if (hipEventCreateWithFlags(&P.ev[k], hipEventDisableTiming) != hipSuccess) return MG_ERR_HIP;
+    if (hipEventCreateWithFlags(&P.evu, hipEventDisableTiming) != hipSuccess) return MG_ERR_HIP;
+    P.evs = true;
+    return plan2_tune_load(P);
+}
+
+void plan2_destroy(Plan2& P)
+{
+    P.tm.destroy();
+    if (P.gready) (void)hipGraphExecDestroy(P.gexec);
+    if (P.cap) (void)hipStreamDestroy(P.cap);
+    if (P.evs) {
+        (void)hipStreamSynchronize(P.stream);
+        for (int k = 0; k < 2; k++) (void)hipEventDestroy(P.ev[k]);
+        (void)hipEventDestroy(P.evu);
+    }
+    if (P.hfin) (void)hipHostFree(P.hfin);
+    if (P.hctl) (void)hipHostFree(P.hctl);
+    if (P.hact) (void)hipHostFree(P.hact);
+    if (P.hres) (void)hipHostFree(P.hres);
+}
+
+int plan2_vcycle(Plan2& P, double* const* u, const double* const* f, double* relres)
+{
+    Ctl* ctls = at<Ctl>(P, P.off_ctl);
+    int* nact = at<int>(P, P.off_nactive);
+    int e = bind_uf(P, u, f);
+    if (e) return e;
+    launch_b_ctl_reset(ctls, P.nprob, 0, 0, 0.0, nact, P.stream);
+    if (P.prec == MG_FP64) {
+        if (relres) enq_norm_f<double>(P, ctls, nact);
+        enq_resid<double>(P, ctls, nact);
+        enq_cycle<double>(P, ctls);
+    } else {
+        if (relres) enq_norm_f<float>(P, ctls, nact);
+        enq_resid<float>(P, ctls, nact);
+        enq_cycle<float>(P, ctls);
+    }
+    e = last_launch();
+    if (e) return e;
+    if (relres) {
+        // relative residual of the entry u of every problem
+        if (hipMemcpy2DAsync(P.hres, sizeof(double) * 9, ctls, sizeof(Ctl), sizeof(double) * 9, P.nprob,
+                             hipMemcpyDeviceToHost, P.stream) != hipSuccess)
+            return MG_ERR_HIP;
+        if (hipStreamSynchronize(P.stream) != hipSuccess) return MG_ERR_HIP;
+        for (int i = 0; i < P.nprob; i++) relres[i] = reinterpret_cast<Ctl*>(P.hres + 9 * (size_t)i)->last;
+    }
+    return MG_OK;
+}
+
+int plan2_solve(Plan2& P, double* const* u, const double* const* f, double rtol, int max_cycles, int* cycles,
+                double* relres, int* status, double* history0)
+{
+    Ctl* ctls = at<Ctl>(P, P.off_ctl);
+    int* nact = at<int>(P, P.off_nactive);
+    int e = bind_uf(P, u, f);
+    if (e) return e;
+    launch_b_ctl_reset(ctls, P.nprob, 1, max_cycles, rtol, nact, P.stream);
+    if (P.prec == MG_FP64) { enq_norm_f<double>(P, ctls, nact); enq_resid<double>(P, ctls, nact); }
+    else { enq_norm_f<float>(P, ctls, nact); enq_resid<float>(P, ctls, nact); }
+    if ((e = last_launch())) return e;
+    if (hipMemcpyAsync(&P.hact[0], nact, sizeof(int), hipMemcpyDeviceToHost, P.stream) != hipSuccess) return MG_ERR_HIP;
+    if (hipEventRecord(P.ev[0], P.stream) != hipSuccess) return MG_ERR_HIP;
+    for (int it = 0;; it++) {
+        // launch iteration it+1 before looking at what iteration it left
+        if (it < max_cycles) {
+            if ((e = run_iteration(P))) return e;
+            int k = (it + 1) & 1;
+            if (hipMemcpyAsync(&P.hact[k], nact, sizeof(int), hipMemcpyDeviceToHost, P.stream) != hipSuccess) return MG_ERR_HIP;
+            if (hipEventRecord(P.ev[k], P.stream) != hipSuccess) return MG_ERR_HIP;
+        }
+        if (hipEventSynchronize(P.ev[it & 1]) != hipSuccess) return MG_ERR_HIP;
+        if (P.hact[it & 1] <= 0 || it >= max_cycles) break;
+    }
+    if (hipStreamSynchronize(P.stream) != hipSuccess) return MG_ERR_HIP;
+    // per-problem outcome: the first fields of each control block
+    if (hipMemcpy2DAsync(P.hres, sizeof(double) * 9, ctls, sizeof(Ctl), sizeof(double) * 9, P.nprob,
+                         hipMemcpyDeviceToHost, P.stream) != hipSuccess)
+        return MG_ERR_HIP;
+    if (history0 && hipMemcpyAsync(P.hctl, ctls, sizeof(Ctl), hipMemcpyDeviceToHost, P.stream) != hipSuccess)
+        return MG_ERR_HIP;
+    if (hipStreamSynchronize(P.stream) != hipSuccess) return MG_ERR_HIP;
+    int worst = MG_OK;
+    for (int i = 0; i < P.nprob; i++) {
+        const Ctl* c = reinterpret_cast<const Ctl*>(P.hres + 9 * (size_t)i);
+        int st = c->done ? c->status : MG_ERR_NOT_CONVERGED;
+        int cy = c->done ? c->cycles : max_cycles;
+        if (cycles) cycles[i] = cy;
+        if (relres) relres[i] = c->last;
+        if (status) status[i] = st;
+        if (st != MG_OK && (worst == MG_OK || st < worst)) worst = st;
+    }
+    if (history0) {
+        const Ctl& H = *P.hctl;
+        int cy = H.done ? H.cycles : max_cycles;
+        for (int k = 0; k <= cy; k++) history0[k] = H.hist[k];
+    }
+    return worst;
+}
+
+int plan2_level_get(Plan2& P, int depth, int which, double* dst)
+{
+    // problem 0; depth counts from its finest level
+    int D = P.D[0];
+    if (depth < 0 || depth > D || (which != 0 && which != 1) || (which == 1 && depth == 0)) return MG_ERR_ARG;
+    int lam = D - depth;
+    int m = side_of(lam);
+    int diag = lam & 1;
+    size_t off = (which == 0) ? (depth == 0 ? P.off_r0[0] : P.off_r[0][lam]) : P.off_v[0][lam];
+    if (P.prec == MG_FP64) launch_b_level_get<double>(diag, m, at<double>(P, off), dst, P.stream);
+    else launch_b_level_get<float>(diag, m, at<float>(P, off), dst, P.stream);
+    return last_launch();
+}
+
+// ------------------------------------------------------------- autotuner
+// For every level launch of the cycle, time each candidate strip length
+// (0 = one thread per point, else rows per wave) on the plan's own arrays and
+// keep the fastest.  The kernels only write level arrays that the next cycle
+// overwrites.  Results can be kept in a text cache (DMG_TUNE_CACHE): one line
+// "kind side prec rows" per tuned launch shape.
+
+namespace {
+
+struct TuneKey { int kind, m, prec; };
+
+int cache_lookup(const char* path, int kind, int m, int prec, int* rows)
+{
+    FILE* fp = path ? fopen(path, "r") : nullptr;
+    if (!fp) return 0;
+    int k, mm, pr, r, found = 0;
+    while (fscanf(fp, "%d %d %d %d", &k, &mm, &pr, &r) == 4)
+        if (k == kind && mm == m && pr == prec) { *rows = r; found = 1; }
+    fclose(fp);
+    return found;
+}
+
+void cache_store(const char* path, int kind, int m, int prec, int rows)
+{
+    FILE* fp = path ? fopen(path, "a") : nullptr;
+    if (!fp) return;
+    fprintf(fp, "%d %d %d %d\n", kind, m, prec, rows);
+    fclose(fp);
+}
+
+template <typename T>
+float time_launch(Plan2& P, int is_rs, int lam, int rows, hipEvent_t e0, hipEvent_t e1)
+{
+    Ctl* ctls = at<Ctl>(P, P.off_ctl);
+    auto go = [&]() {
+        if (is_rs)
+            launch_b_restrict<T>((lam + 1) & 1, side_of(lam + 1), rows, at<Item2<T>>(P, P.off_rs_items[lam]),
+                                 P.n_rs_items[lam], ctls, P.stream);
+        else
+            launch_b_jacobi<T>(lam & 1, side_of(lam), rows, (T)coef(P, lam), at<Item2<T>>(P, P.off_jac_items[lam]),
+                               P.n_jac_items[lam], ctls, P.stream);
+    };
+    go();
+    (void)hipEventRecord(e0, P.stream);
+    for (int k = 0; k < 5; k++) go();
+    (void)hipEventRecord(e1, P.stream);
+    (void)hipEventSynchronize(e1);
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    return ms;
+}
+
+}  // namespace
+
+int plan2_tune_load(Plan2& P)
+{
+    const char* path = getenv("DMG_TUNE_CACHE");
+    if (!path) return MG_OK;
+    for (int lam = 0; lam <= P.Dmax; lam++) {
+        int r;
+        if (P.n_rs_items[lam] && cache_lookup(path, ((lam + 1) & 1) ? 1 : 0, side_of(lam + 1), P.prec, &r)) P.rows_rs[lam] = r;
+        if (P.n_jac_items[lam] && cache_lookup(path, (lam & 1) ? 2 : 3, side_of(lam), P.prec, &r)) P.rows_jac[lam] = r;
+    }
+    return MG_OK;
+}
+
+int plan2_autotune(Plan2& P)
+{
+    const char* path = getenv("DMG_TUNE_CACHE");
+    Ctl* ctls = at<Ctl>(P, P.off_ctl);
+    int* nact = at<int>(P, P.off_nactive);
+    launch_b_ctl_reset(ctls, P.nprob, 0, 0, 0.0, nact, P.stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MG_ERR_HIP;
+    const int cand[] = {0, 4, 8, 16, 32};
+    for (int is_rs = 1; is_rs >= 0; is_rs--) {
+        for (int lam = 0; lam <= P.Dmax; lam++) {
+            int cnt = is_rs ? P.n_rs_items[lam] : P.n_jac_items[lam];
+            if (!cnt) continue;
+            int m = is_rs ? side_of(lam + 1) : side_of(lam);
+            int kind = is_rs ? (((lam + 1) & 1) ? 1 : 0) : ((lam & 1) ? 2 : 3);
+            int best = is_rs ? P.rows_rs[lam] : P.rows_jac[lam];
+            float bt = 1e30f;
+            for (int r : cand) {
+                if (r > 0 && m < 16) continue;
+                float t = P.prec == MG_FP64 ? time_launch<double>(P, is_rs, lam, r, e0, e1)
+                                            : time_launch<float>(P, is_rs, lam, r, e0, e1);
+                if (t < bt) { bt = t; best = r; }
+            }
+            (is_rs ? P.rows_rs : P.rows_jac)[lam] = best;
+            cache_store(path, kind, m, P.prec, best);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (P.gready) {  // the captured graph used the old shapes
+        (void)hipGraphExecDestroy(P.gexec);
+        P.gready = false;
+    }
+    return last_launch();
+}
+
+}  // namespace dmg

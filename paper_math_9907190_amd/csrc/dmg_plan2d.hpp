@@ -1,0 +1,52 @@
+// The 2D plan (a batch of independent problems; one problem is a batch of one).
+#pragma once
+#include "dmg_host.hpp"
+
+#include <vector>
+
+namespace dmg {
+
+struct Plan2 {
+    int nprob = 0, prec = 0;
+    double p = 1.0;
+    std::vector<int> n, D;    // per problem: intervals per side, finest depth (= its finest aligned level)
+    int Dmax = 0, lamc = 0;   // highest aligned level; highest level run by the coarse kernel
+    // size classes (distinct n, ascending); the finest-item table is grouped by class
+    std::vector<int> order, cls_n, cls_first, cls_count, nparts;
+    // workspace offsets
+    size_t off_ctl = 0, off_nactive = 0, off_zero = 0, off_fin = 0, off_coarse = 0, total = 0;
+    std::vector<size_t> off_r0, off_part;
+    std::vector<std::vector<size_t>> off_r, off_v;   // [problem][aligned level]
+    std::vector<size_t> off_rs_items, off_jac_items; // [aligned level]
+    std::vector<int> n_rs_items, n_jac_items;
+    int n_coarse_items = 0;
+    std::vector<int> rows_rs, rows_jac;              // launch shape per level (0: one thread per point)
+    // runtime
+    char* ws = nullptr;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    void* hfin = nullptr;     // pinned host image of the finest-item table
+    Ctl* hctl = nullptr;      // pinned: problem 0's control block (history)
+    int* hact = nullptr;      // pinned: active-problem counts of two iterations
+    double* hres = nullptr;   // pinned: first fields of every control block
+    hipEvent_t ev[2];
+    hipEvent_t evu;           // completion of the last finest-table upload (hfin is then free to rewrite)
+    bool evs = false, fin_valid = false;
+    std::vector<const void*> last_u, last_f;
+    Timing tm;
+    hipGraphExec_t gexec = nullptr;
+    bool gready = false, use_graph = true;
+    hipStream_t cap = nullptr;
+};
+
+int plan2_layout(Plan2& P, int nprob, const int* n, int prec, double p);
+int plan2_setup(Plan2& P, void* ws, size_t ws_bytes, hipStream_t stream);
+void plan2_destroy(Plan2& P);
+int plan2_vcycle(Plan2& P, double* const* u, const double* const* f, double* relres);
+int plan2_solve(Plan2& P, double* const* u, const double* const* f, double rtol, int max_cycles, int* cycles,
+                double* relres, int* status, double* history0);
+int plan2_level_get(Plan2& P, int depth, int which, double* dst);
+int plan2_tune_load(Plan2& P);
+int plan2_autotune(Plan2& P);
+
+}  // namespace dmg

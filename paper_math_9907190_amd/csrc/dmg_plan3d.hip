@@ -1,0 +1,258 @@
+// Host runtime of the 3D solver (Roberts, Section 3): level plan, workspace
+// carving and launch sequencing of one V-cycle: residual on the finest
+// green grid, restriction green -> red -> magenta -> blue group by group,
+// every level of side <= 8 in one persistent workgroup, Jacobi back up
+// (magenta-blue, red-magenta, green-red), the finest fused with u += v.
+#include "dmg_launch.hpp"
+#include "dmg_launch3.hpp"
+#include "dmg_plan3d.hpp"
+
+#include <string.h>
+
+namespace dmg {
+
+namespace {
+
+constexpr int kCoarseSide3 = 8;  // levels of side <= 8 run in the persistent kernel
+
+template <typename T>
+T* at(Plan3& P, size_t off) { return reinterpret_cast<T*>(P.ws + off); }
+
+double bytes_rs3(int coarse_kind, int m, size_t es)
+{
+    double M = m / 2;
+    if (coarse_kind == 1) return (double)es * (sizeG(m) + (double)(m - 1) * (m - 1) * (m - 1) / 2);
+    if (coarse_kind == 2) return (double)es * (sizeR(m) + (M - 1) * (M - 1) * (M - 1) + M * M * M);
+    return (double)es * (sizeME(m) + sizeMO(m) + (M - 1) * (M - 1) * (M - 1));
+}
+double bytes_jac3(int kind, int m, size_t es)
+{
+    double M = m / 2, c = (double)(m - 1) * (m - 1) * (m - 1);
+    if (kind == 2) return (double)es * (2 * ((M - 1) * (M - 1) * (M - 1) + M * M * M) + sizeG(m / 2));
+    if (kind == 1) return (double)es * (2 * ((M - 1) * (M - 1) * (M - 1) + 3 * M * M * (M - 1)) + sizeME(m) + sizeMO(m));
+    return (double)es * (2 * c + sizeR(m));
+}
+double bytes_resid3(int n, size_t es)
+{
+    double inter = (double)(n - 1) * (n - 1) * (n - 1);
+    return 8 * (double)sizeG(n) + 8 * inter + es * inter;
+}
+double bytes_finest3(int n, size_t es)
+{
+    double inter = (double)(n - 1) * (n - 1) * (n - 1);
+    return es * (inter + (double)sizeR(n)) + 16 * inter;
+}
+
+template <typename T>
+void enqueue_cycle3(Plan3& P, double* u, const Ctl* ctl)
+{
+    hipStream_t s = P.stream;
+    int D = P.D, dc = P.dc;
+    const size_t es = sizeof(T);
+    T* r0 = at<T>(P, P.r0);
+    auto lv = [&](int d) {
+        Lev3<T> x;
+        const Level3& q = P.lev[d];
+        x.m = q.m;
+        x.kind = q.kind;
+        x.r = d == 0 ? r0 : at<T>(P, q.r);
+        x.v = d == 0 ? nullptr : at<T>(P, q.v);
+        x.r2 = q.kind == 2 ? at<T>(P, q.r2) : nullptr;
+        x.v2 = q.kind == 2 ? at<T>(P, q.v2) : nullptr;
+        x.c = (T)q.c;
+        x.c2 = (T)q.c2;
+        return x;
+    };
+    int last_rs = dc ? dc : D;
+    for (int d = 1; d <= last_rs; d++) {
+        Timed t(&P.tm, MG_K_RESTRICT, bytes_rs3(P.lev[d].kind, P.lev[d - 1].m, es));
+        launch_rs3<T>(lv(d - 1), lv(d), ctl, s);
+    }
+    if (dc) {
+        double cb = 0;
+        for (int d = dc + 1; d <= D; d++) cb += bytes_rs3(P.lev[d].kind, P.lev[d - 1].m, es);
+        for (int d = dc; d <= D; d++) cb += bytes_jac3(P.lev[d].kind, P.lev[d].m, es);
+        Timed t(&P.tm, MG_K_COARSE, cb);
+        Coarse3<T> a;
+        a.first = dc;
+        a.last = D;
+        for (int d = dc; d <= D; d++) a.lev[d] = lv(d);
+        a.zero = at<T>(P, P.zero);
+        launch_coarse3<T>(a, ctl, s);
+    }
+    for (int d = (dc ? dc - 1 : D); d >= 1; d--) {
+        Lev3<T> c = (d == D) ? Lev3<T>{} : lv(d + 1);
+        Timed t(&P.tm, MG_K_JACOBI, bytes_jac3(P.lev[d].kind, P.lev[d].m, es));
+        launch_jac3<T>(lv(d), c, at<T>(P, P.zero), ctl, s);
+    }
+    Lev3<T> c1 = D >= 1 ? lv(1) : Lev3<T>{};
+    Timed t(&P.tm, MG_K_FINEST, bytes_finest3(P.n, es));
+    launch_jac3_finest<T>(P.n, (T)P.lev[0].c, r0, D >= 1 ? c1.v : at<T>(P, P.zero), u, ctl, s);
+}
+
+void enqueue_cycle_any(Plan3& P, double* u, const Ctl* ctl)
+{
+    if (P.prec == MG_FP64) enqueue_cycle3<double>(P, u, ctl);
+    else enqueue_cycle3<float>(P, u, ctl);
+}
+
+void enqueue_residual(Plan3& P, const double* u, const double* f, const Ctl* ctl)
+{
+    bool dbl = P.prec == MG_FP64;
+    double* part = at<double>(P, P.partial);
+    Timed t(&P.tm, MG_K_RESIDUAL, bytes_resid3(P.n, dbl ? 8 : 4));
+    if (dbl) launch_residual<double>(3, P.n, u, f, at<double>(P, P.r0), part, P.nparts, ctl, P.stream);
+    else launch_residual<float>(3, P.n, u, f, at<float>(P, P.r0), part, P.nparts, ctl, P.stream);
+}
+
+void enqueue_finalize(Plan3& P, int kind, int k, Ctl* ctl)
+{
+    Timed t(&P.tm, MG_K_NORM, 8.0 * P.nparts);
+    launch_finalize(kind, k, at<double>(P, P.partial), P.nparts, ctl, P.stream);
+}
+
+}  // namespace
+
+int plan3_layout(Plan3& P, int n, int prec, const double* p)
+{
+    int K = ilog2(n);
+    if (K < 1 || K > 11) return MG_ERR_SIZE;
+    if (prec != MG_FP64 && prec != MG_FP32_REFINED) return MG_ERR_ARG;
+    size_t es = prec == MG_FP64 ? sizeof(double) : sizeof(float);
+    P.n = n;
+    P.prec = prec;
+    P.D = 3 * (K - 1);
+    if (p)
+        for (int i = 0; i < 4; i++) P.p[i] = p[i];
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = alignUp(off + bytes);
+        return o;
+    };
+    P.ctl = take(sizeof(Ctl));
+    P.nparts = residual_parts(3, n);
+    P.partial = take(sizeof(double) * (size_t)P.nparts);
+    P.zero = take(sizeof(double) * 64);
+    P.r0 = take(es * sizeG(n));
+    double h = 1.0 / n;
+    for (int d = 0; d <= P.D; d++) {
+        Level3& v = P.lev[d];
+        v.m = n >> (d / 3);
+        v.kind = d % 3;
+        double sh = (double)(n / v.m) * h;  // sigma * h
+        double pm = P.p[0], pr1 = P.p[1], pr2 = P.p[2], pg = P.p[3];
+        if (v.kind == 0) v.c = pg * sh * sh;
+        else if (v.kind == 1) { v.c = 2 * pr1 * sh * sh; v.c2 = 4 * pr2 * sh * sh; }
+        else v.c = 4 * pm * sh * sh;
+        if (d >= 1) {
+            if (v.kind == 0) { v.r = take(es * sizeG(v.m)); v.v = take(es * sizeG(v.m)); }
+            else if (v.kind == 1) { v.r = take(es * sizeR(v.m)); v.v = take(es * sizeR(v.m)); }
+            else {
+                v.r = take(es * sizeME(v.m)); v.v = take(es * sizeME(v.m));
+                v.r2 = take(es * sizeMO(v.m)); v.v2 = take(es * sizeMO(v.m));
+            }
+        }
+    }
+    // first depth run by the persistent kernel (0: none), on a green level
+    P.dc = 0;
+    if (P.D >= 1) {
+        for (int d = 1; d <= P.D; d++)
+            if (P.lev[d].m <= kCoarseSide3) { P.dc = d; break; }
+        while (P.dc > 1 && P.dc % 3 != 0) P.dc--;
+    }
+    P.total = off;
+    return MG_OK;
+}
+
+int plan3_setup(Plan3& P, void* ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (!ws || ((uintptr_t)ws % kAlign) != 0 || ws_bytes < P.total) return MG_ERR_WS;
+    P.ws = (char*)ws;
+    P.stream = stream;
+    P.tm.stream = stream;
+    if (hipGetDevice(&P.device) != hipSuccess) return MG_ERR_HIP;
+    if (hipHostMalloc((void**)&P.hctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) return MG_ERR_HIP;
+    // zero the whole workspace once: boundary entries of every level stay 0
+    return hip_status(hipMemsetAsync(P.ws, 0, P.total, P.stream));
+}
+
+void plan3_destroy(Plan3& P)
+{
+    P.tm.destroy();
+    if (P.hctl) (void)hipHostFree(P.hctl);
+}
+
+int plan3_vcycle(Plan3& P, double* u, const double* f, double* relres)
+{
+    Ctl* ctl = at<Ctl>(P, P.ctl);
+    double* part = at<double>(P, P.partial);
+    launch_ctl_reset(ctl, 0, 0, 0.0, P.stream);
+    if (relres) {
+        launch_sumsq(3, P.n, f, part, P.nparts, ctl, P.stream);
+        enqueue_finalize(P, 0, 0, ctl);
+    }
+    enqueue_residual(P, u, f, ctl);
+    if (relres) enqueue_finalize(P, 1, 0, ctl);
+    enqueue_cycle_any(P, u, ctl);
+    int e = last_launch();
+    if (e) return e;
+    if (relres) {
+        if (hipMemcpyAsync(P.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, P.stream) != hipSuccess) return MG_ERR_HIP;
+        if (hipStreamSynchronize(P.stream) != hipSuccess) return MG_ERR_HIP;
+        *relres = P.hctl->last;
+    }
+    return MG_OK;
+}
+
+int plan3_solve(Plan3& P, double* u, const double* f, double rtol, int max_cycles, int* cycles_out, double* rel_res_out,
+                double* history)
+{
+    Ctl* ctl = at<Ctl>(P, P.ctl);
+    double* part = at<double>(P, P.partial);
+    hipStream_t s = P.stream;
+    launch_ctl_reset(ctl, 1, max_cycles, rtol, s);
+    launch_sumsq(3, P.n, f, part, P.nparts, ctl, s);
+    enqueue_finalize(P, 0, 0, ctl);
+    enqueue_residual(P, u, f, ctl);
+    enqueue_finalize(P, 1, 0, ctl);
+    size_t head = offsetof(Ctl, rtol);
+    // the device decides after every residual evaluation; the host launches
+    // the next cycle once it has seen that the last one did not stop
+    for (int k = 0;; k++) {
+        if (hipMemcpyAsync(P.hctl, ctl, head, hipMemcpyDeviceToHost, s) != hipSuccess) return MG_ERR_HIP;
+        if (hipStreamSynchronize(s) != hipSuccess) return MG_ERR_HIP;
+        if (P.hctl->done || k >= max_cycles) break;
+        enqueue_cycle_any(P, u, ctl);
+        enqueue_residual(P, u, f, ctl);
+        enqueue_finalize(P, 1, k + 1, ctl);
+        int e = last_launch();
+        if (e) return e;
+    }
+    if (hipMemcpyAsync(P.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s) != hipSuccess) return MG_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return MG_ERR_HIP;
+    const Ctl& H = *P.hctl;
+    int cyc = H.done ? H.cycles : max_cycles;
+    if (cycles_out) *cycles_out = cyc;
+    if (rel_res_out) *rel_res_out = H.last;
+    if (history)
+        for (int k = 0; k <= cyc; k++) history[k] = H.hist[k];
+    return H.done ? H.status : MG_ERR_NOT_CONVERGED;
+}
+
+int plan3_level_get(Plan3& P, int depth, int which, double* dst)
+{
+    if (depth < 0 || depth > P.D || (which != 0 && which != 1) || (which == 1 && depth == 0)) return MG_ERR_ARG;
+    const Level3& q = P.lev[depth];
+    size_t src = which == 0 ? (depth == 0 ? P.r0 : q.r) : q.v;
+    size_t src2 = which == 0 ? q.r2 : q.v2;
+    if (P.prec == MG_FP64)
+        launch_level_get3<double>(q.kind, q.m, at<double>(P, src), q.kind == 2 ? at<double>(P, src2) : nullptr, dst,
+                                  P.stream);
+    else
+        launch_level_get3<float>(q.kind, q.m, at<float>(P, src), q.kind == 2 ? at<float>(P, src2) : nullptr, dst,
+                                 P.stream);
+    return last_launch();
+}
+
+}  // namespace dmg

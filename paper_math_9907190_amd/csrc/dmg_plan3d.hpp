@@ -1,0 +1,38 @@
+// The 3D plan (one problem).
+#pragma once
+#include "dmg_host.hpp"
+
+namespace dmg {
+
+constexpr int kMaxLev3 = 32;  // 3D n <= 2^11 has 31 levels
+
+struct Level3 {
+    int m = 0;
+    int kind = 0;           // 0 green, 1 red, 2 magenta
+    size_t r = 0, v = 0;    // byte offsets; magenta: corner (E) arrays
+    size_t r2 = 0, v2 = 0;  // magenta: cube-centre (O) arrays
+    double c = 0, c2 = 0;   // Jacobi residual coefficients
+};
+
+struct Plan3 {
+    int n = 0, prec = 0, D = 0, dc = 0;
+    double p[4] = {1, 1, 1, 1};
+    size_t ctl = 0, partial = 0, zero = 0, r0 = 0, total = 0;
+    int nparts = 0;
+    Level3 lev[kMaxLev3];
+    char* ws = nullptr;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    Ctl* hctl = nullptr;
+    Timing tm;
+};
+
+int plan3_layout(Plan3& P, int n, int prec, const double* p);
+int plan3_setup(Plan3& P, void* ws, size_t ws_bytes, hipStream_t stream);
+void plan3_destroy(Plan3& P);
+int plan3_vcycle(Plan3& P, double* u, const double* f, double* relres);
+int plan3_solve(Plan3& P, double* u, const double* f, double rtol, int max_cycles, int* cycles, double* relres,
+                double* history);
+int plan3_level_get(Plan3& P, int depth, int which, double* dst);
+
+}  // namespace dmg

@@ -34,14 +34,23 @@ _lib.mg_level_info.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _i
 _lib.mg_destroy.argtypes = [_vp]
 _lib.mg_timing_enable.argtypes = [_vp, ctypes.c_int]
 _lib.mg_timing_read.argtypes = [_vp, _dp, ctypes.POINTER(ctypes.c_longlong), _dp]
+_lib.mg_batch_workspace_bytes.argtypes = [ctypes.c_int, _ip, ctypes.c_int, ctypes.POINTER(_sz)]
+_lib.mg_setup_batched.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, _ip, ctypes.c_int, ctypes.c_double, _vp, _sz,
+                                  _vp]
+_lib.mg_solve_batched.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_double, ctypes.c_int,
+                                  _ip, _dp, _ip]
+_lib.mg_vcycle_batched.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _dp]
+_lib.mg_autotune.argtypes = [_vp]
 _lib.mg_strerror.argtypes = [ctypes.c_int]
 _lib.mg_strerror.restype = ctypes.c_char_p
 for _f in ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_level_get", "mg_level_info",
-           "mg_destroy", "mg_timing_enable", "mg_timing_read"):
+           "mg_destroy", "mg_timing_enable", "mg_timing_read", "mg_batch_workspace_bytes", "mg_setup_batched",
+           "mg_solve_batched", "mg_vcycle_batched", "mg_autotune"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_level_get", "mg_level_info",
-           "mg_destroy", "mg_strerror", "mg_timing_enable", "mg_timing_read")
+           "mg_destroy", "mg_strerror", "mg_timing_enable", "mg_timing_read", "mg_batch_workspace_bytes",
+           "mg_setup_batched", "mg_solve_batched", "mg_vcycle_batched", "mg_autotune")
 
 # kernel families for mg_timing_enable
 MG_K_RESIDUAL, MG_K_RESTRICT, MG_K_JACOBI, MG_K_FINEST, MG_K_COARSE, MG_K_NORM = range(6)
@@ -110,6 +119,53 @@ def mg_destroy(plan):
     _check(_lib.mg_destroy(plan), "mg_destroy")
 
 
+def _int_array(xs):
+    return (ctypes.c_int * len(xs))(*[int(x) for x in xs])
+
+
+def _ptr_array(ptrs):
+    return (_vp * len(ptrs))(*[_vp(int(x)) for x in ptrs])
+
+
+def mg_batch_workspace_bytes(ns, precision):
+    out = _sz()
+    _check(_lib.mg_batch_workspace_bytes(len(ns), _int_array(ns), precision, ctypes.byref(out)),
+           "mg_batch_workspace_bytes")
+    return out.value
+
+
+def mg_setup_batched(ns, precision, p, workspace_ptr, ws_bytes, stream_ptr):
+    plan = _vp()
+    _check(_lib.mg_setup_batched(ctypes.byref(plan), len(ns), _int_array(ns), precision, float(p), _vp(workspace_ptr),
+                                 ws_bytes, _vp(stream_ptr)), "mg_setup_batched")
+    return plan
+
+
+def mg_solve_batched(plan, u_ptrs, f_ptrs, rtol, max_cycles):
+    """Returns (overall status, cycles list, relres list, status list)."""
+    k = len(u_ptrs)
+    cyc = (ctypes.c_int * k)()
+    rr = (ctypes.c_double * k)()
+    st = (ctypes.c_int * k)()
+    ret = _lib.mg_solve_batched(plan, _ptr_array(u_ptrs), _ptr_array(f_ptrs), float(rtol), int(max_cycles), cyc, rr,
+                                st)
+    if ret not in (MG_OK, MG_ERR_NOT_CONVERGED, MG_ERR_NONFINITE, MG_ERR_DIVERGED):
+        raise MGError(ret, "mg_solve_batched")
+    return ret, list(cyc), list(rr), list(st)
+
+
+def mg_vcycle_batched(plan, u_ptrs, f_ptrs, want_relres=False):
+    k = len(u_ptrs)
+    rr = (ctypes.c_double * k)()
+    _check(_lib.mg_vcycle_batched(plan, _ptr_array(u_ptrs), _ptr_array(f_ptrs), rr if want_relres else None),
+           "mg_vcycle_batched")
+    return list(rr) if want_relres else None
+
+
+def mg_autotune(plan):
+    _check(_lib.mg_autotune(plan), "mg_autotune")
+
+
 def mg_timing_enable(plan, family):
     _check(_lib.mg_timing_enable(plan, int(family)), "mg_timing_enable")
 
@@ -174,6 +230,57 @@ class Solver:
 
     def timing_read(self):
         return mg_timing_read(self.plan)
+
+    def autotune(self):
+        mg_autotune(self.plan)
+
+    def close(self):
+        if getattr(self, "plan", None) is not None:
+            mg_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchSolver:
+    """Independent 2D problems solved together: one kernel launch per level
+    for the whole batch.  ns: intervals per side of each problem."""
+
+    def __init__(self, ns, precision=MG_FP32_REFINED, p=P2D_TUNED[0], device=None, stream=None):
+        self.ns = [int(x) for x in ns]
+        self.precision = precision
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.ws_bytes = mg_batch_workspace_bytes(self.ns, precision)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+            ptr = (self.ws.data_ptr() + 255) // 256 * 256
+            self.plan = mg_setup_batched(self.ns, precision, p, ptr, self.ws_bytes, self.stream.cuda_stream)
+
+    def _chk(self, ts, name):
+        if len(ts) != len(self.ns):
+            raise ValueError("%s: expected %d tensors" % (name, len(self.ns)))
+        for t, n in zip(ts, self.ns):
+            if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape) == (n + 1, n + 1)
+                    and t.device == self.device):
+                raise ValueError("%s: each tensor must be contiguous float64 (n+1, n+1) on %s" % (name, self.device))
+
+    def solve(self, us, fs, rtol=1e-10, max_cycles=50):
+        self._chk(us, "u")
+        self._chk(fs, "f")
+        return mg_solve_batched(self.plan, [u.data_ptr() for u in us], [f.data_ptr() for f in fs], rtol, max_cycles)
+
+    def vcycle(self, us, fs, want_relres=False):
+        self._chk(us, "u")
+        self._chk(fs, "f")
+        return mg_vcycle_batched(self.plan, [u.data_ptr() for u in us], [f.data_ptr() for f in fs], want_relres)
+
+    def autotune(self):
+        mg_autotune(self.plan)
 
     def close(self):
         if getattr(self, "plan", None) is not None:
