@@ -1,4 +1,4 @@
-"""ctypes wrapper of the CPU oracle (``orc_mg.c``).
+"""ctypes wrapper of the CPU oracle (``orc_mg.c``, ``orc_net.c``).
 
 TEST INFRASTRUCTURE ONLY.  The oracle is the plain double-precision CPU
 reference of the diagonally oriented multigrid V-cycle (Roberts, Sections 1-3)
@@ -30,13 +30,13 @@ P3D_TUNED = (1.11, 1.42, 1.08, 0.99)
 
 def build(force=True):
     """Compile ``liborc.so`` with gcc (plain -O2, no FP contraction)."""
-    src = os.path.join(_HERE, "orc_mg.c")
-    if not force and os.path.exists(_SO) and os.path.getmtime(_SO) >= max(
-            os.path.getmtime(src), os.path.getmtime(os.path.join(_HERE, "orc_mg_body.h"))):
+    srcs = [os.path.join(_HERE, f) for f in ("orc_mg.c", "orc_net.c")]
+    deps = srcs + [os.path.join(_HERE, "orc_mg_body.h")]
+    if not force and os.path.exists(_SO) and os.path.getmtime(_SO) >= max(os.path.getmtime(d) for d in deps):
         return _SO
     tmp = _SO + ".tmp%d" % os.getpid()
     subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
-                           "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, src, "-lm"])
+                           "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp] + srcs + ["-lm"])
     os.replace(tmp, _SO)
     return _SO
 
@@ -60,6 +60,12 @@ def lib():
         for fn in ("orc_residual", "orc_relres", "orc_vcycle", "orc_vcycle_trace", "orc_solve",
                    "orc_step_restrict", "orc_step_jacobi"):
             getattr(L, fn).restype = ctypes.c_int
+        L.orc_net_forward.argtypes = [i, i, dp, dp, dp]
+        L.orc_net_forward.restype = ctypes.c_int
+        L.orc_net_loss_grad.argtypes = [i, i, dp, dp, dp, dp]
+        L.orc_net_loss_grad.restype = ctypes.c_double
+        L.orc_net_adam.argtypes = [i, dp, dp, dp, dp, i, d, d, d, d]
+        L.orc_net_adam.restype = None
         _lib = L
     return _lib
 
@@ -173,3 +179,47 @@ def step_jacobi(dim, kind, c, r, vc):
     _chk(lib().orc_step_jacobi(dim, kind, m, _ptr(c), _ptr(np.ascontiguousarray(r)),
                                _ptr(np.ascontiguousarray(vc)), _ptr(out)), "orc_step_jacobi")
     return out
+
+
+# ------------------------------------------------------------ network oracle
+# Four 3x3 (2D) / 3x3x3 (3D) convolutions, 16 channels, ReLU between, no bias,
+# on [B][17][17] or [B][9][9][9] grids (zero boundary); weights
+# [4][taps][16][16] (layer, tap, cin, cout), tap = (dy+1)*3+(dx+1) in 2D and
+# ((dz+1)*3+(dy+1))*3+(dx+1) in 3D; layer 0 reads cin 0, layer 3 writes cout 0.
+NET_G = {2: 17, 3: 9}
+NET_TAPS = {2: 9, 3: 27}
+
+
+def net_shape(dim):
+    return (4, NET_TAPS[dim], 16, 16)
+
+
+def net_forward(inp, w):
+    """inp [B][G]^dim -> network output [B][G]^dim (boundary 0)."""
+    inp = np.ascontiguousarray(inp, dtype=np.float64)
+    dim = inp.ndim - 1
+    w = np.ascontiguousarray(w, dtype=np.float64).reshape(net_shape(dim))
+    out = np.zeros_like(inp)
+    _chk(lib().orc_net_forward(dim, inp.shape[0], _ptr(inp), _ptr(w), _ptr(out)), "orc_net_forward")
+    return out
+
+
+def net_loss_grad(inp, target, w):
+    """(loss, dloss/dw) of the mean squared error over interior points."""
+    inp = np.ascontiguousarray(inp, dtype=np.float64)
+    dim = inp.ndim - 1
+    target = np.ascontiguousarray(target, dtype=np.float64)
+    w = np.ascontiguousarray(w, dtype=np.float64).reshape(net_shape(dim))
+    grad = np.zeros(net_shape(dim))
+    loss = lib().orc_net_loss_grad(dim, inp.shape[0], _ptr(inp), _ptr(target), _ptr(w), _ptr(grad))
+    if not np.isfinite(loss):
+        raise OracleError(-1, "orc_net_loss_grad")
+    return loss, grad
+
+
+def net_adam(w, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step in place on float64 arrays of one shape (step t >= 1)."""
+    for a in (w, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    lib().orc_net_adam(w.size, _ptr(w), _ptr(m), _ptr(v), _ptr(g), t, lr, b1, b2, eps)

@@ -1,0 +1,143 @@
+"""Pins of the oracle's coarse-correction network (CPU only).
+
+* gradients against central finite differences of the oracle's own loss;
+* hand-set weights that make the network compute the 5-point / 7-point
+  Laplacian, checked against the V-cycle oracle's residual (itself pinned by
+  the sine-mode eigenvalues);
+* a one-tap shift along x (and along z in 3D) pins the tap orientation;
+* positive homogeneity of a bias-free ReLU network, zero weights;
+* Adam's first two steps in closed form.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+
+def rand_grid(rng, dim, B):
+    G = O.NET_G[dim]
+    x = np.zeros((B,) + (G,) * dim)
+    sl = (slice(None),) + (slice(1, -1),) * dim
+    x[sl] = rng.standard_normal(x[sl].shape)
+    return x
+
+
+def rand_weights(rng, dim, scale=0.25):
+    w = rng.standard_normal(O.net_shape(dim)) * scale
+    w[0, :, 1:, :] = 0
+    w[3, :, :, 1:] = 0
+    return w
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gradient_matches_finite_differences(orc, dim):
+    rng = np.random.default_rng(10 + dim)
+    x = rand_grid(rng, dim, 2)
+    t = rand_grid(rng, dim, 2)
+    w = rand_weights(rng, dim)
+    loss, g = O.net_loss_grad(x, t, w)
+    assert loss > 0
+    T = O.NET_TAPS[dim]
+    idx = [(0, rng.integers(T), 0, rng.integers(16)) for _ in range(4)]
+    idx += [(l, rng.integers(T), rng.integers(16), rng.integers(16)) for l in (1, 2) for _ in range(4)]
+    idx += [(3, rng.integers(T), rng.integers(16), 0) for _ in range(4)]
+    for i in idx:
+        i = tuple(int(v) for v in i)
+        e = 1e-6
+        wp, wm = w.copy(), w.copy()
+        wp[i] += e
+        wm[i] -= e
+        fd = (O.net_loss_grad(x, t, wp)[0] - O.net_loss_grad(x, t, wm)[0]) / (2 * e)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, g[i])
+    # padded channels carry no gradient
+    assert not g[0, :, 1:, :].any() and not g[3, :, :, 1:].any()
+
+
+def laplacian_weights(dim):
+    """relu(x) - relu(-x) = x carried through two identity layers, then the
+    (2*dim+1)-point stencil (sum of neighbours - 2*dim*centre)."""
+    T = O.NET_TAPS[dim]
+    c = T // 2
+    w = np.zeros(O.net_shape(dim))
+    w[0, c, 0, 0], w[0, c, 0, 1] = 1.0, -1.0
+    for l in (1, 2):
+        w[l, c, 0, 0] = w[l, c, 1, 1] = 1.0
+    stencil = np.zeros(T)
+    stencil[c] = -2.0 * dim
+    for step in [1, 3, 9][:dim]:
+        stencil[c + step] = stencil[c - step] = 1.0
+    w[3, :, 0, 0] = stencil
+    w[3, :, 1, 0] = -stencil
+    return w
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_stencil_weights_reproduce_laplacian(orc, dim):
+    rng = np.random.default_rng(20 + dim)
+    x = rand_grid(rng, dim, 3)
+    out = O.net_forward(x, laplacian_weights(dim))
+    n = O.NET_G[dim] - 1
+    for b in range(3):
+        # the oracle residual with f = 0 is -Lap_h(u) = -(stencil sum) * n^2
+        r = O.residual(x[b], np.zeros_like(x[b]))
+        np.testing.assert_allclose(out[b], -r / n ** 2, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_shift_pins_tap_orientation(orc, dim):
+    rng = np.random.default_rng(30 + dim)
+    x = np.abs(rand_grid(rng, dim, 2))      # nonnegative: the ReLUs pass it
+    T = O.NET_TAPS[dim]
+    c = T // 2
+    step = 9 if dim == 3 else 1            # dz = +1 in 3D, dx = +1 in 2D
+    w = np.zeros(O.net_shape(dim))
+    for l in (0, 1, 2):
+        w[l, c, 0, 0] = 1.0
+    w[3, c + step, 0, 0] = 1.0
+    out = O.net_forward(x, w)
+    want = np.zeros_like(x)
+    if dim == 2:
+        want[:, 1:-1, 1:-1] = x[:, 1:-1, 2:]
+    else:
+        want[:, 1:-1, 1:-1, 1:-1] = x[:, 2:, 1:-1, 1:-1]
+    np.testing.assert_array_equal(out, want)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_homogeneity_and_zero_weights(orc, dim):
+    rng = np.random.default_rng(40 + dim)
+    x = rand_grid(rng, dim, 2)
+    w = rand_weights(rng, dim)
+    y = O.net_forward(x, w)
+    np.testing.assert_allclose(O.net_forward(3.0 * x, w), 3.0 * y, rtol=1e-12, atol=1e-12)
+    w2 = w.copy()
+    w2[3] *= -2.0
+    np.testing.assert_allclose(O.net_forward(x, w2), -2.0 * y, rtol=1e-12, atol=1e-12)
+    z = O.net_forward(x, np.zeros_like(w))
+    assert not z.any()
+    t = rand_grid(rng, dim, 2)
+    loss, g = O.net_loss_grad(x, t, np.zeros_like(w))
+    G2 = O.NET_G[dim] - 2
+    assert loss == pytest.approx((t ** 2).sum() / (2 * G2 ** dim), rel=1e-14)
+    # zero weights: every ReLU is at its kink with zero input, no gradient flows
+    assert not g.any()
+    # a target equal to the output is a stationary point
+    loss, g = O.net_loss_grad(x, y, w)
+    assert loss < 1e-28 and np.abs(g).max() < 1e-14
+
+
+def test_adam_first_two_steps_closed_form(orc):
+    rng = np.random.default_rng(50)
+    w0 = rng.standard_normal(64)
+    g1 = rng.standard_normal(64)
+    g2 = rng.standard_normal(64)
+    lr, b1, b2, eps = 1e-2, 0.9, 0.999, 1e-8
+    w, m, v = w0.copy(), np.zeros(64), np.zeros(64)
+    O.net_adam(w, m, v, g1, 1, lr, b1, b2, eps)
+    # bias correction makes the first step lr * g / (|g| + eps)
+    np.testing.assert_allclose(w, w0 - lr * g1 / (np.abs(g1) + eps), rtol=0, atol=1e-15)
+    w1 = w.copy()
+    O.net_adam(w, m, v, g2, 2, lr, b1, b2, eps)
+    mh = (b1 * (1 - b1) * g1 + (1 - b1) * g2) / (1 - b1 ** 2)
+    vh = (b2 * (1 - b2) * g1 ** 2 + (1 - b2) * g2 ** 2) / (1 - b2 ** 2)
+    np.testing.assert_allclose(w, w1 - lr * mh / (np.sqrt(vh) + eps), rtol=0, atol=1e-15)
