@@ -149,6 +149,86 @@ enum {
 int mg_timing_enable(mg_plan *plan, int family);
 int mg_timing_read(mg_plan *plan, double *ms, long long *launches, double *bytes);
 
+/* ------------------------------------------------------------------------
+ * Learned coarse correction (an extension; the paper has no learned part).
+ *
+ * A network of four convolutions with 16 channels, 3x3 taps in 2D and 3x3x3
+ * in 3D, ReLU after the first three, no bias, zero padding, acting on one
+ * grid of the cut level: aligned level MG_NET_CUT, the axis grid of side 16
+ * (17 x 17 points) in 2D and the cubic grid of side 8 (9^3 points) in 3D.
+ * It maps the cut level's restricted residual r_c to an estimate of the
+ * exact correction e_c = A_c^{-1} r_c (A_c: the 5-point / 7-point Laplacian
+ * of that level, the equation Section 1 solves for v), replacing the
+ * restrictions and Jacobi steps of every coarser level.  bf16 weights and
+ * activations with fp32 accumulation; FP32 master weights.
+ *
+ * Weights: host float arrays of mg_net_weight_count(dim) entries, layout
+ * [layer 4][tap][c_in 16][c_out 16], tap = (dy+1)*3 + (dx+1) in 2D and
+ * ((dz+1)*3 + (dy+1))*3 + (dx+1) in 3D; layer 0 reads channel 0 only and
+ * layer 3 writes channel 0 only (the other entries are forced to 0).
+ *
+ * Normalisation: with s = rms of r_c over interior points and H = 1/(G-1)
+ * the cut level's spacing, the network sees r_c / s and its output y
+ * stands for the correction y s H^2.
+ */
+#define MG_NET_CUT 6
+
+typedef struct mg_net mg_net;
+
+int mg_net_weight_count(int dim);  /* 9216 (2D) or 27648 (3D); 0 for another dim */
+
+/* Trainer state: master weights, Adam moments, bf16 copies and the
+ * per-sample gradient buffers of up to max_batch samples, all in the
+ * caller's device workspace (256-byte aligned). */
+int mg_net_workspace_bytes(int dim, int max_batch, size_t *bytes);
+int mg_net_create(mg_net **out, int dim, int max_batch, void *workspace, size_t ws_bytes,
+                  void *hip_stream);
+/* Set (host array; resets Adam) / read the FP32 master weights; He-normal
+ * initialisation from a seed.  Synchronise the stream. */
+int mg_net_set_weights(mg_net *net, const float *w);
+int mg_net_get_weights(mg_net *net, float *w);
+int mg_net_init(mg_net *net, unsigned long long seed);
+/* Inference on `batch` grids (device, batch x G^dim doubles each, natural
+ * order, boundary ignored; out's boundary is written 0).  normalize = 1
+ * applies the normalisation above (out = the correction estimate);
+ * normalize = 0 returns the raw network output for the raw input. */
+int mg_net_forward(mg_net *net, const double *in, double *out, int batch, int normalize);
+/* Mean-squared-error loss over the interior points of `batch` samples
+ * (batch <= max_batch) and its gradient with respect to the weights (host,
+ * nullable, mg_net_weight_count floats; the padded entries are 0), from the
+ * bf16 forward and backward kernels.  With normalize = 1 the target is
+ * scaled like the output.  Synchronises the stream. */
+int mg_net_loss_grad(mg_net *net, const double *in, const double *target, int batch, int normalize,
+                     float *grad, double *loss);
+/* Adam (lr, beta1 0.9, beta2 0.999, eps 1e-8) on npairs normalised
+ * (r_c, e_c) pairs (device, npairs x G^dim doubles each), `epochs` passes
+ * of npairs / batch steps; the order of every pass is a seeded permutation.
+ * epoch_loss (host, nullable, `epochs` doubles): mean batch loss of each
+ * pass.  Synchronises the stream. */
+int mg_net_train(mg_net *net, const double *r, const double *e, int npairs, int epochs, int batch,
+                 float lr, unsigned long long seed, double *epoch_loss);
+int mg_net_destroy(mg_net *net);
+
+/* Use a trained network in a plan's cycles (w: host weights as above, NULL
+ * removes it; cut_level must be MG_NET_CUT).  Every problem that has the
+ * cut level below its finest grid then runs, per cycle, the network
+ * instead of the levels below the cut.  The plain sub-cycle is the judge:
+ * on the first cycle of a solve both run and the plain one's reduction of
+ * the cut level's residual, ||r_c - A_c v_c|| / ||r_c||, becomes the bar;
+ * a cycle where the network does worse than the bar (or worse than the
+ * plain sub-cycle on the first cycle) takes the plain correction instead,
+ * and the network stays off for the rest of that solve. */
+int mg_set_coarse_net(mg_plan *plan, const float *w, int cut_level);
+/* Per problem, for the last solve (host arrays of nprob, nullable): cycles
+ * whose coarse correction came from the network, and 1 where the judge
+ * switched the network off.  Synchronises the stream. */
+int mg_net_stats(mg_plan *plan, int *net_cycles, int *fell_back);
+/* Copy the restricted residual of aligned level `level` (0 .. the cut
+ * level) of every problem, as left by the last cycle, into dst (device,
+ * nprob x G^dim doubles, G = the level's side + 1; problems without that
+ * level read 0).  For generating training pairs. */
+int mg_coarse_export(mg_plan *plan, int level, double *dst);
+
 int mg_destroy(mg_plan *plan);
 const char *mg_strerror(int code);
 

@@ -14,6 +14,7 @@
 // Per point the arithmetic is the paper's: Eqs. (Erest2r), (Erest2b),
 // (Eajacr), (Eajacb) and the axis-grid Jacobi, terms in the printed order.
 #include "dmg_b2d.hpp"
+#include "dmg_net_dev.hpp"
 #include "dmg_rows.hpp"
 
 namespace dmg {
@@ -521,15 +522,12 @@ struct CoarseLev {
 };
 constexpr int kCoarseThreadsB = 1024;
 
+// restriction into lam for lam = hi-1 down to lo
 template <typename T>
-__global__ void __launch_bounds__(kCoarseThreadsB) kb_coarse(CoarseLev<T> L, const Coarse2B<T>* __restrict__ items,
-                                                             const T* __restrict__ zero, const Ctl* __restrict__ ctls)
+__device__ void coarse_down(const CoarseLev<T>& L, const Coarse2B<T>& it, int hi, int lo)
 {
-    const Coarse2B<T>& it = items[blockIdx.x];
-    ITEM_GATE(ctls, it.prob);
-    const int top = it.top;
     const int tid = threadIdx.x, nt = blockDim.x;
-    for (int lam = top - 1; lam >= 0; lam--) {   // restriction into lam from lam+1
+    for (int lam = hi - 1; lam >= lo; lam--) {
         const LevInfo<T>& Fi = L.l[lam + 1];
         const T* rf = it.r[lam + 1];
         T* rc = it.r[lam];
@@ -550,7 +548,14 @@ __global__ void __launch_bounds__(kCoarseThreadsB) kb_coarse(CoarseLev<T> L, con
         }
         __syncthreads();
     }
-    for (int lam = 0; lam <= top; lam++) {
+}
+
+// Jacobi at lam = lo .. hi (lam = 0 from a zero correction)
+template <typename T>
+__device__ void coarse_up(const CoarseLev<T>& L, const Coarse2B<T>& it, const T* zero, int lo, int hi)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int lam = lo; lam <= hi; lam++) {
         const LevInfo<T>& Li = L.l[lam];
         const T* vc = lam == 0 ? zero : it.v[lam - 1];
         const T* r = it.r[lam];
@@ -574,6 +579,157 @@ __global__ void __launch_bounds__(kCoarseThreadsB) kb_coarse(CoarseLev<T> L, con
             }
         }
         __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kCoarseThreadsB) kb_coarse(CoarseLev<T> L, const Coarse2B<T>* __restrict__ items,
+                                                             const T* __restrict__ zero, const Ctl* __restrict__ ctls)
+{
+    const Coarse2B<T>& it = items[blockIdx.x];
+    ITEM_GATE(ctls, it.prob);
+    coarse_down(L, it, it.top, 0);
+    coarse_up(L, it, zero, 0, it.top);
+}
+
+// ------------------------------------------------- learned coarse correction
+// The cut level c (axis grid, 17 x 17 points) of one problem per workgroup.
+
+__device__ inline double block_sum_d(double v, double* red)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); w++) s += red[w];
+    return s;
+}
+
+// ||r - A v||^2 over the interior of an axis level of side m, A the 5-point
+// Laplacian with spacing 1/m (the equation Lap v = r of Section 1)
+template <typename T>
+__device__ double cut_resid2(const T* __restrict__ r, const T* __restrict__ v, int m, double* red)
+{
+    double s = 0, m2 = (double)m * m;
+    for (int q = threadIdx.x; q < (m - 1) * (m - 1); q += blockDim.x) {
+        int a = q % (m - 1) + 1, b = q / (m - 1) + 1;
+        size_t o = idxA(m, a, b), w = (size_t)(m + 1);
+        double av = ((double)v[o - 1] + (double)v[o + 1] + (double)v[o - w] + (double)v[o + w] - 4.0 * (double)v[o]) * m2;
+        double d = (double)r[o] - av;
+        s += d * d;
+    }
+    return block_sum_d(s, red);
+}
+
+// Network inference on r_c (natural 17 x 17, spacing H = 1/16): the C
+// points (a+b even) of the estimate of A_c^{-1} r_c go to vD (the diagonal
+// level below, D layout of side 16).  Returns ||r_c||^2.
+template <typename T>
+__device__ double net_cut_2d(const T* __restrict__ rc, T* __restrict__ vD, const bf16_t* __restrict__ wf, bf16_t* A,
+                             bf16_t* B, float* out0, short* linq, double* red)
+{
+    using N = NetGeo<2>;
+    net_zero(A, N::ACT);
+    net_zero(B, N::ACT);
+    net_fill_lin<2>(linq);
+    double ss = 0;
+    for (int q = threadIdx.x; q < N::NIN; q += blockDim.x) {
+        double x = (double)rc[N::lin(q)];
+        ss += x * x;
+    }
+    ss = block_sum_d(ss, red);
+    double rms = sqrt(ss / N::NIN);
+    double sc = rms > 0 ? 1.0 / rms : 0.0;
+    for (int q = threadIdx.x; q < N::NIN; q += blockDim.x) {
+        int p = N::lin(q);
+        A[p * kNetCh] = f2bf((float)((double)rc[p] * sc));
+    }
+    __syncthreads();
+    const int WLY = N::T * 256;
+    net_conv_fwd<2, true>(A, B, nullptr, wf, linq);
+    __syncthreads();
+    net_conv_fwd<2, true>(B, A, nullptr, wf + WLY, linq);
+    __syncthreads();
+    net_conv_fwd<2, true>(A, B, nullptr, wf + 2 * WLY, linq);
+    __syncthreads();
+    net_conv_fwd<2, false>(B, nullptr, out0, wf + 3 * WLY, linq);
+    __syncthreads();
+    const double back = rms / ((N::G - 1) * (N::G - 1));
+    for (int q = threadIdx.x; q < N::NIN; q += blockDim.x) {
+        int a = q % N::IN + 1, b = q / N::IN + 1;
+        if (((a + b) & 1) == 0) vD[idxD(N::G - 1, a, b)] = (T)((double)out0[q] * back);
+    }
+    __syncthreads();
+    return ss;
+}
+
+// The coarse kernel with the network at the cut level.  Net state per
+// problem (Ctl::net): 1 on the first cycle, where both the network and the
+// plain sub-cycle run, the plain one's cut-level residual reduction becomes
+// the bar theta and the better of the two is kept; 2 afterwards, where a
+// cycle whose network correction misses the bar falls back to the plain
+// sub-cycle and switches the network off (state 0) for the rest of the solve.
+template <typename T>
+__global__ void __launch_bounds__(kCoarseThreadsB) kb_coarse_net(CoarseLev<T> L, const Coarse2B<T>* __restrict__ items,
+                                                                 const T* __restrict__ zero, Ctl* __restrict__ ctls,
+                                                                 const bf16_t* __restrict__ wf)
+{
+    using N = NetGeo<2>;
+    const Coarse2B<T>& it = items[blockIdx.x];
+    ITEM_GATE(ctls, it.prob);
+    Ctl* c = &ctls[it.prob];
+    const int top = it.top, cut = kNetCut;
+    const int state = top >= cut ? c->net : 0;
+    if (state == 0) {
+        coarse_down(L, it, top, 0);
+        coarse_up(L, it, zero, 0, top);
+        return;
+    }
+    __shared__ __align__(16) bf16_t A[N::ACT];
+    __shared__ __align__(16) bf16_t B[N::ACT];
+    __shared__ float out0[N::TILES * 16];
+    __shared__ short linq[N::TILES * 16];
+    __shared__ double red[kCoarseThreadsB / 64];
+    __shared__ T vsave[(N::G) * (N::G / 2 + 1)];
+    const int m = L.l[cut].m;
+    const int nD = (int)sizeD(m);
+    coarse_down(L, it, top, cut);
+    double rn2 = net_cut_2d<T>(it.r[cut], it.v[cut - 1], wf, A, B, out0, linq, red);
+    coarse_up(L, it, zero, cut, cut);
+    double qn = cut_resid2<T>(it.r[cut], it.v[cut], m, red);
+    int next = state, used = 0;
+    double theta = c->theta;
+    if (state == 1 || !(qn <= theta * theta * rn2)) {
+        if (state == 1)
+            for (int q = threadIdx.x; q < nD; q += blockDim.x) vsave[q] = it.v[cut - 1][q];
+        __syncthreads();
+        coarse_down(L, it, cut, 0);
+        coarse_up(L, it, zero, 0, cut);
+        double qp = cut_resid2<T>(it.r[cut], it.v[cut], m, red);
+        if (state == 1) {
+            theta = rn2 > 0 ? sqrt(qp / rn2) : 0.0;
+            if (qn <= qp) {   // the network wins the first cycle
+                for (int q = threadIdx.x; q < nD; q += blockDim.x) it.v[cut - 1][q] = vsave[q];
+                __syncthreads();
+                coarse_up(L, it, zero, cut, cut);
+                next = 2;
+                used = 1;
+            } else {
+                next = 0;
+            }
+        } else {
+            next = 0;
+        }
+    } else {
+        used = 1;
+    }
+    coarse_up(L, it, zero, cut + 1, top);
+    if (threadIdx.x == 0) {
+        c->net = next;
+        c->theta = theta;
+        c->net_used += used;
+        if (next == 0) c->net_off = 1;
     }
 }
 
@@ -636,7 +792,7 @@ __global__ void __launch_bounds__(256) kb_finalize(int kind, const Fin2<T>* __re
     }
 }
 
-__global__ void kb_ctl_reset(Ctl* ctls, int nprob, int mode, int max_cycles, double rtol, int* nactive)
+__global__ void kb_ctl_reset(Ctl* ctls, int nprob, int mode, int max_cycles, double rtol, int* nactive, int net)
 {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p == 0) *nactive = nprob;
@@ -652,6 +808,10 @@ __global__ void kb_ctl_reset(Ctl* ctls, int nprob, int mode, int max_cycles, dou
     c->rtol = rtol;
     c->fnorm = 0;
     c->rr0 = c->prev = c->last = 0;
+    c->net = net;
+    c->theta = 0;
+    c->net_used = 0;
+    c->net_off = 0;
 }
 
 template <typename T>
@@ -660,10 +820,11 @@ void launch_b_finalize(int kind, const Fin2<T>* items, int nitems, int nparts, C
     hipLaunchKernelGGL(kb_finalize<T>, dim3(nitems), dim3(256), 0, s, kind, items, nparts, ctls, nactive);
 }
 
-void launch_b_ctl_reset(Ctl* ctls, int nprob, int mode, int max_cycles, double rtol, int* nactive, hipStream_t s)
+void launch_b_ctl_reset(Ctl* ctls, int nprob, int mode, int max_cycles, double rtol, int* nactive, int net,
+                        hipStream_t s)
 {
     hipLaunchKernelGGL(kb_ctl_reset, dim3((nprob + 255) / 256), dim3(256), 0, s, ctls, nprob, mode, max_cycles, rtol,
-                       nactive);
+                       nactive, net);
 }
 
 // level -> natural double array (parity tests)
@@ -677,6 +838,32 @@ __global__ void kb_level_get(int diag, int m, const T* __restrict__ src, double*
     if (!diag) x = (double)src[idxA(m, a, b)];
     else if (((a + b) & 1) == 0) x = (double)src[idxD(m, a, b)];
     dst[idxA(m, a, b)] = x;
+}
+
+// restricted residual of aligned level lam of every coarse item's problem,
+// natural layout (points off a diagonal level read 0), problem-major
+template <typename T>
+__global__ void kb_coarse_export(int lam, int diag, int m, const Coarse2B<T>* __restrict__ items,
+                                 double* __restrict__ dst)
+{
+    const Coarse2B<T>& it = items[blockIdx.x];
+    double* d = dst + (size_t)it.prob * sizeA(m);
+    const T* src = lam <= it.top ? it.r[lam] : nullptr;
+    for (int q = threadIdx.x; q < (int)sizeA(m); q += blockDim.x) {
+        int a = q % (m + 1), b = q / (m + 1);
+        double x = 0;
+        if (src) {
+            if (!diag) x = (double)src[idxA(m, a, b)];
+            else if (((a + b) & 1) == 0) x = (double)src[idxD(m, a, b)];
+        }
+        d[q] = x;
+    }
+}
+
+template <typename T>
+void launch_b_coarse_export(int lam, int diag, int m, const Coarse2B<T>* items, int nitems, double* dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_coarse_export<T>, dim3(nitems), dim3(256), 0, s, lam, diag, m, items, dst);
 }
 
 template <typename T>
@@ -828,6 +1015,15 @@ void launch_b_coarse(const LevInfo<T>* lev, const Coarse2B<T>* items, int nitems
     hipLaunchKernelGGL(kb_coarse<T>, dim3(nitems), dim3(kCoarseThreadsB), 0, s, L, items, zero, ctls);
 }
 
+template <typename T>
+void launch_b_coarse_net(const LevInfo<T>* lev, const Coarse2B<T>* items, int nitems, const T* zero, Ctl* ctls,
+                         const bf16_t* wf, hipStream_t s)
+{
+    CoarseLev<T> L;
+    for (int i = 0; i < kCoarseLevels; i++) L.l[i] = lev[i];
+    hipLaunchKernelGGL(kb_coarse_net<T>, dim3(nitems), dim3(kCoarseThreadsB), 0, s, L, items, zero, ctls, wf);
+}
+
 #define DMG_INSTB(T)                                                                                            \
     template void launch_b_resid<T>(int, const Fin2<T>*, int, const Ctl*, hipStream_t);                        \
     template void launch_b_sumsq<T>(int, const Fin2<T>*, int, const Ctl*, hipStream_t);                        \
@@ -836,7 +1032,10 @@ void launch_b_coarse(const LevInfo<T>* lev, const Coarse2B<T>* items, int nitems
     template void launch_b_jacobi<T>(int, int, int, T, const Item2<T>*, int, const Ctl*, hipStream_t);         \
     template void launch_b_coarse<T>(const LevInfo<T>*, const Coarse2B<T>*, int, const T*, const Ctl*, hipStream_t); \
     template void launch_b_finalize<T>(int, const Fin2<T>*, int, int, Ctl*, int*, hipStream_t);                \
-    template void launch_b_level_get<T>(int, int, const T*, double*, hipStream_t);
+    template void launch_b_level_get<T>(int, int, const T*, double*, hipStream_t);                           \
+    template void launch_b_coarse_net<T>(const LevInfo<T>*, const Coarse2B<T>*, int, const T*, Ctl*, const bf16_t*, \
+                                         hipStream_t);                                                          \
+    template void launch_b_coarse_export<T>(int, int, int, const Coarse2B<T>*, int, double*, hipStream_t);
 DMG_INSTB(double)
 DMG_INSTB(float)
 

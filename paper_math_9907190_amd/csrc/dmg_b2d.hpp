@@ -70,7 +70,14 @@ void launch_b_sumsq(int n, const Fin2<T>* items, int nitems, const Ctl* ctls, hi
 template <typename T>
 void launch_b_finalize(int kind, const Fin2<T>* items, int nitems, int nparts, Ctl* ctls, int* nactive,
                        hipStream_t s);
-void launch_b_ctl_reset(Ctl* ctls, int nprob, int mode, int max_cycles, double rtol, int* nactive, hipStream_t s);
+void launch_b_ctl_reset(Ctl* ctls, int nprob, int mode, int max_cycles, double rtol, int* nactive, int net,
+                        hipStream_t s);
+// the coarse kernel with the learned correction at the cut level (wf: packed forward weights)
+template <typename T>
+void launch_b_coarse_net(const LevInfo<T>* lev, const Coarse2B<T>* items, int nitems, const T* zero, Ctl* ctls,
+                         const unsigned short* wf, hipStream_t s);
+template <typename T>
+void launch_b_coarse_export(int lam, int diag, int m, const Coarse2B<T>* items, int nitems, double* dst, hipStream_t s);
 template <typename T>
 void launch_b_level_get(int diag, int m, const T* src, double* dst, hipStream_t s);
 // default strip length of a row-marching launch (0: use the one-thread-per-point kernel)

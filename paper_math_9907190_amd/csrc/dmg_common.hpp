@@ -72,13 +72,18 @@ struct Ctl {
     int mode;        // 0: single cycle (never sets done); 1: solve
     int max_cycles;
     int k;           // evaluations done so far (batched path)
-    int pad1;
+    int net;         // learned coarse correction: 0 off, 1 first (judged) cycle, 2 on
     double rtol;
     double fnorm;    // ||f||_2 over interior nodes
     double rr0, prev;
     double last;     // relative residual of the latest evaluation
+    double theta;    // the plain sub-cycle's cut-level residual reduction on the first cycle
+    int net_used;    // cycles whose coarse correction came from the network
+    int net_off;     // 1 once the judge switched the network off
     double hist[kMaxCycles + 1];
 };
+// leading fields copied back to the host after a solve
+constexpr size_t kCtlHead = offsetof(Ctl, hist);
 
 constexpr size_t kAlign = 256;
 __host__ __device__ inline size_t alignUp(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }

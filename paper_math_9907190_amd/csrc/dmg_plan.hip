@@ -1,6 +1,7 @@
 // Exported C ABI of libdmg (include/dmg.h): argument checks and dispatch to
 // the 2D plan (a batch of problems; a single problem is a batch of one) or
 // the 3D plan.
+#include "dmg_net.hpp"
 #include "dmg_plan2d.hpp"
 #include "dmg_plan3d.hpp"
 
@@ -218,6 +219,35 @@ int mg_timing_read(mg_plan* P, double* ms, long long* launches, double* bytes)
     if (!g.ok) return MG_ERR_HIP;
     P->tm()->read(ms, launches, bytes);
     return MG_OK;
+}
+
+int mg_net_weight_count(int dim) { return net_weight_count(dim); }
+
+int mg_set_coarse_net(mg_plan* P, const float* w, int cut_level)
+{
+    if (!P) return MG_ERR_ARG;
+    DevGuard g(P->device);
+    if (!g.ok) return MG_ERR_HIP;
+    if (P->p2) return plan2_set_net(*P->p2, w, cut_level);
+    return MG_ERR_ARG;
+}
+
+int mg_net_stats(mg_plan* P, int* net_cycles, int* fell_back)
+{
+    if (!P) return MG_ERR_ARG;
+    DevGuard g(P->device);
+    if (!g.ok) return MG_ERR_HIP;
+    if (P->p2) return plan2_net_stats(*P->p2, net_cycles, fell_back);
+    return MG_ERR_ARG;
+}
+
+int mg_coarse_export(mg_plan* P, int level, double* dst)
+{
+    if (!P || !dst) return MG_ERR_ARG;
+    DevGuard g(P->device);
+    if (!g.ok) return MG_ERR_HIP;
+    if (P->p2) return plan2_coarse_export(*P->p2, level, dst);
+    return MG_ERR_ARG;
 }
 
 int mg_level_get(mg_plan* P, int depth, int which, double* dst)

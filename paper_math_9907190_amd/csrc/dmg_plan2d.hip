@@ -16,6 +16,7 @@
 // iteration launched after the last problem stops runs as gated no-ops.
 #include "dmg_b2d.hpp"
 #include "dmg_host.hpp"
+#include "dmg_net.hpp"
 #include "dmg_plan2d.hpp"
 
 #include <algorithm>
@@ -80,6 +81,7 @@ int plan2_layout(Plan2& P, int nprob, const int* n, int prec, double p)
     P.off_zero = take(sizeof(double) * 64);
     P.off_fin = take(sizeof(Fin2<double>) * (size_t)nprob);
     P.off_coarse = take(sizeof(Coarse2B<double>) * (size_t)nprob);
+    P.off_net = take(sizeof(bf16_t) * (size_t)NetGeo<2>::PACK);
     P.off_rs_items.assign(P.Dmax + 1, 0);
     P.off_jac_items.assign(P.Dmax + 1, 0);
     P.n_rs_items.assign(P.Dmax + 1, 0);
@@ -275,8 +277,12 @@ void enq_cycle(Plan2& P, Ctl* ctls)
             }
         }
         Timed t(&P.tm, MG_K_COARSE, cb * P.n_coarse_items);
-        launch_b_coarse<T>(lev, at<Coarse2B<T>>(P, P.off_coarse), P.n_coarse_items, at<T>(P, P.off_zero), ctls,
-                           P.stream);
+        if (P.has_net)
+            launch_b_coarse_net<T>(lev, at<Coarse2B<T>>(P, P.off_coarse), P.n_coarse_items, at<T>(P, P.off_zero), ctls,
+                                   at<bf16_t>(P, P.off_net), P.stream);
+        else
+            launch_b_coarse<T>(lev, at<Coarse2B<T>>(P, P.off_coarse), P.n_coarse_items, at<T>(P, P.off_zero), ctls,
+                               P.stream);
     }
     for (int lam = 0; lam <= P.Dmax; lam++) {
         int k = P.n_jac_items[lam];
@@ -377,7 +383,7 @@ int plan2_setup(Plan2& P, void* ws, size_t ws_bytes, hipStream_t stream)
     if (hipHostMalloc(&P.hfin, fb, hipHostMallocDefault) != hipSuccess) return MG_ERR_HIP;
     if (hipHostMalloc((void**)&P.hctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) return MG_ERR_HIP;
     if (hipHostMalloc((void**)&P.hact, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) return MG_ERR_HIP;
-    if (hipHostMalloc((void**)&P.hres, sizeof(double) * 9 * (size_t)P.nprob, hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc((void**)&P.hres, kCtlHead * (size_t)P.nprob, hipHostMallocDefault) != hipSuccess)
         return MG_ERR_HIP;
     memset(P.hfin, 0, fb);
     if (hipMemsetAsync(P.ws, 0, P.total, stream) != hipSuccess) return MG_ERR_HIP;
@@ -415,7 +421,7 @@ int plan2_vcycle(Plan2& P, double* const* u, const double* const* f, double* rel
     int* nact = at<int>(P, P.off_nactive);
     int e = bind_uf(P, u, f);
     if (e) return e;
-    launch_b_ctl_reset(ctls, P.nprob, 0, 0, 0.0, nact, P.stream);
+    launch_b_ctl_reset(ctls, P.nprob, 0, 0, 0.0, nact, P.has_net ? 1 : 0, P.stream);
     if (P.prec == MG_FP64) {
         if (relres) enq_norm_f<double>(P, ctls, nact);
         enq_resid<double>(P, ctls, nact);
@@ -429,11 +435,11 @@ int plan2_vcycle(Plan2& P, double* const* u, const double* const* f, double* rel
     if (e) return e;
     if (relres) {
         // relative residual of the entry u of every problem
-        if (hipMemcpy2DAsync(P.hres, sizeof(double) * 9, ctls, sizeof(Ctl), sizeof(double) * 9, P.nprob,
+        if (hipMemcpy2DAsync(P.hres, kCtlHead, ctls, sizeof(Ctl), kCtlHead, P.nprob,
                              hipMemcpyDeviceToHost, P.stream) != hipSuccess)
             return MG_ERR_HIP;
         if (hipStreamSynchronize(P.stream) != hipSuccess) return MG_ERR_HIP;
-        for (int i = 0; i < P.nprob; i++) relres[i] = reinterpret_cast<Ctl*>(P.hres + 9 * (size_t)i)->last;
+        for (int i = 0; i < P.nprob; i++) relres[i] = reinterpret_cast<const Ctl*>(P.hres + kCtlHead * (size_t)i)->last;
     }
     return MG_OK;
 }
@@ -445,7 +451,7 @@ int plan2_solve(Plan2& P, double* const* u, const double* const* f, double rtol,
     int* nact = at<int>(P, P.off_nactive);
     int e = bind_uf(P, u, f);
     if (e) return e;
-    launch_b_ctl_reset(ctls, P.nprob, 1, max_cycles, rtol, nact, P.stream);
+    launch_b_ctl_reset(ctls, P.nprob, 1, max_cycles, rtol, nact, P.has_net ? 1 : 0, P.stream);
     if (P.prec == MG_FP64) { enq_norm_f<double>(P, ctls, nact); enq_resid<double>(P, ctls, nact); }
     else { enq_norm_f<float>(P, ctls, nact); enq_resid<float>(P, ctls, nact); }
     if ((e = last_launch())) return e;
@@ -464,7 +470,7 @@ int plan2_solve(Plan2& P, double* const* u, const double* const* f, double rtol,
     }
     if (hipStreamSynchronize(P.stream) != hipSuccess) return MG_ERR_HIP;
     // per-problem outcome: the first fields of each control block
-    if (hipMemcpy2DAsync(P.hres, sizeof(double) * 9, ctls, sizeof(Ctl), sizeof(double) * 9, P.nprob,
+    if (hipMemcpy2DAsync(P.hres, kCtlHead, ctls, sizeof(Ctl), kCtlHead, P.nprob,
                          hipMemcpyDeviceToHost, P.stream) != hipSuccess)
         return MG_ERR_HIP;
     if (history0 && hipMemcpyAsync(P.hctl, ctls, sizeof(Ctl), hipMemcpyDeviceToHost, P.stream) != hipSuccess)
@@ -472,7 +478,7 @@ int plan2_solve(Plan2& P, double* const* u, const double* const* f, double rtol,
     if (hipStreamSynchronize(P.stream) != hipSuccess) return MG_ERR_HIP;
     int worst = MG_OK;
     for (int i = 0; i < P.nprob; i++) {
-        const Ctl* c = reinterpret_cast<const Ctl*>(P.hres + 9 * (size_t)i);
+        const Ctl* c = reinterpret_cast<const Ctl*>(P.hres + kCtlHead * (size_t)i);
         int st = c->done ? c->status : MG_ERR_NOT_CONVERGED;
         int cy = c->done ? c->cycles : max_cycles;
         if (cycles) cycles[i] = cy;
@@ -573,7 +579,7 @@ int plan2_autotune(Plan2& P)
     const char* path = getenv("DMG_TUNE_CACHE");
     Ctl* ctls = at<Ctl>(P, P.off_ctl);
     int* nact = at<int>(P, P.off_nactive);
-    launch_b_ctl_reset(ctls, P.nprob, 0, 0, 0.0, nact, P.stream);
+    launch_b_ctl_reset(ctls, P.nprob, 0, 0, 0.0, nact, 0, P.stream);
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MG_ERR_HIP;
     const int cand[] = {0, 4, 8, 16, 32};
@@ -601,6 +607,66 @@ int plan2_autotune(Plan2& P)
         (void)hipGraphExecDestroy(P.gexec);
         P.gready = false;
     }
+    return last_launch();
+}
+
+}  // namespace dmg
+
+namespace dmg {
+
+// ------------------------------------------------ learned coarse correction
+
+int plan2_set_net(Plan2& P, const float* w, int cut_level)
+{
+    if (cut_level != kNetCut) return MG_ERR_ARG;
+    if (w) {
+        std::vector<bf16_t> wf(NetGeo<2>::PACK);
+        std::vector<float> wm(w, w + NetGeo<2>::NW);
+        for (int i = 0; i < NetGeo<2>::NW; i++) {   // the padded channels are not parameters
+            int layer = (i >> 8) / NetGeo<2>::T, ci = (i >> 4) & 15, co = i & 15;
+            if ((layer == 0 && ci) || (layer == kNetLayers - 1 && co)) wm[i] = 0.f;
+        }
+        net_pack_host(2, wm.data(), wf.data(), nullptr);
+        if (hipStreamSynchronize(P.stream) != hipSuccess ||
+            hipMemcpy(P.ws + P.off_net, wf.data(), sizeof(bf16_t) * wf.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return MG_ERR_HIP;
+    }
+    bool on = w != nullptr;
+    if (on != P.has_net && P.gready) {   // the captured iteration launches the other coarse kernel
+        (void)hipGraphExecDestroy(P.gexec);
+        P.gready = false;
+    }
+    P.has_net = on;
+    return MG_OK;
+}
+
+int plan2_net_stats(Plan2& P, int* net_cycles, int* fell_back)
+{
+    Ctl* ctls = reinterpret_cast<Ctl*>(P.ws + P.off_ctl);
+    if (hipMemcpy2DAsync(P.hres, kCtlHead, ctls, sizeof(Ctl), kCtlHead, P.nprob, hipMemcpyDeviceToHost, P.stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(P.stream) != hipSuccess)
+        return MG_ERR_HIP;
+    for (int i = 0; i < P.nprob; i++) {
+        const Ctl* c = reinterpret_cast<const Ctl*>(P.hres + kCtlHead * (size_t)i);
+        if (net_cycles) net_cycles[i] = c->net_used;
+        if (fell_back) fell_back[i] = c->net_off;
+    }
+    return MG_OK;
+}
+
+int plan2_coarse_export(Plan2& P, int level, double* dst)
+{
+    if (level < 0 || level > P.lamc || !dst) return MG_ERR_ARG;
+    int m = side_of(level), diag = level & 1;
+    if (!P.n_coarse_items) return MG_OK;
+    Coarse2B<double>* items = reinterpret_cast<Coarse2B<double>*>(P.ws + P.off_coarse);
+    if (hipMemsetAsync(dst, 0, sizeof(double) * sizeA(m) * (size_t)P.nprob, P.stream) != hipSuccess) return MG_ERR_HIP;
+    if (P.prec == MG_FP64)
+        launch_b_coarse_export<double>(level, diag, m, items, P.n_coarse_items, dst, P.stream);
+    else
+        launch_b_coarse_export<float>(level, diag, m, reinterpret_cast<Coarse2B<float>*>(items), P.n_coarse_items, dst,
+                                      P.stream);
     return last_launch();
 }
 

@@ -14,7 +14,8 @@ struct Plan2 {
     // size classes (distinct n, ascending); the finest-item table is grouped by class
     std::vector<int> order, cls_n, cls_first, cls_count, nparts;
     // workspace offsets
-    size_t off_ctl = 0, off_nactive = 0, off_zero = 0, off_fin = 0, off_coarse = 0, total = 0;
+    size_t off_ctl = 0, off_nactive = 0, off_zero = 0, off_fin = 0, off_coarse = 0, off_net = 0, total = 0;
+    bool has_net = false;     // learned coarse correction set (packed bf16 weights at off_net)
     std::vector<size_t> off_r0, off_part;
     std::vector<std::vector<size_t>> off_r, off_v;   // [problem][aligned level]
     std::vector<size_t> off_rs_items, off_jac_items; // [aligned level]
@@ -28,7 +29,7 @@ struct Plan2 {
     void* hfin = nullptr;     // pinned host image of the finest-item table
     Ctl* hctl = nullptr;      // pinned: problem 0's control block (history)
     int* hact = nullptr;      // pinned: active-problem counts of two iterations
-    double* hres = nullptr;   // pinned: first fields of every control block
+    char* hres = nullptr;     // pinned: the first kCtlHead bytes of every control block
     hipEvent_t ev[2];
     hipEvent_t evu;           // completion of the last finest-table upload (hfin is then free to rewrite)
     bool evs = false, fin_valid = false;
@@ -48,5 +49,8 @@ int plan2_solve(Plan2& P, double* const* u, const double* const* f, double rtol,
 int plan2_level_get(Plan2& P, int depth, int which, double* dst);
 int plan2_tune_load(Plan2& P);
 int plan2_autotune(Plan2& P);
+int plan2_set_net(Plan2& P, const float* w, int cut_level);
+int plan2_net_stats(Plan2& P, int* net_cycles, int* fell_back);
+int plan2_coarse_export(Plan2& P, int level, double* dst);
 
 }  // namespace dmg

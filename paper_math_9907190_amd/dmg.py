@@ -41,16 +41,39 @@ _lib.mg_solve_batched.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                   _ip, _dp, _ip]
 _lib.mg_vcycle_batched.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _dp]
 _lib.mg_autotune.argtypes = [_vp]
+_fp, _ull = ctypes.POINTER(ctypes.c_float), ctypes.c_ulonglong
+_lib.mg_net_weight_count.argtypes = [ctypes.c_int]
+_lib.mg_net_workspace_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_sz)]
+_lib.mg_net_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _vp, _sz, _vp]
+_lib.mg_net_set_weights.argtypes = [_vp, _fp]
+_lib.mg_net_get_weights.argtypes = [_vp, _fp]
+_lib.mg_net_init.argtypes = [_vp, _ull]
+_lib.mg_net_forward.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int]
+_lib.mg_net_loss_grad.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _fp, _dp]
+_lib.mg_net_train.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_float, _ull, _dp]
+_lib.mg_net_destroy.argtypes = [_vp]
+_lib.mg_set_coarse_net.argtypes = [_vp, _fp, ctypes.c_int]
+_lib.mg_net_stats.argtypes = [_vp, _ip, _ip]
+_lib.mg_coarse_export.argtypes = [_vp, ctypes.c_int, _vp]
 _lib.mg_strerror.argtypes = [ctypes.c_int]
 _lib.mg_strerror.restype = ctypes.c_char_p
 for _f in ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_level_get", "mg_level_info",
            "mg_destroy", "mg_timing_enable", "mg_timing_read", "mg_batch_workspace_bytes", "mg_setup_batched",
-           "mg_solve_batched", "mg_vcycle_batched", "mg_autotune"):
+           "mg_solve_batched", "mg_vcycle_batched", "mg_autotune", "mg_net_weight_count", "mg_net_workspace_bytes",
+           "mg_net_create", "mg_net_set_weights", "mg_net_get_weights", "mg_net_init", "mg_net_forward",
+           "mg_net_loss_grad", "mg_net_train", "mg_net_destroy", "mg_set_coarse_net", "mg_net_stats",
+           "mg_coarse_export"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_level_get", "mg_level_info",
            "mg_destroy", "mg_strerror", "mg_timing_enable", "mg_timing_read", "mg_batch_workspace_bytes",
-           "mg_setup_batched", "mg_solve_batched", "mg_vcycle_batched", "mg_autotune")
+           "mg_setup_batched", "mg_solve_batched", "mg_vcycle_batched", "mg_autotune", "mg_net_weight_count",
+           "mg_net_workspace_bytes", "mg_net_create", "mg_net_set_weights", "mg_net_get_weights", "mg_net_init",
+           "mg_net_forward", "mg_net_loss_grad", "mg_net_train", "mg_net_destroy", "mg_set_coarse_net",
+           "mg_net_stats", "mg_coarse_export")
+
+MG_NET_CUT = 6
+NET_G = {2: 17, 3: 9}
 
 # kernel families for mg_timing_enable
 MG_K_RESIDUAL, MG_K_RESTRICT, MG_K_JACOBI, MG_K_FINEST, MG_K_COARSE, MG_K_NORM = range(6)
@@ -177,6 +200,90 @@ def mg_timing_read(plan):
     return ms.value, cnt.value, by.value
 
 
+# ------------------------------------------- learned coarse correction (raw)
+
+def mg_net_weight_count(dim):
+    return _lib.mg_net_weight_count(dim)
+
+
+def _f32(w, count):
+    import numpy as np
+    w = np.ascontiguousarray(np.asarray(w, dtype=np.float32).reshape(-1))
+    if w.size != count:
+        raise ValueError("expected %d weights, got %d" % (count, w.size))
+    return w, w.ctypes.data_as(_fp)
+
+
+def mg_net_workspace_bytes(dim, max_batch):
+    out = _sz()
+    _check(_lib.mg_net_workspace_bytes(dim, max_batch, ctypes.byref(out)), "mg_net_workspace_bytes")
+    return out.value
+
+
+def mg_net_create(dim, max_batch, workspace_ptr, ws_bytes, stream_ptr):
+    net = _vp()
+    _check(_lib.mg_net_create(ctypes.byref(net), dim, max_batch, workspace_ptr, ws_bytes, stream_ptr), "mg_net_create")
+    return net
+
+
+def mg_net_set_weights(net, dim, w):
+    arr, ptr = _f32(w, mg_net_weight_count(dim))
+    _check(_lib.mg_net_set_weights(net, ptr), "mg_net_set_weights")
+
+
+def mg_net_get_weights(net, dim):
+    import numpy as np
+    w = np.zeros(mg_net_weight_count(dim), dtype=np.float32)
+    _check(_lib.mg_net_get_weights(net, w.ctypes.data_as(_fp)), "mg_net_get_weights")
+    return w
+
+
+def mg_net_init(net, seed):
+    _check(_lib.mg_net_init(net, seed), "mg_net_init")
+
+
+def mg_net_forward(net, in_ptr, out_ptr, batch, normalize):
+    _check(_lib.mg_net_forward(net, in_ptr, out_ptr, batch, int(normalize)), "mg_net_forward")
+
+
+def mg_net_loss_grad(net, dim, in_ptr, target_ptr, batch, normalize):
+    import numpy as np
+    g = np.zeros(mg_net_weight_count(dim), dtype=np.float32)
+    loss = ctypes.c_double()
+    _check(_lib.mg_net_loss_grad(net, in_ptr, target_ptr, batch, int(normalize), g.ctypes.data_as(_fp),
+                                 ctypes.byref(loss)), "mg_net_loss_grad")
+    return loss.value, g
+
+
+def mg_net_train(net, r_ptr, e_ptr, npairs, epochs, batch, lr, seed):
+    h = (ctypes.c_double * max(epochs, 1))()
+    _check(_lib.mg_net_train(net, r_ptr, e_ptr, npairs, epochs, batch, lr, seed, h), "mg_net_train")
+    return list(h)[:epochs]
+
+
+def mg_net_destroy(net):
+    _check(_lib.mg_net_destroy(net), "mg_net_destroy")
+
+
+def mg_set_coarse_net(plan, dim, w, cut_level=MG_NET_CUT):
+    if w is None:
+        _check(_lib.mg_set_coarse_net(plan, None, cut_level), "mg_set_coarse_net")
+        return
+    arr, ptr = _f32(w, mg_net_weight_count(dim))
+    _check(_lib.mg_set_coarse_net(plan, ptr, cut_level), "mg_set_coarse_net")
+
+
+def mg_net_stats(plan, nprob):
+    used = (ctypes.c_int * nprob)()
+    off = (ctypes.c_int * nprob)()
+    _check(_lib.mg_net_stats(plan, used, off), "mg_net_stats")
+    return list(used), list(off)
+
+
+def mg_coarse_export(plan, level, dst_ptr):
+    _check(_lib.mg_coarse_export(plan, level, dst_ptr), "mg_coarse_export")
+
+
 # ------------------------------------------------------------ torch plumbing
 
 P2D_TUNED = (1.052,)                    # Section 2.5
@@ -234,10 +341,85 @@ class Solver:
     def autotune(self):
         mg_autotune(self.plan)
 
+    def set_coarse_net(self, w):
+        """Weights (host array, mg_net_weight_count(2) floats) of the learned
+        coarse correction, or None for the plain cycle."""
+        mg_set_coarse_net(self.plan, 2, w)
+
+    def net_stats(self):
+        """(cycles that used the network, 1 where the judge switched it off) per problem."""
+        return mg_net_stats(self.plan, len(self.ns))
+
+    def coarse_export(self, level=MG_NET_CUT):
+        """Restricted residual of aligned level `level` of every problem after the last cycle."""
+        side = 1 << (1 + (level + 1) // 2)
+        out = torch.empty((len(self.ns), side + 1, side + 1), dtype=torch.float64, device=self.device)
+        mg_coarse_export(self.plan, level, out.data_ptr())
+        return out
+
     def close(self):
         if getattr(self, "plan", None) is not None:
             mg_destroy(self.plan)
             self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Net:
+    """Trainer of the learned coarse correction: master weights, Adam state
+    and gradient buffers for up to max_batch samples in a torch workspace."""
+
+    def __init__(self, dim=2, max_batch=256, seed=None, device=None, stream=None):
+        self.dim, self.max_batch = dim, max_batch
+        self.G = NET_G[dim]
+        self.nw = mg_net_weight_count(dim)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.ws_bytes = mg_net_workspace_bytes(dim, max_batch)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+            ptr = (self.ws.data_ptr() + 255) // 256 * 256
+            self.net = mg_net_create(dim, max_batch, ptr, self.ws_bytes, self.stream.cuda_stream)
+        if seed is not None:
+            mg_net_init(self.net, seed)
+
+    def _grid(self, t, name):
+        shape = (self.G,) * self.dim
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape[1:]) == shape
+                and t.device == self.device):
+            raise ValueError("%s must be a contiguous float64 tensor of shape (B,) + %s on %s" % (name, shape, self.device))
+
+    def set_weights(self, w):
+        mg_net_set_weights(self.net, self.dim, w)
+
+    def weights(self):
+        return mg_net_get_weights(self.net, self.dim).reshape(4, 3 ** self.dim, 16, 16)
+
+    def forward(self, x, normalize=True):
+        self._grid(x, "x")
+        out = torch.empty_like(x)
+        mg_net_forward(self.net, x.data_ptr(), out.data_ptr(), x.shape[0], normalize)
+        return out
+
+    def loss_grad(self, x, target, normalize=False):
+        self._grid(x, "x")
+        self._grid(target, "target")
+        loss, g = mg_net_loss_grad(self.net, self.dim, x.data_ptr(), target.data_ptr(), x.shape[0], normalize)
+        return loss, g.reshape(4, 3 ** self.dim, 16, 16)
+
+    def train(self, r, e, epochs, batch=256, lr=1e-3, seed=0):
+        self._grid(r, "r")
+        self._grid(e, "e")
+        return mg_net_train(self.net, r.data_ptr(), e.data_ptr(), r.shape[0], epochs, batch, lr, seed)
+
+    def close(self):
+        if getattr(self, "net", None) is not None:
+            mg_net_destroy(self.net)
+            self.net = None
 
     def __del__(self):
         try:
@@ -282,10 +464,85 @@ class BatchSolver:
     def autotune(self):
         mg_autotune(self.plan)
 
+    def set_coarse_net(self, w):
+        """Weights (host array, mg_net_weight_count(2) floats) of the learned
+        coarse correction, or None for the plain cycle."""
+        mg_set_coarse_net(self.plan, 2, w)
+
+    def net_stats(self):
+        """(cycles that used the network, 1 where the judge switched it off) per problem."""
+        return mg_net_stats(self.plan, len(self.ns))
+
+    def coarse_export(self, level=MG_NET_CUT):
+        """Restricted residual of aligned level `level` of every problem after the last cycle."""
+        side = 1 << (1 + (level + 1) // 2)
+        out = torch.empty((len(self.ns), side + 1, side + 1), dtype=torch.float64, device=self.device)
+        mg_coarse_export(self.plan, level, out.data_ptr())
+        return out
+
     def close(self):
         if getattr(self, "plan", None) is not None:
             mg_destroy(self.plan)
             self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Net:
+    """Trainer of the learned coarse correction: master weights, Adam state
+    and gradient buffers for up to max_batch samples in a torch workspace."""
+
+    def __init__(self, dim=2, max_batch=256, seed=None, device=None, stream=None):
+        self.dim, self.max_batch = dim, max_batch
+        self.G = NET_G[dim]
+        self.nw = mg_net_weight_count(dim)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.ws_bytes = mg_net_workspace_bytes(dim, max_batch)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+            ptr = (self.ws.data_ptr() + 255) // 256 * 256
+            self.net = mg_net_create(dim, max_batch, ptr, self.ws_bytes, self.stream.cuda_stream)
+        if seed is not None:
+            mg_net_init(self.net, seed)
+
+    def _grid(self, t, name):
+        shape = (self.G,) * self.dim
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape[1:]) == shape
+                and t.device == self.device):
+            raise ValueError("%s must be a contiguous float64 tensor of shape (B,) + %s on %s" % (name, shape, self.device))
+
+    def set_weights(self, w):
+        mg_net_set_weights(self.net, self.dim, w)
+
+    def weights(self):
+        return mg_net_get_weights(self.net, self.dim).reshape(4, 3 ** self.dim, 16, 16)
+
+    def forward(self, x, normalize=True):
+        self._grid(x, "x")
+        out = torch.empty_like(x)
+        mg_net_forward(self.net, x.data_ptr(), out.data_ptr(), x.shape[0], normalize)
+        return out
+
+    def loss_grad(self, x, target, normalize=False):
+        self._grid(x, "x")
+        self._grid(target, "target")
+        loss, g = mg_net_loss_grad(self.net, self.dim, x.data_ptr(), target.data_ptr(), x.shape[0], normalize)
+        return loss, g.reshape(4, 3 ** self.dim, 16, 16)
+
+    def train(self, r, e, epochs, batch=256, lr=1e-3, seed=0):
+        self._grid(r, "r")
+        self._grid(e, "e")
+        return mg_net_train(self.net, r.data_ptr(), e.data_ptr(), r.shape[0], epochs, batch, lr, seed)
+
+    def close(self):
+        if getattr(self, "net", None) is not None:
+            mg_net_destroy(self.net)
+            self.net = None
 
     def __del__(self):
         try:

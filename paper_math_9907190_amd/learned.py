@@ -1,0 +1,75 @@
+"""Learned coarse correction: training pairs, training, evaluation helpers.
+
+Orchestration only: every arithmetic step runs in libdmg's kernels.
+
+* Pairs (r_c, e_c) of the cut level (aligned level 6: the 17 x 17 axis grid
+  of a 2D problem) come from the plain FP64 V-cycle: a batch of problems is
+  cycled from u = 0, and after every cycle the cut level's restricted
+  residual r_c is exported.  The target e_c = A_c^{-1} r_c is the solution of
+  the 17 x 17 Poisson problem with right-hand side r_c, solved by the same
+  library (batched, FP64) to a relative residual of 1e-13.
+* Training: Adam on the normalised pairs (libdmg's bf16 forward/backward
+  kernels, FP32 master weights).
+"""
+import concurrent.futures as cf
+
+import numpy as np
+import torch
+
+from . import dmg, workloads
+
+CUT = dmg.MG_NET_CUT
+
+
+def _rhs_batch(n, seeds, threads=8):
+    with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(lambda s: workloads.training_rhs(2, n, s), seeds))
+
+
+def make_pairs(n=1024, seeds=range(1000, 2250), cycles=8, chunk=125, device=None, target_rtol=1e-13, log=None):
+    """(r, e): float64 device tensors of shape (len(seeds) * cycles, 17, 17)."""
+    device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    seeds = list(seeds)
+    rs = []
+    for c0 in range(0, len(seeds), chunk):
+        sl = seeds[c0:c0 + chunk]
+        if log:
+            log("pairs: problems %d..%d of %d (n=%d)" % (c0, c0 + len(sl) - 1, len(seeds), n))
+        fs = [torch.from_numpy(f).to(device) for f in _rhs_batch(n, sl)]
+        us = [torch.zeros_like(f) for f in fs]
+        B = dmg.BatchSolver([n] * len(sl), precision=dmg.MG_FP64, device=device)
+        for _ in range(cycles):
+            B.vcycle(us, fs)
+            rs.append(B.coarse_export(CUT))
+        B.close()
+        del B, us, fs
+    r = torch.cat(rs).contiguous()
+    e = solve_cut(r, target_rtol, device)
+    return r, e
+
+
+def solve_cut(r, rtol=1e-13, device=None):
+    """e = A_c^{-1} r for each 17 x 17 grid of r (FP64 batched solve)."""
+    P = r.shape[0]
+    G = r.shape[-1]
+    e = torch.zeros_like(r)
+    T = dmg.BatchSolver([G - 1] * P, precision=dmg.MG_FP64, device=device or r.device)
+    st, cyc, rr, sts = T.solve([e[i] for i in range(P)], [r[i] for i in range(P)], rtol=rtol, max_cycles=60)
+    T.close()
+    bad = [i for i, s in enumerate(sts) if s != dmg.MG_OK and rr[i] > 1e-12]
+    if bad:
+        raise RuntimeError("target solves failed for %d pairs (first %d: status %d)" % (len(bad), bad[0], sts[bad[0]]))
+    return e
+
+
+def train(r, e, epochs=30, batch=256, lr=2e-3, seed=7, init_seed=1, net=None):
+    """Train (or continue training) a network on the pairs; returns (net, epoch losses)."""
+    if net is None:
+        net = dmg.Net(dim=2, max_batch=batch, seed=init_seed, device=r.device)
+    hist = net.train(r, e, epochs=epochs, batch=batch, lr=lr, seed=seed)
+    return net, hist
+
+
+def eval_problems(n=1024, seeds=range(5000, 5032)):
+    """Held-out right-hand sides (host arrays)."""
+    return _rhs_batch(n, list(seeds))

@@ -69,3 +69,30 @@ def test_setup_argument_errors_before_any_gpu_call(D):
     assert D._lib.mg_setup(ctypes.byref(plan), 2, 64, 0, p1, 1, ctypes.c_void_p(4096), 16, None) == D.MG_ERR_WS
     assert D._lib.mg_setup(ctypes.byref(plan), 2, 64, 0, p1, 1, ctypes.c_void_p(4097), 1 << 30, None) == D.MG_ERR_WS
     assert D.mg_strerror(D.MG_ERR_WS).startswith("workspace")
+
+
+def test_net_sizes_and_argument_errors(D):
+    assert D.mg_net_weight_count(2) == 4 * 9 * 16 * 16
+    assert D.mg_net_weight_count(3) == 4 * 27 * 16 * 16
+    assert D.mg_net_weight_count(4) == 0
+    b2 = D.mg_net_workspace_bytes(2, 256)
+    # master weights, two Adam moments, two bf16 copies, per-sample gradients
+    assert b2 >= 4 * 9216 * (3 + 256) + 2 * 2 * 9216
+    assert D.mg_net_workspace_bytes(3, 1) < D.mg_net_workspace_bytes(3, 2)
+    out = ctypes.c_size_t()
+    assert D._lib.mg_net_workspace_bytes(4, 8, ctypes.byref(out)) == D.MG_ERR_ARG
+    assert D._lib.mg_net_workspace_bytes(2, 0, ctypes.byref(out)) == D.MG_ERR_ARG
+    net = ctypes.c_void_p()
+    assert D._lib.mg_net_create(ctypes.byref(net), 2, 8, None, 0, None) == D.MG_ERR_WS
+    assert D._lib.mg_net_create(ctypes.byref(net), 5, 8, None, 0, None) == D.MG_ERR_ARG
+    assert D._lib.mg_net_destroy(None) == D.MG_OK
+    # a plan is required; checked before any GPU call
+    assert D._lib.mg_set_coarse_net(None, None, 6) == D.MG_ERR_ARG
+    assert D._lib.mg_net_stats(None, None, None) == D.MG_ERR_ARG
+    assert D._lib.mg_coarse_export(None, 6, None) == D.MG_ERR_ARG
+
+
+def test_batch_workspace_holds_the_net_weights(D):
+    # the packed bf16 forward weights (9216 entries) are part of every 2D plan
+    b = D.mg_batch_workspace_bytes([4], D.MG_FP64)
+    assert b >= 2 * 9216

@@ -1,0 +1,363 @@
+"""Learned coarse correction on the GPU.
+
+* the bf16/MFMA forward and the weight gradient against the FP64 CPU oracle
+  evaluated on the same bf16-rounded weights and inputs (2D and 3D);
+* hand-set stencil and shift weights, exact in bf16, give exactly the
+  oracle's output;
+* one Adam step against the oracle's Adam applied to the GPU gradient;
+* training on pairs from the plain solver lowers the loss, and the trained
+  network estimates the cut level's correction better than the untrained one;
+* the judge: its per-problem decision on a first cycle matches the decision
+  predicted from the stand-alone network and the oracle's plain sub-cycle;
+  poisoned weights leave the solve bitwise equal to the plain one;
+* a learned solve reaches 1e-10; its cycles and time against plain are
+  printed (the gain itself has no reference value).
+"""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_math_9907190_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dmg():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_math_9907190_amd import dmg as D
+    return D
+
+
+def bf(a):
+    """round to bf16 (nearest even) and back, on the CPU"""
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).bfloat16().double().numpy()
+
+
+def rand_grid(rng, dim, B, scale=1.0):
+    G = O.NET_G[dim]
+    x = np.zeros((B,) + (G,) * dim)
+    sl = (slice(None),) + (slice(1, -1),) * dim
+    x[sl] = rng.standard_normal(x[sl].shape) * scale
+    return x
+
+
+def rand_weights(rng, dim):
+    T = O.NET_TAPS[dim]
+    w = np.zeros(O.net_shape(dim))
+    w[0, :, 0, :] = rng.standard_normal((T, 16)) * np.sqrt(2.0 / T)
+    w[1:3] = rng.standard_normal((2, T, 16, 16)) * np.sqrt(2.0 / (16 * T))
+    w[3, :, :, 0] = rng.standard_normal((T, 16)) * np.sqrt(2.0 / (16 * T))
+    return w
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_forward_matches_oracle(dmg, orc, dim):
+    print("forward parity dim", dim, flush=True)
+    rng = np.random.default_rng(100 + dim)
+    w = bf(rand_weights(rng, dim))
+    x = bf(rand_grid(rng, dim, 6))
+    net = dmg.Net(dim=dim, max_batch=8)
+    net.set_weights(w.astype(np.float32))
+    y = net.forward(dev(x), normalize=False).cpu().numpy()
+    yo = O.net_forward(x, w)
+    err = np.abs(y - yo).max() / np.abs(yo).max()
+    print("  max error / max |y| = %.2e" % err)
+    assert err <= 2e-2
+    # normalised inference: input scaled by 1/rms, output by rms * H^2
+    yn = net.forward(dev(x), normalize=True).cpu().numpy()
+    G = O.NET_G[dim]
+    for b in range(x.shape[0]):
+        rms = np.sqrt((x[b] ** 2).sum() / (G - 2) ** dim)
+        yb = O.net_forward(bf(x[b:b + 1] / rms), w)[0] * rms / (G - 1) ** 2
+        assert np.abs(yn[b] - yb).max() <= 2e-2 * np.abs(yb).max()
+    net.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gradient_matches_oracle(dmg, orc, dim):
+    print("gradient parity dim", dim, flush=True)
+    rng = np.random.default_rng(200 + dim)
+    w = bf(rand_weights(rng, dim))
+    x = bf(rand_grid(rng, dim, 5))
+    t = rand_grid(rng, dim, 5, scale=0.5)
+    net = dmg.Net(dim=dim, max_batch=8)
+    net.set_weights(w.astype(np.float32))
+    loss, g = net.loss_grad(dev(x), dev(t), normalize=False)
+    lo, go = O.net_loss_grad(x, t, w)
+    print("  loss gpu %.6e oracle %.6e" % (loss, lo))
+    stats = []
+    for l in range(4):
+        d = np.abs(g[l] - go[l]).max() / np.abs(go[l]).max()
+        cos = (g[l] * go[l]).sum() / np.sqrt((g[l] ** 2).sum() * (go[l] ** 2).sum())
+        print("  layer %d: max err / max |g| = %.2e, cosine %.6f" % (l, d, cos))
+        stats.append((d, cos))
+    # bf16 activations and output gradients: about 8 roundings of 2^-9 along
+    # the deepest chain, amplified by cancellation in sums of up to 432 terms
+    assert abs(loss - lo) <= 1e-2 * lo
+    for d, cos in stats:
+        assert d <= 6e-2 and cos >= 0.998
+    assert not g[0, :, 1:, :].any() and not g[3, :, :, 1:].any()
+    net.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gradient_exact_on_exact_data(dmg, orc, dim):
+    """Stencil weights, inputs k/8 and targets that make every output
+    gradient +-2^-6: every activation, gradient and partial sum is exact in
+    bf16 / fp32, so the GPU gradient must equal the oracle's bit for bit."""
+    print("exact gradient dim", dim, flush=True)
+    rng = np.random.default_rng(250 + dim)
+    G = O.NET_G[dim]
+    B = 3
+    x = np.zeros((B,) + (G,) * dim)
+    sl = (slice(None),) + (slice(1, -1),) * dim
+    x[sl] = rng.integers(-16, 17, x[sl].shape) / 8.0
+    w = stencil_weights(dim)
+    out = O.net_forward(x, w)
+    cnt = B * (G - 2) ** dim
+    sgn = np.zeros_like(x)
+    sgn[sl] = rng.choice([-1.0, 1.0], x[sl].shape)
+    t = out - sgn * 2.0 ** -6 * cnt / 2          # out - t = +-2^-6 cnt / 2, so dloss/dout = +-2^-6
+    net = dmg.Net(dim=dim, max_batch=8)
+    net.set_weights(w.astype(np.float32))
+    loss, g = net.loss_grad(dev(x), dev(t), normalize=False)
+    lo, go = O.net_loss_grad(x, t, w)
+    assert loss == pytest.approx(lo, rel=1e-14)    # a reciprocal against a division
+    assert np.abs(go).max() > 0
+    np.testing.assert_array_equal(g, go.astype(np.float32))
+    net.close()
+
+
+def stencil_weights(dim):
+    T = O.NET_TAPS[dim]
+    c = T // 2
+    w = np.zeros(O.net_shape(dim))
+    w[0, c, 0, 0], w[0, c, 0, 1] = 1.0, -1.0
+    for l in (1, 2):
+        w[l, c, 0, 0] = w[l, c, 1, 1] = 1.0
+    s = np.zeros(T)
+    s[c] = -2.0 * dim
+    for step in [1, 3, 9][:dim]:
+        s[c + step] = s[c - step] = 1.0
+    w[3, :, 0, 0], w[3, :, 1, 0] = s, -s
+    return w
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_exact_weights_give_exact_output(dmg, orc, dim):
+    print("exact stencil/shift dim", dim, flush=True)
+    rng = np.random.default_rng(300 + dim)
+    G = O.NET_G[dim]
+    x = np.zeros((4,) + (G,) * dim)
+    sl = (slice(None),) + (slice(1, -1),) * dim
+    x[sl] = rng.integers(-16, 17, x[sl].shape) / 8.0      # exact in bf16
+    net = dmg.Net(dim=dim, max_batch=8)
+    w = stencil_weights(dim)
+    net.set_weights(w.astype(np.float32))
+    np.testing.assert_array_equal(net.forward(dev(x), normalize=False).cpu().numpy(), O.net_forward(x, w))
+    T = O.NET_TAPS[dim]
+    w = np.zeros(O.net_shape(dim))
+    for l in (0, 1, 2):
+        w[l, T // 2, 0, 0] = 1.0
+    w[3, T // 2 + (9 if dim == 3 else 1), 0, 0] = 1.0
+    net.set_weights(w.astype(np.float32))
+    xa = np.abs(x)
+    np.testing.assert_array_equal(net.forward(dev(xa), normalize=False).cpu().numpy(), O.net_forward(xa, w))
+    net.close()
+
+
+def test_adam_step_matches_oracle(dmg, orc):
+    rng = np.random.default_rng(400)
+    w = rand_weights(rng, 2).astype(np.float32)
+    x = rand_grid(rng, 2, 4)
+    t = rand_grid(rng, 2, 4)
+    net = dmg.Net(dim=2, max_batch=4)
+    net.set_weights(w)
+    loss, g = net.loss_grad(dev(x), dev(t), normalize=True)
+    lr = 1e-3
+    net.train(dev(x), dev(t), epochs=1, batch=4, lr=lr, seed=3)
+    w1 = net.weights()
+    wo, m, v = w.astype(np.float64).copy(), np.zeros(w.shape), np.zeros(w.shape)
+    O.net_adam(wo, m, v, g.astype(np.float64), 1, lr, 0.9, 0.999, 1e-8)
+    big = np.abs(g) > 1e-3 * np.abs(g).max()      # the gradient's sign is unambiguous there
+    assert np.abs(w1 - wo)[big].max() <= 1e-6
+    # the first Adam step moves each weight by at most lr (plus the fp32 rounding of the weight)
+    assert np.all(np.abs(w1 - w) <= lr * (1 + 1e-5) + 2 * np.spacing(np.abs(w)))
+    net.close()
+
+
+# ------------------------------------------------------------ training + solve
+
+NT = 128   # problem size of the training / solve tests (cut level at aligned level 6)
+
+
+@pytest.fixture(scope="module")
+def trained(dmg):
+    from paper_math_9907190_amd import learned as L
+    print("pairs from 64 problems of side %d, 4 cycles each" % NT, flush=True)
+    r, e = L.make_pairs(n=NT, seeds=range(1000, 1064), cycles=4, chunk=64)
+    print("training", flush=True)
+    net, hist = L.train(r, e, epochs=60, batch=64, lr=2e-3, seed=5)
+    w = net.weights().copy()
+    net.close()
+    return r, e, w, hist
+
+
+def test_training_lowers_loss(trained):
+    r, e, w, hist = trained
+    print("epoch losses: first %.4e, last %.4e" % (hist[0], hist[-1]))
+    assert np.all(np.isfinite(hist))
+    assert hist[-1] < 0.5 * hist[0]
+
+
+def jacobi_cut(r6, y, p=1.052):
+    """level 6's Jacobi (the oracle's single-level step) from the C-point
+    values of y"""
+    m = r6.shape[0] - 1
+    return O.step_jacobi(2, 0, p / m ** 2, r6, c_points(y))
+
+
+def cut_ratio(r6, v6):
+    """||r - A v6|| / ||r|| with A the 5-point Laplacian of the cut level"""
+    m = r6.shape[0] - 1
+    res = r6[1:-1, 1:-1] - (v6[2:, 1:-1] + v6[:-2, 1:-1] + v6[1:-1, 2:] + v6[1:-1, :-2] - 4 * v6[1:-1, 1:-1]) * m * m
+    return np.linalg.norm(res) / np.linalg.norm(r6[1:-1, 1:-1])
+
+
+def plain_cut(r6):
+    """the plain sub-cycle below the cut = one V-cycle of the 17 x 17 problem from zero"""
+    return O.vcycle(np.zeros_like(r6), r6, p=(1.052,))
+
+
+def c_points(v):
+    out = v.copy()
+    a, b = np.meshgrid(np.arange(v.shape[0]), np.arange(v.shape[0]), indexing="ij")
+    out[(a + b) % 2 == 1] = 0
+    return out
+
+
+def test_trained_net_beats_untrained_at_the_cut(dmg, orc, trained):
+    r, e, w, hist = trained
+    from paper_math_9907190_amd import learned as L
+    rh, eh = L.make_pairs(n=NT, seeds=range(5000, 5008), cycles=2, chunk=8)
+    net = dmg.Net(dim=2, max_batch=64, seed=1)
+    y0 = net.forward(rh).cpu().numpy()
+    net.set_weights(w)
+    y1 = net.forward(rh).cpu().numpy()
+    rh = rh.cpu().numpy()
+    rows = []
+    for i in range(rh.shape[0]):
+        rows.append((cut_ratio(rh[i], jacobi_cut(rh[i], y0[i])), cut_ratio(rh[i], jacobi_cut(rh[i], y1[i])),
+                     cut_ratio(rh[i], plain_cut(rh[i]))))
+    rows = np.array(rows)
+    print("cut-level residual reduction (median): untrained %.3e, trained %.3e, plain sub-cycle %.3e"
+          % tuple(np.median(rows, axis=0)))
+    assert np.median(rows[:, 1]) < 0.5 * np.median(rows[:, 0])
+    net.close()
+
+
+def test_judge_decisions_match_prediction(dmg, orc, trained):
+    r, e, w, hist = trained
+    ns = [NT] * 8
+    fs = [W.training_rhs(2, NT, s) for s in range(6000, 6008)]
+    B = dmg.BatchSolver(ns, precision=dmg.MG_FP64)
+    B.set_coarse_net(w)
+    us = [dev(np.zeros_like(f)) for f in fs]
+    B.vcycle(us, [dev(f) for f in fs])         # one first (judged) cycle
+    used, off = B.net_stats()
+    r6 = B.coarse_export(6)
+    net = dmg.Net(dim=2, max_batch=8)
+    net.set_weights(w)
+    y = net.forward(r6).cpu().numpy()
+    r6 = r6.cpu().numpy()
+    checked = 0
+    for i in range(len(ns)):
+        qn = cut_ratio(r6[i], jacobi_cut(r6[i], y[i]))
+        qp = cut_ratio(r6[i], plain_cut(r6[i]))
+        print("  problem %d: net %.3e plain %.3e -> used %d off %d" % (i, qn, qp, used[i], off[i]))
+        if abs(qn - qp) > 0.02 * qp:
+            assert used[i] == (1 if qn <= qp else 0) and off[i] == (0 if qn <= qp else 1), i
+            checked += 1
+    assert checked >= 4
+    net.close()
+    B.close()
+
+
+def test_poisoned_net_falls_back_bitwise(dmg, trained):
+    r, e, w, hist = trained
+    ns = [NT, 2 * NT, 16, NT]
+    fs = [dev(W.training_rhs(2, n, 7000 + i)) for i, n in enumerate(ns)]
+    rng = np.random.default_rng(9)
+    for name, wp in (("negated output layer", np.concatenate([w[:3], -w[3:]])),
+                     ("random x100", 100 * rng.standard_normal(w.shape))):
+        print("poisoned:", name, flush=True)
+        Bp = dmg.BatchSolver(ns, precision=dmg.MG_FP64)
+        Bn = dmg.BatchSolver(ns, precision=dmg.MG_FP64)
+        Bn.set_coarse_net(wp.astype(np.float32))
+        up = [torch.zeros_like(f) for f in fs]
+        un = [torch.zeros_like(f) for f in fs]
+        rp = Bp.solve(up, fs, rtol=1e-10, max_cycles=40)
+        rn = Bn.solve(un, fs, rtol=1e-10, max_cycles=40)
+        used, off = Bn.net_stats()
+        print("  net cycles", used, "switched off", off)
+        assert rn[1] == rp[1] and rn[3] == rp[3]
+        assert used == [0, 0, 0, 0]
+        assert off == [1, 1, 0, 1]                 # the side-16 problem has no level below the cut
+        for a, b in zip(up, un):
+            assert torch.equal(a, b)
+        Bp.close()
+        Bn.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_learned_solve_reaches_rtol(dmg, orc, trained, prec):
+    r, e, w, hist = trained
+    ns = [NT] * 16 + [2 * NT] * 4
+    fs = [dev(W.training_rhs(2, n, 8000 + i)) for i, n in enumerate(ns)]
+    out = {}
+    for name, wt in (("plain", None), ("learned", w)):
+        B = dmg.BatchSolver(ns, precision=prec)
+        if wt is not None:
+            B.set_coarse_net(wt)
+        us = [torch.zeros_like(f) for f in fs]
+        B.solve(us, fs, rtol=1e-10, max_cycles=40)        # warm-up (graph capture)
+        us = [torch.zeros_like(f) for f in fs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, cyc, rr, sts = B.solve(us, fs, rtol=1e-10, max_cycles=40)
+        dt = time.perf_counter() - t0
+        stats = B.net_stats()
+        out[name] = (st, cyc, rr, dt, stats, us)
+        B.close()
+    (sp, cp, rp, tp, _, up), (sl, cl, rl, tl, (used, off), ul) = out["plain"], out["learned"]
+    print("prec %d: plain %d..%d cycles %.2f ms; learned %d..%d cycles %.2f ms; net used on %d of %d cycles, "
+          "switched off in %d of %d problems"
+          % (prec, min(cp), max(cp), 1e3 * tp, min(cl), max(cl), 1e3 * tl, sum(used), sum(cl), sum(off), len(ns)))
+    assert sl == dmg.MG_OK and max(rl) <= 1e-10
+    assert max(c1 - c0 for c0, c1 in zip(cp, cl)) <= 1
+    for a, b, f in zip(ul, up, fs):
+        # both within about rtol of the discrete solution
+        assert (a - b).abs().max().item() <= 1e-7 * b.abs().max().item()
+
+
+def test_coarse_export_equals_level_get(dmg):
+    n = 64
+    f = dev(W.training_rhs(2, n, 11))
+    S = dmg.Solver(2, n)
+    u = torch.zeros_like(f)
+    S.vcycle(u, f)
+    depth = 2 * 5 - 6      # aligned level 6 of a side-64 problem (finest aligned level 10)
+    lev = S.level(depth, 0)
+    from paper_math_9907190_amd import dmg as D
+    out = torch.empty((1, 17, 17), dtype=torch.float64, device="cuda")
+    D.mg_coarse_export(S.plan, 6, out.data_ptr())
+    assert torch.equal(out[0], lev)
+    S.close()
