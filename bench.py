@@ -9,8 +9,10 @@ One step = one solve from u = 0 to a relative residual of 1e-10 with the
 plain FP64 V-cycle: residual, the whole restriction hierarchy, the coarse
 levels, the Jacobi prolongation and the on-device convergence check, every
 cycle.  value = unknowns * cycles / second over the timed steps.  The same
-workload is also solved with the single-precision cycle plus FP64 refinement;
-the time to 1e-10 of each form is reported under "modes".
+workload is also solved with the single-precision cycle plus FP64 refinement
+and with the learned coarse correction (network trained first, outside the
+timed region, on 10^4 cut-level pairs from 1025^2 plain solves); the time to
+1e-10 of each form is reported under "modes".
 
 roofline: the dominant kernel's algorithmic bytes per launch (every element
 it must read or write, counted once) over its mean launch time, measured with
@@ -37,6 +39,38 @@ FAMILY_NAMES = {0: "residual", 1: "restriction", 2: "jacobi", 3: "finest jacobi 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+# HBM traffic per launch of the roofline kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (calibrated on a copy of known size), as recorded in profiles/
+# together with a hash of the kernel sources it was taken on; null when the
+# sources have changed since.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_square4097.md")
+KERNEL_SOURCES = ("dmg_b2d.hip", "dmg_rows.hpp", "dmg_common.hpp")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_math_9907190_amd", "csrc", f), "rb") as fp:
+            h.update(fp.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(family):
+    key = {3: "finest_traffic_bytes_per_launch", 0: "residual_traffic_bytes_per_launch"}.get(family)
+    if key is None or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_PROFILE) as fp:
+        for line in fp:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash() or key not in vals:
+        return None
+    return float(vals[key])
 
 
 def timed_solves(S, f, steps, warmup, rtol, family, torch):
@@ -100,6 +134,76 @@ def bench_batched(dmg, workloads, dev, torch, args):
     return res
 
 
+def train_net(dmg, L, torch, log):
+    """10^4 (r_c, e_c) pairs from 1250 plain FP64 solves of 1025^2 problems
+    (f seeds 1000..2249, 8 cycles each), then Adam on the GPU."""
+    t0 = time.perf_counter()
+    r, e = L.make_pairs(n=1024, seeds=range(1000, 2250), cycles=8, log=log)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    epochs = 150
+    net, hist = L.train(r, e, epochs=epochs, batch=256, lr=2e-3, seed=7)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    w = net.weights().copy()
+    info = {"pairs": int(r.shape[0]), "pair_seconds": round(t1 - t0, 2), "epochs": epochs, "batch": 256,
+            "train_seconds": round(t2 - t1, 3),
+            "train_us_per_step": round(1e6 * (t2 - t1) / (epochs * (r.shape[0] // 256)), 1),
+            "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]}
+    log("  net: %d pairs in %.1f s, %d epochs in %.2f s, loss %.3e -> %.3e"
+        % (info["pairs"], t1 - t0, epochs, t2 - t1, hist[0], hist[-1]))
+    net.close()
+    del r, e
+    torch.cuda.empty_cache()
+    return w, info
+
+
+def bench_learned(dmg, L, dev, torch, args, w, info):
+    """Held-out 1025^2 problems (f seeds 5000..5031) solved as one batch to
+    1e-10, plain against learned, FP64 and FP32-refined; the network's and
+    the plain sub-cycle's first-cycle cut-level residual reductions as the
+    coarse kernel measured them, and how often the judge kept the network."""
+    ns = [1024] * 32
+    fs = [torch.from_numpy(f).to(dev) for f in L.eval_problems(1024, range(5000, 5032))]
+    res = {"workload": "32 held-out 1025^2 problems (f seeds 5000..5031: smooth modes / U(-1,1) alternating), "
+                       "batched solve to %.0e; network trained on %d pairs" % (args.rtol, info["pairs"]),
+           "training": info}
+    for pname, prec in (("fp64", dmg.MG_FP64), ("fp32_refined", dmg.MG_FP32_REFINED)):
+        out = {}
+        for mode in ("plain", "learned"):
+            B = dmg.BatchSolver(ns, precision=prec, device=dev)
+            if mode == "learned":
+                B.set_coarse_net(w)
+            us = [torch.zeros_like(f) for f in fs]
+            B.solve(us, fs, rtol=args.rtol, max_cycles=60)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(args.steps):
+                us = [torch.zeros_like(f) for f in fs]
+                st, cyc, rr, sts = B.solve(us, fs, rtol=args.rtol, max_cycles=60)
+                assert st == 0 and max(rr) <= args.rtol, (st, max(rr))
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / args.steps
+            d = {"ms_to_rtol": round(1e3 * dt, 3), "cycles_min": min(cyc), "cycles_max": max(cyc),
+                 "cycles_total": sum(cyc)}
+            if mode == "learned":
+                used, off, qn, qp = B.net_stats()
+                d.update({"net_cycles": sum(used), "judge_switched_off": sum(off),
+                          "first_cycle_cut_ratio_net_median": float(sorted(qn)[len(qn) // 2]),
+                          "first_cycle_cut_ratio_plain_median": float(sorted(qp)[len(qp) // 2])})
+            out[mode] = d
+            B.close()
+            del B, us
+        out["learned_speedup"] = round(out["plain"]["ms_to_rtol"] / out["learned"]["ms_to_rtol"], 3)
+        log("  learned %s: plain %.3f ms (%d cycles), learned %.3f ms (%d cycles), net on %d cycles, judge off %d/32"
+            % (pname, out["plain"]["ms_to_rtol"], out["plain"]["cycles_total"], out["learned"]["ms_to_rtol"],
+               out["learned"]["cycles_total"], out["learned"]["net_cycles"], out["learned"]["judge_switched_off"]))
+        res[pname] = out
+    del fs
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_cube(dmg, workloads, dev, torch, args):
     """3D unit cube 257^3 (h = 1/256), f ~ U(-1,1) (seed 3), tuned 3D
     parameters; FP64 against single-precision cycles, both to 1e-10."""
@@ -138,6 +242,9 @@ def main():
     ap.add_argument("--family", type=int, default=3, help="kernel family for the roofline (3: finest Jacobi)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and 3D workloads")
+    ap.add_argument("--no-learned", action="store_true", help="skip training and the learned modes")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this solver has no multi-GPU path (a single grid is "
@@ -146,49 +253,80 @@ def main():
 
     import numpy as np
     import torch
-    from paper_math_9907190_amd import dmg, workloads
+    from paper_math_9907190_amd import dmg, learned, workloads
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.copy_probe:
+        nb = args.copy_probe << 20
+        a = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": nb, "copy_probe_bytes_written": nb, "launches": 5}), flush=True)
+        return
     n = args.n
     unknowns = (n - 1) ** 2
     log("generating f (n=%d)" % n)
     f_host = workloads.square_modes_noise(n, seed=2)
     f = torch.from_numpy(f_host).to(dev)
 
+    w_net = net_info = None
+    if not args.no_learned:
+        log("learned coarse correction: training pairs and training")
+        w_net, net_info = train_net(dmg, learned, torch, log)
+
     modes = {}
     roof = None
     main_val = None
     ms_per_step = None
-    for name, prec in (("fp64", dmg.MG_FP64), ("fp32_refined", dmg.MG_FP32_REFINED)):
+    forms = [("fp64", dmg.MG_FP64), ("fp32_refined", dmg.MG_FP32_REFINED)]
+    if w_net is not None:
+        forms += [("learned_fp64", dmg.MG_FP64), ("learned_fp32_refined", dmg.MG_FP32_REFINED)]
+    for name, prec in forms:
         S = dmg.Solver(2, n, precision=prec, p=(1.052,), device=dev)
-        fam = args.family if prec == dmg.MG_FP64 else None
+        if name.startswith("learned"):
+            S.set_coarse_net(w_net)
+        fam = args.family if name == "fp64" else None
         log("mode %s: %d warmup + %d timed solves" % (name, args.warmup, args.steps))
         dt, cycles, kern, u_last, hist = timed_solves(S, f, args.steps, args.warmup, args.rtol, fam, torch)
         ms = 1e3 * dt / args.steps
         ucs = unknowns * sum(cycles) / dt
         modes[name] = {"ms_to_rtol": round(ms, 4), "cycles": cycles[-1], "unknowns_cycles_per_s": ucs,
                        "final_rel_res": hist[-1]}
+        if name.startswith("learned"):
+            used, off, qn, qp = S.net_stats()
+            modes[name].update({"net_cycles": used, "judge_switched_off": off, "first_cycle_cut_ratio_net": qn,
+                                "first_cycle_cut_ratio_plain": qp})
         log("  %s: %.3f ms per solve, %d cycles, %.3e unknowns*cycles/s" % (name, ms, cycles[-1], ucs))
-        if prec == dmg.MG_FP64:
+        if name == "fp64":
             main_val, ms_per_step = ucs, ms
             kms, kcount, kbytes = kern
-            if kcount > 0:
-                per_launch_s = kms / kcount * 1e-3
-                achieved = kbytes / kcount / per_launch_s / 1e9
+            # a solve also launches one gated no-op iteration after the last
+            # cycle; bytes count only launches that ran (their few-us no-op
+            # time stays in kms, so the figure errs low)
+            work = sum(cycles) + (args.steps if args.family == dmg.MG_K_RESIDUAL else 0)
+            if kcount > 0 and work > 0:
+                bpl = kbytes / kcount
+                achieved = bpl * work / (kms * 1e-3) / 1e9
+                traffic = measured_traffic(args.family)
                 roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                         "kernel": FAMILY_NAMES.get(args.family, str(args.family)),
-                        "bytes_per_launch": kbytes / kcount, "us_per_launch": round(kms / kcount * 1e3, 2),
-                        "launches": kcount}
+                        "bytes_per_launch": bpl, "us_per_launch": round(kms / work * 1e3, 2),
+                        "launches": work, "launches_enqueued": kcount}
         S.close()
         del S
         torch.cuda.empty_cache()
-    modes["fp32_refined"]["speedup_vs_fp64"] = round(modes["fp64"]["ms_to_rtol"] / modes["fp32_refined"]["ms_to_rtol"], 3)
+    for k in [m for m, _ in forms[1:]]:
+        modes[k]["speedup_vs_fp64"] = round(modes["fp64"]["ms_to_rtol"] / modes[k]["ms_to_rtol"], 3)
 
     extra = {}
     if not args.no_extra:
         extra["batched512"] = bench_batched(dmg, workloads, dev, torch, args)
+        if w_net is not None:
+            extra["learned1025"] = bench_learned(dmg, learned, dev, torch, args, w_net, net_info)
         extra["cube257"] = bench_cube(dmg, workloads, dev, torch, args)
 
     cpu = None

@@ -219,10 +219,13 @@ int mg_net_destroy(mg_net *net);
  * plain sub-cycle on the first cycle) takes the plain correction instead,
  * and the network stays off for the rest of that solve. */
 int mg_set_coarse_net(mg_plan *plan, const float *w, int cut_level);
-/* Per problem, for the last solve (host arrays of nprob, nullable): cycles
- * whose coarse correction came from the network, and 1 where the judge
- * switched the network off.  Synchronises the stream. */
-int mg_net_stats(mg_plan *plan, int *net_cycles, int *fell_back);
+/* Per problem, for the last solve or cycle (host arrays of nprob,
+ * nullable): cycles whose coarse correction came from the network; 1 where
+ * the judge switched the network off; and the first cycle's cut-level
+ * residual reductions ||r_c - A_c v_c|| / ||r_c|| with the network's and
+ * with the plain sub-cycle's correction (0 where the problem has no level
+ * below the cut or no network is set).  Synchronises the stream. */
+int mg_net_stats(mg_plan *plan, int *net_cycles, int *fell_back, double *q_net, double *q_plain);
 /* Copy the restricted residual of aligned level `level` (0 .. the cut
  * level) of every problem, as left by the last cycle, into dst (device,
  * nprob x G^dim doubles, G = the level's side + 1; problems without that

@@ -699,7 +699,7 @@ __global__ void __launch_bounds__(kCoarseThreadsB) kb_coarse_net(CoarseLev<T> L,
     coarse_up(L, it, zero, cut, cut);
     double qn = cut_resid2<T>(it.r[cut], it.v[cut], m, red);
     int next = state, used = 0;
-    double theta = c->theta;
+    double theta = c->theta, qfirst = c->q_net;
     if (state == 1 || !(qn <= theta * theta * rn2)) {
         if (state == 1)
             for (int q = threadIdx.x; q < nD; q += blockDim.x) vsave[q] = it.v[cut - 1][q];
@@ -709,6 +709,7 @@ __global__ void __launch_bounds__(kCoarseThreadsB) kb_coarse_net(CoarseLev<T> L,
         double qp = cut_resid2<T>(it.r[cut], it.v[cut], m, red);
         if (state == 1) {
             theta = rn2 > 0 ? sqrt(qp / rn2) : 0.0;
+            qfirst = rn2 > 0 ? sqrt(qn / rn2) : 0.0;
             if (qn <= qp) {   // the network wins the first cycle
                 for (int q = threadIdx.x; q < nD; q += blockDim.x) it.v[cut - 1][q] = vsave[q];
                 __syncthreads();
@@ -728,6 +729,7 @@ __global__ void __launch_bounds__(kCoarseThreadsB) kb_coarse_net(CoarseLev<T> L,
     if (threadIdx.x == 0) {
         c->net = next;
         c->theta = theta;
+        c->q_net = qfirst;
         c->net_used += used;
         if (next == 0) c->net_off = 1;
     }
@@ -810,6 +812,7 @@ __global__ void kb_ctl_reset(Ctl* ctls, int nprob, int mode, int max_cycles, dou
     c->rr0 = c->prev = c->last = 0;
     c->net = net;
     c->theta = 0;
+    c->q_net = 0;
     c->net_used = 0;
     c->net_off = 0;
 }

@@ -78,6 +78,7 @@ struct Ctl {
     double rr0, prev;
     double last;     // relative residual of the latest evaluation
     double theta;    // the plain sub-cycle's cut-level residual reduction on the first cycle
+    double q_net;    // the network's cut-level residual reduction on the first cycle
     int net_used;    // cycles whose coarse correction came from the network
     int net_off;     // 1 once the judge switched the network off
     double hist[kMaxCycles + 1];

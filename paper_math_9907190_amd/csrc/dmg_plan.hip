@@ -232,12 +232,12 @@ int mg_set_coarse_net(mg_plan* P, const float* w, int cut_level)
     return MG_ERR_ARG;
 }
 
-int mg_net_stats(mg_plan* P, int* net_cycles, int* fell_back)
+int mg_net_stats(mg_plan* P, int* net_cycles, int* fell_back, double* q_net, double* q_plain)
 {
     if (!P) return MG_ERR_ARG;
     DevGuard g(P->device);
     if (!g.ok) return MG_ERR_HIP;
-    if (P->p2) return plan2_net_stats(*P->p2, net_cycles, fell_back);
+    if (P->p2) return plan2_net_stats(*P->p2, net_cycles, fell_back, q_net, q_plain);
     return MG_ERR_ARG;
 }
 

@@ -640,7 +640,7 @@ int plan2_set_net(Plan2& P, const float* w, int cut_level)
     return MG_OK;
 }
 
-int plan2_net_stats(Plan2& P, int* net_cycles, int* fell_back)
+int plan2_net_stats(Plan2& P, int* net_cycles, int* fell_back, double* q_net, double* q_plain)
 {
     Ctl* ctls = reinterpret_cast<Ctl*>(P.ws + P.off_ctl);
     if (hipMemcpy2DAsync(P.hres, kCtlHead, ctls, sizeof(Ctl), kCtlHead, P.nprob, hipMemcpyDeviceToHost, P.stream) !=
@@ -651,6 +651,8 @@ int plan2_net_stats(Plan2& P, int* net_cycles, int* fell_back)
         const Ctl* c = reinterpret_cast<const Ctl*>(P.hres + kCtlHead * (size_t)i);
         if (net_cycles) net_cycles[i] = c->net_used;
         if (fell_back) fell_back[i] = c->net_off;
+        if (q_net) q_net[i] = c->q_net;
+        if (q_plain) q_plain[i] = c->theta;
     }
     return MG_OK;
 }

@@ -50,7 +50,7 @@ int plan2_level_get(Plan2& P, int depth, int which, double* dst);
 int plan2_tune_load(Plan2& P);
 int plan2_autotune(Plan2& P);
 int plan2_set_net(Plan2& P, const float* w, int cut_level);
-int plan2_net_stats(Plan2& P, int* net_cycles, int* fell_back);
+int plan2_net_stats(Plan2& P, int* net_cycles, int* fell_back, double* q_net, double* q_plain);
 int plan2_coarse_export(Plan2& P, int level, double* dst);
 
 }  // namespace dmg

@@ -53,7 +53,7 @@ _lib.mg_net_loss_grad.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _fp
 _lib.mg_net_train.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_float, _ull, _dp]
 _lib.mg_net_destroy.argtypes = [_vp]
 _lib.mg_set_coarse_net.argtypes = [_vp, _fp, ctypes.c_int]
-_lib.mg_net_stats.argtypes = [_vp, _ip, _ip]
+_lib.mg_net_stats.argtypes = [_vp, _ip, _ip, _dp, _dp]
 _lib.mg_coarse_export.argtypes = [_vp, ctypes.c_int, _vp]
 _lib.mg_strerror.argtypes = [ctypes.c_int]
 _lib.mg_strerror.restype = ctypes.c_char_p
@@ -274,10 +274,13 @@ def mg_set_coarse_net(plan, dim, w, cut_level=MG_NET_CUT):
 
 
 def mg_net_stats(plan, nprob):
+    """(net cycles, switched off, first-cycle cut ratio with the network, with the plain sub-cycle)"""
     used = (ctypes.c_int * nprob)()
     off = (ctypes.c_int * nprob)()
-    _check(_lib.mg_net_stats(plan, used, off), "mg_net_stats")
-    return list(used), list(off)
+    qn = (ctypes.c_double * nprob)()
+    qp = (ctypes.c_double * nprob)()
+    _check(_lib.mg_net_stats(plan, used, off, qn, qp), "mg_net_stats")
+    return list(used), list(off), list(qn), list(qp)
 
 
 def mg_coarse_export(plan, level, dst_ptr):
@@ -342,84 +345,19 @@ class Solver:
         mg_autotune(self.plan)
 
     def set_coarse_net(self, w):
-        """Weights (host array, mg_net_weight_count(2) floats) of the learned
-        coarse correction, or None for the plain cycle."""
-        mg_set_coarse_net(self.plan, 2, w)
+        """Learned coarse correction (2D): weights, or None for the plain cycle."""
+        mg_set_coarse_net(self.plan, self.dim, w)
 
     def net_stats(self):
-        """(cycles that used the network, 1 where the judge switched it off) per problem."""
-        return mg_net_stats(self.plan, len(self.ns))
-
-    def coarse_export(self, level=MG_NET_CUT):
-        """Restricted residual of aligned level `level` of every problem after the last cycle."""
-        side = 1 << (1 + (level + 1) // 2)
-        out = torch.empty((len(self.ns), side + 1, side + 1), dtype=torch.float64, device=self.device)
-        mg_coarse_export(self.plan, level, out.data_ptr())
-        return out
+        """(network cycles, judge switched it off, first-cycle cut ratio with the
+        network, with the plain sub-cycle) of the last solve."""
+        used, off, qn, qp = mg_net_stats(self.plan, 1)
+        return used[0], off[0], qn[0], qp[0]
 
     def close(self):
         if getattr(self, "plan", None) is not None:
             mg_destroy(self.plan)
             self.plan = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
-
-
-class Net:
-    """Trainer of the learned coarse correction: master weights, Adam state
-    and gradient buffers for up to max_batch samples in a torch workspace."""
-
-    def __init__(self, dim=2, max_batch=256, seed=None, device=None, stream=None):
-        self.dim, self.max_batch = dim, max_batch
-        self.G = NET_G[dim]
-        self.nw = mg_net_weight_count(dim)
-        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        self.ws_bytes = mg_net_workspace_bytes(dim, max_batch)
-        with torch.cuda.device(self.device):
-            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-            self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
-            ptr = (self.ws.data_ptr() + 255) // 256 * 256
-            self.net = mg_net_create(dim, max_batch, ptr, self.ws_bytes, self.stream.cuda_stream)
-        if seed is not None:
-            mg_net_init(self.net, seed)
-
-    def _grid(self, t, name):
-        shape = (self.G,) * self.dim
-        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous() and tuple(t.shape[1:]) == shape
-                and t.device == self.device):
-            raise ValueError("%s must be a contiguous float64 tensor of shape (B,) + %s on %s" % (name, shape, self.device))
-
-    def set_weights(self, w):
-        mg_net_set_weights(self.net, self.dim, w)
-
-    def weights(self):
-        return mg_net_get_weights(self.net, self.dim).reshape(4, 3 ** self.dim, 16, 16)
-
-    def forward(self, x, normalize=True):
-        self._grid(x, "x")
-        out = torch.empty_like(x)
-        mg_net_forward(self.net, x.data_ptr(), out.data_ptr(), x.shape[0], normalize)
-        return out
-
-    def loss_grad(self, x, target, normalize=False):
-        self._grid(x, "x")
-        self._grid(target, "target")
-        loss, g = mg_net_loss_grad(self.net, self.dim, x.data_ptr(), target.data_ptr(), x.shape[0], normalize)
-        return loss, g.reshape(4, 3 ** self.dim, 16, 16)
-
-    def train(self, r, e, epochs, batch=256, lr=1e-3, seed=0):
-        self._grid(r, "r")
-        self._grid(e, "e")
-        return mg_net_train(self.net, r.data_ptr(), e.data_ptr(), r.shape[0], epochs, batch, lr, seed)
-
-    def close(self):
-        if getattr(self, "net", None) is not None:
-            mg_net_destroy(self.net)
-            self.net = None
 
     def __del__(self):
         try:
@@ -470,7 +408,9 @@ class BatchSolver:
         mg_set_coarse_net(self.plan, 2, w)
 
     def net_stats(self):
-        """(cycles that used the network, 1 where the judge switched it off) per problem."""
+        """Per problem: cycles that used the network, 1 where the judge switched
+        it off, and the first cycle's cut-level residual reduction with the
+        network and with the plain sub-cycle."""
         return mg_net_stats(self.plan, len(self.ns))
 
     def coarse_export(self, level=MG_NET_CUT):

@@ -88,7 +88,7 @@ def test_net_sizes_and_argument_errors(D):
     assert D._lib.mg_net_destroy(None) == D.MG_OK
     # a plan is required; checked before any GPU call
     assert D._lib.mg_set_coarse_net(None, None, 6) == D.MG_ERR_ARG
-    assert D._lib.mg_net_stats(None, None, None) == D.MG_ERR_ARG
+    assert D._lib.mg_net_stats(None, None, None, None, None) == D.MG_ERR_ARG
     assert D._lib.mg_coarse_export(None, 6, None) == D.MG_ERR_ARG
 
 

@@ -272,7 +272,7 @@ def test_judge_decisions_match_prediction(dmg, orc, trained):
     B.set_coarse_net(w)
     us = [dev(np.zeros_like(f)) for f in fs]
     B.vcycle(us, [dev(f) for f in fs])         # one first (judged) cycle
-    used, off = B.net_stats()
+    used, off, qn_gpu, qp_gpu = B.net_stats()
     r6 = B.coarse_export(6)
     net = dmg.Net(dim=2, max_batch=8)
     net.set_weights(w)
@@ -282,7 +282,11 @@ def test_judge_decisions_match_prediction(dmg, orc, trained):
     for i in range(len(ns)):
         qn = cut_ratio(r6[i], jacobi_cut(r6[i], y[i]))
         qp = cut_ratio(r6[i], plain_cut(r6[i]))
-        print("  problem %d: net %.3e plain %.3e -> used %d off %d" % (i, qn, qp, used[i], off[i]))
+        print("  problem %d: net %.3e plain %.3e (kernel: %.3e %.3e) -> used %d off %d"
+              % (i, qn, qp, qn_gpu[i], qp_gpu[i], used[i], off[i]))
+        # the kernel's own measurement of both reductions (bf16 network inside)
+        assert abs(qp_gpu[i] - qp) <= 1e-9 * qp
+        assert abs(qn_gpu[i] - qn) <= 2e-2 * qn
         if abs(qn - qp) > 0.02 * qp:
             assert used[i] == (1 if qn <= qp else 0) and off[i] == (0 if qn <= qp else 1), i
             checked += 1
@@ -306,7 +310,7 @@ def test_poisoned_net_falls_back_bitwise(dmg, trained):
         un = [torch.zeros_like(f) for f in fs]
         rp = Bp.solve(up, fs, rtol=1e-10, max_cycles=40)
         rn = Bn.solve(un, fs, rtol=1e-10, max_cycles=40)
-        used, off = Bn.net_stats()
+        used, off, _, _ = Bn.net_stats()
         print("  net cycles", used, "switched off", off)
         assert rn[1] == rp[1] and rn[3] == rp[3]
         assert used == [0, 0, 0, 0]
@@ -334,7 +338,7 @@ def test_learned_solve_reaches_rtol(dmg, orc, trained, prec):
         t0 = time.perf_counter()
         st, cyc, rr, sts = B.solve(us, fs, rtol=1e-10, max_cycles=40)
         dt = time.perf_counter() - t0
-        stats = B.net_stats()
+        stats = B.net_stats()[:2]
         out[name] = (st, cyc, rr, dt, stats, us)
         B.close()
     (sp, cp, rp, tp, _, up), (sl, cl, rl, tl, (used, off), ul) = out["plain"], out["learned"]
