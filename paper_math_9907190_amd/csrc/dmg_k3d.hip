@@ -142,6 +142,268 @@ __global__ void __launch_bounds__(256) k3_jac_finest(int n, T cc, const T* __res
     }
 }
 
+// ------------------------------------------------------- plane-marching Jacobi
+// Large levels: a workgroup owns an (x, y) tile and marches a chunk of z
+// planes.  For each plane it computes the first-half-sweep values of the
+// tile plus a one-point halo once, into a ring of three LDS planes; the
+// second-half-sweep points of the plane behind then read the values they
+// need from LDS, summed in the same order as the per-point functions, so the
+// results equal those of the one-thread-per-point kernels bit for bit.
+
+constexpr int kPlTX = 64, kPlTY = 8, kPlThreads = 256;
+constexpr int kPlW = kPlTX + 2, kPlH = kPlTY + 2;   // tile plus a one-point halo
+
+// Inputs of one first-half-sweep value, loaded one plane ahead of its use.
+template <typename T>
+struct PlIn {
+    T r, n0, n1, n2, n3, n4, n5;
+    int pos;   // LDS position; -1: no point
+    bool ok;   // interior point (else the value is 0)
+};
+
+// ---- green: F points (a+b+c odd), Eq. (Egprolg)
+template <typename T>
+__device__ inline PlIn<T> green_fload(const T* __restrict__ rG, const T* __restrict__ vR, int m, int x0, int y0,
+                                      int c, int i)
+{
+    PlIn<T> q;
+    q.pos = -1;
+    q.ok = false;
+    q.r = q.n0 = q.n1 = q.n2 = q.n3 = q.n4 = q.n5 = T(0);
+    constexpr int NR = kPlW / 2;   // F points per tile row
+    if (i >= kPlH * NR) return q;
+    const int ly = i / NR, j = i % NR;
+    const int b = y0 - 1 + ly, a0 = x0 - 1;
+    const int a = a0 + ((a0 + b + c + 1) & 1) + 2 * j;
+    q.pos = ly * kPlW + (a - a0);
+    if (a <= 0 || a >= m || b <= 0 || b >= m || c <= 0 || c >= m) return q;
+    q.ok = true;
+    q.r = rG[idxG(m, a, b, c)];
+    q.n0 = vR[idxR(m, a + 1, b, c)];
+    q.n1 = vR[idxR(m, a - 1, b, c)];
+    q.n2 = vR[idxR(m, a, b + 1, c)];
+    q.n3 = vR[idxR(m, a, b - 1, c)];
+    q.n4 = vR[idxR(m, a, b, c + 1)];
+    q.n5 = vR[idxR(m, a, b, c - 1)];
+    return q;
+}
+
+// same arithmetic and order as jac3_greenF
+template <typename T>
+__device__ inline T green_fcomp(const PlIn<T>& q, T cc)
+{
+    if (!q.ok) return T(0);
+    T s = q.n0 + q.n1 + q.n2 + q.n3 + q.n4 + q.n5;
+    return (-cc * q.r + s) * (T(1) / T(6));
+}
+
+// Green grid of side m, Eqs. (Egprolg), (Egprolr): F points from the red
+// grid vR, then C points (a+b+c even) from the six new F values.  FINEST
+// adds the correction to u instead of storing it.  Each thread owns two
+// F-value slots of the extended tile plane and the x pair (2t, 2t+1) of
+// one output row.
+template <typename T, bool FINEST>
+__global__ void __launch_bounds__(kPlThreads) k3_green_planes(int m, T cc, const T* __restrict__ rG,
+                                                               const T* __restrict__ vR, T* __restrict__ vG,
+                                                               double* __restrict__ u, int ntx, int nty, int zc,
+                                                               const Ctl* ctl)
+{
+    DMG_GATE(ctl);
+    constexpr int W = kPlW;
+    __shared__ T F[3][kPlH * kPlW];
+    const int bid = blockIdx.x;
+    const int tx = bid % ntx, ty = (bid / ntx) % nty, tz = bid / (ntx * nty);
+    const int x0 = 1 + tx * kPlTX, y0 = 1 + ty * kPlTY, z0 = 1 + tz * zc;
+    const int z1 = min(z0 + zc, m);   // output planes [z0, z1)
+    const int tid = threadIdx.x;
+    const int oly = tid / (kPlTX / 2), opr = tid % (kPlTX / 2);
+    const int ob = y0 + oly, oa = x0 + 2 * opr;
+    const bool orow = ob < m;
+    // prologue: inputs of plane z0 - 1
+    PlIn<T> n0 = green_fload(rG, vR, m, x0, y0, z0 - 1, tid);
+    PlIn<T> n1 = green_fload(rG, vR, m, x0, y0, z0 - 1, tid + kPlThreads);
+    double un0 = 0, un1 = 0;
+    T rn = T(0);
+    for (int c = z0 - 1; c <= z1; c++) {
+        const PlIn<T> f0 = n0, f1 = n1;
+        const double uc0 = un0, uc1 = un1;
+        const T rc = rn;
+        if (c + 1 <= z1) {   // next plane's F inputs
+            n0 = green_fload(rG, vR, m, x0, y0, c + 1, tid);
+            n1 = green_fload(rG, vR, m, x0, y0, c + 1, tid + kPlThreads);
+        }
+        if (c >= z0 && c < z1 && orow) {   // this plane's output inputs, used next iteration
+            const int aC = oa + ((oa + ob + c) & 1);   // the C point of the pair
+            if (aC < m) rn = rG[idxG(m, aC, ob, c)];
+            if (FINEST) {
+                if (oa < m) un0 = u[idxG(m, oa, ob, c)];
+                if (oa + 1 < m) un1 = u[idxG(m, oa + 1, ob, c)];
+            }
+        }
+        T* Fp = F[c % 3];
+        if (f0.pos >= 0) Fp[f0.pos] = green_fcomp(f0, cc);
+        if (f1.pos >= 0) Fp[f1.pos] = green_fcomp(f1, cc);
+        __syncthreads();
+        const int co = c - 1;
+        if (co >= z0 && orow) {
+            const T* Fm = F[(co + 2) % 3];   // plane co - 1
+            const T* F0 = F[co % 3];
+            const T* Fq = F[c % 3];          // plane co + 1
+            for (int k = 0; k < 2; k++) {
+                const int a = oa + k;
+                if (a >= m) break;
+                const int l = (oly + 1) * W + (a - x0 + 1);
+                T v;
+                if ((a + ob + co) & 1) {
+                    v = F0[l];
+                } else {
+                    T s = F0[l + 1] + F0[l - 1] + F0[l + W] + F0[l - W] + Fq[l] + Fm[l];
+                    v = (-cc * rc + s) * (T(1) / T(6));
+                }
+                size_t q = idxG(m, a, ob, co);
+                if (FINEST) u[q] = (k ? uc1 : uc0) + (double)v;
+                else vG[q] = v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---- red: face centres (two odd indices), Eq. (Erprolr) and its cyclic
+// permutations; corners (all even), Eq. (Erprolm).  Tiles are in R-layout
+// slots: slot s of row (b, c) is the point a = 2s + ((b+c)&1).
+template <typename T>
+__device__ inline PlIn<T> red_fload(const T* __restrict__ rR, const T* __restrict__ vE, const T* __restrict__ vO,
+                                    int m, int s0, int y0, int c, int p)
+{
+    PlIn<T> q;
+    q.pos = -1;
+    q.ok = false;
+    q.r = q.n0 = q.n1 = q.n2 = q.n3 = q.n4 = q.n5 = T(0);
+    if (p >= kPlH * kPlW) return q;
+    const int b = y0 - 1 + p / kPlW, sl = s0 - 1 + p % kPlW;
+    const int a = 2 * sl + ((b + c) & 1);
+    if ((a & 1) + (b & 1) + (c & 1) != 2) return q;   // corners are not first-half-sweep points
+    q.pos = p;
+    if (a < 1 || a >= m || b < 1 || b >= m || c < 1 || c >= m) return q;
+    q.ok = true;
+    q.r = rR[idxR(m, a, b, c)];
+    if (!(c & 1)) {
+        q.n0 = vO[idxMO(m, a, b, c + 1)];
+        q.n1 = vO[idxMO(m, a, b, c - 1)];
+        q.n2 = vE[idxME(m, a + 1, b + 1, c)];
+        q.n3 = vE[idxME(m, a + 1, b - 1, c)];
+        q.n4 = vE[idxME(m, a - 1, b - 1, c)];
+        q.n5 = vE[idxME(m, a - 1, b + 1, c)];
+    } else if (!(a & 1)) {
+        q.n0 = vO[idxMO(m, a + 1, b, c)];
+        q.n1 = vO[idxMO(m, a - 1, b, c)];
+        q.n2 = vE[idxME(m, a, b + 1, c + 1)];
+        q.n3 = vE[idxME(m, a, b + 1, c - 1)];
+        q.n4 = vE[idxME(m, a, b - 1, c - 1)];
+        q.n5 = vE[idxME(m, a, b - 1, c + 1)];
+    } else {
+        q.n0 = vO[idxMO(m, a, b + 1, c)];
+        q.n1 = vO[idxMO(m, a, b - 1, c)];
+        q.n2 = vE[idxME(m, a + 1, b, c + 1)];
+        q.n3 = vE[idxME(m, a - 1, b, c + 1)];
+        q.n4 = vE[idxME(m, a - 1, b, c - 1)];
+        q.n5 = vE[idxME(m, a + 1, b, c - 1)];
+    }
+    return q;
+}
+
+// same arithmetic and order as jac3_redF
+template <typename T>
+__device__ inline T red_fcomp(const PlIn<T>& q, T cc)
+{
+    if (!q.ok) return T(0);
+    T s = 2 * (q.n0 + q.n1) + q.n2 + q.n3 + q.n4 + q.n5;
+    return (-cc * q.r + s) * T(0.125);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kPlThreads) k3_red_planes(int m, T c1, T c2, const T* __restrict__ rR,
+                                                             const T* __restrict__ vE, const T* __restrict__ vO,
+                                                             T* __restrict__ vR, int ntx, int nty, int zc,
+                                                             const Ctl* ctl)
+{
+    DMG_GATE(ctl);
+    constexpr int W = kPlW, NP = (kPlH * kPlW + kPlThreads - 1) / kPlThreads;   // F slots per thread
+    constexpr int NO = kPlTY * kPlTX / kPlThreads;                              // outputs per thread
+    __shared__ T F[3][kPlH * kPlW];
+    const int bid = blockIdx.x;
+    const int tx = bid % ntx, ty = (bid / ntx) % nty, tz = bid / (ntx * nty);
+    const int s0 = tx * kPlTX, y0 = 1 + ty * kPlTY, z0 = 1 + tz * zc;
+    const int z1 = min(z0 + zc, m);
+    const int tid = threadIdx.x;
+    PlIn<T> nx[NP];
+#pragma unroll
+    for (int j = 0; j < NP; j++) nx[j] = red_fload(rR, vE, vO, m, s0, y0, z0 - 1, tid + j * kPlThreads);
+    T rn[NO];
+#pragma unroll
+    for (int k = 0; k < NO; k++) rn[k] = T(0);
+    for (int c = z0 - 1; c <= z1; c++) {
+        PlIn<T> cur[NP];
+        T rc[NO];
+#pragma unroll
+        for (int j = 0; j < NP; j++) cur[j] = nx[j];
+#pragma unroll
+        for (int k = 0; k < NO; k++) rc[k] = rn[k];
+        if (c + 1 <= z1) {
+#pragma unroll
+            for (int j = 0; j < NP; j++) nx[j] = red_fload(rR, vE, vO, m, s0, y0, c + 1, tid + j * kPlThreads);
+        }
+        if (c >= z0 && c < z1) {   // corners of this plane need rR next iteration
+#pragma unroll
+            for (int k = 0; k < NO; k++) {
+                const int e = tid + k * kPlThreads;
+                const int b = y0 + e / kPlTX, sl = s0 + e % kPlTX;
+                const int a = 2 * sl + ((b + c) & 1);
+                if (b < m && a >= 1 && a < m && ((a | b | c) & 1) == 0) rn[k] = rR[idxR(m, a, b, c)];
+            }
+        }
+        T* Fp = F[c % 3];
+#pragma unroll
+        for (int j = 0; j < NP; j++)
+            if (cur[j].pos >= 0) Fp[cur[j].pos] = red_fcomp(cur[j], c1);
+        __syncthreads();
+        const int co = c - 1;
+        if (co >= z0) {
+            const T* Fm = F[(co + 2) % 3];
+            const T* F0 = F[co % 3];
+            const T* Fq = F[c % 3];
+#pragma unroll
+            for (int k = 0; k < NO; k++) {
+                const int e = tid + k * kPlThreads;
+                const int ly = e / kPlTX, ls = e % kPlTX;
+                const int b = y0 + ly, sl = s0 + ls;
+                const int a = 2 * sl + ((b + co) & 1);
+                if (b >= m || a < 1 || a >= m) continue;
+                const int l = (ly + 1) * W + (ls + 1);
+                const int odd = (a & 1) + (b & 1) + (co & 1);
+                T v;
+                if (odd == 2) {
+                    v = F0[l];
+                } else {
+                    // corner (no red point has one or three odd indices): slots a/2 (= l) and a/2 - 1 (= l - 1);
+                    // rows b +- 1 are l +- W; the twelve faces in the order of Eq. (Erprolm) as jac3_redC sums them
+                    T s = F0[l + W] + F0[l - W] + F0[l - W - 1] + F0[l + W - 1]
+                        + Fq[l] + Fm[l] + Fm[l - 1] + Fq[l - 1]
+                        + Fq[l + W] + Fm[l + W] + Fm[l - W] + Fq[l - W];
+                    v = (-c2 * rc[k] + s) * (T(1) / T(12));
+                }
+                vR[idxR(m, a, b, co)] = v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+constexpr int kPlMinSide = 128;   // smaller levels: one thread per point
+
+inline int pl_zchunk(int m) { return m >= 256 ? 16 : 8; }
+
 template <typename T>
 void launch_jac3(const Lev3<T>& L, const Lev3<T>& Cr, T* zero, const Ctl* ctl, hipStream_t s)
 {
@@ -151,17 +413,38 @@ void launch_jac3(const Lev3<T>& L, const Lev3<T>& Cr, T* zero, const Ctl* ctl, h
         dim3 g((m / 2 + 255) / 256, m / 2, m / 2);
         hipLaunchKernelGGL(k3_jac_mag<T>, g, dim3(256), 0, s, m, L.c, L.r, L.r2, vc, L.v, L.v2, ctl);
     } else if (L.kind == 1) {
-        dim3 g((m / 2 + 255) / 256, m / 2, m / 2);
-        hipLaunchKernelGGL(k3_jac_red<T>, g, dim3(256), 0, s, m, L.c, L.c2, L.r, Cr.v, Cr.v2, L.v, ctl);
+        if (m >= kPlMinSide) {
+            int ntx = (m / 2 + kPlTX - 1) / kPlTX, nty = (m - 1 + kPlTY - 1) / kPlTY, zc = pl_zchunk(m);
+            int ntz = (m - 1 + zc - 1) / zc;
+            hipLaunchKernelGGL(k3_red_planes<T>, dim3(ntx * nty * ntz), dim3(kPlThreads), 0, s, m, L.c, L.c2, L.r,
+                               Cr.v, Cr.v2, L.v, ntx, nty, zc, ctl);
+        } else {
+            dim3 g((m / 2 + 255) / 256, m / 2, m / 2);
+            hipLaunchKernelGGL(k3_jac_red<T>, g, dim3(256), 0, s, m, L.c, L.c2, L.r, Cr.v, Cr.v2, L.v, ctl);
+        }
     } else {
-        dim3 g((m / 2 + 1 + 255) / 256, m - 1, m - 1);
-        hipLaunchKernelGGL(k3_jac_green<T>, g, dim3(256), 0, s, m, L.c, L.r, vc, L.v, ctl);
+        if (m >= kPlMinSide) {
+            int ntx = (m - 1 + kPlTX - 1) / kPlTX, nty = (m - 1 + kPlTY - 1) / kPlTY, zc = pl_zchunk(m);
+            int ntz = (m - 1 + zc - 1) / zc;
+            hipLaunchKernelGGL((k3_green_planes<T, false>), dim3(ntx * nty * ntz), dim3(kPlThreads), 0, s, m, L.c, L.r,
+                               vc, L.v, nullptr, ntx, nty, zc, ctl);
+        } else {
+            dim3 g((m / 2 + 1 + 255) / 256, m - 1, m - 1);
+            hipLaunchKernelGGL(k3_jac_green<T>, g, dim3(256), 0, s, m, L.c, L.r, vc, L.v, ctl);
+        }
     }
 }
 
 template <typename T>
 void launch_jac3_finest(int n, T c, const T* r0, const T* vR, double* u, const Ctl* ctl, hipStream_t s)
 {
+    if (n >= kPlMinSide) {
+        int ntx = (n - 1 + kPlTX - 1) / kPlTX, nty = (n - 1 + kPlTY - 1) / kPlTY, zc = pl_zchunk(n);
+        int ntz = (n - 1 + zc - 1) / zc;
+        hipLaunchKernelGGL((k3_green_planes<T, true>), dim3(ntx * nty * ntz), dim3(kPlThreads), 0, s, n, c, r0, vR,
+                           nullptr, u, ntx, nty, zc, ctl);
+        return;
+    }
     dim3 g((n / 2 + 1 + 255) / 256, n - 1, n - 1);
     hipLaunchKernelGGL(k3_jac_finest<T>, g, dim3(256), 0, s, n, c, r0, vR, u, ctl);
 }
