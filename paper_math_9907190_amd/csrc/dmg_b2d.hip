@@ -516,21 +516,35 @@ __global__ void __launch_bounds__(256) kb_jac_axis(int m, T cc, const Item2<T>* 
 // ------------------------------------------------------------ coarse levels
 // Aligned levels top .. 0 of one problem per workgroup: restriction down to
 // the 3x3 grid, its Jacobi from a zero correction, Jacobi back up to top.
+// The levels stay in global memory (L2-resident): their stencils issue
+// about twenty reads per point, more than the fifteen LDS operations a wave
+// can keep in flight, and staging them in LDS measured slower (33 us against
+// 22 us per cycle on MI355X).
 template <typename T>
 struct CoarseLev {
     LevInfo<T> l[kCoarseLevels];
 };
 constexpr int kCoarseThreadsB = 1024;
 
-// restriction into lam for lam = hi-1 down to lo
+// the level arrays of one problem
 template <typename T>
-__device__ void coarse_down(const CoarseLev<T>& L, const Coarse2B<T>& it, int hi, int lo)
+struct GLevs {
+    const Coarse2B<T>& it;
+    const T* z;
+    __device__ T* r(int l) const { return it.r[l]; }
+    __device__ T* v(int l) const { return it.v[l]; }
+    __device__ const T* zero() const { return z; }
+};
+
+// restriction into lam for lam = hi-1 down to lo
+template <typename T, typename LV>
+__device__ void coarse_down(const CoarseLev<T>& L, const LV& it, int hi, int lo)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int lam = hi - 1; lam >= lo; lam--) {
         const LevInfo<T>& Fi = L.l[lam + 1];
-        const T* rf = it.r[lam + 1];
-        T* rc = it.r[lam];
+        const T* rf = it.r(lam + 1);
+        T* rc = it.r(lam);
         int m = Fi.m;
         if (!Fi.diag) {  // axis -> diagonal, same side
             int w = m / 2 + 1;
@@ -551,15 +565,15 @@ __device__ void coarse_down(const CoarseLev<T>& L, const Coarse2B<T>& it, int hi
 }
 
 // Jacobi at lam = lo .. hi (lam = 0 from a zero correction)
-template <typename T>
-__device__ void coarse_up(const CoarseLev<T>& L, const Coarse2B<T>& it, const T* zero, int lo, int hi)
+template <typename T, typename LV>
+__device__ void coarse_up(const CoarseLev<T>& L, const LV& it, int lo, int hi)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     for (int lam = lo; lam <= hi; lam++) {
         const LevInfo<T>& Li = L.l[lam];
-        const T* vc = lam == 0 ? zero : it.v[lam - 1];
-        const T* r = it.r[lam];
-        T* v = it.v[lam];
+        const T* vc = lam == 0 ? it.zero() : it.v(lam - 1);
+        const T* r = it.r(lam);
+        T* v = it.v(lam);
         int m = Li.m;
         T cc = Li.c;
         if (Li.diag) {
@@ -588,8 +602,9 @@ __global__ void __launch_bounds__(kCoarseThreadsB) kb_coarse(CoarseLev<T> L, con
 {
     const Coarse2B<T>& it = items[blockIdx.x];
     ITEM_GATE(ctls, it.prob);
-    coarse_down(L, it, it.top, 0);
-    coarse_up(L, it, zero, 0, it.top);
+    const GLevs<T> S{it, zero};
+    coarse_down(L, S, it.top, 0);
+    coarse_up(L, S, 0, it.top);
 }
 
 // ------------------------------------------------- learned coarse correction
@@ -681,9 +696,10 @@ __global__ void __launch_bounds__(kCoarseThreadsB) kb_coarse_net(CoarseLev<T> L,
     Ctl* c = &ctls[it.prob];
     const int top = it.top, cut = kNetCut;
     const int state = top >= cut ? c->net : 0;
+    const GLevs<T> S{it, zero};
     if (state == 0) {
-        coarse_down(L, it, top, 0);
-        coarse_up(L, it, zero, 0, top);
+        coarse_down(L, S, top, 0);
+        coarse_up(L, S, 0, top);
         return;
     }
     __shared__ __align__(16) bf16_t A[N::ACT];
@@ -694,26 +710,26 @@ __global__ void __launch_bounds__(kCoarseThreadsB) kb_coarse_net(CoarseLev<T> L,
     __shared__ T vsave[(N::G) * (N::G / 2 + 1)];
     const int m = L.l[cut].m;
     const int nD = (int)sizeD(m);
-    coarse_down(L, it, top, cut);
-    double rn2 = net_cut_2d<T>(it.r[cut], it.v[cut - 1], wf, A, B, out0, linq, red);
-    coarse_up(L, it, zero, cut, cut);
-    double qn = cut_resid2<T>(it.r[cut], it.v[cut], m, red);
+    coarse_down(L, S, top, cut);
+    double rn2 = net_cut_2d<T>(S.r(cut), S.v(cut - 1), wf, A, B, out0, linq, red);
+    coarse_up(L, S, cut, cut);
+    double qn = cut_resid2<T>(S.r(cut), S.v(cut), m, red);
     int next = state, used = 0;
     double theta = c->theta, qfirst = c->q_net;
     if (state == 1 || !(qn <= theta * theta * rn2)) {
         if (state == 1)
-            for (int q = threadIdx.x; q < nD; q += blockDim.x) vsave[q] = it.v[cut - 1][q];
+            for (int q = threadIdx.x; q < nD; q += blockDim.x) vsave[q] = S.v(cut - 1)[q];
         __syncthreads();
-        coarse_down(L, it, cut, 0);
-        coarse_up(L, it, zero, 0, cut);
-        double qp = cut_resid2<T>(it.r[cut], it.v[cut], m, red);
+        coarse_down(L, S, cut, 0);
+        coarse_up(L, S, 0, cut);
+        double qp = cut_resid2<T>(S.r(cut), S.v(cut), m, red);
         if (state == 1) {
             theta = rn2 > 0 ? sqrt(qp / rn2) : 0.0;
             qfirst = rn2 > 0 ? sqrt(qn / rn2) : 0.0;
             if (qn <= qp) {   // the network wins the first cycle
-                for (int q = threadIdx.x; q < nD; q += blockDim.x) it.v[cut - 1][q] = vsave[q];
+                for (int q = threadIdx.x; q < nD; q += blockDim.x) S.v(cut - 1)[q] = vsave[q];
                 __syncthreads();
-                coarse_up(L, it, zero, cut, cut);
+                coarse_up(L, S, cut, cut);
                 next = 2;
                 used = 1;
             } else {
@@ -725,7 +741,7 @@ __global__ void __launch_bounds__(kCoarseThreadsB) kb_coarse_net(CoarseLev<T> L,
     } else {
         used = 1;
     }
-    coarse_up(L, it, zero, cut + 1, top);
+    coarse_up(L, S, cut + 1, top);
     if (threadIdx.x == 0) {
         c->net = next;
         c->theta = theta;

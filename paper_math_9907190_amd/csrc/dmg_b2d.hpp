@@ -33,7 +33,7 @@ struct Fin2 {
 };
 
 // one problem's coarse levels (aligned levels 0 .. top, side <= the coarse limit)
-constexpr int kCoarseLevels = 10;
+constexpr int kCoarseLevels = 12;
 template <typename T>
 struct Coarse2B {
     T* r[kCoarseLevels];

@@ -152,6 +152,7 @@ __global__ void __launch_bounds__(256) k3_jac_finest(int n, T cc, const T* __res
 
 constexpr int kPlTX = 64, kPlTY = 8, kPlThreads = 256;
 constexpr int kPlW = kPlTX + 2, kPlH = kPlTY + 2;   // tile plus a one-point halo
+constexpr int kRdTX = 32, kRdW = kRdTX + 2;        // red tiles: 32 slots (64 x positions) wide
 
 // Inputs of one first-half-sweep value, loaded one plane ahead of its use.
 template <typename T>
@@ -280,8 +281,8 @@ __device__ inline PlIn<T> red_fload(const T* __restrict__ rR, const T* __restric
     q.pos = -1;
     q.ok = false;
     q.r = q.n0 = q.n1 = q.n2 = q.n3 = q.n4 = q.n5 = T(0);
-    if (p >= kPlH * kPlW) return q;
-    const int b = y0 - 1 + p / kPlW, sl = s0 - 1 + p % kPlW;
+    if (p >= kPlH * kRdW) return q;
+    const int b = y0 - 1 + p / kRdW, sl = s0 - 1 + p % kRdW;
     const int a = 2 * sl + ((b + c) & 1);
     if ((a & 1) + (b & 1) + (c & 1) != 2) return q;   // corners are not first-half-sweep points
     q.pos = p;
@@ -329,12 +330,12 @@ __global__ void __launch_bounds__(kPlThreads) k3_red_planes(int m, T c1, T c2, c
                                                              const Ctl* ctl)
 {
     DMG_GATE(ctl);
-    constexpr int W = kPlW, NP = (kPlH * kPlW + kPlThreads - 1) / kPlThreads;   // F slots per thread
-    constexpr int NO = kPlTY * kPlTX / kPlThreads;                              // outputs per thread
-    __shared__ T F[3][kPlH * kPlW];
+    constexpr int W = kRdW, NP = (kPlH * kRdW + kPlThreads - 1) / kPlThreads;   // F slots per thread
+    constexpr int NO = kPlTY * kRdTX / kPlThreads;                              // outputs per thread
+    __shared__ T F[3][kPlH * kRdW];
     const int bid = blockIdx.x;
     const int tx = bid % ntx, ty = (bid / ntx) % nty, tz = bid / (ntx * nty);
-    const int s0 = tx * kPlTX, y0 = 1 + ty * kPlTY, z0 = 1 + tz * zc;
+    const int s0 = tx * kRdTX, y0 = 1 + ty * kPlTY, z0 = 1 + tz * zc;
     const int z1 = min(z0 + zc, m);
     const int tid = threadIdx.x;
     PlIn<T> nx[NP];
@@ -358,7 +359,7 @@ __global__ void __launch_bounds__(kPlThreads) k3_red_planes(int m, T c1, T c2, c
 #pragma unroll
             for (int k = 0; k < NO; k++) {
                 const int e = tid + k * kPlThreads;
-                const int b = y0 + e / kPlTX, sl = s0 + e % kPlTX;
+                const int b = y0 + e / kRdTX, sl = s0 + e % kRdTX;
                 const int a = 2 * sl + ((b + c) & 1);
                 if (b < m && a >= 1 && a < m && ((a | b | c) & 1) == 0) rn[k] = rR[idxR(m, a, b, c)];
             }
@@ -376,7 +377,7 @@ __global__ void __launch_bounds__(kPlThreads) k3_red_planes(int m, T c1, T c2, c
 #pragma unroll
             for (int k = 0; k < NO; k++) {
                 const int e = tid + k * kPlThreads;
-                const int ly = e / kPlTX, ls = e % kPlTX;
+                const int ly = e / kRdTX, ls = e % kRdTX;
                 const int b = y0 + ly, sl = s0 + ls;
                 const int a = 2 * sl + ((b + co) & 1);
                 if (b >= m || a < 1 || a >= m) continue;
@@ -402,7 +403,9 @@ __global__ void __launch_bounds__(kPlThreads) k3_red_planes(int m, T c1, T c2, c
 
 constexpr int kPlMinSide = 128;   // smaller levels: one thread per point
 
-inline int pl_zchunk(int m) { return m >= 256 ? 16 : 8; }
+// z planes per workgroup (measured on MI355X at 257^3: 8 is best, longer
+// chunks leave too few workgroups in flight)
+inline int pl_zchunk(int) { return 8; }
 
 template <typename T>
 void launch_jac3(const Lev3<T>& L, const Lev3<T>& Cr, T* zero, const Ctl* ctl, hipStream_t s)
@@ -414,7 +417,7 @@ void launch_jac3(const Lev3<T>& L, const Lev3<T>& Cr, T* zero, const Ctl* ctl, h
         hipLaunchKernelGGL(k3_jac_mag<T>, g, dim3(256), 0, s, m, L.c, L.r, L.r2, vc, L.v, L.v2, ctl);
     } else if (L.kind == 1) {
         if (m >= kPlMinSide) {
-            int ntx = (m / 2 + kPlTX - 1) / kPlTX, nty = (m - 1 + kPlTY - 1) / kPlTY, zc = pl_zchunk(m);
+            int ntx = (m / 2 + kRdTX - 1) / kRdTX, nty = (m - 1 + kPlTY - 1) / kPlTY, zc = pl_zchunk(m);
             int ntz = (m - 1 + zc - 1) / zc;
             hipLaunchKernelGGL(k3_red_planes<T>, dim3(ntx * nty * ntz), dim3(kPlThreads), 0, s, m, L.c, L.c2, L.r,
                                Cr.v, Cr.v2, L.v, ntx, nty, zc, ctl);
@@ -450,37 +453,85 @@ void launch_jac3_finest(int n, T c, const T* r0, const T* vR, double* u, const C
 }
 
 // ------------------------------------------------- coarse persistent kernel
+// Every level of side <= 8 (green, red and magenta of sides 8 and 4, then
+// the green of side 2: at most 1585 points per kind) staged in LDS: the
+// first level's residual is read once, each level step works in LDS with one
+// barrier, and every level is written back at the end.
 constexpr int kCoarse3Threads = 1024;
+constexpr int kCoarse3Lds = 1585;
+
+template <typename T>
+__device__ inline int lev3_elems(const Lev3<T>& L)
+{
+    if (L.kind == 0) return (int)sizeG(L.m);
+    if (L.kind == 1) return (int)sizeR(L.m);
+    return (int)(sizeME(L.m) + sizeMO(L.m));
+}
 
 template <typename T>
 __global__ void __launch_bounds__(kCoarse3Threads) k3_coarse(Coarse3<T> a, const Ctl* ctl)
 {
     DMG_GATE(ctl);
+    __shared__ T lds[2 * kCoarse3Lds + 64];   // + a zero correction below the coarsest level
+    __shared__ int off[33];
     const int tid = threadIdx.x, nt = blockDim.x;
+    if (tid == 0) {
+        int o = 0;
+        for (int d = a.first; d <= a.last; d++) {
+            off[d] = o;
+            o += lev3_elems(a.lev[d]);
+        }
+        off[32] = o;
+    }
+    __syncthreads();
+    // staged arrays: r (magenta: corners, then centres at +sizeME) and v at +kCoarse3Lds
+    auto R = [&](int d) { return lds + off[d]; };
+    auto V = [&](int d) { return lds + kCoarse3Lds + off[d]; };
+    auto R2 = [&](int d) { return lds + off[d] + sizeME(a.lev[d].m); };
+    auto V2 = [&](int d) { return lds + kCoarse3Lds + off[d] + sizeME(a.lev[d].m); };
+    for (int q = tid; q < off[32]; q += nt) {
+        lds[q] = T(0);
+        lds[kCoarse3Lds + q] = T(0);
+    }
+    if (tid < 64) lds[2 * kCoarse3Lds + tid] = T(0);
+    __syncthreads();
+    {
+        const Lev3<T>& L0 = a.lev[a.first];
+        const int ne = L0.kind == 2 ? (int)sizeME(L0.m) : lev3_elems(L0);
+        for (int q = tid; q < ne; q += nt) R(a.first)[q] = L0.r[q];
+        if (L0.kind == 2)
+            for (int q = tid; q < (int)sizeMO(L0.m); q += nt) R2(a.first)[q] = L0.r2[q];
+    }
+    __syncthreads();
     for (int d = a.first + 1; d <= a.last; d++) {
-        const Lev3<T>& F = a.lev[d - 1];
         const Lev3<T>& C = a.lev[d];
-        int m = F.m;
+        const int m = a.lev[d - 1].m;
+        const T* Fr = R(d - 1);
         if (C.kind == 1) {
+            T* Cr = R(d);
             int w = m / 2 + 1;
             int tot = w * (m - 1) * (m - 1);
             for (int q = tid; q < tot; q += nt) {
                 int col = q % w, b = (q / w) % (m - 1) + 1, c = q / (w * (m - 1)) + 1;
                 int aa = 2 * col + ((b + c) & 1);
-                if (aa >= 1 && aa < m) C.r[idxR(m, aa, b, c)] = rs3_g2r(F.r, m, aa, b, c);
+                if (aa >= 1 && aa < m) Cr[idxR(m, aa, b, c)] = rs3_g2r(Fr, m, aa, b, c);
             }
         } else if (C.kind == 2) {
+            T* CrE = R(d);
+            T* CrO = R2(d);
             int h = m / 2;
             for (int q = tid; q < h * h * h; q += nt) {
                 int A = q % h, B = (q / h) % h, Cc = q / (h * h);
-                C.r2[idxMO(m, 2 * A + 1, 2 * B + 1, 2 * Cc + 1)] = rs3_r2mO(F.r, m, 2 * A + 1, 2 * B + 1, 2 * Cc + 1);
-                if (A >= 1 && B >= 1 && Cc >= 1) C.r[idxME(m, 2 * A, 2 * B, 2 * Cc)] = rs3_r2mE(F.r, m, 2 * A, 2 * B, 2 * Cc);
+                CrO[idxMO(m, 2 * A + 1, 2 * B + 1, 2 * Cc + 1)] = rs3_r2mO(Fr, m, 2 * A + 1, 2 * B + 1, 2 * Cc + 1);
+                if (A >= 1 && B >= 1 && Cc >= 1) CrE[idxME(m, 2 * A, 2 * B, 2 * Cc)] = rs3_r2mE(Fr, m, 2 * A, 2 * B, 2 * Cc);
             }
         } else {
+            T* Cr = R(d);
+            const T* FrO = R2(d - 1);
             int mc = m / 2, k = mc - 1;
             for (int q = tid; q < k * k * k; q += nt) {
                 int A = q % k + 1, B = (q / k) % k + 1, Cc = q / (k * k) + 1;
-                C.r[idxG(mc, A, B, Cc)] = rs3_m2b(F.r, F.r2, m, A, B, Cc);
+                Cr[idxG(mc, A, B, Cc)] = rs3_m2b(Fr, FrO, m, A, B, Cc);
             }
         }
         __syncthreads();
@@ -489,38 +540,61 @@ __global__ void __launch_bounds__(kCoarse3Threads) k3_coarse(Coarse3<T> a, const
         const Lev3<T>& L = a.lev[d];
         int m = L.m;
         if (L.kind == 2) {
-            const T* vB = a.lev[d + 1].v;
+            const T* vB = V(d + 1);
+            const T* rE = R(d);
+            const T* rO = R2(d);
+            T* vE = V(d);
+            T* vO = V2(d);
             int h = m / 2;
             for (int q = tid; q < h * h * h; q += nt) {
                 int A = q % h, B = (q / h) % h, Cc = q / (h * h);
                 int x = 2 * A + 1, y = 2 * B + 1, z = 2 * Cc + 1;
-                L.v2[idxMO(m, x, y, z)] = jac3_magF(L.r2, vB, m, L.c, x, y, z);
-                if (A >= 1 && B >= 1 && Cc >= 1) L.v[idxME(m, x - 1, y - 1, z - 1)] = jac3_magC(L.r, L.r2, vB, m, L.c, x - 1, y - 1, z - 1);
+                vO[idxMO(m, x, y, z)] = jac3_magF(rO, vB, m, L.c, x, y, z);
+                if (A >= 1 && B >= 1 && Cc >= 1) vE[idxME(m, x - 1, y - 1, z - 1)] = jac3_magC(rE, rO, vB, m, L.c, x - 1, y - 1, z - 1);
             }
         } else if (L.kind == 1) {
-            const Lev3<T>& M = a.lev[d + 1];
+            const T* mE = V(d + 1);
+            const T* mO = V2(d + 1);
+            const T* rR = R(d);
+            T* vR = V(d);
             int h = m / 2;
             for (int q = tid; q < h * h * h; q += nt) {
                 int A = q % h, B = (q / h) % h, Cc = q / (h * h);
                 int x = 2 * A, y = 2 * B, z = 2 * Cc;
-                if (Cc >= 1) L.v[idxR(m, x + 1, y + 1, z)] = jac3_redF(L.r, M.v, M.v2, m, L.c, x + 1, y + 1, z);
-                if (A >= 1) L.v[idxR(m, x, y + 1, z + 1)] = jac3_redF(L.r, M.v, M.v2, m, L.c, x, y + 1, z + 1);
-                if (B >= 1) L.v[idxR(m, x + 1, y, z + 1)] = jac3_redF(L.r, M.v, M.v2, m, L.c, x + 1, y, z + 1);
-                if (A >= 1 && B >= 1 && Cc >= 1) L.v[idxR(m, x, y, z)] = jac3_redC(L.r, M.v, M.v2, m, L.c, L.c2, x, y, z);
+                if (Cc >= 1) vR[idxR(m, x + 1, y + 1, z)] = jac3_redF(rR, mE, mO, m, L.c, x + 1, y + 1, z);
+                if (A >= 1) vR[idxR(m, x, y + 1, z + 1)] = jac3_redF(rR, mE, mO, m, L.c, x, y + 1, z + 1);
+                if (B >= 1) vR[idxR(m, x + 1, y, z + 1)] = jac3_redF(rR, mE, mO, m, L.c, x + 1, y, z + 1);
+                if (A >= 1 && B >= 1 && Cc >= 1) vR[idxR(m, x, y, z)] = jac3_redC(rR, mE, mO, m, L.c, L.c2, x, y, z);
             }
         } else {
-            const T* vR = (d == a.last) ? a.zero : a.lev[d + 1].v;
+            const T* vR = (d == a.last) ? lds + 2 * kCoarse3Lds : V(d + 1);
+            const T* rG = R(d);
+            T* vG = V(d);
             int w = m / 2 + 1;
             int tot = w * (m - 1) * (m - 1);
             for (int q = tid; q < tot; q += nt) {
                 int t = q % w, b = (q / w) % (m - 1) + 1, c = q / (w * (m - 1)) + 1;
                 int par = (b + c) & 1;
                 int aC = 2 * t + par, aF = 2 * t + 1 - par;
-                if (aF >= 1 && aF < m) L.v[idxG(m, aF, b, c)] = jac3_greenF(L.r, vR, m, L.c, aF, b, c);
-                if (aC >= 1 && aC < m) L.v[idxG(m, aC, b, c)] = jac3_greenC(L.r, vR, m, L.c, aC, b, c);
+                if (aF >= 1 && aF < m) vG[idxG(m, aF, b, c)] = jac3_greenF(rG, vR, m, L.c, aF, b, c);
+                if (aC >= 1 && aC < m) vG[idxG(m, aC, b, c)] = jac3_greenC(rG, vR, m, L.c, aC, b, c);
             }
         }
         __syncthreads();
+    }
+    // write back: residuals below the first level, every correction
+    for (int d = a.first; d <= a.last; d++) {
+        const Lev3<T>& L = a.lev[d];
+        const int n1 = L.kind == 2 ? (int)sizeME(L.m) : lev3_elems(L);
+        for (int q = tid; q < n1; q += nt) {
+            if (d > a.first) L.r[q] = R(d)[q];
+            L.v[q] = V(d)[q];
+        }
+        if (L.kind == 2)
+            for (int q = tid; q < (int)sizeMO(L.m); q += nt) {
+                if (d > a.first) L.r2[q] = R2(d)[q];
+                L.v2[q] = V2(d)[q];
+            }
     }
 }
 

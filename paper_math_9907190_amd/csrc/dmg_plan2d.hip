@@ -28,7 +28,7 @@ namespace dmg {
 
 namespace {
 
-constexpr int kCoarseSide2 = 32;  // aligned levels of side <= this run in the coarse kernel
+constexpr int kCoarseSide2 = 64;  // aligned levels of side <= this run in the coarse kernel
 constexpr int kMaxSide2 = 1 << 15;
 
 int side_of(int lam) { return 1 << (1 + (lam + 1) / 2); }

@@ -160,6 +160,13 @@ int plan3_layout(Plan3& P, int n, int prec, const double* p)
         for (int d = 1; d <= P.D; d++)
             if (P.lev[d].m <= kCoarseSide3) { P.dc = d; break; }
         while (P.dc > 1 && P.dc % 3 != 0) P.dc--;
+        // the persistent kernel stages these levels in LDS (at most 1585 points per kind)
+        size_t staged = 0;
+        for (int d = P.dc; d <= P.D; d++) {
+            const Level3& v = P.lev[d];
+            staged += v.kind == 0 ? sizeG(v.m) : v.kind == 1 ? sizeR(v.m) : sizeME(v.m) + sizeMO(v.m);
+        }
+        if (P.dc && staged > 1585) return MG_ERR_SIZE;
     }
     P.total = off;
     return MG_OK;
