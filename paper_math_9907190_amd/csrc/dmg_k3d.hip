@@ -5,6 +5,7 @@
 // so both half-sweeps run in one launch.
 #include "dmg_launch.hpp"
 #include "dmg_launch3.hpp"
+#include "dmg_net_dev.hpp"
 
 namespace dmg {
 
@@ -468,12 +469,25 @@ __device__ inline int lev3_elems(const Lev3<T>& L)
     return (int)(sizeME(L.m) + sizeMO(L.m));
 }
 
+// the staged levels: r (magenta: corners, then centres at +sizeME) and v at
+// +kCoarse3Lds; a zero correction below the coarsest level at the end
 template <typename T>
-__global__ void __launch_bounds__(kCoarse3Threads) k3_coarse(Coarse3<T> a, const Ctl* ctl)
+struct S3 {
+    T* lds;
+    const int* off;
+    const Coarse3<T>* a;
+    __device__ T* R(int d) const { return lds + off[d]; }
+    __device__ T* V(int d) const { return lds + kCoarse3Lds + off[d]; }
+    __device__ T* R2(int d) const { return lds + off[d] + sizeME(a->lev[d].m); }
+    __device__ T* V2(int d) const { return lds + kCoarse3Lds + off[d] + sizeME(a->lev[d].m); }
+    __device__ T* Z() const { return lds + 2 * kCoarse3Lds; }
+};
+constexpr int kCoarse3LdsTotal = 2 * kCoarse3Lds + 64;
+
+// offsets, zeroing and the first level's residual
+template <typename T>
+__device__ void coarse3_stage_in(const Coarse3<T>& a, T* lds, int* off)
 {
-    DMG_GATE(ctl);
-    __shared__ T lds[2 * kCoarse3Lds + 64];   // + a zero correction below the coarsest level
-    __shared__ int off[33];
     const int tid = threadIdx.x, nt = blockDim.x;
     if (tid == 0) {
         int o = 0;
@@ -484,31 +498,32 @@ __global__ void __launch_bounds__(kCoarse3Threads) k3_coarse(Coarse3<T> a, const
         off[32] = o;
     }
     __syncthreads();
-    // staged arrays: r (magenta: corners, then centres at +sizeME) and v at +kCoarse3Lds
-    auto R = [&](int d) { return lds + off[d]; };
-    auto V = [&](int d) { return lds + kCoarse3Lds + off[d]; };
-    auto R2 = [&](int d) { return lds + off[d] + sizeME(a.lev[d].m); };
-    auto V2 = [&](int d) { return lds + kCoarse3Lds + off[d] + sizeME(a.lev[d].m); };
+    const S3<T> S{lds, off, &a};
     for (int q = tid; q < off[32]; q += nt) {
         lds[q] = T(0);
         lds[kCoarse3Lds + q] = T(0);
     }
-    if (tid < 64) lds[2 * kCoarse3Lds + tid] = T(0);
+    if (tid < 64) S.Z()[tid] = T(0);
     __syncthreads();
-    {
-        const Lev3<T>& L0 = a.lev[a.first];
-        const int ne = L0.kind == 2 ? (int)sizeME(L0.m) : lev3_elems(L0);
-        for (int q = tid; q < ne; q += nt) R(a.first)[q] = L0.r[q];
-        if (L0.kind == 2)
-            for (int q = tid; q < (int)sizeMO(L0.m); q += nt) R2(a.first)[q] = L0.r2[q];
-    }
+    const Lev3<T>& L0 = a.lev[a.first];
+    const int ne = L0.kind == 2 ? (int)sizeME(L0.m) : lev3_elems(L0);
+    for (int q = tid; q < ne; q += nt) S.R(a.first)[q] = L0.r[q];
+    if (L0.kind == 2)
+        for (int q = tid; q < (int)sizeMO(L0.m); q += nt) S.R2(a.first)[q] = L0.r2[q];
     __syncthreads();
-    for (int d = a.first + 1; d <= a.last; d++) {
+}
+
+// restriction into d for d = lo+1 .. hi
+template <typename T>
+__device__ void coarse3_down(const Coarse3<T>& a, const S3<T>& S, int lo, int hi)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int d = lo + 1; d <= hi; d++) {
         const Lev3<T>& C = a.lev[d];
         const int m = a.lev[d - 1].m;
-        const T* Fr = R(d - 1);
+        const T* Fr = S.R(d - 1);
         if (C.kind == 1) {
-            T* Cr = R(d);
+            T* Cr = S.R(d);
             int w = m / 2 + 1;
             int tot = w * (m - 1) * (m - 1);
             for (int q = tid; q < tot; q += nt) {
@@ -517,8 +532,8 @@ __global__ void __launch_bounds__(kCoarse3Threads) k3_coarse(Coarse3<T> a, const
                 if (aa >= 1 && aa < m) Cr[idxR(m, aa, b, c)] = rs3_g2r(Fr, m, aa, b, c);
             }
         } else if (C.kind == 2) {
-            T* CrE = R(d);
-            T* CrO = R2(d);
+            T* CrE = S.R(d);
+            T* CrO = S.R2(d);
             int h = m / 2;
             for (int q = tid; q < h * h * h; q += nt) {
                 int A = q % h, B = (q / h) % h, Cc = q / (h * h);
@@ -526,8 +541,8 @@ __global__ void __launch_bounds__(kCoarse3Threads) k3_coarse(Coarse3<T> a, const
                 if (A >= 1 && B >= 1 && Cc >= 1) CrE[idxME(m, 2 * A, 2 * B, 2 * Cc)] = rs3_r2mE(Fr, m, 2 * A, 2 * B, 2 * Cc);
             }
         } else {
-            T* Cr = R(d);
-            const T* FrO = R2(d - 1);
+            T* Cr = S.R(d);
+            const T* FrO = S.R2(d - 1);
             int mc = m / 2, k = mc - 1;
             for (int q = tid; q < k * k * k; q += nt) {
                 int A = q % k + 1, B = (q / k) % k + 1, Cc = q / (k * k) + 1;
@@ -536,15 +551,22 @@ __global__ void __launch_bounds__(kCoarse3Threads) k3_coarse(Coarse3<T> a, const
         }
         __syncthreads();
     }
-    for (int d = a.last; d >= a.first; d--) {
+}
+
+// Jacobi at d = hi down to lo (the coarsest from a zero correction)
+template <typename T>
+__device__ void coarse3_up(const Coarse3<T>& a, const S3<T>& S, int lo, int hi)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int d = hi; d >= lo; d--) {
         const Lev3<T>& L = a.lev[d];
         int m = L.m;
         if (L.kind == 2) {
-            const T* vB = V(d + 1);
-            const T* rE = R(d);
-            const T* rO = R2(d);
-            T* vE = V(d);
-            T* vO = V2(d);
+            const T* vB = S.V(d + 1);
+            const T* rE = S.R(d);
+            const T* rO = S.R2(d);
+            T* vE = S.V(d);
+            T* vO = S.V2(d);
             int h = m / 2;
             for (int q = tid; q < h * h * h; q += nt) {
                 int A = q % h, B = (q / h) % h, Cc = q / (h * h);
@@ -553,10 +575,10 @@ __global__ void __launch_bounds__(kCoarse3Threads) k3_coarse(Coarse3<T> a, const
                 if (A >= 1 && B >= 1 && Cc >= 1) vE[idxME(m, x - 1, y - 1, z - 1)] = jac3_magC(rE, rO, vB, m, L.c, x - 1, y - 1, z - 1);
             }
         } else if (L.kind == 1) {
-            const T* mE = V(d + 1);
-            const T* mO = V2(d + 1);
-            const T* rR = R(d);
-            T* vR = V(d);
+            const T* mE = S.V(d + 1);
+            const T* mO = S.V2(d + 1);
+            const T* rR = S.R(d);
+            T* vR = S.V(d);
             int h = m / 2;
             for (int q = tid; q < h * h * h; q += nt) {
                 int A = q % h, B = (q / h) % h, Cc = q / (h * h);
@@ -567,9 +589,9 @@ __global__ void __launch_bounds__(kCoarse3Threads) k3_coarse(Coarse3<T> a, const
                 if (A >= 1 && B >= 1 && Cc >= 1) vR[idxR(m, x, y, z)] = jac3_redC(rR, mE, mO, m, L.c, L.c2, x, y, z);
             }
         } else {
-            const T* vR = (d == a.last) ? lds + 2 * kCoarse3Lds : V(d + 1);
-            const T* rG = R(d);
-            T* vG = V(d);
+            const T* vR = (d == a.last) ? S.Z() : S.V(d + 1);
+            const T* rG = S.R(d);
+            T* vG = S.V(d);
             int w = m / 2 + 1;
             int tot = w * (m - 1) * (m - 1);
             for (int q = tid; q < tot; q += nt) {
@@ -582,19 +604,196 @@ __global__ void __launch_bounds__(kCoarse3Threads) k3_coarse(Coarse3<T> a, const
         }
         __syncthreads();
     }
-    // write back: residuals below the first level, every correction
+}
+
+// write back: residuals below the first level, every correction
+template <typename T>
+__device__ void coarse3_stage_out(const Coarse3<T>& a, const S3<T>& S)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
     for (int d = a.first; d <= a.last; d++) {
         const Lev3<T>& L = a.lev[d];
         const int n1 = L.kind == 2 ? (int)sizeME(L.m) : lev3_elems(L);
         for (int q = tid; q < n1; q += nt) {
-            if (d > a.first) L.r[q] = R(d)[q];
-            L.v[q] = V(d)[q];
+            if (d > a.first) L.r[q] = S.R(d)[q];
+            L.v[q] = S.V(d)[q];
         }
         if (L.kind == 2)
             for (int q = tid; q < (int)sizeMO(L.m); q += nt) {
-                if (d > a.first) L.r2[q] = R2(d)[q];
-                L.v2[q] = V2(d)[q];
+                if (d > a.first) L.r2[q] = S.R2(d)[q];
+                L.v2[q] = S.V2(d)[q];
             }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kCoarse3Threads) k3_coarse(Coarse3<T> a, const Ctl* ctl)
+{
+    DMG_GATE(ctl);
+    __shared__ T lds[kCoarse3LdsTotal];
+    __shared__ int off[33];
+    coarse3_stage_in(a, lds, off);
+    const S3<T> S{lds, off, &a};
+    coarse3_down(a, S, a.first, a.last);
+    coarse3_up(a, S, a.first, a.last);
+    coarse3_stage_out(a, S);
+}
+
+// ------------------------------------------------- learned coarse correction
+// The cut is the green level of side 8 (9^3 points): the first coarse level
+// when the grid has a level below it.  The network's output at the red
+// points (a+b+c even) fills the red level's correction, and the cut level's
+// own Jacobi then runs unchanged.  Judge and state as in 2D (Ctl::net).
+
+__device__ inline double block_sum3(double v, double* red)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); w++) s += red[w];
+    return s;
+}
+
+// ||r - A v||^2 over the interior of a green level of side m (7-point
+// Laplacian with spacing 1/m)
+template <typename T>
+__device__ double cut3_resid2(const T* r, const T* v, int m, double* red)
+{
+    double s = 0, m2 = (double)m * m;
+    const int k = m - 1;
+    for (int q = threadIdx.x; q < k * k * k; q += blockDim.x) {
+        int a = q % k + 1, b = (q / k) % k + 1, c = q / (k * k) + 1;
+        size_t o = idxG(m, a, b, c), w = (size_t)(m + 1), w2 = w * w;
+        double av = ((double)v[o - 1] + (double)v[o + 1] + (double)v[o - w] + (double)v[o + w] + (double)v[o - w2] +
+                     (double)v[o + w2] - 6.0 * (double)v[o]) * m2;
+        double d = (double)r[o] - av;
+        s += d * d;
+    }
+    return block_sum3(s, red);
+}
+
+// network on r_c (green 9^3, spacing H = 1/8): the red-point values of the
+// estimate of A_c^{-1} r_c go to vR (R layout of side 8).  Returns ||r_c||^2.
+template <typename T>
+__device__ double net_cut_3d(const T* rc, T* vR, const bf16_t* __restrict__ wf, bf16_t* A, bf16_t* B, float* out0,
+                             short* linq, double* red)
+{
+    using N = NetGeo<3>;
+    net_zero(A, N::ACT);
+    net_zero(B, N::ACT);
+    net_fill_lin<3>(linq);
+    double ss = 0;
+    for (int q = threadIdx.x; q < N::NIN; q += blockDim.x) {
+        double x = (double)rc[N::lin(q)];
+        ss += x * x;
+    }
+    ss = block_sum3(ss, red);
+    double rms = sqrt(ss / N::NIN);
+    double sc = rms > 0 ? 1.0 / rms : 0.0;
+    for (int q = threadIdx.x; q < N::NIN; q += blockDim.x) {
+        int p = N::lin(q);
+        A[p * kNetCh] = f2bf((float)((double)rc[p] * sc));
+    }
+    __syncthreads();
+    const int WLY = N::T * 256;
+    net_conv_fwd<3, true>(A, B, nullptr, wf, linq);
+    __syncthreads();
+    net_conv_fwd<3, true>(B, A, nullptr, wf + WLY, linq);
+    __syncthreads();
+    net_conv_fwd<3, true>(A, B, nullptr, wf + 2 * WLY, linq);
+    __syncthreads();
+    net_conv_fwd<3, false>(B, nullptr, out0, wf + 3 * WLY, linq);
+    __syncthreads();
+    const double back = rms / ((N::G - 1) * (N::G - 1));
+    for (int q = threadIdx.x; q < N::NIN; q += blockDim.x) {
+        int x = q % N::IN + 1, y = (q / N::IN) % N::IN + 1, z = q / (N::IN * N::IN) + 1;
+        if (((x + y + z) & 1) == 0) vR[idxR(N::G - 1, x, y, z)] = (T)((double)out0[q] * back);
+    }
+    __syncthreads();
+    return ss;
+}
+
+// dynamic LDS of the learned kernel: staged levels, then (16-byte aligned)
+// the two activation grids, the fp32 output, the point table and a copy of
+// the red correction of side 8 (405 points)
+template <typename T>
+constexpr size_t coarse3_net_act_off() { return (sizeof(T) * kCoarse3LdsTotal + 15) / 16 * 16; }
+template <typename T>
+constexpr size_t coarse3_net_save_off()
+{
+    using N = NetGeo<3>;
+    return (coarse3_net_act_off<T>() + 2 * sizeof(bf16_t) * N::ACT + N::TILES * 16 * (sizeof(float) + sizeof(short)) +
+            15) / 16 * 16;
+}
+template <typename T>
+constexpr size_t coarse3_net_lds() { return coarse3_net_save_off<T>() + sizeof(T) * 405; }
+
+template <typename T>
+__global__ void __launch_bounds__(kCoarse3Threads) k3_coarse_net(Coarse3<T> a, Ctl* ctl, const bf16_t* __restrict__ wf)
+{
+    using N = NetGeo<3>;
+    DMG_GATE(ctl);
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* lds = reinterpret_cast<T*>(smem);
+    bf16_t* A = reinterpret_cast<bf16_t*>(smem + coarse3_net_act_off<T>());
+    bf16_t* B = A + N::ACT;
+    float* out0 = reinterpret_cast<float*>(B + N::ACT);
+    short* linq = reinterpret_cast<short*>(out0 + N::TILES * 16);
+    T* vsave = reinterpret_cast<T*>(smem + coarse3_net_save_off<T>());
+    __shared__ int off[33];
+    __shared__ double red[kCoarse3Threads / 64];
+    coarse3_stage_in(a, lds, off);
+    const S3<T> S{lds, off, &a};
+    const int cut = a.first;
+    const bool has = a.lev[cut].kind == 0 && a.lev[cut].m == N::G - 1 && a.last > cut;
+    const int state = has ? ctl->net : 0;
+    if (state == 0) {
+        coarse3_down(a, S, a.first, a.last);
+        coarse3_up(a, S, a.first, a.last);
+        coarse3_stage_out(a, S);
+        return;
+    }
+    const int m = a.lev[cut].m;
+    const int nR = (int)sizeR(m);   // 405 (side 8)
+    double rn2 = net_cut_3d<T>(S.R(cut), S.V(cut + 1), wf, A, B, out0, linq, red);
+    coarse3_up(a, S, cut, cut);
+    double qn = cut3_resid2<T>(S.R(cut), S.V(cut), m, red);
+    int next = state, used = 0;
+    double theta = ctl->theta, qfirst = ctl->q_net;
+    if (state == 1 || !(qn <= theta * theta * rn2)) {
+        if (state == 1)
+            for (int q = threadIdx.x; q < nR; q += blockDim.x) vsave[q] = S.V(cut + 1)[q];
+        __syncthreads();
+        coarse3_down(a, S, a.first, a.last);
+        coarse3_up(a, S, a.first, a.last);
+        double qp = cut3_resid2<T>(S.R(cut), S.V(cut), m, red);
+        if (state == 1) {
+            theta = rn2 > 0 ? sqrt(qp / rn2) : 0.0;
+            qfirst = rn2 > 0 ? sqrt(qn / rn2) : 0.0;
+            if (qn <= qp) {
+                for (int q = threadIdx.x; q < nR; q += blockDim.x) S.V(cut + 1)[q] = vsave[q];
+                __syncthreads();
+                coarse3_up(a, S, cut, cut);
+                next = 2;
+                used = 1;
+            } else {
+                next = 0;
+            }
+        } else {
+            next = 0;
+        }
+    } else {
+        used = 1;
+    }
+    coarse3_stage_out(a, S);
+    if (threadIdx.x == 0) {
+        ctl->net = next;
+        ctl->theta = theta;
+        ctl->q_net = qfirst;
+        ctl->net_used += used;
+        if (next == 0) ctl->net_off = 1;
     }
 }
 
@@ -602,6 +801,18 @@ template <typename T>
 void launch_coarse3(const Coarse3<T>& a, const Ctl* ctl, hipStream_t s)
 {
     hipLaunchKernelGGL(k3_coarse<T>, dim3(1), dim3(kCoarse3Threads), 0, s, a, ctl);
+}
+
+template <typename T>
+void launch_coarse3_net(const Coarse3<T>& a, Ctl* ctl, const bf16_t* wf, hipStream_t s)
+{
+    static bool attr = false;
+    if (!attr) {
+        (void)hipFuncSetAttribute((const void*)k3_coarse_net<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)coarse3_net_lds<T>());
+        attr = true;
+    }
+    hipLaunchKernelGGL(k3_coarse_net<T>, dim3(1), dim3(kCoarse3Threads), coarse3_net_lds<T>(), s, a, ctl, wf);
 }
 
 // ------------------------------------------------------------ level export
@@ -635,6 +846,7 @@ void launch_level_get3(int kind, int m, const T* src, const T* src2, double* dst
     template void launch_jac3<T>(const Lev3<T>&, const Lev3<T>&, T*, const Ctl*, hipStream_t);            \
     template void launch_jac3_finest<T>(int, T, const T*, const T*, double*, const Ctl*, hipStream_t);    \
     template void launch_coarse3<T>(const Coarse3<T>&, const Ctl*, hipStream_t);                          \
+    template void launch_coarse3_net<T>(const Coarse3<T>&, Ctl*, const bf16_t*, hipStream_t);             \
     template void launch_level_get3<T>(int, int, const T*, const T*, double*, hipStream_t);
 DMG_INST3(double)
 DMG_INST3(float)

@@ -164,6 +164,9 @@ template <typename T>
 void launch_jac3_finest(int n, T c, const T* r0, const T* vR, double* u, const Ctl* ctl, hipStream_t s);
 template <typename T>
 void launch_coarse3(const Coarse3<T>& a, const Ctl* ctl, hipStream_t s);
+// the coarse kernel with the learned correction at the green level of side 8 (wf: packed forward weights)
+template <typename T>
+void launch_coarse3_net(const Coarse3<T>& a, Ctl* ctl, const unsigned short* wf, hipStream_t s);
 template <typename T>
 void launch_level_get3(int kind, int m, const T* src, const T* src2, double* dst, hipStream_t s);
 

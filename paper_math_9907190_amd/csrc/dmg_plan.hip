@@ -229,7 +229,7 @@ int mg_set_coarse_net(mg_plan* P, const float* w, int cut_level)
     DevGuard g(P->device);
     if (!g.ok) return MG_ERR_HIP;
     if (P->p2) return plan2_set_net(*P->p2, w, cut_level);
-    return MG_ERR_ARG;
+    return plan3_set_net(*P->p3, w, cut_level);
 }
 
 int mg_net_stats(mg_plan* P, int* net_cycles, int* fell_back, double* q_net, double* q_plain)
@@ -238,7 +238,7 @@ int mg_net_stats(mg_plan* P, int* net_cycles, int* fell_back, double* q_net, dou
     DevGuard g(P->device);
     if (!g.ok) return MG_ERR_HIP;
     if (P->p2) return plan2_net_stats(*P->p2, net_cycles, fell_back, q_net, q_plain);
-    return MG_ERR_ARG;
+    return plan3_net_stats(*P->p3, net_cycles, fell_back, q_net, q_plain);
 }
 
 int mg_coarse_export(mg_plan* P, int level, double* dst)
@@ -247,7 +247,7 @@ int mg_coarse_export(mg_plan* P, int level, double* dst)
     DevGuard g(P->device);
     if (!g.ok) return MG_ERR_HIP;
     if (P->p2) return plan2_coarse_export(*P->p2, level, dst);
-    return MG_ERR_ARG;
+    return plan3_coarse_export(*P->p3, level, dst);
 }
 
 int mg_level_get(mg_plan* P, int depth, int which, double* dst)

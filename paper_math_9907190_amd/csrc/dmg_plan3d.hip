@@ -5,9 +5,11 @@
 // (magenta-blue, red-magenta, green-red), the finest fused with u += v.
 #include "dmg_launch.hpp"
 #include "dmg_launch3.hpp"
+#include "dmg_net.hpp"
 #include "dmg_plan3d.hpp"
 
 #include <string.h>
+#include <vector>
 
 namespace dmg {
 
@@ -78,7 +80,8 @@ void enqueue_cycle3(Plan3& P, double* u, const Ctl* ctl)
         a.last = D;
         for (int d = dc; d <= D; d++) a.lev[d] = lv(d);
         a.zero = at<T>(P, P.zero);
-        launch_coarse3<T>(a, ctl, s);
+        if (P.has_net) launch_coarse3_net<T>(a, at<Ctl>(P, P.ctl), at<bf16_t>(P, P.net), s);
+        else launch_coarse3<T>(a, ctl, s);
     }
     for (int d = (dc ? dc - 1 : D); d >= 1; d--) {
         Lev3<T> c = (d == D) ? Lev3<T>{} : lv(d + 1);
@@ -135,6 +138,7 @@ int plan3_layout(Plan3& P, int n, int prec, const double* p)
     P.partial = take(sizeof(double) * (size_t)P.nparts);
     P.zero = take(sizeof(double) * 64);
     P.r0 = take(es * sizeG(n));
+    P.net = take(sizeof(bf16_t) * (size_t)NetGeo<3>::PACK);
     double h = 1.0 / n;
     for (int d = 0; d <= P.D; d++) {
         Level3& v = P.lev[d];
@@ -194,7 +198,7 @@ int plan3_vcycle(Plan3& P, double* u, const double* f, double* relres)
 {
     Ctl* ctl = at<Ctl>(P, P.ctl);
     double* part = at<double>(P, P.partial);
-    launch_ctl_reset(ctl, 0, 0, 0.0, P.stream);
+    launch_ctl_reset(ctl, 0, 0, 0.0, P.stream, P.has_net ? 1 : 0);
     if (relres) {
         launch_sumsq(3, P.n, f, part, P.nparts, ctl, P.stream);
         enqueue_finalize(P, 0, 0, ctl);
@@ -218,7 +222,7 @@ int plan3_solve(Plan3& P, double* u, const double* f, double rtol, int max_cycle
     Ctl* ctl = at<Ctl>(P, P.ctl);
     double* part = at<double>(P, P.partial);
     hipStream_t s = P.stream;
-    launch_ctl_reset(ctl, 1, max_cycles, rtol, s);
+    launch_ctl_reset(ctl, 1, max_cycles, rtol, s, P.has_net ? 1 : 0);
     launch_sumsq(3, P.n, f, part, P.nparts, ctl, s);
     enqueue_finalize(P, 0, 0, ctl);
     enqueue_residual(P, u, f, ctl);
@@ -260,6 +264,48 @@ int plan3_level_get(Plan3& P, int depth, int which, double* dst)
         launch_level_get3<float>(q.kind, q.m, at<float>(P, src), q.kind == 2 ? at<float>(P, src2) : nullptr, dst,
                                  P.stream);
     return last_launch();
+}
+
+// ------------------------------------------------ learned coarse correction
+
+int plan3_set_net(Plan3& P, const float* w, int cut_level)
+{
+    if (cut_level != kNetCut) return MG_ERR_ARG;
+    if (w) {
+        const int nw = NetGeo<3>::NW;
+        std::vector<float> wm(w, w + nw);
+        for (int i = 0; i < nw; i++) {   // the padded channels are not parameters
+            int layer = (i >> 8) / NetGeo<3>::T, ci = (i >> 4) & 15, co = i & 15;
+            if ((layer == 0 && ci) || (layer == kNetLayers - 1 && co)) wm[i] = 0.f;
+        }
+        std::vector<bf16_t> wf(NetGeo<3>::PACK);
+        net_pack_host(3, wm.data(), wf.data(), nullptr);
+        if (hipStreamSynchronize(P.stream) != hipSuccess ||
+            hipMemcpy(P.ws + P.net, wf.data(), sizeof(bf16_t) * wf.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return MG_ERR_HIP;
+    }
+    P.has_net = w != nullptr;
+    return MG_OK;
+}
+
+int plan3_net_stats(Plan3& P, int* net_cycles, int* fell_back, double* q_net, double* q_plain)
+{
+    if (hipMemcpyAsync(P.hctl, at<Ctl>(P, P.ctl), kCtlHead, hipMemcpyDeviceToHost, P.stream) != hipSuccess ||
+        hipStreamSynchronize(P.stream) != hipSuccess)
+        return MG_ERR_HIP;
+    const Ctl& c = *P.hctl;
+    if (net_cycles) *net_cycles = c.net_used;
+    if (fell_back) *fell_back = c.net_off;
+    if (q_net) *q_net = c.q_net;
+    if (q_plain) *q_plain = c.theta;
+    return MG_OK;
+}
+
+// aligned level `level` (0 = the coarsest) of the 3D hierarchy: depth D - level
+int plan3_coarse_export(Plan3& P, int level, double* dst)
+{
+    if (level < 0 || level > P.D || !dst) return MG_ERR_ARG;
+    return plan3_level_get(P, P.D - level, 0, dst);
 }
 
 }  // namespace dmg

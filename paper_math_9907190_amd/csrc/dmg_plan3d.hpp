@@ -17,7 +17,8 @@ struct Level3 {
 struct Plan3 {
     int n = 0, prec = 0, D = 0, dc = 0;
     double p[4] = {1, 1, 1, 1};
-    size_t ctl = 0, partial = 0, zero = 0, r0 = 0, total = 0;
+    size_t ctl = 0, partial = 0, zero = 0, r0 = 0, net = 0, total = 0;
+    bool has_net = false;   // learned coarse correction set (packed bf16 weights at net)
     int nparts = 0;
     Level3 lev[kMaxLev3];
     char* ws = nullptr;
@@ -34,5 +35,8 @@ int plan3_vcycle(Plan3& P, double* u, const double* f, double* relres);
 int plan3_solve(Plan3& P, double* u, const double* f, double rtol, int max_cycles, int* cycles, double* relres,
                 double* history);
 int plan3_level_get(Plan3& P, int depth, int which, double* dst);
+int plan3_set_net(Plan3& P, const float* w, int cut_level);
+int plan3_net_stats(Plan3& P, int* net_cycles, int* fell_back, double* q_net, double* q_plain);
+int plan3_coarse_export(Plan3& P, int level, double* dst);
 
 }  // namespace dmg

@@ -170,7 +170,7 @@ void launch_finalize(int kind, int k, const double* partial, int nparts, Ctl* ct
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, kind, k, partial, nparts, ctl);
 }
 
-__global__ void k_ctl_reset(Ctl* ctl, int mode, int max_cycles, double rtol)
+__global__ void k_ctl_reset(Ctl* ctl, int mode, int max_cycles, double rtol, int net)
 {
     if (threadIdx.x != 0) return;
     ctl->done = 0;
@@ -182,11 +182,16 @@ __global__ void k_ctl_reset(Ctl* ctl, int mode, int max_cycles, double rtol)
     ctl->rtol = rtol;
     ctl->fnorm = 0;
     ctl->rr0 = ctl->prev = ctl->last = 0;
+    ctl->net = net;
+    ctl->theta = 0;
+    ctl->q_net = 0;
+    ctl->net_used = 0;
+    ctl->net_off = 0;
 }
 
-void launch_ctl_reset(Ctl* ctl, int mode, int max_cycles, double rtol, hipStream_t s)
+void launch_ctl_reset(Ctl* ctl, int mode, int max_cycles, double rtol, hipStream_t s, int net)
 {
-    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, ctl, mode, max_cycles, rtol);
+    hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, ctl, mode, max_cycles, rtol, net);
 }
 
 template void launch_residual<double>(int, int, const double*, const double*, double*, double*, int, const Ctl*,

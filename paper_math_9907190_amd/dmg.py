@@ -354,6 +354,15 @@ class Solver:
         used, off, qn, qp = mg_net_stats(self.plan, 1)
         return used[0], off[0], qn[0], qp[0]
 
+    def coarse_export(self, level=MG_NET_CUT):
+        """Restricted residual of aligned level `level` (0 = the coarsest) after the last cycle."""
+        K = self.n.bit_length() - 1
+        depth = self.dim * (K - 1) - level
+        side = mg_level_info(self.dim, self.n, depth)[1]
+        out = torch.empty((side + 1,) * self.dim, dtype=torch.float64, device=self.device)
+        mg_coarse_export(self.plan, level, out.data_ptr())
+        return out
+
     def close(self):
         if getattr(self, "plan", None) is not None:
             mg_destroy(self.plan)

@@ -62,10 +62,38 @@ def solve_cut(r, rtol=1e-13, device=None):
     return e
 
 
+def make_pairs_3d(n=128, seeds=range(1000, 1250), cycles=8, device=None, target_rtol=1e-13, log=None):
+    """3D pairs: the cut is the green grid of side 8 (9^3 points); one plain
+    FP64 solve per right-hand side, the cut residual exported after every
+    cycle, targets from FP64 solves of the 9^3 problems.  Shapes (P, 9, 9, 9)."""
+    device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    seeds = list(seeds)
+    S = dmg.Solver(3, n, precision=dmg.MG_FP64, device=device)
+    rs = []
+    for k, sd in enumerate(seeds):
+        if log and k % 50 == 0:
+            log("pairs 3D: problem %d of %d (n=%d)" % (k, len(seeds), n))
+        f = torch.from_numpy(workloads.training_rhs(3, n, sd)).to(device)
+        u = torch.zeros_like(f)
+        for _ in range(cycles):
+            S.vcycle(u, f)
+            rs.append(S.coarse_export(CUT).clone())
+    S.close()
+    r = torch.stack(rs).contiguous()
+    e = torch.zeros_like(r)
+    T = dmg.Solver(3, r.shape[-1] - 1, precision=dmg.MG_FP64, device=device)
+    for i in range(r.shape[0]):
+        st, cyc, rr, _ = T.solve(e[i], r[i], rtol=target_rtol, max_cycles=60)
+        if st != dmg.MG_OK and rr > 1e-12:
+            raise RuntimeError("target solve %d failed: status %d" % (i, st))
+    T.close()
+    return r, e
+
+
 def train(r, e, epochs=30, batch=256, lr=2e-3, seed=7, init_seed=1, net=None):
     """Train (or continue training) a network on the pairs; returns (net, epoch losses)."""
     if net is None:
-        net = dmg.Net(dim=2, max_batch=batch, seed=init_seed, device=r.device)
+        net = dmg.Net(dim=r.dim() - 1, max_batch=batch, seed=init_seed, device=r.device)
     hist = net.train(r, e, epochs=epochs, batch=batch, lr=lr, seed=seed)
     return net, hist
 

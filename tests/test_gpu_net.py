@@ -365,3 +365,88 @@ def test_coarse_export_equals_level_get(dmg):
     D.mg_coarse_export(S.plan, 6, out.data_ptr())
     assert torch.equal(out[0], lev)
     S.close()
+
+
+# ------------------------------------------------------------------- 3D cut
+
+N3 = 64
+
+
+@pytest.fixture(scope="module")
+def trained3(dmg):
+    from paper_math_9907190_amd import learned as L
+    print("3D pairs from 24 problems of side %d, 4 cycles each" % N3, flush=True)
+    r, e = L.make_pairs_3d(n=N3, seeds=range(1000, 1024), cycles=4)
+    net, hist = L.train(r, e, epochs=80, batch=32, lr=2e-3, seed=5)
+    w = net.weights().copy()
+    net.close()
+    return r, e, w, hist
+
+
+def jacobi_cut3(r6, y, pg=0.99):
+    """green level 8's Jacobi from the red-point values of y (oracle step)"""
+    m = r6.shape[0] - 1
+    Z, Y, X = np.meshgrid(*(np.arange(m + 1),) * 3, indexing="ij")
+    vC = np.where((X + Y + Z) % 2 == 0, y, 0.0)
+    return O.step_jacobi(3, 0, pg / m ** 2, r6, vC)
+
+
+def cut_ratio3(r6, v6):
+    m = r6.shape[0] - 1
+    c = (slice(1, -1),) * 3
+    av = (v6[2:, 1:-1, 1:-1] + v6[:-2, 1:-1, 1:-1] + v6[1:-1, 2:, 1:-1] + v6[1:-1, :-2, 1:-1]
+          + v6[1:-1, 1:-1, 2:] + v6[1:-1, 1:-1, :-2] - 6 * v6[c]) * m * m
+    return np.linalg.norm(r6[c] - av) / np.linalg.norm(r6[c])
+
+
+def test_3d_training_and_judge(dmg, orc, trained3):
+    r, e, w, hist = trained3
+    print("3D epoch losses: first %.4e, last %.4e" % (hist[0], hist[-1]))
+    assert np.all(np.isfinite(hist)) and hist[-1] < 0.7 * hist[0]
+    checked = 0
+    net = dmg.Net(dim=3, max_batch=8)
+    net.set_weights(w)
+    for i in range(6):
+        f = dev(W.training_rhs(3, N3, 6100 + i))
+        S = dmg.Solver(3, N3)
+        S.set_coarse_net(w)
+        u = torch.zeros_like(f)
+        S.vcycle(u, f)                       # one first (judged) cycle
+        used, off, qn_gpu, qp_gpu = S.net_stats()
+        r6 = S.coarse_export(6)
+        y = net.forward(r6[None].contiguous())[0].cpu().numpy()
+        r6 = r6.cpu().numpy()
+        qn = cut_ratio3(r6, jacobi_cut3(r6, y))
+        qp = cut_ratio3(r6, O.vcycle(np.zeros_like(r6), r6))
+        print("  3D problem %d: net %.3e plain %.3e (kernel: %.3e %.3e) -> used %d off %d"
+              % (i, qn, qp, qn_gpu, qp_gpu, used, off))
+        assert abs(qp_gpu - qp) <= 1e-9 * qp
+        assert abs(qn_gpu - qn) <= 2e-2 * qn
+        if abs(qn - qp) > 0.02 * qp:
+            assert used == (1 if qn <= qp else 0) and off == (0 if qn <= qp else 1)
+            checked += 1
+        S.close()
+    assert checked >= 3
+    net.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_3d_learned_solve_and_poisoned_fallback(dmg, trained3, prec):
+    r, e, w, hist = trained3
+    f = dev(W.training_rhs(3, 2 * N3, 7300 + prec))
+    out = {}
+    for name, wt in (("plain", None), ("learned", w), ("poisoned", 100 * np.random.default_rng(3).standard_normal(w.shape))):
+        S = dmg.Solver(3, 2 * N3, precision=prec)
+        if wt is not None:
+            S.set_coarse_net(np.asarray(wt, dtype=np.float32))
+        u = torch.zeros_like(f)
+        st, cyc, rr, _ = S.solve(u, f, rtol=1e-10, max_cycles=40)
+        out[name] = (st, cyc, rr, u, S.net_stats())
+        S.close()
+    print("3D prec %d: plain %d cycles, learned %d cycles (net on %d), poisoned %d cycles (off %d)"
+          % (prec, out["plain"][1], out["learned"][1], out["learned"][4][0], out["poisoned"][1], out["poisoned"][4][1]))
+    assert out["learned"][0] == dmg.MG_OK and out["learned"][2] <= 1e-10
+    assert out["learned"][1] <= out["plain"][1] + 1
+    # poisoned weights: the judge keeps the plain correction, bit for bit
+    assert out["poisoned"][4][0] == 0 and out["poisoned"][4][1] == 1
+    assert out["poisoned"][1] == out["plain"][1] and torch.equal(out["poisoned"][3], out["plain"][3])
