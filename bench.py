@@ -141,13 +141,13 @@ def train_net(dmg, L, torch, log):
     r, e = L.make_pairs(n=1024, seeds=range(1000, 2250), cycles=8, log=log)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    epochs = 150
-    net, hist = L.train(r, e, epochs=epochs, batch=256, lr=2e-3, seed=7)
+    epochs = sum(k for k, _ in L.SCHEDULE)
+    net, hist = L.train(r, e, batch=256, seed=7, schedule=L.SCHEDULE)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     w = net.weights().copy()
     info = {"pairs": int(r.shape[0]), "pair_seconds": round(t1 - t0, 2), "epochs": epochs, "batch": 256,
-            "train_seconds": round(t2 - t1, 3),
+            "lr_schedule": [list(x) for x in L.SCHEDULE], "train_seconds": round(t2 - t1, 3),
             "train_us_per_step": round(1e6 * (t2 - t1) / (epochs * (r.shape[0] // 256)), 1),
             "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]}
     log("  net: %d pairs in %.1f s, %d epochs in %.2f s, loss %.3e -> %.3e"
@@ -197,6 +197,67 @@ def bench_learned(dmg, L, dev, torch, args, w, info):
         out["learned_speedup"] = round(out["plain"]["ms_to_rtol"] / out["learned"]["ms_to_rtol"], 3)
         log("  learned %s: plain %.3f ms (%d cycles), learned %.3f ms (%d cycles), net on %d cycles, judge off %d/32"
             % (pname, out["plain"]["ms_to_rtol"], out["plain"]["cycles_total"], out["learned"]["ms_to_rtol"],
+               out["learned"]["cycles_total"], out["learned"]["net_cycles"], out["learned"]["judge_switched_off"]))
+        res[pname] = out
+    del fs
+    torch.cuda.empty_cache()
+    return res
+
+
+def bench_learned3d(dmg, L, dev, torch, args):
+    """3D learned coarse correction: 10^4 pairs from 1250 plain FP64 solves
+    of 129^3 problems (f seeds 1000..2249, 8 cycles each; the cut is the 9^3
+    green grid), Adam on the GPU, then 8 held-out 129^3 problems (seeds
+    5000..5007) solved to 1e-10 plain against learned."""
+    t0 = time.perf_counter()
+    r, e = L.make_pairs_3d(n=128, seeds=range(1000, 2250), cycles=8)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    epochs = sum(k for k, _ in L.SCHEDULE)
+    net, hist = L.train(r, e, batch=256, seed=7, schedule=L.SCHEDULE)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    w = net.weights().copy()
+    net.close()
+    info = {"pairs": int(r.shape[0]), "pair_seconds": round(t1 - t0, 2), "epochs": epochs, "batch": 256,
+            "lr_schedule": [list(x) for x in L.SCHEDULE], "train_seconds": round(t2 - t1, 3),
+            "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]}
+    del r, e
+    fs = [torch.from_numpy(f).to(dev) for f in L.eval_problems(128, range(5000, 5008), dim=3)]
+    res = {"workload": "8 held-out 129^3 problems (f seeds 5000..5007), each solved to %.0e; network trained on "
+                       "%d cut-level pairs" % (args.rtol, info["pairs"]), "training": info}
+    for pname, prec in (("fp64", dmg.MG_FP64), ("fp32_refined", dmg.MG_FP32_REFINED)):
+        out = {}
+        for mode in ("plain", "learned"):
+            S = dmg.Solver(3, 128, precision=prec, device=dev)
+            if mode == "learned":
+                S.set_coarse_net(w)
+            u = torch.zeros_like(fs[0])
+            S.solve(u, fs[0], rtol=args.rtol, max_cycles=60)
+            cyc_tot, used_tot, off_tot, qn, qp = 0, 0, 0, [], []
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for f in fs:
+                u = torch.zeros_like(f)
+                st, cyc, rr, _ = S.solve(u, f, rtol=args.rtol, max_cycles=60)
+                assert st == 0 and rr <= args.rtol, (st, rr)
+                cyc_tot += cyc
+                if mode == "learned":
+                    a, b, c, d = S.net_stats()
+                    used_tot, off_tot = used_tot + a, off_tot + b
+                    qn.append(c)
+                    qp.append(d)
+            torch.cuda.synchronize()
+            d = {"ms_per_problem": round(1e3 * (time.perf_counter() - t0) / len(fs), 3), "cycles_total": cyc_tot}
+            if mode == "learned":
+                d.update({"net_cycles": used_tot, "judge_switched_off": off_tot,
+                          "first_cycle_cut_ratio_net_median": float(sorted(qn)[len(qn) // 2]),
+                          "first_cycle_cut_ratio_plain_median": float(sorted(qp)[len(qp) // 2])})
+            out[mode] = d
+            S.close()
+        out["learned_speedup"] = round(out["plain"]["ms_per_problem"] / out["learned"]["ms_per_problem"], 3)
+        log("  learned 3D %s: plain %.3f ms (%d cycles), learned %.3f ms (%d cycles), net on %d cycles, judge off %d/8"
+            % (pname, out["plain"]["ms_per_problem"], out["plain"]["cycles_total"], out["learned"]["ms_per_problem"],
                out["learned"]["cycles_total"], out["learned"]["net_cycles"], out["learned"]["judge_switched_off"]))
         res[pname] = out
     del fs
@@ -327,6 +388,8 @@ def main():
         extra["batched512"] = bench_batched(dmg, workloads, dev, torch, args)
         if w_net is not None:
             extra["learned1025"] = bench_learned(dmg, learned, dev, torch, args, w_net, net_info)
+            log("learned coarse correction in 3D: pairs, training, held-out solves")
+            extra["learned129_3d"] = bench_learned3d(dmg, learned, dev, torch, args)
         extra["cube257"] = bench_cube(dmg, workloads, dev, torch, args)
 
     cpu = None
