@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(kRowBlock) kb_resid(int m, double inv_h2, cons
     auto ldf = [&](int j, double& x, double& y) {
         x = y = 0;
         if (!colok || j < 1 || j > m - 1) return;
-        P2<double> v = *reinterpret_cast<const P2<double>*>(f + (size_t)j * w + 2 * t);
+        P2<double> v = ld_pair_nt(f + (size_t)j * w + 2 * t);
         x = v.x; y = v.y;
     };
     struct Ck { double ux[CH], uy[CH], fx[CH], fy[CH]; };
@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(kRowBlock) kb_resid(int m, double inv_h2, cons
             T r1j = (rowin && c1) ? (T)x1 : T(0);
             if (j >= y0 && j < y1 && useful) {
                 T* p = r0 + (size_t)j * w + 2 * t;
-                if (c0 && c1) { *reinterpret_cast<P2<T>*>(p) = P2<T>{r0j, r1j}; acc += x0 * x0 + x1 * x1; }
+                if (c0 && c1) { st_pair_nt(p, r0j, r1j); acc += x0 * x0 + x1 * x1; }
                 else if (c1) { p[1] = r1j; acc += x1 * x1; }
                 else if (c0) { p[0] = r0j; acc += x0 * x0; }
             }
@@ -178,7 +178,7 @@ __device__ inline void jaxis_body(int m, T cc, const T* __restrict__ rA, const T
     auto ldR = [&](int j, T& x, T& y) {
         x = y = 0;
         if (!colok || j < 1 || j > m - 1) return;
-        P2<T> v = *reinterpret_cast<const P2<T>*>(rA + (size_t)j * w + 2 * t);
+        P2<T> v = FINEST ? ld_pair_nt(rA + (size_t)j * w + 2 * t) : *reinterpret_cast<const P2<T>*>(rA + (size_t)j * w + 2 * t);
         x = c0 ? v.x : T(0);
         y = c1 ? v.y : T(0);
     };

@@ -81,4 +81,24 @@ void launch_jac2_rows(int diag, int m, T c, const T* r, const T* vc, T* v, const
 template <typename T>
 void launch_jac2_finest_rows(int n, T c, const T* r0, const T* vD, double* u, const Ctl* ctl, hipStream_t s);
 
+
+// Streaming pair accesses for arrays that are not reused before the cache
+// would evict them anyway (f, and r0 between the residual and the finest
+// Jacobi): non-temporal hints keep them from displacing u and the level
+// arrays the next kernels read.
+template <typename T>
+__device__ inline P2<T> ld_pair_nt(const T* p)
+{
+    typedef T V __attribute__((ext_vector_type(2)));
+    V v = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+    return P2<T>{v.x, v.y};
+}
+template <typename T>
+__device__ inline void st_pair_nt(T* p, T x, T y)
+{
+    typedef T V __attribute__((ext_vector_type(2)));
+    V v = {x, y};
+    __builtin_nontemporal_store(v, reinterpret_cast<V*>(p));
+}
+
 }  // namespace dmg
