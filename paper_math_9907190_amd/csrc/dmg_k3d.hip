@@ -402,6 +402,162 @@ __global__ void __launch_bounds__(kPlThreads) k3_red_planes(int m, T c1, T c2, c
     }
 }
 
+// ------------------------------------------ residual fused with green -> red
+// r = f - Lap_h(u) (Eq. Evpois, 7-point, in double, stored as T) on the
+// finest green grid, its squared norm, and Eq. (Erred) onto the red grid of
+// the same side, in one pass.  A workgroup marches an (x, y) tile through a
+// chunk of z planes: planes of u (tile plus a two-point halo) go through a
+// ring of three LDS planes, the residual of each plane (tile plus a
+// one-point halo) through a second ring, and the red points of the plane
+// behind read their seven residuals from LDS.  The next plane's u and f are
+// loaded while the current one is processed.
+constexpr int kRsUW = kPlTX + 4, kRsUH = kPlTY + 4;   // u region
+constexpr int kRsRW = kPlTX + 2, kRsRH = kPlTY + 2;   // residual region
+constexpr int kRsUS = (kRsUW * kRsUH + kPlThreads - 1) / kPlThreads;
+constexpr int kRsFS = (kRsRW * kRsRH + kPlThreads - 1) / kPlThreads;
+
+template <typename T>
+__global__ void __launch_bounds__(kPlThreads) k3_resid_planes(int n, double inv_h2, const double* __restrict__ u,
+                                                               const double* __restrict__ f, T* __restrict__ r0,
+                                                               T* __restrict__ rR, double* __restrict__ partial,
+                                                               int ntx, int nty, int zc, const Ctl* ctl)
+{
+    DMG_GATE(ctl);
+    __shared__ double U[3][kRsUW * kRsUH];
+    __shared__ T Rr[3][kRsRW * kRsRH];
+    __shared__ double red[kPlThreads / 64];
+    const int bid = blockIdx.x;
+    const int tx = bid % ntx, ty = (bid / ntx) % nty, tz = bid / (ntx * nty);
+    const int x0 = 1 + tx * kPlTX, y0 = 1 + ty * kPlTY, z0 = 1 + tz * zc;
+    const int z1 = min(z0 + zc, n);
+    const int tid = threadIdx.x;
+    auto uload = [&](int c, int i) -> double {
+        const int p = tid + i * kPlThreads;
+        if (p >= kRsUW * kRsUH) return 0.0;
+        const int a = x0 - 2 + p % kRsUW, b = y0 - 2 + p / kRsUW;
+        if (a < 0 || a > n || b < 0 || b > n || c < 0 || c > n) return 0.0;
+        return u[idxG(n, a, b, c)];
+    };
+    auto fload = [&](int c, int i) -> double {
+        const int p = tid + i * kPlThreads;
+        if (p >= kRsRW * kRsRH) return 0.0;
+        const int a = x0 - 1 + p % kRsRW, b = y0 - 1 + p / kRsRW;
+        if (a < 1 || a >= n || b < 1 || b >= n || c < 1 || c >= n) return 0.0;
+        return __builtin_nontemporal_load(f + idxG(n, a, b, c));
+    };
+    // u planes z0-2 and z0-1 into LDS; registers: u of plane z0, f of plane z0-1
+    {
+        double a0[kRsUS], a1[kRsUS];
+#pragma unroll
+        for (int i = 0; i < kRsUS; i++) { a0[i] = uload(z0 - 2, i); a1[i] = uload(z0 - 1, i); }
+#pragma unroll
+        for (int i = 0; i < kRsUS; i++) {
+            const int p = tid + i * kPlThreads;
+            if (p < kRsUW * kRsUH) { U[(z0 + 1) % 3][p] = a0[i]; U[(z0 + 2) % 3][p] = a1[i]; }
+        }
+    }
+    double un[kRsUS], fn[kRsFS];
+#pragma unroll
+    for (int i = 0; i < kRsUS; i++) un[i] = uload(z0, i);
+#pragma unroll
+    for (int i = 0; i < kRsFS; i++) fn[i] = fload(z0 - 1, i);
+    double acc = 0;
+    for (int c = z0 - 1; c <= z1; c++) {
+        double* Up = U[(c + 1) % 3];   // plane c+1
+#pragma unroll
+        for (int i = 0; i < kRsUS; i++) {
+            const int p = tid + i * kPlThreads;
+            if (p < kRsUW * kRsUH) Up[p] = un[i];
+        }
+        double fc[kRsFS];
+#pragma unroll
+        for (int i = 0; i < kRsFS; i++) fc[i] = fn[i];
+        if (c + 1 <= z1) {
+#pragma unroll
+            for (int i = 0; i < kRsUS; i++) un[i] = uload(c + 2, i);
+#pragma unroll
+            for (int i = 0; i < kRsFS; i++) fn[i] = fload(c + 1, i);
+        }
+        __syncthreads();
+        const double* Um = U[(c + 2) % 3];   // plane c-1
+        const double* U0 = U[c % 3];
+        const double* Uq = U[(c + 1) % 3];
+        T* Rp = Rr[c % 3];
+#pragma unroll
+        for (int i = 0; i < kRsFS; i++) {
+            const int p = tid + i * kPlThreads;
+            if (p >= kRsRW * kRsRH) continue;
+            const int lx = p % kRsRW, ly = p / kRsRW;
+            const int a = x0 - 1 + lx, b = y0 - 1 + ly;
+            const bool in = a >= 1 && a < n && b >= 1 && b < n && c >= 1 && c < n;
+            T rt = T(0);
+            if (in) {
+                const int l = (ly + 1) * kRsUW + (lx + 1);
+                double lap = (U0[l + 1] + U0[l - 1] + U0[l + kRsUW] + U0[l - kRsUW] + Uq[l] + Um[l] - 6 * U0[l]) * inv_h2;
+                double r = fc[i] - lap;
+                rt = (T)r;
+                if (lx >= 1 && lx <= kPlTX && ly >= 1 && ly <= kPlTY && c >= z0 && c < z1) {
+                    __builtin_nontemporal_store(rt, r0 + idxG(n, a, b, c));
+                    acc += r * r;
+                }
+            }
+            Rp[p] = rt;
+        }
+        __syncthreads();
+        const int co = c - 1;
+        if (co >= z0) {
+            const T* Rm = Rr[(co + 2) % 3];
+            const T* R0 = Rr[co % 3];
+            const T* Rq = Rr[c % 3];
+            const int ly = tid / (kPlTX / 2), k = tid % (kPlTX / 2);
+            const int b = y0 + ly;
+            const int a = x0 + ((x0 + b + co) & 1) + 2 * k;   // the red point (a+b+co even) of pair k
+            if (b < n && a < n) {
+                const int l = (ly + 1) * kRsRW + (a - x0 + 1);
+                T sum = 6 * R0[l] + R0[l + 1] + R0[l - 1] + R0[l + kRsRW] + R0[l - kRsRW] + Rq[l] + Rm[l];
+                rR[idxR(n, a, b, co)] = sum * (T(1) / T(12));
+            }
+        }
+    }
+    // block sum of the squared residual, one partial per workgroup
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o);
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0;
+        for (int w = 0; w < kPlThreads / 64; w++) t += red[w];
+        partial[blockIdx.x] = t;
+    }
+}
+
+inline void resid3_grid(int n, int& ntx, int& nty, int& zc, int& nb)
+{
+    ntx = (n - 1 + kPlTX - 1) / kPlTX;
+    nty = (n - 1 + kPlTY - 1) / kPlTY;
+    zc = 8;
+    nb = ntx * nty * ((n - 1 + zc - 1) / zc);
+}
+
+// number of norm partials the fused kernel writes (0: not used at this size)
+int resid3_fused_parts(int n)
+{
+    if (n < 128) return 0;
+    int ntx, nty, zc, nb;
+    resid3_grid(n, ntx, nty, zc, nb);
+    return nb;
+}
+
+template <typename T>
+void launch_resid3_fused(int n, const double* u, const double* f, T* r0, T* rR, double* partial, const Ctl* ctl,
+                         hipStream_t s)
+{
+    int ntx, nty, zc, nb;
+    resid3_grid(n, ntx, nty, zc, nb);
+    double inv_h2 = (double)n * (double)n;
+    hipLaunchKernelGGL(k3_resid_planes<T>, dim3(nb), dim3(kPlThreads), 0, s, n, inv_h2, u, f, r0, rR, partial, ntx,
+                       nty, zc, ctl);
+}
+
 constexpr int kPlMinSide = 128;   // smaller levels: one thread per point
 
 // z planes per workgroup (measured on MI355X at 257^3: 8 is best, longer
@@ -847,7 +1003,8 @@ void launch_level_get3(int kind, int m, const T* src, const T* src2, double* dst
     template void launch_jac3_finest<T>(int, T, const T*, const T*, double*, const Ctl*, hipStream_t);    \
     template void launch_coarse3<T>(const Coarse3<T>&, const Ctl*, hipStream_t);                          \
     template void launch_coarse3_net<T>(const Coarse3<T>&, Ctl*, const bf16_t*, hipStream_t);             \
-    template void launch_level_get3<T>(int, int, const T*, const T*, double*, hipStream_t);
+    template void launch_level_get3<T>(int, int, const T*, const T*, double*, hipStream_t);              \
+    template void launch_resid3_fused<T>(int, const double*, const double*, T*, T*, double*, const Ctl*, hipStream_t);
 DMG_INST3(double)
 DMG_INST3(float)
 

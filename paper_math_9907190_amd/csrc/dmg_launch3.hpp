@@ -169,5 +169,11 @@ template <typename T>
 void launch_coarse3_net(const Coarse3<T>& a, Ctl* ctl, const unsigned short* wf, hipStream_t s);
 template <typename T>
 void launch_level_get3(int kind, int m, const T* src, const T* src2, double* dst, hipStream_t s);
+// residual of the finest green grid fused with Eq. (Erred) onto the red grid of
+// the same side (n >= 128); writes resid3_fused_parts(n) norm partials
+int resid3_fused_parts(int n);
+template <typename T>
+void launch_resid3_fused(int n, const double* u, const double* f, T* r0, T* rR, double* partial, const Ctl* ctl,
+                         hipStream_t s);
 
 }  // namespace dmg

@@ -8,6 +8,7 @@
 #include "dmg_net.hpp"
 #include "dmg_plan3d.hpp"
 
+#include <algorithm>
 #include <string.h>
 #include <vector>
 
@@ -66,7 +67,7 @@ void enqueue_cycle3(Plan3& P, double* u, const Ctl* ctl)
         return x;
     };
     int last_rs = dc ? dc : D;
-    for (int d = 1; d <= last_rs; d++) {
+    for (int d = P.fused_resid ? 2 : 1; d <= last_rs; d++) {   // the fused residual produced level 1
         Timed t(&P.tm, MG_K_RESTRICT, bytes_rs3(P.lev[d].kind, P.lev[d - 1].m, es));
         launch_rs3<T>(lv(d - 1), lv(d), ctl, s);
     }
@@ -103,15 +104,23 @@ void enqueue_residual(Plan3& P, const double* u, const double* f, const Ctl* ctl
 {
     bool dbl = P.prec == MG_FP64;
     double* part = at<double>(P, P.partial);
-    Timed t(&P.tm, MG_K_RESIDUAL, bytes_resid3(P.n, dbl ? 8 : 4));
+    size_t es = dbl ? 8 : 4;
+    if (P.fused_resid) {
+        Timed t(&P.tm, MG_K_RESIDUAL, bytes_resid3(P.n, es) + es * (double)sizeR(P.n) / 2);
+        if (dbl) launch_resid3_fused<double>(P.n, u, f, at<double>(P, P.r0), at<double>(P, P.lev[1].r), part, ctl, P.stream);
+        else launch_resid3_fused<float>(P.n, u, f, at<float>(P, P.r0), at<float>(P, P.lev[1].r), part, ctl, P.stream);
+        return;
+    }
+    Timed t(&P.tm, MG_K_RESIDUAL, bytes_resid3(P.n, es));
     if (dbl) launch_residual<double>(3, P.n, u, f, at<double>(P, P.r0), part, P.nparts, ctl, P.stream);
     else launch_residual<float>(3, P.n, u, f, at<float>(P, P.r0), part, P.nparts, ctl, P.stream);
 }
 
 void enqueue_finalize(Plan3& P, int kind, int k, Ctl* ctl)
 {
-    Timed t(&P.tm, MG_K_NORM, 8.0 * P.nparts);
-    launch_finalize(kind, k, at<double>(P, P.partial), P.nparts, ctl, P.stream);
+    const int np = kind == 0 ? P.nparts : P.nparts_res;
+    Timed t(&P.tm, MG_K_NORM, 8.0 * np);
+    launch_finalize(kind, k, at<double>(P, P.partial), np, ctl, P.stream);
 }
 
 }  // namespace
@@ -135,7 +144,9 @@ int plan3_layout(Plan3& P, int n, int prec, const double* p)
     };
     P.ctl = take(sizeof(Ctl));
     P.nparts = residual_parts(3, n);
-    P.partial = take(sizeof(double) * (size_t)P.nparts);
+    P.fused_resid = resid3_fused_parts(n) > 0;
+    P.nparts_res = P.fused_resid ? resid3_fused_parts(n) : P.nparts;
+    P.partial = take(sizeof(double) * (size_t)std::max(P.nparts, P.nparts_res));
     P.zero = take(sizeof(double) * 64);
     P.r0 = take(es * sizeG(n));
     P.net = take(sizeof(bf16_t) * (size_t)NetGeo<3>::PACK);

@@ -19,7 +19,9 @@ struct Plan3 {
     double p[4] = {1, 1, 1, 1};
     size_t ctl = 0, partial = 0, zero = 0, r0 = 0, net = 0, total = 0;
     bool has_net = false;   // learned coarse correction set (packed bf16 weights at net)
-    int nparts = 0;
+    int nparts = 0;         // norm partials of ||f|| (and of the residual when not fused)
+    int nparts_res = 0;     // norm partials of the residual
+    bool fused_resid = false;   // residual fused with the first restriction (n >= 128)
     Level3 lev[kMaxLev3];
     char* ws = nullptr;
     hipStream_t stream = nullptr;
