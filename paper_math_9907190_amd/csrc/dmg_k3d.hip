@@ -558,6 +558,128 @@ void launch_resid3_fused(int n, const double* u, const double* f, T* r0, T* rR, 
                        nty, zc, ctl);
 }
 
+// ---- magenta of side m, Eqs. (Emprolm), (Emprolb), in half indices (A,B,C):
+// cube centres (2A+1, 2B+1, 2C+1), 0 <= A,B,C < m/2, from the blue grid (the
+// green grid of side m/2), then interior corners (2A, 2B, 2C) from the eight
+// new centres around them.  A workgroup marches a tile of centres (plus one
+// centre of halo below in A and B) through a chunk of C planes; the corner
+// plane C reads centre planes C-1 and C from a ring of two LDS planes.
+constexpr int kMgTX = 32, kMgW = kMgTX + 1, kMgH = kPlTY + 1;
+
+template <typename T>
+struct MgIn {
+    T r, b0, b1, b2, b3, b4, b5, b6, b7;
+    int pos;   // LDS position; -1: no centre
+    bool ok;
+};
+
+template <typename T>
+__device__ inline MgIn<T> mag_fload(const T* __restrict__ rO, const T* __restrict__ vB, int m, int A0, int B0, int C,
+                                    int p)
+{
+    MgIn<T> q;
+    q.pos = -1;
+    q.ok = false;
+    q.r = q.b0 = q.b1 = q.b2 = q.b3 = q.b4 = q.b5 = q.b6 = q.b7 = T(0);
+    if (p >= kMgW * kMgH) return q;
+    q.pos = p;
+    const int h = m / 2;
+    const int A = A0 - 1 + p % kMgW, B = B0 - 1 + p / kMgW;
+    if (A < 0 || A >= h || B < 0 || B >= h || C < 0 || C >= h) return q;
+    q.ok = true;
+    const size_t w = (size_t)(h + 1), w2 = w * w;
+    const size_t o = idxG(h, A, B, C);
+    q.r = rO[idxMO(m, 2 * A + 1, 2 * B + 1, 2 * C + 1)];
+    q.b0 = vB[o + 1 + w + w2];
+    q.b1 = vB[o + 1 + w];
+    q.b2 = vB[o + 1 + w2];
+    q.b3 = vB[o + 1];
+    q.b4 = vB[o + w + w2];
+    q.b5 = vB[o + w];
+    q.b6 = vB[o + w2];
+    q.b7 = vB[o];
+    return q;
+}
+
+// same arithmetic and order as jac3_magF
+template <typename T>
+__device__ inline T mag_fcomp(const MgIn<T>& q, T cc)
+{
+    if (!q.ok) return T(0);
+    return (-cc * q.r + q.b0 + q.b1 + q.b2 + q.b3 + q.b4 + q.b5 + q.b6 + q.b7) * T(0.125);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kPlThreads) k3_mag_planes(int m, T cc, const T* __restrict__ rE,
+                                                             const T* __restrict__ rO, const T* __restrict__ vB,
+                                                             T* __restrict__ vE, T* __restrict__ vO, int ntx, int nty,
+                                                             int zc, const Ctl* ctl)
+{
+    DMG_GATE(ctl);
+    constexpr int W = kMgW, NP = (kMgW * kMgH + kPlThreads - 1) / kPlThreads, NO = kMgTX * kPlTY / kPlThreads;
+    __shared__ T F[2][kMgW * kMgH];
+    const int h = m / 2;
+    const int bid = blockIdx.x;
+    const int tx = bid % ntx, ty = (bid / ntx) % nty, tz = bid / (ntx * nty);
+    const int A0 = tx * kMgTX, B0 = ty * kPlTY, C0 = tz * zc;
+    const int C1 = min(C0 + zc, h);   // centre planes [C0, C1) and corner planes [C0, C1) are output
+    const int tid = threadIdx.x;
+    MgIn<T> nx[NP];
+#pragma unroll
+    for (int j = 0; j < NP; j++) nx[j] = mag_fload(rO, vB, m, A0, B0, C0 - 1, tid + j * kPlThreads);
+    T rn[NO];
+#pragma unroll
+    for (int k = 0; k < NO; k++) rn[k] = T(0);
+    for (int C = C0 - 1; C < C1; C++) {
+        MgIn<T> cur[NP];
+        T rc[NO];
+#pragma unroll
+        for (int j = 0; j < NP; j++) cur[j] = nx[j];
+#pragma unroll
+        for (int k = 0; k < NO; k++) rc[k] = rn[k];
+        if (C + 1 < C1) {
+#pragma unroll
+            for (int j = 0; j < NP; j++) nx[j] = mag_fload(rO, vB, m, A0, B0, C + 1, tid + j * kPlThreads);
+        }
+        if (C + 1 >= C0 && C + 1 < C1) {   // corners of plane C+1 need rE next iteration
+#pragma unroll
+            for (int k = 0; k < NO; k++) {
+                const int e = tid + k * kPlThreads;
+                const int A = A0 + e % kMgTX, B = B0 + e / kMgTX;
+                if (A >= 1 && A < h && B >= 1 && B < h && C + 1 >= 1 && C + 1 < h)
+                    rn[k] = rE[idxME(m, 2 * A, 2 * B, 2 * (C + 1))];
+            }
+        }
+        T* Fp = F[(C + 2) & 1];   // plane C (C >= -1)
+#pragma unroll
+        for (int j = 0; j < NP; j++) {
+            if (cur[j].pos < 0) continue;
+            const T v = mag_fcomp(cur[j], cc);
+            Fp[cur[j].pos] = v;
+            const int p = cur[j].pos;
+            const int A = A0 - 1 + p % W, B = B0 - 1 + p / W;
+            if (cur[j].ok && C >= C0 && A >= A0 && A < A0 + kMgTX && B >= B0 && B < B0 + kPlTY)
+                vO[idxMO(m, 2 * A + 1, 2 * B + 1, 2 * C + 1)] = v;
+        }
+        __syncthreads();
+        if (C >= C0 && C >= 1) {   // corner plane C from centre planes C-1 and C
+            const T* Fm = F[(C + 1) & 1];
+            const T* F0 = F[(C + 2) & 1];
+#pragma unroll
+            for (int k = 0; k < NO; k++) {
+                const int e = tid + k * kPlThreads;
+                const int A = A0 + e % kMgTX, B = B0 + e / kMgTX;
+                if (A < 1 || A >= h || B < 1 || B >= h) continue;
+                const int l = (B - B0 + 1) * W + (A - A0 + 1);   // centre (A, B); (A-1) is l-1, (B-1) is l-W
+                // the eight centres in the order of Eq. (Emprolb) as jac3_magC sums them
+                T s = F0[l] + Fm[l] + F0[l - W] + Fm[l - W] + F0[l - 1] + Fm[l - 1] + F0[l - W - 1] + Fm[l - W - 1];
+                vE[idxME(m, 2 * A, 2 * B, 2 * C)] = (-cc * rc[k] + s) * T(0.125);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 constexpr int kPlMinSide = 128;   // smaller levels: one thread per point
 
 // z planes per workgroup (measured on MI355X at 257^3: 8 is best, longer
@@ -570,8 +692,15 @@ void launch_jac3(const Lev3<T>& L, const Lev3<T>& Cr, T* zero, const Ctl* ctl, h
     int m = L.m;
     const T* vc = Cr.v ? Cr.v : zero;
     if (L.kind == 2) {
-        dim3 g((m / 2 + 255) / 256, m / 2, m / 2);
-        hipLaunchKernelGGL(k3_jac_mag<T>, g, dim3(256), 0, s, m, L.c, L.r, L.r2, vc, L.v, L.v2, ctl);
+        if (m >= 2 * kPlMinSide) {   // at side 128 the 64^3 centres give too few workgroups (measured slower)
+            int h = m / 2, ntx = (h + kMgTX - 1) / kMgTX, nty = (h + kPlTY - 1) / kPlTY, zc = pl_zchunk(m);
+            int ntz = (h + zc - 1) / zc;
+            hipLaunchKernelGGL(k3_mag_planes<T>, dim3(ntx * nty * ntz), dim3(kPlThreads), 0, s, m, L.c, L.r, L.r2, vc,
+                               L.v, L.v2, ntx, nty, zc, ctl);
+        } else {
+            dim3 g((m / 2 + 255) / 256, m / 2, m / 2);
+            hipLaunchKernelGGL(k3_jac_mag<T>, g, dim3(256), 0, s, m, L.c, L.r, L.r2, vc, L.v, L.v2, ctl);
+        }
     } else if (L.kind == 1) {
         if (m >= kPlMinSide) {
             int ntx = (m / 2 + kRdTX - 1) / kRdTX, nty = (m - 1 + kPlTY - 1) / kPlTY, zc = pl_zchunk(m);
