@@ -304,6 +304,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and 3D workloads")
     ap.add_argument("--no-learned", action="store_true", help="skip training and the learned modes")
+    ap.add_argument("--cube-only", action="store_true", help="only the 3D 257^3 workload (for profiling)")
+    ap.add_argument("--batched-only", action="store_true", help="only the 512-problem batched workload")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (calibrates HBM byte counters) and exit")
     args = ap.parse_args()
@@ -326,6 +328,12 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": nb, "copy_probe_bytes_written": nb, "launches": 5}), flush=True)
+        return
+    if args.cube_only:
+        print(json.dumps({"cube257": bench_cube(dmg, workloads, dev, torch, args)}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched512": bench_batched(dmg, workloads, dev, torch, args)}), flush=True)
         return
     n = args.n
     unknowns = (n - 1) ** 2

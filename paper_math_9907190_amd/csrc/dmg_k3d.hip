@@ -6,6 +6,7 @@
 #include "dmg_launch.hpp"
 #include "dmg_launch3.hpp"
 #include "dmg_net_dev.hpp"
+#include "dmg_rows.hpp"
 
 namespace dmg {
 
@@ -155,55 +156,45 @@ constexpr int kPlTX = 64, kPlTY = 8, kPlThreads = 256;
 constexpr int kPlW = kPlTX + 2, kPlH = kPlTY + 2;   // tile plus a one-point halo
 constexpr int kRdTX = 32, kRdW = kRdTX + 2;        // red tiles: 32 slots (64 x positions) wide
 
-// Inputs of one first-half-sweep value, loaded one plane ahead of its use.
-template <typename T>
-struct PlIn {
-    T r, n0, n1, n2, n3, n4, n5;
-    int pos;   // LDS position; -1: no point
-    bool ok;   // interior point (else the value is 0)
-};
+// ---- green: F points (a+b+c odd), Eq. (Egprolg).  The red grid is staged
+// plane by plane in LDS over the tile plus a two-point halo: row (b, c) of
+// the red grid holds a = 2s + ((b+c)&1) at slot s, so the 35 slots from
+// s = (x0-3)/2 cover a in [x0-2, x0+65] for either parity and load as one
+// contiguous run; each red value is then loaded once instead of once per
+// F neighbour.
+constexpr int kGrRS = 35, kGrRH = kPlTY + 4;                    // red LDS plane: rows y0-2 .. y0+9
+constexpr int kGrRN = kGrRS * kGrRH;
+constexpr int kGrRP = (kGrRN + kPlThreads - 1) / kPlThreads;   // red slots per thread
+constexpr int kGrFR = kPlW / 2;                                  // F points per extended tile row
+constexpr int kGrFN = kPlH * kGrFR;
+constexpr int kGrFP = (kGrFN + kPlThreads - 1) / kPlThreads;   // F points per thread
 
-// ---- green: F points (a+b+c odd), Eq. (Egprolg)
+// red value e of the staged plane c (0 outside the grid)
 template <typename T>
-__device__ inline PlIn<T> green_fload(const T* __restrict__ rG, const T* __restrict__ vR, int m, int x0, int y0,
-                                      int c, int i)
+__device__ inline T green_rload(const T* __restrict__ vR, int m, int x0, int y0, int c, int e)
 {
-    PlIn<T> q;
-    q.pos = -1;
-    q.ok = false;
-    q.r = q.n0 = q.n1 = q.n2 = q.n3 = q.n4 = q.n5 = T(0);
-    constexpr int NR = kPlW / 2;   // F points per tile row
-    if (i >= kPlH * NR) return q;
-    const int ly = i / NR, j = i % NR;
-    const int b = y0 - 1 + ly, a0 = x0 - 1;
-    const int a = a0 + ((a0 + b + c + 1) & 1) + 2 * j;
-    q.pos = ly * kPlW + (a - a0);
-    if (a <= 0 || a >= m || b <= 0 || b >= m || c <= 0 || c >= m) return q;
-    q.ok = true;
-    q.r = rG[idxG(m, a, b, c)];
-    q.n0 = vR[idxR(m, a + 1, b, c)];
-    q.n1 = vR[idxR(m, a - 1, b, c)];
-    q.n2 = vR[idxR(m, a, b + 1, c)];
-    q.n3 = vR[idxR(m, a, b - 1, c)];
-    q.n4 = vR[idxR(m, a, b, c + 1)];
-    q.n5 = vR[idxR(m, a, b, c - 1)];
-    return q;
+    if (e >= kGrRN) return T(0);
+    const int b = y0 - 2 + e / kGrRS, s = (x0 - 3) / 2 + e % kGrRS;
+    const int a = 2 * s + ((b + c) & 1);
+    if (a < 0 || a > m || b < 0 || b > m || c < 0 || c > m) return T(0);
+    return vR[idxR(m, a, b, c)];
 }
 
-// same arithmetic and order as jac3_greenF
-template <typename T>
-__device__ inline T green_fcomp(const PlIn<T>& q, T cc)
+// F point e of the extended tile plane c: (a, b) and whether it is interior
+__device__ inline bool green_fpoint(int m, int x0, int y0, int c, int e, int& a, int& b)
 {
-    if (!q.ok) return T(0);
-    T s = q.n0 + q.n1 + q.n2 + q.n3 + q.n4 + q.n5;
-    return (-cc * q.r + s) * (T(1) / T(6));
+    const int ly = e / kGrFR, j = e % kGrFR;
+    b = y0 - 1 + ly;
+    a = x0 - 1 + ((x0 + b + c) & 1) + 2 * j;
+    return a > 0 && a < m && b > 0 && b < m && c > 0 && c < m;
 }
 
 // Green grid of side m, Eqs. (Egprolg), (Egprolr): F points from the red
 // grid vR, then C points (a+b+c even) from the six new F values.  FINEST
-// adds the correction to u instead of storing it.  Each thread owns two
-// F-value slots of the extended tile plane and the x pair (2t, 2t+1) of
-// one output row.
+// adds the correction to u instead of storing it.  Per plane c a thread
+// stages red slots of plane c+1, computes F values of plane c (tile plus a
+// one-point halo) into a second ring, and then the x pair (2t, 2t+1) of one
+// output row of plane c-1; the inputs of the next plane are loaded meanwhile.
 template <typename T, bool FINEST>
 __global__ void __launch_bounds__(kPlThreads) k3_green_planes(int m, T cc, const T* __restrict__ rG,
                                                                const T* __restrict__ vR, T* __restrict__ vG,
@@ -213,7 +204,8 @@ __global__ void __launch_bounds__(kPlThreads) k3_green_planes(int m, T cc, const
     DMG_GATE(ctl);
     constexpr int W = kPlW;
     __shared__ T F[3][kPlH * kPlW];
-    const int bid = blockIdx.x;
+    __shared__ T R[3][kGrRN];
+    const int bid = xcd_block();   // tiles of one die are neighbours
     const int tx = bid % ntx, ty = (bid / ntx) % nty, tz = bid / (ntx * nty);
     const int x0 = 1 + tx * kPlTX, y0 = 1 + ty * kPlTY, z0 = 1 + tz * zc;
     const int z1 = min(z0 + zc, m);   // output planes [z0, z1)
@@ -221,18 +213,47 @@ __global__ void __launch_bounds__(kPlThreads) k3_green_planes(int m, T cc, const
     const int oly = tid / (kPlTX / 2), opr = tid % (kPlTX / 2);
     const int ob = y0 + oly, oa = x0 + 2 * opr;
     const bool orow = ob < m;
-    // prologue: inputs of plane z0 - 1
-    PlIn<T> n0 = green_fload(rG, vR, m, x0, y0, z0 - 1, tid);
-    PlIn<T> n1 = green_fload(rG, vR, m, x0, y0, z0 - 1, tid + kPlThreads);
+    // prologue: red planes z0-2 and z0-1 into LDS; red plane z0 and the F
+    // residuals of plane z0-1 into registers (ring slot of plane c: (c+3)%3)
+    T rr[kGrRP], rf[kGrFP];
+#pragma unroll
+    for (int i = 0; i < kGrRP; i++) {
+        const int e = tid + i * kPlThreads;
+        const T a0 = green_rload(vR, m, x0, y0, z0 - 2, e), a1 = green_rload(vR, m, x0, y0, z0 - 1, e);
+        if (e < kGrRN) {
+            R[(z0 + 1) % 3][e] = a0;
+            R[(z0 + 2) % 3][e] = a1;
+        }
+        rr[i] = green_rload(vR, m, x0, y0, z0, e);
+    }
+#pragma unroll
+    for (int i = 0; i < kGrFP; i++) {
+        const int e = tid + i * kPlThreads;
+        int a, b;
+        rf[i] = (e < kGrFN && green_fpoint(m, x0, y0, z0 - 1, e, a, b)) ? rG[idxG(m, a, b, z0 - 1)] : T(0);
+    }
     double un0 = 0, un1 = 0;
     T rn = T(0);
     for (int c = z0 - 1; c <= z1; c++) {
-        const PlIn<T> f0 = n0, f1 = n1;
+#pragma unroll
+        for (int i = 0; i < kGrRP; i++) {   // red plane c+1
+            const int e = tid + i * kPlThreads;
+            if (e < kGrRN) R[(c + 4) % 3][e] = rr[i];
+        }
+        T rfc[kGrFP];
+#pragma unroll
+        for (int i = 0; i < kGrFP; i++) rfc[i] = rf[i];
         const double uc0 = un0, uc1 = un1;
         const T rc = rn;
-        if (c + 1 <= z1) {   // next plane's F inputs
-            n0 = green_fload(rG, vR, m, x0, y0, c + 1, tid);
-            n1 = green_fload(rG, vR, m, x0, y0, c + 1, tid + kPlThreads);
+        if (c + 1 <= z1) {   // next plane's inputs
+#pragma unroll
+            for (int i = 0; i < kGrRP; i++) rr[i] = green_rload(vR, m, x0, y0, c + 2, tid + i * kPlThreads);
+#pragma unroll
+            for (int i = 0; i < kGrFP; i++) {
+                const int e = tid + i * kPlThreads;
+                int a, b;
+                rf[i] = (e < kGrFN && green_fpoint(m, x0, y0, c + 1, e, a, b)) ? rG[idxG(m, a, b, c + 1)] : T(0);
+            }
         }
         if (c >= z0 && c < z1 && orow) {   // this plane's output inputs, used next iteration
             const int aC = oa + ((oa + ob + c) & 1);   // the C point of the pair
@@ -242,9 +263,30 @@ __global__ void __launch_bounds__(kPlThreads) k3_green_planes(int m, T cc, const
                 if (oa + 1 < m) un1 = u[idxG(m, oa + 1, ob, c)];
             }
         }
-        T* Fp = F[c % 3];
-        if (f0.pos >= 0) Fp[f0.pos] = green_fcomp(f0, cc);
-        if (f1.pos >= 0) Fp[f1.pos] = green_fcomp(f1, cc);
+        __syncthreads();
+        {   // F values of plane c, same arithmetic and order as jac3_greenF
+            const T* Rm = R[(c + 2) % 3];
+            const T* R0 = R[c % 3];
+            const T* Rq = R[(c + 1) % 3];
+            T* Fp = F[c % 3];
+#pragma unroll
+            for (int i = 0; i < kGrFP; i++) {
+                const int e = tid + i * kPlThreads;
+                if (e >= kGrFN) continue;
+                int a, b;
+                const bool ok = green_fpoint(m, x0, y0, c, e, a, b);
+                T v = T(0);
+                if (ok) {
+                    const int ly = b - y0 + 2, k = (a - x0 + 3) >> 1;   // red row and slot of (a, b)
+                    const int l = ly * kGrRS + k;
+                    const T n0 = R0[ly * kGrRS + ((a - x0 + 4) >> 1)];   // (a+1, b, c)
+                    const T n1 = R0[ly * kGrRS + ((a - x0 + 2) >> 1)];   // (a-1, b, c)
+                    T s = n0 + n1 + R0[l + kGrRS] + R0[l - kGrRS] + Rq[l] + Rm[l];
+                    v = (-cc * rfc[i] + s) * (T(1) / T(6));
+                }
+                Fp[(b - y0 + 1) * W + (a - x0 + 1)] = v;
+            }
+        }
         __syncthreads();
         const int co = c - 1;
         if (co >= z0 && orow) {
@@ -273,55 +315,35 @@ __global__ void __launch_bounds__(kPlThreads) k3_green_planes(int m, T cc, const
 
 // ---- red: face centres (two odd indices), Eq. (Erprolr) and its cyclic
 // permutations; corners (all even), Eq. (Erprolm).  Tiles are in R-layout
-// slots: slot s of row (b, c) is the point a = 2s + ((b+c)&1).
+// slots: slot s of row (b, c) is the point a = 2s + ((b+c)&1).  The magenta
+// grid is staged plane by plane in LDS: plane c holds the corners (c even)
+// or the cube centres (c odd) at half indices (a>>1, b>>1), over the tile
+// plus a one-point halo (36 x 7 values), so each magenta value is loaded
+// once; face centres read their six magenta neighbours from there.
+constexpr int kMsW = kRdTX + 4, kMsH = kPlTY / 2 + 3, kMsN = kMsW * kMsH;
+static_assert(kMsN <= kPlThreads, "one staged magenta value per thread");
+
+// staged magenta value e of plane c (0 outside the grid)
 template <typename T>
-__device__ inline PlIn<T> red_fload(const T* __restrict__ rR, const T* __restrict__ vE, const T* __restrict__ vO,
-                                    int m, int s0, int y0, int c, int p)
+__device__ inline T red_mload(const T* __restrict__ vE, const T* __restrict__ vO, int m, int s0, int y0, int c, int e)
 {
-    PlIn<T> q;
-    q.pos = -1;
-    q.ok = false;
-    q.r = q.n0 = q.n1 = q.n2 = q.n3 = q.n4 = q.n5 = T(0);
-    if (p >= kPlH * kRdW) return q;
-    const int b = y0 - 1 + p / kRdW, sl = s0 - 1 + p % kRdW;
-    const int a = 2 * sl + ((b + c) & 1);
-    if ((a & 1) + (b & 1) + (c & 1) != 2) return q;   // corners are not first-half-sweep points
-    q.pos = p;
-    if (a < 1 || a >= m || b < 1 || b >= m || c < 1 || c >= m) return q;
-    q.ok = true;
-    q.r = rR[idxR(m, a, b, c)];
-    if (!(c & 1)) {
-        q.n0 = vO[idxMO(m, a, b, c + 1)];
-        q.n1 = vO[idxMO(m, a, b, c - 1)];
-        q.n2 = vE[idxME(m, a + 1, b + 1, c)];
-        q.n3 = vE[idxME(m, a + 1, b - 1, c)];
-        q.n4 = vE[idxME(m, a - 1, b - 1, c)];
-        q.n5 = vE[idxME(m, a - 1, b + 1, c)];
-    } else if (!(a & 1)) {
-        q.n0 = vO[idxMO(m, a + 1, b, c)];
-        q.n1 = vO[idxMO(m, a - 1, b, c)];
-        q.n2 = vE[idxME(m, a, b + 1, c + 1)];
-        q.n3 = vE[idxME(m, a, b + 1, c - 1)];
-        q.n4 = vE[idxME(m, a, b - 1, c - 1)];
-        q.n5 = vE[idxME(m, a, b - 1, c + 1)];
-    } else {
-        q.n0 = vO[idxMO(m, a, b + 1, c)];
-        q.n1 = vO[idxMO(m, a, b - 1, c)];
-        q.n2 = vE[idxME(m, a + 1, b, c + 1)];
-        q.n3 = vE[idxME(m, a - 1, b, c + 1)];
-        q.n4 = vE[idxME(m, a - 1, b, c - 1)];
-        q.n5 = vE[idxME(m, a + 1, b, c - 1)];
+    if (e >= kMsN) return T(0);
+    const int h = m / 2;
+    const int i = s0 - 2 + e % kMsW, j = (y0 - 1) / 2 - 1 + e / kMsW;
+    if (c & 1) {
+        if (i < 0 || i >= h || j < 0 || j >= h || c < 1 || c >= m) return T(0);
+        return vO[idxMO(m, 2 * i + 1, 2 * j + 1, c)];
     }
-    return q;
+    if (i < 0 || i > h || j < 0 || j > h || c < 0 || c > m) return T(0);
+    return vE[idxME(m, 2 * i, 2 * j, c)];
 }
 
-// same arithmetic and order as jac3_redF
-template <typename T>
-__device__ inline T red_fcomp(const PlIn<T>& q, T cc)
+// face-centre slot p of the extended tile plane c: (a, b); false for corners
+__device__ inline bool red_fpoint(int s0, int y0, int c, int p, int& a, int& b)
 {
-    if (!q.ok) return T(0);
-    T s = 2 * (q.n0 + q.n1) + q.n2 + q.n3 + q.n4 + q.n5;
-    return (-cc * q.r + s) * T(0.125);
+    b = y0 - 1 + p / kRdW;
+    a = 2 * (s0 - 1 + p % kRdW) + ((b + c) & 1);
+    return (a & 1) + (b & 1) + (c & 1) == 2;
 }
 
 template <typename T>
@@ -334,27 +356,50 @@ __global__ void __launch_bounds__(kPlThreads) k3_red_planes(int m, T c1, T c2, c
     constexpr int W = kRdW, NP = (kPlH * kRdW + kPlThreads - 1) / kPlThreads;   // F slots per thread
     constexpr int NO = kPlTY * kRdTX / kPlThreads;                              // outputs per thread
     __shared__ T F[3][kPlH * kRdW];
-    const int bid = blockIdx.x;
+    __shared__ T M[3][kMsN];
+    const int bid = xcd_block();   // tiles of one die are neighbours
     const int tx = bid % ntx, ty = (bid / ntx) % nty, tz = bid / (ntx * nty);
     const int s0 = tx * kRdTX, y0 = 1 + ty * kPlTY, z0 = 1 + tz * zc;
     const int z1 = min(z0 + zc, m);
     const int tid = threadIdx.x;
-    PlIn<T> nx[NP];
+    const int iL = s0 - 2, jL = (y0 - 1) / 2 - 1;   // half indices of staged value 0
+    // F residuals of plane c (0 for corners and points off the interior)
+    auto fload = [&](int c, T (&rf)[NP]) {
 #pragma unroll
-    for (int j = 0; j < NP; j++) nx[j] = red_fload(rR, vE, vO, m, s0, y0, z0 - 1, tid + j * kPlThreads);
+        for (int k = 0; k < NP; k++) {
+            const int p = tid + k * kPlThreads;
+            int a, b;
+            rf[k] = T(0);
+            if (p < kPlH * kRdW && red_fpoint(s0, y0, c, p, a, b) && a >= 1 && a < m && b >= 1 && b < m && c >= 1 &&
+                c < m)
+                rf[k] = rR[idxR(m, a, b, c)];
+        }
+    };
+    // prologue: magenta planes z0-2 and z0-1 into LDS (ring slot of plane c:
+    // (c+3)%3), plane z0 and the F residuals of plane z0-1 into registers
+    {
+        const T a0 = red_mload(vE, vO, m, s0, y0, z0 - 2, tid), a1 = red_mload(vE, vO, m, s0, y0, z0 - 1, tid);
+        if (tid < kMsN) {
+            M[(z0 + 1) % 3][tid] = a0;
+            M[(z0 + 2) % 3][tid] = a1;
+        }
+    }
+    T mn = red_mload(vE, vO, m, s0, y0, z0, tid);
+    T rf[NP];
+    fload(z0 - 1, rf);
     T rn[NO];
 #pragma unroll
     for (int k = 0; k < NO; k++) rn[k] = T(0);
     for (int c = z0 - 1; c <= z1; c++) {
-        PlIn<T> cur[NP];
-        T rc[NO];
+        if (tid < kMsN) M[(c + 4) % 3][tid] = mn;   // magenta plane c+1
+        T rfc[NP], rc[NO];
 #pragma unroll
-        for (int j = 0; j < NP; j++) cur[j] = nx[j];
+        for (int k = 0; k < NP; k++) rfc[k] = rf[k];
 #pragma unroll
         for (int k = 0; k < NO; k++) rc[k] = rn[k];
         if (c + 1 <= z1) {
-#pragma unroll
-            for (int j = 0; j < NP; j++) nx[j] = red_fload(rR, vE, vO, m, s0, y0, c + 1, tid + j * kPlThreads);
+            mn = red_mload(vE, vO, m, s0, y0, c + 2, tid);
+            fload(c + 1, rf);
         }
         if (c >= z0 && c < z1) {   // corners of this plane need rR next iteration
 #pragma unroll
@@ -365,10 +410,36 @@ __global__ void __launch_bounds__(kPlThreads) k3_red_planes(int m, T c1, T c2, c
                 if (b < m && a >= 1 && a < m && ((a | b | c) & 1) == 0) rn[k] = rR[idxR(m, a, b, c)];
             }
         }
-        T* Fp = F[c % 3];
+        __syncthreads();
+        {   // face centres of plane c, same arithmetic and order as jac3_redF
+            const T* Mm = M[(c + 2) % 3];   // plane c-1
+            const T* M0 = M[c % 3];
+            const T* Mq = M[(c + 1) % 3];   // plane c+1
+            T* Fp = F[c % 3];
 #pragma unroll
-        for (int j = 0; j < NP; j++)
-            if (cur[j].pos >= 0) Fp[cur[j].pos] = red_fcomp(cur[j], c1);
+            for (int k = 0; k < NP; k++) {
+                const int p = tid + k * kPlThreads;
+                int a, b;
+                if (p >= kPlH * kRdW || !red_fpoint(s0, y0, c, p, a, b)) continue;
+                T v = T(0);
+                if (a >= 1 && a < m && b >= 1 && b < m && c >= 1 && c < m) {
+                    // staged position of half indices (i, j): (j - jL) * kMsW + (i - iL)
+                    auto at = [&](int aa, int bb) { return ((bb >> 1) - jL) * kMsW + ((aa >> 1) - iL); };
+                    T s;
+                    if (!(c & 1))
+                        s = 2 * (Mq[at(a, b)] + Mm[at(a, b)]) + M0[at(a + 1, b + 1)] + M0[at(a + 1, b - 1)]
+                            + M0[at(a - 1, b - 1)] + M0[at(a - 1, b + 1)];
+                    else if (!(a & 1))
+                        s = 2 * (M0[at(a + 1, b)] + M0[at(a - 1, b)]) + Mq[at(a, b + 1)] + Mm[at(a, b + 1)]
+                            + Mm[at(a, b - 1)] + Mq[at(a, b - 1)];
+                    else
+                        s = 2 * (M0[at(a, b + 1)] + M0[at(a, b - 1)]) + Mq[at(a + 1, b)] + Mq[at(a - 1, b)]
+                            + Mm[at(a - 1, b)] + Mm[at(a + 1, b)];
+                    v = (-c1 * rfc[k] + s) * T(0.125);
+                }
+                Fp[p] = v;
+            }
+        }
         __syncthreads();
         const int co = c - 1;
         if (co >= z0) {
@@ -426,7 +497,7 @@ __global__ void __launch_bounds__(kPlThreads) k3_resid_planes(int n, double inv_
     __shared__ double U[3][kRsUW * kRsUH];
     __shared__ T Rr[3][kRsRW * kRsRH];
     __shared__ double red[kPlThreads / 64];
-    const int bid = blockIdx.x;
+    const int bid = xcd_block();   // tiles of one die are neighbours
     const int tx = bid % ntx, ty = (bid / ntx) % nty, tz = bid / (ntx * nty);
     const int x0 = 1 + tx * kPlTX, y0 = 1 + ty * kPlTY, z0 = 1 + tz * zc;
     const int z1 = min(z0 + zc, n);
@@ -456,13 +527,17 @@ __global__ void __launch_bounds__(kPlThreads) k3_resid_planes(int n, double inv_
             if (p < kRsUW * kRsUH) { U[(z0 + 1) % 3][p] = a0[i]; U[(z0 + 2) % 3][p] = a1[i]; }
         }
     }
-    double un[kRsUS], fn[kRsFS];
+    // two register sets in turn, each holding the u plane and the f plane of
+    // one step, so every load is issued two planes ahead of its use
+    double uA[kRsUS], fA[kRsFS], uB[kRsUS], fB[kRsFS];
 #pragma unroll
-    for (int i = 0; i < kRsUS; i++) un[i] = uload(z0, i);
+    for (int i = 0; i < kRsUS; i++) { uA[i] = uload(z0, i); uB[i] = uload(z0 + 1, i); }
 #pragma unroll
-    for (int i = 0; i < kRsFS; i++) fn[i] = fload(z0 - 1, i);
+    for (int i = 0; i < kRsFS; i++) { fA[i] = fload(z0 - 1, i); fB[i] = fload(z0, i); }
     double acc = 0;
-    for (int c = z0 - 1; c <= z1; c++) {
+    // plane c: u plane c+1 from the set into LDS, the residual of plane c, then
+    // the red points of plane c-1; the set is refilled with planes c+3 and c+2
+    auto step = [&](int c, double (&un)[kRsUS], double (&fn)[kRsFS]) {
         double* Up = U[(c + 1) % 3];   // plane c+1
 #pragma unroll
         for (int i = 0; i < kRsUS; i++) {
@@ -472,11 +547,11 @@ __global__ void __launch_bounds__(kPlThreads) k3_resid_planes(int n, double inv_
         double fc[kRsFS];
 #pragma unroll
         for (int i = 0; i < kRsFS; i++) fc[i] = fn[i];
-        if (c + 1 <= z1) {
+        if (c + 2 <= z1) {
 #pragma unroll
-            for (int i = 0; i < kRsUS; i++) un[i] = uload(c + 2, i);
+            for (int i = 0; i < kRsUS; i++) un[i] = uload(c + 3, i);
 #pragma unroll
-            for (int i = 0; i < kRsFS; i++) fn[i] = fload(c + 1, i);
+            for (int i = 0; i < kRsFS; i++) fn[i] = fload(c + 2, i);
         }
         __syncthreads();
         const double* Um = U[(c + 2) % 3];   // plane c-1
@@ -518,6 +593,10 @@ __global__ void __launch_bounds__(kPlThreads) k3_resid_planes(int n, double inv_
                 rR[idxR(n, a, b, co)] = sum * (T(1) / T(12));
             }
         }
+    };
+    for (int c = z0 - 1; c <= z1; c += 2) {
+        step(c, uA, fA);
+        if (c + 1 <= z1) step(c + 1, uB, fB);
     }
     // block sum of the squared residual, one partial per workgroup
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o);
@@ -619,7 +698,7 @@ __global__ void __launch_bounds__(kPlThreads) k3_mag_planes(int m, T cc, const T
     constexpr int W = kMgW, NP = (kMgW * kMgH + kPlThreads - 1) / kPlThreads, NO = kMgTX * kPlTY / kPlThreads;
     __shared__ T F[2][kMgW * kMgH];
     const int h = m / 2;
-    const int bid = blockIdx.x;
+    const int bid = xcd_block();   // tiles of one die are neighbours
     const int tx = bid % ntx, ty = (bid / ntx) % nty, tz = bid / (ntx * nty);
     const int A0 = tx * kMgTX, B0 = ty * kPlTY, C0 = tz * zc;
     const int C1 = min(C0 + zc, h);   // centre planes [C0, C1) and corner planes [C0, C1) are output

@@ -14,18 +14,22 @@ constexpr int kColsPerWave = 63;     // one-sided halo (lane 0 only)
 constexpr int kXcds = 8;             // MI355X: 8 accelerator dies, one L2 each
 
 // Blocks are dispatched to the XCDs round-robin (block b runs on XCD b % 8).
-// Renumber them so that each XCD gets a contiguous range of logical blocks:
-// consecutive waves march neighbouring column bands of the same strip, so
-// the halo rows they share stay in one L2.
+// Renumber them so that each XCD gets a contiguous range of logical blocks
+// (a bijection of [0, gridDim.x)): neighbouring tiles then run on the same
+// die, so the halo they share stays in one L2.
+__device__ inline int xcd_block()
+{
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int per = nb / kXcds, rem = nb % kXcds;
+    const int x = b % kXcds;
+    return x * per + (x < rem ? x : rem) + b / kXcds;
+}
+
+// consecutive waves march neighbouring column bands of the same strip
 __device__ inline int rows_wave_id(int nwaves)
 {
-    int nb = gridDim.x;
-    int b = blockIdx.x;
-    int per = nb / kXcds, rem = nb % kXcds;
-    int x = b % kXcds;
-    int logical = x * per + (x < rem ? x : rem) + b / kXcds;
     (void)nwaves;
-    return logical * kWavesPerBlock + (threadIdx.x >> 6);
+    return xcd_block() * kWavesPerBlock + (threadIdx.x >> 6);
 }
 
 // Two adjacent elements (columns 2t, 2t+1 of a row) moved as one access.
@@ -68,19 +72,6 @@ __device__ inline void rows_march(int jbeg, int jlast, Load&& load, Proc&& proc)
         if (jb > jlast) break;
     }
 }
-
-int rows_resid_parts(int n);
-
-template <typename T>
-void launch_resid_a2d(int n, const double* u, const double* f, T* r0, T* rD, double* partial, const Ctl* ctl,
-                      hipStream_t s);
-template <typename T>
-void launch_rs2_rows(int diag_in, int m, const T* in, T* out, const Ctl* ctl, hipStream_t s);
-template <typename T>
-void launch_jac2_rows(int diag, int m, T c, const T* r, const T* vc, T* v, const Ctl* ctl, hipStream_t s);
-template <typename T>
-void launch_jac2_finest_rows(int n, T c, const T* r0, const T* vD, double* u, const Ctl* ctl, hipStream_t s);
-
 
 // Streaming pair accesses for arrays that are not reused before the cache
 // would evict them anyway (f, and r0 between the residual and the finest
