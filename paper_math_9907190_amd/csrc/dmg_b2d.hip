@@ -570,7 +570,11 @@ __device__ void coarse_down(const CoarseLev<T>& L, const LV& it, int hi, int lo)
     }
 }
 
-// Jacobi at lam = lo .. hi (lam = 0 from a zero correction)
+// Jacobi at lam = lo .. hi (lam = 0 from a zero correction).  Levels of side
+// >= kCoarseTwoPassSide store their F points first and take the C points'
+// neighbours from there after a barrier, instead of recomputing four F
+// values per C point (same operands, same order, same result).
+constexpr int kCoarseTwoPassSide = 16;
 template <typename T, typename LV>
 __device__ void coarse_up(const CoarseLev<T>& L, const LV& it, int lo, int hi)
 {
@@ -582,12 +586,20 @@ __device__ void coarse_up(const CoarseLev<T>& L, const LV& it, int lo, int hi)
         T* v = it.v(lam);
         int m = Li.m;
         T cc = Li.c;
+        const bool two = m >= kCoarseTwoPassSide;
         if (Li.diag) {
             int h = m / 2;
             for (int q = tid; q < h * h; q += nt) {
                 int A = q % h, B = q / h;
                 v[idxD(m, 2 * A + 1, 2 * B + 1)] = jac2_diagF(r, vc, m, cc, 2 * A + 1, 2 * B + 1);
-                if (A >= 1 && B >= 1) v[idxD(m, 2 * A, 2 * B)] = jac2_diagC(r, vc, m, cc, 2 * A, 2 * B);
+                if (!two && A >= 1 && B >= 1) v[idxD(m, 2 * A, 2 * B)] = jac2_diagC(r, vc, m, cc, 2 * A, 2 * B);
+            }
+            if (two) {
+                __syncthreads();
+                for (int q = tid; q < (h - 1) * (h - 1); q += nt) {
+                    int A = q % (h - 1) + 1, B = q / (h - 1) + 1;
+                    v[idxD(m, 2 * A, 2 * B)] = jac2_diagC_stored(r, v, m, cc, 2 * A, 2 * B);
+                }
             }
         } else {
             int w = m / 2 + 1;
@@ -595,7 +607,15 @@ __device__ void coarse_up(const CoarseLev<T>& L, const LV& it, int lo, int hi)
                 int t = q % w, b = q / w + 1;
                 int aC = 2 * t + (b & 1), aF = 2 * t + 1 - (b & 1);
                 if (aF >= 1 && aF < m) v[idxA(m, aF, b)] = jac2_axisF(r, vc, m, cc, aF, b);
-                if (aC >= 1 && aC < m) v[idxA(m, aC, b)] = jac2_axisC(r, vc, m, cc, aC, b);
+                if (!two && aC >= 1 && aC < m) v[idxA(m, aC, b)] = jac2_axisC(r, vc, m, cc, aC, b);
+            }
+            if (two) {
+                __syncthreads();
+                for (int q = tid; q < w * (m - 1); q += nt) {
+                    int t = q % w, b = q / w + 1;
+                    int aC = 2 * t + (b & 1);
+                    if (aC >= 1 && aC < m) v[idxA(m, aC, b)] = jac2_axisC_stored(r, v, m, cc, aC, b);
+                }
             }
         }
         __syncthreads();

@@ -92,12 +92,14 @@ __host__ __device__ inline size_t alignUp(size_t x) { return (x + kAlign - 1) / 
 // ------------------------------------------------------------ 2D stencils
 // Argument order of every sum follows the paper's printed equations.
 
+// The 2D point functions below serve the levels of side < 512 (one thread
+// per point, the coarse kernel), so their offsets fit in 32 bits.
+
 // Eq. (Erest2r): axis grid (A, side m) -> diagonal grid (D, side m) at (a,b), a+b even.
 template <typename T>
 __device__ inline T rs2_a2d(const T* __restrict__ rA, int m, int a, int b)
 {
-    size_t c = idxA(m, a, b);
-    size_t w = (size_t)(m + 1);
+    const int w = m + 1, c = b * w + a;
     return (4 * rA[c] + rA[c - 1] + rA[c - w] + rA[c + 1] + rA[c + w]) * T(0.125);
 }
 
@@ -105,10 +107,9 @@ __device__ inline T rs2_a2d(const T* __restrict__ rA, int m, int a, int b)
 template <typename T>
 __device__ inline T rs2_d2a(const T* __restrict__ rD, int m, int A, int B)
 {
-    int a = 2 * A, b = 2 * B;
-    size_t w = (size_t)(m / 2 + 1);
-    size_t c = (size_t)b * w + A;          // row b (even), column a>>1 = A
-    size_t lo = c - w, hi = c + w;         // rows b-1, b+1 (odd): columns (a-1)>>1 = A-1 and (a+1)>>1 = A
+    const int w = m / 2 + 1;
+    const int c = 2 * B * w + A;         // row b = 2B (even), column a>>1 = A
+    const int lo = c - w, hi = c + w;    // rows b-1, b+1 (odd): columns (a-1)>>1 = A-1 and (a+1)>>1 = A
     return (4 * rD[c] + rD[lo - 1] + rD[lo] + rD[hi] + rD[hi - 1]) * T(0.125);
 }
 
@@ -117,12 +118,10 @@ __device__ inline T rs2_d2a(const T* __restrict__ rD, int m, int A, int B)
 template <typename T>
 __device__ inline T jac2_diagF(const T* __restrict__ rD, const T* __restrict__ vA2, int m, T cc, int a, int b)
 {
-    int mc = m / 2;
-    int A0 = (a - 1) >> 1, B0 = (b - 1) >> 1;
-    size_t w = (size_t)(mc + 1);
-    size_t q = (size_t)B0 * w + A0;
+    const int w = m / 2 + 1;             // row length of vA2 (side m/2) and of the D layout
+    const int q = ((b - 1) >> 1) * w + ((a - 1) >> 1);
     // v_{i-1,j-1} + v_{i+1,j-1} + v_{i+1,j+1} + v_{i-1,j+1}
-    return (-cc * rD[idxD(m, a, b)] + vA2[q] + vA2[q + 1] + vA2[q + w + 1] + vA2[q + w]) * T(0.25);
+    return (-cc * rD[b * w + (a >> 1)] + vA2[q] + vA2[q + 1] + vA2[q + w + 1] + vA2[q + w]) * T(0.25);
 }
 
 // Eq. (Eajacb): diagonal-grid point (a,b), a and b even, interior, from the
@@ -132,7 +131,17 @@ __device__ inline T jac2_diagC(const T* __restrict__ rD, const T* __restrict__ v
 {
     T s = jac2_diagF(rD, vA2, m, cc, a - 1, b - 1) + jac2_diagF(rD, vA2, m, cc, a + 1, b - 1)
         + jac2_diagF(rD, vA2, m, cc, a + 1, b + 1) + jac2_diagF(rD, vA2, m, cc, a - 1, b + 1);
-    return (-cc * rD[idxD(m, a, b)] + s) * T(0.25);
+    return (-cc * rD[b * (m / 2 + 1) + (a >> 1)] + s) * T(0.25);
+}
+
+// Eq. (Eajacb) from stored new values: vD already holds the level's F
+// points (a and b odd); same operands and order as jac2_diagC.
+template <typename T>
+__device__ inline T jac2_diagC_stored(const T* __restrict__ rD, const T* vD, int m, T cc, int a, int b)
+{
+    const int w = m / 2 + 1, c = b * w + (a >> 1);   // (a-1)>>1 = (a>>1) - 1 and (a+1)>>1 = a>>1 on odd rows
+    T s = vD[c - w - 1] + vD[c - w] + vD[c + w] + vD[c + w - 1];
+    return (-cc * rD[c] + s) * T(0.25);
 }
 
 // Axis-grid analogue ("similarly for a green grid", Section 2.5): point
@@ -141,12 +150,11 @@ template <typename T>
 __device__ inline T jac2_axisF(const T* __restrict__ rA, const T* __restrict__ vD, int m, T cc, int a, int b)
 {
     if (a <= 0 || a >= m || b <= 0 || b >= m) return T(0);
-    size_t w = (size_t)(m / 2 + 1);
-    size_t rowb = (size_t)b * w;
+    const int w = m / 2 + 1, rowb = b * w;
     // neighbours (a-1,b), (a,b-1), (a+1,b), (a,b+1): all have an even index sum
     T s = vD[rowb + ((a - 1) >> 1)] + vD[rowb - w + (a >> 1)] + vD[rowb + ((a + 1) >> 1)]
         + vD[rowb + w + (a >> 1)];
-    return (-cc * rA[idxA(m, a, b)] + s) * T(0.25);
+    return (-cc * rA[b * (m + 1) + a] + s) * T(0.25);
 }
 
 // Point (a,b) with a+b even, interior, from the new values at its four axis
@@ -156,7 +164,17 @@ __device__ inline T jac2_axisC(const T* __restrict__ rA, const T* __restrict__ v
 {
     T s = jac2_axisF(rA, vD, m, cc, a - 1, b) + jac2_axisF(rA, vD, m, cc, a, b - 1)
         + jac2_axisF(rA, vD, m, cc, a + 1, b) + jac2_axisF(rA, vD, m, cc, a, b + 1);
-    return (-cc * rA[idxA(m, a, b)] + s) * T(0.25);
+    return (-cc * rA[b * (m + 1) + a] + s) * T(0.25);
+}
+
+// The same from stored new values: vA already holds the level's F points
+// (a+b odd; the boundary entries hold 0, as jac2_axisF returns there).
+template <typename T>
+__device__ inline T jac2_axisC_stored(const T* __restrict__ rA, const T* vA, int m, T cc, int a, int b)
+{
+    const int w = m + 1, c = b * w + a;
+    T s = vA[c - 1] + vA[c - w] + vA[c + 1] + vA[c + w];
+    return (-cc * rA[c] + s) * T(0.25);
 }
 
 }  // namespace dmg
