@@ -622,15 +622,71 @@ __device__ void coarse_up(const CoarseLev<T>& L, const LV& it, int lo, int hi)
     }
 }
 
+// Levels 0 .. kCoarseLdsTop (side <= 32, 2277 points per array) run in LDS:
+// each of their steps then waits on LDS instead of L2.  The larger levels
+// stay in global memory, so batched launches still fit two workgroups per CU.
+constexpr int kCoarseLdsTop = 8;
+constexpr int kCoarseLdsPts = 2304;   // >= the points of levels 0 .. 8
+
+template <typename T>
+struct SLevs {
+    T* lds;            // r of the staged levels, then v at + kCoarseLdsPts
+    const int* off;    // offset of each staged level
+    const T* z;        // zero correction below level 0 (in LDS)
+    __device__ T* r(int l) const { return lds + off[l]; }
+    __device__ T* v(int l) const { return lds + kCoarseLdsPts + off[l]; }
+    __device__ const T* zero() const { return z; }
+};
+
+template <typename T>
+__device__ inline int lev2_points(const LevInfo<T>& l)
+{
+    return l.diag ? (l.m + 1) * (l.m / 2 + 1) : (l.m + 1) * (l.m + 1);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kCoarseThreadsB) kb_coarse(CoarseLev<T> L, const Coarse2B<T>* __restrict__ items,
                                                              const T* __restrict__ zero, const Ctl* __restrict__ ctls)
 {
+    __shared__ T lds[2 * kCoarseLdsPts + 64];
+    __shared__ int off[kCoarseLdsTop + 1];
     const Coarse2B<T>& it = items[blockIdx.x];
     ITEM_GATE(ctls, it.prob);
-    const GLevs<T> S{it, zero};
-    coarse_down(L, S, it.top, 0);
-    coarse_up(L, S, 0, it.top);
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const GLevs<T> G{it, zero};
+    const int st = min(it.top, kCoarseLdsTop);   // highest staged level
+    if (tid == 0) {
+        int o = 0;
+        for (int l = 0; l <= st; l++) {
+            off[l] = o;
+            o += lev2_points(L.l[l]);
+        }
+    }
+    __syncthreads();
+    // global part of the restriction: into levels top-1 .. st
+    coarse_down(L, G, it.top, st);
+    // stage r of level st; zero the other staged arrays (boundary entries
+    // stay 0) and the zero correction below level 0
+    const int nst = off[st] + lev2_points(L.l[st]);
+    for (int q = tid; q < nst; q += nt) {
+        lds[q] = q >= off[st] ? it.r[st][q - off[st]] : T(0);
+        lds[kCoarseLdsPts + q] = T(0);
+    }
+    if (tid < 64) lds[2 * kCoarseLdsPts + tid] = T(0);
+    __syncthreads();
+    const SLevs<T> S{lds, off, lds + 2 * kCoarseLdsPts};
+    coarse_down(L, S, st, 0);
+    coarse_up(L, S, 0, st);
+    // every staged level back to global memory (r below st, v of all)
+    for (int q = tid; q < nst; q += nt) {
+        int l = 0;
+        while (l < st && q >= off[l + 1]) l++;
+        const int k = q - off[l];
+        if (l < st) it.r[l][k] = lds[q];
+        it.v[l][k] = lds[kCoarseLdsPts + q];
+    }
+    __syncthreads();
+    coarse_up(L, G, st + 1, it.top);
 }
 
 // ------------------------------------------------- learned coarse correction

@@ -93,12 +93,16 @@ __host__ __device__ inline size_t alignUp(size_t x) { return (x + kAlign - 1) / 
 // Argument order of every sum follows the paper's printed equations.
 
 // The 2D point functions below serve the levels of side < 512 (one thread
-// per point, the coarse kernel), so their offsets fit in 32 bits.
+// per point, the coarse kernel), so their offsets fit in 32 bits.  They are
+// not contracted into fused multiply-adds: every caller (global or LDS
+// operands, any kernel) then rounds each product and sum the same way, as
+// the equations are written.
 
 // Eq. (Erest2r): axis grid (A, side m) -> diagonal grid (D, side m) at (a,b), a+b even.
 template <typename T>
 __device__ inline T rs2_a2d(const T* __restrict__ rA, int m, int a, int b)
 {
+#pragma clang fp contract(off)
     const int w = m + 1, c = b * w + a;
     return (4 * rA[c] + rA[c - 1] + rA[c - w] + rA[c + 1] + rA[c + w]) * T(0.125);
 }
@@ -107,6 +111,7 @@ __device__ inline T rs2_a2d(const T* __restrict__ rA, int m, int a, int b)
 template <typename T>
 __device__ inline T rs2_d2a(const T* __restrict__ rD, int m, int A, int B)
 {
+#pragma clang fp contract(off)
     const int w = m / 2 + 1;
     const int c = 2 * B * w + A;         // row b = 2B (even), column a>>1 = A
     const int lo = c - w, hi = c + w;    // rows b-1, b+1 (odd): columns (a-1)>>1 = A-1 and (a+1)>>1 = A
@@ -118,6 +123,7 @@ __device__ inline T rs2_d2a(const T* __restrict__ rD, int m, int A, int B)
 template <typename T>
 __device__ inline T jac2_diagF(const T* __restrict__ rD, const T* __restrict__ vA2, int m, T cc, int a, int b)
 {
+#pragma clang fp contract(off)
     const int w = m / 2 + 1;             // row length of vA2 (side m/2) and of the D layout
     const int q = ((b - 1) >> 1) * w + ((a - 1) >> 1);
     // v_{i-1,j-1} + v_{i+1,j-1} + v_{i+1,j+1} + v_{i-1,j+1}
@@ -129,6 +135,7 @@ __device__ inline T jac2_diagF(const T* __restrict__ rD, const T* __restrict__ v
 template <typename T>
 __device__ inline T jac2_diagC(const T* __restrict__ rD, const T* __restrict__ vA2, int m, T cc, int a, int b)
 {
+#pragma clang fp contract(off)
     T s = jac2_diagF(rD, vA2, m, cc, a - 1, b - 1) + jac2_diagF(rD, vA2, m, cc, a + 1, b - 1)
         + jac2_diagF(rD, vA2, m, cc, a + 1, b + 1) + jac2_diagF(rD, vA2, m, cc, a - 1, b + 1);
     return (-cc * rD[b * (m / 2 + 1) + (a >> 1)] + s) * T(0.25);
@@ -139,6 +146,7 @@ __device__ inline T jac2_diagC(const T* __restrict__ rD, const T* __restrict__ v
 template <typename T>
 __device__ inline T jac2_diagC_stored(const T* __restrict__ rD, const T* vD, int m, T cc, int a, int b)
 {
+#pragma clang fp contract(off)
     const int w = m / 2 + 1, c = b * w + (a >> 1);   // (a-1)>>1 = (a>>1) - 1 and (a+1)>>1 = a>>1 on odd rows
     T s = vD[c - w - 1] + vD[c - w] + vD[c + w] + vD[c + w - 1];
     return (-cc * rD[c] + s) * T(0.25);
@@ -149,6 +157,7 @@ __device__ inline T jac2_diagC_stored(const T* __restrict__ rD, const T* vD, int
 template <typename T>
 __device__ inline T jac2_axisF(const T* __restrict__ rA, const T* __restrict__ vD, int m, T cc, int a, int b)
 {
+#pragma clang fp contract(off)
     if (a <= 0 || a >= m || b <= 0 || b >= m) return T(0);
     const int w = m / 2 + 1, rowb = b * w;
     // neighbours (a-1,b), (a,b-1), (a+1,b), (a,b+1): all have an even index sum
@@ -162,6 +171,7 @@ __device__ inline T jac2_axisF(const T* __restrict__ rA, const T* __restrict__ v
 template <typename T>
 __device__ inline T jac2_axisC(const T* __restrict__ rA, const T* __restrict__ vD, int m, T cc, int a, int b)
 {
+#pragma clang fp contract(off)
     T s = jac2_axisF(rA, vD, m, cc, a - 1, b) + jac2_axisF(rA, vD, m, cc, a, b - 1)
         + jac2_axisF(rA, vD, m, cc, a + 1, b) + jac2_axisF(rA, vD, m, cc, a, b + 1);
     return (-cc * rA[b * (m + 1) + a] + s) * T(0.25);
@@ -172,6 +182,7 @@ __device__ inline T jac2_axisC(const T* __restrict__ rA, const T* __restrict__ v
 template <typename T>
 __device__ inline T jac2_axisC_stored(const T* __restrict__ rA, const T* vA, int m, T cc, int a, int b)
 {
+#pragma clang fp contract(off)
     const int w = m + 1, c = b * w + a;
     T s = vA[c - 1] + vA[c - w] + vA[c + 1] + vA[c + w];
     return (-cc * rA[c] + s) * T(0.25);
