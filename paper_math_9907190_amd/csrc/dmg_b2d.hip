@@ -519,6 +519,187 @@ __global__ void __launch_bounds__(256) kb_jac_axis(int m, T cc, const Item2<T>* 
     if (aC >= 1 && aC < m) it.v[idxA(m, aC, b)] = jac2_axisC(it.r, it.in, m, cc, aC, b);
 }
 
+// ------------------------------------------------------ mid levels, fused
+// A single problem with n >= 512 runs its levels of side 256 and 128
+// (aligned levels 14 .. 11) one thread per point: four restriction and four
+// Jacobi launches that are latency-bound.  These two kernels do the same
+// work in one launch each.  A workgroup owns a tile of the output and
+// recomputes in LDS the part of every intermediate level its tile depends
+// on (halo included); it writes only the points it owns.  Every value goes
+// through the same point arithmetic as the per-level kernels, so the results
+// are bit-identical to theirs.
+constexpr int kMidTiles = 8;   // tiles per side: 64 workgroups
+
+// restriction: r14 (axis 256) -> r13 (diagonal 256), r12 (axis 128),
+// r11 (diagonal 128), r10 (axis 64).  Tile (tx, ty) owns level-10 points
+// [8t+1, 8t+8], levels 12 and 11 [16t+1, 16t+16], level 13 [32t+1, 32t+32]
+// (in each level's own coordinates, interior points only).
+template <typename T>
+__global__ void __launch_bounds__(256) kb_mid_down(const T* __restrict__ r14, T* __restrict__ r13, T* __restrict__ r12,
+                                                   T* __restrict__ r11, T* __restrict__ r10, const Ctl* __restrict__ ctl)
+{
+    if (ctl->done) return;
+    constexpr int W13 = 39, W12 = 19, W11 = 17;
+    __shared__ T R13[W13 * W13], R12[W12 * W12], R11[W11 * W11];
+    const int tx = blockIdx.x % kMidTiles, ty = blockIdx.x / kMidTiles;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    auto own = [](int a, int t, int s) { return a > s * t && a <= s * t + s; };
+    // level 13 on [32t-1, 32t+37] from level 14 (global)
+    const int a13 = 32 * tx - 1, b13 = 32 * ty - 1;
+    for (int q = tid; q < W13 * W13; q += nt) {
+        const int a = a13 + q % W13, b = b13 + q / W13;
+        T x = T(0);
+        if (a >= 1 && a <= 255 && b >= 1 && b <= 255 && !((a + b) & 1)) {
+            x = rs2_a2d(r14, 256, a, b);
+            if (own(a, tx, 32) && own(b, ty, 32)) r13[idxD(256, a, b)] = x;
+        }
+        R13[q] = x;
+    }
+    __syncthreads();
+    // level 12 on [16t, 16t+18], Eq. (Erest2b) from level 13 (LDS)
+    const int a12 = 16 * tx, b12 = 16 * ty;
+    for (int q = tid; q < W12 * W12; q += nt) {
+        const int A = a12 + q % W12, B = b12 + q / W12;
+        T x = T(0);
+        if (A >= 1 && A <= 127 && B >= 1 && B <= 127) {
+            const int c = (2 * B - b13) * W13 + (2 * A - a13);
+            x = rs2_core(R13[c], R13[c - W13 - 1], R13[c - W13 + 1], R13[c + W13 + 1], R13[c + W13 - 1]);
+            if (own(A, tx, 16) && own(B, ty, 16)) r12[idxA(128, A, B)] = x;
+        }
+        R12[q] = x;
+    }
+    __syncthreads();
+    // level 11 on [16t+1, 16t+17], Eq. (Erest2r) from level 12 (LDS)
+    const int a11 = 16 * tx + 1, b11 = 16 * ty + 1;
+    for (int q = tid; q < W11 * W11; q += nt) {
+        const int a = a11 + q % W11, b = b11 + q / W11;
+        T x = T(0);
+        if (a <= 127 && b <= 127 && !((a + b) & 1)) {
+            const int c = (b - b12) * W12 + (a - a12);
+            x = rs2_core(R12[c], R12[c - 1], R12[c - W12], R12[c + 1], R12[c + W12]);
+            if (own(a, tx, 16) && own(b, ty, 16)) r11[idxD(128, a, b)] = x;
+        }
+        R11[q] = x;
+    }
+    __syncthreads();
+    // level 10, the tile itself, Eq. (Erest2b) from level 11 (LDS)
+    if (tid < 64) {
+        const int A = 8 * tx + 1 + tid % 8, B = 8 * ty + 1 + tid / 8;
+        if (A <= 63 && B <= 63) {
+            const int c = (2 * B - b11) * W11 + (2 * A - a11);
+            r10[idxA(64, A, B)] = rs2_core(R11[c], R11[c - W11 - 1], R11[c - W11 + 1], R11[c + W11 + 1], R11[c + W11 - 1]);
+        }
+    }
+}
+
+// Jacobi up from v10 (axis 64): v11 (diagonal 128), v12 (axis 128), v13
+// (diagonal 256), v14 (axis 256).  Tile (tx, ty) owns level-14 points
+// [32t+1, 32t+32] and the same ownership as above below it.  Each level's
+// F points are computed over one point more than its C points need; LDS
+// entries off the interior stay 0 (the boundary values).
+template <typename T>
+__global__ void __launch_bounds__(256) kb_mid_up(const T* __restrict__ v10, const T* __restrict__ r11,
+                                                 const T* __restrict__ r12, const T* __restrict__ r13,
+                                                 const T* __restrict__ r14, T* __restrict__ v11, T* __restrict__ v12,
+                                                 T* __restrict__ v13, T* __restrict__ v14, T c11, T c12, T c13, T c14,
+                                                 const Ctl* __restrict__ ctl)
+{
+    if (ctl->done) return;
+    constexpr int W11 = 26, W12 = 22, W13 = 38, W14 = 34;
+    __shared__ T L11[W11 * W11], L12[W12 * W12], L13[W13 * W13], L14[W14 * W14];
+    const int tx = blockIdx.x % kMidTiles, ty = blockIdx.x / kMidTiles;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    auto own = [](int a, int t, int s) { return a > s * t && a <= s * t + s; };
+    for (int q = tid; q < W13 * W13; q += nt) {
+        L13[q] = T(0);
+        if (q < W11 * W11) L11[q] = T(0);
+        if (q < W12 * W12) L12[q] = T(0);
+        if (q < W14 * W14) L14[q] = T(0);
+    }
+    __syncthreads();
+    // level 11: F on [16t-4, 16t+21] from v10 (global), C on [16t-3, 16t+20]
+    const int a11 = 16 * tx - 4, b11 = 16 * ty - 4;
+    for (int q = tid; q < W11 * W11; q += nt) {
+        const int a = a11 + q % W11, b = b11 + q / W11;
+        if (a >= 1 && a <= 127 && b >= 1 && b <= 127 && (a & b & 1)) L11[q] = jac2_diagF(r11, v10, 128, c11, a, b);
+    }
+    __syncthreads();
+    for (int q = tid; q < W11 * W11; q += nt) {
+        const int la = q % W11, lb = q / W11, a = a11 + la, b = b11 + lb;
+        if (la >= 1 && la < W11 - 1 && lb >= 1 && lb < W11 - 1 && a >= 1 && a <= 127 && b >= 1 && b <= 127 &&
+            !((a | b) & 1))
+            L11[q] = jac2_sum(c11, r11[idxD(128, a, b)], L11[q - W11 - 1], L11[q - W11 + 1], L11[q + W11 + 1],
+                              L11[q + W11 - 1]);
+    }
+    __syncthreads();
+    // level 12: F on [16t-2, 16t+19] from level 11, C on [16t-1, 16t+18]
+    const int a12 = 16 * tx - 2, b12 = 16 * ty - 2;
+    for (int q = tid; q < W12 * W12; q += nt) {
+        const int a = a12 + q % W12, b = b12 + q / W12;
+        if (a >= 1 && a <= 127 && b >= 1 && b <= 127 && ((a + b) & 1)) {
+            const int c = (b - b11) * W11 + (a - a11);
+            L12[q] = jac2_sum(c12, r12[idxA(128, a, b)], L11[c - 1], L11[c - W11], L11[c + 1], L11[c + W11]);
+        }
+    }
+    __syncthreads();
+    for (int q = tid; q < W12 * W12; q += nt) {
+        const int la = q % W12, lb = q / W12, a = a12 + la, b = b12 + lb;
+        if (la >= 1 && la < W12 - 1 && lb >= 1 && lb < W12 - 1 && a >= 1 && a <= 127 && b >= 1 && b <= 127 &&
+            !((a + b) & 1))
+            L12[q] = jac2_sum(c12, r12[idxA(128, a, b)], L12[q - 1], L12[q - W12], L12[q + 1], L12[q + W12]);
+    }
+    __syncthreads();
+    // owned points of levels 11 and 12
+    for (int q = tid; q < 16 * 16; q += nt) {
+        const int a = 16 * tx + 1 + q % 16, b = 16 * ty + 1 + q / 16;
+        if (a <= 127 && b <= 127) {
+            if (!((a + b) & 1)) v11[idxD(128, a, b)] = L11[(b - b11) * W11 + (a - a11)];
+            v12[idxA(128, a, b)] = L12[(b - b12) * W12 + (a - a12)];
+        }
+    }
+    // level 13: F on [32t-2, 32t+35] from level 12, C on [32t-1, 32t+34]
+    const int a13 = 32 * tx - 2, b13 = 32 * ty - 2;
+    for (int q = tid; q < W13 * W13; q += nt) {
+        const int a = a13 + q % W13, b = b13 + q / W13;
+        if (a >= 1 && a <= 255 && b >= 1 && b <= 255 && (a & b & 1)) {
+            const int c = (((b - 1) >> 1) - b12) * W12 + (((a - 1) >> 1) - a12);   // v12((a-1)/2, (b-1)/2)
+            L13[q] = jac2_chain(c13, r13[idxD(256, a, b)], L12[c], L12[c + 1], L12[c + W12 + 1], L12[c + W12]);
+        }
+    }
+    __syncthreads();
+    for (int q = tid; q < W13 * W13; q += nt) {
+        const int la = q % W13, lb = q / W13, a = a13 + la, b = b13 + lb;
+        if (la >= 1 && la < W13 - 1 && lb >= 1 && lb < W13 - 1 && a >= 1 && a <= 255 && b >= 1 && b <= 255 &&
+            !((a | b) & 1))
+            L13[q] = jac2_sum(c13, r13[idxD(256, a, b)], L13[q - W13 - 1], L13[q - W13 + 1], L13[q + W13 + 1],
+                              L13[q + W13 - 1]);
+    }
+    __syncthreads();
+    // level 14: F on [32t, 32t+33] from level 13; owned points of level 13
+    const int a14 = 32 * tx, b14 = 32 * ty;
+    for (int q = tid; q < W14 * W14; q += nt) {
+        const int a = a14 + q % W14, b = b14 + q / W14;
+        if (a >= 1 && a <= 255 && b >= 1 && b <= 255 && ((a + b) & 1)) {
+            const int c = (b - b13) * W13 + (a - a13);
+            L14[q] = jac2_sum(c14, r14[idxA(256, a, b)], L13[c - 1], L13[c - W13], L13[c + 1], L13[c + W13]);
+        }
+    }
+    for (int q = tid; q < 32 * 32; q += nt) {
+        const int a = 32 * tx + 1 + q % 32, b = 32 * ty + 1 + q / 32;
+        if (a <= 255 && b <= 255 && !((a + b) & 1)) v13[idxD(256, a, b)] = L13[(b - b13) * W13 + (a - a13)];
+    }
+    __syncthreads();
+    // level 14, the tile: F from LDS, C from its four F neighbours
+    for (int q = tid; q < 32 * 32; q += nt) {
+        const int a = 32 * tx + 1 + q % 32, b = 32 * ty + 1 + q / 32;
+        if (a > 255 || b > 255) continue;
+        const int c = (b - b14) * W14 + (a - a14);
+        v14[idxA(256, a, b)] = ((a + b) & 1) ? L14[c]
+                                             : jac2_sum(c14, r14[idxA(256, a, b)], L14[c - 1], L14[c - W14],
+                                                        L14[c + 1], L14[c + W14]);
+    }
+}
+
 // ------------------------------------------------------------ coarse levels
 // Aligned levels top .. 0 of one problem per workgroup: restriction down to
 // the 3x3 grid, its Jacobi from a zero correction, Jacobi back up to top.
@@ -1121,6 +1302,19 @@ void launch_b_jacobi(int diag, int m, int rows, T c, const Item2<T>* items, int 
 }
 
 template <typename T>
+void launch_b_mid_down(const T* r14, T* r13, T* r12, T* r11, T* r10, const Ctl* ctl, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_mid_down<T>, dim3(kMidTiles * kMidTiles), dim3(256), 0, s, r14, r13, r12, r11, r10, ctl);
+}
+
+template <typename T>
+void launch_b_mid_up(const T* v10, const T* const* r, T* const* v, const T* c, const Ctl* ctl, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_mid_up<T>, dim3(kMidTiles * kMidTiles), dim3(256), 0, s, v10, r[0], r[1], r[2], r[3], v[0],
+                       v[1], v[2], v[3], c[0], c[1], c[2], c[3], ctl);
+}
+
+template <typename T>
 void launch_b_coarse(const LevInfo<T>* lev, const Coarse2B<T>* items, int nitems, const T* zero, const Ctl* ctls,
                      hipStream_t s)
 {
@@ -1149,7 +1343,9 @@ void launch_b_coarse_net(const LevInfo<T>* lev, const Coarse2B<T>* items, int ni
     template void launch_b_level_get<T>(int, int, const T*, double*, hipStream_t);                           \
     template void launch_b_coarse_net<T>(const LevInfo<T>*, const Coarse2B<T>*, int, const T*, Ctl*, const bf16_t*, \
                                          hipStream_t);                                                          \
-    template void launch_b_coarse_export<T>(int, int, int, const Coarse2B<T>*, int, double*, hipStream_t);
+    template void launch_b_coarse_export<T>(int, int, int, const Coarse2B<T>*, int, double*, hipStream_t);       \
+    template void launch_b_mid_down<T>(const T*, T*, T*, T*, T*, const Ctl*, hipStream_t);                     \
+    template void launch_b_mid_up<T>(const T*, const T* const*, T* const*, const T*, const Ctl*, hipStream_t);
 DMG_INSTB(double)
 DMG_INSTB(float)
 

@@ -76,6 +76,14 @@ void launch_b_ctl_reset(Ctl* ctls, int nprob, int mode, int max_cycles, double r
 template <typename T>
 void launch_b_coarse_net(const LevInfo<T>* lev, const Coarse2B<T>* items, int nitems, const T* zero, Ctl* ctls,
                          const unsigned short* wf, hipStream_t s);
+// A single problem's aligned levels 14 .. 11 (sides 256 and 128) in one
+// launch each way: restriction r14 -> r13, r12, r11, r10; Jacobi from v10
+// up to v11 .. v14 (r[k], v[k], c[k]: level 11 + k).  Needs n >= 512.
+constexpr int kMidTop = 14, kMidLow = 10;
+template <typename T>
+void launch_b_mid_down(const T* r14, T* r13, T* r12, T* r11, T* r10, const Ctl* ctl, hipStream_t s);
+template <typename T>
+void launch_b_mid_up(const T* v10, const T* const* r, T* const* v, const T* c, const Ctl* ctl, hipStream_t s);
 template <typename T>
 void launch_b_coarse_export(int lam, int diag, int m, const Coarse2B<T>* items, int nitems, double* dst, hipStream_t s);
 template <typename T>

@@ -93,29 +93,51 @@ __host__ __device__ inline size_t alignUp(size_t x) { return (x + kAlign - 1) / 
 // Argument order of every sum follows the paper's printed equations.
 
 // The 2D point functions below serve the levels of side < 512 (one thread
-// per point, the coarse kernel), so their offsets fit in 32 bits.  They are
-// not contracted into fused multiply-adds: every caller (global or LDS
-// operands, any kernel) then rounds each product and sum the same way, as
-// the equations are written.
+// per point, the coarse kernel, the fused mid-level kernels), so their
+// offsets fit in 32 bits.  Their arithmetic lives in three cores on loaded
+// operands, compiled without fused multiply-add contraction: every caller
+// (global or LDS operands, any kernel) then rounds each product and sum the
+// same way, as the equations are written.
+
+// Eqs. (Erest2r), (Erest2b): (4 r_c + four neighbours) / 8, summed in order
+template <typename T>
+__device__ inline T rs2_core(T c, T n0, T n1, T n2, T n3)
+{
+#pragma clang fp contract(off)
+    return (4 * c + n0 + n1 + n2 + n3) * T(0.125);
+}
+// Eq. (Eajacr): (-cc r + four coarse values) / 4, accumulated in order
+template <typename T>
+__device__ inline T jac2_chain(T cc, T r, T n0, T n1, T n2, T n3)
+{
+#pragma clang fp contract(off)
+    return (-cc * r + n0 + n1 + n2 + n3) * T(0.25);
+}
+// Eq. (Eajacb) and the axis-grid steps: the four neighbours summed first
+template <typename T>
+__device__ inline T jac2_sum(T cc, T r, T n0, T n1, T n2, T n3)
+{
+#pragma clang fp contract(off)
+    T s = n0 + n1 + n2 + n3;
+    return (-cc * r + s) * T(0.25);
+}
 
 // Eq. (Erest2r): axis grid (A, side m) -> diagonal grid (D, side m) at (a,b), a+b even.
 template <typename T>
 __device__ inline T rs2_a2d(const T* __restrict__ rA, int m, int a, int b)
 {
-#pragma clang fp contract(off)
     const int w = m + 1, c = b * w + a;
-    return (4 * rA[c] + rA[c - 1] + rA[c - w] + rA[c + 1] + rA[c + w]) * T(0.125);
+    return rs2_core(rA[c], rA[c - 1], rA[c - w], rA[c + 1], rA[c + w]);
 }
 
 // Eq. (Erest2b): diagonal grid (D, side m) -> axis grid of side m/2 at (2A, 2B).
 template <typename T>
 __device__ inline T rs2_d2a(const T* __restrict__ rD, int m, int A, int B)
 {
-#pragma clang fp contract(off)
     const int w = m / 2 + 1;
     const int c = 2 * B * w + A;         // row b = 2B (even), column a>>1 = A
     const int lo = c - w, hi = c + w;    // rows b-1, b+1 (odd): columns (a-1)>>1 = A-1 and (a+1)>>1 = A
-    return (4 * rD[c] + rD[lo - 1] + rD[lo] + rD[hi] + rD[hi - 1]) * T(0.125);
+    return rs2_core(rD[c], rD[lo - 1], rD[lo], rD[hi], rD[hi - 1]);
 }
 
 // Eq. (Eajacr): Jacobi value at a diagonal-grid point (a,b), a and b odd,
@@ -123,11 +145,10 @@ __device__ inline T rs2_d2a(const T* __restrict__ rD, int m, int A, int B)
 template <typename T>
 __device__ inline T jac2_diagF(const T* __restrict__ rD, const T* __restrict__ vA2, int m, T cc, int a, int b)
 {
-#pragma clang fp contract(off)
     const int w = m / 2 + 1;             // row length of vA2 (side m/2) and of the D layout
     const int q = ((b - 1) >> 1) * w + ((a - 1) >> 1);
     // v_{i-1,j-1} + v_{i+1,j-1} + v_{i+1,j+1} + v_{i-1,j+1}
-    return (-cc * rD[b * w + (a >> 1)] + vA2[q] + vA2[q + 1] + vA2[q + w + 1] + vA2[q + w]) * T(0.25);
+    return jac2_chain(cc, rD[b * w + (a >> 1)], vA2[q], vA2[q + 1], vA2[q + w + 1], vA2[q + w]);
 }
 
 // Eq. (Eajacb): diagonal-grid point (a,b), a and b even, interior, from the
@@ -135,10 +156,9 @@ __device__ inline T jac2_diagF(const T* __restrict__ rD, const T* __restrict__ v
 template <typename T>
 __device__ inline T jac2_diagC(const T* __restrict__ rD, const T* __restrict__ vA2, int m, T cc, int a, int b)
 {
-#pragma clang fp contract(off)
-    T s = jac2_diagF(rD, vA2, m, cc, a - 1, b - 1) + jac2_diagF(rD, vA2, m, cc, a + 1, b - 1)
-        + jac2_diagF(rD, vA2, m, cc, a + 1, b + 1) + jac2_diagF(rD, vA2, m, cc, a - 1, b + 1);
-    return (-cc * rD[b * (m / 2 + 1) + (a >> 1)] + s) * T(0.25);
+    return jac2_sum(cc, rD[b * (m / 2 + 1) + (a >> 1)], jac2_diagF(rD, vA2, m, cc, a - 1, b - 1),
+                    jac2_diagF(rD, vA2, m, cc, a + 1, b - 1), jac2_diagF(rD, vA2, m, cc, a + 1, b + 1),
+                    jac2_diagF(rD, vA2, m, cc, a - 1, b + 1));
 }
 
 // Eq. (Eajacb) from stored new values: vD already holds the level's F
@@ -146,10 +166,8 @@ __device__ inline T jac2_diagC(const T* __restrict__ rD, const T* __restrict__ v
 template <typename T>
 __device__ inline T jac2_diagC_stored(const T* __restrict__ rD, const T* vD, int m, T cc, int a, int b)
 {
-#pragma clang fp contract(off)
     const int w = m / 2 + 1, c = b * w + (a >> 1);   // (a-1)>>1 = (a>>1) - 1 and (a+1)>>1 = a>>1 on odd rows
-    T s = vD[c - w - 1] + vD[c - w] + vD[c + w] + vD[c + w - 1];
-    return (-cc * rD[c] + s) * T(0.25);
+    return jac2_sum(cc, rD[c], vD[c - w - 1], vD[c - w], vD[c + w], vD[c + w - 1]);
 }
 
 // Axis-grid analogue ("similarly for a green grid", Section 2.5): point
@@ -157,13 +175,11 @@ __device__ inline T jac2_diagC_stored(const T* __restrict__ rD, const T* vD, int
 template <typename T>
 __device__ inline T jac2_axisF(const T* __restrict__ rA, const T* __restrict__ vD, int m, T cc, int a, int b)
 {
-#pragma clang fp contract(off)
     if (a <= 0 || a >= m || b <= 0 || b >= m) return T(0);
     const int w = m / 2 + 1, rowb = b * w;
     // neighbours (a-1,b), (a,b-1), (a+1,b), (a,b+1): all have an even index sum
-    T s = vD[rowb + ((a - 1) >> 1)] + vD[rowb - w + (a >> 1)] + vD[rowb + ((a + 1) >> 1)]
-        + vD[rowb + w + (a >> 1)];
-    return (-cc * rA[b * (m + 1) + a] + s) * T(0.25);
+    return jac2_sum(cc, rA[b * (m + 1) + a], vD[rowb + ((a - 1) >> 1)], vD[rowb - w + (a >> 1)],
+                    vD[rowb + ((a + 1) >> 1)], vD[rowb + w + (a >> 1)]);
 }
 
 // Point (a,b) with a+b even, interior, from the new values at its four axis
@@ -171,10 +187,8 @@ __device__ inline T jac2_axisF(const T* __restrict__ rA, const T* __restrict__ v
 template <typename T>
 __device__ inline T jac2_axisC(const T* __restrict__ rA, const T* __restrict__ vD, int m, T cc, int a, int b)
 {
-#pragma clang fp contract(off)
-    T s = jac2_axisF(rA, vD, m, cc, a - 1, b) + jac2_axisF(rA, vD, m, cc, a, b - 1)
-        + jac2_axisF(rA, vD, m, cc, a + 1, b) + jac2_axisF(rA, vD, m, cc, a, b + 1);
-    return (-cc * rA[b * (m + 1) + a] + s) * T(0.25);
+    return jac2_sum(cc, rA[b * (m + 1) + a], jac2_axisF(rA, vD, m, cc, a - 1, b), jac2_axisF(rA, vD, m, cc, a, b - 1),
+                    jac2_axisF(rA, vD, m, cc, a + 1, b), jac2_axisF(rA, vD, m, cc, a, b + 1));
 }
 
 // The same from stored new values: vA already holds the level's F points
@@ -182,10 +196,8 @@ __device__ inline T jac2_axisC(const T* __restrict__ rA, const T* __restrict__ v
 template <typename T>
 __device__ inline T jac2_axisC_stored(const T* __restrict__ rA, const T* vA, int m, T cc, int a, int b)
 {
-#pragma clang fp contract(off)
     const int w = m + 1, c = b * w + a;
-    T s = vA[c - 1] + vA[c - w] + vA[c + 1] + vA[c + w];
-    return (-cc * rA[c] + s) * T(0.25);
+    return jac2_sum(cc, rA[c], vA[c - 1], vA[c - w], vA[c + 1], vA[c + w]);
 }
 
 }  // namespace dmg

@@ -252,13 +252,38 @@ void enq_resid(Plan2& P, Ctl* ctls, int* nact)
     }
 }
 
+// A single problem whose aligned levels kMidTop .. kMidLow (sides 256 .. 64)
+// all run one thread per point, with the coarse kernel starting at kMidLow:
+// the fused mid-level kernels replace those eight launches.
+bool use_mid(const Plan2& P)
+{
+    if (P.nprob != 1 || P.D[0] < kMidTop + 2 || P.lamc != kMidLow) return false;
+    for (int lam = kMidLow; lam < kMidTop; lam++)
+        if (P.n_rs_items[lam] != 1 || P.rows_rs[lam] != 0) return false;
+    for (int lam = kMidLow + 1; lam <= kMidTop; lam++)
+        if (P.n_jac_items[lam] != 1 || P.rows_jac[lam] != 0) return false;
+    return true;
+}
+
 template <typename T>
 void enq_cycle(Plan2& P, Ctl* ctls)
 {
     size_t es = sizeof(T);
+    const bool mid = use_mid(P);
+    auto R = [&](int lam) { return at<T>(P, P.off_r[0][lam]); };
+    auto V = [&](int lam) { return at<T>(P, P.off_v[0][lam]); };
     for (int lam = P.Dmax - 2; lam >= 0; lam--) {
         int k = P.n_rs_items[lam];
         if (!k) continue;
+        if (mid && lam >= kMidLow && lam < kMidTop) {
+            if (lam == kMidTop - 1) {
+                double b = 0;
+                for (int l = kMidLow; l < kMidTop; l++) b += bytes_rs((l + 1) & 1, side_of(l + 1), es);
+                Timed t(&P.tm, MG_K_RESTRICT, b);
+                launch_b_mid_down<T>(R(14), R(13), R(12), R(11), R(10), ctls, P.stream);
+            }
+            continue;
+        }
         int diag_in = (lam + 1) & 1;
         Timed t(&P.tm, MG_K_RESTRICT, bytes_rs(diag_in, side_of(lam + 1), es) * k);
         launch_b_restrict<T>(diag_in, side_of(lam + 1), P.rows_rs[lam], at<Item2<T>>(P, P.off_rs_items[lam]), k, ctls,
@@ -287,6 +312,18 @@ void enq_cycle(Plan2& P, Ctl* ctls)
     for (int lam = 0; lam <= P.Dmax; lam++) {
         int k = P.n_jac_items[lam];
         if (!k) continue;
+        if (mid && lam > kMidLow && lam <= kMidTop) {
+            if (lam == kMidLow + 1) {
+                double b = 0;
+                for (int l = kMidLow + 1; l <= kMidTop; l++) b += bytes_jac(l & 1, side_of(l), es);
+                Timed t(&P.tm, MG_K_JACOBI, b);
+                const T* r[4] = {R(11), R(12), R(13), R(14)};
+                T* v[4] = {V(11), V(12), V(13), V(14)};
+                const T c[4] = {(T)coef(P, 11), (T)coef(P, 12), (T)coef(P, 13), (T)coef(P, 14)};
+                launch_b_mid_up<T>(V(10), r, v, c, ctls, P.stream);
+            }
+            continue;
+        }
         Timed t(&P.tm, MG_K_JACOBI, bytes_jac(lam & 1, side_of(lam), es) * k);
         launch_b_jacobi<T>(lam & 1, side_of(lam), P.rows_jac[lam], (T)coef(P, lam), at<Item2<T>>(P, P.off_jac_items[lam]),
                            k, ctls, P.stream);

@@ -60,8 +60,8 @@ def one_cycle_levels(dmg, orc, dim, n, prec, seed):
     return uo, rs, vs, ud.cpu().numpy(), gl_r, gl_v, u
 
 
-@pytest.mark.parametrize("dim,n", [(2, 2), (2, 4), (2, 8), (2, 16), (2, 64), (2, 128), (3, 2), (3, 4), (3, 8),
-                                   (3, 16), (3, 32), (3, 64), (3, 128)])
+@pytest.mark.parametrize("dim,n", [(2, 2), (2, 4), (2, 8), (2, 16), (2, 64), (2, 128), (2, 512), (2, 1024), (3, 2),
+                                   (3, 4), (3, 8), (3, 16), (3, 32), (3, 64), (3, 128)])
 def test_every_level_of_one_cycle_fp64(dmg, orc, dim, n):
     uo, rs, vs, ug, gr, gv, u0 = one_cycle_levels(dmg, orc, dim, n, 0, 7 + n)
     for d in range(len(rs)):
@@ -73,7 +73,7 @@ def test_every_level_of_one_cycle_fp64(dmg, orc, dim, n):
     assert np.array_equal(ug[(0,) + (slice(None),) * (dim - 1)], u0[(0,) + (slice(None),) * (dim - 1)])
 
 
-@pytest.mark.parametrize("dim,n", [(2, 16), (2, 256), (3, 8), (3, 32), (3, 128)])
+@pytest.mark.parametrize("dim,n", [(2, 16), (2, 256), (2, 512), (3, 8), (3, 32), (3, 128)])
 def test_every_level_of_one_cycle_fp32(dmg, orc, dim, n):
     """Single-precision levels.  Every restriction is an average with positive
     weights, so its rounding error is bounded by a few float ulps of the
