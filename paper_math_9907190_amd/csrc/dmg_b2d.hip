@@ -529,13 +529,14 @@ __global__ void __launch_bounds__(256) kb_jac_axis(int m, T cc, const Item2<T>* 
 // through the same point arithmetic as the per-level kernels, so the results
 // are bit-identical to theirs.
 constexpr int kMidTiles = 8;   // tiles per side: 64 workgroups
+constexpr int kMidThreads = 1024;   // 16 waves: the level steps are latency-bound
 
 // restriction: r14 (axis 256) -> r13 (diagonal 256), r12 (axis 128),
 // r11 (diagonal 128), r10 (axis 64).  Tile (tx, ty) owns level-10 points
 // [8t+1, 8t+8], levels 12 and 11 [16t+1, 16t+16], level 13 [32t+1, 32t+32]
 // (in each level's own coordinates, interior points only).
 template <typename T>
-__global__ void __launch_bounds__(256) kb_mid_down(const T* __restrict__ r14, T* __restrict__ r13, T* __restrict__ r12,
+__global__ void __launch_bounds__(kMidThreads) kb_mid_down(const T* __restrict__ r14, T* __restrict__ r13, T* __restrict__ r12,
                                                    T* __restrict__ r11, T* __restrict__ r10, const Ctl* __restrict__ ctl)
 {
     if (ctl->done) return;
@@ -598,7 +599,7 @@ __global__ void __launch_bounds__(256) kb_mid_down(const T* __restrict__ r14, T*
 // F points are computed over one point more than its C points need; LDS
 // entries off the interior stay 0 (the boundary values).
 template <typename T>
-__global__ void __launch_bounds__(256) kb_mid_up(const T* __restrict__ v10, const T* __restrict__ r11,
+__global__ void __launch_bounds__(kMidThreads) kb_mid_up(const T* __restrict__ v10, const T* __restrict__ r11,
                                                  const T* __restrict__ r12, const T* __restrict__ r13,
                                                  const T* __restrict__ r14, T* __restrict__ v11, T* __restrict__ v12,
                                                  T* __restrict__ v13, T* __restrict__ v14, T c11, T c12, T c13, T c14,
@@ -1304,13 +1305,13 @@ void launch_b_jacobi(int diag, int m, int rows, T c, const Item2<T>* items, int 
 template <typename T>
 void launch_b_mid_down(const T* r14, T* r13, T* r12, T* r11, T* r10, const Ctl* ctl, hipStream_t s)
 {
-    hipLaunchKernelGGL(kb_mid_down<T>, dim3(kMidTiles * kMidTiles), dim3(256), 0, s, r14, r13, r12, r11, r10, ctl);
+    hipLaunchKernelGGL(kb_mid_down<T>, dim3(kMidTiles * kMidTiles), dim3(kMidThreads), 0, s, r14, r13, r12, r11, r10, ctl);
 }
 
 template <typename T>
 void launch_b_mid_up(const T* v10, const T* const* r, T* const* v, const T* c, const Ctl* ctl, hipStream_t s)
 {
-    hipLaunchKernelGGL(kb_mid_up<T>, dim3(kMidTiles * kMidTiles), dim3(256), 0, s, v10, r[0], r[1], r[2], r[3], v[0],
+    hipLaunchKernelGGL(kb_mid_up<T>, dim3(kMidTiles * kMidTiles), dim3(kMidThreads), 0, s, v10, r[0], r[1], r[2], r[3], v[0],
                        v[1], v[2], v[3], c[0], c[1], c[2], c[3], ctl);
 }
 
