@@ -155,6 +155,7 @@ __global__ void __launch_bounds__(256) k3_jac_finest(int n, T cc, const T* __res
 constexpr int kPlTX = 64, kPlTY = 8, kPlThreads = 256;
 constexpr int kPlW = kPlTX + 2, kPlH = kPlTY + 2;   // tile plus a one-point halo
 constexpr int kRdTX = 32, kRdW = kRdTX + 2;        // red tiles: 32 slots (64 x positions) wide
+constexpr int kRdTY = 8, kRdH = kRdTY + 2;         // red tiles: rows (16 and 32 measured slower)
 
 // ---- green: F points (a+b+c odd), Eq. (Egprolg).  The red grid is staged
 // plane by plane in LDS over the tile plus a two-point halo: row (b, c) of
@@ -320,8 +321,8 @@ __global__ void __launch_bounds__(kPlThreads) k3_green_planes(int m, T cc, const
 // or the cube centres (c odd) at half indices (a>>1, b>>1), over the tile
 // plus a one-point halo (36 x 7 values), so each magenta value is loaded
 // once; face centres read their six magenta neighbours from there.
-constexpr int kMsW = kRdTX + 4, kMsH = kPlTY / 2 + 3, kMsN = kMsW * kMsH;
-static_assert(kMsN <= kPlThreads, "one staged magenta value per thread");
+constexpr int kMsW = kRdTX + 4, kMsH = kRdTY / 2 + 3, kMsN = kMsW * kMsH;
+constexpr int kMsP = (kMsN + kPlThreads - 1) / kPlThreads;   // staged magenta values per thread
 
 // staged magenta value e of plane c (0 outside the grid)
 template <typename T>
@@ -353,13 +354,13 @@ __global__ void __launch_bounds__(kPlThreads) k3_red_planes(int m, T c1, T c2, c
                                                              const Ctl* ctl)
 {
     DMG_GATE(ctl);
-    constexpr int W = kRdW, NP = (kPlH * kRdW + kPlThreads - 1) / kPlThreads;   // F slots per thread
-    constexpr int NO = kPlTY * kRdTX / kPlThreads;                              // outputs per thread
-    __shared__ T F[3][kPlH * kRdW];
+    constexpr int W = kRdW, NP = (kRdH * kRdW + kPlThreads - 1) / kPlThreads;   // F slots per thread
+    constexpr int NO = kRdTY * kRdTX / kPlThreads;                              // outputs per thread
+    __shared__ T F[3][kRdH * kRdW];
     __shared__ T M[3][kMsN];
     const int bid = xcd_block();   // tiles of one die are neighbours
     const int tx = bid % ntx, ty = (bid / ntx) % nty, tz = bid / (ntx * nty);
-    const int s0 = tx * kRdTX, y0 = 1 + ty * kPlTY, z0 = 1 + tz * zc;
+    const int s0 = tx * kRdTX, y0 = 1 + ty * kRdTY, z0 = 1 + tz * zc;
     const int z1 = min(z0 + zc, m);
     const int tid = threadIdx.x;
     const int iL = s0 - 2, jL = (y0 - 1) / 2 - 1;   // half indices of staged value 0
@@ -370,35 +371,44 @@ __global__ void __launch_bounds__(kPlThreads) k3_red_planes(int m, T c1, T c2, c
             const int p = tid + k * kPlThreads;
             int a, b;
             rf[k] = T(0);
-            if (p < kPlH * kRdW && red_fpoint(s0, y0, c, p, a, b) && a >= 1 && a < m && b >= 1 && b < m && c >= 1 &&
+            if (p < kRdH * kRdW && red_fpoint(s0, y0, c, p, a, b) && a >= 1 && a < m && b >= 1 && b < m && c >= 1 &&
                 c < m)
                 rf[k] = rR[idxR(m, a, b, c)];
         }
     };
     // prologue: magenta planes z0-2 and z0-1 into LDS (ring slot of plane c:
     // (c+3)%3), plane z0 and the F residuals of plane z0-1 into registers
-    {
-        const T a0 = red_mload(vE, vO, m, s0, y0, z0 - 2, tid), a1 = red_mload(vE, vO, m, s0, y0, z0 - 1, tid);
-        if (tid < kMsN) {
-            M[(z0 + 1) % 3][tid] = a0;
-            M[(z0 + 2) % 3][tid] = a1;
+#pragma unroll
+    for (int k = 0; k < kMsP; k++) {
+        const int e = tid + k * kPlThreads;
+        const T a0 = red_mload(vE, vO, m, s0, y0, z0 - 2, e), a1 = red_mload(vE, vO, m, s0, y0, z0 - 1, e);
+        if (e < kMsN) {
+            M[(z0 + 1) % 3][e] = a0;
+            M[(z0 + 2) % 3][e] = a1;
         }
     }
-    T mn = red_mload(vE, vO, m, s0, y0, z0, tid);
+    T mn[kMsP];
+#pragma unroll
+    for (int k = 0; k < kMsP; k++) mn[k] = red_mload(vE, vO, m, s0, y0, z0, tid + k * kPlThreads);
     T rf[NP];
     fload(z0 - 1, rf);
     T rn[NO];
 #pragma unroll
     for (int k = 0; k < NO; k++) rn[k] = T(0);
     for (int c = z0 - 1; c <= z1; c++) {
-        if (tid < kMsN) M[(c + 4) % 3][tid] = mn;   // magenta plane c+1
+#pragma unroll
+        for (int k = 0; k < kMsP; k++) {   // magenta plane c+1
+            const int e = tid + k * kPlThreads;
+            if (e < kMsN) M[(c + 4) % 3][e] = mn[k];
+        }
         T rfc[NP], rc[NO];
 #pragma unroll
         for (int k = 0; k < NP; k++) rfc[k] = rf[k];
 #pragma unroll
         for (int k = 0; k < NO; k++) rc[k] = rn[k];
         if (c + 1 <= z1) {
-            mn = red_mload(vE, vO, m, s0, y0, c + 2, tid);
+#pragma unroll
+            for (int k = 0; k < kMsP; k++) mn[k] = red_mload(vE, vO, m, s0, y0, c + 2, tid + k * kPlThreads);
             fload(c + 1, rf);
         }
         if (c >= z0 && c < z1) {   // corners of this plane need rR next iteration
@@ -420,7 +430,7 @@ __global__ void __launch_bounds__(kPlThreads) k3_red_planes(int m, T c1, T c2, c
             for (int k = 0; k < NP; k++) {
                 const int p = tid + k * kPlThreads;
                 int a, b;
-                if (p >= kPlH * kRdW || !red_fpoint(s0, y0, c, p, a, b)) continue;
+                if (p >= kRdH * kRdW || !red_fpoint(s0, y0, c, p, a, b)) continue;
                 T v = T(0);
                 if (a >= 1 && a < m && b >= 1 && b < m && c >= 1 && c < m) {
                     // staged position of half indices (i, j): (j - jL) * kMsW + (i - iL)
@@ -760,6 +770,7 @@ __global__ void __launch_bounds__(kPlThreads) k3_mag_planes(int m, T cc, const T
 }
 
 constexpr int kPlMinSide = 128;   // smaller levels: one thread per point
+constexpr int kRdPlMinSide = 128, kGrPlMinSide = 128;   // the red and green steps
 
 // z planes per workgroup (measured on MI355X at 257^3: 8 is best, longer
 // chunks leave too few workgroups in flight)
@@ -781,8 +792,8 @@ void launch_jac3(const Lev3<T>& L, const Lev3<T>& Cr, T* zero, const Ctl* ctl, h
             hipLaunchKernelGGL(k3_jac_mag<T>, g, dim3(256), 0, s, m, L.c, L.r, L.r2, vc, L.v, L.v2, ctl);
         }
     } else if (L.kind == 1) {
-        if (m >= kPlMinSide) {
-            int ntx = (m / 2 + kRdTX - 1) / kRdTX, nty = (m - 1 + kPlTY - 1) / kPlTY, zc = pl_zchunk(m);
+        if (m >= kRdPlMinSide) {
+            int ntx = (m / 2 + kRdTX - 1) / kRdTX, nty = (m - 1 + kRdTY - 1) / kRdTY, zc = pl_zchunk(m);
             int ntz = (m - 1 + zc - 1) / zc;
             hipLaunchKernelGGL(k3_red_planes<T>, dim3(ntx * nty * ntz), dim3(kPlThreads), 0, s, m, L.c, L.c2, L.r,
                                Cr.v, Cr.v2, L.v, ntx, nty, zc, ctl);
@@ -791,7 +802,7 @@ void launch_jac3(const Lev3<T>& L, const Lev3<T>& Cr, T* zero, const Ctl* ctl, h
             hipLaunchKernelGGL(k3_jac_red<T>, g, dim3(256), 0, s, m, L.c, L.c2, L.r, Cr.v, Cr.v2, L.v, ctl);
         }
     } else {
-        if (m >= kPlMinSide) {
+        if (m >= kGrPlMinSide) {
             int ntx = (m - 1 + kPlTX - 1) / kPlTX, nty = (m - 1 + kPlTY - 1) / kPlTY, zc = pl_zchunk(m);
             int ntz = (m - 1 + zc - 1) / zc;
             hipLaunchKernelGGL((k3_green_planes<T, false>), dim3(ntx * nty * ntz), dim3(kPlThreads), 0, s, m, L.c, L.r,
