@@ -20,6 +20,11 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed fp32 instructions are kept off: plain scalar/float2 code only
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # the first 16 kernel-argument dwords arrive in SGPRs: one dependent
+          # scalar load less at the start of every (mostly latency-bound) small
+          # kernel; the compiler keeps a prologue that loads them where the
+          # firmware does not preload
+          "-mllvm", "-amdgpu-kernarg-preload-count=16",
           "-I" + os.path.join(ROOT, "include")]
 
 
