@@ -520,184 +520,224 @@ __global__ void __launch_bounds__(256) kb_jac_axis(int m, T cc, const Item2<T>* 
 }
 
 // ------------------------------------------------------ mid levels, fused
-// A single problem with n >= 512 runs its levels of side 256 and 128
-// (aligned levels 14 .. 11) one thread per point: four restriction and four
-// Jacobi launches that are latency-bound.  These two kernels do the same
-// work in one launch each.  A workgroup owns a tile of the output and
-// recomputes in LDS the part of every intermediate level its tile depends
-// on (halo included); it writes only the points it owns.  Every value goes
-// through the same point arithmetic as the per-level kernels, so the results
-// are bit-identical to theirs.
-constexpr int kMidTiles = 8;   // tiles per side: 64 workgroups
+// A single problem with n >= 512 would run its levels of side 256 .. 64
+// (aligned levels 14 .. 9) one thread per point or inside the one-workgroup
+// coarse kernel: latency-bound steps.  These two kernels do that work in one
+// launch each.  A workgroup owns a tile of the output and recomputes in LDS
+// the part of every intermediate level its tile depends on (halo included);
+// it writes only the points it owns.  Every value goes through the same
+// point arithmetic as the per-level kernels, so the results are
+// bit-identical to theirs.  Regions are square [lo, lo + W) in a level's own
+// coordinates (diagonal levels use the points with an even index sum);
+// entries off the interior are 0, the boundary value.
+constexpr int kMidTiles = 8;        // tiles per side: 64 workgroups
 constexpr int kMidThreads = 1024;   // 16 waves: the level steps are latency-bound
 
-// restriction: r14 (axis 256) -> r13 (diagonal 256), r12 (axis 128),
-// r11 (diagonal 128), r10 (axis 64).  Tile (tx, ty) owns level-10 points
-// [8t+1, 8t+8], levels 12 and 11 [16t+1, 16t+16], level 13 [32t+1, 32t+32]
-// (in each level's own coordinates, interior points only).
 template <typename T>
-__global__ void __launch_bounds__(kMidThreads) kb_mid_down(const T* __restrict__ r14, T* __restrict__ r13, T* __restrict__ r12,
-                                                   T* __restrict__ r11, T* __restrict__ r10, const Ctl* __restrict__ ctl)
+struct MReg {   // a level's region in LDS
+    T* p;
+    int a0, b0, w;
+    __device__ T& at(int a, int b) const { return p[(b - b0) * w + (a - a0)]; }
+};
+
+// restriction steps region -> region (each point as rs2_a2d / rs2_d2a);
+// `own` points are also stored to the level's global array
+template <typename T, typename Own>
+__device__ inline void mid_a2d(const MReg<T>& in, const MReg<T>& out, int m, T* g, Own own)
+{
+    for (int q = threadIdx.x; q < out.w * out.w; q += blockDim.x) {
+        const int a = out.a0 + q % out.w, b = out.b0 + q / out.w;
+        T x = T(0);
+        if (a >= 1 && a < m && b >= 1 && b < m && !((a + b) & 1)) {
+            x = rs2_core(in.at(a, b), in.at(a - 1, b), in.at(a, b - 1), in.at(a + 1, b), in.at(a, b + 1));
+            if (own(a, b)) g[idxD(m, a, b)] = x;
+        }
+        out.p[q] = x;
+    }
+}
+template <typename T, typename Own>
+__device__ inline void mid_d2a(const MReg<T>& in, const MReg<T>& out, int mc, T* g, Own own)
+{
+    for (int q = threadIdx.x; q < out.w * out.w; q += blockDim.x) {
+        const int A = out.a0 + q % out.w, B = out.b0 + q / out.w;
+        T x = T(0);
+        if (A >= 1 && A < mc && B >= 1 && B < mc) {
+            const int a = 2 * A, b = 2 * B;
+            x = rs2_core(in.at(a, b), in.at(a - 1, b - 1), in.at(a + 1, b - 1), in.at(a + 1, b + 1), in.at(a - 1, b + 1));
+            if (own(A, B)) g[idxA(mc, A, B)] = x;
+        }
+        out.p[q] = x;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kMidThreads) kb_mid_down(const T* __restrict__ r14, T* __restrict__ r13,
+                                                           T* __restrict__ r12, T* __restrict__ r11, T* __restrict__ r10,
+                                                           T* __restrict__ r9, T* __restrict__ r8,
+                                                           const Ctl* __restrict__ ctl)
 {
     if (ctl->done) return;
-    constexpr int W13 = 39, W12 = 19, W11 = 17;
-    __shared__ T R13[W13 * W13], R12[W12 * W12], R11[W11 * W11];
+    constexpr int W13 = 51, W12 = 25, W11 = 23, W10 = 11, W9 = 9;
+    __shared__ T S13[W13 * W13], S12[W12 * W12], S11[W11 * W11], S10[W10 * W10], S9[W9 * W9];
     const int tx = blockIdx.x % kMidTiles, ty = blockIdx.x / kMidTiles;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    auto own = [](int a, int t, int s) { return a > s * t && a <= s * t + s; };
-    // level 13 on [32t-1, 32t+37] from level 14 (global)
-    const int a13 = 32 * tx - 1, b13 = 32 * ty - 1;
-    for (int q = tid; q < W13 * W13; q += nt) {
-        const int a = a13 + q % W13, b = b13 + q / W13;
+    // tile (tx, ty) owns level-8 points [4t+1, 4t+4], levels 10 and 9 [8t+1, 8t+8],
+    // 12 and 11 [16t+1, 16t+16], 13 [32t+1, 32t+32]
+    auto own = [tx, ty](int s) {
+        return [tx, ty, s](int a, int b) { return a > s * tx && a <= s * tx + s && b > s * ty && b <= s * ty + s; };
+    };
+    const MReg<T> R13{S13, 32 * tx - 5, 32 * ty - 5, W13}, R12{S12, 16 * tx - 2, 16 * ty - 2, W12};
+    const MReg<T> R11{S11, 16 * tx - 1, 16 * ty - 1, W11}, R10{S10, 8 * tx, 8 * ty, W10};
+    const MReg<T> R9{S9, 8 * tx + 1, 8 * ty + 1, W9};
+    // level 13 from level 14 (global), Eq. (Erest2r) as rs2_a2d
+    auto own13 = own(32);
+    for (int q = threadIdx.x; q < W13 * W13; q += blockDim.x) {
+        const int a = R13.a0 + q % W13, b = R13.b0 + q / W13;
         T x = T(0);
         if (a >= 1 && a <= 255 && b >= 1 && b <= 255 && !((a + b) & 1)) {
             x = rs2_a2d(r14, 256, a, b);
-            if (own(a, tx, 32) && own(b, ty, 32)) r13[idxD(256, a, b)] = x;
+            if (own13(a, b)) r13[idxD(256, a, b)] = x;
         }
-        R13[q] = x;
+        S13[q] = x;
     }
     __syncthreads();
-    // level 12 on [16t, 16t+18], Eq. (Erest2b) from level 13 (LDS)
-    const int a12 = 16 * tx, b12 = 16 * ty;
-    for (int q = tid; q < W12 * W12; q += nt) {
-        const int A = a12 + q % W12, B = b12 + q / W12;
-        T x = T(0);
-        if (A >= 1 && A <= 127 && B >= 1 && B <= 127) {
-            const int c = (2 * B - b13) * W13 + (2 * A - a13);
-            x = rs2_core(R13[c], R13[c - W13 - 1], R13[c - W13 + 1], R13[c + W13 + 1], R13[c + W13 - 1]);
-            if (own(A, tx, 16) && own(B, ty, 16)) r12[idxA(128, A, B)] = x;
-        }
-        R12[q] = x;
-    }
+    mid_d2a(R13, R12, 128, r12, own(16));
     __syncthreads();
-    // level 11 on [16t+1, 16t+17], Eq. (Erest2r) from level 12 (LDS)
-    const int a11 = 16 * tx + 1, b11 = 16 * ty + 1;
-    for (int q = tid; q < W11 * W11; q += nt) {
-        const int a = a11 + q % W11, b = b11 + q / W11;
-        T x = T(0);
-        if (a <= 127 && b <= 127 && !((a + b) & 1)) {
-            const int c = (b - b12) * W12 + (a - a12);
-            x = rs2_core(R12[c], R12[c - 1], R12[c - W12], R12[c + 1], R12[c + W12]);
-            if (own(a, tx, 16) && own(b, ty, 16)) r11[idxD(128, a, b)] = x;
-        }
-        R11[q] = x;
-    }
+    mid_a2d(R12, R11, 128, r11, own(16));
     __syncthreads();
-    // level 10, the tile itself, Eq. (Erest2b) from level 11 (LDS)
-    if (tid < 64) {
-        const int A = 8 * tx + 1 + tid % 8, B = 8 * ty + 1 + tid / 8;
-        if (A <= 63 && B <= 63) {
-            const int c = (2 * B - b11) * W11 + (2 * A - a11);
-            r10[idxA(64, A, B)] = rs2_core(R11[c], R11[c - W11 - 1], R11[c - W11 + 1], R11[c + W11 + 1], R11[c + W11 - 1]);
+    mid_d2a(R11, R10, 64, r10, own(8));
+    __syncthreads();
+    mid_a2d(R10, R9, 64, r9, own(8));
+    __syncthreads();
+    // level 8, the tile itself, Eq. (Erest2b)
+    if (threadIdx.x < 16) {
+        const int A = 4 * tx + 1 + threadIdx.x % 4, B = 4 * ty + 1 + threadIdx.x / 4;
+        if (A <= 31 && B <= 31) {
+            const int a = 2 * A, b = 2 * B;
+            r8[idxA(32, A, B)] = rs2_core(R9.at(a, b), R9.at(a - 1, b - 1), R9.at(a + 1, b - 1), R9.at(a + 1, b + 1),
+                                          R9.at(a - 1, b + 1));
         }
     }
 }
 
-// Jacobi up from v10 (axis 64): v11 (diagonal 128), v12 (axis 128), v13
-// (diagonal 256), v14 (axis 256).  Tile (tx, ty) owns level-14 points
-// [32t+1, 32t+32] and the same ownership as above below it.  Each level's
-// F points are computed over one point more than its C points need; LDS
-// entries off the interior stay 0 (the boundary values).
+// Jacobi steps on a region: F points over the whole region, then (after a
+// barrier) C points over the region less its border, from the stored F
+// values.  Diagonal levels: F from the coarser axis level `vc` (region, or
+// global when vcg is set), as jac2_diagF; axis levels: F from the diagonal
+// level of the same side, as jac2_axisF.  r: the level's global residual.
 template <typename T>
-__global__ void __launch_bounds__(kMidThreads) kb_mid_up(const T* __restrict__ v10, const T* __restrict__ r11,
-                                                 const T* __restrict__ r12, const T* __restrict__ r13,
-                                                 const T* __restrict__ r14, T* __restrict__ v11, T* __restrict__ v12,
-                                                 T* __restrict__ v13, T* __restrict__ v14, T c11, T c12, T c13, T c14,
-                                                 const Ctl* __restrict__ ctl)
+__device__ inline void mid_jdiag(const MReg<T>& L, const MReg<T>* vc, const T* vcg, const T* r, int m, T cc)
+{
+    const int w = m / 2 + 1;
+    for (int q = threadIdx.x; q < L.w * L.w; q += blockDim.x) {
+        const int a = L.a0 + q % L.w, b = L.b0 + q / L.w;
+        if (a >= 1 && a < m && b >= 1 && b < m && (a & b & 1)) {
+            if (vcg) {
+                L.p[q] = jac2_diagF(r, vcg, m, cc, a, b);
+            } else {
+                const int A0 = (a - 1) >> 1, B0 = (b - 1) >> 1;
+                L.p[q] = jac2_chain(cc, r[b * w + (a >> 1)], vc->at(A0, B0), vc->at(A0 + 1, B0), vc->at(A0 + 1, B0 + 1),
+                                    vc->at(A0, B0 + 1));
+            }
+        }
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < L.w * L.w; q += blockDim.x) {
+        const int la = q % L.w, lb = q / L.w, a = L.a0 + la, b = L.b0 + lb;
+        if (la >= 1 && la < L.w - 1 && lb >= 1 && lb < L.w - 1 && a >= 1 && a < m && b >= 1 && b < m && !((a | b) & 1))
+            L.p[q] = jac2_sum(cc, r[b * w + (a >> 1)], L.p[q - L.w - 1], L.p[q - L.w + 1], L.p[q + L.w + 1],
+                              L.p[q + L.w - 1]);
+    }
+    __syncthreads();
+}
+template <typename T>
+__device__ inline void mid_jaxis(const MReg<T>& L, const MReg<T>& vd, const T* r, int m, T cc)
+{
+    const int w = m + 1;
+    for (int q = threadIdx.x; q < L.w * L.w; q += blockDim.x) {
+        const int a = L.a0 + q % L.w, b = L.b0 + q / L.w;
+        if (a >= 1 && a < m && b >= 1 && b < m && ((a + b) & 1))
+            L.p[q] = jac2_sum(cc, r[b * w + a], vd.at(a - 1, b), vd.at(a, b - 1), vd.at(a + 1, b), vd.at(a, b + 1));
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < L.w * L.w; q += blockDim.x) {
+        const int la = q % L.w, lb = q / L.w, a = L.a0 + la, b = L.b0 + lb;
+        if (la >= 1 && la < L.w - 1 && lb >= 1 && lb < L.w - 1 && a >= 1 && a < m && b >= 1 && b < m && !((a + b) & 1))
+            L.p[q] = jac2_sum(cc, r[b * w + a], L.p[q - 1], L.p[q - L.w], L.p[q + 1], L.p[q + L.w]);
+    }
+    __syncthreads();
+}
+
+// Jacobi up from v8 (axis 32) through v9 (diagonal 64), v10 (axis 64), v11
+// (diagonal 128), v12 (axis 128), v13 (diagonal 256) to v14 (axis 256).
+// Tile (tx, ty) owns level-14 and 13 points [32t+1, 32t+32], levels 12 and
+// 11 [16t+1, 16t+16], levels 10 and 9 [8t+1, 8t+8].  r[k], v[k], c[k]:
+// level 9 + k.
+template <typename T>
+struct MidUp {
+    const T* r[6];
+    T* v[6];
+    T c[6];
+};
+template <typename T>
+__global__ void __launch_bounds__(kMidThreads) kb_mid_up(const T* __restrict__ v8, MidUp<T> L, const Ctl* __restrict__ ctl)
 {
     if (ctl->done) return;
-    constexpr int W11 = 26, W12 = 22, W13 = 38, W14 = 34;
-    __shared__ T L11[W11 * W11], L12[W12 * W12], L13[W13 * W13], L14[W14 * W14];
+    constexpr int W9 = 20, W10 = 16, W11 = 26, W12 = 22, W13 = 38, W14 = 34;
+    __shared__ T S9[W9 * W9], S10[W10 * W10], S11[W11 * W11], S12[W12 * W12], S13[W13 * W13], S14[W14 * W14];
     const int tx = blockIdx.x % kMidTiles, ty = blockIdx.x / kMidTiles;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    auto own = [](int a, int t, int s) { return a > s * t && a <= s * t + s; };
-    for (int q = tid; q < W13 * W13; q += nt) {
-        L13[q] = T(0);
-        if (q < W11 * W11) L11[q] = T(0);
-        if (q < W12 * W12) L12[q] = T(0);
-        if (q < W14 * W14) L14[q] = T(0);
+    const MReg<T> L9{S9, 8 * tx - 5, 8 * ty - 5, W9}, L10{S10, 8 * tx - 3, 8 * ty - 3, W10};
+    const MReg<T> L11{S11, 16 * tx - 4, 16 * ty - 4, W11}, L12{S12, 16 * tx - 2, 16 * ty - 2, W12};
+    const MReg<T> L13{S13, 32 * tx - 2, 32 * ty - 2, W13}, L14{S14, 32 * tx, 32 * ty, W14};
+    for (int q = threadIdx.x; q < W13 * W13; q += blockDim.x) {
+        S13[q] = T(0);
+        if (q < W9 * W9) S9[q] = T(0);
+        if (q < W10 * W10) S10[q] = T(0);
+        if (q < W11 * W11) S11[q] = T(0);
+        if (q < W12 * W12) S12[q] = T(0);
+        if (q < W14 * W14) S14[q] = T(0);
     }
     __syncthreads();
-    // level 11: F on [16t-4, 16t+21] from v10 (global), C on [16t-3, 16t+20]
-    const int a11 = 16 * tx - 4, b11 = 16 * ty - 4;
-    for (int q = tid; q < W11 * W11; q += nt) {
-        const int a = a11 + q % W11, b = b11 + q / W11;
-        if (a >= 1 && a <= 127 && b >= 1 && b <= 127 && (a & b & 1)) L11[q] = jac2_diagF(r11, v10, 128, c11, a, b);
-    }
-    __syncthreads();
-    for (int q = tid; q < W11 * W11; q += nt) {
-        const int la = q % W11, lb = q / W11, a = a11 + la, b = b11 + lb;
-        if (la >= 1 && la < W11 - 1 && lb >= 1 && lb < W11 - 1 && a >= 1 && a <= 127 && b >= 1 && b <= 127 &&
-            !((a | b) & 1))
-            L11[q] = jac2_sum(c11, r11[idxD(128, a, b)], L11[q - W11 - 1], L11[q - W11 + 1], L11[q + W11 + 1],
-                              L11[q + W11 - 1]);
-    }
-    __syncthreads();
-    // level 12: F on [16t-2, 16t+19] from level 11, C on [16t-1, 16t+18]
-    const int a12 = 16 * tx - 2, b12 = 16 * ty - 2;
-    for (int q = tid; q < W12 * W12; q += nt) {
-        const int a = a12 + q % W12, b = b12 + q / W12;
-        if (a >= 1 && a <= 127 && b >= 1 && b <= 127 && ((a + b) & 1)) {
-            const int c = (b - b11) * W11 + (a - a11);
-            L12[q] = jac2_sum(c12, r12[idxA(128, a, b)], L11[c - 1], L11[c - W11], L11[c + 1], L11[c + W11]);
-        }
-    }
-    __syncthreads();
-    for (int q = tid; q < W12 * W12; q += nt) {
-        const int la = q % W12, lb = q / W12, a = a12 + la, b = b12 + lb;
-        if (la >= 1 && la < W12 - 1 && lb >= 1 && lb < W12 - 1 && a >= 1 && a <= 127 && b >= 1 && b <= 127 &&
-            !((a + b) & 1))
-            L12[q] = jac2_sum(c12, r12[idxA(128, a, b)], L12[q - 1], L12[q - W12], L12[q + 1], L12[q + W12]);
-    }
-    __syncthreads();
-    // owned points of levels 11 and 12
-    for (int q = tid; q < 16 * 16; q += nt) {
+    mid_jdiag(L9, (const MReg<T>*)nullptr, v8, L.r[0], 64, L.c[0]);
+    mid_jaxis(L10, L9, L.r[1], 64, L.c[1]);
+    mid_jdiag(L11, &L10, (const T*)nullptr, L.r[2], 128, L.c[2]);
+    mid_jaxis(L12, L11, L.r[3], 128, L.c[3]);
+    // owned points of levels 9 .. 12
+    for (int q = threadIdx.x; q < 16 * 16; q += blockDim.x) {
         const int a = 16 * tx + 1 + q % 16, b = 16 * ty + 1 + q / 16;
         if (a <= 127 && b <= 127) {
-            if (!((a + b) & 1)) v11[idxD(128, a, b)] = L11[(b - b11) * W11 + (a - a11)];
-            v12[idxA(128, a, b)] = L12[(b - b12) * W12 + (a - a12)];
+            if (!((a + b) & 1)) L.v[2][idxD(128, a, b)] = L11.at(a, b);
+            L.v[3][idxA(128, a, b)] = L12.at(a, b);
+        }
+        if (q < 64) {
+            const int a8 = 8 * tx + 1 + q % 8, b8 = 8 * ty + 1 + q / 8;
+            if (a8 <= 63 && b8 <= 63) {
+                if (!((a8 + b8) & 1)) L.v[0][idxD(64, a8, b8)] = L9.at(a8, b8);
+                L.v[1][idxA(64, a8, b8)] = L10.at(a8, b8);
+            }
         }
     }
-    // level 13: F on [32t-2, 32t+35] from level 12, C on [32t-1, 32t+34]
-    const int a13 = 32 * tx - 2, b13 = 32 * ty - 2;
-    for (int q = tid; q < W13 * W13; q += nt) {
-        const int a = a13 + q % W13, b = b13 + q / W13;
-        if (a >= 1 && a <= 255 && b >= 1 && b <= 255 && (a & b & 1)) {
-            const int c = (((b - 1) >> 1) - b12) * W12 + (((a - 1) >> 1) - a12);   // v12((a-1)/2, (b-1)/2)
-            L13[q] = jac2_chain(c13, r13[idxD(256, a, b)], L12[c], L12[c + 1], L12[c + W12 + 1], L12[c + W12]);
-        }
-    }
-    __syncthreads();
-    for (int q = tid; q < W13 * W13; q += nt) {
-        const int la = q % W13, lb = q / W13, a = a13 + la, b = b13 + lb;
-        if (la >= 1 && la < W13 - 1 && lb >= 1 && lb < W13 - 1 && a >= 1 && a <= 255 && b >= 1 && b <= 255 &&
-            !((a | b) & 1))
-            L13[q] = jac2_sum(c13, r13[idxD(256, a, b)], L13[q - W13 - 1], L13[q - W13 + 1], L13[q + W13 + 1],
-                              L13[q + W13 - 1]);
-    }
-    __syncthreads();
+    mid_jdiag(L13, &L12, (const T*)nullptr, L.r[4], 256, L.c[4]);
     // level 14: F on [32t, 32t+33] from level 13; owned points of level 13
-    const int a14 = 32 * tx, b14 = 32 * ty;
-    for (int q = tid; q < W14 * W14; q += nt) {
-        const int a = a14 + q % W14, b = b14 + q / W14;
-        if (a >= 1 && a <= 255 && b >= 1 && b <= 255 && ((a + b) & 1)) {
-            const int c = (b - b13) * W13 + (a - a13);
-            L14[q] = jac2_sum(c14, r14[idxA(256, a, b)], L13[c - 1], L13[c - W13], L13[c + 1], L13[c + W13]);
-        }
+    const T* r14 = L.r[5];
+    for (int q = threadIdx.x; q < W14 * W14; q += blockDim.x) {
+        const int a = L14.a0 + q % W14, b = L14.b0 + q / W14;
+        if (a >= 1 && a <= 255 && b >= 1 && b <= 255 && ((a + b) & 1))
+            S14[q] = jac2_sum(L.c[5], r14[idxA(256, a, b)], L13.at(a - 1, b), L13.at(a, b - 1), L13.at(a + 1, b),
+                              L13.at(a, b + 1));
     }
-    for (int q = tid; q < 32 * 32; q += nt) {
+    for (int q = threadIdx.x; q < 32 * 32; q += blockDim.x) {
         const int a = 32 * tx + 1 + q % 32, b = 32 * ty + 1 + q / 32;
-        if (a <= 255 && b <= 255 && !((a + b) & 1)) v13[idxD(256, a, b)] = L13[(b - b13) * W13 + (a - a13)];
+        if (a <= 255 && b <= 255 && !((a + b) & 1)) L.v[4][idxD(256, a, b)] = L13.at(a, b);
     }
     __syncthreads();
     // level 14, the tile: F from LDS, C from its four F neighbours
-    for (int q = tid; q < 32 * 32; q += nt) {
+    for (int q = threadIdx.x; q < 32 * 32; q += blockDim.x) {
         const int a = 32 * tx + 1 + q % 32, b = 32 * ty + 1 + q / 32;
         if (a > 255 || b > 255) continue;
-        const int c = (b - b14) * W14 + (a - a14);
-        v14[idxA(256, a, b)] = ((a + b) & 1) ? L14[c]
-                                             : jac2_sum(c14, r14[idxA(256, a, b)], L14[c - 1], L14[c - W14],
-                                                        L14[c + 1], L14[c + W14]);
+        L.v[5][idxA(256, a, b)] =
+            ((a + b) & 1) ? L14.at(a, b)
+                          : jac2_sum(L.c[5], r14[idxA(256, a, b)], L14.at(a - 1, b), L14.at(a, b - 1), L14.at(a + 1, b),
+                                     L14.at(a, b + 1));
     }
 }
 
@@ -711,6 +751,7 @@ __global__ void __launch_bounds__(kMidThreads) kb_mid_up(const T* __restrict__ v
 template <typename T>
 struct CoarseLev {
     LevInfo<T> l[kCoarseLevels];
+    int top_cap;   // highest level run here (levels above it run in the fused mid-level kernels)
 };
 constexpr int kCoarseThreadsB = 1024;
 
@@ -836,7 +877,8 @@ __global__ void __launch_bounds__(kCoarseThreadsB) kb_coarse(CoarseLev<T> L, con
     ITEM_GATE(ctls, it.prob);
     const int tid = threadIdx.x, nt = blockDim.x;
     const GLevs<T> G{it, zero};
-    const int st = min(it.top, kCoarseLdsTop);   // highest staged level
+    const int top = min(it.top, L.top_cap);
+    const int st = min(top, kCoarseLdsTop);      // highest staged level
     if (tid == 0) {
         int o = 0;
         for (int l = 0; l <= st; l++) {
@@ -846,7 +888,7 @@ __global__ void __launch_bounds__(kCoarseThreadsB) kb_coarse(CoarseLev<T> L, con
     }
     __syncthreads();
     // global part of the restriction: into levels top-1 .. st
-    coarse_down(L, G, it.top, st);
+    coarse_down(L, G, top, st);
     // stage r of level st; zero the other staged arrays (boundary entries
     // stay 0) and the zero correction below level 0
     const int nst = off[st] + lev2_points(L.l[st]);
@@ -868,7 +910,7 @@ __global__ void __launch_bounds__(kCoarseThreadsB) kb_coarse(CoarseLev<T> L, con
         it.v[l][k] = lds[kCoarseLdsPts + q];
     }
     __syncthreads();
-    coarse_up(L, G, st + 1, it.top);
+    coarse_up(L, G, st + 1, top);
 }
 
 // ------------------------------------------------- learned coarse correction
@@ -958,7 +1000,7 @@ __global__ void __launch_bounds__(kCoarseThreadsB) kb_coarse_net(CoarseLev<T> L,
     const Coarse2B<T>& it = items[blockIdx.x];
     ITEM_GATE(ctls, it.prob);
     Ctl* c = &ctls[it.prob];
-    const int top = it.top, cut = kNetCut;
+    const int top = min(it.top, L.top_cap), cut = kNetCut;
     const int state = top >= cut ? c->net : 0;
     const GLevs<T> S{it, zero};
     if (state == 0) {
@@ -1303,33 +1345,41 @@ void launch_b_jacobi(int diag, int m, int rows, T c, const Item2<T>* items, int 
 }
 
 template <typename T>
-void launch_b_mid_down(const T* r14, T* r13, T* r12, T* r11, T* r10, const Ctl* ctl, hipStream_t s)
+void launch_b_mid_down(const T* r14, T* const* r, const Ctl* ctl, hipStream_t s)
 {
-    hipLaunchKernelGGL(kb_mid_down<T>, dim3(kMidTiles * kMidTiles), dim3(kMidThreads), 0, s, r14, r13, r12, r11, r10, ctl);
+    hipLaunchKernelGGL(kb_mid_down<T>, dim3(kMidTiles * kMidTiles), dim3(kMidThreads), 0, s, r14, r[5], r[4], r[3],
+                       r[2], r[1], r[0], ctl);
 }
 
 template <typename T>
-void launch_b_mid_up(const T* v10, const T* const* r, T* const* v, const T* c, const Ctl* ctl, hipStream_t s)
+void launch_b_mid_up(const T* v8, const T* const* r, T* const* v, const T* c, const Ctl* ctl, hipStream_t s)
 {
-    hipLaunchKernelGGL(kb_mid_up<T>, dim3(kMidTiles * kMidTiles), dim3(kMidThreads), 0, s, v10, r[0], r[1], r[2], r[3], v[0],
-                       v[1], v[2], v[3], c[0], c[1], c[2], c[3], ctl);
+    MidUp<T> L;
+    for (int k = 0; k < 6; k++) {
+        L.r[k] = r[k];
+        L.v[k] = v[k];
+        L.c[k] = c[k];
+    }
+    hipLaunchKernelGGL(kb_mid_up<T>, dim3(kMidTiles * kMidTiles), dim3(kMidThreads), 0, s, v8, L, ctl);
 }
 
 template <typename T>
 void launch_b_coarse(const LevInfo<T>* lev, const Coarse2B<T>* items, int nitems, const T* zero, const Ctl* ctls,
-                     hipStream_t s)
+                     hipStream_t s, int top_cap)
 {
     CoarseLev<T> L;
     for (int i = 0; i < kCoarseLevels; i++) L.l[i] = lev[i];
+    L.top_cap = top_cap;
     hipLaunchKernelGGL(kb_coarse<T>, dim3(nitems), dim3(kCoarseThreadsB), 0, s, L, items, zero, ctls);
 }
 
 template <typename T>
 void launch_b_coarse_net(const LevInfo<T>* lev, const Coarse2B<T>* items, int nitems, const T* zero, Ctl* ctls,
-                         const bf16_t* wf, hipStream_t s)
+                         const bf16_t* wf, hipStream_t s, int top_cap)
 {
     CoarseLev<T> L;
     for (int i = 0; i < kCoarseLevels; i++) L.l[i] = lev[i];
+    L.top_cap = top_cap;
     hipLaunchKernelGGL(kb_coarse_net<T>, dim3(nitems), dim3(kCoarseThreadsB), 0, s, L, items, zero, ctls, wf);
 }
 
@@ -1339,13 +1389,14 @@ void launch_b_coarse_net(const LevInfo<T>* lev, const Coarse2B<T>* items, int ni
     template void launch_b_finest<T>(int, T, const Fin2<T>*, int, const Ctl*, hipStream_t);                    \
     template void launch_b_restrict<T>(int, int, int, const Item2<T>*, int, const Ctl*, hipStream_t);          \
     template void launch_b_jacobi<T>(int, int, int, T, const Item2<T>*, int, const Ctl*, hipStream_t);         \
-    template void launch_b_coarse<T>(const LevInfo<T>*, const Coarse2B<T>*, int, const T*, const Ctl*, hipStream_t); \
+    template void launch_b_coarse<T>(const LevInfo<T>*, const Coarse2B<T>*, int, const T*, const Ctl*, hipStream_t, \
+                                     int);                                                                    \
     template void launch_b_finalize<T>(int, const Fin2<T>*, int, int, Ctl*, int*, hipStream_t);                \
     template void launch_b_level_get<T>(int, int, const T*, double*, hipStream_t);                           \
     template void launch_b_coarse_net<T>(const LevInfo<T>*, const Coarse2B<T>*, int, const T*, Ctl*, const bf16_t*, \
-                                         hipStream_t);                                                          \
+                                         hipStream_t, int);                                                     \
     template void launch_b_coarse_export<T>(int, int, int, const Coarse2B<T>*, int, double*, hipStream_t);       \
-    template void launch_b_mid_down<T>(const T*, T*, T*, T*, T*, const Ctl*, hipStream_t);                     \
+    template void launch_b_mid_down<T>(const T*, T* const*, const Ctl*, hipStream_t);                         \
     template void launch_b_mid_up<T>(const T*, const T* const*, T* const*, const T*, const Ctl*, hipStream_t);
 DMG_INSTB(double)
 DMG_INSTB(float)

@@ -62,8 +62,9 @@ template <typename T>
 void launch_b_jacobi(int diag, int m, int rows, T c, const Item2<T>* items, int nitems, const Ctl* ctls,
                      hipStream_t s);
 template <typename T>
+// top_cap: highest level the coarse kernel runs (below each item's top)
 void launch_b_coarse(const LevInfo<T>* lev, const Coarse2B<T>* items, int nitems, const T* zero, const Ctl* ctls,
-                     hipStream_t s);
+                     hipStream_t s, int top_cap = kCoarseLevels);
 // sum of f^2 over interior nodes per problem, into the problem's partials (b_resid_parts(n) of them)
 template <typename T>
 void launch_b_sumsq(int n, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s);
@@ -75,15 +76,16 @@ void launch_b_ctl_reset(Ctl* ctls, int nprob, int mode, int max_cycles, double r
 // the coarse kernel with the learned correction at the cut level (wf: packed forward weights)
 template <typename T>
 void launch_b_coarse_net(const LevInfo<T>* lev, const Coarse2B<T>* items, int nitems, const T* zero, Ctl* ctls,
-                         const unsigned short* wf, hipStream_t s);
-// A single problem's aligned levels 14 .. 11 (sides 256 and 128) in one
-// launch each way: restriction r14 -> r13, r12, r11, r10; Jacobi from v10
-// up to v11 .. v14 (r[k], v[k], c[k]: level 11 + k).  Needs n >= 512.
-constexpr int kMidTop = 14, kMidLow = 10;
+                         const unsigned short* wf, hipStream_t s, int top_cap = kCoarseLevels);
+// A single problem's aligned levels 14 .. 9 (sides 256 .. 64) in one launch
+// each way: restriction r14 -> r13 .. r8 (r[k]: level 8 + k); Jacobi from
+// v8 up to v9 .. v14 (r[k], v[k], c[k]: level 9 + k).  The coarse kernel
+// then runs levels 8 .. 0 only.  Needs n >= 512.
+constexpr int kMidTop = 14, kMidLow = 10, kMidCoarseTop = 8;
 template <typename T>
-void launch_b_mid_down(const T* r14, T* r13, T* r12, T* r11, T* r10, const Ctl* ctl, hipStream_t s);
+void launch_b_mid_down(const T* r14, T* const* r, const Ctl* ctl, hipStream_t s);
 template <typename T>
-void launch_b_mid_up(const T* v10, const T* const* r, T* const* v, const T* c, const Ctl* ctl, hipStream_t s);
+void launch_b_mid_up(const T* v8, const T* const* r, T* const* v, const T* c, const Ctl* ctl, hipStream_t s);
 template <typename T>
 void launch_b_coarse_export(int lam, int diag, int m, const Coarse2B<T>* items, int nitems, double* dst, hipStream_t s);
 template <typename T>

@@ -279,8 +279,10 @@ void enq_cycle(Plan2& P, Ctl* ctls)
             if (lam == kMidTop - 1) {
                 double b = 0;
                 for (int l = kMidLow; l < kMidTop; l++) b += bytes_rs((l + 1) & 1, side_of(l + 1), es);
+                for (int l = kMidCoarseTop; l < kMidLow; l++) b += bytes_rs((l + 1) & 1, side_of(l + 1), es);
                 Timed t(&P.tm, MG_K_RESTRICT, b);
-                launch_b_mid_down<T>(R(14), R(13), R(12), R(11), R(10), ctls, P.stream);
+                T* r[6] = {R(8), R(9), R(10), R(11), R(12), R(13)};
+                launch_b_mid_down<T>(R(14), r, ctls, P.stream);
             }
             continue;
         }
@@ -296,18 +298,20 @@ void enq_cycle(Plan2& P, Ctl* ctls)
             lev[lam].m = side_of(lam);
             lev[lam].diag = lam & 1;
             lev[lam].c = (T)coef(P, lam);
-            if (lam <= P.lamc) {
+            const int ctop = mid ? kMidCoarseTop : P.lamc;
+            if (lam <= ctop) {
                 cb += bytes_jac(lam & 1, side_of(lam), es);
-                if (lam < P.lamc) cb += bytes_rs((lam + 1) & 1, side_of(lam + 1), es);
+                if (lam < ctop) cb += bytes_rs((lam + 1) & 1, side_of(lam + 1), es);
             }
         }
         Timed t(&P.tm, MG_K_COARSE, cb * P.n_coarse_items);
+        const int cap = mid ? kMidCoarseTop : kCoarseLevels;
         if (P.has_net)
             launch_b_coarse_net<T>(lev, at<Coarse2B<T>>(P, P.off_coarse), P.n_coarse_items, at<T>(P, P.off_zero), ctls,
-                                   at<bf16_t>(P, P.off_net), P.stream);
+                                   at<bf16_t>(P, P.off_net), P.stream, cap);
         else
             launch_b_coarse<T>(lev, at<Coarse2B<T>>(P, P.off_coarse), P.n_coarse_items, at<T>(P, P.off_zero), ctls,
-                               P.stream);
+                               P.stream, cap);
     }
     for (int lam = 0; lam <= P.Dmax; lam++) {
         int k = P.n_jac_items[lam];
@@ -315,12 +319,13 @@ void enq_cycle(Plan2& P, Ctl* ctls)
         if (mid && lam > kMidLow && lam <= kMidTop) {
             if (lam == kMidLow + 1) {
                 double b = 0;
-                for (int l = kMidLow + 1; l <= kMidTop; l++) b += bytes_jac(l & 1, side_of(l), es);
+                for (int l = kMidCoarseTop + 1; l <= kMidTop; l++) b += bytes_jac(l & 1, side_of(l), es);
                 Timed t(&P.tm, MG_K_JACOBI, b);
-                const T* r[4] = {R(11), R(12), R(13), R(14)};
-                T* v[4] = {V(11), V(12), V(13), V(14)};
-                const T c[4] = {(T)coef(P, 11), (T)coef(P, 12), (T)coef(P, 13), (T)coef(P, 14)};
-                launch_b_mid_up<T>(V(10), r, v, c, ctls, P.stream);
+                const T* r[6] = {R(9), R(10), R(11), R(12), R(13), R(14)};
+                T* v[6] = {V(9), V(10), V(11), V(12), V(13), V(14)};
+                T c[6];
+                for (int k = 0; k < 6; k++) c[k] = (T)coef(P, 9 + k);
+                launch_b_mid_up<T>(V(8), r, v, c, ctls, P.stream);
             }
             continue;
         }
