@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(kRowBlock) kb_resid(int m, double inv_h2, cons
                 T rn = q ? r1j : r0j;
                 int a = 2 * t + q;
                 if (useful && a >= 1 && a <= m - 1)
-                    rD[(size_t)(j - 1) * W + t] = (4 * rc + rw + rs + re + rn) * T(0.125);
+                    rD[(size_t)(j - 1) * W + t] = rs2_core(rc, rw, rs, re, rn);
             }
             rm2_0 = rm1_0; rm2_1 = rm1_1; rm1_0 = r0j; rm1_1 = r1j;
             um0 = uc0; um1 = uc1; uc0 = up0; uc1 = up1; up0 = c.ux[i]; up1 = c.uy[i];
@@ -224,13 +224,13 @@ __device__ inline void jaxis_body(int m, T cc, const T* __restrict__ rA, const T
             T vw = q ? nb : d0;
             T ve = q ? d0 : nb;
             int aF = 2 * t + 1 - q;
-            T Fj = (aF >= 1 && aF <= m - 1 && j >= 1 && j <= m - 1) ? (-cc * rF + vw + dm + ve + dp) * T(0.25) : T(0);
+            T Fj = (aF >= 1 && aF <= m - 1 && j >= 1 && j <= m - 1) ? jac2_sum(cc, rF, vw, dm, ve, dp) : T(0);
             if (j - 1 >= y0) {
                 int qq = (j - 1) & 1;
                 T sb = qq ? __shfl_down(Fm1, 1) : __shfl_up(Fm1, 1);
                 T cw = qq ? Fm1 : sb;
                 T ce = qq ? sb : Fm1;
-                T C = (-cc * rCm1 + cw + Fm2 + ce + Fj) * T(0.25);
+                T C = jac2_sum(cc, rCm1, cw, Fm2, ce, Fj);
                 T vx = qq ? Fm1 : C;  // column 2t
                 T vy = qq ? C : Fm1;  // column 2t+1
                 size_t o = (size_t)(j - 1) * w + 2 * t;
@@ -331,7 +331,7 @@ __global__ void __launch_bounds__(kRowBlock) kb_a2d_rows(int m, const Item2<T>* 
             T rs = q ? rm1 : rm0;
             T rn = q ? c.y[i] : c.x[i];
             int a = 2 * t + q;
-            if (useful && a >= 1 && a <= m - 1) rD[(size_t)j * W + t] = (4 * rc + rw + rs + re + rn) * T(0.125);
+            if (useful && a >= 1 && a <= m - 1) rD[(size_t)j * W + t] = rs2_core(rc, rw, rs, re, rn);
             rm0 = rc0; rm1 = rc1; rc0 = c.x[i]; rc1 = c.y[i];
         }
     };
@@ -378,7 +378,7 @@ __global__ void __launch_bounds__(kRowBlock) kb_d2a_rows(int m, const Item2<T>* 
             T hi = q.h[i];
             T lo_w = __shfl_up(lo, 1), hi_w = __shfl_up(hi, 1);
             // 4 r(2A,2B) + r(2A-1,2B-1) + r(2A+1,2B-1) + r(2A+1,2B+1) + r(2A-1,2B+1)
-            if (useful) rA2[(size_t)B * (mc + 1) + A] = (4 * q.c[i] + lo_w + lo + hi + hi_w) * T(0.125);
+            if (useful) rA2[(size_t)B * (mc + 1) + A] = rs2_core(q.c[i], lo_w, lo, hi, hi_w);
             lo = hi;
         }
     };
@@ -419,7 +419,7 @@ __global__ void __launch_bounds__(kRowBlock) kb_jdiag_rows(int m, T cc, const It
         T vn = ldv(B0, true);
         T rf = ldr(2 * B0 - 1, true);
         T vb_e = __shfl_down(vb, 1), vn_e = __shfl_down(vn, 1);
-        Fprev = (-cc * rf + vb + vb_e + vn_e + vn) * T(0.25);
+        Fprev = jac2_chain(cc, rf, vb, vb_e, vn_e, vn);
         vb = vn;
     }
     struct Ck { T v[CH], rf[CH], rc[CH]; };
@@ -441,11 +441,11 @@ __global__ void __launch_bounds__(kRowBlock) kb_jdiag_rows(int m, T cc, const It
             T vn = q.v[i];
             T vb_e = __shfl_down(vb, 1), vn_e = __shfl_down(vn, 1);
             // v_{i-1,j-1} + v_{i+1,j-1} + v_{i+1,j+1} + v_{i-1,j+1} on the coarse grid
-            T F = (-cc * q.rf[i] + vb + vb_e + vn_e + vn) * T(0.25);
+            T F = jac2_chain(cc, q.rf[i], vb, vb_e, vn_e, vn);
             T Fw = __shfl_up(F, 1), Fpw = __shfl_up(Fprev, 1);
             if (useful) {
                 vD[(size_t)(2 * B + 1) * W + A] = F;
-                if (B >= 1 && A >= 1) vD[(size_t)(2 * B) * W + A] = (-cc * q.rc[i] + Fpw + Fprev + F + Fw) * T(0.25);
+                if (B >= 1 && A >= 1) vD[(size_t)(2 * B) * W + A] = jac2_sum(cc, q.rc[i], Fpw, Fprev, F, Fw);
             }
             Fprev = F;
             vb = vn;

@@ -36,7 +36,7 @@ def relerr(a, b):
     return np.abs(a - b).max() / (den if den > 0 else 1.0)
 
 
-NS = [8, 64, 16, 512, 64, 128, 2, 4, 256]
+NS = [8, 64, 16, 512, 64, 128, 2, 4, 256, 1024]
 
 
 def problems(ns, seed=4):
