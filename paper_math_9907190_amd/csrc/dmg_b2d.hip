@@ -263,6 +263,139 @@ __global__ void __launch_bounds__(kRowBlock) kb_finest(int m, T cc, const Fin2<T
     jaxis_body<T, true, CH, NT>(m, cc, it.r0, it.v1, nullptr, it.u, nwx, nwaves, rows);
 }
 
+// Finest axis Jacobi fused with the Jacobi of the first diagonal level
+// (level D-1, Eqs. (Eajacr), (Eajacb)) and with u <- u + v (Section 1).  The
+// diagonal level's new values are computed in the row march instead of being
+// stored by one kernel and read by the next: a lane's diagonal point of row
+// k is (2t + (k&1), k); F points (odd rows) come from two rows of the
+// coarser axis level v2 (columns t, t+1), C points (even rows) from the F
+// values of the rows above and below (lanes t-1, t), so the F row k+1 is
+// computed one row ahead.  These extra neighbour dependencies leave lanes
+// 2 .. 61 to write u (lanes 0, 1, 62, 63 are halo).  Same arithmetic cores
+// as the per-level kernels: the results are bit-identical to running the
+// diagonal Jacobi and then kb_finest.
+constexpr int kFusePairs = 60;
+
+template <typename T, bool NT>
+__global__ void __launch_bounds__(kRowBlock) kb_finest_fused(int m, T cc, T cd, const Fin2<T>* __restrict__ items,
+                                                             int nwx, int nwaves, int rows, const Ctl* __restrict__ ctls)
+{
+    const Fin2<T> it = items[blockIdx.y];
+    ITEM_GATE(ctls, it.prob);
+    const T* __restrict__ rA = it.r0;
+    const T* __restrict__ r1 = it.r1;
+    const T* __restrict__ v2 = it.v2;
+    double* __restrict__ u = it.u;
+    const int lane = threadIdx.x & 63;
+    const int wv = rows_wave_id(nwaves);
+    if (wv >= nwaves) return;
+    const int wx = wv % nwx, sy = wv / nwx;
+    const int t = wx * kFusePairs - 2 + lane;
+    const int y0 = 1 + sy * rows;
+    const int y1 = min(y0 + rows, m);
+    const int h = m / 2, W = h + 1;   // row length of the diagonal level and of v2 (side m/2)
+    const bool useful = lane >= 2 && lane < kFusePairs + 2 && t >= 0 && t <= h;
+    const bool colok = t >= 0 && t <= h;
+    const bool c0 = t >= 1 && 2 * t <= m - 1, c1 = t >= 0 && 2 * t + 1 <= m - 1;
+    const size_t w = (size_t)(m + 1);
+    auto ld2 = [&](int B) -> T { return (colok && B >= 0 && B <= h) ? v2[(size_t)B * W + t] : T(0); };
+    auto ld1 = [&](int k) -> T { return (colok && k >= 0 && k <= m) ? r1[(size_t)k * W + t] : T(0); };
+    // F point (2t+1, k), k odd, from v2 rows (k-1)/2 (vlo) and (k+1)/2 (vhi), as jac2_diagF
+    auto f21 = [&](int k, T rF, T vlo, T vhi) -> T {
+        const T vlo_e = __shfl_down(vlo, 1), vhi_e = __shfl_down(vhi, 1);
+        return (t >= 0 && t <= h - 1 && k >= 1 && k <= m - 1) ? jac2_chain(cd, rF, vlo, vlo_e, vhi_e, vhi) : T(0);
+    };
+    // C point (2t, k), k even, from the F rows k-1 (Fm) and k+1 (Fp), as jac2_diagC
+    auto c21 = [&](int k, T rC, T Fm, T Fp) -> T {
+        const T Fm_w = __shfl_up(Fm, 1), Fp_w = __shfl_up(Fp, 1);
+        return (t >= 1 && t <= h - 1 && k >= 2 && k <= m - 2) ? jac2_sum(cd, rC, Fm_w, Fm, Fp, Fp_w) : T(0);
+    };
+    auto fs = [&](int k) -> T { return f21(k, ld1(k), ld2((k - 1) >> 1), ld2((k + 1) >> 1)); };
+    auto vs = [&](int k) -> T { return (k & 1) ? fs(k) : c21(k, ld1(k), fs(k - 1), fs(k + 1)); };
+    // pair of an interior row: column m+1 is the next row's column 0 and never used
+    auto ldR = [&](int j, T& x, T& y) {
+        x = y = 0;
+        if (!colok || j < 1 || j > m - 1) return;
+        P2<T> v = NT ? ld_pair_nt(rA + (size_t)j * w + 2 * t) : *reinterpret_cast<const P2<T>*>(rA + (size_t)j * w + 2 * t);
+        x = c0 ? v.x : T(0);
+        y = c1 ? v.y : T(0);
+    };
+    // window entering row j: diagonal values of rows j-1 (dm), j (d0); at even
+    // j, Fn = F row j+1; at odd j, vlo = v2 row (j+1)/2
+    int j = y0 - 1;
+    T dm = vs(j - 1), d0 = vs(j);
+    T vlo, Fn = T(0);
+    if (j & 1) {
+        vlo = ld2((j + 1) >> 1);
+    } else {
+        Fn = fs(j + 1);
+        vlo = ld2((j + 2) >> 1);
+    }
+    // raw inputs of one row j, loaded a row ahead of their use
+    struct Ck { T rx, ry, r1c, r1f, vhi; double ux, uy; };
+    auto load = [&](int jj, Ck& c) {
+        c.rx = c.ry = c.r1c = c.r1f = c.vhi = 0;
+        c.ux = c.uy = 0;
+        if (jj > y1) return;
+        ldR(jj, c.rx, c.ry);
+        if (useful && jj >= y0 && jj < y1 && (c0 || c1)) {
+            P2<double> v = *reinterpret_cast<const P2<double>*>(u + (size_t)jj * w + 2 * t);
+            c.ux = v.x;
+            c.uy = v.y;
+        }
+        if (jj & 1) {
+            c.r1c = ld1(jj + 1);
+            c.r1f = ld1(jj + 2);
+            c.vhi = ld2((jj + 3) >> 1);
+        }
+    };
+    T Fm2 = 0, Fm1 = 0, rCm1 = 0;
+    double uxm1 = 0, uym1 = 0;
+    auto proc = [&](int jj, const Ck& c) {
+        if (jj > y1) return;
+        T dp;
+        if (jj & 1) {   // row jj+1 even: its C points from F rows jj (= d0) and jj+2
+            const T F2 = f21(jj + 2, c.r1f, vlo, c.vhi);
+            dp = c21(jj + 1, c.r1c, d0, F2);
+            Fn = F2;
+            vlo = c.vhi;
+        } else {        // row jj+1 odd: its F points, computed one row ago
+            dp = Fn;
+        }
+        const int q = jj & 1;
+        const T rF = q ? c.rx : c.ry;   // F at column 2t+1-q
+        const T rC = q ? c.ry : c.rx;   // C at column 2t+q
+        const T nb = q ? __shfl_up(d0, 1) : __shfl_down(d0, 1);
+        const T vw = q ? nb : d0;
+        const T ve = q ? d0 : nb;
+        const int aF = 2 * t + 1 - q;
+        const T Fj = (aF >= 1 && aF <= m - 1 && jj >= 1 && jj <= m - 1) ? jac2_sum(cc, rF, vw, dm, ve, dp) : T(0);
+        if (jj - 1 >= y0) {
+            const int qq = (jj - 1) & 1;
+            const T sb = qq ? __shfl_down(Fm1, 1) : __shfl_up(Fm1, 1);
+            const T cw = qq ? Fm1 : sb;
+            const T ce = qq ? sb : Fm1;
+            const T C = jac2_sum(cc, rCm1, cw, Fm2, ce, Fj);
+            const T vx = qq ? Fm1 : C;   // column 2t
+            const T vy = qq ? C : Fm1;   // column 2t+1
+            const size_t o = (size_t)(jj - 1) * w + 2 * t;
+            if (useful) {
+                if (c0 && c1) *reinterpret_cast<P2<double>*>(u + o) = P2<double>{uxm1 + (double)vx, uym1 + (double)vy};
+                else if (c1) u[o + 1] = uym1 + (double)vy;
+                else if (c0) u[o] = uxm1 + (double)vx;
+            }
+        }
+        Fm2 = Fm1;
+        Fm1 = Fj;
+        rCm1 = rC;
+        dm = d0;
+        d0 = dp;
+        uxm1 = c.ux;
+        uym1 = c.uy;
+    };
+    rows_march<1, Ck>(j, y1, load, proc);
+}
+
 // tiny finest grids: one thread per point (both half-sweeps recomputed)
 template <typename T>
 __global__ void kb_finest_small(int n, T cc, const Fin2<T>* __restrict__ items, const Ctl* __restrict__ ctls)
@@ -1273,13 +1406,24 @@ void launch_b_sumsq(int n, const Fin2<T>* items, int nitems, const Ctl* ctls, hi
 }
 
 template <typename T>
-void launch_b_finest(int n, T c, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s)
+void launch_b_finest(int n, T c, T c1, int fused, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s)
 {
     if (n < 8) {
         hipLaunchKernelGGL(kb_finest_small<T>, dim3(1, nitems), dim3(kRowBlock), 0, s, n, c, items, ctls);
         return;
     }
     int nwx, nw, nb;
+    if (fused) {
+        int rows = pick_rows(n / 2 + 1, kFusePairs, n - 1);
+        rows_grid(n / 2 + 1, kFusePairs, n - 1, rows, nwx, nw, nb);
+        if (nt_hint(n))
+            hipLaunchKernelGGL((kb_finest_fused<T, true>), dim3(nb, nitems), dim3(kRowBlock), 0, s, n, c, c1, items, nwx,
+                               nw, rows, ctls);
+        else
+            hipLaunchKernelGGL((kb_finest_fused<T, false>), dim3(nb, nitems), dim3(kRowBlock), 0, s, n, c, c1, items, nwx,
+                               nw, rows, ctls);
+        return;
+    }
     int rows = pick_rows(n / 2 + 1, kPairsPerWave, n - 1);
     rows_grid(n / 2 + 1, kPairsPerWave, n - 1, rows, nwx, nw, nb);
     if (nt_hint(n))
@@ -1386,7 +1530,7 @@ void launch_b_coarse_net(const LevInfo<T>* lev, const Coarse2B<T>* items, int ni
 #define DMG_INSTB(T)                                                                                            \
     template void launch_b_resid<T>(int, const Fin2<T>*, int, const Ctl*, hipStream_t);                        \
     template void launch_b_sumsq<T>(int, const Fin2<T>*, int, const Ctl*, hipStream_t);                        \
-    template void launch_b_finest<T>(int, T, const Fin2<T>*, int, const Ctl*, hipStream_t);                    \
+    template void launch_b_finest<T>(int, T, T, int, const Fin2<T>*, int, const Ctl*, hipStream_t);          \
     template void launch_b_restrict<T>(int, int, int, const Item2<T>*, int, const Ctl*, hipStream_t);          \
     template void launch_b_jacobi<T>(int, int, int, T, const Item2<T>*, int, const Ctl*, hipStream_t);         \
     template void launch_b_coarse<T>(const LevInfo<T>*, const Coarse2B<T>*, int, const T*, const Ctl*, hipStream_t, \

@@ -82,6 +82,7 @@ int plan2_layout(Plan2& P, int nprob, const int* n, int prec, double p)
     P.off_fin = take(sizeof(Fin2<double>) * (size_t)nprob);
     P.off_coarse = take(sizeof(Coarse2B<double>) * (size_t)nprob);
     P.off_net = take(sizeof(bf16_t) * (size_t)NetGeo<2>::PACK);
+    P.off_lg_item = take(sizeof(Item2<double>));
     P.off_rs_items.assign(P.Dmax + 1, 0);
     P.off_jac_items.assign(P.Dmax + 1, 0);
     P.n_rs_items.assign(P.Dmax + 1, 0);
@@ -91,7 +92,8 @@ int plan2_layout(Plan2& P, int nprob, const int* n, int prec, double p)
             int Dp = P.D[i];
             int top = std::min(P.lamc, Dp - 1);
             if (Dp >= 1 && lam >= top && lam <= Dp - 2) P.n_rs_items[lam]++;   // restriction into lam
-            if (Dp >= 1 && lam >= top + 1 && lam <= Dp - 1) P.n_jac_items[lam]++;  // Jacobi at lam
+            // Jacobi at lam (the first diagonal level's runs in the finest kernel when fused)
+            if (Dp >= 1 && lam >= top + 1 && lam <= Dp - 1 - (int)fin_fused(Dp, P.lamc)) P.n_jac_items[lam]++;
         }
         if (P.n_rs_items[lam]) P.off_rs_items[lam] = take(sizeof(Item2<double>) * (size_t)P.n_rs_items[lam]);
         if (P.n_jac_items[lam]) P.off_jac_items[lam] = take(sizeof(Item2<double>) * (size_t)P.n_jac_items[lam]);
@@ -164,13 +166,19 @@ int write_tables(Plan2& P)
         for (int i = 0; i < P.nprob; i++) {
             int Dp = P.D[i];
             int top = std::min(P.lamc, Dp - 1);
-            if (Dp >= 1 && lam >= top + 1 && lam <= Dp - 1)
+            if (Dp >= 1 && lam >= top + 1 && lam <= Dp - 1 - (int)fin_fused(Dp, P.lamc))
                 items.push_back(Item2<T>{at<T>(P, P.off_r[i][lam]), at<T>(P, P.off_v[i][lam]),
                                          lam >= 1 ? at<T>(P, P.off_v[i][lam - 1]) : zero, i, 0});
         }
         if (!items.empty() &&
             hipMemcpy(P.ws + P.off_jac_items[lam], items.data(), items.size() * sizeof(Item2<T>), hipMemcpyHostToDevice) != hipSuccess)
             return MG_ERR_HIP;
+    }
+    if (fin_fused(P.D[0], P.lamc)) {
+        // problem 0's first diagonal level, for plan2_level_get
+        const int D = P.D[0];
+        Item2<T> it{at<T>(P, P.off_r[0][D - 1]), at<T>(P, P.off_v[0][D - 1]), at<T>(P, P.off_v[0][D - 2]), 0, 0};
+        if (hipMemcpy(P.ws + P.off_lg_item, &it, sizeof(it), hipMemcpyHostToDevice) != hipSuccess) return MG_ERR_HIP;
     }
     std::vector<Coarse2B<T>> co;
     for (int i = 0; i < P.nprob; i++) {
@@ -196,6 +204,7 @@ int write_tables(Plan2& P)
         x.r0 = at<T>(P, P.off_r0[i]);
         x.r1 = P.D[i] >= 1 ? at<T>(P, P.off_r[i][P.D[i] - 1]) : nullptr;
         x.v1 = P.D[i] >= 1 ? at<T>(P, P.off_v[i][P.D[i] - 1]) : zero;
+        x.v2 = P.D[i] >= 2 ? at<T>(P, P.off_v[i][P.D[i] - 2]) : zero;
         x.part = at<double>(P, P.off_part[i]);
         x.prob = i;
         hf[s] = x;
@@ -220,10 +229,13 @@ double bytes_resid(int n, size_t es)
     double inter = (double)(n - 1) * (n - 1), M = n / 2;
     return 8 * (double)sizeA(n) + 8 * inter + es * inter + (n >= 4 ? es * (M * M + (M - 1) * (M - 1)) : 0);
 }
-double bytes_finest(int n, size_t es)
+// fused: the first diagonal level's residual (half the finest points) and
+// the correction below it (a quarter) replace the read of its correction
+double bytes_finest(int n, size_t es, bool fused)
 {
-    double inter = (double)(n - 1) * (n - 1);
-    return es * (inter + (double)sizeD(n)) + 16 * inter;
+    double inter = (double)(n - 1) * (n - 1), M = n / 2;
+    double lev = fused ? (double)sizeD(n) + (M + 1) * (M + 1) : (double)sizeD(n);
+    return es * (inter + lev) + 16 * inter;
 }
 double bytes_rs(int diag_in, int m, size_t es)
 {
@@ -335,9 +347,12 @@ void enq_cycle(Plan2& P, Ctl* ctls)
     }
     for (size_t c = 0; c < P.cls_n.size(); c++) {
         int n = P.cls_n[c];
-        Timed t(&P.tm, MG_K_FINEST, bytes_finest(n, es) * P.cls_count[c]);
+        const int D = 2 * (ilog2(n) - 1);
+        const bool fz = fin_fused(D, P.lamc);
+        Timed t(&P.tm, MG_K_FINEST, bytes_finest(n, es, fz) * P.cls_count[c]);
         double sh = 1.0 / n;
-        launch_b_finest<T>(n, (T)(P.p * sh * sh), fin_items<T>(P, (int)c), P.cls_count[c], ctls, P.stream);
+        launch_b_finest<T>(n, (T)(P.p * sh * sh), (T)(fz ? coef(P, D - 1) : 0.0), fz ? 1 : 0, fin_items<T>(P, (int)c),
+                           P.cls_count[c], ctls, P.stream);
     }
 }
 
@@ -536,6 +551,15 @@ int plan2_solve(Plan2& P, double* const* u, const double* const* f, double rtol,
     return worst;
 }
 
+template <typename T>
+void recompute_first_diag(Plan2& P)
+{
+    const int D = P.D[0];
+    // the zero block serves as a control block that is never done
+    launch_b_jacobi<T>(1, side_of(D - 1), P.rows_jac[D - 1], (T)coef(P, D - 1), at<Item2<T>>(P, P.off_lg_item), 1,
+                       at<Ctl>(P, P.off_zero), P.stream);
+}
+
 int plan2_level_get(Plan2& P, int depth, int which, double* dst)
 {
     // problem 0; depth counts from its finest level
@@ -545,6 +569,13 @@ int plan2_level_get(Plan2& P, int depth, int which, double* dst)
     int m = side_of(lam);
     int diag = lam & 1;
     size_t off = (which == 0) ? (depth == 0 ? P.off_r0[0] : P.off_r[0][lam]) : P.off_v[0][lam];
+    if (which == 1 && depth == 1 && fin_fused(D, P.lamc)) {
+        // the cycle computed this level inside the finest kernel without
+        // storing it: rerun its Jacobi (same arithmetic, so the same values)
+        // from the residual and the coarser correction the cycle left
+        if (P.prec == MG_FP64) recompute_first_diag<double>(P);
+        else recompute_first_diag<float>(P);
+    }
     if (P.prec == MG_FP64) launch_b_level_get<double>(diag, m, at<double>(P, off), dst, P.stream);
     else launch_b_level_get<float>(diag, m, at<float>(P, off), dst, P.stream);
     return last_launch();

@@ -14,7 +14,7 @@ struct Plan2 {
     // size classes (distinct n, ascending); the finest-item table is grouped by class
     std::vector<int> order, cls_n, cls_first, cls_count, nparts;
     // workspace offsets
-    size_t off_ctl = 0, off_nactive = 0, off_zero = 0, off_fin = 0, off_coarse = 0, off_net = 0, total = 0;
+    size_t off_ctl = 0, off_nactive = 0, off_zero = 0, off_fin = 0, off_coarse = 0, off_net = 0, off_lg_item = 0, total = 0;
     bool has_net = false;     // learned coarse correction set (packed bf16 weights at off_net)
     std::vector<size_t> off_r0, off_part;
     std::vector<std::vector<size_t>> off_r, off_v;   // [problem][aligned level]
