@@ -26,9 +26,10 @@ namespace dmg {
 
 // r = f - Lap_h(u) on rows [y0, y1) (stored as T, squared norm accumulated
 // in double), then Eq. (Erest2r) onto the first diagonal level at those rows.
-// NT: non-temporal f and r0 accesses.
+// NT: non-temporal f and r0 accesses.  At most 128 VGPRs: four waves per
+// SIMD keep enough loads in flight.
 template <typename T, int CH, bool NT>
-__global__ void __launch_bounds__(kRowBlock) kb_resid(int m, double inv_h2, const Fin2<T>* __restrict__ items,
+__global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(4))) kb_resid(int m, double inv_h2, const Fin2<T>* __restrict__ items,
                                                       int nwx, int nwaves, int rows, const Ctl* __restrict__ ctls)
 {
     const Fin2<T> it = items[blockIdx.y];
@@ -79,11 +80,14 @@ __global__ void __launch_bounds__(kRowBlock) kb_resid(int m, double inv_h2, cons
     ldu(y0 - 1, uc0, uc1);
     ldu(y0, up0, up1);
     T rm2_0 = 0, rm2_1 = 0, rm1_0 = 0, rm1_1 = 0;  // r rows j-2, j-1 (as stored)
-    auto proc = [&](int jb, const Ck& c) {
-#pragma unroll
-        for (int i = 0; i < CH; i++) {
-            int j = jb + i;
-            if (j > y1) break;
+    // P0: parity of jb (-1: not known at compile time).  With the vector
+    // stores of NT, a select on a run-time parity between the two values of a
+    // stored pair became a dynamically indexed vector kept in scratch memory.
+    auto proc_p = [&](int jb, const Ck& c, auto P0) {
+        static_for<0, CH>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const int j = jb + i;
+            if (j > y1) return;
             bool rowin = j >= 1 && j <= m - 1;
             double uW = __shfl_up(uc1, 1);   // u(2t-1, j)
             double uE = __shfl_down(uc0, 1); // u(2t+2, j)
@@ -103,7 +107,8 @@ __global__ void __launch_bounds__(kRowBlock) kb_resid(int m, double inv_h2, cons
             }
             if (j - 1 >= y0) {
                 // Eq. Erest2r at the diagonal point of row j-1 (a + j-1 even)
-                int q = (j - 1) & 1;
+                constexpr int p0 = decltype(P0)::value;
+                const int q = p0 >= 0 ? (p0 + i + 1) & 1 : (j - 1) & 1;
                 T sh = q ? __shfl_down(rm1_0, 1) : __shfl_up(rm1_1, 1);
                 T rc = q ? rm1_1 : rm1_0;
                 T rw = q ? rm1_0 : sh;
@@ -116,6 +121,14 @@ __global__ void __launch_bounds__(kRowBlock) kb_resid(int m, double inv_h2, cons
             }
             rm2_0 = rm1_0; rm2_1 = rm1_1; rm1_0 = r0j; rm1_1 = r1j;
             um0 = uc0; um1 = uc1; uc0 = up0; uc1 = up1; up0 = c.ux[i]; up1 = c.uy[i];
+        });
+    };
+    auto proc = [&](int jb, const Ck& c) {
+        if constexpr (NT) {
+            if (jb & 1) proc_p(jb, c, Int<1>{});
+            else proc_p(jb, c, Int<0>{});
+        } else {
+            proc_p(jb, c, Int<-1>{});   // run-time parity (no vector stores here)
         }
     };
     rows_march<CH, Ck>(y0 - 1, y1, load, proc);

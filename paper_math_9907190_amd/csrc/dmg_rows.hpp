@@ -73,6 +73,21 @@ __device__ inline void rows_march(int jbeg, int jlast, Load&& load, Proc&& proc)
     }
 }
 
+// f(Int<0>{}), ..., f(Int<N-1>{}): a row loop whose index is a compile-time
+// constant in the body, so that per-row choices (a row's parity) fold away
+template <int I>
+struct Int {
+    static constexpr int value = I;
+};
+template <int I, int N, typename F>
+__device__ inline void static_for(F&& f)
+{
+    if constexpr (I < N) {
+        f(Int<I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
 // Streaming pair accesses for arrays that are not reused before the cache
 // would evict them anyway (f, and r0 between the residual and the finest
 // Jacobi): non-temporal hints keep them from displacing u and the level
