@@ -71,7 +71,7 @@ struct Ctl {
     int grow;        // consecutive cycles with a growing residual
     int mode;        // 0: single cycle (never sets done); 1: solve
     int max_cycles;
-    int k;           // evaluations done so far (batched path)
+    int k;           // residual evaluations done so far
     int net;         // learned coarse correction: 0 off, 1 first (judged) cycle, 2 on
     double rtol;
     double fnorm;    // ||f||_2 over interior nodes

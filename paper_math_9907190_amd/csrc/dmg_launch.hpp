@@ -14,7 +14,7 @@ int residual_parts(int dim, int n);
 
 void launch_sumsq(int dim, int n, const double* a, double* partial, int nparts, const Ctl* ctl, hipStream_t s);
 // finalize: kind 0 -> ||f|| into ctl->fnorm; kind 1 -> relative residual of evaluation k
-void launch_finalize(int kind, int k, const double* partial, int nparts, Ctl* ctl, hipStream_t s);
+void launch_finalize(int kind, const double* partial, int nparts, Ctl* ctl, hipStream_t s);
 void launch_ctl_reset(Ctl* ctl, int mode, int max_cycles, double rtol, hipStream_t s, int net = 0);
 
 }  // namespace dmg

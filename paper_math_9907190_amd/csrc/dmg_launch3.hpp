@@ -123,7 +123,7 @@ __device__ inline T jac3_redF(const T* __restrict__ rR, const T* __restrict__ vE
 
 // Eq. (Erprolm): red corner (all even, interior) from its twelve new face-centre neighbours.
 template <typename T>
-__device__ inline T jac3_redC(const T* __restrict__ rR, const T* __restrict__ vE, const T* __restrict__ vO, int m,
+__device__ __forceinline__ T jac3_redC(const T* __restrict__ rR, const T* __restrict__ vE, const T* __restrict__ vO, int m,
                               T c1, T c2, int a, int b, int c)
 {
     T s = jac3_redF(rR, vE, vO, m, c1, a + 1, b + 1, c) + jac3_redF(rR, vE, vO, m, c1, a + 1, b - 1, c)

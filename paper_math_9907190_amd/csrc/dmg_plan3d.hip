@@ -116,11 +116,11 @@ void enqueue_residual(Plan3& P, const double* u, const double* f, const Ctl* ctl
     else launch_residual<float>(3, P.n, u, f, at<float>(P, P.r0), part, P.nparts, ctl, P.stream);
 }
 
-void enqueue_finalize(Plan3& P, int kind, int k, Ctl* ctl)
+void enqueue_finalize(Plan3& P, int kind, Ctl* ctl)
 {
     const int np = kind == 0 ? P.nparts : P.nparts_res;
     Timed t(&P.tm, MG_K_NORM, 8.0 * np);
-    launch_finalize(kind, k, at<double>(P, P.partial), np, ctl, P.stream);
+    launch_finalize(kind, at<double>(P, P.partial), np, ctl, P.stream);
 }
 
 }  // namespace
@@ -195,6 +195,10 @@ int plan3_setup(Plan3& P, void* ws, size_t ws_bytes, hipStream_t stream)
     P.tm.stream = stream;
     if (hipGetDevice(&P.device) != hipSuccess) return MG_ERR_HIP;
     if (hipHostMalloc((void**)&P.hctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) return MG_ERR_HIP;
+    if (hipHostMalloc((void**)&P.hhead, 2 * kCtlHead, hipHostMallocDefault) != hipSuccess) return MG_ERR_HIP;
+    for (int k = 0; k < 2; k++)
+        if (hipEventCreateWithFlags(&P.ev[k], hipEventDisableTiming) != hipSuccess) return MG_ERR_HIP;
+    P.evs = true;
     // zero the whole workspace once: boundary entries of every level stay 0
     return hip_status(hipMemsetAsync(P.ws, 0, P.total, P.stream));
 }
@@ -202,7 +206,12 @@ int plan3_setup(Plan3& P, void* ws, size_t ws_bytes, hipStream_t stream)
 void plan3_destroy(Plan3& P)
 {
     P.tm.destroy();
+    if (P.evs) {
+        (void)hipStreamSynchronize(P.stream);
+        for (int k = 0; k < 2; k++) (void)hipEventDestroy(P.ev[k]);
+    }
     if (P.hctl) (void)hipHostFree(P.hctl);
+    if (P.hhead) (void)hipHostFree(P.hhead);
 }
 
 int plan3_vcycle(Plan3& P, double* u, const double* f, double* relres)
@@ -212,10 +221,10 @@ int plan3_vcycle(Plan3& P, double* u, const double* f, double* relres)
     launch_ctl_reset(ctl, 0, 0, 0.0, P.stream, P.has_net ? 1 : 0);
     if (relres) {
         launch_sumsq(3, P.n, f, part, P.nparts, ctl, P.stream);
-        enqueue_finalize(P, 0, 0, ctl);
+        enqueue_finalize(P, 0, ctl);
     }
     enqueue_residual(P, u, f, ctl);
-    if (relres) enqueue_finalize(P, 1, 0, ctl);
+    if (relres) enqueue_finalize(P, 1, ctl);
     enqueue_cycle_any(P, u, ctl);
     int e = last_launch();
     if (e) return e;
@@ -235,21 +244,46 @@ int plan3_solve(Plan3& P, double* u, const double* f, double rtol, int max_cycle
     hipStream_t s = P.stream;
     launch_ctl_reset(ctl, 1, max_cycles, rtol, s, P.has_net ? 1 : 0);
     launch_sumsq(3, P.n, f, part, P.nparts, ctl, s);
-    enqueue_finalize(P, 0, 0, ctl);
+    enqueue_finalize(P, 0, ctl);
     enqueue_residual(P, u, f, ctl);
-    enqueue_finalize(P, 1, 0, ctl);
-    size_t head = offsetof(Ctl, rtol);
-    // the device decides after every residual evaluation; the host launches
-    // the next cycle once it has seen that the last one did not stop
-    for (int k = 0;; k++) {
-        if (hipMemcpyAsync(P.hctl, ctl, head, hipMemcpyDeviceToHost, s) != hipSuccess) return MG_ERR_HIP;
-        if (hipStreamSynchronize(s) != hipSuccess) return MG_ERR_HIP;
-        if (P.hctl->done || k >= max_cycles) break;
+    enqueue_finalize(P, 1, ctl);
+    // The device decides after every residual evaluation (later launches of
+    // a finished solve return at once).  While the host waits for what
+    // iteration it decided, iteration it+1 is already queued, so the GPU does
+    // not wait for the host between cycles -- unless the residual trend says
+    // iteration it is probably the last: then the host waits first, rather
+    // than queue a whole gated iteration that would only return.
+    auto launch = [&](int it1) -> int {   // iteration it1: cycle, residual evaluation it1
         enqueue_cycle_any(P, u, ctl);
         enqueue_residual(P, u, f, ctl);
-        enqueue_finalize(P, 1, k + 1, ctl);
+        enqueue_finalize(P, 1, ctl);
         int e = last_launch();
         if (e) return e;
+        const int k = it1 & 1;
+        if (hipMemcpyAsync(P.hhead + k * kCtlHead, ctl, kCtlHead, hipMemcpyDeviceToHost, s) != hipSuccess)
+            return MG_ERR_HIP;
+        return hip_status(hipEventRecord(P.ev[k], s));
+    };
+    if (hipMemcpyAsync(P.hhead, ctl, kCtlHead, hipMemcpyDeviceToHost, s) != hipSuccess) return MG_ERR_HIP;
+    if (hipEventRecord(P.ev[0], s) != hipSuccess) return MG_ERR_HIP;
+    double rr1 = -1, rr2 = -1;   // relative residuals of evaluations it-1, it-2
+    for (int it = 0;; it++) {
+        const bool likely_last = rr1 > 0 && rr2 > 0 && rr1 * (rr1 / rr2) <= 2 * rtol;
+        bool ahead = false;
+        if (it < max_cycles && !likely_last) {
+            int e = launch(it + 1);
+            if (e) return e;
+            ahead = true;
+        }
+        if (hipEventSynchronize(P.ev[it & 1]) != hipSuccess) return MG_ERR_HIP;
+        const Ctl* h = reinterpret_cast<const Ctl*>(P.hhead + (it & 1) * kCtlHead);
+        if (h->done || it >= max_cycles) break;
+        rr2 = rr1;
+        rr1 = h->last;
+        if (!ahead) {
+            int e = launch(it + 1);
+            if (e) return e;
+        }
     }
     if (hipMemcpyAsync(P.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s) != hipSuccess) return MG_ERR_HIP;
     if (hipStreamSynchronize(s) != hipSuccess) return MG_ERR_HIP;

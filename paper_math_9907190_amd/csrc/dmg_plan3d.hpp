@@ -27,6 +27,9 @@ struct Plan3 {
     hipStream_t stream = nullptr;
     int device = 0;
     Ctl* hctl = nullptr;
+    char* hhead = nullptr;    // pinned: the control block head after two consecutive iterations
+    hipEvent_t ev[2];
+    bool evs = false;
     Timing tm;
 };
 

@@ -120,8 +120,8 @@ void launch_sumsq(int dim, int n, const double* a, double* partial, int nparts, 
 // and the outer iteration's decision (Section 1): stop when it is <= rtol,
 // when it is not finite, when it grew three cycles in a row above the
 // starting value, or after max_cycles cycles.
-__global__ void __launch_bounds__(1024) k_finalize(int kind, int k, const double* __restrict__ partial,
-                                                   int nparts, Ctl* ctl)
+__global__ void __launch_bounds__(1024) k_finalize(int kind, const double* __restrict__ partial, int nparts,
+                                                   Ctl* ctl)
 {
     if (ctl->done) return;
     __shared__ double red[1024];
@@ -139,6 +139,8 @@ __global__ void __launch_bounds__(1024) k_finalize(int kind, int k, const double
         ctl->fnorm = sqrt(tot);
         return;
     }
+    const int k = ctl->k;   // evaluation index = cycles run so far
+    ctl->k = k + 1;
     double rn = sqrt(tot);
     double rr = ctl->fnorm > 0 ? rn / ctl->fnorm : rn;
     ctl->last = rr;
@@ -165,9 +167,9 @@ __global__ void __launch_bounds__(1024) k_finalize(int kind, int k, const double
     if (ctl->done) ctl->cycles = k;
 }
 
-void launch_finalize(int kind, int k, const double* partial, int nparts, Ctl* ctl, hipStream_t s)
+void launch_finalize(int kind, const double* partial, int nparts, Ctl* ctl, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, kind, k, partial, nparts, ctl);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, kind, partial, nparts, ctl);
 }
 
 __global__ void k_ctl_reset(Ctl* ctl, int mode, int max_cycles, double rtol, int net)
@@ -176,6 +178,7 @@ __global__ void k_ctl_reset(Ctl* ctl, int mode, int max_cycles, double rtol, int
     ctl->done = 0;
     ctl->status = 0;
     ctl->cycles = 0;
+    ctl->k = 0;
     ctl->grow = 0;
     ctl->mode = mode;
     ctl->max_cycles = max_cycles;
