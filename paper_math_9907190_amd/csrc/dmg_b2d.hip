@@ -26,10 +26,19 @@ namespace dmg {
 
 // r = f - Lap_h(u) on rows [y0, y1) (stored as T, squared norm accumulated
 // in double), then Eq. (Erest2r) onto the first diagonal level at those rows.
-// NT: non-temporal f and r0 accesses.  At most 128 VGPRs: four waves per
-// SIMD keep enough loads in flight.
-template <typename T, int CH, bool NT>
-__global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(4))) kb_resid(int m, double inv_h2, const Fin2<T>* __restrict__ items,
+// FZ: also Eq. (Erest2b) onto the axis level below it, from the diagonal
+// values of three consecutive rows kept in registers (the strip then
+// computes one diagonal row past its end; strips start on odd rows).
+// Lane t owns the column pair (2t, 2t+1); a diagonal value needs the lanes
+// beside it, and an FZ value the lanes beside those: lanes 1 .. 61 write r
+// and r1, lanes 2 .. 62 write r2.
+// NT: non-temporal f and r0 accesses.  At most 128 VGPRs (four waves per
+// SIMD keep enough loads in flight); the FP64 FZ variant needs a few more
+// and runs three waves rather than spill (measured faster than halving its
+// row chunk to stay at four).
+constexpr int kResidPairs = 61;
+template <typename T, int CH, bool NT, bool FZ>
+__global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(FZ && sizeof(T) == 8 ? 3 : 4))) kb_resid(int m, double inv_h2, const Fin2<T>* __restrict__ items,
                                                       int nwx, int nwaves, int rows, const Ctl* __restrict__ ctls)
 {
     const Fin2<T> it = items[blockIdx.y];
@@ -38,14 +47,18 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
     const double* __restrict__ f = it.f;
     T* __restrict__ r0 = it.r0;
     T* __restrict__ rD = it.r1;
+    T* __restrict__ rA2 = it.r2;
     const int lane = threadIdx.x & 63;
     const int wv = rows_wave_id(nwaves);
     const bool live = wv < nwaves;
     const int wx = wv % nwx, sy = wv / nwx;
-    const int t = wx * kPairsPerWave - 1 + lane;
+    const int t = wx * kResidPairs - 1 + lane;
     const int y0 = 1 + sy * rows;
     const int y1 = min(y0 + rows, m);
-    const bool useful = lane >= 1 && lane <= kPairsPerWave && t >= 0 && t <= m / 2;
+    const int ylast = y1 + (FZ ? 1 : 0);   // last row of the march
+    const int mc = m / 2;
+    const bool useful = lane >= 1 && lane <= kResidPairs && t >= 0 && t <= m / 2;
+    const bool useful2 = lane >= 2 && lane <= kResidPairs + 1 && t >= 1 && t <= mc - 1;
     const size_t w = (size_t)(m + 1);
     const int W = m / 2 + 1;
     const bool c0 = t >= 1 && 2 * t <= m - 1, c1 = t >= 0 && 2 * t + 1 <= m - 1;  // columns 2t, 2t+1 interior
@@ -71,7 +84,7 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
         for (int i = 0; i < CH; i++) {
             int j = jb + i;
             c.ux[i] = c.uy[i] = c.fx[i] = c.fy[i] = 0;
-            if (j <= y1) { ldu(j + 2, c.ux[i], c.uy[i]); ldf(j, c.fx[i], c.fy[i]); }
+            if (j <= ylast) { ldu(j + 2, c.ux[i], c.uy[i]); ldf(j, c.fx[i], c.fy[i]); }
         }
     };
     double acc = 0;
@@ -80,6 +93,7 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
     ldu(y0 - 1, uc0, uc1);
     ldu(y0, up0, up1);
     T rm2_0 = 0, rm2_1 = 0, rm1_0 = 0, rm1_1 = 0;  // r rows j-2, j-1 (as stored)
+    T d3 = 0, d2 = 0;                               // FZ: diagonal values of rows j-3, j-2
     // P0: parity of jb (-1: not known at compile time).  With the vector
     // stores of NT, a select on a run-time parity between the two values of a
     // stored pair became a dynamically indexed vector kept in scratch memory.
@@ -87,7 +101,7 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
         static_for<0, CH>([&](auto I) {
             constexpr int i = decltype(I)::value;
             const int j = jb + i;
-            if (j > y1) return;
+            if (j > ylast) return;
             bool rowin = j >= 1 && j <= m - 1;
             double uW = __shfl_up(uc1, 1);   // u(2t-1, j)
             double uE = __shfl_down(uc0, 1); // u(2t+2, j)
@@ -116,8 +130,20 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
                 T rs = q ? rm2_1 : rm2_0;
                 T rn = q ? r1j : r0j;
                 int a = 2 * t + q;
-                if (useful && a >= 1 && a <= m - 1)
-                    rD[(size_t)(j - 1) * W + t] = rs2_core(rc, rw, rs, re, rn);
+                const T d1 = rs2_core(rc, rw, rs, re, rn);
+                if (useful && a >= 1 && a <= m - 1 && j - 1 < y1) rD[(size_t)(j - 1) * W + t] = d1;
+                if constexpr (FZ) {
+                    // Eq. (Erest2b) at axis point (t, B) of the level below,
+                    // B = (j-2)/2: diagonal rows 2B-1 (d3), 2B (d2), 2B+1 (d1)
+                    if (!(j & 1) && j - 2 >= y0 && j - 2 < y1) {
+                        const int B = (j - 2) >> 1;
+                        const T d3w = __shfl_up(d3, 1), d1w = __shfl_up(d1, 1);
+                        if (useful2 && B >= 1 && B <= mc - 1)
+                            rA2[(size_t)B * (mc + 1) + t] = rs2_core(d2, d3w, d3, d1, d1w);
+                    }
+                    d3 = d2;
+                    d2 = d1;
+                }
             }
             rm2_0 = rm1_0; rm2_1 = rm1_1; rm1_0 = r0j; rm1_1 = r1j;
             um0 = uc0; um1 = uc1; uc0 = up0; uc1 = up1; up0 = c.ux[i]; up1 = c.uy[i];
@@ -131,7 +157,7 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
             proc_p(jb, c, Int<-1>{});   // run-time parity (no vector stores here)
         }
     };
-    rows_march<CH, Ck>(y0 - 1, y1, load, proc);
+    rows_march<CH, Ck>(y0 - 1, ylast, load, proc);
     double sum = rows_block_sum(acc);
     if (threadIdx.x == 0) it.part[blockIdx.x] = sum;
 }
@@ -1388,13 +1414,13 @@ int b_resid_parts(int n)
 {
     if (n < 4) return 1;
     int nwx, nw, nb;
-    rows_grid(n / 2 + 1, kPairsPerWave, n - 1, pick_rows(n / 2 + 1, kPairsPerWave, n - 1, kTargetWavesResid), nwx,
-              nw, nb);
+    rows_grid(n / 2 + 1, kResidPairs, n - 1, pick_rows(n / 2 + 1, kResidPairs, n - 1, kTargetWavesResid), nwx, nw,
+              nb);
     return nb;
 }
 
 template <typename T>
-void launch_b_resid(int n, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s)
+void launch_b_resid(int n, int fused, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s)
 {
     double inv_h2 = (double)n * (double)n;
     if (n < 4) {
@@ -1402,14 +1428,20 @@ void launch_b_resid(int n, const Fin2<T>* items, int nitems, const Ctl* ctls, hi
         return;
     }
     int nwx, nw, nb;
-    int rows = pick_rows(n / 2 + 1, kPairsPerWave, n - 1, kTargetWavesResid);
-    rows_grid(n / 2 + 1, kPairsPerWave, n - 1, rows, nwx, nw, nb);
-    if (nt_hint(n))
-        hipLaunchKernelGGL((kb_resid<T, kChunkResid, true>), dim3(nb, nitems), dim3(kRowBlock), 0, s, n, inv_h2, items,
-                           nwx, nw, rows, ctls);
-    else
-        hipLaunchKernelGGL((kb_resid<T, kChunkResid, false>), dim3(nb, nitems), dim3(kRowBlock), 0, s, n, inv_h2, items,
-                           nwx, nw, rows, ctls);
+    // rows is a power of two >= 4: every strip starts on an odd row
+    int rows = pick_rows(n / 2 + 1, kResidPairs, n - 1, kTargetWavesResid);
+    rows_grid(n / 2 + 1, kResidPairs, n - 1, rows, nwx, nw, nb);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(nb, nitems), dim3(kRowBlock), 0, s, n, inv_h2, items, nwx, nw, rows, ctls);
+    };
+    const bool nt = nt_hint(n);
+    if (fused && n >= 8) {
+        if (nt) go(kb_resid<T, kChunkResid, true, true>);
+        else go(kb_resid<T, kChunkResid, false, true>);
+    } else {
+        if (nt) go(kb_resid<T, kChunkResid, true, false>);
+        else go(kb_resid<T, kChunkResid, false, false>);
+    }
 }
 
 template <typename T>
@@ -1541,7 +1573,7 @@ void launch_b_coarse_net(const LevInfo<T>* lev, const Coarse2B<T>* items, int ni
 }
 
 #define DMG_INSTB(T)                                                                                            \
-    template void launch_b_resid<T>(int, const Fin2<T>*, int, const Ctl*, hipStream_t);                        \
+    template void launch_b_resid<T>(int, int, const Fin2<T>*, int, const Ctl*, hipStream_t);                   \
     template void launch_b_sumsq<T>(int, const Fin2<T>*, int, const Ctl*, hipStream_t);                        \
     template void launch_b_finest<T>(int, T, T, int, const Fin2<T>*, int, const Ctl*, hipStream_t);          \
     template void launch_b_restrict<T>(int, int, int, const Item2<T>*, int, const Ctl*, hipStream_t);          \

@@ -28,6 +28,7 @@ struct Fin2 {
     T* r1;         // residual of the first diagonal level (written by the fused residual)
     const T* v1;   // correction of the first diagonal level (or a zero array)
     const T* v2;   // correction of the level below it (read when the finest kernel runs its Jacobi)
+    T* r2;         // residual of that level (written by the residual kernel when fused)
     double* part;  // norm partial sums of this problem
     int prob;
     int pad;
@@ -51,16 +52,18 @@ struct LevInfo {
     T c;
 };
 
+// fused = 1: the kernel also restricts r1 onto the axis level below it (r2)
 template <typename T>
-void launch_b_resid(int n, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s);
+void launch_b_resid(int n, int fused, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s);
 int b_resid_parts(int n);
 // fused = 1: the kernel also runs the Jacobi of the first diagonal level
 // (coefficient c1) from r1 and v2 instead of reading v1
 template <typename T>
 void launch_b_finest(int n, T c, T c1, int fused, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s);
 // does a problem with finest level D run the first diagonal level's Jacobi in
-// the finest kernel (levels above the coarse kernel's top lamc only)
-inline bool fin_fused(int D, int lamc) { return D - 1 > lamc; }
+// the finest kernel, and the restriction into the level below it (D-2) in
+// the residual kernel (when both levels are above the coarse kernel's top lamc)
+inline bool fin_fused(int D, int lamc) { return D - 2 >= lamc; }
 template <typename T>
 void launch_b_restrict(int diag_in, int m, int rows, const Item2<T>* items, int nitems, const Ctl* ctls,
                        hipStream_t s);

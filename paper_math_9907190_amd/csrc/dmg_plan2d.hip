@@ -91,7 +91,8 @@ int plan2_layout(Plan2& P, int nprob, const int* n, int prec, double p)
         for (int i = 0; i < nprob; i++) {
             int Dp = P.D[i];
             int top = std::min(P.lamc, Dp - 1);
-            if (Dp >= 1 && lam >= top && lam <= Dp - 2) P.n_rs_items[lam]++;   // restriction into lam
+            // restriction into lam (into D-2 it runs in the residual kernel when fused)
+            if (Dp >= 1 && lam >= top && lam <= Dp - 2 - (int)fin_fused(Dp, P.lamc)) P.n_rs_items[lam]++;
             // Jacobi at lam (the first diagonal level's runs in the finest kernel when fused)
             if (Dp >= 1 && lam >= top + 1 && lam <= Dp - 1 - (int)fin_fused(Dp, P.lamc)) P.n_jac_items[lam]++;
         }
@@ -155,7 +156,7 @@ int write_tables(Plan2& P)
         for (int i = 0; i < P.nprob; i++) {
             int Dp = P.D[i];
             int top = std::min(P.lamc, Dp - 1);
-            if (Dp >= 1 && lam >= top && lam <= Dp - 2)
+            if (Dp >= 1 && lam >= top && lam <= Dp - 2 - (int)fin_fused(Dp, P.lamc))
                 items.push_back(Item2<T>{at<T>(P, P.off_r[i][lam]), at<T>(P, P.off_v[i][lam]),
                                          at<T>(P, P.off_r[i][lam + 1]), i, 0});
         }
@@ -205,6 +206,7 @@ int write_tables(Plan2& P)
         x.r1 = P.D[i] >= 1 ? at<T>(P, P.off_r[i][P.D[i] - 1]) : nullptr;
         x.v1 = P.D[i] >= 1 ? at<T>(P, P.off_v[i][P.D[i] - 1]) : zero;
         x.v2 = P.D[i] >= 2 ? at<T>(P, P.off_v[i][P.D[i] - 2]) : zero;
+        x.r2 = fin_fused(P.D[i], P.lamc) ? at<T>(P, P.off_r[i][P.D[i] - 2]) : nullptr;
         x.part = at<double>(P, P.off_part[i]);
         x.prob = i;
         hf[s] = x;
@@ -224,10 +226,12 @@ void enq_norm_f(Plan2& P, Ctl* ctls, int* nact)
     }
 }
 
-double bytes_resid(int n, size_t es)
+// fused: the restriction of r1 onto the level below ((n/2 - 1)^2 interior points) is written too
+double bytes_resid(int n, size_t es, bool fused)
 {
     double inter = (double)(n - 1) * (n - 1), M = n / 2;
-    return 8 * (double)sizeA(n) + 8 * inter + es * inter + (n >= 4 ? es * (M * M + (M - 1) * (M - 1)) : 0);
+    return 8 * (double)sizeA(n) + 8 * inter + es * inter + (n >= 4 ? es * (M * M + (M - 1) * (M - 1)) : 0) +
+           (fused ? es * (M - 1) * (M - 1) : 0);
 }
 // fused: the first diagonal level's residual (half the finest points) and
 // the correction below it (a quarter) replace the read of its correction
@@ -256,8 +260,10 @@ void enq_resid(Plan2& P, Ctl* ctls, int* nact)
     size_t es = sizeof(T);
     for (size_t c = 0; c < P.cls_n.size(); c++) {
         {
-            Timed t(&P.tm, MG_K_RESIDUAL, bytes_resid(P.cls_n[c], es) * P.cls_count[c]);
-            launch_b_resid<T>(P.cls_n[c], fin_items<T>(P, (int)c), P.cls_count[c], ctls, P.stream);
+            const int n = P.cls_n[c];
+            const bool fz = fin_fused(2 * (ilog2(n) - 1), P.lamc);
+            Timed t(&P.tm, MG_K_RESIDUAL, bytes_resid(n, es, fz) * P.cls_count[c]);
+            launch_b_resid<T>(n, fz ? 1 : 0, fin_items<T>(P, (int)c), P.cls_count[c], ctls, P.stream);
         }
         Timed t(&P.tm, MG_K_NORM, 8.0 * P.nparts[c] * P.cls_count[c]);
         launch_b_finalize<T>(1, fin_items<T>(P, (int)c), P.cls_count[c], P.nparts[c], ctls, nact, P.stream);
