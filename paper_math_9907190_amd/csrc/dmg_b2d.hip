@@ -302,8 +302,9 @@ __global__ void __launch_bounds__(kRowBlock) kb_finest(int m, T cc, const Fin2<T
     jaxis_body<T, true, CH, NT>(m, cc, it.r0, it.v1, nullptr, it.u, nwx, nwaves, rows);
 }
 
-// Finest axis Jacobi fused with the Jacobi of the first diagonal level
-// (level D-1, Eqs. (Eajacr), (Eajacb)) and with u <- u + v (Section 1).  The
+// Axis Jacobi fused with the Jacobi of the diagonal level below it (Eqs.
+// (Eajacr), (Eajacb)); on the finest level (D, below it D-1) also with
+// u <- u + v (Section 1).  The
 // diagonal level's new values are computed in the row march instead of being
 // stored by one kernel and read by the next: a lane's diagonal point of row
 // k is (2t + (k&1), k); F points (odd rows) come from two rows of the
@@ -315,16 +316,12 @@ __global__ void __launch_bounds__(kRowBlock) kb_finest(int m, T cc, const Fin2<T
 // diagonal Jacobi and then kb_finest.
 constexpr int kFusePairs = 60;
 
-template <typename T, bool NT>
-__global__ void __launch_bounds__(kRowBlock) kb_finest_fused(int m, T cc, T cd, const Fin2<T>* __restrict__ items,
-                                                             int nwx, int nwaves, int rows, const Ctl* __restrict__ ctls)
+// FINEST: add the axis values to u (else store them in vA)
+template <typename T, bool FINEST, bool NT>
+__device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, const T* __restrict__ r1,
+                                  const T* __restrict__ v2, T* __restrict__ vA, double* __restrict__ u, int nwx,
+                                  int nwaves, int rows)
 {
-    const Fin2<T> it = items[blockIdx.y];
-    ITEM_GATE(ctls, it.prob);
-    const T* __restrict__ rA = it.r0;
-    const T* __restrict__ r1 = it.r1;
-    const T* __restrict__ v2 = it.v2;
-    double* __restrict__ u = it.u;
     const int lane = threadIdx.x & 63;
     const int wv = rows_wave_id(nwaves);
     if (wv >= nwaves) return;
@@ -355,7 +352,8 @@ __global__ void __launch_bounds__(kRowBlock) kb_finest_fused(int m, T cc, T cd, 
     auto ldR = [&](int j, T& x, T& y) {
         x = y = 0;
         if (!colok || j < 1 || j > m - 1) return;
-        P2<T> v = NT ? ld_pair_nt(rA + (size_t)j * w + 2 * t) : *reinterpret_cast<const P2<T>*>(rA + (size_t)j * w + 2 * t);
+        P2<T> v = (FINEST && NT) ? ld_pair_nt(rA + (size_t)j * w + 2 * t)
+                                 : *reinterpret_cast<const P2<T>*>(rA + (size_t)j * w + 2 * t);
         x = c0 ? v.x : T(0);
         y = c1 ? v.y : T(0);
     };
@@ -377,7 +375,7 @@ __global__ void __launch_bounds__(kRowBlock) kb_finest_fused(int m, T cc, T cd, 
         c.ux = c.uy = 0;
         if (jj > y1) return;
         ldR(jj, c.rx, c.ry);
-        if (useful && jj >= y0 && jj < y1 && (c0 || c1)) {
+        if (FINEST && useful && jj >= y0 && jj < y1 && (c0 || c1)) {
             P2<double> v = *reinterpret_cast<const P2<double>*>(u + (size_t)jj * w + 2 * t);
             c.ux = v.x;
             c.uy = v.y;
@@ -419,9 +417,15 @@ __global__ void __launch_bounds__(kRowBlock) kb_finest_fused(int m, T cc, T cd, 
             const T vy = qq ? C : Fm1;   // column 2t+1
             const size_t o = (size_t)(jj - 1) * w + 2 * t;
             if (useful) {
-                if (c0 && c1) *reinterpret_cast<P2<double>*>(u + o) = P2<double>{uxm1 + (double)vx, uym1 + (double)vy};
-                else if (c1) u[o + 1] = uym1 + (double)vy;
-                else if (c0) u[o] = uxm1 + (double)vx;
+                if constexpr (FINEST) {
+                    if (c0 && c1) *reinterpret_cast<P2<double>*>(u + o) = P2<double>{uxm1 + (double)vx, uym1 + (double)vy};
+                    else if (c1) u[o + 1] = uym1 + (double)vy;
+                    else if (c0) u[o] = uxm1 + (double)vx;
+                } else {
+                    if (c0 && c1) *reinterpret_cast<P2<T>*>(vA + o) = P2<T>{vx, vy};
+                    else if (c1) vA[o + 1] = vy;
+                    else if (c0) vA[o] = vx;
+                }
             }
         }
         Fm2 = Fm1;
@@ -433,6 +437,26 @@ __global__ void __launch_bounds__(kRowBlock) kb_finest_fused(int m, T cc, T cd, 
         uym1 = c.uy;
     };
     rows_march<1, Ck>(j, y1, load, proc);
+}
+
+template <typename T, bool NT>
+__global__ void __launch_bounds__(kRowBlock) kb_finest_fused(int m, T cc, T cd, const Fin2<T>* __restrict__ items,
+                                                             int nwx, int nwaves, int rows, const Ctl* __restrict__ ctls)
+{
+    const Fin2<T> it = items[blockIdx.y];
+    ITEM_GATE(ctls, it.prob);
+    fused_body<T, true, NT>(m, cc, cd, it.r0, it.r1, it.v2, nullptr, it.u, nwx, nwaves, rows);
+}
+
+// The Jacobi of an axis level L (side m, coefficient cc) with that of the
+// diagonal level L-1 below it (coefficient cd) computed in the same march
+template <typename T>
+__global__ void __launch_bounds__(kRowBlock) kb_jac_pair(int m, T cc, T cd, const JPair2<T>* __restrict__ items,
+                                                         int nwx, int nwaves, int rows, const Ctl* __restrict__ ctls)
+{
+    const JPair2<T> it = items[blockIdx.y];
+    ITEM_GATE(ctls, it.prob);
+    fused_body<T, false, false>(m, cc, cd, it.rA, it.r1, it.v2, it.vA, nullptr, nwx, nwaves, rows);
 }
 
 // tiny finest grids: one thread per point (both half-sweeps recomputed)
@@ -1480,6 +1504,15 @@ void launch_b_finest(int n, T c, T c1, int fused, const Fin2<T>* items, int nite
 }
 
 template <typename T>
+void launch_b_jac_pair(int m, T cc, T cd, const JPair2<T>* items, int nitems, const Ctl* ctls, hipStream_t s)
+{
+    int nwx, nw, nb;
+    int rows = pick_rows(m / 2 + 1, kFusePairs, m - 1);
+    rows_grid(m / 2 + 1, kFusePairs, m - 1, rows, nwx, nw, nb);
+    hipLaunchKernelGGL(kb_jac_pair<T>, dim3(nb, nitems), dim3(kRowBlock), 0, s, m, cc, cd, items, nwx, nw, rows, ctls);
+}
+
+template <typename T>
 void launch_b_restrict(int diag_in, int m, int rows, const Item2<T>* items, int nitems, const Ctl* ctls,
                        hipStream_t s)
 {
@@ -1577,6 +1610,7 @@ void launch_b_coarse_net(const LevInfo<T>* lev, const Coarse2B<T>* items, int ni
     template void launch_b_sumsq<T>(int, const Fin2<T>*, int, const Ctl*, hipStream_t);                        \
     template void launch_b_finest<T>(int, T, T, int, const Fin2<T>*, int, const Ctl*, hipStream_t);          \
     template void launch_b_restrict<T>(int, int, int, const Item2<T>*, int, const Ctl*, hipStream_t);          \
+    template void launch_b_jac_pair<T>(int, T, T, const JPair2<T>*, int, const Ctl*, hipStream_t);              \
     template void launch_b_jacobi<T>(int, int, int, T, const Item2<T>*, int, const Ctl*, hipStream_t);         \
     template void launch_b_coarse<T>(const LevInfo<T>*, const Coarse2B<T>*, int, const T*, const Ctl*, hipStream_t, \
                                      int);                                                                    \

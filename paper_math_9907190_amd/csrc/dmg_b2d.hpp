@@ -19,6 +19,18 @@ struct Item2 {
     int pad;
 };
 
+// one problem's arrays for the Jacobi of an axis level L run together with
+// that of the diagonal level L-1 below it
+template <typename T>
+struct JPair2 {
+    const T* rA;   // residual of level L
+    const T* r1;   // residual of level L-1
+    const T* v2;   // correction of level L-2
+    T* vA;         // correction of level L (output; level L-1's is not stored)
+    int prob;
+    int pad;
+};
+
 // one problem's finest-level arrays
 template <typename T>
 struct Fin2 {
@@ -64,6 +76,14 @@ void launch_b_finest(int n, T c, T c1, int fused, const Fin2<T>* items, int nite
 // the finest kernel, and the restriction into the level below it (D-2) in
 // the residual kernel (when both levels are above the coarse kernel's top lamc)
 inline bool fin_fused(int D, int lamc) { return D - 2 >= lamc; }
+// In single-problem plans (pairs = true), axis levels L = kPairLow,
+// kPairLow+2, ... below the finest (L <= D-2) run their Jacobi together with
+// that of level L-1 (launch_b_jac_pair).  Batches keep the autotuned
+// per-level launches there (measured faster).
+constexpr int kPairLow = 16;
+inline bool jac_pair(int L, int D, bool pairs) { return pairs && !(L & 1) && L >= kPairLow && L <= D - 2; }
+template <typename T>
+void launch_b_jac_pair(int m, T cc, T cd, const JPair2<T>* items, int nitems, const Ctl* ctls, hipStream_t s);
 template <typename T>
 void launch_b_restrict(int diag_in, int m, int rows, const Item2<T>* items, int nitems, const Ctl* ctls,
                        hipStream_t s);
@@ -91,6 +111,7 @@ void launch_b_coarse_net(const LevInfo<T>* lev, const Coarse2B<T>* items, int ni
 // v8 up to v9 .. v14 (r[k], v[k], c[k]: level 9 + k).  The coarse kernel
 // then runs levels 8 .. 0 only.  Needs n >= 512.
 constexpr int kMidTop = 14, kMidLow = 10, kMidCoarseTop = 8;
+static_assert(kPairLow == kMidTop + 2, "Jacobi pairs start right above the fused mid levels");
 template <typename T>
 void launch_b_mid_down(const T* r14, T* const* r, const Ctl* ctl, hipStream_t s);
 template <typename T>

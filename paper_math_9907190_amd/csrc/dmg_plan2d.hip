@@ -33,6 +33,14 @@ constexpr int kMaxSide2 = 1 << 15;
 
 int side_of(int lam) { return 1 << (1 + (lam + 1) / 2); }
 
+// does a problem (finest level D, coarse top `top`) run the Jacobi of level
+// lam as a launch of its own
+bool jac_one(const Plan2& P, int lam, int D, int top)
+{
+    return D >= 1 && lam >= top + 1 && lam <= D - 1 - (int)fin_fused(D, P.lamc) && !jac_pair(lam, D, P.pairs) &&
+           !jac_pair(lam + 1, D, P.pairs);
+}
+
 }  // namespace
 
 int plan2_layout(Plan2& P, int nprob, const int* n, int prec, double p)
@@ -87,15 +95,21 @@ int plan2_layout(Plan2& P, int nprob, const int* n, int prec, double p)
     P.off_jac_items.assign(P.Dmax + 1, 0);
     P.n_rs_items.assign(P.Dmax + 1, 0);
     P.n_jac_items.assign(P.Dmax + 1, 0);
+    P.pairs = nprob == 1;
+    P.off_pair_items.assign(P.Dmax + 1, 0);
+    P.n_pair_items.assign(P.Dmax + 1, 0);
     for (int lam = 0; lam <= P.Dmax; lam++) {
         for (int i = 0; i < nprob; i++) {
             int Dp = P.D[i];
             int top = std::min(P.lamc, Dp - 1);
             // restriction into lam (into D-2 it runs in the residual kernel when fused)
             if (Dp >= 1 && lam >= top && lam <= Dp - 2 - (int)fin_fused(Dp, P.lamc)) P.n_rs_items[lam]++;
-            // Jacobi at lam (the first diagonal level's runs in the finest kernel when fused)
-            if (Dp >= 1 && lam >= top + 1 && lam <= Dp - 1 - (int)fin_fused(Dp, P.lamc)) P.n_jac_items[lam]++;
+            // Jacobi at lam (the first diagonal level's runs in the finest kernel
+            // when fused; pair levels run together)
+            if (jac_one(P, lam, Dp, top)) P.n_jac_items[lam]++;
+            if (jac_pair(lam, Dp, P.pairs)) P.n_pair_items[lam]++;
         }
+        if (P.n_pair_items[lam]) P.off_pair_items[lam] = take(sizeof(JPair2<double>) * (size_t)P.n_pair_items[lam]);
         if (P.n_rs_items[lam]) P.off_rs_items[lam] = take(sizeof(Item2<double>) * (size_t)P.n_rs_items[lam]);
         if (P.n_jac_items[lam]) P.off_jac_items[lam] = take(sizeof(Item2<double>) * (size_t)P.n_jac_items[lam]);
     }
@@ -167,19 +181,21 @@ int write_tables(Plan2& P)
         for (int i = 0; i < P.nprob; i++) {
             int Dp = P.D[i];
             int top = std::min(P.lamc, Dp - 1);
-            if (Dp >= 1 && lam >= top + 1 && lam <= Dp - 1 - (int)fin_fused(Dp, P.lamc))
+            if (jac_one(P, lam, Dp, top))
                 items.push_back(Item2<T>{at<T>(P, P.off_r[i][lam]), at<T>(P, P.off_v[i][lam]),
                                          lam >= 1 ? at<T>(P, P.off_v[i][lam - 1]) : zero, i, 0});
         }
         if (!items.empty() &&
             hipMemcpy(P.ws + P.off_jac_items[lam], items.data(), items.size() * sizeof(Item2<T>), hipMemcpyHostToDevice) != hipSuccess)
             return MG_ERR_HIP;
-    }
-    if (fin_fused(P.D[0], P.lamc)) {
-        // problem 0's first diagonal level, for plan2_level_get
-        const int D = P.D[0];
-        Item2<T> it{at<T>(P, P.off_r[0][D - 1]), at<T>(P, P.off_v[0][D - 1]), at<T>(P, P.off_v[0][D - 2]), 0, 0};
-        if (hipMemcpy(P.ws + P.off_lg_item, &it, sizeof(it), hipMemcpyHostToDevice) != hipSuccess) return MG_ERR_HIP;
+        std::vector<JPair2<T>> pairs;
+        for (int i = 0; i < P.nprob; i++)
+            if (jac_pair(lam, P.D[i], P.pairs))
+                pairs.push_back(JPair2<T>{at<T>(P, P.off_r[i][lam]), at<T>(P, P.off_r[i][lam - 1]),
+                                          at<T>(P, P.off_v[i][lam - 2]), at<T>(P, P.off_v[i][lam]), i, 0});
+        if (!pairs.empty() &&
+            hipMemcpy(P.ws + P.off_pair_items[lam], pairs.data(), pairs.size() * sizeof(JPair2<T>), hipMemcpyHostToDevice) != hipSuccess)
+            return MG_ERR_HIP;
     }
     std::vector<Coarse2B<T>> co;
     for (int i = 0; i < P.nprob; i++) {
@@ -332,6 +348,15 @@ void enq_cycle(Plan2& P, Ctl* ctls)
                                P.stream, cap);
     }
     for (int lam = 0; lam <= P.Dmax; lam++) {
+        if (int kp = P.n_pair_items[lam]) {
+            const int m = side_of(lam);
+            const double M = m / 2;
+            // r of both levels, v of the level below the pair, v written
+            const double b = es * (2.0 * (double)sizeA(m) + (double)sizeD(m) + (M + 1) * (M + 1));
+            Timed t(&P.tm, MG_K_JACOBI, b * kp);
+            launch_b_jac_pair<T>(m, (T)coef(P, lam), (T)coef(P, lam - 1), at<JPair2<T>>(P, P.off_pair_items[lam]), kp,
+                                 ctls, P.stream);
+        }
         int k = P.n_jac_items[lam];
         if (!k) continue;
         if (mid && lam > kMidLow && lam <= kMidTop) {
@@ -558,12 +583,16 @@ int plan2_solve(Plan2& P, double* const* u, const double* const* f, double rtol,
 }
 
 template <typename T>
-void recompute_first_diag(Plan2& P)
+int recompute_diag(Plan2& P, int lam)
 {
-    const int D = P.D[0];
+    Item2<T> it{at<T>(P, P.off_r[0][lam]), at<T>(P, P.off_v[0][lam]), at<T>(P, P.off_v[0][lam - 1]), 0, 0};
+    if (hipStreamSynchronize(P.stream) != hipSuccess ||
+        hipMemcpy(P.ws + P.off_lg_item, &it, sizeof(it), hipMemcpyHostToDevice) != hipSuccess)
+        return MG_ERR_HIP;
     // the zero block serves as a control block that is never done
-    launch_b_jacobi<T>(1, side_of(D - 1), P.rows_jac[D - 1], (T)coef(P, D - 1), at<Item2<T>>(P, P.off_lg_item), 1,
-                       at<Ctl>(P, P.off_zero), P.stream);
+    launch_b_jacobi<T>(1, side_of(lam), b_default_rows(2, side_of(lam)), (T)coef(P, lam),
+                       at<Item2<T>>(P, P.off_lg_item), 1, at<Ctl>(P, P.off_zero), P.stream);
+    return last_launch();
 }
 
 int plan2_level_get(Plan2& P, int depth, int which, double* dst)
@@ -575,12 +604,13 @@ int plan2_level_get(Plan2& P, int depth, int which, double* dst)
     int m = side_of(lam);
     int diag = lam & 1;
     size_t off = (which == 0) ? (depth == 0 ? P.off_r0[0] : P.off_r[0][lam]) : P.off_v[0][lam];
-    if (which == 1 && depth == 1 && fin_fused(D, P.lamc)) {
-        // the cycle computed this level inside the finest kernel without
-        // storing it: rerun its Jacobi (same arithmetic, so the same values)
-        // from the residual and the coarser correction the cycle left
-        if (P.prec == MG_FP64) recompute_first_diag<double>(P);
-        else recompute_first_diag<float>(P);
+    if (which == 1 && (lam & 1) && ((lam == D - 1 && fin_fused(D, P.lamc)) || jac_pair(lam + 1, D, P.pairs))) {
+        // the cycle computed this diagonal level inside the Jacobi of the
+        // axis level above it without storing it: rerun its Jacobi (same
+        // arithmetic, so the same values) from the residual and the coarser
+        // correction the cycle left
+        int e = P.prec == MG_FP64 ? recompute_diag<double>(P, lam) : recompute_diag<float>(P, lam);
+        if (e) return e;
     }
     if (P.prec == MG_FP64) launch_b_level_get<double>(diag, m, at<double>(P, off), dst, P.stream);
     else launch_b_level_get<float>(diag, m, at<float>(P, off), dst, P.stream);

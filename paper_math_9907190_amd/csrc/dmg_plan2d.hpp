@@ -20,6 +20,9 @@ struct Plan2 {
     std::vector<std::vector<size_t>> off_r, off_v;   // [problem][aligned level]
     std::vector<size_t> off_rs_items, off_jac_items; // [aligned level]
     std::vector<int> n_rs_items, n_jac_items;
+    bool pairs = false;                              // Jacobi pairs in use (single problem)
+    std::vector<size_t> off_pair_items;              // [aligned level L]: Jacobi pairs (L, L-1)
+    std::vector<int> n_pair_items;
     int n_coarse_items = 0;
     std::vector<int> rows_rs, rows_jac;              // launch shape per level (0: one thread per point)
     // runtime

@@ -73,7 +73,7 @@ def test_every_level_of_one_cycle_fp64(dmg, orc, dim, n):
     assert np.array_equal(ug[(0,) + (slice(None),) * (dim - 1)], u0[(0,) + (slice(None),) * (dim - 1)])
 
 
-@pytest.mark.parametrize("dim,n", [(2, 16), (2, 256), (2, 512), (3, 8), (3, 32), (3, 128)])
+@pytest.mark.parametrize("dim,n", [(2, 16), (2, 256), (2, 512), (2, 1024), (3, 8), (3, 32), (3, 128)])
 def test_every_level_of_one_cycle_fp32(dmg, orc, dim, n):
     """Single-precision levels.  Every restriction is an average with positive
     weights, so its rounding error is bounded by a few float ulps of the
