@@ -95,12 +95,13 @@ int mg_solve(mg_plan *plan, double *u, const double *f, double rtol, int max_cyc
  * natural order, m = the level's side in units of its stride; points not on
  * the level and boundary points read 0).  which = 0: restricted residual
  * r (depth 0 .. D); which = 1: correction v (depth 1 .. D; the finest
- * correction is added to u and not kept).  When the finest level's kernel
- * also runs the Jacobi of depth 1 (finest grids of side 128 and up), that
- * correction is not stored by the cycle: which = 1, depth = 1 recomputes it
- * (same arithmetic, same values) from the depth-1 residual and the depth-2
- * correction, so it is the last cycle's only right after mg_vcycle (mg_solve
- * ends with a fresh residual).  For parity tests. */
+ * correction is added to u and not kept).  Some diagonal levels' Jacobi runs
+ * inside the kernel of the axis level above them, which does not store their
+ * correction (2D: depth 1 for finest sides >= 128; in a single-problem plan
+ * also the odd depths whose aligned level is >= 15).  which = 1 recomputes
+ * such a level (same arithmetic, same values) from its residual and the
+ * next coarser correction, so it is the last cycle's only right after
+ * mg_vcycle (mg_solve ends with a fresh residual).  For parity tests. */
 int mg_level_get(mg_plan *plan, int depth, int which, double *dst);
 
 /* Number of levels D+1 and the side m of level `depth` (host-only). */
