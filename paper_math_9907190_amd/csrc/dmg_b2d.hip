@@ -534,6 +534,83 @@ __global__ void __launch_bounds__(kRowBlock) kb_a2d_rows(int m, const Item2<T>* 
     rows_march<CH, Ck>(y0, y1 - 1, load, proc);
 }
 
+// Eqs. (Erest2r) then (Erest2b) in one march: the residual of an axis level
+// L (side m) onto the diagonal level L-1 (stored) and from there onto the
+// axis level L-2 (side m/2), the diagonal values of three consecutive rows
+// kept in registers, as the residual kernel does below the finest level.
+// Lanes 1 .. 61 write r1, lanes 2 .. 62 write r2; strips start on odd rows
+// (rows is even) and compute one diagonal row past their end.
+template <typename T, int CH>
+__global__ void __launch_bounds__(kRowBlock) kb_rs_pair(int m, const RsPair2<T>* __restrict__ items, int nwx,
+                                                        int nwaves, int rows, const Ctl* __restrict__ ctls)
+{
+    const RsPair2<T> it = items[blockIdx.y];
+    ITEM_GATE(ctls, it.prob);
+    const T* __restrict__ rA = it.rA;
+    T* __restrict__ rD = it.r1;
+    T* __restrict__ rA2 = it.r2;
+    const int lane = threadIdx.x & 63;
+    const int wv = rows_wave_id(nwaves);
+    if (wv >= nwaves) return;
+    const int wx = wv % nwx, sy = wv / nwx;
+    const int t = wx * kResidPairs - 1 + lane;
+    const int y0 = 1 + sy * rows;
+    const int y1 = min(y0 + rows, m);
+    const int mc = m / 2;
+    const bool useful = lane >= 1 && lane <= kResidPairs && t >= 0 && t <= m / 2;
+    const bool useful2 = lane >= 2 && lane <= kResidPairs + 1 && t >= 1 && t <= mc - 1;
+    const bool colok = t >= 0 && t <= m / 2;
+    const bool c0 = t >= 1 && 2 * t <= m - 1, c1 = t >= 0 && 2 * t + 1 <= m - 1;
+    const size_t w = (size_t)(m + 1);
+    const int W = m / 2 + 1;
+    auto ldr = [&](int j, T& x, T& y) {
+        x = y = 0;
+        if (!colok || j < 1 || j > m - 1) return;
+        P2<T> v = *reinterpret_cast<const P2<T>*>(rA + (size_t)j * w + 2 * t);
+        x = c0 ? v.x : T(0);
+        y = c1 ? v.y : T(0);
+    };
+    struct Ck { T x[CH], y[CH]; };
+    auto load = [&](int jb, Ck& c) {
+#pragma unroll
+        for (int i = 0; i < CH; i++) {
+            c.x[i] = c.y[i] = 0;
+            if (jb + i <= y1) ldr(jb + i + 1, c.x[i], c.y[i]);
+        }
+    };
+    T rm0, rm1, rc0, rc1;
+    ldr(y0 - 1, rm0, rm1);
+    ldr(y0, rc0, rc1);
+    T d3 = 0, d2 = 0;   // diagonal values of rows j-2, j-1
+    auto proc = [&](int jb, const Ck& c) {
+#pragma unroll
+        for (int i = 0; i < CH; i++) {
+            const int j = jb + i;
+            if (j > y1) break;
+            const int q = j & 1;
+            const T sh = q ? __shfl_down(rc0, 1) : __shfl_up(rc1, 1);
+            const T rc = q ? rc1 : rc0;
+            const T rw = q ? rc0 : sh;
+            const T re = q ? sh : rc1;
+            const T rs = q ? rm1 : rm0;
+            const T rn = q ? c.y[i] : c.x[i];
+            const int a = 2 * t + q;
+            const T d1 = rs2_core(rc, rw, rs, re, rn);
+            if (useful && a >= 1 && a <= m - 1 && j < y1) rD[(size_t)j * W + t] = d1;
+            // axis point (t, B) of level L-2, B = (j-1)/2: diagonal rows 2B-1, 2B, 2B+1
+            if (q && j - 1 >= y0 && j - 1 < y1) {
+                const int B = (j - 1) >> 1;
+                const T d3w = __shfl_up(d3, 1), d1w = __shfl_up(d1, 1);
+                if (useful2 && B >= 1 && B <= mc - 1) rA2[(size_t)B * (mc + 1) + t] = rs2_core(d2, d3w, d3, d1, d1w);
+            }
+            d3 = d2;
+            d2 = d1;
+            rm0 = rc0; rm1 = rc1; rc0 = c.x[i]; rc1 = c.y[i];
+        }
+    };
+    rows_march<CH, Ck>(y0, y1, load, proc);
+}
+
 // Eq. (Erest2b): diagonal grid (side m) -> axis grid (side m/2), row-marching.
 // Lane owns coarse column A (lane 0 is a halo lane) and marches over coarse rows B.
 template <typename T, int CH>
@@ -1395,6 +1472,7 @@ void launch_b_level_get(int diag, int m, const T* src, double* dst, hipStream_t 
 }
 
 // ================================================================= launchers
+constexpr int kChunkRsPair = 2;
 constexpr int kChunkResid = 4, kChunkA2D = 1, kChunkD2A = 4, kChunkJDiag = 2, kChunkJAxis = 1;
 constexpr int kTargetWavesResid = 8192;  // ~120 VGPRs: 16 waves per CU
 constexpr int kRowsMinSide = 512;        // smaller levels: one thread per point
@@ -1501,6 +1579,17 @@ void launch_b_finest(int n, T c, T c1, int fused, const Fin2<T>* items, int nite
     else
         hipLaunchKernelGGL((kb_finest<T, kChunkJAxis, false>), dim3(nb, nitems), dim3(kRowBlock), 0, s, n, c, items, nwx,
                            nw, rows, ctls);
+}
+
+template <typename T>
+void launch_b_rs_pair(int m, const RsPair2<T>* items, int nitems, const Ctl* ctls, hipStream_t s)
+{
+    int nwx, nw, nb;
+    // rows is a power of two >= 4: every strip starts on an odd row
+    int rows = pick_rows(m / 2 + 1, kResidPairs, m - 1);
+    rows_grid(m / 2 + 1, kResidPairs, m - 1, rows, nwx, nw, nb);
+    hipLaunchKernelGGL((kb_rs_pair<T, kChunkRsPair>), dim3(nb, nitems), dim3(kRowBlock), 0, s, m, items, nwx, nw, rows,
+                       ctls);
 }
 
 template <typename T>
@@ -1611,6 +1700,7 @@ void launch_b_coarse_net(const LevInfo<T>* lev, const Coarse2B<T>* items, int ni
     template void launch_b_finest<T>(int, T, T, int, const Fin2<T>*, int, const Ctl*, hipStream_t);          \
     template void launch_b_restrict<T>(int, int, int, const Item2<T>*, int, const Ctl*, hipStream_t);          \
     template void launch_b_jac_pair<T>(int, T, T, const JPair2<T>*, int, const Ctl*, hipStream_t);              \
+    template void launch_b_rs_pair<T>(int, const RsPair2<T>*, int, const Ctl*, hipStream_t);                    \
     template void launch_b_jacobi<T>(int, int, int, T, const Item2<T>*, int, const Ctl*, hipStream_t);         \
     template void launch_b_coarse<T>(const LevInfo<T>*, const Coarse2B<T>*, int, const T*, const Ctl*, hipStream_t, \
                                      int);                                                                    \

@@ -31,6 +31,17 @@ struct JPair2 {
     int pad;
 };
 
+// one problem's arrays for the restrictions from an axis level L to L-1
+// and on to L-2 in one launch
+template <typename T>
+struct RsPair2 {
+    const T* rA;   // residual of level L
+    T* r1;         // residual of level L-1 (output)
+    T* r2;         // residual of level L-2 (output)
+    int prob;
+    int pad;
+};
+
 // one problem's finest-level arrays
 template <typename T>
 struct Fin2 {
@@ -78,12 +89,15 @@ void launch_b_finest(int n, T c, T c1, int fused, const Fin2<T>* items, int nite
 inline bool fin_fused(int D, int lamc) { return D - 2 >= lamc; }
 // In single-problem plans (pairs = true), axis levels L = kPairLow,
 // kPairLow+2, ... below the finest (L <= D-2) run their Jacobi together with
-// that of level L-1 (launch_b_jac_pair).  Batches keep the autotuned
-// per-level launches there (measured faster).
+// that of level L-1 (launch_b_jac_pair), and the restrictions from L into L-1
+// and L-2 run in one launch (launch_b_rs_pair).  Batches keep the autotuned
+// per-level launches there (measured faster for the Jacobi steps).
 constexpr int kPairLow = 16;
-inline bool jac_pair(int L, int D, bool pairs) { return pairs && !(L & 1) && L >= kPairLow && L <= D - 2; }
+inline bool pair_level(int L, int D, bool pairs) { return pairs && !(L & 1) && L >= kPairLow && L <= D - 2; }
 template <typename T>
 void launch_b_jac_pair(int m, T cc, T cd, const JPair2<T>* items, int nitems, const Ctl* ctls, hipStream_t s);
+template <typename T>
+void launch_b_rs_pair(int m, const RsPair2<T>* items, int nitems, const Ctl* ctls, hipStream_t s);
 template <typename T>
 void launch_b_restrict(int diag_in, int m, int rows, const Item2<T>* items, int nitems, const Ctl* ctls,
                        hipStream_t s);

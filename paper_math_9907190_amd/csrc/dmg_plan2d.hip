@@ -37,8 +37,15 @@ int side_of(int lam) { return 1 << (1 + (lam + 1) / 2); }
 // lam as a launch of its own
 bool jac_one(const Plan2& P, int lam, int D, int top)
 {
-    return D >= 1 && lam >= top + 1 && lam <= D - 1 - (int)fin_fused(D, P.lamc) && !jac_pair(lam, D, P.pairs) &&
-           !jac_pair(lam + 1, D, P.pairs);
+    return D >= 1 && lam >= top + 1 && lam <= D - 1 - (int)fin_fused(D, P.lamc) && !pair_level(lam, D, P.pairs) &&
+           !pair_level(lam + 1, D, P.pairs);
+}
+
+// ... and the restriction into level lam
+bool rs_one(const Plan2& P, int lam, int D, int top)
+{
+    return D >= 1 && lam >= top && lam <= D - 2 - (int)fin_fused(D, P.lamc) && !pair_level(lam + 1, D, P.pairs) &&
+           !pair_level(lam + 2, D, P.pairs);
 }
 
 }  // namespace
@@ -98,18 +105,23 @@ int plan2_layout(Plan2& P, int nprob, const int* n, int prec, double p)
     P.pairs = nprob == 1;
     P.off_pair_items.assign(P.Dmax + 1, 0);
     P.n_pair_items.assign(P.Dmax + 1, 0);
+    P.off_rsp_items.assign(P.Dmax + 1, 0);
+    P.n_rsp_items.assign(P.Dmax + 1, 0);
     for (int lam = 0; lam <= P.Dmax; lam++) {
         for (int i = 0; i < nprob; i++) {
             int Dp = P.D[i];
             int top = std::min(P.lamc, Dp - 1);
-            // restriction into lam (into D-2 it runs in the residual kernel when fused)
-            if (Dp >= 1 && lam >= top && lam <= Dp - 2 - (int)fin_fused(Dp, P.lamc)) P.n_rs_items[lam]++;
+            // restriction into lam (into D-2 it runs in the residual kernel when
+            // fused; pair levels restrict two levels at once)
+            if (rs_one(P, lam, Dp, top)) P.n_rs_items[lam]++;
+            if (pair_level(lam, Dp, P.pairs)) P.n_rsp_items[lam]++;
             // Jacobi at lam (the first diagonal level's runs in the finest kernel
             // when fused; pair levels run together)
             if (jac_one(P, lam, Dp, top)) P.n_jac_items[lam]++;
-            if (jac_pair(lam, Dp, P.pairs)) P.n_pair_items[lam]++;
+            if (pair_level(lam, Dp, P.pairs)) P.n_pair_items[lam]++;
         }
         if (P.n_pair_items[lam]) P.off_pair_items[lam] = take(sizeof(JPair2<double>) * (size_t)P.n_pair_items[lam]);
+        if (P.n_rsp_items[lam]) P.off_rsp_items[lam] = take(sizeof(RsPair2<double>) * (size_t)P.n_rsp_items[lam]);
         if (P.n_rs_items[lam]) P.off_rs_items[lam] = take(sizeof(Item2<double>) * (size_t)P.n_rs_items[lam]);
         if (P.n_jac_items[lam]) P.off_jac_items[lam] = take(sizeof(Item2<double>) * (size_t)P.n_jac_items[lam]);
     }
@@ -170,7 +182,7 @@ int write_tables(Plan2& P)
         for (int i = 0; i < P.nprob; i++) {
             int Dp = P.D[i];
             int top = std::min(P.lamc, Dp - 1);
-            if (Dp >= 1 && lam >= top && lam <= Dp - 2 - (int)fin_fused(Dp, P.lamc))
+            if (rs_one(P, lam, Dp, top))
                 items.push_back(Item2<T>{at<T>(P, P.off_r[i][lam]), at<T>(P, P.off_v[i][lam]),
                                          at<T>(P, P.off_r[i][lam + 1]), i, 0});
         }
@@ -188,9 +200,17 @@ int write_tables(Plan2& P)
         if (!items.empty() &&
             hipMemcpy(P.ws + P.off_jac_items[lam], items.data(), items.size() * sizeof(Item2<T>), hipMemcpyHostToDevice) != hipSuccess)
             return MG_ERR_HIP;
+        std::vector<RsPair2<T>> rsp;
+        for (int i = 0; i < P.nprob; i++)
+            if (pair_level(lam, P.D[i], P.pairs))
+                rsp.push_back(RsPair2<T>{at<T>(P, P.off_r[i][lam]), at<T>(P, P.off_r[i][lam - 1]),
+                                         at<T>(P, P.off_r[i][lam - 2]), i, 0});
+        if (!rsp.empty() &&
+            hipMemcpy(P.ws + P.off_rsp_items[lam], rsp.data(), rsp.size() * sizeof(RsPair2<T>), hipMemcpyHostToDevice) != hipSuccess)
+            return MG_ERR_HIP;
         std::vector<JPair2<T>> pairs;
         for (int i = 0; i < P.nprob; i++)
-            if (jac_pair(lam, P.D[i], P.pairs))
+            if (pair_level(lam, P.D[i], P.pairs))
                 pairs.push_back(JPair2<T>{at<T>(P, P.off_r[i][lam]), at<T>(P, P.off_r[i][lam - 1]),
                                           at<T>(P, P.off_v[i][lam - 2]), at<T>(P, P.off_v[i][lam]), i, 0});
         if (!pairs.empty() &&
@@ -307,6 +327,12 @@ void enq_cycle(Plan2& P, Ctl* ctls)
     auto R = [&](int lam) { return at<T>(P, P.off_r[0][lam]); };
     auto V = [&](int lam) { return at<T>(P, P.off_v[0][lam]); };
     for (int lam = P.Dmax - 2; lam >= 0; lam--) {
+        if (int kp = lam + 1 <= P.Dmax ? P.n_rsp_items[lam + 1] : 0) {   // into lam and lam-1
+            const int m = side_of(lam + 1);
+            const double M = m / 2;
+            Timed t(&P.tm, MG_K_RESTRICT, (bytes_rs(0, m, es) + es * (M - 1) * (M - 1)) * kp);
+            launch_b_rs_pair<T>(m, at<RsPair2<T>>(P, P.off_rsp_items[lam + 1]), kp, ctls, P.stream);
+        }
         int k = P.n_rs_items[lam];
         if (!k) continue;
         if (mid && lam >= kMidLow && lam < kMidTop) {
@@ -604,7 +630,7 @@ int plan2_level_get(Plan2& P, int depth, int which, double* dst)
     int m = side_of(lam);
     int diag = lam & 1;
     size_t off = (which == 0) ? (depth == 0 ? P.off_r0[0] : P.off_r[0][lam]) : P.off_v[0][lam];
-    if (which == 1 && (lam & 1) && ((lam == D - 1 && fin_fused(D, P.lamc)) || jac_pair(lam + 1, D, P.pairs))) {
+    if (which == 1 && (lam & 1) && ((lam == D - 1 && fin_fused(D, P.lamc)) || pair_level(lam + 1, D, P.pairs))) {
         // the cycle computed this diagonal level inside the Jacobi of the
         // axis level above it without storing it: rerun its Jacobi (same
         // arithmetic, so the same values) from the residual and the coarser

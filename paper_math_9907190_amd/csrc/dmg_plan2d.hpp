@@ -23,6 +23,8 @@ struct Plan2 {
     bool pairs = false;                              // Jacobi pairs in use (single problem)
     std::vector<size_t> off_pair_items;              // [aligned level L]: Jacobi pairs (L, L-1)
     std::vector<int> n_pair_items;
+    std::vector<size_t> off_rsp_items;               // [aligned level L]: restrictions L -> L-1 -> L-2
+    std::vector<int> n_rsp_items;
     int n_coarse_items = 0;
     std::vector<int> rows_rs, rows_jac;              // launch shape per level (0: one thread per point)
     // runtime
