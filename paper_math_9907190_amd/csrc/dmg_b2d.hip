@@ -14,8 +14,11 @@
 // Per point the arithmetic is the paper's: Eqs. (Erest2r), (Erest2b),
 // (Eajacr), (Eajacb) and the axis-grid Jacobi, terms in the printed order.
 #include "dmg_b2d.hpp"
+#include "dmg_host.hpp"
 #include "dmg_net_dev.hpp"
 #include "dmg_rows.hpp"
+
+#include <hip/hip_ext.h>
 
 namespace dmg {
 
@@ -1521,21 +1524,32 @@ int b_resid_parts(int n)
     return nb;
 }
 
+// A launch that takes the events of an open timing bracket, if any
+template <typename K, typename... Args>
+static void launch_timed(K kern, dim3 g, dim3 b, hipStream_t s, Args... args)
+{
+    TimedSlot*& ts = timed_slot();
+    if (ts) {
+        hipExtLaunchKernelGGL(kern, g, b, 0, s, ts->beg, ts->end, 0, args...);
+        ts = nullptr;
+    } else {
+        hipLaunchKernelGGL(kern, g, b, 0, s, args...);
+    }
+}
+
 template <typename T>
 void launch_b_resid(int n, int fused, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s)
 {
     double inv_h2 = (double)n * (double)n;
     if (n < 4) {
-        hipLaunchKernelGGL(kb_resid_small<T>, dim3(1, nitems), dim3(kRowBlock), 0, s, n, inv_h2, items, ctls);
+        launch_timed(kb_resid_small<T>, dim3(1, nitems), dim3(kRowBlock), s, n, inv_h2, items, ctls);
         return;
     }
     int nwx, nw, nb;
     // rows is a power of two >= 4: every strip starts on an odd row
     int rows = pick_rows(n / 2 + 1, kResidPairs, n - 1, kTargetWavesResid);
     rows_grid(n / 2 + 1, kResidPairs, n - 1, rows, nwx, nw, nb);
-    auto go = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3(nb, nitems), dim3(kRowBlock), 0, s, n, inv_h2, items, nwx, nw, rows, ctls);
-    };
+    auto go = [&](auto kern) { launch_timed(kern, dim3(nb, nitems), dim3(kRowBlock), s, n, inv_h2, items, nwx, nw, rows, ctls); };
     const bool nt = nt_hint(n);
     if (fused && n >= 8) {
         if (nt) go(kb_resid<T, kChunkResid, true, true>);
@@ -1556,7 +1570,7 @@ template <typename T>
 void launch_b_finest(int n, T c, T c1, int fused, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s)
 {
     if (n < 8) {
-        hipLaunchKernelGGL(kb_finest_small<T>, dim3(1, nitems), dim3(kRowBlock), 0, s, n, c, items, ctls);
+        launch_timed(kb_finest_small<T>, dim3(1, nitems), dim3(kRowBlock), s, n, c, items, ctls);
         return;
     }
     int nwx, nw, nb;
@@ -1564,21 +1578,21 @@ void launch_b_finest(int n, T c, T c1, int fused, const Fin2<T>* items, int nite
         int rows = pick_rows(n / 2 + 1, kFusePairs, n - 1);
         rows_grid(n / 2 + 1, kFusePairs, n - 1, rows, nwx, nw, nb);
         if (nt_hint(n))
-            hipLaunchKernelGGL((kb_finest_fused<T, true>), dim3(nb, nitems), dim3(kRowBlock), 0, s, n, c, c1, items, nwx,
-                               nw, rows, ctls);
+            launch_timed((kb_finest_fused<T, true>), dim3(nb, nitems), dim3(kRowBlock), s, n, c, c1, items, nwx,
+                         nw, rows, ctls);
         else
-            hipLaunchKernelGGL((kb_finest_fused<T, false>), dim3(nb, nitems), dim3(kRowBlock), 0, s, n, c, c1, items, nwx,
-                               nw, rows, ctls);
+            launch_timed((kb_finest_fused<T, false>), dim3(nb, nitems), dim3(kRowBlock), s, n, c, c1, items, nwx,
+                         nw, rows, ctls);
         return;
     }
     int rows = pick_rows(n / 2 + 1, kPairsPerWave, n - 1);
     rows_grid(n / 2 + 1, kPairsPerWave, n - 1, rows, nwx, nw, nb);
     if (nt_hint(n))
-        hipLaunchKernelGGL((kb_finest<T, kChunkJAxis, true>), dim3(nb, nitems), dim3(kRowBlock), 0, s, n, c, items, nwx,
-                           nw, rows, ctls);
+        launch_timed((kb_finest<T, kChunkJAxis, true>), dim3(nb, nitems), dim3(kRowBlock), s, n, c, items, nwx,
+                     nw, rows, ctls);
     else
-        hipLaunchKernelGGL((kb_finest<T, kChunkJAxis, false>), dim3(nb, nitems), dim3(kRowBlock), 0, s, n, c, items, nwx,
-                           nw, rows, ctls);
+        launch_timed((kb_finest<T, kChunkJAxis, false>), dim3(nb, nitems), dim3(kRowBlock), s, n, c, items, nwx,
+                     nw, rows, ctls);
 }
 
 template <typename T>

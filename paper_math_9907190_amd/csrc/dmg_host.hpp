@@ -63,20 +63,48 @@ struct Timing {
 };
 
 // Brackets one launch with events when its family is the measured one.
+// The start and stop events of an open Timed bracket whose launcher times
+// its single kernel itself (the dispatch records them: hipExtLaunchKernel),
+// so that the figure is the kernel's own duration without the event packets
+// around it.  Set only while such a bracket is open.
+struct TimedSlot {
+    hipEvent_t beg, end;
+};
+inline TimedSlot*& timed_slot()
+{
+    static thread_local TimedSlot* s = nullptr;
+    return s;
+}
+
+// ext: the launcher in the bracket takes the events from timed_slot()
 struct Timed {
     Timing* T;
-    bool on;
-    Timed(Timing* t, int fam, double bytes) : T(t), on(t->ev && t->fam == fam)
+    bool on, ext;
+    TimedSlot slot;
+    Timed(Timing* t, int fam, double bytes, bool ext_ = false) : T(t), on(t->ev && t->fam == fam), ext(ext_)
     {
         if (!on) return;
         if (T->pend == kTimedMax) T->flush();
-        (void)hipEventRecord(T->beg[T->pend], T->stream);
+        if (ext) {
+            slot = TimedSlot{T->beg[T->pend], T->end[T->pend]};
+            timed_slot() = &slot;
+        } else {
+            (void)hipEventRecord(T->beg[T->pend], T->stream);
+        }
         T->bytes += bytes;
         T->count++;
     }
     ~Timed()
     {
-        if (on) (void)hipEventRecord(T->end[T->pend++], T->stream);
+        if (!on) return;
+        if (ext && timed_slot() == &slot) {   // nothing took the events: an empty bracket
+            (void)hipEventRecord(T->beg[T->pend], T->stream);
+            (void)hipEventRecord(T->end[T->pend], T->stream);
+            timed_slot() = nullptr;
+        } else if (!ext) {
+            (void)hipEventRecord(T->end[T->pend], T->stream);
+        }
+        T->pend++;
     }
 };
 

@@ -298,7 +298,7 @@ void enq_resid(Plan2& P, Ctl* ctls, int* nact)
         {
             const int n = P.cls_n[c];
             const bool fz = fin_fused(2 * (ilog2(n) - 1), P.lamc);
-            Timed t(&P.tm, MG_K_RESIDUAL, bytes_resid(n, es, fz) * P.cls_count[c]);
+            Timed t(&P.tm, MG_K_RESIDUAL, bytes_resid(n, es, fz) * P.cls_count[c], true);
             launch_b_resid<T>(n, fz ? 1 : 0, fin_items<T>(P, (int)c), P.cls_count[c], ctls, P.stream);
         }
         Timed t(&P.tm, MG_K_NORM, 8.0 * P.nparts[c] * P.cls_count[c]);
@@ -406,7 +406,7 @@ void enq_cycle(Plan2& P, Ctl* ctls)
         int n = P.cls_n[c];
         const int D = 2 * (ilog2(n) - 1);
         const bool fz = fin_fused(D, P.lamc);
-        Timed t(&P.tm, MG_K_FINEST, bytes_finest(n, es, fz) * P.cls_count[c]);
+        Timed t(&P.tm, MG_K_FINEST, bytes_finest(n, es, fz) * P.cls_count[c], true);
         double sh = 1.0 / n;
         launch_b_finest<T>(n, (T)(P.p * sh * sh), (T)(fz ? coef(P, D - 1) : 0.0), fz ? 1 : 0, fin_items<T>(P, (int)c),
                            P.cls_count[c], ctls, P.stream);
