@@ -319,35 +319,44 @@ __global__ void __launch_bounds__(kRowBlock) kb_finest(int m, T cc, const Fin2<T
 // diagonal Jacobi and then kb_finest.
 constexpr int kFusePairs = 60;
 
-// FINEST: add the axis values to u (else store them in vA)
-template <typename T, bool FINEST, bool NT>
+// FINEST: add the axis values to u (else store them in vA).
+// MIR (odd strips): the strip is marched from its last row to its first, as
+// the same march over the grid mirrored in y (rows m - j; m is even, so row
+// parities and the F/C structure are unchanged); the stencil operands are
+// passed in the unmirrored order, so the values are the same bits.  Two
+// neighbouring strips then reach the rows they share at the same time (both
+// at their start or both at their end), while those rows are still in L2.
+template <typename T, bool FINEST, bool NT, bool MIR>
 __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, const T* __restrict__ r1,
-                                  const T* __restrict__ v2, T* __restrict__ vA, double* __restrict__ u, int nwx,
-                                  int nwaves, int rows)
+                                  const T* __restrict__ v2, T* __restrict__ vA, double* __restrict__ u, int wv,
+                                  int nwx, int rows)
 {
     const int lane = threadIdx.x & 63;
-    const int wv = rows_wave_id(nwaves);
-    if (wv >= nwaves) return;
     const int wx = wv % nwx, sy = wv / nwx;
     const int t = wx * kFusePairs - 2 + lane;
-    const int y0 = 1 + sy * rows;
-    const int y1 = min(y0 + rows, m);
+    const int ya = 1 + sy * rows, yb = min(ya + rows, m);   // the strip's rows [ya, yb)
+    const int y0 = MIR ? m - yb + 1 : ya;                   // the same rows as marched
+    const int y1 = MIR ? m - ya + 1 : yb;
     const int h = m / 2, W = h + 1;   // row length of the diagonal level and of v2 (side m/2)
+    auto R = [&](int k) { return MIR ? m - k : k; };       // marched row -> grid row
+    auto RB = [&](int B) { return MIR ? h - B : B; };      // the same on the level of side m/2
     const bool useful = lane >= 2 && lane < kFusePairs + 2 && t >= 0 && t <= h;
     const bool colok = t >= 0 && t <= h;
     const bool c0 = t >= 1 && 2 * t <= m - 1, c1 = t >= 0 && 2 * t + 1 <= m - 1;
     const size_t w = (size_t)(m + 1);
-    auto ld2 = [&](int B) -> T { return (colok && B >= 0 && B <= h) ? v2[(size_t)B * W + t] : T(0); };
-    auto ld1 = [&](int k) -> T { return (colok && k >= 0 && k <= m) ? r1[(size_t)k * W + t] : T(0); };
+    auto ld2 = [&](int B) -> T { return (colok && B >= 0 && B <= h) ? v2[(size_t)RB(B) * W + t] : T(0); };
+    auto ld1 = [&](int k) -> T { return (colok && k >= 0 && k <= m) ? r1[(size_t)R(k) * W + t] : T(0); };
     // F point (2t+1, k), k odd, from v2 rows (k-1)/2 (vlo) and (k+1)/2 (vhi), as jac2_diagF
     auto f21 = [&](int k, T rF, T vlo, T vhi) -> T {
         const T vlo_e = __shfl_down(vlo, 1), vhi_e = __shfl_down(vhi, 1);
-        return (t >= 0 && t <= h - 1 && k >= 1 && k <= m - 1) ? jac2_chain(cd, rF, vlo, vlo_e, vhi_e, vhi) : T(0);
+        if (!(t >= 0 && t <= h - 1 && k >= 1 && k <= m - 1)) return T(0);
+        return MIR ? jac2_chain(cd, rF, vhi, vhi_e, vlo_e, vlo) : jac2_chain(cd, rF, vlo, vlo_e, vhi_e, vhi);
     };
     // C point (2t, k), k even, from the F rows k-1 (Fm) and k+1 (Fp), as jac2_diagC
     auto c21 = [&](int k, T rC, T Fm, T Fp) -> T {
         const T Fm_w = __shfl_up(Fm, 1), Fp_w = __shfl_up(Fp, 1);
-        return (t >= 1 && t <= h - 1 && k >= 2 && k <= m - 2) ? jac2_sum(cd, rC, Fm_w, Fm, Fp, Fp_w) : T(0);
+        if (!(t >= 1 && t <= h - 1 && k >= 2 && k <= m - 2)) return T(0);
+        return MIR ? jac2_sum(cd, rC, Fp_w, Fp, Fm, Fm_w) : jac2_sum(cd, rC, Fm_w, Fm, Fp, Fp_w);
     };
     auto fs = [&](int k) -> T { return f21(k, ld1(k), ld2((k - 1) >> 1), ld2((k + 1) >> 1)); };
     auto vs = [&](int k) -> T { return (k & 1) ? fs(k) : c21(k, ld1(k), fs(k - 1), fs(k + 1)); };
@@ -355,8 +364,8 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
     auto ldR = [&](int j, T& x, T& y) {
         x = y = 0;
         if (!colok || j < 1 || j > m - 1) return;
-        P2<T> v = (FINEST && NT) ? ld_pair_nt(rA + (size_t)j * w + 2 * t)
-                                 : *reinterpret_cast<const P2<T>*>(rA + (size_t)j * w + 2 * t);
+        const T* p = rA + (size_t)R(j) * w + 2 * t;
+        P2<T> v = (FINEST && NT) ? ld_pair_nt(p) : *reinterpret_cast<const P2<T>*>(p);
         x = c0 ? v.x : T(0);
         y = c1 ? v.y : T(0);
     };
@@ -379,7 +388,7 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
         if (jj > y1) return;
         ldR(jj, c.rx, c.ry);
         if (FINEST && useful && jj >= y0 && jj < y1 && (c0 || c1)) {
-            P2<double> v = *reinterpret_cast<const P2<double>*>(u + (size_t)jj * w + 2 * t);
+            P2<double> v = *reinterpret_cast<const P2<double>*>(u + (size_t)R(jj) * w + 2 * t);
             c.ux = v.x;
             c.uy = v.y;
         }
@@ -409,16 +418,18 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
         const T vw = q ? nb : d0;
         const T ve = q ? d0 : nb;
         const int aF = 2 * t + 1 - q;
-        const T Fj = (aF >= 1 && aF <= m - 1 && jj >= 1 && jj <= m - 1) ? jac2_sum(cc, rF, vw, dm, ve, dp) : T(0);
+        const T Fj = (aF >= 1 && aF <= m - 1 && jj >= 1 && jj <= m - 1)
+                         ? (MIR ? jac2_sum(cc, rF, vw, dp, ve, dm) : jac2_sum(cc, rF, vw, dm, ve, dp))
+                         : T(0);
         if (jj - 1 >= y0) {
             const int qq = (jj - 1) & 1;
             const T sb = qq ? __shfl_down(Fm1, 1) : __shfl_up(Fm1, 1);
             const T cw = qq ? Fm1 : sb;
             const T ce = qq ? sb : Fm1;
-            const T C = jac2_sum(cc, rCm1, cw, Fm2, ce, Fj);
+            const T C = MIR ? jac2_sum(cc, rCm1, cw, Fj, ce, Fm2) : jac2_sum(cc, rCm1, cw, Fm2, ce, Fj);
             const T vx = qq ? Fm1 : C;   // column 2t
             const T vy = qq ? C : Fm1;   // column 2t+1
-            const size_t o = (size_t)(jj - 1) * w + 2 * t;
+            const size_t o = (size_t)R(jj - 1) * w + 2 * t;
             if (useful) {
                 if constexpr (FINEST) {
                     if (c0 && c1) *reinterpret_cast<P2<double>*>(u + o) = P2<double>{uxm1 + (double)vx, uym1 + (double)vy};
@@ -448,7 +459,10 @@ __global__ void __launch_bounds__(kRowBlock) kb_finest_fused(int m, T cc, T cd, 
 {
     const Fin2<T> it = items[blockIdx.y];
     ITEM_GATE(ctls, it.prob);
-    fused_body<T, true, NT>(m, cc, cd, it.r0, it.r1, it.v2, nullptr, it.u, nwx, nwaves, rows);
+    const int wv = rows_wave_id(nwaves);
+    if (wv >= nwaves) return;
+    if ((wv / nwx) & 1) fused_body<T, true, NT, true>(m, cc, cd, it.r0, it.r1, it.v2, nullptr, it.u, wv, nwx, rows);
+    else fused_body<T, true, NT, false>(m, cc, cd, it.r0, it.r1, it.v2, nullptr, it.u, wv, nwx, rows);
 }
 
 // The Jacobi of an axis level L (side m, coefficient cc) with that of the
@@ -459,7 +473,10 @@ __global__ void __launch_bounds__(kRowBlock) kb_jac_pair(int m, T cc, T cd, cons
 {
     const JPair2<T> it = items[blockIdx.y];
     ITEM_GATE(ctls, it.prob);
-    fused_body<T, false, false>(m, cc, cd, it.rA, it.r1, it.v2, it.vA, nullptr, nwx, nwaves, rows);
+    const int wv = rows_wave_id(nwaves);
+    if (wv >= nwaves) return;
+    if ((wv / nwx) & 1) fused_body<T, false, false, true>(m, cc, cd, it.rA, it.r1, it.v2, it.vA, nullptr, wv, nwx, rows);
+    else fused_body<T, false, false, false>(m, cc, cd, it.rA, it.r1, it.v2, it.vA, nullptr, wv, nwx, rows);
 }
 
 // tiny finest grids: one thread per point (both half-sweeps recomputed)
