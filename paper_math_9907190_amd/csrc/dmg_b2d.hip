@@ -20,6 +20,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <map>
+
 namespace dmg {
 
 #define ITEM_GATE(ctls, prob) \
@@ -1512,6 +1514,38 @@ static inline int pick_rows(int ncols_units, int per_wave, int nrows, int target
     return r;
 }
 
+// Waves of `kern` (kRowBlock threads per block) the device holds at once,
+// from the compiled kernel's occupancy; cached per kernel and device.
+static int resident_waves(const void* kern)
+{
+    static std::map<std::pair<const void*, int>, int> cache;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    auto key = std::make_pair(kern, dev);
+    auto f = cache.find(key);
+    if (f != cache.end()) return f->second;
+    int blocks = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kern, kRowBlock, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        blocks = cus = 0;
+    const int w = blocks * cus * kWavesPerBlock;
+    cache[key] = w;
+    return w;
+}
+
+// Strip length for a single problem: the shortest whose waves all fit on the
+// device at once (more waves in flight, one round, no tail); pick_rows when
+// no length up to 2 kMaxRows fits or the count is unknown.
+static inline int fill_rows(const void* kern, int ncols_units, int per_wave, int nrows)
+{
+    const int cap = resident_waves(kern);
+    const int nwx = (ncols_units + per_wave - 1) / per_wave;
+    if (cap > 0)
+        for (int r = 4; r <= 2 * kMaxRows; r++)
+            if ((long)nwx * ((nrows + r - 1) / r) <= cap) return r;
+    return pick_rows(ncols_units, per_wave, nrows);
+}
+
 static inline void rows_grid(int ncols_units, int per_wave, int nrows, int rows, int& nwx, int& nwaves, int& nblocks)
 {
     nwx = (ncols_units + per_wave - 1) / per_wave;
@@ -1592,14 +1626,14 @@ void launch_b_finest(int n, T c, T c1, int fused, const Fin2<T>* items, int nite
     }
     int nwx, nw, nb;
     if (fused) {
-        int rows = pick_rows(n / 2 + 1, kFusePairs, n - 1);
-        rows_grid(n / 2 + 1, kFusePairs, n - 1, rows, nwx, nw, nb);
-        if (nt_hint(n))
-            launch_timed((kb_finest_fused<T, true>), dim3(nb, nitems), dim3(kRowBlock), s, n, c, c1, items, nwx,
-                         nw, rows, ctls);
-        else
-            launch_timed((kb_finest_fused<T, false>), dim3(nb, nitems), dim3(kRowBlock), s, n, c, c1, items, nwx,
-                         nw, rows, ctls);
+        auto go = [&](auto kern) {
+            const int rows = nitems == 1 ? fill_rows((const void*)kern, n / 2 + 1, kFusePairs, n - 1)
+                                         : pick_rows(n / 2 + 1, kFusePairs, n - 1);
+            rows_grid(n / 2 + 1, kFusePairs, n - 1, rows, nwx, nw, nb);
+            launch_timed(kern, dim3(nb, nitems), dim3(kRowBlock), s, n, c, c1, items, nwx, nw, rows, ctls);
+        };
+        if (nt_hint(n)) go(kb_finest_fused<T, true>);
+        else go(kb_finest_fused<T, false>);
         return;
     }
     int rows = pick_rows(n / 2 + 1, kPairsPerWave, n - 1);
