@@ -21,6 +21,7 @@
 #include <hip/hip_ext.h>
 
 #include <map>
+#include <mutex>
 
 namespace dmg {
 
@@ -1518,10 +1519,12 @@ static inline int pick_rows(int ncols_units, int per_wave, int nrows, int target
 // from the compiled kernel's occupancy; cached per kernel and device.
 static int resident_waves(const void* kern)
 {
+    static std::mutex mu;
     static std::map<std::pair<const void*, int>, int> cache;
     int dev = 0;
     (void)hipGetDevice(&dev);
     auto key = std::make_pair(kern, dev);
+    std::lock_guard<std::mutex> lock(mu);
     auto f = cache.find(key);
     if (f != cache.end()) return f->second;
     int blocks = 0, cus = 0;
