@@ -38,7 +38,9 @@ namespace dmg {
 // Lane t owns the column pair (2t, 2t+1); a diagonal value needs the lanes
 // beside it, and an FZ value the lanes beside those: lanes 1 .. 61 write r
 // and r1, lanes 2 .. 62 write r2.
-// NT: non-temporal f and r0 accesses.  At most 128 VGPRs (four waves per
+// NT: non-temporal f, r0 and r1 accesses (r1 is next read by the finest
+// kernel, after the whole cycle: kept out of the caches, it leaves them to
+// the level arrays in between).  At most 128 VGPRs (four waves per
 // SIMD keep enough loads in flight); the FP64 FZ variant needs a few more
 // and runs three waves rather than spill (measured faster than halving its
 // row chunk to stay at four).
@@ -137,7 +139,10 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
                 T rn = q ? r1j : r0j;
                 int a = 2 * t + q;
                 const T d1 = rs2_core(rc, rw, rs, re, rn);
-                if (useful && a >= 1 && a <= m - 1 && j - 1 < y1) rD[(size_t)(j - 1) * W + t] = d1;
+                if (useful && a >= 1 && a <= m - 1 && j - 1 < y1) {
+                    if (NT) __builtin_nontemporal_store(d1, rD + (size_t)(j - 1) * W + t);
+                    else rD[(size_t)(j - 1) * W + t] = d1;
+                }
                 if constexpr (FZ) {
                     // Eq. (Erest2b) at axis point (t, B) of the level below,
                     // B = (j-2)/2: diagonal rows 2B-1 (d3), 2B (d2), 2B+1 (d1)
@@ -348,7 +353,11 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
     const bool c0 = t >= 1 && 2 * t <= m - 1, c1 = t >= 0 && 2 * t + 1 <= m - 1;
     const size_t w = (size_t)(m + 1);
     auto ld2 = [&](int B) -> T { return (colok && B >= 0 && B <= h) ? v2[(size_t)RB(B) * W + t] : T(0); };
-    auto ld1 = [&](int k) -> T { return (colok && k >= 0 && k <= m) ? r1[(size_t)R(k) * W + t] : T(0); };
+    auto ld1 = [&](int k) -> T {
+        if (!(colok && k >= 0 && k <= m)) return T(0);
+        const T* p = r1 + (size_t)R(k) * W + t;
+        return (FINEST && NT) ? __builtin_nontemporal_load(p) : *p;
+    };
     // F point (2t+1, k), k odd, from v2 rows (k-1)/2 (vlo) and (k+1)/2 (vhi), as jac2_diagF
     auto f21 = [&](int k, T rF, T vlo, T vhi) -> T {
         const T vlo_e = __shfl_down(vlo, 1), vhi_e = __shfl_down(vhi, 1);
