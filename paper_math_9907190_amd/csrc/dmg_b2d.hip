@@ -1370,7 +1370,8 @@ __global__ void __launch_bounds__(kCoarseThreadsB) kb_coarse_net(CoarseLev<T> L,
 // max_cycles cycles.  A problem that stops decrements *nactive.
 template <typename T>
 __global__ void __launch_bounds__(256) kb_finalize(int kind, const Fin2<T>* __restrict__ items, int nparts,
-                                                   Ctl* __restrict__ ctls, int* __restrict__ nactive)
+                                                   Ctl* __restrict__ ctls, int* __restrict__ nactive,
+                                                   int* __restrict__ host_active)
 {
     const Fin2<T> it = items[blockIdx.x];
     Ctl* c = &ctls[it.prob];
@@ -1419,6 +1420,9 @@ __global__ void __launch_bounds__(256) kb_finalize(int kind, const Fin2<T>* __re
         c->cycles = k;
         atomicSub(nactive, 1);
     }
+    // a single problem's state straight into the host's pinned word (the
+    // host reads it after an event that follows this kernel)
+    if (host_active) *host_active = c->done ? 0 : 1;
 }
 
 __global__ void kb_ctl_reset(Ctl* ctls, int nprob, int mode, int max_cycles, double rtol, int* nactive, int net)
@@ -1445,9 +1449,11 @@ __global__ void kb_ctl_reset(Ctl* ctls, int nprob, int mode, int max_cycles, dou
 }
 
 template <typename T>
-void launch_b_finalize(int kind, const Fin2<T>* items, int nitems, int nparts, Ctl* ctls, int* nactive, hipStream_t s)
+void launch_b_finalize(int kind, const Fin2<T>* items, int nitems, int nparts, Ctl* ctls, int* nactive, hipStream_t s,
+                       int* host_active)
 {
-    hipLaunchKernelGGL(kb_finalize<T>, dim3(nitems), dim3(256), 0, s, kind, items, nparts, ctls, nactive);
+    hipLaunchKernelGGL(kb_finalize<T>, dim3(nitems), dim3(256), 0, s, kind, items, nparts, ctls, nactive,
+                       nitems == 1 ? host_active : nullptr);
 }
 
 void launch_b_ctl_reset(Ctl* ctls, int nprob, int mode, int max_cycles, double rtol, int* nactive, int net,
@@ -1781,7 +1787,7 @@ void launch_b_coarse_net(const LevInfo<T>* lev, const Coarse2B<T>* items, int ni
     template void launch_b_jacobi<T>(int, int, int, T, const Item2<T>*, int, const Ctl*, hipStream_t);         \
     template void launch_b_coarse<T>(const LevInfo<T>*, const Coarse2B<T>*, int, const T*, const Ctl*, hipStream_t, \
                                      int);                                                                    \
-    template void launch_b_finalize<T>(int, const Fin2<T>*, int, int, Ctl*, int*, hipStream_t);                \
+    template void launch_b_finalize<T>(int, const Fin2<T>*, int, int, Ctl*, int*, hipStream_t, int*);          \
     template void launch_b_level_get<T>(int, int, const T*, double*, hipStream_t);                           \
     template void launch_b_coarse_net<T>(const LevInfo<T>*, const Coarse2B<T>*, int, const T*, Ctl*, const bf16_t*, \
                                          hipStream_t, int);                                                     \

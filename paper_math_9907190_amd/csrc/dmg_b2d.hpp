@@ -111,9 +111,11 @@ void launch_b_coarse(const LevInfo<T>* lev, const Coarse2B<T>* items, int nitems
 // sum of f^2 over interior nodes per problem, into the problem's partials (b_resid_parts(n) of them)
 template <typename T>
 void launch_b_sumsq(int n, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s);
+// host_active (pinned host memory, single-item launches only): receives 1 while
+// the problem is active, 0 once it stopped
 template <typename T>
 void launch_b_finalize(int kind, const Fin2<T>* items, int nitems, int nparts, Ctl* ctls, int* nactive,
-                       hipStream_t s);
+                       hipStream_t s, int* host_active = nullptr);
 void launch_b_ctl_reset(Ctl* ctls, int nprob, int mode, int max_cycles, double rtol, int* nactive, int net,
                         hipStream_t s);
 // the coarse kernel with the learned correction at the cut level (wf: packed forward weights)

@@ -302,7 +302,8 @@ void enq_resid(Plan2& P, Ctl* ctls, int* nact)
             launch_b_resid<T>(n, fz ? 1 : 0, fin_items<T>(P, (int)c), P.cls_count[c], ctls, P.stream);
         }
         Timed t(&P.tm, MG_K_NORM, 8.0 * P.nparts[c] * P.cls_count[c]);
-        launch_b_finalize<T>(1, fin_items<T>(P, (int)c), P.cls_count[c], P.nparts[c], ctls, nact, P.stream);
+        launch_b_finalize<T>(1, fin_items<T>(P, (int)c), P.cls_count[c], P.nparts[c], ctls, nact, P.stream,
+                             P.nprob == 1 ? P.hact : nullptr);
     }
 }
 
@@ -569,18 +570,27 @@ int plan2_solve(Plan2& P, double* const* u, const double* const* f, double rtol,
     if (P.prec == MG_FP64) { enq_norm_f<double>(P, ctls, nact); enq_resid<double>(P, ctls, nact); }
     else { enq_norm_f<float>(P, ctls, nact); enq_resid<float>(P, ctls, nact); }
     if ((e = last_launch())) return e;
-    if (hipMemcpyAsync(&P.hact[0], nact, sizeof(int), hipMemcpyDeviceToHost, P.stream) != hipSuccess) return MG_ERR_HIP;
-    if (hipEventRecord(P.ev[0], P.stream) != hipSuccess) return MG_ERR_HIP;
+    // The active-problem count after evaluation it lands in host slot it & 1
+    // before event ev[it & 1]: copied, or for a single problem written by
+    // the finalize kernel itself into slot 0 (then the host may read the
+    // next evaluation's value; it never grows, and that evaluation is
+    // already queued, so stopping on it is right).
+    const bool direct = P.nprob == 1;
+    auto mark = [&](int it1) -> int {
+        const int k = it1 & 1;
+        if (!direct && hipMemcpyAsync(&P.hact[k], nact, sizeof(int), hipMemcpyDeviceToHost, P.stream) != hipSuccess)
+            return MG_ERR_HIP;
+        return hip_status(hipEventRecord(P.ev[k], P.stream));
+    };
+    if ((e = mark(0))) return e;
     for (int it = 0;; it++) {
         // launch iteration it+1 before looking at what iteration it left
         if (it < max_cycles) {
-            if ((e = run_iteration(P))) return e;
-            int k = (it + 1) & 1;
-            if (hipMemcpyAsync(&P.hact[k], nact, sizeof(int), hipMemcpyDeviceToHost, P.stream) != hipSuccess) return MG_ERR_HIP;
-            if (hipEventRecord(P.ev[k], P.stream) != hipSuccess) return MG_ERR_HIP;
+            if ((e = run_iteration(P)) || (e = mark(it + 1))) return e;
         }
         if (hipEventSynchronize(P.ev[it & 1]) != hipSuccess) return MG_ERR_HIP;
-        if (P.hact[it & 1] <= 0 || it >= max_cycles) break;
+        const int active = direct ? *(volatile int*)&P.hact[0] : P.hact[it & 1];
+        if (active <= 0 || it >= max_cycles) break;
     }
     if (hipStreamSynchronize(P.stream) != hipSuccess) return MG_ERR_HIP;
     // per-problem outcome: the first fields of each control block
