@@ -86,6 +86,14 @@ struct Ctl {
 // leading fields copied back to the host after a solve
 constexpr size_t kCtlHead = offsetof(Ctl, hist);
 
+// what a solve loop needs after each residual evaluation, written by the
+// finalize kernel into pinned host memory
+struct HostState {
+    int done;
+    int pad;
+    double last;
+};
+
 constexpr size_t kAlign = 256;
 __host__ __device__ inline size_t alignUp(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 

@@ -14,7 +14,8 @@ int residual_parts(int dim, int n);
 
 void launch_sumsq(int dim, int n, const double* a, double* partial, int nparts, const Ctl* ctl, hipStream_t s);
 // finalize: kind 0 -> ||f|| into ctl->fnorm; kind 1 -> relative residual of evaluation k
-void launch_finalize(int kind, const double* partial, int nparts, Ctl* ctl, hipStream_t s);
+// host (pinned, nullable): receives done and the relative residual after each kind-1 evaluation
+void launch_finalize(int kind, const double* partial, int nparts, Ctl* ctl, hipStream_t s, HostState* host = nullptr);
 void launch_ctl_reset(Ctl* ctl, int mode, int max_cycles, double rtol, hipStream_t s, int net = 0);
 
 }  // namespace dmg

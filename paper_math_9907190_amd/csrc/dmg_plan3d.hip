@@ -116,11 +116,11 @@ void enqueue_residual(Plan3& P, const double* u, const double* f, const Ctl* ctl
     else launch_residual<float>(3, P.n, u, f, at<float>(P, P.r0), part, P.nparts, ctl, P.stream);
 }
 
-void enqueue_finalize(Plan3& P, int kind, Ctl* ctl)
+void enqueue_finalize(Plan3& P, int kind, Ctl* ctl, HostState* host = nullptr)
 {
     const int np = kind == 0 ? P.nparts : P.nparts_res;
     Timed t(&P.tm, MG_K_NORM, 8.0 * np);
-    launch_finalize(kind, at<double>(P, P.partial), np, ctl, P.stream);
+    launch_finalize(kind, at<double>(P, P.partial), np, ctl, P.stream, host);
 }
 
 }  // namespace
@@ -195,7 +195,7 @@ int plan3_setup(Plan3& P, void* ws, size_t ws_bytes, hipStream_t stream)
     P.tm.stream = stream;
     if (hipGetDevice(&P.device) != hipSuccess) return MG_ERR_HIP;
     if (hipHostMalloc((void**)&P.hctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) return MG_ERR_HIP;
-    if (hipHostMalloc((void**)&P.hhead, 2 * kCtlHead, hipHostMallocDefault) != hipSuccess) return MG_ERR_HIP;
+    if (hipHostMalloc((void**)&P.hstate, sizeof(HostState), hipHostMallocDefault) != hipSuccess) return MG_ERR_HIP;
     for (int k = 0; k < 2; k++)
         if (hipEventCreateWithFlags(&P.ev[k], hipEventDisableTiming) != hipSuccess) return MG_ERR_HIP;
     P.evs = true;
@@ -211,7 +211,7 @@ void plan3_destroy(Plan3& P)
         for (int k = 0; k < 2; k++) (void)hipEventDestroy(P.ev[k]);
     }
     if (P.hctl) (void)hipHostFree(P.hctl);
-    if (P.hhead) (void)hipHostFree(P.hhead);
+    if (P.hstate) (void)hipHostFree(P.hstate);
 }
 
 int plan3_vcycle(Plan3& P, double* u, const double* f, double* relres)
@@ -246,25 +246,24 @@ int plan3_solve(Plan3& P, double* u, const double* f, double rtol, int max_cycle
     launch_sumsq(3, P.n, f, part, P.nparts, ctl, s);
     enqueue_finalize(P, 0, ctl);
     enqueue_residual(P, u, f, ctl);
-    enqueue_finalize(P, 1, ctl);
+    enqueue_finalize(P, 1, ctl, P.hstate);
     // The device decides after every residual evaluation (later launches of
-    // a finished solve return at once).  While the host waits for what
+    // a finished solve return at once) and its finalize kernel writes the
+    // decision into pinned host memory.  While the host waits for what
     // iteration it decided, iteration it+1 is already queued, so the GPU does
     // not wait for the host between cycles -- unless the residual trend says
     // iteration it is probably the last: then the host waits first, rather
-    // than queue a whole gated iteration that would only return.
+    // than queue a whole gated iteration that would only return.  (The host
+    // may see the next evaluation's state: done never reverts, and that
+    // evaluation is already queued, so stopping on it is right.)
     auto launch = [&](int it1) -> int {   // iteration it1: cycle, residual evaluation it1
         enqueue_cycle_any(P, u, ctl);
         enqueue_residual(P, u, f, ctl);
-        enqueue_finalize(P, 1, ctl);
+        enqueue_finalize(P, 1, ctl, P.hstate);
         int e = last_launch();
         if (e) return e;
-        const int k = it1 & 1;
-        if (hipMemcpyAsync(P.hhead + k * kCtlHead, ctl, kCtlHead, hipMemcpyDeviceToHost, s) != hipSuccess)
-            return MG_ERR_HIP;
-        return hip_status(hipEventRecord(P.ev[k], s));
+        return hip_status(hipEventRecord(P.ev[it1 & 1], s));
     };
-    if (hipMemcpyAsync(P.hhead, ctl, kCtlHead, hipMemcpyDeviceToHost, s) != hipSuccess) return MG_ERR_HIP;
     if (hipEventRecord(P.ev[0], s) != hipSuccess) return MG_ERR_HIP;
     double rr1 = -1, rr2 = -1;   // relative residuals of evaluations it-1, it-2
     for (int it = 0;; it++) {
@@ -276,7 +275,7 @@ int plan3_solve(Plan3& P, double* u, const double* f, double rtol, int max_cycle
             ahead = true;
         }
         if (hipEventSynchronize(P.ev[it & 1]) != hipSuccess) return MG_ERR_HIP;
-        const Ctl* h = reinterpret_cast<const Ctl*>(P.hhead + (it & 1) * kCtlHead);
+        const volatile HostState* h = P.hstate;
         if (h->done || it >= max_cycles) break;
         rr2 = rr1;
         rr1 = h->last;

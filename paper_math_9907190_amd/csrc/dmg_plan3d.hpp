@@ -27,7 +27,7 @@ struct Plan3 {
     hipStream_t stream = nullptr;
     int device = 0;
     Ctl* hctl = nullptr;
-    char* hhead = nullptr;    // pinned: the control block head after two consecutive iterations
+    HostState* hstate = nullptr;   // pinned: written by the finalize kernel of a solve
     hipEvent_t ev[2];
     bool evs = false;
     Timing tm;

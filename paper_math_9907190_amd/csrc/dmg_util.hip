@@ -121,7 +121,7 @@ void launch_sumsq(int dim, int n, const double* a, double* partial, int nparts, 
 // when it is not finite, when it grew three cycles in a row above the
 // starting value, or after max_cycles cycles.
 __global__ void __launch_bounds__(1024) k_finalize(int kind, const double* __restrict__ partial, int nparts,
-                                                   Ctl* ctl)
+                                                   Ctl* ctl, HostState* host)
 {
     if (ctl->done) return;
     __shared__ double red[1024];
@@ -165,11 +165,15 @@ __global__ void __launch_bounds__(1024) k_finalize(int kind, const double* __res
         }
     }
     if (ctl->done) ctl->cycles = k;
+    if (host) {   // pinned host memory, read by the host after an event that follows this kernel
+        host->last = rr;
+        host->done = ctl->done;
+    }
 }
 
-void launch_finalize(int kind, const double* partial, int nparts, Ctl* ctl, hipStream_t s)
+void launch_finalize(int kind, const double* partial, int nparts, Ctl* ctl, hipStream_t s, HostState* host)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, kind, partial, nparts, ctl);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1024), 0, s, kind, partial, nparts, ctl, host);
 }
 
 __global__ void k_ctl_reset(Ctl* ctl, int mode, int max_cycles, double rtol, int net)
