@@ -1,7 +1,8 @@
 """Batched 2D solves (one launch per aligned level for the whole batch).
 
 * every problem's batched result is bitwise equal to its single-problem
-  solve (same kernels and launch shapes; only the work item differs);
+  solve (batches run per-level launches where a single problem runs the
+  fused and paired ones; the arithmetic is the same, so are the bits);
 * FP64 batched solves match the CPU oracle (1e-12) with the same cycle count;
 * single-precision cycles with FP64 refinement reach 1e-10 on an uneven batch;
 * the hipGraph-captured iteration gives bitwise the same results as eager
@@ -143,3 +144,20 @@ def test_one_failing_problem_stops_alone(dmg):
     assert sts == [dmg.MG_OK, dmg.MG_ERR_NONFINITE, dmg.MG_OK]
     assert st == dmg.MG_ERR_NONFINITE
     assert rr[0] <= 1e-10 and rr[2] <= 1e-10
+
+
+def test_paired_levels_equal_per_level_bitwise(dmg):
+    """A 2049^2 problem alone runs the Jacobi and restriction pairs at levels
+    16 and 18; in a batch of two it runs every one of those levels per level.
+    The solves agree to the bit."""
+    ns = [2048, 64]
+    fs = problems(ns, seed=17)
+    B = dmg.BatchSolver(ns, precision=dmg.MG_FP64)
+    us = [dev(np.zeros_like(f)) for f in fs]
+    st, cyc, rr, sts = B.solve(us, [dev(f) for f in fs], rtol=1e-10, max_cycles=40)
+    assert st == dmg.MG_OK
+    S = dmg.Solver(2, 2048, p=(1.052,))
+    u1 = dev(np.zeros_like(fs[0]))
+    st1, c1, r1, h1 = S.solve(u1, dev(fs[0]), rtol=1e-10, max_cycles=40)
+    assert st1 == dmg.MG_OK and c1 == cyc[0] and r1 == rr[0]
+    assert torch.equal(u1, us[0])
