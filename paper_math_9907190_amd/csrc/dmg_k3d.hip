@@ -55,6 +55,89 @@ __global__ void __launch_bounds__(256) k3_rs_m2b(int m, const T* __restrict__ rE
     rB[idxG(mc, A, B, C)] = rs3_m2b(rE, rO, m, A, B, C);
 }
 
+// red (side m) -> magenta, plane-marching (sides >= 128).  A workgroup owns
+// 32 x 8 magenta half-index columns (A, B) and marches a chunk of fine
+// planes c: plane c holds corners (c even) or cube centres (c odd), and both
+// stencils read red planes c-1, c, c+1 only.  Each red plane is staged in
+// LDS once per chunk (the tile's slots plus a one-slot halo, rows 2B0-1 ..
+// 2B0+16), a ring of three planes; the next plane is loaded into registers
+// while the current one is computed.  Same terms in the same order as
+// rs3_r2mE / rs3_r2mO.
+constexpr int kRmTA = 32, kRmTB = 8, kRmThreads = kRmTA * kRmTB;
+constexpr int kRmS = kRmTA + 2, kRmH = 2 * kRmTB + 2, kRmN = kRmS * kRmH;
+constexpr int kRmP = (kRmN + kRmThreads - 1) / kRmThreads;   // staged red slots per thread
+
+template <typename T>
+__global__ void __launch_bounds__(kRmThreads) k3_r2m_planes(int m, const T* __restrict__ rR, T* __restrict__ rE,
+                                                             T* __restrict__ rO, int nta, int ntb, int zc,
+                                                             const Ctl* ctl)
+{
+    DMG_GATE(ctl);
+    __shared__ T Rp[3][kRmN];
+    const int h = m / 2;
+    const int bid = xcd_block();   // tiles of one die are neighbours
+    const int ta = bid % nta, tb = (bid / nta) % ntb, tz = bid / (nta * ntb);
+    const int A0 = ta * kRmTA, B0 = tb * kRmTB;
+    const int z0 = 1 + tz * zc, z1 = min(z0 + zc, m);   // output planes [z0, z1)
+    const int tid = threadIdx.x;
+    const int yb = 2 * B0 - 1, sb = A0 - 1;   // fine row and slot of staged element 0
+    // staged red value e of plane c (0 off the grid)
+    auto rload = [&](int c, int e) -> T {
+        if (e >= kRmN) return T(0);
+        const int b = yb + e / kRmS, sl = sb + e % kRmS;
+        const int a = 2 * sl + ((b + c) & 1);
+        if (sl < 0 || a > m || b < 0 || b > m || c < 0 || c > m) return T(0);
+        return rR[idxR(m, a, b, c)];
+    };
+    T nx[kRmP];
+#pragma unroll
+    for (int k = 0; k < kRmP; k++) {
+        const int e = tid + k * kRmThreads;
+        const T v0 = rload(z0 - 1, e), v1 = rload(z0, e);
+        if (e < kRmN) {
+            Rp[(z0 + 2) % 3][e] = v0;
+            Rp[z0 % 3][e] = v1;
+        }
+        nx[k] = rload(z0 + 1, e);
+    }
+    const int A = A0 + tid % kRmTA, B = B0 + tid / kRmTA;
+    for (int c = z0; c < z1; c++) {
+#pragma unroll
+        for (int k = 0; k < kRmP; k++) {   // red plane c+1
+            const int e = tid + k * kRmThreads;
+            if (e < kRmN) Rp[(c + 1) % 3][e] = nx[k];
+        }
+        if (c + 1 < z1) {
+#pragma unroll
+            for (int k = 0; k < kRmP; k++) nx[k] = rload(c + 2, tid + k * kRmThreads);
+        }
+        __syncthreads();
+        const T* Rm = Rp[(c + 2) % 3];   // plane c-1
+        const T* R0 = Rp[c % 3];
+        const T* Rq = Rp[(c + 1) % 3];   // plane c+1
+        // staged position of red point (a, b) of any plane
+        auto at = [&](int a, int b) { return (b - yb) * kRmS + ((a >> 1) - sb); };
+        if (c & 1) {   // cube centre (2A+1, 2B+1, c), Eq. (Ermagm)
+            const int a = 2 * A + 1, b = 2 * B + 1;
+            if (A < h && B < h)
+                rO[idxMO(m, a, b, c)] = (R0[at(a + 1, b)] + R0[at(a - 1, b)] + R0[at(a, b + 1)] + R0[at(a, b - 1)] +
+                                         Rq[at(a, b)] + Rm[at(a, b)]) * (T(1) / T(6));
+        } else {       // corner (2A, 2B, c), Eq. (Ermagc)
+            const int a = 2 * A, b = 2 * B;
+            if (A >= 1 && A < h && B >= 1 && B < h && c >= 2 && c <= m - 2)
+                rE[idxME(m, a, b, c)] =
+                    (12 * R0[at(a, b)] + R0[at(a + 1, b + 1)] + R0[at(a + 1, b - 1)] + R0[at(a - 1, b - 1)] +
+                     R0[at(a - 1, b + 1)] + Rq[at(a + 1, b)] + Rm[at(a + 1, b)] + Rm[at(a - 1, b)] + Rq[at(a - 1, b)] +
+                     Rq[at(a, b + 1)] + Rm[at(a, b + 1)] + Rm[at(a, b - 1)] + Rq[at(a, b - 1)]) * (T(1) / T(24));
+        }
+        __syncthreads();
+    }
+}
+
+// smaller red levels (too few tiles at 128), and single-precision levels
+// (half the bytes: the point kernel measured as fast), use one thread per point
+constexpr int kRmPlMinSide = 256;
+
 template <typename T>
 void launch_rs3(const Lev3<T>& F, const Lev3<T>& Cc, const Ctl* ctl, hipStream_t s)
 {
@@ -63,6 +146,13 @@ void launch_rs3(const Lev3<T>& F, const Lev3<T>& Cc, const Ctl* ctl, hipStream_t
         dim3 g((m / 2 + 1 + 255) / 256, m - 1, m - 1);
         hipLaunchKernelGGL(k3_rs_g2r<T>, g, dim3(256), 0, s, m, F.r, Cc.r, ctl);
     } else if (Cc.kind == 2) {
+        if (m >= kRmPlMinSide && sizeof(T) == 8) {
+            const int h = m / 2, nta = (h + kRmTA - 1) / kRmTA, ntb = (h + kRmTB - 1) / kRmTB, zc = 8;
+            const int ntz = (m - 1 + zc - 1) / zc;
+            hipLaunchKernelGGL(k3_r2m_planes<T>, dim3(nta * ntb * ntz), dim3(kRmThreads), 0, s, m, F.r, Cc.r, Cc.r2,
+                               nta, ntb, zc, ctl);
+            return;
+        }
         dim3 g((m / 2 + 255) / 256, m / 2, m / 2);
         hipLaunchKernelGGL(k3_rs_r2m<T>, g, dim3(256), 0, s, m, F.r, Cc.r, Cc.r2, ctl);
     } else {
