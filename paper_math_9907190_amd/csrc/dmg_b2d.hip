@@ -2,14 +2,19 @@
 // single launch per level serves a batch of independent problems.
 //
 // Large levels (side >= 512) use row-marching kernels: a wavefront owns a
-// band of columns and marches down a strip of rows holding a three-row
-// register window; on an axis grid each lane owns the column pair (2t, 2t+1)
+// band of columns and marches down a strip of rows holding a register window
+// of a few rows; on an axis grid each lane owns the column pair (2t, 2t+1)
 // (one point of each colour per row), so both half-sweeps of the red-black
 // Jacobi run in one launch, the value needed from the neighbouring pair
-// comes across lanes by shuffle, and lanes 0 and 63 are halo lanes so no
-// value crosses a wave.  Loads are double-buffered (rows_march) and pairs
-// move as one 16-byte access.  Small levels (latency-bound) use one thread
-// per point.  Levels of side <= 32 run in one workgroup per problem.
+// comes across lanes by shuffle, and the lanes at the band's edges are halo
+// lanes so no value crosses a wave.  Loads are double-buffered (rows_march)
+// and pairs move as one 16-byte access.  The finest residual also restricts
+// onto the next two levels, the finest Jacobi runs the diagonal level's
+// below it on the fly, and in single-problem plans the levels >= 16 restrict
+// and relax two at a time (kb_rs_pair, kb_jac_pair).  Levels of sides 64 ..
+// 256 of a single problem run in two tiled launches (kb_mid_down,
+// kb_mid_up); small levels otherwise use one thread per point, and levels of
+// side <= 32 run in one workgroup per problem (kb_coarse).
 //
 // Per point the arithmetic is the paper's: Eqs. (Erest2r), (Erest2b),
 // (Eajacr), (Eajacb) and the axis-grid Jacobi, terms in the printed order.
