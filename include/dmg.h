@@ -7,7 +7,7 @@
  *   2D (Section 2): grids alternate between axis-aligned and 45-degree
  *   rotated (spacings h, sqrt2 h, 2h, ...); restriction Eqs. (Erest2r),
  *   (Erest2b); red-black Jacobi prolongation with over-relaxation p,
- *   Eqs. (Eajacr), (Eajacb) (Section 2.5).
+ *   Eqs. (Eajacr), (Eajacb) (Section 2.4).
  *   3D (Section 3): cubic -> FCC -> BCC -> cubic of twice the spacing;
  *   restrictions Eqs. (Erred), (Ermagc), (Ermagm), (Erblu); Jacobi steps
  *   Eqs. (Emprolm)-(Egprolr) with parameters p_m, p_r1, p_r2, p_g.
@@ -69,7 +69,7 @@ int mg_workspace_bytes(int dim, int n, int precision, size_t *bytes);
 
 /* Build a plan.  p: over-relaxation parameters, np = 1 in 2D (p, Section
  * 2.5; the paper's tuned value is 1.052) and np = 4 in 3D (p_m, p_r1, p_r2,
- * p_g, Section 3.5; tuned 1.11, 1.42, 1.08, 0.99).  workspace: device
+ * p_g, Section 3.4; tuned 1.11, 1.42, 1.08, 0.99).  workspace: device
  * memory of at least mg_workspace_bytes bytes, 256-byte aligned, used only
  * by this plan until mg_destroy.  hip_stream: a hipStream_t or NULL.
  * Enqueues the zeroing of the workspace on the stream. */
@@ -109,7 +109,7 @@ int mg_level_info(int dim, int n, int depth, int *num_levels, int *side);
 
 /* Batched 2D solve.  nprob independent problems on the unit square, problem
  * i with n[i] intervals per side (a power of two, 2 .. 2^15), all with the
- * same over-relaxation p (Section 2.5).  The hierarchies are aligned from the
+ * same over-relaxation p (Section 2.4).  The hierarchies are aligned from the
  * coarsest grid, where every level of the same aligned index has the same
  * side whatever the problem's size, so one kernel launch per level serves the
  * whole batch; a converged problem's work returns at once.  One outer

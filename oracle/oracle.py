@@ -22,10 +22,14 @@ _lib = None
 
 OK, ERR_ARG, ERR_SIZE, ERR_ALLOC, ERR_NONFINITE, ERR_DIVERGED, ERR_NOT_CONVERGED = 0, -1, -2, -4, -6, -7, -8
 
-# over-relaxation parameters the paper tunes: 2D p (Section 2.5, Table tbl:2d);
-# 3D (p_m, p_r1, p_r2, p_g) (Section 3.5, Table tbl:3dopt)
+# over-relaxation parameters the paper tunes: 2D p (Section 2.4, Table tbl:2d);
+# 3D (p_m, p_r1, p_r2, p_g) (Section 3.4, Table tbl:3dopt)
 P2D_TUNED = (1.052,)
 P3D_TUNED = (1.11, 1.42, 1.08, 0.99)
+# tuned for the fourth-order residuals: 2D p = 1.20 (Section 2.4, Table
+# tbl:2d); 3D (Section 3.4, Table tbl:3dopt)
+P2D_H4 = (1.20,)
+P3D_H4 = (0.91, 0.80, 0.70, 1.77)
 
 
 def build(force=True):
@@ -55,9 +59,14 @@ def lib():
         L.orc_vcycle.argtypes = [i, i, dp, i, dp, dp]
         L.orc_vcycle_trace.argtypes = [i, i, dp, i, dp, dp, dp, dp]
         L.orc_solve.argtypes = [i, i, dp, i, dp, dp, d, i, ip, dp, dp]
+        L.orc_residual_ord.argtypes = [i, i, i, dp, dp, dp]
+        L.orc_relres_ord.argtypes = [i, i, i, dp, dp, dp]
+        L.orc_vcycle_ord_trace.argtypes = [i, i, dp, i, i, dp, dp, dp, dp]
+        L.orc_solve_ord.argtypes = [i, i, dp, i, i, dp, dp, d, i, ip, dp, dp]
         L.orc_step_restrict.argtypes = [i, i, i, dp, dp]
         L.orc_step_jacobi.argtypes = [i, i, i, dp, dp, dp, dp]
         for fn in ("orc_residual", "orc_relres", "orc_vcycle", "orc_vcycle_trace", "orc_solve",
+                   "orc_residual_ord", "orc_relres_ord", "orc_vcycle_ord_trace", "orc_solve_ord",
                    "orc_step_restrict", "orc_step_jacobi"):
             getattr(L, fn).restype = ctypes.c_int
         L.orc_net_forward.argtypes = [i, i, dp, dp, dp]
@@ -107,29 +116,32 @@ def level_sides(dim, n):
     return [n >> (d // dim) for d in range(D + 1)]
 
 
-def residual(u, f):
+def residual(u, f, order=2):
+    """Finest residual: order 2, f - Lap_h u (Eq. Evpois); order 4, Eq. Efos2 / Efos4."""
     dim, n = _dimn(u)
     r = np.zeros_like(u)
-    _chk(lib().orc_residual(dim, n, _ptr(u), _ptr(f), _ptr(r)), "orc_residual")
+    _chk(lib().orc_residual_ord(dim, n, order, _ptr(u), _ptr(f), _ptr(r)), "orc_residual_ord")
     return r
 
 
-def relres(u, f):
+def relres(u, f, order=2):
+    """||r(u)|| / ||r(0)|| over interior nodes for the residual of that order."""
     dim, n = _dimn(u)
     out = ctypes.c_double()
-    _chk(lib().orc_relres(dim, n, _ptr(u), _ptr(f), ctypes.byref(out)), "orc_relres")
+    _chk(lib().orc_relres_ord(dim, n, order, _ptr(u), _ptr(f), ctypes.byref(out)), "orc_relres_ord")
     return out.value
 
 
-def vcycle(u, f, p=None, prec=0):
+def vcycle(u, f, p=None, prec=0, order=2):
     """One V-cycle; returns the new u (the input is not modified)."""
     dim, n = _dimn(u)
     u = np.array(u, dtype=np.float64, order="C")
-    _chk(lib().orc_vcycle(dim, n, _ptr(_params(dim, p)), prec, _ptr(u), _ptr(f)), "orc_vcycle")
+    _chk(lib().orc_vcycle_ord_trace(dim, n, _ptr(_params(dim, p)), prec, order, _ptr(u), _ptr(f), None, None),
+         "orc_vcycle_ord_trace")
     return u
 
 
-def vcycle_trace(u, f, p=None, prec=0):
+def vcycle_trace(u, f, p=None, prec=0, order=2):
     """One V-cycle; returns (u_new, [r per level], [v per level])."""
     dim, n = _dimn(u)
     sides = level_sides(dim, n)
@@ -137,8 +149,8 @@ def vcycle_trace(u, f, p=None, prec=0):
     rt = np.zeros(sum(sizes))
     vt = np.zeros(sum(sizes))
     u = np.array(u, dtype=np.float64, order="C")
-    _chk(lib().orc_vcycle_trace(dim, n, _ptr(_params(dim, p)), prec, _ptr(u), _ptr(f), _ptr(rt), _ptr(vt)),
-         "orc_vcycle_trace")
+    _chk(lib().orc_vcycle_ord_trace(dim, n, _ptr(_params(dim, p)), prec, order, _ptr(u), _ptr(f), _ptr(rt),
+                                    _ptr(vt)), "orc_vcycle_ord_trace")
     rs, vs, off = [], [], 0
     for m, s in zip(sides, sizes):
         rs.append(rt[off:off + s].reshape((m + 1,) * dim))
@@ -147,18 +159,33 @@ def vcycle_trace(u, f, p=None, prec=0):
     return u, rs, vs
 
 
-def solve(u, f, p=None, prec=0, rtol=1e-10, max_cycles=50, check=True):
-    """Returns (u, cycles, relres, history, status)."""
+def solve(u, f, p=None, prec=0, rtol=1e-10, max_cycles=50, check=True, order=2):
+    """Returns (u, cycles, relres, history, status); relres of the given order."""
     dim, n = _dimn(u)
     u = np.array(u, dtype=np.float64, order="C")
     hist = np.zeros(max_cycles + 1)
     cyc = ctypes.c_int()
     rr = ctypes.c_double()
-    st = lib().orc_solve(dim, n, _ptr(_params(dim, p)), prec, _ptr(u), _ptr(f), rtol, max_cycles,
-                         ctypes.byref(cyc), ctypes.byref(rr), _ptr(hist))
+    st = lib().orc_solve_ord(dim, n, _ptr(_params(dim, p)), prec, order, _ptr(u), _ptr(f), rtol, max_cycles,
+                             ctypes.byref(cyc), ctypes.byref(rr), _ptr(hist))
     if check and st not in (OK, ERR_NOT_CONVERGED):
-        raise OracleError(st, "orc_solve")
+        raise OracleError(st, "orc_solve_ord")
     return u, cyc.value, rr.value, hist[:cyc.value + 1], st
+
+
+def solve_two_stage(u, f, p2=None, p4=None, prec=0, rtol1=1e-6, rtol=1e-10, max_cycles=50):
+    """Fourth-order solution in two stages (Sections 2.3 and 3.3): cycles on
+    the second-order residual until its relative residual is <= rtol1, then
+    cycles on the fourth-order residual (with the parameters tuned for it)
+    until that one's is <= rtol.  Returns (u, cycles1, cycles2, relres4)."""
+    dim, _ = _dimn(u)
+    if p2 is None:
+        p2 = P2D_TUNED if dim == 2 else P3D_TUNED
+    if p4 is None:
+        p4 = P2D_H4 if dim == 2 else P3D_H4
+    u, c1, _, _, _ = solve(u, f, p2, prec, rtol1, max_cycles, order=2)
+    u, c2, rr, _, _ = solve(u, f, p4, prec, rtol, max_cycles, order=4)
+    return u, c1, c2, rr
 
 
 def step_restrict(dim, kind, fine):

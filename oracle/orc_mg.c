@@ -14,9 +14,11 @@
  * Return codes match the GPU library's numbering so tests can compare them.
  *
  * Parity pins live in tests/: closed-form sine-mode symbols of every
- * restriction and Jacobi half-sweep, a dense direct solve as the fixed
- * point, point counts, grid symmetries, and the paper's tabulated
- * convergence factors (Tables tbl:2d, tbl:3d, tbl:3dopt).
+ * restriction and Jacobi half-sweep and of the fourth-order residuals, a
+ * dense direct solve as the fixed point, point counts, grid symmetries,
+ * polynomial exactness and the fourth-order convergence of the Mehrstellen
+ * schemes, and the paper's tabulated convergence factors (Tables tbl:2d,
+ * tbl:3d, tbl:3dopt).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -68,6 +70,52 @@ static void orc_residual_core(int dim, int n, const double *u, const double *f, 
     }
 }
 
+/* Fourth-order residual at interior nodes, 0 on the boundary: the compact
+ * "Mehrstellen" scheme of Section 2.3, Eq. (Efos2), in 2D (the right-hand
+ * side combination (8f + 4 neighbours)/12 minus the 9-point operator over
+ * 6h^2) and the 19-point scheme of Section 3.3, Eq. (Efos4), in 3D
+ * ((6f + 6 face neighbours)/12 minus the operator with weights -24 centre,
+ * 2 faces, 1 edges, over 6h^2).  Reads f on boundary nodes too: the
+ * right-hand side combination of a node next to the boundary includes them. */
+static void orc_residual4_core(int dim, int n, const double *u, const double *f, double *r)
+{
+    double h2 = (1.0 / n) * (1.0 / n);
+    size_t s = (size_t)n + 1;
+    if (dim == 2) {
+        memset(r, 0, s * s * sizeof(double));
+        for (int j = 1; j < n; j++)
+            for (int i = 1; i < n; i++) {
+                size_t c = (size_t)j * s + (size_t)i;
+                double rhs = (8 * f[c] + f[c + 1] + f[c + s] + f[c - 1] + f[c - s]) / 12;
+                double op = (-20 * u[c] + 4 * (u[c - s] + u[c + s] + u[c - 1] + u[c + 1])
+                             + u[c + 1 + s] + u[c - 1 + s] + u[c - 1 - s] + u[c + 1 - s]) / (6 * h2);
+                r[c] = rhs - op;
+            }
+    } else {
+        size_t s2 = s * s;
+        memset(r, 0, s2 * s * sizeof(double));
+        for (int k = 1; k < n; k++)
+            for (int j = 1; j < n; j++)
+                for (int i = 1; i < n; i++) {
+                    size_t c = (size_t)k * s2 + (size_t)j * s + (size_t)i;
+                    double rhs = (6 * f[c] + f[c + 1] + f[c + s] + f[c - 1] + f[c - s] + f[c + s2] + f[c - s2]) / 12;
+                    double op = (-24 * u[c]
+                                 + 2 * (u[c - s] + u[c + s] + u[c - 1] + u[c + 1] + u[c + s2] + u[c - s2])
+                                 + u[c + 1 + s] + u[c - 1 + s] + u[c - 1 - s] + u[c + 1 - s]
+                                 + u[c + s + s2] + u[c + s - s2] + u[c - s - s2] + u[c - s + s2]
+                                 + u[c + 1 + s2] + u[c - 1 + s2] + u[c - 1 - s2] + u[c + 1 - s2]) / (6 * h2);
+                    r[c] = rhs - op;
+                }
+    }
+}
+
+/* the finest residual of a cycle: order 2 (Eq. Evpois) or 4 (Eqs. Efos2 / Efos4) */
+static void orc_residual_ord_core(int dim, int n, int order, const double *u, const double *f, double *r)
+{
+    if (order == 4) orc_residual4_core(dim, n, u, f, r);
+    else orc_residual_core(dim, n, u, f, r);
+}
+
 /* sum of squares over interior nodes, natural order */
 static double orc_interior_sumsq(int dim, int n, const double *a)
 {
@@ -111,45 +159,76 @@ static int orc_check(int dim, int n)
     return ORC_OK;
 }
 
-int orc_residual(int dim, int n, const double *u, const double *f, double *r)
+int orc_residual_ord(int dim, int n, int order, const double *u, const double *f, double *r)
 {
     int e = orc_check(dim, n);
     if (e) return e;
-    if (!u || !f || !r) return ORC_ERR_ARG;
-    orc_residual_core(dim, n, u, f, r);
+    if (!u || !f || !r || (order != 2 && order != 4)) return ORC_ERR_ARG;
+    orc_residual_ord_core(dim, n, order, u, f, r);
     return ORC_OK;
 }
 
-/* ||f - Lap_h u||_2 / ||f||_2 over interior nodes (||r||_2 when f = 0). */
-int orc_relres(int dim, int n, const double *u, const double *f, double *out)
+int orc_residual(int dim, int n, const double *u, const double *f, double *r)
+{
+    return orc_residual_ord(dim, n, 2, u, f, r);
+}
+
+/* ||r(u)||_2 / ||r(0)||_2 over interior nodes (||r(u)||_2 when r(0) = 0):
+ * order 2, r = f - Lap_h u and r(0) = f; order 4, the residual of Eq. Efos2
+ * / Efos4, whose r(0) is the right-hand side combination of f. */
+int orc_relres_ord(int dim, int n, int order, const double *u, const double *f, double *out)
 {
     int e = orc_check(dim, n);
     if (e) return e;
-    double *r = (double *)malloc(orc_count(dim, n) * sizeof(double));
+    if (order != 2 && order != 4) return ORC_ERR_ARG;
+    size_t cnt = orc_count(dim, n);
+    double *r = (double *)malloc(cnt * sizeof(double));
     if (!r) return ORC_ERR_ALLOC;
-    orc_residual_core(dim, n, u, f, r);
+    orc_residual_ord_core(dim, n, order, u, f, r);
     double rn = sqrt(orc_interior_sumsq(dim, n, r));
-    double fn = sqrt(orc_interior_sumsq(dim, n, f));
+    double fn;
+    if (order == 2) {
+        fn = sqrt(orc_interior_sumsq(dim, n, f));
+    } else {
+        double *z = (double *)calloc(cnt, sizeof(double));
+        if (!z) { free(r); return ORC_ERR_ALLOC; }
+        orc_residual4_core(dim, n, z, f, r);
+        fn = sqrt(orc_interior_sumsq(dim, n, r));
+        free(z);
+    }
     free(r);
     *out = fn > 0 ? rn / fn : rn;
     return ORC_OK;
 }
 
+int orc_relres(int dim, int n, const double *u, const double *f, double *out)
+{
+    return orc_relres_ord(dim, n, 2, u, f, out);
+}
+
 /* prec 0: every level in double; prec 1: levels in single, the residual
- * and the update in double (iterative refinement). */
-int orc_vcycle_trace(int dim, int n, const double *p, int prec, double *u, const double *f,
-                     double *rtrace, double *vtrace)
+ * and the update in double (iterative refinement).  order: 2, or 4 for the
+ * fourth-order residual on the finest grid, the rest of the cycle unchanged
+ * (Sections 2.3 and 3.3). */
+int orc_vcycle_ord_trace(int dim, int n, const double *p, int prec, int order, double *u, const double *f,
+                         double *rtrace, double *vtrace)
 {
     int e = orc_check(dim, n);
     if (e) return e;
-    if (!p || !u || !f || (prec != 0 && prec != 1)) return ORC_ERR_ARG;
-    return prec == 0 ? vcycle(dim, n, p, u, f, rtrace, vtrace)
-                     : vcycle_f32(dim, n, p, u, f, rtrace, vtrace);
+    if (!p || !u || !f || (prec != 0 && prec != 1) || (order != 2 && order != 4)) return ORC_ERR_ARG;
+    return prec == 0 ? vcycle(dim, n, order, p, u, f, rtrace, vtrace)
+                     : vcycle_f32(dim, n, order, p, u, f, rtrace, vtrace);
+}
+
+int orc_vcycle_trace(int dim, int n, const double *p, int prec, double *u, const double *f,
+                     double *rtrace, double *vtrace)
+{
+    return orc_vcycle_ord_trace(dim, n, p, prec, 2, u, f, rtrace, vtrace);
 }
 
 int orc_vcycle(int dim, int n, const double *p, int prec, double *u, const double *f)
 {
-    return orc_vcycle_trace(dim, n, p, prec, u, f, NULL, NULL);
+    return orc_vcycle_ord_trace(dim, n, p, prec, 2, u, f, NULL, NULL);
 }
 
 /* Outer iteration u <- u + v (Section 1): check the relative residual
@@ -158,14 +237,14 @@ int orc_vcycle(int dim, int n, const double *p, int prec, double *u, const doubl
  * 0, 1, ... cycles.  A residual that grows for three cycles in a row and
  * exceeds the starting residual is reported as divergence (growth at the
  * rounding floor is not). */
-int orc_solve(int dim, int n, const double *p, int prec, double *u, const double *f,
-              double rtol, int max_cycles, int *cycles_out, double *relres_out, double *history)
+int orc_solve_ord(int dim, int n, const double *p, int prec, int order, double *u, const double *f,
+                  double rtol, int max_cycles, int *cycles_out, double *relres_out, double *history)
 {
     int e = orc_check(dim, n);
     if (e) return e;
-    if (!p || !u || !f || max_cycles < 0 || !(rtol >= 0)) return ORC_ERR_ARG;
+    if (!p || !u || !f || max_cycles < 0 || !(rtol >= 0) || (order != 2 && order != 4)) return ORC_ERR_ARG;
     double rr;
-    e = orc_relres(dim, n, u, f, &rr);
+    e = orc_relres_ord(dim, n, order, u, f, &rr);
     if (e) return e;
     if (history) history[0] = rr;
     int k = 0, grow = 0;
@@ -173,10 +252,10 @@ int orc_solve(int dim, int n, const double *p, int prec, double *u, const double
     int status = ORC_OK;
     while (!(rr <= rtol) && k < max_cycles) {
         if (!isfinite(rr)) { status = ORC_ERR_NONFINITE; break; }
-        e = orc_vcycle(dim, n, p, prec, u, f);
+        e = orc_vcycle_ord_trace(dim, n, p, prec, order, u, f, NULL, NULL);
         if (e) return e;
         k++;
-        e = orc_relres(dim, n, u, f, &rr);
+        e = orc_relres_ord(dim, n, order, u, f, &rr);
         if (e) return e;
         if (history) history[k] = rr;
         if (!isfinite(rr)) { status = ORC_ERR_NONFINITE; break; }
@@ -188,6 +267,12 @@ int orc_solve(int dim, int n, const double *p, int prec, double *u, const double
     if (cycles_out) *cycles_out = k;
     if (relres_out) *relres_out = rr;
     return status;
+}
+
+int orc_solve(int dim, int n, const double *p, int prec, double *u, const double *f,
+              double rtol, int max_cycles, int *cycles_out, double *relres_out, double *history)
+{
+    return orc_solve_ord(dim, n, p, prec, 2, u, f, rtol, max_cycles, cycles_out, relres_out, history);
 }
 
 /* Single steps, for the tests that pin each equation on its own.

@@ -66,7 +66,7 @@ static void SFX(rs2_diag_to_axis)(int m, const R *r, R *rc)
 }
 
 /* Jacobi prolongation onto an axis grid of side m (Section 2.2, "similarly
- * for a green grid"; over-relaxed form Section 2.5).  c = p*(sigma*h)^2.
+ * for a green grid"; over-relaxed form Section 2.4).  c = p*(sigma*h)^2.
  * First the points with (a+b) odd, which are not on the coarser diagonal
  * grid, from the four axis neighbours of vd (the coarser diagonal level,
  * same side m); then the points with (a+b) even from the new odd values. */
@@ -270,14 +270,15 @@ static void SFX(jac3_green)(int m, R c, const R *r, const R *vr, R *v)
 
 /* ------------------------------------------------------------ V-cycle */
 
-/* One V-cycle (Section 1, Eq. Evpois): r = f - Lap_h(u) on the finest grid,
+/* One V-cycle (Section 1, Eq. Evpois): r = f - Lap_h(u) on the finest grid
+ * (order 4: the fourth-order residual of Sections 2.3 / 3.3 instead),
  * restrict down to the coarsest grid (3x3 or 3x3x3, one interior node),
  * one Jacobi iteration on each grid going back up, the coarsest one starting
  * from zero, then u <- u + v.
  * p: 2D {p}; 3D {p_m, p_r1, p_r2, p_g}.
  * rtrace / vtrace (nullable): every level's residual and correction, in
  * depth order, each level as its full (m+1)^dim array, converted to double. */
-static int SFX(vcycle)(int dim, int n, const double *p, double *u, const double *f,
+static int SFX(vcycle)(int dim, int n, int order, const double *p, double *u, const double *f,
                        double *rtrace, double *vtrace)
 {
     int K = orc_log2(n);
@@ -297,12 +298,12 @@ static int SFX(vcycle)(int dim, int n, const double *p, double *u, const double 
         vl[d] = (R *)calloc(cnt, sizeof(R));
         if (!rl[d] || !vl[d]) { rc = ORC_ERR_ALLOC; goto done; }
     }
-    /* finest residual, computed in double (Eq. Evpois) */
+    /* finest residual, computed in double (Eq. Evpois; order 4: Eq. Efos2 / Efos4) */
     {
         size_t cnt = (dim == 2) ? (size_t)(n + 1) * (size_t)(n + 1) : SFX(vol3)(n);
         double *r0 = (double *)malloc(cnt * sizeof(double));
         if (!r0) { rc = ORC_ERR_ALLOC; goto done; }
-        orc_residual_core(dim, n, u, f, r0);
+        orc_residual_ord_core(dim, n, order, u, f, r0);
         for (size_t q = 0; q < cnt; q++) rl[0][q] = (R)r0[q];
         free(r0);
     }

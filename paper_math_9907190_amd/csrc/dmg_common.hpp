@@ -178,7 +178,7 @@ __device__ inline T jac2_diagC_stored(const T* __restrict__ rD, const T* vD, int
     return jac2_sum(cc, rD[c], vD[c - w - 1], vD[c - w], vD[c + w], vD[c + w - 1]);
 }
 
-// Axis-grid analogue ("similarly for a green grid", Section 2.5): point
+// Axis-grid analogue ("similarly for a green grid", Section 2.4): point
 // (a,b) with a+b odd from the diagonal grid vD of the same side.
 template <typename T>
 __device__ inline T jac2_axisF(const T* __restrict__ rA, const T* __restrict__ vD, int m, T cc, int a, int b)

@@ -289,8 +289,8 @@ def mg_coarse_export(plan, level, dst_ptr):
 
 # ------------------------------------------------------------ torch plumbing
 
-P2D_TUNED = (1.052,)                    # Section 2.5
-P3D_TUNED = (1.11, 1.42, 1.08, 0.99)    # Section 3.5, Table tbl:3dopt
+P2D_TUNED = (1.052,)                    # Section 2.4
+P3D_TUNED = (1.11, 1.42, 1.08, 0.99)    # Section 3.4, Table tbl:3dopt
 
 
 class Solver:
