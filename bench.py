@@ -12,7 +12,9 @@ cycle.  value = unknowns * cycles / second over the timed steps.  The same
 workload is also solved with the single-precision cycle plus FP64 refinement
 and with the learned coarse correction (network trained first, outside the
 timed region, on 10^4 cut-level pairs from 1025^2 plain solves); the time to
-1e-10 of each form is reported under "modes".
+1e-10 of each form is reported under "modes".  The fourth-order residual
+(Eq. Efos2) is timed on the same f, directly and in two stages, under
+"fourth_order4097".
 
 roofline: the dominant kernel's algorithmic bytes per launch (every element
 it must read or write, counted once) over its mean launch time, measured with
@@ -94,6 +96,49 @@ def timed_solves(S, f, steps, warmup, rtol, family, torch):
     if family is not None:
         S.timing(-1)
     return dt, cycles, kern, us[-1], hist
+
+
+def bench_fourth_order(dmg, f, dev, torch, args):
+    """Fourth-order solution of the main workload (Section 2.3, Eq. Efos2):
+    fourth-order cycles from u = 0 (p = 1.20, Section 2.4) against the
+    two-stage solve (second-order cycles with p = 1.052 to 1e-3, then
+    fourth-order cycles), each to a 1e-10 fourth-order relative residual,
+    FP64 and FP32-refined levels."""
+    n = f.shape[0] - 1
+    n1 = n + 1
+    out = {}
+    for pname, prec in (("fp64", dmg.MG_FP64), ("fp32_refined", dmg.MG_FP32_REFINED)):
+        S2 = dmg.Solver(2, n, precision=prec, p=(1.052,), device=dev)
+        S4 = dmg.Solver(2, n, precision=prec, p=(1.20,), device=dev, order=4)
+        for mode in ("direct", "two_stage"):
+            us = [torch.zeros((n1, n1), dtype=torch.float64, device=dev) for _ in range(args.steps + args.warmup)]
+
+            def one(u):
+                if mode == "direct":
+                    st, c2, rr, _ = S4.solve(u, f, rtol=args.rtol, max_cycles=60)
+                    c1 = 0
+                else:
+                    st, c1, c2, rr = dmg.solve_two_stage(S2, S4, u, f, rtol1=1e-3, rtol=args.rtol, max_cycles=60)
+                assert st == 0 and rr <= args.rtol, (st, c1, c2, rr)
+                return c1, c2
+
+            for k in range(args.warmup):
+                one(us[k])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(args.warmup, args.warmup + args.steps):
+                c1, c2 = one(us[k])
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / args.steps
+            out["%s_%s" % (pname, mode)] = {"ms_to_rtol": round(ms, 4), "cycles_order2": c1, "cycles_order4": c2}
+            log("  fourth order %s %s: %.3f ms per solve, %d + %d cycles" % (pname, mode, ms, c1, c2))
+        S2.close()
+        S4.close()
+        torch.cuda.empty_cache()
+    for pname in ("fp64", "fp32_refined"):
+        out[pname + "_two_stage"]["speedup_vs_direct"] = round(
+            out[pname + "_direct"]["ms_to_rtol"] / out[pname + "_two_stage"]["ms_to_rtol"], 3)
+    return out
 
 
 def bench_batched(dmg, workloads, dev, torch, args):
@@ -305,6 +350,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and 3D workloads")
     ap.add_argument("--no-learned", action="store_true", help="skip training and the learned modes")
     ap.add_argument("--cube-only", action="store_true", help="only the 3D 257^3 workload (for profiling)")
+    ap.add_argument("--fourth-only", action="store_true", help="only the fourth-order solves of the 2D workload")
     ap.add_argument("--batched-only", action="store_true", help="only the 512-problem batched workload")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (calibrates HBM byte counters) and exit")
@@ -340,6 +386,9 @@ def main():
     log("generating f (n=%d)" % n)
     f_host = workloads.square_modes_noise(n, seed=2)
     f = torch.from_numpy(f_host).to(dev)
+    if args.fourth_only:
+        print(json.dumps({"fourth_order%d" % (n + 1): bench_fourth_order(dmg, f, dev, torch, args)}), flush=True)
+        return
 
     w_net = net_info = None
     if not args.no_learned:
@@ -393,6 +442,8 @@ def main():
 
     extra = {}
     if not args.no_extra:
+        log("fourth-order residual: direct and two-stage solves")
+        extra["fourth_order%d" % (n + 1)] = bench_fourth_order(dmg, f, dev, torch, args)
         extra["batched512"] = bench_batched(dmg, workloads, dev, torch, args)
         if w_net is not None:
             extra["learned1025"] = bench_learned(dmg, learned, dev, torch, args, w_net, net_info)

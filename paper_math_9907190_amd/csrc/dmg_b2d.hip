@@ -49,9 +49,14 @@ namespace dmg {
 // SIMD keep enough loads in flight); the FP64 FZ variant needs a few more
 // and runs three waves rather than spill (measured faster than halving its
 // row chunk to stay at four).
+// M4: the fourth-order residual of Section 2.3, Eq. (Efos2): f holds the
+// right-hand side combination (8f + 4 neighbours)/12, made once per solve by
+// kb_rhs4, and inv_h2 is 1/(6h^2) for the 9-point operator; the extra
+// diagonal neighbours come from the rows already held, by lane shuffles
+// (its FZ variants run three waves per SIMD in both precisions).
 constexpr int kResidPairs = 61;
-template <typename T, int CH, bool NT, bool FZ>
-__global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(FZ && sizeof(T) == 8 ? 3 : 4))) kb_resid(int m, double inv_h2, const Fin2<T>* __restrict__ items,
+template <typename T, int CH, bool NT, bool FZ, bool M4>
+__global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(FZ && (sizeof(T) == 8 || M4) ? 3 : 4))) kb_resid(int m, double inv_h2, const Fin2<T>* __restrict__ items,
                                                       int nwx, int nwaves, int rows, const Ctl* __restrict__ ctls)
 {
     const Fin2<T> it = items[blockIdx.y];
@@ -118,8 +123,17 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
             bool rowin = j >= 1 && j <= m - 1;
             double uW = __shfl_up(uc1, 1);   // u(2t-1, j)
             double uE = __shfl_down(uc0, 1); // u(2t+2, j)
-            double x0 = c.fx[i] - (uW + um0 + uc1 + up0 - 4 * uc0) * inv_h2;
-            double x1 = c.fy[i] - (uc0 + um1 + uE + up1 - 4 * uc1) * inv_h2;
+            double x0, x1;
+            if constexpr (M4) {
+                // Eq. (Efos2): -20 centre, 4 x (S, N, W, E), then NE, NW, SW, SE
+                const double mW = __shfl_up(um1, 1), mE = __shfl_down(um0, 1);   // row j-1, columns 2t-1, 2t+2
+                const double pW = __shfl_up(up1, 1), pE = __shfl_down(up0, 1);   // row j+1
+                x0 = c.fx[i] - (-20 * uc0 + 4 * (um0 + up0 + uW + uc1) + up1 + pW + mW + um1) * inv_h2;
+                x1 = c.fy[i] - (-20 * uc1 + 4 * (um1 + up1 + uc0 + uE) + pE + up0 + um0 + mE) * inv_h2;
+            } else {
+                x0 = c.fx[i] - (uW + um0 + uc1 + up0 - 4 * uc0) * inv_h2;
+                x1 = c.fy[i] - (uc0 + um1 + uE + up1 - 4 * uc1) * inv_h2;
+            }
             T r0j = (rowin && c0) ? (T)x0 : T(0);
             T r1j = (rowin && c1) ? (T)x1 : T(0);
             if (j >= y0 && j < y1 && useful) {
@@ -178,9 +192,11 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
     if (threadIdx.x == 0) it.part[blockIdx.x] = sum;
 }
 
-// One-thread-per-point residual for tiny grids (side < 4: no diagonal level).
+// One-thread-per-point residual for tiny grids (side < 4: no diagonal level);
+// m4: the fourth-order residual as in kb_resid.
 template <typename T>
-__global__ void kb_resid_small(int n, double inv_h2, const Fin2<T>* __restrict__ items, const Ctl* __restrict__ ctls)
+__global__ void kb_resid_small(int n, double inv_h2, const Fin2<T>* __restrict__ items, const Ctl* __restrict__ ctls,
+                               int m4)
 {
     const Fin2<T> it = items[blockIdx.y];
     ITEM_GATE(ctls, it.prob);
@@ -189,13 +205,29 @@ __global__ void kb_resid_small(int n, double inv_h2, const Fin2<T>* __restrict__
     for (int q = threadIdx.x; q < (n - 1) * (n - 1); q += blockDim.x) {
         int a = q % (n - 1) + 1, b = q / (n - 1) + 1;
         size_t c = (size_t)b * s + a;
-        double lap = (it.u[c - 1] + it.u[c - s] + it.u[c + 1] + it.u[c + s] - 4 * it.u[c]) * inv_h2;
+        const double* u = it.u;
+        double lap = m4 ? (-20 * u[c] + 4 * (u[c - s] + u[c + s] + u[c - 1] + u[c + 1]) + u[c + 1 + s] +
+                           u[c - 1 + s] + u[c - 1 - s] + u[c + 1 - s]) * inv_h2
+                        : (u[c - 1] + u[c - s] + u[c + 1] + u[c + s] - 4 * u[c]) * inv_h2;
         double r = it.f[c] - lap;
         it.r0[c] = (T)r;
         acc += r * r;
     }
     double sum = rows_block_sum(acc);
     if (threadIdx.x == 0) it.part[0] = sum;
+}
+
+// The right-hand side combination of the fourth-order residual (Section 2.3,
+// Eq. Efos2): g = (8 f + f(E) + f(N) + f(W) + f(S)) / 12 at interior nodes,
+// made once per solve; reads f on boundary nodes too.  One thread per point,
+// x fastest.
+__global__ void kb_rhs4(int n, const double* __restrict__ f, double* __restrict__ g)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    const int b = blockIdx.y + 1;
+    if (a > n - 1) return;
+    const size_t s = (size_t)n + 1, c = (size_t)b * s + a;
+    g[c] = (8 * f[c] + f[c + 1] + f[c + s] + f[c - 1] + f[c - s]) / 12;
 }
 
 // sum of f^2 over interior nodes, per problem (same partial count as kb_resid)
@@ -1611,12 +1643,18 @@ static void launch_timed(K kern, dim3 g, dim3 b, hipStream_t s, Args... args)
     }
 }
 
-template <typename T>
-void launch_b_resid(int n, int fused, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s)
+void launch_b_rhs4(int n, const double* f, double* g, hipStream_t s)
 {
-    double inv_h2 = (double)n * (double)n;
+    hipLaunchKernelGGL(kb_rhs4, dim3((n - 1 + 255) / 256, n - 1), dim3(256), 0, s, n, f, g);
+}
+
+template <typename T>
+void launch_b_resid(int n, int fused, int order, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s)
+{
+    const bool m4 = order == 4;
+    double inv_h2 = m4 ? (double)n * (double)n / 6 : (double)n * (double)n;
     if (n < 4) {
-        launch_timed(kb_resid_small<T>, dim3(1, nitems), dim3(kRowBlock), s, n, inv_h2, items, ctls);
+        launch_timed(kb_resid_small<T>, dim3(1, nitems), dim3(kRowBlock), s, n, inv_h2, items, ctls, m4 ? 1 : 0);
         return;
     }
     int nwx, nw, nb;
@@ -1625,13 +1663,18 @@ void launch_b_resid(int n, int fused, const Fin2<T>* items, int nitems, const Ct
     rows_grid(n / 2 + 1, kResidPairs, n - 1, rows, nwx, nw, nb);
     auto go = [&](auto kern) { launch_timed(kern, dim3(nb, nitems), dim3(kRowBlock), s, n, inv_h2, items, nwx, nw, rows, ctls); };
     const bool nt = nt_hint(n);
-    if (fused && n >= 8) {
-        if (nt) go(kb_resid<T, kChunkResid, true, true>);
-        else go(kb_resid<T, kChunkResid, false, true>);
-    } else {
-        if (nt) go(kb_resid<T, kChunkResid, true, false>);
-        else go(kb_resid<T, kChunkResid, false, false>);
-    }
+    auto pick = [&](auto M) {
+        constexpr bool M4 = decltype(M)::value != 0;
+        if (fused && n >= 8) {
+            if (nt) go(kb_resid<T, kChunkResid, true, true, M4>);
+            else go(kb_resid<T, kChunkResid, false, true, M4>);
+        } else {
+            if (nt) go(kb_resid<T, kChunkResid, true, false, M4>);
+            else go(kb_resid<T, kChunkResid, false, false, M4>);
+        }
+    };
+    if (m4) pick(Int<1>{});
+    else pick(Int<0>{});
 }
 
 template <typename T>
@@ -1783,7 +1826,7 @@ void launch_b_coarse_net(const LevInfo<T>* lev, const Coarse2B<T>* items, int ni
 }
 
 #define DMG_INSTB(T)                                                                                            \
-    template void launch_b_resid<T>(int, int, const Fin2<T>*, int, const Ctl*, hipStream_t);                   \
+    template void launch_b_resid<T>(int, int, int, const Fin2<T>*, int, const Ctl*, hipStream_t);                   \
     template void launch_b_sumsq<T>(int, const Fin2<T>*, int, const Ctl*, hipStream_t);                        \
     template void launch_b_finest<T>(int, T, T, int, const Fin2<T>*, int, const Ctl*, hipStream_t);          \
     template void launch_b_restrict<T>(int, int, int, const Item2<T>*, int, const Ctl*, hipStream_t);          \

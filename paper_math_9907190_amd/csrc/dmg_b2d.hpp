@@ -77,7 +77,9 @@ struct LevInfo {
 
 // fused = 1: the kernel also restricts r1 onto the axis level below it (r2)
 template <typename T>
-void launch_b_resid(int n, int fused, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s);
+void launch_b_resid(int n, int fused, int order, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s);
+// order 4: f of the items is the right-hand side combination made by launch_b_rhs4
+void launch_b_rhs4(int n, const double* f, double* g, hipStream_t s);
 int b_resid_parts(int n);
 // fused = 1: the kernel also runs the Jacobi of the first diagonal level
 // (coefficient c1) from r1 and v2 instead of reading v1

@@ -53,7 +53,10 @@ bool rs_one(const Plan2& P, int lam, int D, int top)
 int plan2_layout(Plan2& P, int nprob, const int* n, int prec, double p)
 {
     if (nprob < 1 || !n) return MG_ERR_ARG;
+    P.rorder = (prec & MG_ORDER4) ? 4 : 2;
+    prec &= ~MG_ORDER4;
     if (prec != MG_FP64 && prec != MG_FP32_REFINED) return MG_ERR_ARG;
+    if (P.rorder == 4 && nprob != 1) return MG_ERR_ARG;
     P.nprob = nprob;
     P.prec = prec;
     P.p = p;
@@ -148,6 +151,7 @@ int plan2_layout(Plan2& P, int nprob, const int* n, int prec, double p)
             P.off_v[i][lam] = take(es * c);
         }
     }
+    if (P.rorder == 4) P.off_g = take(sizeof(double) * sizeA(n[0]));
     P.rows_rs.assign(P.Dmax + 1, 0);
     P.rows_jac.assign(P.Dmax + 1, 0);
     for (int lam = 0; lam <= P.Dmax; lam++) {
@@ -299,7 +303,7 @@ void enq_resid(Plan2& P, Ctl* ctls, int* nact)
             const int n = P.cls_n[c];
             const bool fz = fin_fused(2 * (ilog2(n) - 1), P.lamc);
             Timed t(&P.tm, MG_K_RESIDUAL, bytes_resid(n, es, fz) * P.cls_count[c], true);
-            launch_b_resid<T>(n, fz ? 1 : 0, fin_items<T>(P, (int)c), P.cls_count[c], ctls, P.stream);
+            launch_b_resid<T>(n, fz ? 1 : 0, P.rorder, fin_items<T>(P, (int)c), P.cls_count[c], ctls, P.stream);
         }
         Timed t(&P.tm, MG_K_NORM, 8.0 * P.nparts[c] * P.cls_count[c]);
         launch_b_finalize<T>(1, fin_items<T>(P, (int)c), P.cls_count[c], P.nparts[c], ctls, nact, P.stream,
@@ -466,14 +470,16 @@ int bind_uf(Plan2& P, double* const* u, const double* const* f)
     if (P.fin_valid && hipEventSynchronize(P.evu) != hipSuccess) return MG_ERR_HIP;
     for (int s = 0; s < P.nprob; s++) {
         int i = P.order[s];
+        // order 4: the kernels read the right-hand side combination made from f
+        const double* fi = P.rorder == 4 ? at<double>(P, P.off_g) : f[i];
         if (P.prec == MG_FP64) {
             Fin2<double>* hf = reinterpret_cast<Fin2<double>*>(P.hfin);
             hf[s].u = u[i];
-            hf[s].f = f[i];
+            hf[s].f = fi;
         } else {
             Fin2<float>* hf = reinterpret_cast<Fin2<float>*>(P.hfin);
             hf[s].u = u[i];
-            hf[s].f = f[i];
+            hf[s].f = fi;
         }
     }
     size_t bytes = (P.prec == MG_FP64 ? sizeof(Fin2<double>) : sizeof(Fin2<float>)) * (size_t)P.nprob;
@@ -536,6 +542,7 @@ int plan2_vcycle(Plan2& P, double* const* u, const double* const* f, double* rel
     int* nact = at<int>(P, P.off_nactive);
     int e = bind_uf(P, u, f);
     if (e) return e;
+    if (P.rorder == 4) launch_b_rhs4(P.n[0], f[0], at<double>(P, P.off_g), P.stream);
     launch_b_ctl_reset(ctls, P.nprob, 0, 0, 0.0, nact, P.has_net ? 1 : 0, P.stream);
     if (P.prec == MG_FP64) {
         if (relres) enq_norm_f<double>(P, ctls, nact);
@@ -566,6 +573,7 @@ int plan2_solve(Plan2& P, double* const* u, const double* const* f, double rtol,
     int* nact = at<int>(P, P.off_nactive);
     int e = bind_uf(P, u, f);
     if (e) return e;
+    if (P.rorder == 4) launch_b_rhs4(P.n[0], f[0], at<double>(P, P.off_g), P.stream);
     launch_b_ctl_reset(ctls, P.nprob, 1, max_cycles, rtol, nact, P.has_net ? 1 : 0, P.stream);
     if (P.prec == MG_FP64) { enq_norm_f<double>(P, ctls, nact); enq_resid<double>(P, ctls, nact); }
     else { enq_norm_f<float>(P, ctls, nact); enq_resid<float>(P, ctls, nact); }

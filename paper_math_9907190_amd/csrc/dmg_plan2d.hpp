@@ -8,6 +8,8 @@ namespace dmg {
 
 struct Plan2 {
     int nprob = 0, prec = 0;
+    int rorder = 2;           // finest residual: 2 (Eq. Evpois) or 4 (Eq. Efos2; single problem)
+    size_t off_g = 0;         // order 4: the right-hand side combination of f, (n+1)^2 doubles
     double p = 1.0;
     std::vector<int> n, D;    // per problem: intervals per side, finest depth (= its finest aligned level)
     int Dmax = 0, lamc = 0;   // highest aligned level; highest level run by the coarse kernel

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libdmg.so")
 MG_OK, MG_ERR_ARG, MG_ERR_SIZE, MG_ERR_WS, MG_ERR_ALLOC, MG_ERR_HIP = 0, -1, -2, -3, -4, -5
 MG_ERR_NONFINITE, MG_ERR_DIVERGED, MG_ERR_NOT_CONVERGED = -6, -7, -8
 MG_FP64, MG_FP32_REFINED = 0, 1
+MG_ORDER4 = 0x100   # OR-ed into the precision: fourth-order finest residual (2D, Eq. Efos2)
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libdmg.so is not built (%s); run __graft_entry__.build() or "
@@ -290,7 +291,9 @@ def mg_coarse_export(plan, level, dst_ptr):
 # ------------------------------------------------------------ torch plumbing
 
 P2D_TUNED = (1.052,)                    # Section 2.4
+P2D_H4 = (1.20,)                        # Section 2.4: tuned for the fourth-order residual
 P3D_TUNED = (1.11, 1.42, 1.08, 0.99)    # Section 3.4, Table tbl:3dopt
+P3D_H4 = (0.91, 0.80, 0.70, 1.77)       # Section 3.4, Table tbl:3dopt: tuned for the fourth-order residual
 
 
 class Solver:
@@ -299,10 +302,17 @@ class Solver:
     u, f: float64 CUDA tensors of shape (n+1,)*dim, contiguous (x fastest).
     """
 
-    def __init__(self, dim, n, precision=MG_FP64, p=None, device=None, stream=None):
+    def __init__(self, dim, n, precision=MG_FP64, p=None, device=None, stream=None, order=2):
+        if order not in (2, 4):
+            raise ValueError("order must be 2 or 4")
         if p is None:
-            p = P2D_TUNED if dim == 2 else P3D_TUNED
+            if order == 4:
+                p = P2D_H4 if dim == 2 else P3D_H4
+            else:
+                p = P2D_TUNED if dim == 2 else P3D_TUNED
         self.dim, self.n, self.precision, self.p = dim, n, precision, tuple(float(x) for x in p)
+        self.order = order
+        precision = precision | (MG_ORDER4 if order == 4 else 0)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.ws_bytes = mg_workspace_bytes(dim, n, precision)
         with torch.cuda.device(self.device):
@@ -373,6 +383,21 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+
+def solve_two_stage(first, second, u, f, rtol1=1e-4, rtol=1e-10, max_cycles=50):
+    """Fourth-order solution in two stages (Sections 2.3 and 3.3): `first`, a
+    second-order Solver, cycles until its relative residual is <= rtol1; then
+    `second`, an order-4 Solver of the same dim and n, cycles on the same u
+    until the fourth-order relative residual is <= rtol.
+    Returns (status, cycles of each stage, fourth-order relative residual)."""
+    if first.order != 2 or second.order != 4 or (first.dim, first.n) != (second.dim, second.n):
+        raise ValueError("two-stage solve needs an order-2 and an order-4 Solver of one size")
+    st1, c1, _, _ = first.solve(u, f, rtol=rtol1, max_cycles=max_cycles)
+    if st1 not in (MG_OK, MG_ERR_NOT_CONVERGED):
+        return st1, c1, 0, float("nan")
+    st, c2, rr, _ = second.solve(u, f, rtol=rtol, max_cycles=max_cycles)
+    return st, c1, c2, rr
 
 
 class BatchSolver:

@@ -1,0 +1,152 @@
+"""Parity of the fourth-order residual path (Section 2.3, Eq. Efos2; C ABI
+flag MG_ORDER4) with the oracle's order-4 cycle, solve and two-stage solve.
+
+Inputs carry nonzero boundary values of u and f: the scheme reads f on the
+boundary (the right-hand side combination of a node next to it) and u there
+(its operator's corner neighbours).  FP64 bar 1e-12 (max-norm, relative to
+the largest value of the compared array); single-precision levels 1e-5 of
+the largest value in the cycle, as for the second-order path.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_math_9907190_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+P4 = (1.20,)
+
+
+@pytest.fixture(scope="module")
+def dmg():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_math_9907190_amd import dmg as D
+    return D
+
+
+def relerr(a, b):
+    den = np.abs(b).max()
+    return np.abs(a - b).max() / (den if den > 0 else 1.0)
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def with_boundary(a, seed, scale):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    b = a.copy()
+    edge = np.ones_like(b, dtype=bool)
+    edge[1:-1, 1:-1] = False
+    b[edge] = scale * rng.uniform(-1, 1, edge.sum())
+    return b
+
+
+def case(n, seed):
+    u = with_boundary(W.uniform(2, n, seed), seed + 1, 0.5)
+    f = with_boundary(W.uniform(2, n, seed + 2), seed + 3, 1.0)
+    return u, f
+
+
+@pytest.mark.parametrize("n", [2, 4, 8, 16, 64, 128, 512, 1024])
+def test_one_cycle_order4_fp64(dmg, orc, n):
+    u, f = case(n, 50 + n)
+    uo, rs, vs = orc.vcycle_trace(u, f, P4, prec=0, order=4)
+    rel_o = orc.relres(u, f, order=4)
+    S = dmg.Solver(2, n, precision=dmg.MG_FP64, p=P4, order=4)
+    ud, fd = to_dev(u), to_dev(f)
+    print("order4 cycle n=%d" % n, flush=True)
+    rel_g = S.vcycle(ud, fd, want_relres=True)
+    torch.cuda.synchronize()
+    gr = [S.level(d, 0).cpu().numpy() for d in range(S.num_levels)]
+    gv = [S.level(d, 1).cpu().numpy() for d in range(1, S.num_levels)]
+    ug = ud.cpu().numpy()
+    assert relerr(gr[0], orc.residual(u, f, order=4)) <= TOL64
+    for d in range(len(rs)):
+        assert relerr(gr[d], rs[d]) <= TOL64, ("r", d)
+    for d in range(1, len(vs)):
+        assert relerr(gv[d - 1], vs[d]) <= TOL64, ("v", d)
+    assert relerr(ug - u, uo - u) <= TOL64
+    assert abs(rel_g - rel_o) <= 1e-12 * rel_o
+    edge = np.ones_like(u, dtype=bool)
+    edge[1:-1, 1:-1] = False
+    assert np.array_equal(ug[edge], u[edge])   # boundary values of u are never written
+    S.close()
+
+
+@pytest.mark.parametrize("n", [16, 512])
+def test_one_cycle_order4_fp32(dmg, orc, n):
+    u, f = case(n, 70 + n)
+    uo, rs, vs = orc.vcycle_trace(u, f, P4, prec=1, order=4)
+    S = dmg.Solver(2, n, precision=dmg.MG_FP32_REFINED, p=P4, order=4)
+    ud, fd = to_dev(u), to_dev(f)
+    print("order4 fp32 cycle n=%d" % n, flush=True)
+    S.vcycle(ud, fd)
+    torch.cuda.synchronize()
+    gr = [S.level(d, 0).cpu().numpy() for d in range(S.num_levels)]
+    rmax = max(np.abs(r).max() for r in rs)
+    for d in range(len(rs)):
+        assert np.abs(gr[d] - rs[d]).max() <= 1e-5 * rmax, ("r", d)
+    assert relerr(ud.cpu().numpy() - u, uo - u) <= 1e-5
+    S.close()
+
+
+@pytest.mark.parametrize("n,prec", [(64, 0), (512, 0), (512, 1)])
+def test_solve_order4_matches_oracle(dmg, orc, n, prec):
+    """Same bar as the second-order solve parity: FP64 same cycle count and u
+    to 1e-11; single-precision levels within one cycle and 1e-8."""
+    f = with_boundary(W.uniform(2, n, 90 + n), 91 + n, 1.0)
+    uo, co, ro, ho, so = orc.solve(np.zeros_like(f), f, P4, prec=prec, rtol=1e-10, max_cycles=60, order=4)
+    S = dmg.Solver(2, n, precision=prec, p=P4, order=4)
+    ud, fd = to_dev(np.zeros_like(f)), to_dev(f)
+    print("order4 solve n=%d prec=%d" % (n, prec), flush=True)
+    st, cyc, rr, hist = S.solve(ud, fd, rtol=1e-10, max_cycles=60)
+    ug = ud.cpu().numpy()
+    assert st == so == dmg.MG_OK and rr <= 1e-10
+    if prec == 0:
+        assert cyc == co
+        assert relerr(ug, uo) <= 1e-11
+        for g, o in zip(hist, ho):
+            assert abs(g - o) <= 1e-6 * o + 1e-14
+    else:
+        assert abs(cyc - co) <= 1
+        assert relerr(ug, uo) <= 1e-8
+    S.close()
+
+
+def test_two_stage_matches_oracle(dmg, orc):
+    """Second-order cycles to 1e-4, then fourth-order cycles to 1e-10, on
+    smooth data: the same stage lengths and solution as the oracle's."""
+    n = 256
+    f = W.square_modes_noise(n, seed=5, modes=8, kmax=8, noise=0.0)
+    uo, c1o, c2o, rro = orc.solve_two_stage(np.zeros_like(f), f, p2=(1.052,), p4=P4, rtol1=1e-4, rtol=1e-10)
+    S2 = dmg.Solver(2, n, p=(1.052,))
+    S4 = dmg.Solver(2, n, p=P4, order=4)
+    ud, fd = to_dev(np.zeros_like(f)), to_dev(f)
+    print("two-stage n=%d" % n, flush=True)
+    st, c1, c2, rr = dmg.solve_two_stage(S2, S4, ud, fd, rtol1=1e-4, rtol=1e-10)
+    assert st == dmg.MG_OK and rr <= 1e-10
+    assert (c1, c2) == (c1o, c2o)
+    assert relerr(ud.cpu().numpy(), uo) <= 1e-11
+    S2.close()
+    S4.close()
+
+
+def test_full_size_square_one_cycle_order4(dmg, orc):
+    """4097 x 4097, the benchmark's launch configuration (fused residual with
+    non-temporal accesses), one fourth-order cycle in FP64 and in single
+    precision, every element."""
+    n = 4096
+    f = W.square_modes_noise(n, seed=2)
+    for prec, tol in ((0, TOL64), (1, 1e-5)):
+        uo = orc.vcycle(np.zeros_like(f), f, P4, prec=prec, order=4)
+        S = dmg.Solver(2, n, precision=prec, p=P4, order=4)
+        ud, fd = to_dev(np.zeros_like(f)), to_dev(f)
+        print("order4 full size prec=%d" % prec, flush=True)
+        S.vcycle(ud, fd)
+        assert relerr(ud.cpu().numpy(), uo) <= tol, prec
+        S.close()
+        del ud, fd, S
+        torch.cuda.empty_cache()
