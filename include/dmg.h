@@ -62,19 +62,22 @@ enum {
                              (iterative refinement, u and f stay double) */
 };
 
-/* Flag OR-ed into `precision` of mg_workspace_bytes / mg_setup (2D; a batch
- * of one in mg_setup_batched): the finest residual is the fourth-order
- * compact ("Mehrstellen") scheme of Section 2.3, Eq. (Efos2),
- *   r = (8f + f_E + f_N + f_W + f_S)/12
- *       - (-20u + 4(u_S + u_N + u_W + u_E) + u_NE + u_NW + u_SW + u_SE)/(6h^2),
- * and the rest of the cycle is unchanged.  The right-hand side combination is
- * made once per mg_solve / mg_vcycle call into the workspace (which grows by
- * (n+1)^2 doubles); boundary entries of f are then read too.  The relative
- * residual becomes ||r(u)||_2 / ||r(0)||_2.  The paper tunes p = 1.20 for
- * this residual (Section 2.4); a fourth-order solution is reached fastest
- * after second-order cycles (two plans on the same u, Section 2.3).
- * Another precision value with this flag, 3D, or a batch of more than one
- * problem: MG_ERR_ARG. */
+/* Flag OR-ed into `precision` of mg_workspace_bytes / mg_setup (a batch of
+ * one in mg_setup_batched): the finest residual is the fourth-order compact
+ * ("Mehrstellen") scheme, and the rest of the cycle is unchanged.
+ *   2D, Section 2.3, Eq. (Efos2):
+ *     r = (8f + f_E + f_N + f_W + f_S)/12
+ *         - (-20u + 4(u_S + u_N + u_W + u_E) + u_NE + u_NW + u_SW + u_SE)/(6h^2);
+ *   3D, Section 3.3, Eq. (Efos4): r = (6f + the 6 face neighbours of f)/12
+ *     - (-24u + 2 (the 6 face neighbours) + the 12 edge neighbours)/(6h^2).
+ * The right-hand side combination is made once per mg_solve / mg_vcycle call
+ * into the workspace (which grows by (n+1)^dim doubles); boundary entries of
+ * f are then read too.  The relative residual becomes ||r(u)||_2 / ||r(0)||_2.
+ * The paper tunes p = 1.20 (2D, Section 2.4) and (p_m, p_r1, p_r2, p_g) =
+ * (0.91, 0.80, 0.70, 1.77) (3D, Section 3.4) for this residual; a
+ * fourth-order solution is reached fastest after second-order cycles (two
+ * plans on the same u, Sections 2.3 and 3.3).  Another precision value with
+ * this flag, or a batch of more than one problem: MG_ERR_ARG. */
 enum { MG_ORDER4 = 0x100 };
 
 typedef struct mg_plan mg_plan;

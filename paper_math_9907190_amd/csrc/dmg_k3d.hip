@@ -587,7 +587,7 @@ constexpr int kRsRW = kPlTX + 2, kRsRH = kPlTY + 2;   // residual region
 constexpr int kRsUS = (kRsUW * kRsUH + kPlThreads - 1) / kPlThreads;
 constexpr int kRsFS = (kRsRW * kRsRH + kPlThreads - 1) / kPlThreads;
 
-template <typename T>
+template <typename T, bool M4>
 __global__ void __launch_bounds__(kPlThreads) k3_resid_planes(int n, double inv_h2, const double* __restrict__ u,
                                                                const double* __restrict__ f, T* __restrict__ r0,
                                                                T* __restrict__ rR, double* __restrict__ partial,
@@ -668,7 +668,18 @@ __global__ void __launch_bounds__(kPlThreads) k3_resid_planes(int n, double inv_
             T rt = T(0);
             if (in) {
                 const int l = (ly + 1) * kRsUW + (lx + 1);
-                double lap = (U0[l + 1] + U0[l - 1] + U0[l + kRsUW] + U0[l - kRsUW] + Uq[l] + Um[l] - 6 * U0[l]) * inv_h2;
+                double lap;
+                if constexpr (M4) {
+                    // Eq. (Efos4): -24 centre, 2 x (6 faces), then the 12 edges
+                    // (xy, yz, xz planes); inv_h2 is 1/(6h^2), fc the
+                    // right-hand side combination
+                    const int W = kRsUW;
+                    lap = (-24 * U0[l] + 2 * (U0[l - W] + U0[l + W] + U0[l - 1] + U0[l + 1] + Uq[l] + Um[l]) +
+                           U0[l + 1 + W] + U0[l - 1 + W] + U0[l - 1 - W] + U0[l + 1 - W] + Uq[l + W] + Um[l + W] +
+                           Um[l - W] + Uq[l - W] + Uq[l + 1] + Uq[l - 1] + Um[l - 1] + Um[l + 1]) * inv_h2;
+                } else {
+                    lap = (U0[l + 1] + U0[l - 1] + U0[l + kRsUW] + U0[l - kRsUW] + Uq[l] + Um[l] - 6 * U0[l]) * inv_h2;
+                }
                 double r = fc[i] - lap;
                 rt = (T)r;
                 if (lx >= 1 && lx <= kPlTX && ly >= 1 && ly <= kPlTY && c >= z0 && c < z1) {
@@ -728,13 +739,33 @@ int resid3_fused_parts(int n)
 
 template <typename T>
 void launch_resid3_fused(int n, const double* u, const double* f, T* r0, T* rR, double* partial, const Ctl* ctl,
-                         hipStream_t s)
+                         hipStream_t s, int order)
 {
     int ntx, nty, zc, nb;
     resid3_grid(n, ntx, nty, zc, nb);
-    double inv_h2 = (double)n * (double)n;
-    hipLaunchKernelGGL(k3_resid_planes<T>, dim3(nb), dim3(kPlThreads), 0, s, n, inv_h2, u, f, r0, rR, partial, ntx,
-                       nty, zc, ctl);
+    if (order == 4)
+        hipLaunchKernelGGL((k3_resid_planes<T, true>), dim3(nb), dim3(kPlThreads), 0, s, n, (double)n * n / 6, u, f, r0,
+                           rR, partial, ntx, nty, zc, ctl);
+    else
+        hipLaunchKernelGGL((k3_resid_planes<T, false>), dim3(nb), dim3(kPlThreads), 0, s, n, (double)n * n, u, f, r0,
+                           rR, partial, ntx, nty, zc, ctl);
+}
+
+// The right-hand side combination of the fourth-order residual (Section
+// 3.3, Eq. Efos4): g = (6 f + the six face neighbours of f) / 12 at interior
+// nodes, made once per solve; reads f on boundary nodes too.
+__global__ void k3_rhs4(int n, const double* __restrict__ f, double* __restrict__ g)
+{
+    const int a = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    const int b = blockIdx.y + 1, c = blockIdx.z + 1;
+    if (a > n - 1) return;
+    const size_t s = (size_t)n + 1, s2 = s * s, q = (size_t)c * s2 + (size_t)b * s + a;
+    g[q] = (6 * f[q] + f[q + 1] + f[q + s] + f[q - 1] + f[q - s] + f[q + s2] + f[q - s2]) / 12;
+}
+
+void launch_rhs4_3d(int n, const double* f, double* g, hipStream_t s)
+{
+    hipLaunchKernelGGL(k3_rhs4, dim3((n - 1 + 255) / 256, n - 1, n - 1), dim3(256), 0, s, n, f, g);
 }
 
 // ---- magenta of side m, Eqs. (Emprolm), (Emprolb), in half indices (A,B,C):
@@ -1313,7 +1344,7 @@ void launch_level_get3(int kind, int m, const T* src, const T* src2, double* dst
     template void launch_coarse3<T>(const Coarse3<T>&, const Ctl*, hipStream_t);                          \
     template void launch_coarse3_net<T>(const Coarse3<T>&, Ctl*, const bf16_t*, hipStream_t);             \
     template void launch_level_get3<T>(int, int, const T*, const T*, double*, hipStream_t);              \
-    template void launch_resid3_fused<T>(int, const double*, const double*, T*, T*, double*, const Ctl*, hipStream_t);
+    template void launch_resid3_fused<T>(int, const double*, const double*, T*, T*, double*, const Ctl*, hipStream_t, int);
 DMG_INST3(double)
 DMG_INST3(float)
 

@@ -7,9 +7,11 @@ namespace dmg {
 
 // residual r = f - Lap_h u on the finest grid (5- or 7-point), written as T
 // into r0 (natural layout), per-block partial sums of r^2 (double) in partial.
+// order 4: f holds the right-hand side combination of the fourth-order scheme
+// (Eqs. Efos2 / Efos4) and the operator is the 9- / 19-point one.
 template <typename T>
 void launch_residual(int dim, int n, const double* u, const double* f, T* r0, double* partial, int nparts,
-                     const Ctl* ctl, hipStream_t s);
+                     const Ctl* ctl, hipStream_t s, int order = 2);
 int residual_parts(int dim, int n);
 
 void launch_sumsq(int dim, int n, const double* a, double* partial, int nparts, const Ctl* ctl, hipStream_t s);

@@ -172,8 +172,12 @@ void launch_level_get3(int kind, int m, const T* src, const T* src2, double* dst
 // residual of the finest green grid fused with Eq. (Erred) onto the red grid of
 // the same side (n >= 128); writes resid3_fused_parts(n) norm partials
 int resid3_fused_parts(int n);
+// (order 4: f is the right-hand side combination of Eq. Efos4 and the
+// operator the 19-point one)
 template <typename T>
 void launch_resid3_fused(int n, const double* u, const double* f, T* r0, T* rR, double* partial, const Ctl* ctl,
-                         hipStream_t s);
+                         hipStream_t s, int order = 2);
+// g = the right-hand side combination of the fourth-order residual (Eq. Efos4)
+void launch_rhs4_3d(int n, const double* f, double* g, hipStream_t s);
 
 }  // namespace dmg

@@ -107,13 +107,13 @@ void enqueue_residual(Plan3& P, const double* u, const double* f, const Ctl* ctl
     size_t es = dbl ? 8 : 4;
     if (P.fused_resid) {
         Timed t(&P.tm, MG_K_RESIDUAL, bytes_resid3(P.n, es) + es * (double)sizeR(P.n) / 2);
-        if (dbl) launch_resid3_fused<double>(P.n, u, f, at<double>(P, P.r0), at<double>(P, P.lev[1].r), part, ctl, P.stream);
-        else launch_resid3_fused<float>(P.n, u, f, at<float>(P, P.r0), at<float>(P, P.lev[1].r), part, ctl, P.stream);
+        if (dbl) launch_resid3_fused<double>(P.n, u, f, at<double>(P, P.r0), at<double>(P, P.lev[1].r), part, ctl, P.stream, P.rorder);
+        else launch_resid3_fused<float>(P.n, u, f, at<float>(P, P.r0), at<float>(P, P.lev[1].r), part, ctl, P.stream, P.rorder);
         return;
     }
     Timed t(&P.tm, MG_K_RESIDUAL, bytes_resid3(P.n, es));
-    if (dbl) launch_residual<double>(3, P.n, u, f, at<double>(P, P.r0), part, P.nparts, ctl, P.stream);
-    else launch_residual<float>(3, P.n, u, f, at<float>(P, P.r0), part, P.nparts, ctl, P.stream);
+    if (dbl) launch_residual<double>(3, P.n, u, f, at<double>(P, P.r0), part, P.nparts, ctl, P.stream, P.rorder);
+    else launch_residual<float>(3, P.n, u, f, at<float>(P, P.r0), part, P.nparts, ctl, P.stream, P.rorder);
 }
 
 void enqueue_finalize(Plan3& P, int kind, Ctl* ctl, HostState* host = nullptr)
@@ -129,6 +129,8 @@ int plan3_layout(Plan3& P, int n, int prec, const double* p)
 {
     int K = ilog2(n);
     if (K < 1 || K > 11) return MG_ERR_SIZE;
+    P.rorder = (prec & MG_ORDER4) ? 4 : 2;
+    prec &= ~MG_ORDER4;
     if (prec != MG_FP64 && prec != MG_FP32_REFINED) return MG_ERR_ARG;
     size_t es = prec == MG_FP64 ? sizeof(double) : sizeof(float);
     P.n = n;
@@ -149,6 +151,7 @@ int plan3_layout(Plan3& P, int n, int prec, const double* p)
     P.partial = take(sizeof(double) * (size_t)std::max(P.nparts, P.nparts_res));
     P.zero = take(sizeof(double) * 64);
     P.r0 = take(es * sizeG(n));
+    if (P.rorder == 4) P.g = take(sizeof(double) * sizeG(n));
     P.net = take(sizeof(bf16_t) * (size_t)NetGeo<3>::PACK);
     double h = 1.0 / n;
     for (int d = 0; d <= P.D; d++) {
@@ -218,6 +221,10 @@ int plan3_vcycle(Plan3& P, double* u, const double* f, double* relres)
 {
     Ctl* ctl = at<Ctl>(P, P.ctl);
     double* part = at<double>(P, P.partial);
+    if (P.rorder == 4) {   // the kernels read the right-hand side combination made from f
+        launch_rhs4_3d(P.n, f, at<double>(P, P.g), P.stream);
+        f = at<double>(P, P.g);
+    }
     launch_ctl_reset(ctl, 0, 0, 0.0, P.stream, P.has_net ? 1 : 0);
     if (relres) {
         launch_sumsq(3, P.n, f, part, P.nparts, ctl, P.stream);
@@ -242,6 +249,10 @@ int plan3_solve(Plan3& P, double* u, const double* f, double rtol, int max_cycle
     Ctl* ctl = at<Ctl>(P, P.ctl);
     double* part = at<double>(P, P.partial);
     hipStream_t s = P.stream;
+    if (P.rorder == 4) {
+        launch_rhs4_3d(P.n, f, at<double>(P, P.g), s);
+        f = at<double>(P, P.g);
+    }
     launch_ctl_reset(ctl, 1, max_cycles, rtol, s, P.has_net ? 1 : 0);
     launch_sumsq(3, P.n, f, part, P.nparts, ctl, s);
     enqueue_finalize(P, 0, ctl);

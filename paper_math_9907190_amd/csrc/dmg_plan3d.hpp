@@ -16,6 +16,8 @@ struct Level3 {
 
 struct Plan3 {
     int n = 0, prec = 0, D = 0, dc = 0;
+    int rorder = 2;           // finest residual: 2 (Eq. Evpois) or 4 (Eq. Efos4)
+    size_t g = 0;             // order 4: the right-hand side combination of f, (n+1)^3 doubles
     double p[4] = {1, 1, 1, 1};
     size_t ctl = 0, partial = 0, zero = 0, r0 = 0, net = 0, total = 0;
     bool has_net = false;   // learned coarse correction set (packed bf16 weights at net)

@@ -50,7 +50,7 @@ template <typename T>
 __global__ void __launch_bounds__(kRowThreads) k_residual(int dim, int n, double inv_h2,
                                                           const double* __restrict__ u,
                                                           const double* __restrict__ f, T* __restrict__ r0,
-                                                          double* __restrict__ partial, const Ctl* ctl)
+                                                          double* __restrict__ partial, const Ctl* ctl, int m4)
 {
     if (ctl && ctl->done) return;
     int a = blockIdx.x * blockDim.x + threadIdx.x + 1;
@@ -61,14 +61,20 @@ __global__ void __launch_bounds__(kRowThreads) k_residual(int dim, int n, double
         if (a >= n) continue;
         if (dim == 2) {
             size_t c = (size_t)(q + 1) * s + a;
-            double lap = (u[c - 1] + u[c - s] + u[c + 1] + u[c + s] - 4 * u[c]) * inv_h2;
+            double lap = m4 ? (-20 * u[c] + 4 * (u[c - s] + u[c + s] + u[c - 1] + u[c + 1]) + u[c + 1 + s] +
+                               u[c - 1 + s] + u[c - 1 - s] + u[c + 1 - s]) * inv_h2
+                            : (u[c - 1] + u[c - s] + u[c + 1] + u[c + s] - 4 * u[c]) * inv_h2;
             double r = f[c] - lap;
             r0[c] = (T)r;
             acc += r * r;
         } else {
             long b = q % (n - 1) + 1, cz = q / (n - 1) + 1;
             size_t c = (size_t)cz * s2 + (size_t)b * s + a;
-            double lap = (u[c + 1] + u[c - 1] + u[c + s] + u[c - s] + u[c + s2] + u[c - s2] - 6 * u[c]) * inv_h2;
+            double lap = m4 ? (-24 * u[c] + 2 * (u[c - s] + u[c + s] + u[c - 1] + u[c + 1] + u[c + s2] + u[c - s2]) +
+                               u[c + 1 + s] + u[c - 1 + s] + u[c - 1 - s] + u[c + 1 - s] + u[c + s + s2] +
+                               u[c + s - s2] + u[c - s - s2] + u[c - s + s2] + u[c + 1 + s2] + u[c - 1 + s2] +
+                               u[c - 1 - s2] + u[c + 1 - s2]) * inv_h2
+                            : (u[c + 1] + u[c - 1] + u[c + s] + u[c - s] + u[c + s2] + u[c - s2] - 6 * u[c]) * inv_h2;
             double r = f[c] - lap;
             r0[c] = (T)r;
             acc += r * r;
@@ -80,13 +86,14 @@ __global__ void __launch_bounds__(kRowThreads) k_residual(int dim, int n, double
 
 template <typename T>
 void launch_residual(int dim, int n, const double* u, const double* f, T* r0, double* partial, int nparts,
-                     const Ctl* ctl, hipStream_t s)
+                     const Ctl* ctl, hipStream_t s, int order)
 {
     dim3 g;
     row_grid(dim, n, g);
     (void)nparts;
-    double inv_h2 = (double)n * (double)n;
-    hipLaunchKernelGGL(k_residual<T>, g, dim3(kRowThreads), 0, s, dim, n, inv_h2, u, f, r0, partial, ctl);
+    const int m4 = order == 4 ? 1 : 0;
+    double inv_h2 = m4 ? (double)n * (double)n / 6 : (double)n * (double)n;
+    hipLaunchKernelGGL(k_residual<T>, g, dim3(kRowThreads), 0, s, dim, n, inv_h2, u, f, r0, partial, ctl, m4);
 }
 
 __global__ void __launch_bounds__(kRowThreads) k_sumsq(int dim, int n, const double* __restrict__ a_,
@@ -202,8 +209,8 @@ void launch_ctl_reset(Ctl* ctl, int mode, int max_cycles, double rtol, hipStream
 }
 
 template void launch_residual<double>(int, int, const double*, const double*, double*, double*, int, const Ctl*,
-                                      hipStream_t);
+                                      hipStream_t, int);
 template void launch_residual<float>(int, int, const double*, const double*, float*, double*, int, const Ctl*,
-                                     hipStream_t);
+                                     hipStream_t, int);
 
 }  // namespace dmg

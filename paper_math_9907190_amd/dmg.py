@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libdmg.so")
 MG_OK, MG_ERR_ARG, MG_ERR_SIZE, MG_ERR_WS, MG_ERR_ALLOC, MG_ERR_HIP = 0, -1, -2, -3, -4, -5
 MG_ERR_NONFINITE, MG_ERR_DIVERGED, MG_ERR_NOT_CONVERGED = -6, -7, -8
 MG_FP64, MG_FP32_REFINED = 0, 1
-MG_ORDER4 = 0x100   # OR-ed into the precision: fourth-order finest residual (2D, Eq. Efos2)
+MG_ORDER4 = 0x100   # OR-ed into the precision: fourth-order finest residual (Eqs. Efos2, Efos4)
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libdmg.so is not built (%s); run __graft_entry__.build() or "

@@ -50,15 +50,18 @@ def test_workspace_bytes(D):
 
 
 def test_order4_flag(D):
-    """The fourth-order flag adds one (n+1)^2 double array (the right-hand side
-    combination) to a 2D workspace; 3D and batches of several problems reject it."""
+    """The fourth-order flag adds one (n+1)^dim double array (the right-hand
+    side combination) to the workspace; batches of several problems reject it."""
     for n in (64, 4096):
         plain = D.mg_workspace_bytes(2, n, D.MG_FP64)
         o4 = D.mg_workspace_bytes(2, n, D.MG_FP64 | D.MG_ORDER4)
         assert 8 * (n + 1) ** 2 <= o4 - plain < 8 * (n + 1) ** 2 + 256
         assert D.mg_workspace_bytes(2, n, D.MG_FP32_REFINED | D.MG_ORDER4) > D.mg_workspace_bytes(2, n, D.MG_FP32_REFINED)
     out = ctypes.c_size_t()
-    assert D._lib.mg_workspace_bytes(3, 16, D.MG_ORDER4, ctypes.byref(out)) == D.MG_ERR_ARG
+    for n in (16, 256):
+        plain = D.mg_workspace_bytes(3, n, D.MG_FP64)
+        assert 8 * (n + 1) ** 3 <= D.mg_workspace_bytes(3, n, D.MG_FP64 | D.MG_ORDER4) - plain < 8 * (n + 1) ** 3 + 256
+    assert D._lib.mg_workspace_bytes(3, 16, 2 | D.MG_ORDER4, ctypes.byref(out)) == D.MG_ERR_ARG
     assert D._lib.mg_workspace_bytes(2, 16, 2 | D.MG_ORDER4, ctypes.byref(out)) == D.MG_ERR_ARG
     ns = (ctypes.c_int * 2)(64, 128)
     assert D._lib.mg_batch_workspace_bytes(2, ns, D.MG_ORDER4, ctypes.byref(out)) == D.MG_ERR_ARG

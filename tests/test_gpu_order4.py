@@ -1,5 +1,6 @@
-"""Parity of the fourth-order residual path (Section 2.3, Eq. Efos2; C ABI
-flag MG_ORDER4) with the oracle's order-4 cycle, solve and two-stage solve.
+"""Parity of the fourth-order residual path (Section 2.3 Eq. Efos2, Section
+3.3 Eq. Efos4; C ABI flag MG_ORDER4) with the oracle's order-4 cycle, solve
+and two-stage solve.
 
 Inputs carry nonzero boundary values of u and f: the scheme reads f on the
 boundary (the right-hand side combination of a node next to it) and u there
@@ -35,29 +36,42 @@ def to_dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
+P4_3D = (0.91, 0.80, 0.70, 1.77)
+
+
+def p4(dim):
+    return P4 if dim == 2 else P4_3D
+
+
+def edge_mask(shape):
+    edge = np.ones(shape, dtype=bool)
+    edge[(slice(1, -1),) * len(shape)] = False
+    return edge
+
+
 def with_boundary(a, seed, scale):
     rng = np.random.Generator(np.random.PCG64(seed))
     b = a.copy()
-    edge = np.ones_like(b, dtype=bool)
-    edge[1:-1, 1:-1] = False
+    edge = edge_mask(b.shape)
     b[edge] = scale * rng.uniform(-1, 1, edge.sum())
     return b
 
 
-def case(n, seed):
-    u = with_boundary(W.uniform(2, n, seed), seed + 1, 0.5)
-    f = with_boundary(W.uniform(2, n, seed + 2), seed + 3, 1.0)
+def case(n, seed, dim=2):
+    u = with_boundary(W.uniform(dim, n, seed), seed + 1, 0.5)
+    f = with_boundary(W.uniform(dim, n, seed + 2), seed + 3, 1.0)
     return u, f
 
 
-@pytest.mark.parametrize("n", [2, 4, 8, 16, 64, 128, 512, 1024])
-def test_one_cycle_order4_fp64(dmg, orc, n):
-    u, f = case(n, 50 + n)
-    uo, rs, vs = orc.vcycle_trace(u, f, P4, prec=0, order=4)
+@pytest.mark.parametrize("dim,n", [(2, 2), (2, 4), (2, 8), (2, 16), (2, 64), (2, 128), (2, 512), (2, 1024),
+                                   (3, 2), (3, 4), (3, 8), (3, 16), (3, 64), (3, 128)])
+def test_one_cycle_order4_fp64(dmg, orc, dim, n):
+    u, f = case(n, 50 + n, dim)
+    uo, rs, vs = orc.vcycle_trace(u, f, p4(dim), prec=0, order=4)
     rel_o = orc.relres(u, f, order=4)
-    S = dmg.Solver(2, n, precision=dmg.MG_FP64, p=P4, order=4)
+    S = dmg.Solver(dim, n, precision=dmg.MG_FP64, p=p4(dim), order=4)
     ud, fd = to_dev(u), to_dev(f)
-    print("order4 cycle n=%d" % n, flush=True)
+    print("order4 cycle dim=%d n=%d" % (dim, n), flush=True)
     rel_g = S.vcycle(ud, fd, want_relres=True)
     torch.cuda.synchronize()
     gr = [S.level(d, 0).cpu().numpy() for d in range(S.num_levels)]
@@ -70,19 +84,18 @@ def test_one_cycle_order4_fp64(dmg, orc, n):
         assert relerr(gv[d - 1], vs[d]) <= TOL64, ("v", d)
     assert relerr(ug - u, uo - u) <= TOL64
     assert abs(rel_g - rel_o) <= 1e-12 * rel_o
-    edge = np.ones_like(u, dtype=bool)
-    edge[1:-1, 1:-1] = False
+    edge = edge_mask(u.shape)
     assert np.array_equal(ug[edge], u[edge])   # boundary values of u are never written
     S.close()
 
 
-@pytest.mark.parametrize("n", [16, 512])
-def test_one_cycle_order4_fp32(dmg, orc, n):
-    u, f = case(n, 70 + n)
-    uo, rs, vs = orc.vcycle_trace(u, f, P4, prec=1, order=4)
-    S = dmg.Solver(2, n, precision=dmg.MG_FP32_REFINED, p=P4, order=4)
+@pytest.mark.parametrize("dim,n", [(2, 16), (2, 512), (3, 16), (3, 128)])
+def test_one_cycle_order4_fp32(dmg, orc, dim, n):
+    u, f = case(n, 70 + n, dim)
+    uo, rs, vs = orc.vcycle_trace(u, f, p4(dim), prec=1, order=4)
+    S = dmg.Solver(dim, n, precision=dmg.MG_FP32_REFINED, p=p4(dim), order=4)
     ud, fd = to_dev(u), to_dev(f)
-    print("order4 fp32 cycle n=%d" % n, flush=True)
+    print("order4 fp32 cycle dim=%d n=%d" % (dim, n), flush=True)
     S.vcycle(ud, fd)
     torch.cuda.synchronize()
     gr = [S.level(d, 0).cpu().numpy() for d in range(S.num_levels)]
@@ -93,15 +106,15 @@ def test_one_cycle_order4_fp32(dmg, orc, n):
     S.close()
 
 
-@pytest.mark.parametrize("n,prec", [(64, 0), (512, 0), (512, 1)])
-def test_solve_order4_matches_oracle(dmg, orc, n, prec):
+@pytest.mark.parametrize("dim,n,prec", [(2, 64, 0), (2, 512, 0), (2, 512, 1), (3, 16, 0), (3, 64, 0), (3, 64, 1)])
+def test_solve_order4_matches_oracle(dmg, orc, dim, n, prec):
     """Same bar as the second-order solve parity: FP64 same cycle count and u
     to 1e-11; single-precision levels within one cycle and 1e-8."""
-    f = with_boundary(W.uniform(2, n, 90 + n), 91 + n, 1.0)
-    uo, co, ro, ho, so = orc.solve(np.zeros_like(f), f, P4, prec=prec, rtol=1e-10, max_cycles=60, order=4)
-    S = dmg.Solver(2, n, precision=prec, p=P4, order=4)
+    f = with_boundary(W.uniform(dim, n, 90 + n), 91 + n, 1.0)
+    uo, co, ro, ho, so = orc.solve(np.zeros_like(f), f, p4(dim), prec=prec, rtol=1e-10, max_cycles=60, order=4)
+    S = dmg.Solver(dim, n, precision=prec, p=p4(dim), order=4)
     ud, fd = to_dev(np.zeros_like(f)), to_dev(f)
-    print("order4 solve n=%d prec=%d" % (n, prec), flush=True)
+    print("order4 solve dim=%d n=%d prec=%d" % (dim, n, prec), flush=True)
     st, cyc, rr, hist = S.solve(ud, fd, rtol=1e-10, max_cycles=60)
     ug = ud.cpu().numpy()
     assert st == so == dmg.MG_OK and rr <= 1e-10
@@ -145,6 +158,23 @@ def test_full_size_square_one_cycle_order4(dmg, orc):
         S = dmg.Solver(2, n, precision=prec, p=P4, order=4)
         ud, fd = to_dev(np.zeros_like(f)), to_dev(f)
         print("order4 full size prec=%d" % prec, flush=True)
+        S.vcycle(ud, fd)
+        assert relerr(ud.cpu().numpy(), uo) <= tol, prec
+        S.close()
+        del ud, fd, S
+        torch.cuda.empty_cache()
+
+
+def test_full_size_cube_one_cycle_order4(dmg, orc):
+    """257^3, the 3D launch configuration (plane-marching fused residual), one
+    fourth-order cycle in FP64 and in single precision, every element."""
+    n = 256
+    f = W.cube_uniform(n, seed=3)
+    for prec, tol in ((0, TOL64), (1, 1e-5)):
+        uo = orc.vcycle(np.zeros_like(f), f, P4_3D, prec=prec, order=4)
+        S = dmg.Solver(3, n, precision=prec, p=P4_3D, order=4)
+        ud, fd = to_dev(np.zeros_like(f)), to_dev(f)
+        print("order4 full size cube prec=%d" % prec, flush=True)
         S.vcycle(ud, fd)
         assert relerr(ud.cpu().numpy(), uo) <= tol, prec
         S.close()
