@@ -15,7 +15,9 @@ timed region, on 10^4 cut-level pairs from 1025^2 plain solves); the time to
 1e-10 of each form is reported under "modes".  The fourth-order residual
 (Eq. Efos2) is timed on the same f, directly and in two stages, under
 "fourth_order4097"; the 19-point one (Eq. Efos4) on the 257^3 cube under
-"fourth_order_cube257".
+"fourth_order_cube257".  The over-relaxation parameters re-tuned at 4097^2
+and 257^3 (Nelder-Mead on the GPU cycle's factor) and the solves with them
+are under "retuned4097" / "retuned_cube257".
 
 roofline: the dominant kernel's algorithmic bytes per launch (every element
 it must read or write, counted once) over its mean launch time, measured with
@@ -77,8 +79,7 @@ def measured_traffic(family):
 
 
 def timed_solves(S, f, steps, warmup, rtol, family, torch):
-    n1 = f.shape[0]
-    us = [torch.zeros((n1, n1), dtype=torch.float64, device=f.device) for _ in range(steps + warmup)]
+    us = [torch.zeros_like(f) for _ in range(steps + warmup)]
     for k in range(warmup):
         st, cyc, rr, hist = S.solve(us[k], f, rtol=rtol, max_cycles=60)
         assert st == 0, (st, cyc, rr)
@@ -139,6 +140,34 @@ def bench_fourth_order(dmg, f, dev, torch, args):
     for pname in ("fp64", "fp32_refined"):
         out[pname + "_two_stage"]["speedup_vs_direct"] = round(
             out[pname + "_direct"]["ms_to_rtol"] / out[pname + "_two_stage"]["ms_to_rtol"], 3)
+    return out
+
+
+def bench_retuned(dmg, f, dev, torch, args):
+    """Over-relaxation parameters re-tuned at this size (Nelder-Mead on the GPU
+    cycle's factor, Sections 2.4 / 3.4; the tuning is outside the timed
+    region and timed on its own), then FP64 solves to 1e-10 with the paper's
+    parameters and with the re-tuned ones."""
+    from paper_math_9907190_amd import tune
+
+    dim, n = f.dim(), f.shape[0] - 1
+    paper = dmg.P2D_TUNED if dim == 2 else dmg.P3D_TUNED
+    t0 = time.perf_counter()
+    p, fac, nfev = tune.tune_p(dim, n, p0=paper, device=dev, maxfev=40 if dim == 2 else 120)
+    tune_s = time.perf_counter() - t0
+    out = {"p": [round(x, 4) for x in p], "factor": round(fac, 5), "evaluations": nfev, "tune_s": round(tune_s, 2),
+           "paper_p": list(paper), "paper_factor": round(tune.gpu_factor(dim, n, paper, device=dev), 5)}
+    for name, pp in (("paper_p", paper), ("retuned_p", p)):
+        S = dmg.Solver(dim, n, precision=dmg.MG_FP64, p=pp, device=dev)
+        dt, cycles, _, _, hist = timed_solves(S, f, args.steps, args.warmup, args.rtol, None, torch)
+        out[name + "_fp64"] = {"ms_to_rtol": round(1e3 * dt / args.steps, 4), "cycles": cycles[-1],
+                               "final_rel_res": hist[-1]}
+        S.close()
+        torch.cuda.empty_cache()
+    out["speedup"] = round(out["paper_p_fp64"]["ms_to_rtol"] / out["retuned_p_fp64"]["ms_to_rtol"], 3)
+    log("  retuned p %s (factor %.4f vs %.4f, %d evaluations, %.1f s): %.3f ms (%d cycles) vs %.3f ms (%d cycles)"
+        % (out["p"], fac, out["paper_factor"], nfev, tune_s, out["retuned_p_fp64"]["ms_to_rtol"],
+           out["retuned_p_fp64"]["cycles"], out["paper_p_fp64"]["ms_to_rtol"], out["paper_p_fp64"]["cycles"]))
     return out
 
 
@@ -352,6 +381,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip training and the learned modes")
     ap.add_argument("--cube-only", action="store_true", help="only the 3D 257^3 workload (for profiling)")
     ap.add_argument("--fourth-only", action="store_true", help="only the fourth-order solves of the 2D workload")
+    ap.add_argument("--retune-only", action="store_true", help="only the re-tuned parameter solves")
     ap.add_argument("--batched-only", action="store_true", help="only the 512-problem batched workload")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (calibrates HBM byte counters) and exit")
@@ -387,6 +417,11 @@ def main():
     log("generating f (n=%d)" % n)
     f_host = workloads.square_modes_noise(n, seed=2)
     f = torch.from_numpy(f_host).to(dev)
+    if args.retune_only:
+        f3 = torch.from_numpy(workloads.cube_uniform(256, seed=3)).to(dev)
+        print(json.dumps({"retuned%d" % (n + 1): bench_retuned(dmg, f, dev, torch, args),
+                          "retuned_cube257": bench_retuned(dmg, f3, dev, torch, args)}), flush=True)
+        return
     if args.fourth_only:
         f3 = torch.from_numpy(workloads.cube_uniform(256, seed=3)).to(dev)
         print(json.dumps({"fourth_order%d" % (n + 1): bench_fourth_order(dmg, f, dev, torch, args),
@@ -456,6 +491,9 @@ def main():
         log("fourth-order residual in 3D: direct and two-stage solves")
         f3 = torch.from_numpy(workloads.cube_uniform(256, seed=3)).to(dev)
         extra["fourth_order_cube257"] = bench_fourth_order(dmg, f3, dev, torch, args)
+        log("over-relaxation re-tuned per size: 4097^2 and 257^3")
+        extra["retuned%d" % (n + 1)] = bench_retuned(dmg, f, dev, torch, args)
+        extra["retuned_cube257"] = bench_retuned(dmg, f3, dev, torch, args)
         del f3
 
     cpu = None
