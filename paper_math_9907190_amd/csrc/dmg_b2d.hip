@@ -237,13 +237,16 @@ __global__ void __launch_bounds__(kRowBlock) kb_sumsq(int n, const Fin2<T>* __re
 {
     const Fin2<T> it = items[blockIdx.y];
     ITEM_GATE(ctls, it.prob);
-    size_t s = (size_t)n + 1;
-    long tot = (long)(n - 1) * (n - 1);
+    const size_t s = (size_t)n + 1;
     double acc = 0;
-    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += (long)gridDim.x * blockDim.x) {
-        long a = q % (n - 1) + 1, b = q / (n - 1) + 1;
-        double x = it.f[(size_t)b * s + a];
-        acc += x * x;
+    // interior rows b = blockIdx.x + 1, + gridDim.x, ...; a row's columns
+    // across the block's threads (coalesced, no division per element)
+    for (int b = blockIdx.x + 1; b < n; b += gridDim.x) {
+        const double* __restrict__ row = it.f + (size_t)b * s;
+        for (int a = threadIdx.x + 1; a < n; a += blockDim.x) {
+            const double x = row[a];
+            acc += x * x;
+        }
     }
     double sum = rows_block_sum(acc);
     if (threadIdx.x == 0) it.part[blockIdx.x] = sum;
