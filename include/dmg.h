@@ -109,6 +109,19 @@ int mg_vcycle(mg_plan *plan, double *u, const double *f, double *rel_res_before)
 int mg_solve(mg_plan *plan, double *u, const double *f, double rtol, int max_cycles,
              int *cycles_out, double *rel_res_out, double *history);
 
+/* Fourth-order solution in two stages (Sections 2.3 and 3.3): mg_solve on
+ * `first` (a plan without MG_ORDER4) until its relative residual is <= rtol1,
+ * then mg_solve on `second` (the same dim and n, with MG_ORDER4) on the same u
+ * until the fourth-order relative residual is <= rtol; each stage at most
+ * max_cycles cycles.  cycles1, cycles2, rel_res_out (host, nullable): the
+ * cycles of each stage and the final fourth-order relative residual (the
+ * first stage's if it failed).  Returns the second stage's status, or the
+ * first stage's if that one failed with another code than
+ * MG_ERR_NOT_CONVERGED (the second stage then does not run).  Mismatched or
+ * batched plans: MG_ERR_ARG.  Synchronises both plans' streams. */
+int mg_solve_two_stage(mg_plan *first, mg_plan *second, double *u, const double *f, double rtol1, double rtol,
+                       int max_cycles, int *cycles1, int *cycles2, double *rel_res_out);
+
 /* Copy level `depth` of the last cycle into dst (device, (m+1)^dim doubles,
  * natural order, m = the level's side in units of its stride; points not on
  * the level and boundary points read 0).  which = 0: restricted residual

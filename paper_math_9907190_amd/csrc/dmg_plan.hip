@@ -185,6 +185,31 @@ int mg_solve(mg_plan* P, double* u, const double* f, double rtol, int max_cycles
     return plan2_solve(*P->p2, &u, &f, rtol, max_cycles, cycles_out, rel_res_out, nullptr, history);
 }
 
+int mg_solve_two_stage(mg_plan* first, mg_plan* second, double* u, const double* f, double rtol1, double rtol,
+                       int max_cycles, int* cycles1, int* cycles2, double* rel_res_out)
+{
+    if (!first || !second || first == second) return MG_ERR_ARG;
+    auto shape = [](const mg_plan* P, int& dim, int& n, int& order, int& nprob) {
+        dim = P->dim;
+        n = P->p3 ? P->p3->n : P->p2->n[0];
+        order = P->p3 ? P->p3->rorder : P->p2->rorder;
+        nprob = P->p3 ? 1 : P->p2->nprob;
+    };
+    int d1, n1, o1, b1, d2, n2, o2, b2;
+    shape(first, d1, n1, o1, b1);
+    shape(second, d2, n2, o2, b2);
+    if (d1 != d2 || n1 != n2 || o1 != 2 || o2 != 4 || b1 != 1 || b2 != 1) return MG_ERR_ARG;
+    int c1 = 0, c2 = 0;
+    double rr = 0;
+    int e = mg_solve(first, u, f, rtol1, max_cycles, &c1, &rr, nullptr);
+    if (e == MG_OK || e == MG_ERR_NOT_CONVERGED)   // mg_solve has synchronised the first plan's stream
+        e = mg_solve(second, u, f, rtol, max_cycles, &c2, &rr, nullptr);
+    if (cycles1) *cycles1 = c1;
+    if (cycles2) *cycles2 = c2;
+    if (rel_res_out) *rel_res_out = rr;
+    return e;
+}
+
 int mg_solve_batched(mg_plan* P, double* const* u, const double* const* f, double rtol, int max_cycles, int* cycles,
                      double* rel_res, int* status)
 {

@@ -30,6 +30,7 @@ _lib.mg_setup.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctype
                           _vp, _sz, _vp]
 _lib.mg_vcycle.argtypes = [_vp, _vp, _vp, _dp]
 _lib.mg_solve.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, _ip, _dp, _dp]
+_lib.mg_solve_two_stage.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, _ip, _ip, _dp]
 _lib.mg_level_get.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp]
 _lib.mg_level_info.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _ip]
 _lib.mg_destroy.argtypes = [_vp]
@@ -58,7 +59,7 @@ _lib.mg_net_stats.argtypes = [_vp, _ip, _ip, _dp, _dp]
 _lib.mg_coarse_export.argtypes = [_vp, ctypes.c_int, _vp]
 _lib.mg_strerror.argtypes = [ctypes.c_int]
 _lib.mg_strerror.restype = ctypes.c_char_p
-for _f in ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_level_get", "mg_level_info",
+for _f in ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_solve_two_stage", "mg_level_get", "mg_level_info",
            "mg_destroy", "mg_timing_enable", "mg_timing_read", "mg_batch_workspace_bytes", "mg_setup_batched",
            "mg_solve_batched", "mg_vcycle_batched", "mg_autotune", "mg_net_weight_count", "mg_net_workspace_bytes",
            "mg_net_create", "mg_net_set_weights", "mg_net_get_weights", "mg_net_init", "mg_net_forward",
@@ -66,7 +67,7 @@ for _f in ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_level_
            "mg_coarse_export"):
     getattr(_lib, _f).restype = ctypes.c_int
 
-EXPORTS = ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_level_get", "mg_level_info",
+EXPORTS = ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_solve_two_stage", "mg_level_get", "mg_level_info",
            "mg_destroy", "mg_strerror", "mg_timing_enable", "mg_timing_read", "mg_batch_workspace_bytes",
            "mg_setup_batched", "mg_solve_batched", "mg_vcycle_batched", "mg_autotune", "mg_net_weight_count",
            "mg_net_workspace_bytes", "mg_net_create", "mg_net_set_weights", "mg_net_get_weights", "mg_net_init",
@@ -393,11 +394,14 @@ def solve_two_stage(first, second, u, f, rtol1=1e-4, rtol=1e-10, max_cycles=50):
     Returns (status, cycles of each stage, fourth-order relative residual)."""
     if first.order != 2 or second.order != 4 or (first.dim, first.n) != (second.dim, second.n):
         raise ValueError("two-stage solve needs an order-2 and an order-4 Solver of one size")
-    st1, c1, _, _ = first.solve(u, f, rtol=rtol1, max_cycles=max_cycles)
-    if st1 not in (MG_OK, MG_ERR_NOT_CONVERGED):
-        return st1, c1, 0, float("nan")
-    st, c2, rr, _ = second.solve(u, f, rtol=rtol, max_cycles=max_cycles)
-    return st, c1, c2, rr
+    first._chk(u, "u")
+    first._chk(f, "f")
+    c1, c2, rr = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    st = _lib.mg_solve_two_stage(first.plan, second.plan, _vp(u.data_ptr()), _vp(f.data_ptr()), float(rtol1),
+                                 float(rtol), int(max_cycles), ctypes.byref(c1), ctypes.byref(c2), ctypes.byref(rr))
+    if st not in (MG_OK, MG_ERR_NOT_CONVERGED, MG_ERR_NONFINITE, MG_ERR_DIVERGED):
+        raise MGError(st, "mg_solve_two_stage")
+    return st, c1.value, c2.value, rr.value
 
 
 class BatchSolver:

@@ -88,6 +88,8 @@ def test_setup_argument_errors_before_any_gpu_call(D):
     assert D._lib.mg_setup(ctypes.byref(plan), 2, 64, 0, p1, 1, ctypes.c_void_p(4096), 16, None) == D.MG_ERR_WS
     assert D._lib.mg_setup(ctypes.byref(plan), 2, 64, 0, p1, 1, ctypes.c_void_p(4097), 1 << 30, None) == D.MG_ERR_WS
     assert D.mg_strerror(D.MG_ERR_WS).startswith("workspace")
+    # two-stage solve: null or identical plans
+    assert D._lib.mg_solve_two_stage(None, None, None, None, 1e-4, 1e-10, 10, None, None, None) == D.MG_ERR_ARG
 
 
 def test_net_sizes_and_argument_errors(D):
