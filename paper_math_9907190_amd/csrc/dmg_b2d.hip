@@ -54,9 +54,11 @@ namespace dmg {
 // kb_rhs4, and inv_h2 is 1/(6h^2) for the 9-point operator; the extra
 // diagonal neighbours come from the rows already held, by lane shuffles
 // (its FZ variants run three waves per SIMD in both precisions).
+// WF: the partial sums of f^2 over the same interior points too (the first
+// evaluation of a solve, so that ||f|| needs no pass of its own).
 constexpr int kResidPairs = 61;
-template <typename T, int CH, bool NT, bool FZ, bool M4>
-__global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(FZ && (sizeof(T) == 8 || M4) ? 3 : 4))) kb_resid(int m, double inv_h2, const Fin2<T>* __restrict__ items,
+template <typename T, int CH, bool NT, bool FZ, bool M4, bool WF>
+__global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu((FZ && (sizeof(T) == 8 || M4)) || WF ? 3 : 4))) kb_resid(int m, double inv_h2, const Fin2<T>* __restrict__ items,
                                                       int nwx, int nwaves, int rows, const Ctl* __restrict__ ctls)
 {
     const Fin2<T> it = items[blockIdx.y];
@@ -105,7 +107,7 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
             if (j <= ylast) { ldu(j + 2, c.ux[i], c.uy[i]); ldf(j, c.fx[i], c.fy[i]); }
         }
     };
-    double acc = 0;
+    double acc = 0, accf = 0;
     double um0, um1, uc0, uc1, up0, up1;  // u rows j-1, j, j+1 of the lane's pair
     ldu(y0 - 2, um0, um1);
     ldu(y0 - 1, uc0, uc1);
@@ -142,9 +144,18 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
                     if (NT) st_pair_nt(p, r0j, r1j);
                     else *reinterpret_cast<P2<T>*>(p) = P2<T>{r0j, r1j};
                     acc += x0 * x0 + x1 * x1;
+                    if constexpr (WF) accf += c.fx[i] * c.fx[i] + c.fy[i] * c.fy[i];
                 }
-                else if (c1) { p[1] = r1j; acc += x1 * x1; }
-                else if (c0) { p[0] = r0j; acc += x0 * x0; }
+                else if (c1) {
+                    p[1] = r1j;
+                    acc += x1 * x1;
+                    if constexpr (WF) accf += c.fy[i] * c.fy[i];
+                }
+                else if (c0) {
+                    p[0] = r0j;
+                    acc += x0 * x0;
+                    if constexpr (WF) accf += c.fx[i] * c.fx[i];
+                }
             }
             if (j - 1 >= y0) {
                 // Eq. Erest2r at the diagonal point of row j-1 (a + j-1 even)
@@ -190,6 +201,11 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
     rows_march<CH, Ck>(y0 - 1, ylast, load, proc);
     double sum = rows_block_sum(acc);
     if (threadIdx.x == 0) it.part[blockIdx.x] = sum;
+    if constexpr (WF) {
+        __syncthreads();   // the block sum's shared slots are reused
+        double sf = rows_block_sum(accf);
+        if (threadIdx.x == 0) it.partf[blockIdx.x] = sf;
+    }
 }
 
 // One-thread-per-point residual for tiny grids (side < 4: no diagonal level);
@@ -1417,16 +1433,27 @@ __global__ void __launch_bounds__(256) kb_finalize(int kind, const Fin2<T>* __re
     Ctl* c = &ctls[it.prob];
     if (c->done) return;
     __shared__ double red[256];
-    double s = 0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += it.part[i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    auto reduce = [&](const double* a) {
+        double s = 0;
+        for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += a[i];
+        red[threadIdx.x] = s;
         __syncthreads();
+        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        const double t = red[0];
+        __syncthreads();
+        return t;
+    };
+    // kind 2: ||f|| from the residual kernel's f^2 partials, then as kind 1
+    if (kind == 2) {
+        const double tf = reduce(it.partf);
+        if (threadIdx.x == 0) c->fnorm = sqrt(tf);
+        kind = 1;
     }
+    const double tot = reduce(it.part);
     if (threadIdx.x != 0) return;
-    double tot = red[0];
     if (kind == 0) {
         c->fnorm = sqrt(tot);
         return;
@@ -1652,7 +1679,8 @@ void launch_b_rhs4(int n, const double* f, double* g, hipStream_t s)
 }
 
 template <typename T>
-void launch_b_resid(int n, int fused, int order, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s)
+void launch_b_resid(int n, int fused, int order, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s,
+                    int withf)
 {
     const bool m4 = order == 4;
     double inv_h2 = m4 ? (double)n * (double)n / 6 : (double)n * (double)n;
@@ -1666,18 +1694,18 @@ void launch_b_resid(int n, int fused, int order, const Fin2<T>* items, int nitem
     rows_grid(n / 2 + 1, kResidPairs, n - 1, rows, nwx, nw, nb);
     auto go = [&](auto kern) { launch_timed(kern, dim3(nb, nitems), dim3(kRowBlock), s, n, inv_h2, items, nwx, nw, rows, ctls); };
     const bool nt = nt_hint(n);
-    auto pick = [&](auto M) {
-        constexpr bool M4 = decltype(M)::value != 0;
+    auto pick = [&](auto M, auto F) {
+        constexpr bool M4 = decltype(M)::value != 0, WF = decltype(F)::value != 0;
         if (fused && n >= 8) {
-            if (nt) go(kb_resid<T, kChunkResid, true, true, M4>);
-            else go(kb_resid<T, kChunkResid, false, true, M4>);
+            if (nt) go(kb_resid<T, kChunkResid, true, true, M4, WF>);
+            else go(kb_resid<T, kChunkResid, false, true, M4, WF>);
         } else {
-            if (nt) go(kb_resid<T, kChunkResid, true, false, M4>);
-            else go(kb_resid<T, kChunkResid, false, false, M4>);
+            if (nt) go(kb_resid<T, kChunkResid, true, false, M4, WF>);
+            else go(kb_resid<T, kChunkResid, false, false, M4, WF>);
         }
     };
-    if (m4) pick(Int<1>{});
-    else pick(Int<0>{});
+    if (m4) { if (withf) pick(Int<1>{}, Int<1>{}); else pick(Int<1>{}, Int<0>{}); }
+    else { if (withf) pick(Int<0>{}, Int<1>{}); else pick(Int<0>{}, Int<0>{}); }
 }
 
 template <typename T>
@@ -1829,7 +1857,7 @@ void launch_b_coarse_net(const LevInfo<T>* lev, const Coarse2B<T>* items, int ni
 }
 
 #define DMG_INSTB(T)                                                                                            \
-    template void launch_b_resid<T>(int, int, int, const Fin2<T>*, int, const Ctl*, hipStream_t);                   \
+    template void launch_b_resid<T>(int, int, int, const Fin2<T>*, int, const Ctl*, hipStream_t, int);                   \
     template void launch_b_sumsq<T>(int, const Fin2<T>*, int, const Ctl*, hipStream_t);                        \
     template void launch_b_finest<T>(int, T, T, int, const Fin2<T>*, int, const Ctl*, hipStream_t);          \
     template void launch_b_restrict<T>(int, int, int, const Item2<T>*, int, const Ctl*, hipStream_t);          \

@@ -53,6 +53,7 @@ struct Fin2 {
     const T* v2;   // correction of the level below it (read when the finest kernel runs its Jacobi)
     T* r2;         // residual of that level (written by the residual kernel when fused)
     double* part;  // norm partial sums of this problem
+    double* partf; // partial sums of f^2 (first evaluation of a solve, made by the residual kernel)
     int prob;
     int pad;
 };
@@ -77,7 +78,9 @@ struct LevInfo {
 
 // fused = 1: the kernel also restricts r1 onto the axis level below it (r2)
 template <typename T>
-void launch_b_resid(int n, int fused, int order, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s);
+// withf: also the partial sums of f^2 (into partf), for finalize kind 2
+void launch_b_resid(int n, int fused, int order, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s,
+                    int withf = 0);
 // order 4: f of the items is the right-hand side combination made by launch_b_rhs4
 void launch_b_rhs4(int n, const double* f, double* g, hipStream_t s);
 int b_resid_parts(int n);

@@ -133,6 +133,7 @@ int plan2_layout(Plan2& P, int nprob, const int* n, int prec, double p)
         if (P.D[i] >= 1) P.n_coarse_items++;
     P.off_r0.resize(nprob);
     P.off_part.resize(nprob);
+    P.off_partf.resize(nprob);
     P.off_r.assign(nprob, {});
     P.off_v.assign(nprob, {});
     for (int s = 0; s < nprob; s++) {
@@ -142,6 +143,7 @@ int plan2_layout(Plan2& P, int nprob, const int* n, int prec, double p)
         P.off_r0[i] = take(es * cnt);
         int cls = (int)(std::lower_bound(P.cls_n.begin(), P.cls_n.end(), m) - P.cls_n.begin());
         P.off_part[i] = take(sizeof(double) * (size_t)P.nparts[cls]);
+        P.off_partf[i] = take(sizeof(double) * (size_t)P.nparts[cls]);
         P.off_r[i].assign(std::max(P.D[i], 1), 0);
         P.off_v[i].assign(std::max(P.D[i], 1), 0);
         for (int lam = P.D[i] - 1; lam >= 0; lam--) {
@@ -248,6 +250,7 @@ int write_tables(Plan2& P)
         x.v2 = P.D[i] >= 2 ? at<T>(P, P.off_v[i][P.D[i] - 2]) : zero;
         x.r2 = fin_fused(P.D[i], P.lamc) ? at<T>(P, P.off_r[i][P.D[i] - 2]) : nullptr;
         x.part = at<double>(P, P.off_part[i]);
+        x.partf = at<double>(P, P.off_partf[i]);
         x.prob = i;
         hf[s] = x;
     }
@@ -257,10 +260,13 @@ int write_tables(Plan2& P)
 template <typename T>
 const Fin2<T>* fin_items(Plan2& P, int cls) { return at<Fin2<T>>(P, P.off_fin) + P.cls_first[cls]; }
 
+// small_only: only the size classes whose residual kernel does not sum f^2
+// itself (n < 4; see enq_resid)
 template <typename T>
-void enq_norm_f(Plan2& P, Ctl* ctls, int* nact)
+void enq_norm_f(Plan2& P, Ctl* ctls, int* nact, bool small_only = false)
 {
     for (size_t c = 0; c < P.cls_n.size(); c++) {
+        if (small_only && P.cls_n[c] >= 4) continue;
         launch_b_sumsq<T>(P.cls_n[c], fin_items<T>(P, (int)c), P.cls_count[c], ctls, P.stream);
         launch_b_finalize<T>(0, fin_items<T>(P, (int)c), P.cls_count[c], P.nparts[c], ctls, nact, P.stream);
     }
@@ -294,22 +300,28 @@ double bytes_jac(int diag, int m, size_t es)
     return es * (2.0 * (m - 1) * (m - 1) + (double)sizeD(m));
 }
 
+// withf: the first evaluation of a solve: the residual kernel of every size
+// class with n >= 4 also sums f^2, so that the norm of f needs no pass of its
+// own (the others have theirs from enq_norm_f(small_only))
 template <typename T>
-void enq_resid(Plan2& P, Ctl* ctls, int* nact)
+void enq_resid(Plan2& P, Ctl* ctls, int* nact, bool withf_all = false)
 {
     size_t es = sizeof(T);
     for (size_t c = 0; c < P.cls_n.size(); c++) {
+        const bool withf = withf_all && P.cls_n[c] >= 4;
         {
             const int n = P.cls_n[c];
             const bool fz = fin_fused(2 * (ilog2(n) - 1), P.lamc);
             Timed t(&P.tm, MG_K_RESIDUAL, bytes_resid(n, es, fz) * P.cls_count[c], true);
-            launch_b_resid<T>(n, fz ? 1 : 0, P.rorder, fin_items<T>(P, (int)c), P.cls_count[c], ctls, P.stream);
+            launch_b_resid<T>(n, fz ? 1 : 0, P.rorder, fin_items<T>(P, (int)c), P.cls_count[c], ctls, P.stream,
+                              withf ? 1 : 0);
         }
-        Timed t(&P.tm, MG_K_NORM, 8.0 * P.nparts[c] * P.cls_count[c]);
-        launch_b_finalize<T>(1, fin_items<T>(P, (int)c), P.cls_count[c], P.nparts[c], ctls, nact, P.stream,
-                             P.nprob == 1 ? P.hact : nullptr);
+        Timed t(&P.tm, MG_K_NORM, 8.0 * P.nparts[c] * P.cls_count[c] * (withf ? 2 : 1));
+        launch_b_finalize<T>(withf ? 2 : 1, fin_items<T>(P, (int)c), P.cls_count[c], P.nparts[c], ctls, nact,
+                             P.stream, P.nprob == 1 ? P.hact : nullptr);
     }
 }
+
 
 // A single problem whose aligned levels kMidTop .. kMidLow (sides 256 .. 64)
 // all run one thread per point, with the coarse kernel starting at kMidLow:
@@ -544,13 +556,14 @@ int plan2_vcycle(Plan2& P, double* const* u, const double* const* f, double* rel
     if (e) return e;
     if (P.rorder == 4) launch_b_rhs4(P.n[0], f[0], at<double>(P, P.off_g), P.stream);
     launch_b_ctl_reset(ctls, P.nprob, 0, 0, 0.0, nact, P.has_net ? 1 : 0, P.stream);
+    const bool wf = relres != nullptr;
     if (P.prec == MG_FP64) {
-        if (relres) enq_norm_f<double>(P, ctls, nact);
-        enq_resid<double>(P, ctls, nact);
+        if (wf) enq_norm_f<double>(P, ctls, nact, true);
+        enq_resid<double>(P, ctls, nact, wf);
         enq_cycle<double>(P, ctls);
     } else {
-        if (relres) enq_norm_f<float>(P, ctls, nact);
-        enq_resid<float>(P, ctls, nact);
+        if (wf) enq_norm_f<float>(P, ctls, nact, true);
+        enq_resid<float>(P, ctls, nact, wf);
         enq_cycle<float>(P, ctls);
     }
     e = last_launch();
@@ -575,8 +588,13 @@ int plan2_solve(Plan2& P, double* const* u, const double* const* f, double rtol,
     if (e) return e;
     if (P.rorder == 4) launch_b_rhs4(P.n[0], f[0], at<double>(P, P.off_g), P.stream);
     launch_b_ctl_reset(ctls, P.nprob, 1, max_cycles, rtol, nact, P.has_net ? 1 : 0, P.stream);
-    if (P.prec == MG_FP64) { enq_norm_f<double>(P, ctls, nact); enq_resid<double>(P, ctls, nact); }
-    else { enq_norm_f<float>(P, ctls, nact); enq_resid<float>(P, ctls, nact); }
+    if (P.prec == MG_FP64) {
+        enq_norm_f<double>(P, ctls, nact, true);
+        enq_resid<double>(P, ctls, nact, true);
+    } else {
+        enq_norm_f<float>(P, ctls, nact, true);
+        enq_resid<float>(P, ctls, nact, true);
+    }
     if ((e = last_launch())) return e;
     // The active-problem count after evaluation it lands in host slot it & 1
     // before event ev[it & 1]: copied, or for a single problem written by

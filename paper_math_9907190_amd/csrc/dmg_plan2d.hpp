@@ -18,7 +18,7 @@ struct Plan2 {
     // workspace offsets
     size_t off_ctl = 0, off_nactive = 0, off_zero = 0, off_fin = 0, off_coarse = 0, off_net = 0, off_lg_item = 0, total = 0;
     bool has_net = false;     // learned coarse correction set (packed bf16 weights at off_net)
-    std::vector<size_t> off_r0, off_part;
+    std::vector<size_t> off_r0, off_part, off_partf;
     std::vector<std::vector<size_t>> off_r, off_v;   // [problem][aligned level]
     std::vector<size_t> off_rs_items, off_jac_items; // [aligned level]
     std::vector<int> n_rs_items, n_jac_items;
