@@ -63,11 +63,13 @@ def lib():
         L.orc_relres_ord.argtypes = [i, i, i, dp, dp, dp]
         L.orc_vcycle_ord_trace.argtypes = [i, i, dp, i, i, dp, dp, dp, dp]
         L.orc_solve_ord.argtypes = [i, i, dp, i, i, dp, dp, d, i, ip, dp, dp]
+        L.orc_vcycle_usual.argtypes = [i, i, d, i, i, dp, dp, dp, dp]
+        L.orc_solve_usual.argtypes = [i, i, d, i, i, dp, dp, d, i, ip, dp, dp]
         L.orc_step_restrict.argtypes = [i, i, i, dp, dp]
         L.orc_step_jacobi.argtypes = [i, i, i, dp, dp, dp, dp]
         for fn in ("orc_residual", "orc_relres", "orc_vcycle", "orc_vcycle_trace", "orc_solve",
                    "orc_residual_ord", "orc_relres_ord", "orc_vcycle_ord_trace", "orc_solve_ord",
-                   "orc_step_restrict", "orc_step_jacobi"):
+                   "orc_step_restrict", "orc_step_jacobi", "orc_vcycle_usual", "orc_solve_usual"):
             getattr(L, fn).restype = ctypes.c_int
         L.orc_net_forward.argtypes = [i, i, dp, dp, dp]
         L.orc_net_forward.restype = ctypes.c_int
@@ -188,9 +190,63 @@ def solve_two_stage(u, f, p2=None, p4=None, prec=0, rtol1=1e-6, rtol=1e-10, max_
     return u, c1, c2, rr
 
 
+# ----------------------------------------------- the conventional cycle
+# over-relaxation the paper tunes for it: 2D p (Table tbl:2d), 3D p_g
+# (Table tbl:3dopt); fourth-order residual: 1.216 (2D), 1.70 (3D)
+P2D_USUAL = 1.121
+P3D_USUAL = 1.30
+P2D_USUAL_H4 = 1.216
+P3D_USUAL_H4 = 1.70
+
+
+def usual_sides(dim, n):
+    K = int(round(np.log2(n)))
+    return [n >> d for d in range(K)]
+
+
+def vcycle_usual_trace(u, f, p, prec=0, order=2):
+    """One conventional V-cycle (Sections 2.1-2.3, 3.1-3.3); returns
+    (u_new, [r per level], [v per level]), finest first."""
+    dim, n = _dimn(u)
+    sides = usual_sides(dim, n)
+    sizes = [(m + 1) ** dim for m in sides]
+    rt = np.zeros(sum(sizes))
+    vt = np.zeros(sum(sizes))
+    u = np.array(u, dtype=np.float64, order="C")
+    _chk(lib().orc_vcycle_usual(dim, n, float(p), prec, order, _ptr(u), _ptr(f), _ptr(rt), _ptr(vt)),
+         "orc_vcycle_usual")
+    rs, vs, off = [], [], 0
+    for m, s in zip(sides, sizes):
+        rs.append(rt[off:off + s].reshape((m + 1,) * dim))
+        vs.append(vt[off:off + s].reshape((m + 1,) * dim))
+        off += s
+    return u, rs, vs
+
+
+def vcycle_usual(u, f, p, prec=0, order=2):
+    dim, n = _dimn(u)
+    u = np.array(u, dtype=np.float64, order="C")
+    _chk(lib().orc_vcycle_usual(dim, n, float(p), prec, order, _ptr(u), _ptr(f), None, None), "orc_vcycle_usual")
+    return u
+
+
+def solve_usual(u, f, p, prec=0, rtol=1e-10, max_cycles=100, check=True, order=2):
+    """Returns (u, cycles, relres, history, status) of the conventional cycle."""
+    dim, n = _dimn(u)
+    u = np.array(u, dtype=np.float64, order="C")
+    hist = np.zeros(max_cycles + 1)
+    cyc = ctypes.c_int()
+    rr = ctypes.c_double()
+    st = lib().orc_solve_usual(dim, n, float(p), prec, order, _ptr(u), _ptr(f), rtol, max_cycles, ctypes.byref(cyc),
+                               ctypes.byref(rr), _ptr(hist))
+    if check and st not in (OK, ERR_NOT_CONVERGED):
+        raise OracleError(st, "orc_solve_usual")
+    return u, cyc.value, rr.value, hist[:cyc.value + 1], st
+
+
 def step_restrict(dim, kind, fine):
     m = fine.shape[0] - 1
-    mc = m // 2 if (dim == 2 and kind == 1) or (dim == 3 and kind == 2) else m
+    mc = m // 2 if (dim == 2 and kind in (1, 2)) or (dim == 3 and kind in (2, 3)) else m
     out = np.zeros((mc + 1,) * dim)
     _chk(lib().orc_step_restrict(dim, kind, m, _ptr(np.ascontiguousarray(fine, dtype=np.float64)), _ptr(out)),
          "orc_step_restrict")

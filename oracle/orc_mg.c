@@ -236,15 +236,14 @@ int orc_vcycle(int dim, int n, const double *p, int prec, double *u, const doubl
  * history (nullable, max_cycles+1 entries): relative residual after
  * 0, 1, ... cycles.  A residual that grows for three cycles in a row and
  * exceeds the starting residual is reported as divergence (growth at the
- * rounding floor is not). */
-int orc_solve_ord(int dim, int n, const double *p, int prec, int order, double *u, const double *f,
-                  double rtol, int max_cycles, int *cycles_out, double *relres_out, double *history)
+ * rounding floor is not).  `cycle` runs one cycle of the chosen scheme. */
+typedef int (*orc_cycle_fn)(const void *ctx, double *u, const double *f);
+
+static int orc_solve_loop(int dim, int n, int order, double *u, const double *f, double rtol, int max_cycles,
+                          int *cycles_out, double *relres_out, double *history, orc_cycle_fn cycle, const void *ctx)
 {
-    int e = orc_check(dim, n);
-    if (e) return e;
-    if (!p || !u || !f || max_cycles < 0 || !(rtol >= 0) || (order != 2 && order != 4)) return ORC_ERR_ARG;
     double rr;
-    e = orc_relres_ord(dim, n, order, u, f, &rr);
+    int e = orc_relres_ord(dim, n, order, u, f, &rr);
     if (e) return e;
     if (history) history[0] = rr;
     int k = 0, grow = 0;
@@ -252,7 +251,7 @@ int orc_solve_ord(int dim, int n, const double *p, int prec, int order, double *
     int status = ORC_OK;
     while (!(rr <= rtol) && k < max_cycles) {
         if (!isfinite(rr)) { status = ORC_ERR_NONFINITE; break; }
-        e = orc_vcycle_ord_trace(dim, n, p, prec, order, u, f, NULL, NULL);
+        e = cycle(ctx, u, f);
         if (e) return e;
         k++;
         e = orc_relres_ord(dim, n, order, u, f, &rr);
@@ -269,6 +268,56 @@ int orc_solve_ord(int dim, int n, const double *p, int prec, int order, double *
     return status;
 }
 
+struct orc_cycle_args {
+    int dim, n, prec, order;
+    const double *p;
+};
+
+static int orc_diag_cycle(const void *ctx, double *u, const double *f)
+{
+    const struct orc_cycle_args *a = (const struct orc_cycle_args *)ctx;
+    return orc_vcycle_ord_trace(a->dim, a->n, a->p, a->prec, a->order, u, f, NULL, NULL);
+}
+
+int orc_solve_ord(int dim, int n, const double *p, int prec, int order, double *u, const double *f,
+                  double rtol, int max_cycles, int *cycles_out, double *relres_out, double *history)
+{
+    int e = orc_check(dim, n);
+    if (e) return e;
+    if (!p || !u || !f || max_cycles < 0 || !(rtol >= 0) || (order != 2 && order != 4)) return ORC_ERR_ARG;
+    struct orc_cycle_args a = {dim, n, prec, order, p};
+    return orc_solve_loop(dim, n, order, u, f, rtol, max_cycles, cycles_out, relres_out, history, orc_diag_cycle, &a);
+}
+
+/* The conventional comparison cycle (Sections 2.1-2.3, 3.1-3.3): one
+ * parameter p (2D) / p_g (3D) scaling the residual term of every Jacobi
+ * iteration; prec and order as for the diagonal cycle. */
+int orc_vcycle_usual(int dim, int n, double p, int prec, int order, double *u, const double *f, double *rtrace,
+                     double *vtrace)
+{
+    int e = orc_check(dim, n);
+    if (e) return e;
+    if (!u || !f || !(p > 0) || (prec != 0 && prec != 1) || (order != 2 && order != 4)) return ORC_ERR_ARG;
+    return prec == 0 ? vcycle_usual(dim, n, order, p, u, f, rtrace, vtrace)
+                     : vcycle_usual_f32(dim, n, order, p, u, f, rtrace, vtrace);
+}
+
+static int orc_usual_cycle(const void *ctx, double *u, const double *f)
+{
+    const struct orc_cycle_args *a = (const struct orc_cycle_args *)ctx;
+    return orc_vcycle_usual(a->dim, a->n, a->p[0], a->prec, a->order, u, f, NULL, NULL);
+}
+
+int orc_solve_usual(int dim, int n, double p, int prec, int order, double *u, const double *f, double rtol,
+                    int max_cycles, int *cycles_out, double *relres_out, double *history)
+{
+    int e = orc_check(dim, n);
+    if (e) return e;
+    if (!u || !f || !(p > 0) || max_cycles < 0 || !(rtol >= 0) || (order != 2 && order != 4)) return ORC_ERR_ARG;
+    struct orc_cycle_args a = {dim, n, prec, order, &p};
+    return orc_solve_loop(dim, n, order, u, f, rtol, max_cycles, cycles_out, relres_out, history, orc_usual_cycle, &a);
+}
+
 int orc_solve(int dim, int n, const double *p, int prec, double *u, const double *f,
               double rtol, int max_cycles, int *cycles_out, double *relres_out, double *history)
 {
@@ -281,7 +330,11 @@ int orc_solve(int dim, int n, const double *p, int prec, double *u, const double
  * dim 2 jacobi kind: 0 axis grid (coarse input side m), 1 diagonal grid
  *   (coarse input side m/2); c[0] the residual coefficient.
  * dim 3 jacobi kind: 0 green (input red, side m), 1 red (input magenta, side
- *   m; c[0], c[1]), 2 magenta (input blue, side m/2).  All in double. */
+ *   m; c[0], c[1]), 2 magenta (input blue, side m/2).
+ * The conventional cycle: restrict kind 2 (dim 2) / 3 (dim 3) is the full
+ *   weighting (m -> m/2); jacobi kind 2 (dim 2) / 3 (dim 3) interpolates the
+ *   coarse correction (side m/2) and runs one red-black iteration.
+ * All in double. */
 int orc_step_restrict(int dim, int kind, int m, const double *fine, double *coarse)
 {
     if (orc_log2(m) < 1 || !fine || !coarse) return ORC_ERR_ARG;
@@ -290,6 +343,8 @@ int orc_step_restrict(int dim, int kind, int m, const double *fine, double *coar
     else if (dim == 3 && kind == 0) rs3_green_to_red(m, fine, coarse);
     else if (dim == 3 && kind == 1) rs3_red_to_magenta(m, fine, coarse);
     else if (dim == 3 && kind == 2) rs3_magenta_to_blue(m, fine, coarse);
+    else if (dim == 2 && kind == 2) rs2_full(m, fine, coarse);
+    else if (dim == 3 && kind == 3) rs3_full(m, fine, coarse);
     else return ORC_ERR_ARG;
     return ORC_OK;
 }
@@ -303,6 +358,10 @@ int orc_step_jacobi(int dim, int kind, int m, const double *c, const double *r, 
     else if (dim == 3 && kind == 0) jac3_green(m, c[0], r, vc, v);
     else if (dim == 3 && kind == 1) jac3_red(m, c[0], c[1], r, vc, v);
     else if (dim == 3 && kind == 2) jac3_magenta(m, c[0], r, vc, v);
+    else if ((dim == 2 && kind == 2) || (dim == 3 && kind == 3)) {
+        interp_lin(dim, m, vc, v);
+        rbj_cubic(dim, m, c[0], r, v);
+    }
     else return ORC_ERR_ARG;
     return ORC_OK;
 }

@@ -360,3 +360,180 @@ done:
     free(rl); free(vl); free(ml);
     return rc;
 }
+
+/* ------------------------------------------- the conventional ("usual") cycle
+ * The comparison scheme of Sections 2.1-2.3 and 3.1-3.3: the standard
+ * hierarchy of axis-aligned (cubic) grids of spacing h, 2h, 4h, ... down to
+ * one interior node; the conventional nine-point (2D) or 27-point (3D)
+ * full-weighting restriction; bilinear (trilinear) interpolation of the
+ * coarse correction followed by one Jacobi iteration on the finer grid
+ * (nu1 = 0, nu2 = 1), taken in red-black order as the diagonal scheme's
+ * sweeps are: the points with an odd index sum first, then the even ones
+ * from the new odd values.  Every level is a full array of side m = n/sigma. */
+
+/* nine-point full weighting: coarse (A,B) from the 3x3 fine block around
+ * (2A,2B), weights 4 (centre), 2 (axis neighbours), 1 (diagonal), over 16 */
+static void SFX(rs2_full)(int m, const R *r, R *rc)
+{
+    int mc = m / 2;
+    memset(rc, 0, sizeof(R) * (size_t)(mc + 1) * (size_t)(mc + 1));
+    for (int B = 1; B < mc; B++)
+        for (int A = 1; A < mc; A++) {
+            int a = 2 * A, b = 2 * B;
+            rc[I2(mc, A, B)] = (R)((4 * r[I2(m, a, b)]
+                + 2 * (r[I2(m, a + 1, b)] + r[I2(m, a, b + 1)] + r[I2(m, a - 1, b)] + r[I2(m, a, b - 1)])
+                + r[I2(m, a + 1, b + 1)] + r[I2(m, a - 1, b + 1)] + r[I2(m, a - 1, b - 1)] + r[I2(m, a + 1, b - 1)])
+                / 16);
+        }
+}
+
+/* 27-point full weighting: weights 8 (centre), 4 (6 faces), 2 (12 edges),
+ * 1 (8 corners), over 64 */
+static void SFX(rs3_full)(int m, const R *r, R *rc)
+{
+    int mc = m / 2;
+    memset(rc, 0, sizeof(R) * SFX(vol3)(mc));
+    for (int C = 1; C < mc; C++)
+        for (int B = 1; B < mc; B++)
+            for (int A = 1; A < mc; A++) {
+                int i = 2 * A, j = 2 * B, k = 2 * C;
+                R faces = r[I3(m, i + 1, j, k)] + r[I3(m, i - 1, j, k)] + r[I3(m, i, j + 1, k)]
+                        + r[I3(m, i, j - 1, k)] + r[I3(m, i, j, k + 1)] + r[I3(m, i, j, k - 1)];
+                R edges = r[I3(m, i + 1, j + 1, k)] + r[I3(m, i + 1, j - 1, k)] + r[I3(m, i - 1, j + 1, k)]
+                        + r[I3(m, i - 1, j - 1, k)] + r[I3(m, i + 1, j, k + 1)] + r[I3(m, i + 1, j, k - 1)]
+                        + r[I3(m, i - 1, j, k + 1)] + r[I3(m, i - 1, j, k - 1)] + r[I3(m, i, j + 1, k + 1)]
+                        + r[I3(m, i, j + 1, k - 1)] + r[I3(m, i, j - 1, k + 1)] + r[I3(m, i, j - 1, k - 1)];
+                R corners = r[I3(m, i + 1, j + 1, k + 1)] + r[I3(m, i + 1, j + 1, k - 1)]
+                          + r[I3(m, i + 1, j - 1, k + 1)] + r[I3(m, i + 1, j - 1, k - 1)]
+                          + r[I3(m, i - 1, j + 1, k + 1)] + r[I3(m, i - 1, j + 1, k - 1)]
+                          + r[I3(m, i - 1, j - 1, k + 1)] + r[I3(m, i - 1, j - 1, k - 1)];
+                rc[I3(mc, A, B, C)] = (R)((8 * r[I3(m, i, j, k)] + 4 * faces + 2 * edges + corners) / 64);
+            }
+}
+
+/* bilinear (2D) / trilinear (3D) interpolation from the grid of side m/2 onto
+ * the grid of side m: a fine point with q odd indices is the mean of its 2^q
+ * coarse neighbours (boundary values are 0 on both grids) */
+static void SFX(interp_lin)(int dim, int m, const R *vc, R *v)
+{
+    int mc = m / 2;
+    if (dim == 2) {
+        memset(v, 0, sizeof(R) * (size_t)(m + 1) * (size_t)(m + 1));
+        for (int b = 1; b < m; b++)
+            for (int a = 1; a < m; a++) {
+                int a0 = a / 2, a1 = (a + 1) / 2, b0 = b / 2, b1 = (b + 1) / 2;
+                if (a % 2 == 0 && b % 2 == 0) v[I2(m, a, b)] = vc[I2(mc, a0, b0)];
+                else if (b % 2 == 0) v[I2(m, a, b)] = (R)((vc[I2(mc, a0, b0)] + vc[I2(mc, a1, b0)]) / 2);
+                else if (a % 2 == 0) v[I2(m, a, b)] = (R)((vc[I2(mc, a0, b0)] + vc[I2(mc, a0, b1)]) / 2);
+                else v[I2(m, a, b)] = (R)((vc[I2(mc, a0, b0)] + vc[I2(mc, a1, b0)] + vc[I2(mc, a1, b1)]
+                                            + vc[I2(mc, a0, b1)]) / 4);
+            }
+        return;
+    }
+    memset(v, 0, sizeof(R) * SFX(vol3)(m));
+    for (int k = 1; k < m; k++)
+        for (int j = 1; j < m; j++)
+            for (int i = 1; i < m; i++) {
+                /* the mean of the distinct coarse corners: the indices of an
+                 * odd axis take both neighbours, an even axis its own */
+                int i0 = i / 2, i1 = (i + 1) / 2, j0 = j / 2, j1 = (j + 1) / 2, k0 = k / 2, k1 = (k + 1) / 2;
+                int q = (i & 1) + (j & 1) + (k & 1);
+                R s = 0;
+                for (int kk = k0; kk <= k1; kk++)
+                    for (int jj = j0; jj <= j1; jj++)
+                        for (int ii = i0; ii <= i1; ii++) s = (R)(s + vc[I3(mc, ii, jj, kk)]);
+                s = (R)(s / (R)(1 << q));
+                v[I3(m, i, j, k)] = s;
+            }
+}
+
+/* One red-black Jacobi iteration in place on the cubic grid of side m for
+ * Lap v = r with spacing s (c = p s^2): v(x) = (sum of the 2 dim axis
+ * neighbours - c r(x)) / (2 dim), first at the points with an odd index sum
+ * from the values v holds, then at the even ones from the new odd values. */
+static void SFX(rbj_cubic)(int dim, int m, R c, const R *r, R *v)
+{
+    for (int par = 1; par >= 0; par--) {
+        if (dim == 2) {
+            for (int b = 1; b < m; b++)
+                for (int a = 1; a < m; a++) {
+                    if ((a + b) % 2 != par) continue;
+                    v[I2(m, a, b)] = (R)((-c * r[I2(m, a, b)] + v[I2(m, a - 1, b)] + v[I2(m, a, b - 1)]
+                                          + v[I2(m, a + 1, b)] + v[I2(m, a, b + 1)]) / 4);
+                }
+        } else {
+            for (int k = 1; k < m; k++)
+                for (int j = 1; j < m; j++)
+                    for (int i = 1; i < m; i++) {
+                        if ((i + j + k) % 2 != par) continue;
+                        v[I3(m, i, j, k)] = (R)((-c * r[I3(m, i, j, k)]
+                            + v[I3(m, i + 1, j, k)] + v[I3(m, i - 1, j, k)] + v[I3(m, i, j + 1, k)]
+                            + v[I3(m, i, j - 1, k)] + v[I3(m, i, j, k + 1)] + v[I3(m, i, j, k - 1)]) / 6);
+                    }
+        }
+    }
+}
+
+/* One conventional V-cycle: r = f - Lap_h(u) on the finest grid (order 4:
+ * Eq. Efos2 / Efos4), full weighting down to side 2, then from a zero
+ * correction on the coarsest grid: interpolate, one red-black Jacobi
+ * iteration with c = p (sigma h)^2, up to the finest grid; u <- u + v.
+ * rtrace / vtrace (nullable): every level's residual and correction, finest
+ * first, each as its full (m+1)^dim array. */
+static int SFX(vcycle_usual)(int dim, int n, int order, double p, double *u, const double *f, double *rtrace,
+                             double *vtrace)
+{
+    int K = orc_log2(n);
+    if (K < 1 || (dim != 2 && dim != 3)) return ORC_ERR_SIZE;
+    int D = K - 1;
+    double h = 1.0 / n;
+    R **rl = (R **)calloc((size_t)D + 1, sizeof(R *));
+    R **vl = (R **)calloc((size_t)D + 1, sizeof(R *));
+    if (!rl || !vl) { free(rl); free(vl); return ORC_ERR_ALLOC; }
+    int rc = ORC_OK;
+    for (int d = 0; d <= D; d++) {
+        int m = n >> d;
+        size_t cnt = (dim == 2) ? (size_t)(m + 1) * (size_t)(m + 1) : SFX(vol3)(m);
+        rl[d] = (R *)calloc(cnt, sizeof(R));
+        vl[d] = (R *)calloc(cnt, sizeof(R));
+        if (!rl[d] || !vl[d]) { rc = ORC_ERR_ALLOC; goto done; }
+    }
+    {
+        size_t cnt = (dim == 2) ? (size_t)(n + 1) * (size_t)(n + 1) : SFX(vol3)(n);
+        double *r0 = (double *)malloc(cnt * sizeof(double));
+        if (!r0) { rc = ORC_ERR_ALLOC; goto done; }
+        orc_residual_ord_core(dim, n, order, u, f, r0);
+        for (size_t q = 0; q < cnt; q++) rl[0][q] = (R)r0[q];
+        free(r0);
+    }
+    for (int d = 1; d <= D; d++) {
+        if (dim == 2) SFX(rs2_full)(n >> (d - 1), rl[d - 1], rl[d]);
+        else SFX(rs3_full)(n >> (d - 1), rl[d - 1], rl[d]);
+    }
+    for (int d = D; d >= 0; d--) {
+        int m = n >> d;
+        double sh = (double)(1 << d) * h;    /* sigma * h */
+        if (d < D) SFX(interp_lin)(dim, m, vl[d + 1], vl[d]);   /* the coarsest starts from vl[D] = 0 */
+        SFX(rbj_cubic)(dim, m, (R)(p * sh * sh), rl[d], vl[d]);
+    }
+    {
+        size_t cnt = (dim == 2) ? (size_t)(n + 1) * (size_t)(n + 1) : SFX(vol3)(n);
+        for (size_t q = 0; q < cnt; q++) u[q] = u[q] + (double)vl[0][q];
+    }
+    if (rtrace || vtrace) {
+        size_t off = 0;
+        for (int d = 0; d <= D; d++) {
+            int m = n >> d;
+            size_t cnt = (dim == 2) ? (size_t)(m + 1) * (size_t)(m + 1) : SFX(vol3)(m);
+            for (size_t q = 0; q < cnt; q++) {
+                if (rtrace) rtrace[off + q] = (double)rl[d][q];
+                if (vtrace) vtrace[off + q] = (double)vl[d][q];
+            }
+            off += cnt;
+        }
+    }
+done:
+    for (int d = 0; d <= D; d++) { free(rl[d]); free(vl[d]); }
+    free(rl); free(vl);
+    return rc;
+}
