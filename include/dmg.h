@@ -86,7 +86,7 @@ typedef struct mg_plan mg_plan;
 int mg_workspace_bytes(int dim, int n, int precision, size_t *bytes);
 
 /* Build a plan.  p: over-relaxation parameters, np = 1 in 2D (p, Section
- * 2.5; the paper's tuned value is 1.052) and np = 4 in 3D (p_m, p_r1, p_r2,
+ * 2.4; the paper's tuned value is 1.052) and np = 4 in 3D (p_m, p_r1, p_r2,
  * p_g, Section 3.4; tuned 1.11, 1.42, 1.08, 0.99).  workspace: device
  * memory of at least mg_workspace_bytes bytes, 256-byte aligned, used only
  * by this plan until mg_destroy.  hip_stream: a hipStream_t or NULL.
@@ -99,7 +99,9 @@ int mg_setup(mg_plan **out, int dim, int n, int precision, const double *p, int 
  * entry (||r||_2 if f = 0); passing it synchronises the stream. */
 int mg_vcycle(mg_plan *plan, double *u, const double *f, double *rel_res_before);
 
-/* Outer iteration u <- u + v until the relative residual is <= rtol or
+/* Solve of Lap_h u = f (Section 1, Eq. Evpois: each cycle computes the
+ * correction v of the residual equation Lap_h v = f - Lap_h u and sets
+ * u <- u + v).  Outer iteration u <- u + v until the relative residual is <= rtol or
  * max_cycles (0 .. 1000) cycles have run; the residual is checked before
  * every cycle.  cycles_out, rel_res_out (host, nullable).  history (host,
  * nullable, max_cycles+1 doubles): relative residual after 0, 1, ...
