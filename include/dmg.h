@@ -53,7 +53,8 @@ enum {
     MG_ERR_HIP = -5,            /* a HIP runtime call failed */
     MG_ERR_NONFINITE = -6,      /* residual norm became NaN or Inf */
     MG_ERR_DIVERGED = -7,       /* residual grew 3 cycles in a row and exceeds the initial one */
-    MG_ERR_NOT_CONVERGED = -8   /* max_cycles reached; cycles and residual still returned */
+    MG_ERR_NOT_CONVERGED = -8,  /* max_cycles reached; cycles and residual still returned */
+    MG_ERR_SCRATCH = -9         /* mg_vcycle_static: the problem needs more than MG_STATIC_SCRATCH_BYTES */
 };
 
 enum {
@@ -273,6 +274,36 @@ int mg_coarse_export(mg_plan *plan, int level, double *dst);
 
 int mg_destroy(mg_plan *plan);
 const char *mg_strerror(int code);
+
+/* ------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one
+ * V-cycle in place on u, as mg_setup + mg_vcycle would run it, with the
+ * workspace taken from a device array inside the library instead of the
+ * caller's memory.  The call allocates nothing: no hipMalloc, hipHostMalloc
+ * or hipFree, no event, stream or graph; the array is zeroed and the plan's
+ * tables are written into it by kernels on hip_stream (host bookkeeping for
+ * the call is a few hundred bytes of ordinary host memory).
+ *
+ * dim, n, precision (MG_FP64 or MG_FP32_REFINED, optionally | MG_ORDER4),
+ * p, np, u, f, rel_res_before: as for mg_setup and mg_vcycle (u, f device
+ * pointers on the current device; rel_res_before host, nullable, and when
+ * given the call synchronises hip_stream).  hip_stream: a stream of the
+ * current device, or NULL.
+ *
+ * The array holds MG_STATIC_SCRATCH_BYTES (64 MiB) on every device the
+ * library runs on, from the first call there until the process ends.
+ * Problems whose workspace (mg_workspace_bytes) is larger return
+ * MG_ERR_SCRATCH and enqueue nothing; 64 MiB covers 2D n <= 1024 in every
+ * precision (n = 2048 with single-precision levels) and 3D n <= 128
+ * (second-order residual).  Every call on one device uses the same array
+ * and leaves its contents behind; the next call zeroes it first.  Calls
+ * that overlap on one device (two host threads, or two streams whose work
+ * runs concurrently) race on the array and give wrong results: serialise
+ * them. */
+#define MG_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int mg_vcycle_static(int dim, int n, int precision, const double *p, int np, double *u, const double *f,
+                     double *rel_res_before, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -20,4 +20,14 @@ void launch_sumsq(int dim, int n, const double* a, double* partial, int nparts, 
 void launch_finalize(int kind, const double* partial, int nparts, Ctl* ctl, hipStream_t s, HostState* host = nullptr);
 void launch_ctl_reset(Ctl* ctl, int mode, int max_cycles, double rtol, hipStream_t s, int net = 0);
 
+// Stream-ordered set-up of a workspace without host copies: zero `bytes`
+// (a multiple of 16) at dst; copy `bytes` (a multiple of 4) of host data to
+// dst through the arguments of small kernels (the host data may be reused
+// as soon as the call returns).
+struct PutWords {
+    unsigned w[960];   // 3840 bytes per launch, inside the kernel-argument limit
+};
+void launch_zero(void* dst, size_t bytes, hipStream_t s);
+void launch_put_bytes(void* dst, const void* src, size_t bytes, hipStream_t s);
+
 }  // namespace dmg

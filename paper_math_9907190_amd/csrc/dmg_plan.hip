@@ -60,6 +60,7 @@ const char* mg_strerror(int code)
     case MG_ERR_NONFINITE: return "residual is not finite";
     case MG_ERR_DIVERGED: return "iteration diverged";
     case MG_ERR_NOT_CONVERGED: return "not converged within max_cycles";
+    case MG_ERR_SCRATCH: return "problem too large for the static scratch buffer";
     default: return "unknown error code";
     }
 }

@@ -15,6 +15,7 @@
 // by iteration k, so the GPU never waits for the host round trip; the one
 // iteration launched after the last problem stops runs as gated no-ops.
 #include "dmg_b2d.hpp"
+#include "dmg_launch.hpp"
 #include "dmg_host.hpp"
 #include "dmg_net.hpp"
 #include "dmg_plan2d.hpp"
@@ -177,6 +178,39 @@ double coef(const Plan2& P, int lam)
     return (lam & 1) ? 2 * P.p * sh * sh : P.p * sh * sh;
 }
 
+// host bytes into the workspace at offset off: a synchronous copy, or (plans
+// bound without allocation) into a host image of the table region that
+// plan2_bind_static then writes with a few stream-ordered kernels
+int put(Plan2& P, size_t off, const void* src, size_t bytes)
+{
+    if (P.stat) {
+        if (bytes % 4) return MG_ERR_ARG;
+        if (P.stage.size() < off + bytes) P.stage.resize(off + bytes, 0);
+        memcpy(P.stage.data() + off, src, bytes);
+        P.stage_lo = std::min(P.stage_lo, off);
+        return MG_OK;
+    }
+    return hip_status(hipMemcpy(P.ws + off, src, bytes, hipMemcpyHostToDevice));
+}
+
+// the finest item of problem i (u and f are filled per call)
+template <typename T>
+Fin2<T> fin_item(Plan2& P, int i)
+{
+    T* zero = at<T>(P, P.off_zero);
+    Fin2<T> x;
+    memset(&x, 0, sizeof(x));
+    x.r0 = at<T>(P, P.off_r0[i]);
+    x.r1 = P.D[i] >= 1 ? at<T>(P, P.off_r[i][P.D[i] - 1]) : nullptr;
+    x.v1 = P.D[i] >= 1 ? at<T>(P, P.off_v[i][P.D[i] - 1]) : zero;
+    x.v2 = P.D[i] >= 2 ? at<T>(P, P.off_v[i][P.D[i] - 2]) : zero;
+    x.r2 = fin_fused(P.D[i], P.lamc) ? at<T>(P, P.off_r[i][P.D[i] - 2]) : nullptr;
+    x.part = at<double>(P, P.off_part[i]);
+    x.partf = at<double>(P, P.off_partf[i]);
+    x.prob = i;
+    return x;
+}
+
 // host images of the item tables (pointers into the workspace)
 template <typename T>
 int write_tables(Plan2& P)
@@ -192,8 +226,7 @@ int write_tables(Plan2& P)
                 items.push_back(Item2<T>{at<T>(P, P.off_r[i][lam]), at<T>(P, P.off_v[i][lam]),
                                          at<T>(P, P.off_r[i][lam + 1]), i, 0});
         }
-        if (!items.empty() &&
-            hipMemcpy(P.ws + P.off_rs_items[lam], items.data(), items.size() * sizeof(Item2<T>), hipMemcpyHostToDevice) != hipSuccess)
+        if (!items.empty() && put(P, P.off_rs_items[lam], items.data(), items.size() * sizeof(Item2<T>)))
             return MG_ERR_HIP;
         items.clear();
         for (int i = 0; i < P.nprob; i++) {
@@ -203,24 +236,21 @@ int write_tables(Plan2& P)
                 items.push_back(Item2<T>{at<T>(P, P.off_r[i][lam]), at<T>(P, P.off_v[i][lam]),
                                          lam >= 1 ? at<T>(P, P.off_v[i][lam - 1]) : zero, i, 0});
         }
-        if (!items.empty() &&
-            hipMemcpy(P.ws + P.off_jac_items[lam], items.data(), items.size() * sizeof(Item2<T>), hipMemcpyHostToDevice) != hipSuccess)
+        if (!items.empty() && put(P, P.off_jac_items[lam], items.data(), items.size() * sizeof(Item2<T>)))
             return MG_ERR_HIP;
         std::vector<RsPair2<T>> rsp;
         for (int i = 0; i < P.nprob; i++)
             if (pair_level(lam, P.D[i], P.pairs))
                 rsp.push_back(RsPair2<T>{at<T>(P, P.off_r[i][lam]), at<T>(P, P.off_r[i][lam - 1]),
                                          at<T>(P, P.off_r[i][lam - 2]), i, 0});
-        if (!rsp.empty() &&
-            hipMemcpy(P.ws + P.off_rsp_items[lam], rsp.data(), rsp.size() * sizeof(RsPair2<T>), hipMemcpyHostToDevice) != hipSuccess)
+        if (!rsp.empty() && put(P, P.off_rsp_items[lam], rsp.data(), rsp.size() * sizeof(RsPair2<T>)))
             return MG_ERR_HIP;
         std::vector<JPair2<T>> pairs;
         for (int i = 0; i < P.nprob; i++)
             if (pair_level(lam, P.D[i], P.pairs))
                 pairs.push_back(JPair2<T>{at<T>(P, P.off_r[i][lam]), at<T>(P, P.off_r[i][lam - 1]),
                                           at<T>(P, P.off_v[i][lam - 2]), at<T>(P, P.off_v[i][lam]), i, 0});
-        if (!pairs.empty() &&
-            hipMemcpy(P.ws + P.off_pair_items[lam], pairs.data(), pairs.size() * sizeof(JPair2<T>), hipMemcpyHostToDevice) != hipSuccess)
+        if (!pairs.empty() && put(P, P.off_pair_items[lam], pairs.data(), pairs.size() * sizeof(JPair2<T>)))
             return MG_ERR_HIP;
     }
     std::vector<Coarse2B<T>> co;
@@ -236,23 +266,13 @@ int write_tables(Plan2& P)
         }
         co.push_back(c);
     }
-    if (!co.empty() && hipMemcpy(P.ws + P.off_coarse, co.data(), co.size() * sizeof(Coarse2B<T>), hipMemcpyHostToDevice) != hipSuccess)
+    if (!co.empty() && put(P, P.off_coarse, co.data(), co.size() * sizeof(Coarse2B<T>)))
         return MG_ERR_HIP;
-    // finest items (u, f filled per call), in class order
-    Fin2<T>* hf = reinterpret_cast<Fin2<T>*>(P.hfin);
-    for (int s = 0; s < P.nprob; s++) {
-        int i = P.order[s];
-        Fin2<T> x;
-        memset(&x, 0, sizeof(x));
-        x.r0 = at<T>(P, P.off_r0[i]);
-        x.r1 = P.D[i] >= 1 ? at<T>(P, P.off_r[i][P.D[i] - 1]) : nullptr;
-        x.v1 = P.D[i] >= 1 ? at<T>(P, P.off_v[i][P.D[i] - 1]) : zero;
-        x.v2 = P.D[i] >= 2 ? at<T>(P, P.off_v[i][P.D[i] - 2]) : zero;
-        x.r2 = fin_fused(P.D[i], P.lamc) ? at<T>(P, P.off_r[i][P.D[i] - 2]) : nullptr;
-        x.part = at<double>(P, P.off_part[i]);
-        x.partf = at<double>(P, P.off_partf[i]);
-        x.prob = i;
-        hf[s] = x;
+    // finest items (u, f filled per call), in class order; a statically
+    // bound plan writes its one item with u and f on every call instead
+    if (P.hfin) {
+        Fin2<T>* hf = reinterpret_cast<Fin2<T>*>(P.hfin);
+        for (int s = 0; s < P.nprob; s++) hf[s] = fin_item<T>(P, P.order[s]);
     }
     return MG_OK;
 }
@@ -476,6 +496,21 @@ int run_iteration(Plan2& P)
 // uploaded when a pointer changed.
 int bind_uf(Plan2& P, double* const* u, const double* const* f)
 {
+    if (P.stat) {   // one problem: its item, with this call's u and f, written in stream order
+        const double* f0 = P.rorder == 4 ? at<double>(P, P.off_g) : f[0];
+        if (P.prec == MG_FP64) {
+            Fin2<double> x = fin_item<double>(P, 0);
+            x.u = u[0];
+            x.f = f0;
+            launch_put_bytes(P.ws + P.off_fin, &x, sizeof(x), P.stream);
+        } else {
+            Fin2<float> x = fin_item<float>(P, 0);
+            x.u = u[0];
+            x.f = f0;
+            launch_put_bytes(P.ws + P.off_fin, &x, sizeof(x), P.stream);
+        }
+        return last_launch();
+    }
     bool same = P.fin_valid;
     for (int i = 0; same && i < P.nprob; i++) same = P.last_u[i] == u[i] && P.last_f[i] == f[i];
     if (same) return MG_OK;
@@ -532,6 +567,31 @@ int plan2_setup(Plan2& P, void* ws, size_t ws_bytes, hipStream_t stream)
     return plan2_tune_load(P);
 }
 
+int plan2_bind_static(Plan2& P, void* ws, hipStream_t stream)
+{
+    if (P.nprob != 1) return MG_ERR_ARG;
+    if (!ws || ((uintptr_t)ws % kAlign) != 0) return MG_ERR_WS;
+    P.ws = (char*)ws;
+    P.stream = stream;
+    P.tm.stream = stream;
+    P.stat = true;
+    P.use_graph = false;
+    if (hipGetDevice(&P.device) != hipSuccess) return MG_ERR_HIP;
+    // every call starts from a zero workspace: boundary entries of every
+    // level read 0, and the previous call's contents are gone
+    launch_zero(P.ws, P.total, stream);
+    int e = last_launch();
+    if (e) return e;
+    P.stage.clear();
+    P.stage_lo = P.total;
+    if ((e = P.prec == MG_FP64 ? write_tables<double>(P) : write_tables<float>(P))) return e;
+    if (P.stage.size() > P.stage_lo) {   // the tables sit together at the start of the workspace
+        launch_put_bytes(P.ws + P.stage_lo, P.stage.data() + P.stage_lo, P.stage.size() - P.stage_lo, stream);
+        e = last_launch();
+    }
+    return e;
+}
+
 void plan2_destroy(Plan2& P)
 {
     P.tm.destroy();
@@ -568,6 +628,12 @@ int plan2_vcycle(Plan2& P, double* const* u, const double* const* f, double* rel
     }
     e = last_launch();
     if (e) return e;
+    if (relres && P.stat) {   // no pinned buffer: one double straight into the caller's
+        if (hipMemcpyAsync(relres, &ctls[0].last, sizeof(double), hipMemcpyDeviceToHost, P.stream) != hipSuccess ||
+            hipStreamSynchronize(P.stream) != hipSuccess)
+            return MG_ERR_HIP;
+        return MG_OK;
+    }
     if (relres) {
         // relative residual of the entry u of every problem
         if (hipMemcpy2DAsync(P.hres, kCtlHead, ctls, sizeof(Ctl), kCtlHead, P.nprob,

@@ -45,11 +45,21 @@ struct Plan2 {
     hipGraphExec_t gexec = nullptr;
     bool gready = false, use_graph = true;
     hipStream_t cap = nullptr;
+    // bound by plan2_bind_static: no pinned host memory, events or graph; the
+    // tables are written by stream-ordered kernels
+    bool stat = false;
+    std::vector<unsigned char> stage;   // static binding: host image of the tables, by workspace offset
+    size_t stage_lo = 0;                // lowest offset written into stage
 };
 
 int plan2_layout(Plan2& P, int nprob, const int* n, int prec, double p);
 int plan2_setup(Plan2& P, void* ws, size_t ws_bytes, hipStream_t stream);
 void plan2_destroy(Plan2& P);
+// Single problem: bind the laid-out plan to workspace ws (P.total bytes,
+// 256-byte aligned) on `stream` without allocating anything: the workspace
+// is zeroed by a fill kernel and the item tables are written by kernels, all
+// in stream order.  Then only plan2_vcycle may be called; nothing to destroy.
+int plan2_bind_static(Plan2& P, void* ws, hipStream_t stream);
 int plan2_vcycle(Plan2& P, double* const* u, const double* const* f, double* relres);
 int plan2_solve(Plan2& P, double* const* u, const double* const* f, double rtol, int max_cycles, int* cycles,
                 double* relres, int* status, double* history0);

@@ -206,6 +206,19 @@ int plan3_setup(Plan3& P, void* ws, size_t ws_bytes, hipStream_t stream)
     return hip_status(hipMemsetAsync(P.ws, 0, P.total, P.stream));
 }
 
+int plan3_bind_static(Plan3& P, void* ws, hipStream_t stream)
+{
+    if (!ws || ((uintptr_t)ws % kAlign) != 0) return MG_ERR_WS;
+    P.ws = (char*)ws;
+    P.stream = stream;
+    P.tm.stream = stream;
+    if (hipGetDevice(&P.device) != hipSuccess) return MG_ERR_HIP;
+    // every call starts from a zero workspace (boundary entries of every
+    // level read 0; the previous call's contents are gone)
+    launch_zero(P.ws, P.total, stream);
+    return last_launch();
+}
+
 void plan3_destroy(Plan3& P)
 {
     P.tm.destroy();
@@ -235,6 +248,12 @@ int plan3_vcycle(Plan3& P, double* u, const double* f, double* relres)
     enqueue_cycle_any(P, u, ctl);
     int e = last_launch();
     if (e) return e;
+    if (relres && !P.hctl) {   // bound without pinned memory: one double straight into the caller's
+        if (hipMemcpyAsync(relres, &ctl->last, sizeof(double), hipMemcpyDeviceToHost, P.stream) != hipSuccess ||
+            hipStreamSynchronize(P.stream) != hipSuccess)
+            return MG_ERR_HIP;
+        return MG_OK;
+    }
     if (relres) {
         if (hipMemcpyAsync(P.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, P.stream) != hipSuccess) return MG_ERR_HIP;
         if (hipStreamSynchronize(P.stream) != hipSuccess) return MG_ERR_HIP;

@@ -38,6 +38,11 @@ struct Plan3 {
 int plan3_layout(Plan3& P, int n, int prec, const double* p);
 int plan3_setup(Plan3& P, void* ws, size_t ws_bytes, hipStream_t stream);
 void plan3_destroy(Plan3& P);
+// Bind the laid-out plan to workspace ws (P.total bytes, 256-byte aligned) on
+// `stream` without allocating anything (the workspace is zeroed by a fill
+// kernel in stream order).  Then only plan3_vcycle may be called; nothing to
+// destroy.
+int plan3_bind_static(Plan3& P, void* ws, hipStream_t stream);
 int plan3_vcycle(Plan3& P, double* u, const double* f, double* relres);
 int plan3_solve(Plan3& P, double* u, const double* f, double rtol, int max_cycles, int* cycles, double* relres,
                 double* history);

@@ -9,6 +9,7 @@
 #include "dmg_launch.hpp"
 
 #include <math.h>
+#include <string.h>
 
 namespace dmg {
 
@@ -206,6 +207,47 @@ __global__ void k_ctl_reset(Ctl* ctl, int mode, int max_cycles, double rtol, int
 void launch_ctl_reset(Ctl* ctl, int mode, int max_cycles, double rtol, hipStream_t s, int net)
 {
     hipLaunchKernelGGL(k_ctl_reset, dim3(1), dim3(64), 0, s, ctl, mode, max_cycles, rtol, net);
+}
+
+// ------------------------------------------------ stream-ordered workspace set-up
+// Zero `bytes` (a multiple of 16) at dst: a fill kernel rather than a
+// memset, so the set-up stays a kernel on the caller's stream.
+__global__ void __launch_bounds__(256) k_zero16(uint4* __restrict__ dst, size_t n16)
+{
+    const uint4 z = make_uint4(0, 0, 0, 0);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = z;
+}
+
+void launch_zero(void* dst, size_t bytes, hipStream_t s)
+{
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return;
+    const size_t want = (n16 + 255) / 256;
+    const int blocks = (int)(want < 4096 ? want : 4096);
+    hipLaunchKernelGGL(k_zero16, dim3(blocks), dim3(256), 0, s, (uint4*)dst, n16);
+}
+
+// Copy words carried in the kernel arguments to dst: host data reaches the
+// device in stream order without a host buffer that must outlive the call.
+__global__ void __launch_bounds__(256) k_put_words(unsigned* __restrict__ dst, PutWords c, int nw)
+{
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) dst[i] = c.w[i];
+}
+
+void launch_put_bytes(void* dst, const void* src, size_t bytes, hipStream_t s)
+{
+    const unsigned char* p = (const unsigned char*)src;
+    unsigned char* d = (unsigned char*)dst;
+    while (bytes > 0) {
+        const size_t chunk = bytes < sizeof(PutWords) ? bytes : sizeof(PutWords);
+        PutWords c;
+        memcpy(c.w, p, chunk);
+        hipLaunchKernelGGL(k_put_words, dim3(1), dim3(256), 0, s, (unsigned*)d, c, (int)(chunk / 4));
+        p += chunk;
+        d += chunk;
+        bytes -= chunk;
+    }
 }
 
 template void launch_residual<double>(int, int, const double*, const double*, double*, double*, int, const Ctl*,

@@ -15,7 +15,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdmg.so")
 
 MG_OK, MG_ERR_ARG, MG_ERR_SIZE, MG_ERR_WS, MG_ERR_ALLOC, MG_ERR_HIP = 0, -1, -2, -3, -4, -5
-MG_ERR_NONFINITE, MG_ERR_DIVERGED, MG_ERR_NOT_CONVERGED = -6, -7, -8
+MG_ERR_NONFINITE, MG_ERR_DIVERGED, MG_ERR_NOT_CONVERGED, MG_ERR_SCRATCH = -6, -7, -8, -9
+MG_STATIC_SCRATCH_BYTES = 64 << 20
 MG_FP64, MG_FP32_REFINED = 0, 1
 MG_ORDER4 = 0x100   # OR-ed into the precision: fourth-order finest residual (Eqs. Efos2, Efos4)
 
@@ -57,6 +58,7 @@ _lib.mg_net_destroy.argtypes = [_vp]
 _lib.mg_set_coarse_net.argtypes = [_vp, _fp, ctypes.c_int]
 _lib.mg_net_stats.argtypes = [_vp, _ip, _ip, _dp, _dp]
 _lib.mg_coarse_export.argtypes = [_vp, ctypes.c_int, _vp]
+_lib.mg_vcycle_static.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _vp, _vp, _dp, _vp]
 _lib.mg_strerror.argtypes = [ctypes.c_int]
 _lib.mg_strerror.restype = ctypes.c_char_p
 for _f in ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_solve_two_stage", "mg_level_get", "mg_level_info",
@@ -64,7 +66,7 @@ for _f in ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_solve_
            "mg_solve_batched", "mg_vcycle_batched", "mg_autotune", "mg_net_weight_count", "mg_net_workspace_bytes",
            "mg_net_create", "mg_net_set_weights", "mg_net_get_weights", "mg_net_init", "mg_net_forward",
            "mg_net_loss_grad", "mg_net_train", "mg_net_destroy", "mg_set_coarse_net", "mg_net_stats",
-           "mg_coarse_export"):
+           "mg_coarse_export", "mg_vcycle_static"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_solve_two_stage", "mg_level_get", "mg_level_info",
@@ -72,7 +74,7 @@ EXPORTS = ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_solve_
            "mg_setup_batched", "mg_solve_batched", "mg_vcycle_batched", "mg_autotune", "mg_net_weight_count",
            "mg_net_workspace_bytes", "mg_net_create", "mg_net_set_weights", "mg_net_get_weights", "mg_net_init",
            "mg_net_forward", "mg_net_loss_grad", "mg_net_train", "mg_net_destroy", "mg_set_coarse_net",
-           "mg_net_stats", "mg_coarse_export")
+           "mg_net_stats", "mg_coarse_export", "mg_vcycle_static")
 
 MG_NET_CUT = 6
 NET_G = {2: 17, 3: 9}
@@ -138,6 +140,15 @@ def mg_solve(plan, u_ptr, f_ptr, rtol, max_cycles):
 
 def mg_level_get(plan, depth, which, dst_ptr):
     _check(_lib.mg_level_get(plan, depth, which, _vp(dst_ptr)), "mg_level_get")
+
+
+def mg_vcycle_static(dim, n, precision, p, u_ptr, f_ptr, stream_ptr, want_relres=False):
+    """One V-cycle on the library's static scratch array (no allocation)."""
+    arr = (ctypes.c_double * len(p))(*[float(x) for x in p])
+    rr = ctypes.c_double()
+    _check(_lib.mg_vcycle_static(dim, n, precision, arr, len(p), _vp(u_ptr), _vp(f_ptr),
+                                 ctypes.byref(rr) if want_relres else None, _vp(stream_ptr)), "mg_vcycle_static")
+    return rr.value if want_relres else None
 
 
 def mg_destroy(plan):

@@ -117,3 +117,30 @@ def test_batch_workspace_holds_the_net_weights(D):
     # the packed bf16 forward weights (9216 entries) are part of every 2D plan
     b = D.mg_batch_workspace_bytes([4], D.MG_FP64)
     assert b >= 2 * 9216
+
+
+def test_vcycle_static_errors_before_any_gpu_call(D):
+    """The allocation-free cycle rejects bad arguments and problems larger
+    than its 64 MiB scratch array before it touches the GPU."""
+    p1 = (ctypes.c_double * 1)(1.052)
+    p4 = (ctypes.c_double * 4)(1.11, 1.42, 1.08, 0.99)
+    u = ctypes.c_void_p(4096)
+    f = ctypes.c_void_p(8192)
+    call = D._lib.mg_vcycle_static
+    assert call(2, 64, 0, p1, 1, None, f, None, None) == D.MG_ERR_ARG
+    assert call(2, 64, 0, p1, 1, u, None, None, None) == D.MG_ERR_ARG
+    assert call(2, 64, 0, p4, 4, u, f, None, None) == D.MG_ERR_ARG
+    assert call(3, 16, 0, p1, 1, u, f, None, None) == D.MG_ERR_ARG
+    assert call(2, 48, 0, p1, 1, u, f, None, None) == D.MG_ERR_SIZE
+    assert call(2, 64, 5, p1, 1, u, f, None, None) == D.MG_ERR_ARG
+    assert call(4, 8, 0, p1, 1, u, f, None, None) == D.MG_ERR_ARG
+    # sizes: the largest that fit, and the first that do not
+    cap = D.MG_STATIC_SCRATCH_BYTES
+    assert D.mg_workspace_bytes(2, 1024, D.MG_FP64 | D.MG_ORDER4) <= cap
+    assert D.mg_workspace_bytes(2, 2048, D.MG_FP32_REFINED) <= cap
+    assert D.mg_workspace_bytes(3, 128, D.MG_FP64) <= cap
+    for dim, n, prec, p, np_ in ((2, 2048, D.MG_FP64, p1, 1), (2, 4096, D.MG_FP32_REFINED, p1, 1),
+                                 (3, 256, D.MG_FP32_REFINED, p4, 4), (3, 128, D.MG_FP64 | D.MG_ORDER4, p4, 4)):
+        assert D.mg_workspace_bytes(dim, n, prec) > cap
+        assert call(dim, n, prec, p, np_, u, f, None, None) == D.MG_ERR_SCRATCH
+    assert "scratch" in D.mg_strerror(D.MG_ERR_SCRATCH)
