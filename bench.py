@@ -40,6 +40,69 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "time to 1e-10 rel. residual & unknowns*cycles/s; plain FP64 vs FP32-refined/learned"
 FAMILY_NAMES = {0: "residual", 1: "restriction", 2: "jacobi", 3: "finest jacobi + u update", 4: "coarse levels",
                 5: "norm"}
+# the kernels of each family, as rocprofv3 names them
+FAMILY_KERNELS = {
+    2: {0: "kb_resid (r0, Eq. Erest2r onto r1, Eq. Erest2b onto r2, norm partials)",
+        1: "kb_rs_pair, kb_mid_down, kb_rs_*",
+        2: "kb_jac_pair, kb_mid_up, kb_jac_*",
+        3: "kb_finest_fused (Jacobi of the first diagonal and the finest axis level, u += v)",
+        4: "kb_coarse", 5: "kb_finalize"},
+    3: {0: "k3_resid_planes (r0 and Eq. Erred onto the red level, norm partials)",
+        1: "k3_r2m_planes, k3_rs_r2m, k3_rs_m2b, k3_rs_g2r",
+        2: "k3_red_planes, k3_mag_planes, k3_green_planes, k3_jac_*",
+        3: "k3_green_planes<finest> (green-red Jacobi, u += v)",
+        4: "k3_coarse", 5: "k_finalize"},
+}
+
+
+def cpu_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fp:
+            for line in fp:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
+
+
+def err_vs(u, ref):
+    """Error of a solution against a reference solution (max-norm and 2-norm, relative)."""
+    import numpy as np
+    if hasattr(u, "cpu"):
+        u = u.cpu().numpy()
+    d = u - ref
+    return {"inf": float(np.abs(d).max() / np.abs(ref).max()), "l2": float(np.linalg.norm(d) / np.linalg.norm(ref))}
+
+
+def kernel_table(S, f, cycles, torch):
+    """Per kernel family: mean launch time, launches and algorithmic bytes per
+    cycle, from HIP events around every launch of the family on the solver's
+    stream over `cycles` V-cycles (mg_vcycle: every launch does its work)."""
+    u = torch.zeros_like(f)
+    S.vcycle(u, f)
+    torch.cuda.synchronize()
+    rows = []
+    for fam in range(6):
+        S.timing(fam)
+        for _ in range(cycles):
+            S.vcycle(u, f)
+        ms, cnt, byt = S.timing_read()
+        S.timing(-1)
+        if cnt == 0:
+            continue
+        gbs = byt / (ms * 1e-3) / 1e9
+        rows.append({"family": FAMILY_NAMES[fam], "kernels": FAMILY_KERNELS[f.dim()][fam],
+                     "us_per_cycle": round(1e3 * ms / cycles, 2), "launches_per_cycle": cnt / cycles,
+                     "bytes_per_cycle": byt / cycles, "achieved_GBs": round(gbs, 1),
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "family_id": fam})
+    return rows
 
 
 def log(*a):
@@ -100,7 +163,7 @@ def timed_solves(S, f, steps, warmup, rtol, family, torch):
     return dt, cycles, kern, us[-1], hist
 
 
-def bench_fourth_order(dmg, f, dev, torch, args):
+def bench_fourth_order(dmg, f, dev, torch, args, ref=None):
     """Fourth-order solution (Eq. Efos2 / Efos4): fourth-order cycles from
     u = 0 with the parameters tuned for them (Sections 2.4 / 3.4) against the
     two-stage solve (second-order cycles with the tuned second-order
@@ -133,6 +196,8 @@ def bench_fourth_order(dmg, f, dev, torch, args):
             torch.cuda.synchronize()
             ms = 1e3 * (time.perf_counter() - t0) / args.steps
             out["%s_%s" % (pname, mode)] = {"ms_to_rtol": round(ms, 4), "cycles_order2": c1, "cycles_order4": c2}
+            if ref is not None:   # against the oracle's fourth-order FP64 solution
+                out["%s_%s" % (pname, mode)]["err_vs_oracle"] = err_vs(us[-1], ref)
             log("  fourth order %s %s: %.3f ms per solve, %d + %d cycles" % (pname, mode, ms, c1, c2))
         S2.close()
         S4.close()
@@ -143,7 +208,7 @@ def bench_fourth_order(dmg, f, dev, torch, args):
     return out
 
 
-def bench_retuned(dmg, f, dev, torch, args):
+def bench_retuned(dmg, f, dev, torch, args, ref=None):
     """Over-relaxation parameters re-tuned at this size (Nelder-Mead on the GPU
     cycle's factor, Sections 2.4 / 3.4; the tuning is outside the timed
     region and timed on its own), then FP64 solves to 1e-10 with the paper's
@@ -159,9 +224,11 @@ def bench_retuned(dmg, f, dev, torch, args):
            "paper_p": list(paper), "paper_factor": round(tune.gpu_factor(dim, n, paper, device=dev), 5)}
     for name, pp in (("paper_p", paper), ("retuned_p", p)):
         S = dmg.Solver(dim, n, precision=dmg.MG_FP64, p=pp, device=dev)
-        dt, cycles, _, _, hist = timed_solves(S, f, args.steps, args.warmup, args.rtol, None, torch)
+        dt, cycles, _, u_last, hist = timed_solves(S, f, args.steps, args.warmup, args.rtol, None, torch)
         out[name + "_fp64"] = {"ms_to_rtol": round(1e3 * dt / args.steps, 4), "cycles": cycles[-1],
                                "final_rel_res": hist[-1]}
+        if ref is not None:
+            out[name + "_fp64"]["err_vs_oracle"] = err_vs(u_last, ref)
         S.close()
         torch.cuda.empty_cache()
     out["speedup"] = round(out["paper_p_fp64"]["ms_to_rtol"] / out["retuned_p_fp64"]["ms_to_rtol"], 3)
@@ -171,7 +238,7 @@ def bench_retuned(dmg, f, dev, torch, args):
     return out
 
 
-def bench_batched(dmg, workloads, dev, torch, args):
+def bench_batched(dmg, workloads, dev, torch, args, with_oracle=False):
     """512 independent 2D problems, sides drawn from {129, 257, 513, 1025}
     (seed 4), smooth-mode f per problem (seed 4+b); single-precision cycles with
     FP64 refinement to 1e-10; one launch per aligned level for the whole
@@ -201,6 +268,17 @@ def bench_batched(dmg, workloads, dev, torch, args):
            "unknowns": unknowns, "ms_to_rtol": round(1e3 * dt / args.steps, 3),
            "unknowns_cycles_per_s": ucs / dt, "cycles_max": max(cyc), "cycles_min": min(cyc),
            "max_final_rel_res": max(rr)}
+    if with_oracle:
+        # the first problem of each size against the oracle's FP64 solution
+        from oracle import oracle as O
+        errs = {}
+        for side in sorted(set(ns)):
+            b = ns.index(side)
+            fh = fs[b].cpu().numpy()
+            uo = O.solve(0 * fh, fh, p=(1.052,), rtol=args.rtol, max_cycles=60)[0]
+            errs["problem%d_n%d" % (b, side)] = err_vs(us[-1][b], uo)
+        res["err_vs_oracle_sample"] = errs
+        res["err_vs_oracle_max_inf"] = max(e["inf"] for e in errs.values())
     log("  batched: %.3f ms per batch solve, cycles %d..%d, %.3e unknowns*cycles/s"
         % (res["ms_to_rtol"], min(cyc), max(cyc), res["unknowns_cycles_per_s"]))
     B.close()
@@ -233,13 +311,19 @@ def train_net(dmg, L, torch, log):
     return w, info
 
 
-def bench_learned(dmg, L, dev, torch, args, w, info):
+def bench_learned(dmg, L, dev, torch, args, w, info, with_oracle=False):
     """Held-out 1025^2 problems (f seeds 5000..5031) solved as one batch to
     1e-10, plain against learned, FP64 and FP32-refined; the network's and
     the plain sub-cycle's first-cycle cut-level residual reductions as the
     coarse kernel measured them, and how often the judge kept the network."""
     ns = [1024] * 32
     fs = [torch.from_numpy(f).to(dev) for f in L.eval_problems(1024, range(5000, 5032))]
+    refs = {}
+    if with_oracle:   # oracle FP64 solutions of two held-out problems (one of each kind)
+        from oracle import oracle as O
+        for b in (0, 1):
+            fh = fs[b].cpu().numpy()
+            refs[b] = O.solve(0 * fh, fh, p=(1.052,), rtol=args.rtol, max_cycles=60)[0]
     res = {"workload": "32 held-out 1025^2 problems (f seeds 5000..5031: smooth modes / U(-1,1) alternating), "
                        "batched solve to %.0e; network trained on %d pairs" % (args.rtol, info["pairs"]),
            "training": info}
@@ -261,6 +345,8 @@ def bench_learned(dmg, L, dev, torch, args, w, info):
             dt = (time.perf_counter() - t0) / args.steps
             d = {"ms_to_rtol": round(1e3 * dt, 3), "cycles_min": min(cyc), "cycles_max": max(cyc),
                  "cycles_total": sum(cyc)}
+            if refs:
+                d["err_vs_oracle_sample"] = {"problem%d" % b: err_vs(us[b], r) for b, r in refs.items()}
             if mode == "learned":
                 used, off, qn, qp = B.net_stats()
                 d.update({"net_cycles": sum(used), "judge_switched_off": sum(off),
@@ -279,7 +365,7 @@ def bench_learned(dmg, L, dev, torch, args, w, info):
     return res
 
 
-def bench_learned3d(dmg, L, dev, torch, args):
+def bench_learned3d(dmg, L, dev, torch, args, with_oracle=False):
     """3D learned coarse correction: 10^4 pairs from 1250 plain FP64 solves
     of 129^3 problems (f seeds 1000..2249, 8 cycles each; the cut is the 9^3
     green grid), Adam on the GPU, then 8 held-out 129^3 problems (seeds
@@ -299,6 +385,11 @@ def bench_learned3d(dmg, L, dev, torch, args):
             "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]}
     del r, e
     fs = [torch.from_numpy(f).to(dev) for f in L.eval_problems(128, range(5000, 5008), dim=3)]
+    ref = None
+    if with_oracle:   # the oracle's FP64 solution of the last held-out problem
+        from oracle import oracle as O
+        fh = fs[-1].cpu().numpy()
+        ref = O.solve(0 * fh, fh, p=dmg.P3D_TUNED, rtol=args.rtol, max_cycles=60)[0]
     res = {"workload": "8 held-out 129^3 problems (f seeds 5000..5007), each solved to %.0e; network trained on "
                        "%d cut-level pairs" % (args.rtol, info["pairs"]), "training": info}
     for pname, prec in (("fp64", dmg.MG_FP64), ("fp32_refined", dmg.MG_FP32_REFINED)):
@@ -324,6 +415,8 @@ def bench_learned3d(dmg, L, dev, torch, args):
                     qp.append(d)
             torch.cuda.synchronize()
             d = {"ms_per_problem": round(1e3 * (time.perf_counter() - t0) / len(fs), 3), "cycles_total": cyc_tot}
+            if ref is not None:
+                d["err_vs_oracle_last_problem"] = err_vs(u, ref)
             if mode == "learned":
                 d.update({"net_cycles": used_tot, "judge_switched_off": off_tot,
                           "first_cycle_cut_ratio_net_median": float(sorted(qn)[len(qn) // 2]),
@@ -340,7 +433,7 @@ def bench_learned3d(dmg, L, dev, torch, args):
     return res
 
 
-def bench_cube(dmg, workloads, dev, torch, args):
+def bench_cube(dmg, workloads, dev, torch, args, ref=None):
     """3D unit cube 257^3 (h = 1/256), f ~ U(-1,1) (seed 3), tuned 3D
     parameters; FP64 against single-precision cycles, both to 1e-10."""
     n = 256
@@ -361,11 +454,28 @@ def bench_cube(dmg, workloads, dev, torch, args):
         dt = time.perf_counter() - t0
         res[name] = {"ms_to_rtol": round(1e3 * dt / args.steps, 3), "cycles": cyc,
                      "unknowns_cycles_per_s": (n - 1) ** 3 * cyc * args.steps / dt, "final_rel_res": rr}
+        if ref is not None:
+            res[name]["err_vs_oracle"] = err_vs(us[-1], ref)
+        if name == "fp64":
+            res["kernels3d"] = kernel_table(S, f, max(args.steps, 5), torch)
         log("  cube257 %s: %.3f ms, %d cycles" % (name, res[name]["ms_to_rtol"], cyc))
         S.close()
         del S, us
         torch.cuda.empty_cache()
     return res
+
+
+def oracle_solve_timed(O, f_host, p, rtol, runs):
+    """The CPU oracle's FP64 solve of one workload from u = 0, `runs` times:
+    (solution, cycles, median seconds, all times)."""
+    import numpy as np
+    times = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        uo, co, ro, ho, so = O.solve(np.zeros_like(f_host), f_host, p=p, rtol=rtol, max_cycles=60)
+        times.append(time.perf_counter() - t0)
+        assert so == O.OK, so
+    return uo, co, ro, float(np.median(times)), [round(t, 3) for t in times]
 
 
 def main():
@@ -375,8 +485,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--n", type=int, default=4096)
-    ap.add_argument("--family", type=int, default=3, help="kernel family for the roofline (3: finest Jacobi)")
-    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--family", type=int, default=-1,
+                    help="kernel family for the roofline (-1: the single-kernel family that takes the most time)")
+    ap.add_argument("--cpu-runs", type=int, default=3, help="oracle runs per CPU-baseline leg (median reported)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (CPU baseline and errors against it)")
     ap.add_argument("--no-extra", action="store_true", help="skip the batched and 3D workloads")
     ap.add_argument("--no-learned", action="store_true", help="skip training and the learned modes")
     ap.add_argument("--cube-only", action="store_true", help="only the 3D 257^3 workload (for profiling)")
@@ -428,10 +540,55 @@ def main():
                           "fourth_order_cube257": bench_fourth_order(dmg, f3, dev, torch, args)}), flush=True)
         return
 
+    # The CPU oracle first: its FP64 solutions are the references every GPU
+    # result's error is stated against, and its timings the CPU baseline.
+    refs = {}
+    cpu = None
+    if not args.no_cpu:
+        from oracle import oracle as O
+        O.build(force=False)
+        log("cpu oracle: FP64 solve of the %d^2 workload to %.0e, %d runs (single thread)" % (n + 1, args.rtol,
+                                                                                          args.cpu_runs))
+        uo, co, ro, med, times = oracle_solve_timed(O, f_host, (1.052,), args.rtol, args.cpu_runs)
+        refs["square"] = uo
+        legs = [{"workload": "2D %d^2 (this line's workload), FP64 solve to %.0e" % (n + 1, args.rtol),
+                 "cycles": co, "final_rel_res": ro, "median_s": round(med, 3), "runs_s": times,
+                 "unknowns_cycles_per_s": unknowns * co / med}]
+        cpu = {"value": unknowns * co / med, "unit": "unknowns*cycles/s", "cores": 1, "kind": "oracle",
+               "sample": "full FP64 solves of the %d^2 workload to %.0e (%d cycles), median of %d runs, one thread"
+                         % (n + 1, args.rtol, co, args.cpu_runs)}
+        if not args.no_extra:
+            f3_host = workloads.cube_uniform(256, seed=3)
+            log("cpu oracle: FP64 solve of the 257^3 workload, %d runs" % args.cpu_runs)
+            uo3, co3, ro3, med3, times3 = oracle_solve_timed(O, f3_host, dmg.P3D_TUNED, args.rtol, args.cpu_runs)
+            refs["cube"] = uo3
+            legs.append({"workload": "3D 257^3, f ~ U(-1,1) (seed 3), FP64 solve to %.0e" % args.rtol, "cycles": co3,
+                         "final_rel_res": ro3, "median_s": round(med3, 3), "runs_s": times3,
+                         "unknowns_cycles_per_s": 255 ** 3 * co3 / med3})
+            log("cpu oracle: fourth-order reference solutions (2D and 3D, untimed)")
+            refs["square_o4"] = O.solve(np.zeros_like(f_host), f_host, p=dmg.P2D_H4, rtol=args.rtol, max_cycles=60,
+                                        order=4)[0]
+            refs["cube_o4"] = O.solve(np.zeros_like(f3_host), f3_host, p=dmg.P3D_H4, rtol=args.rtol, max_cycles=60,
+                                      order=4)[0]
+            del f3_host
+        cpu.update(cpu_info())
+        cpu["legs"] = legs
+
     w_net = net_info = None
     if not args.no_learned:
         log("learned coarse correction: training pairs and training")
         w_net, net_info = train_net(dmg, learned, torch, log)
+
+    # per-family kernel times of the FP64 cycle; the roofline follows the
+    # single-kernel family (residual or finest Jacobi) that takes the most time
+    S = dmg.Solver(2, n, precision=dmg.MG_FP64, p=(1.052,), device=dev)
+    ktab = kernel_table(S, f, max(args.steps, 5), torch)
+    S.close()
+    del S
+    family = args.family
+    if family < 0:
+        single = [r for r in ktab if r["family_id"] in (dmg.MG_K_RESIDUAL, dmg.MG_K_FINEST)]
+        family = max(single, key=lambda r: r["us_per_cycle"])["family_id"]
 
     modes = {}
     roof = None
@@ -444,32 +601,36 @@ def main():
         S = dmg.Solver(2, n, precision=prec, p=(1.052,), device=dev)
         if name.startswith("learned"):
             S.set_coarse_net(w_net)
-        fam = args.family if name == "fp64" else None
+        fam = family if name == "fp64" else None
         log("mode %s: %d warmup + %d timed solves" % (name, args.warmup, args.steps))
         dt, cycles, kern, u_last, hist = timed_solves(S, f, args.steps, args.warmup, args.rtol, fam, torch)
         ms = 1e3 * dt / args.steps
         ucs = unknowns * sum(cycles) / dt
         modes[name] = {"ms_to_rtol": round(ms, 4), "cycles": cycles[-1], "unknowns_cycles_per_s": ucs,
                        "final_rel_res": hist[-1]}
+        if "square" in refs:
+            modes[name]["err_vs_oracle"] = err_vs(u_last, refs["square"])
         if name.startswith("learned"):
             used, off, qn, qp = S.net_stats()
             modes[name].update({"net_cycles": used, "judge_switched_off": off, "first_cycle_cut_ratio_net": qn,
                                 "first_cycle_cut_ratio_plain": qp})
-        log("  %s: %.3f ms per solve, %d cycles, %.3e unknowns*cycles/s" % (name, ms, cycles[-1], ucs))
+        log("  %s: %.3f ms per solve, %d cycles, %.3e unknowns*cycles/s%s"
+            % (name, ms, cycles[-1], ucs, ", error vs oracle %.2e" % modes[name]["err_vs_oracle"]["inf"]
+               if "err_vs_oracle" in modes[name] else ""))
         if name == "fp64":
             main_val, ms_per_step = ucs, ms
             kms, kcount, kbytes = kern
             # a solve also launches one gated no-op iteration after the last
             # cycle; bytes count only launches that ran (their few-us no-op
             # time stays in kms, so the figure errs low)
-            work = sum(cycles) + (args.steps if args.family == dmg.MG_K_RESIDUAL else 0)
+            work = sum(cycles) + (args.steps if family == dmg.MG_K_RESIDUAL else 0)
             if kcount > 0 and work > 0:
                 bpl = kbytes / kcount
                 achieved = bpl * work / (kms * 1e-3) / 1e9
-                traffic = measured_traffic(args.family)
+                traffic = measured_traffic(family)
                 roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                        "kernel": FAMILY_NAMES.get(args.family, str(args.family)),
+                        "kernel": FAMILY_KERNELS[2][family], "family": FAMILY_NAMES[family],
                         "bytes_per_launch": bpl, "us_per_launch": round(kms / work * 1e3, 2),
                         "launches": work, "launches_enqueued": kcount}
         S.close()
@@ -481,32 +642,20 @@ def main():
     extra = {}
     if not args.no_extra:
         log("fourth-order residual: direct and two-stage solves")
-        extra["fourth_order%d" % (n + 1)] = bench_fourth_order(dmg, f, dev, torch, args)
-        extra["batched512"] = bench_batched(dmg, workloads, dev, torch, args)
+        extra["fourth_order%d" % (n + 1)] = bench_fourth_order(dmg, f, dev, torch, args, refs.get("square_o4"))
+        extra["batched512"] = bench_batched(dmg, workloads, dev, torch, args, not args.no_cpu)
         if w_net is not None:
-            extra["learned1025"] = bench_learned(dmg, learned, dev, torch, args, w_net, net_info)
+            extra["learned1025"] = bench_learned(dmg, learned, dev, torch, args, w_net, net_info, not args.no_cpu)
             log("learned coarse correction in 3D: pairs, training, held-out solves")
-            extra["learned129_3d"] = bench_learned3d(dmg, learned, dev, torch, args)
-        extra["cube257"] = bench_cube(dmg, workloads, dev, torch, args)
+            extra["learned129_3d"] = bench_learned3d(dmg, learned, dev, torch, args, not args.no_cpu)
+        extra["cube257"] = bench_cube(dmg, workloads, dev, torch, args, refs.get("cube"))
         log("fourth-order residual in 3D: direct and two-stage solves")
         f3 = torch.from_numpy(workloads.cube_uniform(256, seed=3)).to(dev)
-        extra["fourth_order_cube257"] = bench_fourth_order(dmg, f3, dev, torch, args)
+        extra["fourth_order_cube257"] = bench_fourth_order(dmg, f3, dev, torch, args, refs.get("cube_o4"))
         log("over-relaxation re-tuned per size: 4097^2 and 257^3")
-        extra["retuned%d" % (n + 1)] = bench_retuned(dmg, f, dev, torch, args)
-        extra["retuned_cube257"] = bench_retuned(dmg, f3, dev, torch, args)
+        extra["retuned%d" % (n + 1)] = bench_retuned(dmg, f, dev, torch, args, refs.get("square"))
+        extra["retuned_cube257"] = bench_retuned(dmg, f3, dev, torch, args, refs.get("cube"))
         del f3
-
-    cpu = None
-    if not args.no_cpu:
-        from oracle import oracle as O
-        O.build(force=False)
-        log("cpu oracle: one FP64 solve of the same workload to %.0e (single thread)" % args.rtol)
-        t0 = time.perf_counter()
-        uo, co, ro, ho, so = O.solve(np.zeros_like(f_host), f_host, p=(1.052,), rtol=args.rtol, max_cycles=60)
-        dt = time.perf_counter() - t0
-        cpu = {"value": unknowns * co / dt, "unit": "unknowns*cycles/s", "cores": 1, "kind": "oracle",
-               "sample": "one full FP64 solve of the %d^2 workload to %.0e (%d cycles, %.2f s), one thread"
-                         % (n + 1, args.rtol, co, dt)}
 
     out = {"metric": METRIC, "value": main_val, "unit": "unknowns*cycles/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
@@ -514,7 +663,7 @@ def main():
            "config": {"workload": "2D unit square %dx%d (h=1/%d), f = 16 seeded sine modes + 1e-3 noise, "
                                   "p=1.052, solve from u=0 to %.0e rel. residual" % (n + 1, n + 1, n, args.rtol),
                       "unknowns": unknowns, "grid": n + 1, "rtol": args.rtol},
-           "modes": modes, "roofline": roof, "cpu_baseline": cpu}
+           "modes": modes, "roofline": roof, "kernels2d": ktab, "cpu_baseline": cpu}
     out.update(extra)
     print(json.dumps(out), flush=True)
 
