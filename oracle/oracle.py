@@ -65,11 +65,14 @@ def lib():
         L.orc_solve_ord.argtypes = [i, i, dp, i, i, dp, dp, d, i, ip, dp, dp]
         L.orc_vcycle_usual.argtypes = [i, i, d, i, i, dp, dp, dp, dp]
         L.orc_solve_usual.argtypes = [i, i, d, i, i, dp, dp, d, i, ip, dp, dp]
+        L.orc_cycle_gen.argtypes = [i, i, dp, i, i, i, i, dp, dp, dp, dp]
+        L.orc_solve_gen.argtypes = [i, i, dp, i, i, i, i, dp, dp, d, i, ip, dp, dp]
         L.orc_step_restrict.argtypes = [i, i, i, dp, dp]
         L.orc_step_jacobi.argtypes = [i, i, i, dp, dp, dp, dp]
         for fn in ("orc_residual", "orc_relres", "orc_vcycle", "orc_vcycle_trace", "orc_solve",
                    "orc_residual_ord", "orc_relres_ord", "orc_vcycle_ord_trace", "orc_solve_ord",
-                   "orc_step_restrict", "orc_step_jacobi", "orc_vcycle_usual", "orc_solve_usual"):
+                   "orc_step_restrict", "orc_step_jacobi", "orc_vcycle_usual", "orc_solve_usual",
+                   "orc_cycle_gen", "orc_solve_gen"):
             getattr(L, fn).restype = ctypes.c_int
         L.orc_net_forward.argtypes = [i, i, dp, dp, dp]
         L.orc_net_forward.restype = ctypes.c_int
@@ -188,6 +191,46 @@ def solve_two_stage(u, f, p2=None, p4=None, prec=0, rtol1=1e-6, rtol=1e-10, max_
     u, c1, _, _, _ = solve(u, f, p2, prec, rtol1, max_cycles, order=2)
     u, c2, rr, _, _ = solve(u, f, p4, prec, rtol, max_cycles, order=4)
     return u, c1, c2, rr
+
+
+# --------------------------- more sweeps per level and W-cycles (Section 4)
+
+def cycle_gen(u, f, p=None, nu=1, gamma=1, prec=0, order=2, trace=False):
+    """One cycle with nu red-black sweeps per level and gamma coarse visits
+    per group of levels (nu = gamma = 1: the V-cycle).  Returns the new u,
+    or (u, [r per level], [v per level]) with trace=True."""
+    dim, n = _dimn(u)
+    u = np.array(u, dtype=np.float64, order="C")
+    if not trace:
+        _chk(lib().orc_cycle_gen(dim, n, _ptr(_params(dim, p)), prec, order, nu, gamma, _ptr(u), _ptr(f), None, None),
+             "orc_cycle_gen")
+        return u
+    sides = level_sides(dim, n)
+    sizes = [(m + 1) ** dim for m in sides]
+    rt = np.zeros(sum(sizes))
+    vt = np.zeros(sum(sizes))
+    _chk(lib().orc_cycle_gen(dim, n, _ptr(_params(dim, p)), prec, order, nu, gamma, _ptr(u), _ptr(f), _ptr(rt),
+                             _ptr(vt)), "orc_cycle_gen")
+    rs, vs, off = [], [], 0
+    for m, s in zip(sides, sizes):
+        rs.append(rt[off:off + s].reshape((m + 1,) * dim))
+        vs.append(vt[off:off + s].reshape((m + 1,) * dim))
+        off += s
+    return u, rs, vs
+
+
+def solve_gen(u, f, p=None, nu=1, gamma=1, prec=0, rtol=1e-10, max_cycles=50, check=True, order=2):
+    """Returns (u, cycles, relres, history, status) of the nu / gamma cycle."""
+    dim, n = _dimn(u)
+    u = np.array(u, dtype=np.float64, order="C")
+    hist = np.zeros(max_cycles + 1)
+    cyc = ctypes.c_int()
+    rr = ctypes.c_double()
+    st = lib().orc_solve_gen(dim, n, _ptr(_params(dim, p)), prec, order, nu, gamma, _ptr(u), _ptr(f), rtol,
+                             max_cycles, ctypes.byref(cyc), ctypes.byref(rr), _ptr(hist))
+    if check and st not in (OK, ERR_NOT_CONVERGED):
+        raise OracleError(st, "orc_solve_gen")
+    return u, cyc.value, rr.value, hist[:cyc.value + 1], st
 
 
 # ----------------------------------------------- the conventional cycle

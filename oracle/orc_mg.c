@@ -324,6 +324,44 @@ int orc_solve(int dim, int n, const double *p, int prec, double *u, const double
     return orc_solve_ord(dim, n, p, prec, 2, u, f, rtol, max_cycles, cycles_out, relres_out, history);
 }
 
+/* More Jacobi sweeps per level (nu >= 1) and W-cycles (gamma = 2) on the
+ * diagonal hierarchy, the two directions Section 4 leaves to further
+ * research (readings in orc_mg_body.h); nu = gamma = 1 is the V-cycle. */
+int orc_cycle_gen(int dim, int n, const double *p, int prec, int order, int nu, int gamma, double *u, const double *f,
+                  double *rtrace, double *vtrace)
+{
+    int e = orc_check(dim, n);
+    if (e) return e;
+    if (!p || !u || !f || (prec != 0 && prec != 1) || (order != 2 && order != 4) || nu < 1 || nu > 16 ||
+        gamma < 1 || gamma > 2)
+        return ORC_ERR_ARG;
+    return prec == 0 ? cycle_gen(dim, n, order, p, nu, gamma, u, f, rtrace, vtrace)
+                     : cycle_gen_f32(dim, n, order, p, nu, gamma, u, f, rtrace, vtrace);
+}
+
+struct orc_gen_args {
+    struct orc_cycle_args c;
+    int nu, gamma;
+};
+
+static int orc_gen_cycle(const void *ctx, double *u, const double *f)
+{
+    const struct orc_gen_args *a = (const struct orc_gen_args *)ctx;
+    return orc_cycle_gen(a->c.dim, a->c.n, a->c.p, a->c.prec, a->c.order, a->nu, a->gamma, u, f, NULL, NULL);
+}
+
+int orc_solve_gen(int dim, int n, const double *p, int prec, int order, int nu, int gamma, double *u,
+                  const double *f, double rtol, int max_cycles, int *cycles_out, double *relres_out, double *history)
+{
+    int e = orc_check(dim, n);
+    if (e) return e;
+    if (!p || !u || !f || max_cycles < 0 || !(rtol >= 0) || (order != 2 && order != 4) || nu < 1 || nu > 16 ||
+        gamma < 1 || gamma > 2)
+        return ORC_ERR_ARG;
+    struct orc_gen_args a = {{dim, n, prec, order, p}, nu, gamma};
+    return orc_solve_loop(dim, n, order, u, f, rtol, max_cycles, cycles_out, relres_out, history, orc_gen_cycle, &a);
+}
+
 /* Single steps, for the tests that pin each equation on its own.
  * dim 2 restrict kind: 0 Eq. Erest2r (side m -> m), 1 Eq. Erest2b (m -> m/2).
  * dim 3 restrict kind: 0 Eq. Erred, 1 Eqs. Ermagc/Ermagm, 2 Eq. Erblu (m -> m/2).

@@ -537,3 +537,196 @@ done:
     free(rl); free(vl);
     return rc;
 }
+
+/* ------------------------------------------ more sweeps per level, W-cycles
+ * The paper leaves both to further research (Section 4: extra Jacobi
+ * iterations on each level of the diagonal hierarchy; W-cycles, with more
+ * scope there because the hierarchy has more levels).  Readings:
+ *  - nu >= 1 red-black iterations per level on the way up: the first as in
+ *    the V-cycle (first colour from the coarser level's values at the points
+ *    both levels share), each further one the same step with the level's own
+ *    current values at those points.  The red level's first colour also
+ *    reads the magenta cube centres, which are not red points: those keep
+ *    the values the magenta level handed up.
+ *  - gamma visits (1: V-cycle, 2: W-cycle) of the coarse correction per
+ *    group of levels (2D: axis -> diagonal -> axis of twice the stride; 3D:
+ *    green -> red -> magenta -> blue): after the first visit returns w, the
+ *    residual of the coarser axis (green) grid's own equation, r - A w with
+ *    the 5-point (7-point) Laplacian of that grid's spacing, goes through a
+ *    second visit whose correction is added to w.
+ */
+
+/* the coarse input of a further sweep on level d: the level's own values at
+ * the points it shares with the level below, in that level's layout */
+static void SFX(again_input)(int dim, int d, int m, const R *v, const R *vc_prev, R *out)
+{
+    if (dim == 2) {
+        if (d % 2 == 0) { memcpy(out, v, sizeof(R) * (size_t)(m + 1) * (size_t)(m + 1)); return; }
+        int mc = m / 2;
+        for (int B = 0; B <= mc; B++)
+            for (int A = 0; A <= mc; A++) out[I2(mc, A, B)] = v[I2(m, 2 * A, 2 * B)];
+        return;
+    }
+    int t = d % 3;
+    if (t == 0) { memcpy(out, v, sizeof(R) * SFX(vol3)(m)); return; }
+    if (t == 1) {   /* the magenta input with its corners replaced by the red level's own */
+        memcpy(out, vc_prev, sizeof(R) * SFX(vol3)(m));
+        for (int k = 0; k <= m; k += 2)
+            for (int j = 0; j <= m; j += 2)
+                for (int i = 0; i <= m; i += 2) out[I3(m, i, j, k)] = v[I3(m, i, j, k)];
+        return;
+    }
+    int mc = m / 2;
+    for (int C = 0; C <= mc; C++)
+        for (int B = 0; B <= mc; B++)
+            for (int A = 0; A <= mc; A++) out[I3(mc, A, B, C)] = v[I3(m, 2 * A, 2 * B, 2 * C)];
+}
+
+/* one red-black Jacobi step of level d from the coarse input vc */
+static void SFX(jac_step)(int dim, int n, int d, const int *ml, const double *p, const R *r, const R *vc, R *v)
+{
+    int m = ml[d];
+    double sh = (double)(n / m) * (1.0 / n);   /* sigma * h */
+    if (dim == 2) {
+        if (d % 2 == 0) SFX(jac2_axis)(m, (R)(p[0] * sh * sh), r, vc, v);
+        else SFX(jac2_diag)(m, (R)(2 * p[0] * sh * sh), r, vc, v);
+    } else {
+        if (d % 3 == 0) SFX(jac3_green)(m, (R)(p[3] * sh * sh), r, vc, v);
+        else if (d % 3 == 1) SFX(jac3_red)(m, (R)(2 * p[1] * sh * sh), (R)(4 * p[2] * sh * sh), r, vc, v);
+        else SFX(jac3_magenta)(m, (R)(4 * p[0] * sh * sh), r, vc, v);
+    }
+}
+
+static void SFX(restrict_step)(int dim, int d, const int *ml, const R *fine, R *coarse)
+{
+    if (dim == 2) {
+        if (d % 2 == 1) SFX(rs2_axis_to_diag)(ml[d - 1], fine, coarse);
+        else SFX(rs2_diag_to_axis)(ml[d - 1], fine, coarse);
+    } else {
+        if (d % 3 == 1) SFX(rs3_green_to_red)(ml[d - 1], fine, coarse);
+        else if (d % 3 == 2) SFX(rs3_red_to_magenta)(ml[d - 1], fine, coarse);
+        else SFX(rs3_magenta_to_blue)(ml[d - 1], fine, coarse);
+    }
+}
+
+/* r <- r - A w on the axis (green) grid of side m and spacing s */
+static void SFX(coarse_residual)(int dim, int m, double s, R *r, const R *w)
+{
+    R is2 = (R)(1.0 / (s * s));
+    if (dim == 2) {
+        for (int b = 1; b < m; b++)
+            for (int a = 1; a < m; a++) {
+                R lap = (w[I2(m, a - 1, b)] + w[I2(m, a, b - 1)] + w[I2(m, a + 1, b)] + w[I2(m, a, b + 1)]
+                         - 4 * w[I2(m, a, b)]) * is2;
+                r[I2(m, a, b)] = (R)(r[I2(m, a, b)] - lap);
+            }
+        return;
+    }
+    for (int k = 1; k < m; k++)
+        for (int j = 1; j < m; j++)
+            for (int i = 1; i < m; i++) {
+                R lap = (w[I3(m, i + 1, j, k)] + w[I3(m, i - 1, j, k)] + w[I3(m, i, j + 1, k)]
+                         + w[I3(m, i, j - 1, k)] + w[I3(m, i, j, k + 1)] + w[I3(m, i, j, k - 1)]
+                         - 6 * w[I3(m, i, j, k)]) * is2;
+                r[I3(m, i, j, k)] = (R)(r[I3(m, i, j, k)] - lap);
+            }
+}
+
+struct SFX(gen_state) {
+    int dim, n, D, nu, gamma;
+    const int *ml;
+    const double *p;
+    R **rl, **vl, **tsave_r, **tsave_v, **tq;
+    R *vz;
+};
+
+static size_t SFX(gen_count)(int dim, int m)
+{
+    return dim == 2 ? (size_t)(m + 1) * (size_t)(m + 1) : SFX(vol3)(m);
+}
+
+/* the correction of level d (an axis / green level) for the residual rl[d] */
+static void SFX(gen_group)(const struct SFX(gen_state) *S, int d)
+{
+    int dim = S->dim, g = dim;
+    if (d < S->D) {
+        for (int j = d + 1; j <= d + g; j++) SFX(restrict_step)(dim, j, S->ml, S->rl[j - 1], S->rl[j]);
+        SFX(gen_group)(S, d + g);
+        for (int k = 1; k < S->gamma; k++) {
+            int c = d + g;
+            size_t cnt = SFX(gen_count)(dim, S->ml[c]);
+            memcpy(S->tsave_r[c], S->rl[c], cnt * sizeof(R));
+            memcpy(S->tsave_v[c], S->vl[c], cnt * sizeof(R));
+            SFX(coarse_residual)(dim, S->ml[c], (double)(S->n / S->ml[c]) / S->n, S->rl[c], S->vl[c]);
+            SFX(gen_group)(S, c);
+            for (size_t q = 0; q < cnt; q++) S->vl[c][q] = (R)(S->tsave_v[c][q] + S->vl[c][q]);
+            memcpy(S->rl[c], S->tsave_r[c], cnt * sizeof(R));
+        }
+    }
+    int top = d < S->D ? d + g - 1 : d;
+    for (int j = top; j >= d; j--) {
+        const R *vc = (j == S->D) ? S->vz : S->vl[j + 1];
+        SFX(jac_step)(dim, S->n, j, S->ml, S->p, S->rl[j], vc, S->vl[j]);
+        for (int s = 1; s < S->nu; s++) {
+            SFX(again_input)(dim, j, S->ml[j], S->vl[j], vc, S->tq[j]);
+            SFX(jac_step)(dim, S->n, j, S->ml, S->p, S->rl[j], S->tq[j], S->vl[j]);
+        }
+    }
+}
+
+/* One cycle with nu sweeps per level and gamma coarse visits per group (nu =
+ * gamma = 1: the V-cycle above).  rtrace / vtrace as for the V-cycle (each
+ * level's arrays as the cycle leaves them). */
+static int SFX(cycle_gen)(int dim, int n, int order, const double *p, int nu, int gamma, double *u, const double *f,
+                          double *rtrace, double *vtrace)
+{
+    int K = orc_log2(n);
+    if (K < 1 || (dim != 2 && dim != 3) || nu < 1 || gamma < 1 || gamma > 2) return ORC_ERR_ARG;
+    int D = (dim == 2) ? 2 * (K - 1) : 3 * (K - 1);
+    R **rl = (R **)calloc((size_t)D + 1, sizeof(R *));
+    R **vl = (R **)calloc((size_t)D + 1, sizeof(R *));
+    R **t1 = (R **)calloc((size_t)D + 1, sizeof(R *));
+    R **t2 = (R **)calloc((size_t)D + 1, sizeof(R *));
+    R **tq = (R **)calloc((size_t)D + 1, sizeof(R *));
+    int *ml = (int *)calloc((size_t)D + 1, sizeof(int));
+    R *vz = (R *)calloc(27, sizeof(R));
+    int rc = ORC_OK;
+    if (!rl || !vl || !t1 || !t2 || !tq || !ml || !vz) { rc = ORC_ERR_ALLOC; goto done; }
+    for (int d = 0; d <= D; d++) {
+        ml[d] = n >> (d / dim);
+        size_t cnt = SFX(gen_count)(dim, ml[d]);
+        rl[d] = (R *)calloc(cnt, sizeof(R));
+        vl[d] = (R *)calloc(cnt, sizeof(R));
+        t1[d] = (R *)calloc(cnt, sizeof(R));
+        t2[d] = (R *)calloc(cnt, sizeof(R));
+        tq[d] = (R *)calloc(cnt, sizeof(R));
+        if (!rl[d] || !vl[d] || !t1[d] || !t2[d] || !tq[d]) { rc = ORC_ERR_ALLOC; goto done; }
+    }
+    {
+        size_t cnt = SFX(gen_count)(dim, n);
+        double *r0 = (double *)malloc(cnt * sizeof(double));
+        if (!r0) { rc = ORC_ERR_ALLOC; goto done; }
+        orc_residual_ord_core(dim, n, order, u, f, r0);
+        for (size_t q = 0; q < cnt; q++) rl[0][q] = (R)r0[q];
+        free(r0);
+        struct SFX(gen_state) S = {dim, n, D, nu, gamma, ml, p, rl, vl, t1, t2, tq, vz};
+        SFX(gen_group)(&S, 0);
+        for (size_t q = 0; q < cnt; q++) u[q] = u[q] + (double)vl[0][q];
+    }
+    if (rtrace || vtrace) {
+        size_t off = 0;
+        for (int d = 0; d <= D; d++) {
+            size_t cnt = SFX(gen_count)(dim, ml[d]);
+            for (size_t q = 0; q < cnt; q++) {
+                if (rtrace) rtrace[off + q] = (double)rl[d][q];
+                if (vtrace) vtrace[off + q] = (double)vl[d][q];
+            }
+            off += cnt;
+        }
+    }
+done:
+    if (rl && vl && t1 && t2 && tq)
+        for (int d = 0; d <= D; d++) { free(rl[d]); free(vl[d]); free(t1[d]); free(t2[d]); free(tq[d]); }
+    free(rl); free(vl); free(t1); free(t2); free(tq); free(ml); free(vz);
+    return rc;
+}
