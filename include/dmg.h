@@ -81,6 +81,23 @@ enum {
  * this flag, or a batch of more than one problem: MG_ERR_ARG. */
 enum { MG_ORDER4 = 0x100 };
 
+/* Flag OR-ed into `precision` of mg_workspace_bytes / mg_setup: the
+ * conventional V-cycle the paper compares its diagonal grids with (Sections
+ * 2.1-2.3 and 3.1-3.3; Tables tbl:2d, tbl:3d, tbl:3dopt, rows "usual") on
+ * the standard hierarchy of grids of spacing h, 2h, 4h, ... down to one
+ * interior node: the nine-point (2D) / 27-point (3D) full-weighting
+ * restriction (weights 4, 2, 1 over 16; 8, 4, 2, 1 over 64), and on the way
+ * up bilinear / trilinear interpolation of the coarse correction followed
+ * by one Jacobi iteration of Lap v = r in red-black order (the points with
+ * an odd index sum first, then the even ones from the new odd values), with
+ * one parameter on the residual term: np = 1 in 2D and 3D (p; the paper
+ * tunes 1.121 in 2D and p_g = 1.30 in 3D, 1.216 / 1.70 with MG_ORDER4).
+ * Levels: depth d = 0 .. log2(n) - 1 of side n >> d, natural arrays (for
+ * mg_level_get).  Combines with MG_FP64 / MG_FP32_REFINED and MG_ORDER4;
+ * single problems only (mg_setup), no learned correction, no two-stage
+ * solve (MG_ERR_ARG). */
+enum { MG_USUAL = 0x200 };
+
 typedef struct mg_plan mg_plan;
 
 /* Bytes of device workspace mg_setup needs for (dim, n, precision). */
@@ -124,6 +141,28 @@ int mg_solve(mg_plan *plan, double *u, const double *f, double rtol, int max_cyc
  * batched plans: MG_ERR_ARG.  Synchronises both plans' streams. */
 int mg_solve_two_stage(mg_plan *first, mg_plan *second, double *u, const double *f, double rtol1, double rtol,
                        int max_cycles, int *cycles1, int *cycles2, double *rel_res_out);
+
+/* Cycles with more Jacobi sweeps per level and W-cycles on the diagonal
+ * hierarchy, the two directions the paper leaves to further research
+ * (Section 4).  nu (1 .. 8): red-black iterations per level on the way up,
+ * the first as in the V-cycle, each further one the same step with the
+ * level's own values, at the points it shares with the level below, as the
+ * coarse input (the red level's step keeps the magenta cube centres).
+ * gamma (1 or 2): visits of each group's coarse correction (2D: axis ->
+ * diagonal -> axis of twice the stride; 3D: green -> red -> magenta ->
+ * blue); the second visit corrects the residual of the coarse axis (green)
+ * grid's own equation, r - A w with its 5-/7-point Laplacian, and its
+ * correction is added to w.  nu = gamma = 1 is the V-cycle (with one launch
+ * per level step instead of the fused kernels of mg_setup).  Other
+ * arguments, the use with mg_vcycle / mg_solve / mg_level_get /
+ * mg_timing_*, and mg_destroy as for mg_setup; no learned correction, no
+ * batching, no two-stage solve (MG_ERR_ARG).  Extra workspace: each level's
+ * further-sweep input (nu > 1), a finest-size correction array (nu > 1),
+ * and a saved residual and correction per coarse axis / green level
+ * (gamma = 2). */
+int mg_cycle_workspace_bytes(int dim, int n, int precision, int nu, int gamma, size_t *bytes);
+int mg_setup_cycle(mg_plan **out, int dim, int n, int precision, const double *p, int np, int nu, int gamma,
+                   void *workspace, size_t ws_bytes, void *hip_stream);
 
 /* Copy level `depth` of the last cycle into dst (device, (m+1)^dim doubles,
  * natural order, m = the level's side in units of its stride; points not on

@@ -4,6 +4,8 @@
 #include "dmg_net.hpp"
 #include "dmg_plan2d.hpp"
 #include "dmg_plan3d.hpp"
+#include "dmg_gen.hpp"
+#include "dmg_usual.hpp"
 
 #include <new>
 
@@ -13,8 +15,10 @@ struct mg_plan {
     int dim = 0;
     Plan2* p2 = nullptr;
     Plan3* p3 = nullptr;
+    PlanU* pu = nullptr;   // the conventional comparison cycle (MG_USUAL)
+    PlanG* pg = nullptr;   // the diagonal cycle with nu sweeps and gamma coarse visits
     int device = 0;
-    Timing* tm() { return p2 ? &p2->tm : &p3->tm; }
+    Timing* tm() { return p2 ? &p2->tm : p3 ? &p3->tm : pu ? &pu->tm : &pg->tm; }
 };
 
 namespace {
@@ -41,6 +45,8 @@ void free_plan(mg_plan* P)
     if (!P) return;
     if (P->p2) { plan2_destroy(*P->p2); delete P->p2; }
     if (P->p3) { plan3_destroy(*P->p3); delete P->p3; }
+    if (P->pu) { planu_destroy(*P->pu); delete P->pu; }
+    if (P->pg) { plang_destroy(*P->pg); delete P->pg; }
     delete P;
 }
 
@@ -83,6 +89,12 @@ int mg_workspace_bytes(int dim, int n, int precision, size_t* bytes)
     if (!bytes) return MG_ERR_ARG;
     int e = check_size(dim, n);
     if (e) return e;
+    if (precision & MG_USUAL) {
+        PlanU L;
+        if ((e = planu_layout(L, dim, n, precision, 1.0))) return e;
+        *bytes = L.total;
+        return MG_OK;
+    }
     if (dim == 2) {
         Plan2 L;
         if ((e = plan2_layout(L, 1, &n, precision, 1.0))) return e;
@@ -129,10 +141,24 @@ int mg_setup(mg_plan** out, int dim, int n, int precision, const double* p, int 
 {
     if (!out || !p) return MG_ERR_ARG;
     *out = nullptr;
-    if ((dim == 2 && np != 1) || (dim == 3 && np != 4)) return MG_ERR_ARG;
+    const bool usual = (precision & MG_USUAL) != 0;
+    if (usual ? np != 1 : ((dim == 2 && np != 1) || (dim == 3 && np != 4))) return MG_ERR_ARG;
     if (check_p(p, np)) return MG_ERR_ARG;
     int e = check_size(dim, n);
     if (e) return e;
+    if (usual) {
+        mg_plan* P = new (std::nothrow) mg_plan;
+        if (!P) return MG_ERR_ALLOC;
+        P->dim = dim;
+        P->pu = new (std::nothrow) PlanU;
+        if (!P->pu) { delete P; return MG_ERR_ALLOC; }
+        e = planu_layout(*P->pu, dim, n, precision, p[0]);
+        if (!e) e = planu_setup(*P->pu, workspace, ws_bytes, (hipStream_t)hip_stream);
+        if (e) { free_plan(P); return e; }
+        P->device = P->pu->device;
+        *out = P;
+        return MG_OK;
+    }
     if (dim == 2) return mg_setup_batched(out, 1, &n, precision, p[0], workspace, ws_bytes, hip_stream);
     mg_plan* P = new (std::nothrow) mg_plan;
     if (!P) return MG_ERR_ALLOC;
@@ -143,6 +169,39 @@ int mg_setup(mg_plan** out, int dim, int n, int precision, const double* p, int 
     if (!e) e = plan3_setup(*P->p3, workspace, ws_bytes, (hipStream_t)hip_stream);
     if (e) { free_plan(P); return e; }
     P->device = P->p3->device;
+    *out = P;
+    return MG_OK;
+}
+
+int mg_cycle_workspace_bytes(int dim, int n, int precision, int nu, int gamma, size_t* bytes)
+{
+    if (!bytes) return MG_ERR_ARG;
+    int e = check_size(dim, n);
+    if (e) return e;
+    PlanG L;
+    if ((e = plang_layout(L, dim, n, precision, nullptr, nu, gamma))) return e;
+    *bytes = L.total;
+    return MG_OK;
+}
+
+int mg_setup_cycle(mg_plan** out, int dim, int n, int precision, const double* p, int np, int nu, int gamma,
+                   void* workspace, size_t ws_bytes, void* hip_stream)
+{
+    if (!out || !p) return MG_ERR_ARG;
+    *out = nullptr;
+    if ((dim == 2 && np != 1) || (dim == 3 && np != 4)) return MG_ERR_ARG;
+    if (check_p(p, np)) return MG_ERR_ARG;
+    int e = check_size(dim, n);
+    if (e) return e;
+    mg_plan* P = new (std::nothrow) mg_plan;
+    if (!P) return MG_ERR_ALLOC;
+    P->dim = dim;
+    P->pg = new (std::nothrow) PlanG;
+    if (!P->pg) { delete P; return MG_ERR_ALLOC; }
+    e = plang_layout(*P->pg, dim, n, precision, p, nu, gamma);
+    if (!e) e = plang_setup(*P->pg, workspace, ws_bytes, (hipStream_t)hip_stream);
+    if (e) { free_plan(P); return e; }
+    P->device = P->pg->device;
     *out = P;
     return MG_OK;
 }
@@ -160,6 +219,8 @@ int mg_vcycle(mg_plan* P, double* u, const double* f, double* rel_res_before)
     if (!P || !u || !f) return MG_ERR_ARG;
     DevGuard g(P->device);
     if (!g.ok) return MG_ERR_HIP;
+    if (P->pu) return planu_vcycle(*P->pu, u, f, rel_res_before);
+    if (P->pg) return plang_vcycle(*P->pg, u, f, rel_res_before);
     if (P->p3) return plan3_vcycle(*P->p3, u, f, rel_res_before);
     if (P->p2->nprob != 1) return MG_ERR_ARG;
     return plan2_vcycle(*P->p2, &u, &f, rel_res_before);
@@ -181,6 +242,8 @@ int mg_solve(mg_plan* P, double* u, const double* f, double rtol, int max_cycles
     if (!P || !u || !f || !(rtol >= 0) || max_cycles < 0 || max_cycles > kMaxCycles) return MG_ERR_ARG;
     DevGuard g(P->device);
     if (!g.ok) return MG_ERR_HIP;
+    if (P->pu) return planu_solve(*P->pu, u, f, rtol, max_cycles, cycles_out, rel_res_out, history);
+    if (P->pg) return plang_solve(*P->pg, u, f, rtol, max_cycles, cycles_out, rel_res_out, history);
     if (P->p3) return plan3_solve(*P->p3, u, f, rtol, max_cycles, cycles_out, rel_res_out, history);
     if (P->p2->nprob != 1) return MG_ERR_ARG;
     return plan2_solve(*P->p2, &u, &f, rtol, max_cycles, cycles_out, rel_res_out, nullptr, history);
@@ -189,7 +252,7 @@ int mg_solve(mg_plan* P, double* u, const double* f, double rtol, int max_cycles
 int mg_solve_two_stage(mg_plan* first, mg_plan* second, double* u, const double* f, double rtol1, double rtol,
                        int max_cycles, int* cycles1, int* cycles2, double* rel_res_out)
 {
-    if (!first || !second || first == second) return MG_ERR_ARG;
+    if (!first || !second || first == second || first->pu || second->pu || first->pg || second->pg) return MG_ERR_ARG;
     auto shape = [](const mg_plan* P, int& dim, int& n, int& order, int& nprob) {
         dim = P->dim;
         n = P->p3 ? P->p3->n : P->p2->n[0];
@@ -255,6 +318,7 @@ int mg_set_coarse_net(mg_plan* P, const float* w, int cut_level)
     DevGuard g(P->device);
     if (!g.ok) return MG_ERR_HIP;
     if (P->p2) return plan2_set_net(*P->p2, w, cut_level);
+    if (!P->p3) return MG_ERR_ARG;
     return plan3_set_net(*P->p3, w, cut_level);
 }
 
@@ -264,6 +328,7 @@ int mg_net_stats(mg_plan* P, int* net_cycles, int* fell_back, double* q_net, dou
     DevGuard g(P->device);
     if (!g.ok) return MG_ERR_HIP;
     if (P->p2) return plan2_net_stats(*P->p2, net_cycles, fell_back, q_net, q_plain);
+    if (!P->p3) return MG_ERR_ARG;
     return plan3_net_stats(*P->p3, net_cycles, fell_back, q_net, q_plain);
 }
 
@@ -273,6 +338,7 @@ int mg_coarse_export(mg_plan* P, int level, double* dst)
     DevGuard g(P->device);
     if (!g.ok) return MG_ERR_HIP;
     if (P->p2) return plan2_coarse_export(*P->p2, level, dst);
+    if (!P->p3) return MG_ERR_ARG;
     return plan3_coarse_export(*P->p3, level, dst);
 }
 
@@ -281,6 +347,8 @@ int mg_level_get(mg_plan* P, int depth, int which, double* dst)
     if (!P || !dst) return MG_ERR_ARG;
     DevGuard g(P->device);
     if (!g.ok) return MG_ERR_HIP;
+    if (P->pu) return planu_level_get(*P->pu, depth, which, dst);
+    if (P->pg) return plang_level_get(*P->pg, depth, which, dst);
     return P->p3 ? plan3_level_get(*P->p3, depth, which, dst) : plan2_level_get(*P->p2, depth, which, dst);
 }
 

@@ -19,6 +19,7 @@ MG_ERR_NONFINITE, MG_ERR_DIVERGED, MG_ERR_NOT_CONVERGED, MG_ERR_SCRATCH = -6, -7
 MG_STATIC_SCRATCH_BYTES = 64 << 20
 MG_FP64, MG_FP32_REFINED = 0, 1
 MG_ORDER4 = 0x100   # OR-ed into the precision: fourth-order finest residual (Eqs. Efos2, Efos4)
+MG_USUAL = 0x200    # OR-ed into the precision: the conventional comparison cycle (Sections 2.1-2.3, 3.1-3.3)
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libdmg.so is not built (%s); run __graft_entry__.build() or "
@@ -58,6 +59,10 @@ _lib.mg_net_destroy.argtypes = [_vp]
 _lib.mg_set_coarse_net.argtypes = [_vp, _fp, ctypes.c_int]
 _lib.mg_net_stats.argtypes = [_vp, _ip, _ip, _dp, _dp]
 _lib.mg_coarse_export.argtypes = [_vp, ctypes.c_int, _vp]
+_lib.mg_cycle_workspace_bytes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(_sz)]
+_lib.mg_setup_cycle.argtypes = [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int,
+                                ctypes.c_int, ctypes.c_int, _vp, _sz, _vp]
 _lib.mg_vcycle_static.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, _vp, _vp, _dp, _vp]
 _lib.mg_strerror.argtypes = [ctypes.c_int]
 _lib.mg_strerror.restype = ctypes.c_char_p
@@ -66,7 +71,7 @@ for _f in ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_solve_
            "mg_solve_batched", "mg_vcycle_batched", "mg_autotune", "mg_net_weight_count", "mg_net_workspace_bytes",
            "mg_net_create", "mg_net_set_weights", "mg_net_get_weights", "mg_net_init", "mg_net_forward",
            "mg_net_loss_grad", "mg_net_train", "mg_net_destroy", "mg_set_coarse_net", "mg_net_stats",
-           "mg_coarse_export", "mg_vcycle_static"):
+           "mg_coarse_export", "mg_vcycle_static", "mg_cycle_workspace_bytes", "mg_setup_cycle"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_solve_two_stage", "mg_level_get", "mg_level_info",
@@ -74,7 +79,7 @@ EXPORTS = ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_solve_
            "mg_setup_batched", "mg_solve_batched", "mg_vcycle_batched", "mg_autotune", "mg_net_weight_count",
            "mg_net_workspace_bytes", "mg_net_create", "mg_net_set_weights", "mg_net_get_weights", "mg_net_init",
            "mg_net_forward", "mg_net_loss_grad", "mg_net_train", "mg_net_destroy", "mg_set_coarse_net",
-           "mg_net_stats", "mg_coarse_export", "mg_vcycle_static")
+           "mg_net_stats", "mg_coarse_export", "mg_vcycle_static", "mg_cycle_workspace_bytes", "mg_setup_cycle")
 
 MG_NET_CUT = 6
 NET_G = {2: 17, 3: 9}
@@ -118,6 +123,20 @@ def mg_setup(dim, n, precision, p, workspace_ptr, ws_bytes, stream_ptr):
     arr = (ctypes.c_double * len(p))(*[float(x) for x in p])
     _check(_lib.mg_setup(ctypes.byref(plan), dim, n, precision, arr, len(p), _vp(workspace_ptr), ws_bytes,
                          _vp(stream_ptr)), "mg_setup")
+    return plan
+
+
+def mg_cycle_workspace_bytes(dim, n, precision, nu, gamma):
+    out = _sz()
+    _check(_lib.mg_cycle_workspace_bytes(dim, n, precision, nu, gamma, ctypes.byref(out)), "mg_cycle_workspace_bytes")
+    return out.value
+
+
+def mg_setup_cycle(dim, n, precision, p, nu, gamma, workspace_ptr, ws_bytes, stream_ptr):
+    plan = _vp()
+    arr = (ctypes.c_double * len(p))(*[float(x) for x in p])
+    _check(_lib.mg_setup_cycle(ctypes.byref(plan), dim, n, precision, arr, len(p), nu, gamma, _vp(workspace_ptr),
+                               ws_bytes, _vp(stream_ptr)), "mg_setup_cycle")
     return plan
 
 
@@ -306,6 +325,8 @@ P2D_TUNED = (1.052,)                    # Section 2.4
 P2D_H4 = (1.20,)                        # Section 2.4: tuned for the fourth-order residual
 P3D_TUNED = (1.11, 1.42, 1.08, 0.99)    # Section 3.4, Table tbl:3dopt
 P3D_H4 = (0.91, 0.80, 0.70, 1.77)       # Section 3.4, Table tbl:3dopt: tuned for the fourth-order residual
+# the conventional cycle's one parameter as the paper tunes it (Tables tbl:2d, tbl:3dopt, rows "usual")
+P_USUAL = {(2, 2): (1.121,), (2, 4): (1.216,), (3, 2): (1.30,), (3, 4): (1.70,)}
 
 
 class Solver:
@@ -314,26 +335,43 @@ class Solver:
     u, f: float64 CUDA tensors of shape (n+1,)*dim, contiguous (x fastest).
     """
 
-    def __init__(self, dim, n, precision=MG_FP64, p=None, device=None, stream=None, order=2):
+    def __init__(self, dim, n, precision=MG_FP64, p=None, device=None, stream=None, order=2, scheme="diagonal",
+                 nu=None, gamma=None):
         if order not in (2, 4):
             raise ValueError("order must be 2 or 4")
+        if scheme not in ("diagonal", "usual"):
+            raise ValueError("scheme must be 'diagonal' or 'usual'")
         if p is None:
-            if order == 4:
+            if scheme == "usual":
+                p = P_USUAL[(dim, order)]
+            elif order == 4:
                 p = P2D_H4 if dim == 2 else P3D_H4
             else:
                 p = P2D_TUNED if dim == 2 else P3D_TUNED
         self.dim, self.n, self.precision, self.p = dim, n, precision, tuple(float(x) for x in p)
         self.order = order
-        precision = precision | (MG_ORDER4 if order == 4 else 0)
+        self.scheme = scheme
+        # nu / gamma given: the generalised diagonal cycle (mg_setup_cycle)
+        self.general = nu is not None or gamma is not None
+        self.nu, self.gamma = int(nu or 1), int(gamma or 1)
+        if self.general and scheme != "diagonal":
+            raise ValueError("nu / gamma apply to the diagonal scheme")
+        precision = precision | (MG_ORDER4 if order == 4 else 0) | (MG_USUAL if scheme == "usual" else 0)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        self.ws_bytes = mg_workspace_bytes(dim, n, precision)
+        self.ws_bytes = (mg_cycle_workspace_bytes(dim, n, precision, self.nu, self.gamma) if self.general
+                         else mg_workspace_bytes(dim, n, precision))
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
             self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
             base = self.ws.data_ptr()
             self._ws_ptr = (base + 255) // 256 * 256
-            self.plan = mg_setup(dim, n, precision, self.p, self._ws_ptr, self.ws_bytes, self.stream.cuda_stream)
-        self.num_levels = mg_level_info(dim, n)[0]
+            if self.general:
+                self.plan = mg_setup_cycle(dim, n, precision, self.p, self.nu, self.gamma, self._ws_ptr, self.ws_bytes,
+                                           self.stream.cuda_stream)
+            else:
+                self.plan = mg_setup(dim, n, precision, self.p, self._ws_ptr, self.ws_bytes, self.stream.cuda_stream)
+        # the usual hierarchy has the grids of side n, n/2, ..., 2
+        self.num_levels = n.bit_length() - 1 if scheme == "usual" else mg_level_info(dim, n)[0]
 
     def _chk(self, t, name):
         if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
@@ -352,7 +390,7 @@ class Solver:
         return mg_solve(self.plan, u.data_ptr(), f.data_ptr(), rtol, max_cycles)
 
     def level(self, depth, which=0):
-        side = mg_level_info(self.dim, self.n, depth)[1]
+        side = self.n >> depth if self.scheme == "usual" else mg_level_info(self.dim, self.n, depth)[1]
         out = torch.empty((side + 1,) * self.dim, dtype=torch.float64, device=self.device)
         mg_level_get(self.plan, depth, which, out.data_ptr())
         return out

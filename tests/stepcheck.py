@@ -92,3 +92,41 @@ def check_fp32_cycle(orc, dim, n, p, u0, f, ug, gr, gv, order=2):
         assert err <= bound, ("v", d, err, bound)
         worst = max(worst, err / bound)
     return worst
+
+
+def check_fp32_cycle_usual(orc, dim, n, p, u0, f, ug, gr, gv, order=2):
+    """The same per-step check for the conventional cycle (full weighting,
+    interpolation plus one red-black Jacobi iteration; levels of side n >> d).
+    The bounds are those above: the full weighting has positive weights
+    summing to 1 (at most 27 terms; its running sums round to at most ~4 eps32
+    of the largest input), and an up step's interpolated values are means of
+    coarse values, so they never exceed max|v_{d+1}|."""
+    D = len(gr) - 1
+    worst = 0.0
+    r0 = orc.residual(u0, f, order=order)
+    sten = 2 * dim + 4 if order == 2 else (40 if dim == 2 else 60)
+    b0 = EPS32 * np.abs(r0).max() + 64 * EPS64 * (np.abs(f).max() + sten * np.abs(u0).max() * n * n)
+    e0 = np.abs(gr[0] - r0).max()
+    assert e0 <= b0, ("r", 0, e0, b0)
+    worst = max(worst, e0 / b0)
+    rk = 2 if dim == 2 else 3
+    for d in range(1, D + 1):
+        ref = orc.step_restrict(dim, rk, gr[d - 1])
+        bound = 16 * EPS32 * np.abs(gr[d - 1]).max() + 1e-300
+        err = np.abs(gr[d] - ref).max()
+        assert err <= bound, ("r", d, err, bound)
+        worst = max(worst, err / bound)
+    for d in range(D, -1, -1):
+        m = n >> d
+        c = _f32(p * ((1 << d) / n) ** 2)
+        vc = np.zeros((m // 2 + 1,) * dim) if d == D else gv[d]
+        ref = orc.step_jacobi(dim, rk, [c], gr[d], vc)
+        got = gv[d - 1] if d >= 1 else ug - u0
+        bound = 16 * EPS32 * (np.abs(vc).max() + abs(c) * np.abs(gr[d]).max() + np.abs(ref).max())
+        if d == 0:
+            bound += 4 * EPS64 * np.abs(ug).max()
+        bound += 1e-300
+        err = np.abs(got - ref).max()
+        assert err <= bound, ("v", d, err, bound)
+        worst = max(worst, err / bound)
+    return worst

@@ -48,3 +48,29 @@ def test_step_bound_catches_small_level_errors(orc, dim, n):
             tgt[d][c] += 400 * stepcheck.EPS32 * scale
             with pytest.raises(AssertionError):
                 stepcheck.check_fp32_cycle(orc, dim, n, P[dim], u0, f, uo, rs2, vs2[1:])
+
+
+@pytest.mark.parametrize("dim,n,order", [(2, 2, 2), (2, 64, 2), (2, 32, 4), (3, 2, 2), (3, 16, 2), (3, 8, 4)])
+def test_oracle_single_usual_cycle_meets_the_step_bound(orc, dim, n, order):
+    u0, f = rand_u(dim, n, 13 + n), W.uniform(dim, n, 14 + n)
+    p = 1.121 if dim == 2 else 1.30
+    uo, rs, vs = orc.vcycle_usual_trace(u0, f, p, prec=1, order=order)
+    worst = stepcheck.check_fp32_cycle_usual(orc, dim, n, p, u0, f, uo, rs, vs[1:], order=order)
+    assert worst <= 1.0
+    if n > 2:
+        assert worst > 1e-3, worst
+
+
+def test_usual_step_bound_catches_small_level_errors(orc):
+    dim, n, p = 2, 32, 1.121
+    u0, f = rand_u(dim, n, 17), W.uniform(dim, n, 18)
+    uo, rs, vs = orc.vcycle_usual_trace(u0, f, p, prec=1)
+    for d in (1, 2, len(rs) - 1):
+        for which in ("r", "v"):
+            rs2 = [a.copy() for a in rs]
+            vs2 = [a.copy() for a in vs]
+            tgt = rs2 if which == "r" else vs2
+            scale = np.abs(rs[d - 1] if which == "r" else (vs[d + 1] if d + 1 < len(vs) else rs[d])).max()
+            tgt[d][1, 1] += 400 * stepcheck.EPS32 * max(scale, np.abs(tgt[d]).max())
+            with pytest.raises(AssertionError):
+                stepcheck.check_fp32_cycle_usual(orc, dim, n, p, u0, f, uo, rs2, vs2[1:])
