@@ -40,13 +40,16 @@ def tail_factor(norms, tail):
     return float((r[-1] / r[-1 - tail]) ** (1.0 / tail))
 
 
-def gpu_factor(dim, n, p, precision=D.MG_FP64, cycles=30, tail=10, seed=0, device=None):
-    """Factor of the cycle with parameters p on the GPU (see the module text)."""
+def gpu_factor(dim, n, p, precision=D.MG_FP64, cycles=30, tail=10, seed=0, device=None, nu=None, gamma=None,
+               scheme="diagonal"):
+    """Factor of the cycle with parameters p on the GPU (see the module text);
+    nu / gamma: the generalised diagonal cycle; scheme "usual": the
+    conventional comparison cycle."""
     import torch
 
     if not 1 <= tail <= cycles:
         raise ValueError("need 1 <= tail <= cycles")
-    S = D.Solver(dim, n, precision=precision, p=p, device=device)
+    S = D.Solver(dim, n, precision=precision, p=p, device=device, nu=nu, gamma=gamma, scheme=scheme)
     try:
         u = torch.from_numpy(W.uniform(dim, n, seed)).to(S.device)
         f = torch.zeros_like(u)
@@ -56,7 +59,8 @@ def gpu_factor(dim, n, p, precision=D.MG_FP64, cycles=30, tail=10, seed=0, devic
     return tail_factor(norms, tail)
 
 
-def tune_p(dim, n, p0=None, precision=D.MG_FP64, cycles=30, tail=10, seed=0, maxfev=200, device=None):
+def tune_p(dim, n, p0=None, precision=D.MG_FP64, cycles=30, tail=10, seed=0, maxfev=200, device=None, nu=None,
+           gamma=None):
     """Parameters minimising the GPU cycle's factor at this size, from p0
     (default: the paper's tuned values).  Returns (p, factor, evaluations)."""
     if p0 is None:
@@ -65,6 +69,6 @@ def tune_p(dim, n, p0=None, precision=D.MG_FP64, cycles=30, tail=10, seed=0, max
     def factor(p):
         if min(p) <= 0:
             return 1e3   # outside the parameters' domain
-        return gpu_factor(dim, n, p, precision, cycles, tail, seed, device)
+        return gpu_factor(dim, n, p, precision, cycles, tail, seed, device, nu, gamma)
 
     return nelder_mead(factor, p0, maxfev=maxfev)
