@@ -42,6 +42,8 @@ FAMILY_NAMES = {0: "residual", 1: "restriction", 2: "jacobi", 3: "finest jacobi 
                 5: "norm"}
 # the kernels of each family, as rocprofv3 names them
 FAMILY_KERNELS = {
+    "usual": {0: "k_residual", 1: "ku2_fw / ku3_fw (full weighting)", 2: "ku2_up / ku3_up (interpolation + red-black Jacobi)",
+              3: "ku2_up / ku3_up, finest (u += v)", 4: "-", 5: "k_finalize"},
     2: {0: "kb_resid (r0, Eq. Erest2r onto r1, Eq. Erest2b onto r2, norm partials)",
         1: "kb_rs_pair, kb_mid_down, kb_rs_*",
         2: "kb_jac_pair, kb_mid_up, kb_jac_*",
@@ -98,7 +100,8 @@ def kernel_table(S, f, cycles, torch):
         if cnt == 0:
             continue
         gbs = byt / (ms * 1e-3) / 1e9
-        rows.append({"family": FAMILY_NAMES[fam], "kernels": FAMILY_KERNELS[f.dim()][fam],
+        key = "usual" if getattr(S, "scheme", "diagonal") == "usual" else f.dim()
+        rows.append({"family": FAMILY_NAMES[fam], "kernels": FAMILY_KERNELS[key][fam],
                      "us_per_cycle": round(1e3 * ms / cycles, 2), "launches_per_cycle": cnt / cycles,
                      "bytes_per_cycle": byt / cycles, "achieved_GBs": round(gbs, 1),
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "family_id": fam})
@@ -235,6 +238,80 @@ def bench_retuned(dmg, f, dev, torch, args, ref=None):
     log("  retuned p %s (factor %.4f vs %.4f, %d evaluations, %.1f s): %.3f ms (%d cycles) vs %.3f ms (%d cycles)"
         % (out["p"], fac, out["paper_factor"], nfev, tune_s, out["retuned_p_fp64"]["ms_to_rtol"],
            out["retuned_p_fp64"]["cycles"], out["paper_p_fp64"]["ms_to_rtol"], out["paper_p_fp64"]["cycles"]))
+    return out
+
+
+def bench_usual(dmg, f, dev, torch, args, diag, ref=None):
+    """The conventional comparison cycle (Sections 2.1-2.3, 3.1-3.3: full
+    weighting, linear interpolation plus one red-black Jacobi iteration, the
+    parameter the paper tunes for it) on the same workload to the same
+    tolerance, FP64 and FP32-refined, against the diagonal cycle's times
+    `diag` ({form: ms}) measured on the same GPU: the paper's claim that the
+    diagonal grids are about twice as fast (Abstract, Sections 2.3, 3.4)."""
+    dim, n = f.dim(), f.shape[0] - 1
+    out = {}
+    for pname, prec in (("fp64", dmg.MG_FP64), ("fp32_refined", dmg.MG_FP32_REFINED)):
+        S = dmg.Solver(dim, n, precision=prec, scheme="usual", device=dev)
+        dt, cycles, _, u_last, hist = timed_solves(S, f, args.steps, args.warmup, args.rtol, None, torch)
+        ms = 1e3 * dt / args.steps
+        d = {"ms_to_rtol": round(ms, 4), "cycles": cycles[-1], "p": S.p[0], "final_rel_res": hist[-1],
+             "unknowns_cycles_per_s": (n - 1) ** dim * sum(cycles) / dt}
+        if ref is not None:
+            d["err_vs_oracle"] = err_vs(u_last, ref)
+        if pname in diag:
+            d["diagonal_ms_to_rtol"] = diag[pname]
+            d["diagonal_speedup"] = round(ms / diag[pname], 3)
+        if pname == "fp64":
+            out["kernels"] = kernel_table(S, f, max(args.steps, 5), torch)
+        out[pname] = d
+        log("  usual %dD %s: %.3f ms, %d cycles (diagonal %s ms)" % (dim, pname, ms, cycles[-1], diag.get(pname)))
+        S.close()
+        del S
+        torch.cuda.empty_cache()
+    return out
+
+
+CYCLE_SHAPES = ((1, 1), (2, 1), (3, 1), (1, 2), (2, 2))
+
+
+def bench_cycles(dmg, f, dev, torch, args, v_ms, ref=None):
+    """More Jacobi sweeps per level (nu) and W-cycles (gamma = 2), the
+    directions Section 4 leaves to further research, on the same workload:
+    FP64 time to 1e-10, cycles, the cycle's asymptotic factor (power
+    iteration, f = 0) and the error against the oracle, for each (nu, gamma)
+    through the per-level launches of mg_setup_cycle; (1, 1) there is the
+    V-cycle without the fused kernels, so the ratios to it isolate the
+    algorithm and the ratio to v_ms (the fused V-cycle) the whole cost.  The
+    parameters are the paper's (tuned for nu = gamma = 1); nu = 2 is also run
+    with parameters re-tuned for it at this size."""
+    from paper_math_9907190_amd import tune
+
+    dim, n = f.dim(), f.shape[0] - 1
+    paper = dmg.P2D_TUNED if dim == 2 else dmg.P3D_TUNED
+    out = {"fused_v_cycle_ms": v_ms}
+    runs = [(nu, g, paper) for nu, g in CYCLE_SHAPES]
+    t0 = time.perf_counter()
+    p2, fac2, nfev = tune.tune_p(dim, n, p0=paper, device=dev, maxfev=30 if dim == 2 else 80, nu=2, gamma=1)
+    out["retuned_nu2"] = {"p": [round(x, 4) for x in p2], "factor": round(fac2, 5), "evaluations": nfev,
+                          "tune_s": round(time.perf_counter() - t0, 2)}
+    runs.append((2, 1, p2))
+    for nu, g, p in runs:
+        key = "nu%d_gamma%d%s" % (nu, g, "" if p is paper else "_retuned")
+        S = dmg.Solver(dim, n, p=p, device=dev, nu=nu, gamma=g)
+        dt, cycles, _, u_last, hist = timed_solves(S, f, args.steps, args.warmup, args.rtol, None, torch)
+        S.close()
+        d = {"ms_to_rtol": round(1e3 * dt / args.steps, 4), "cycles": cycles[-1], "final_rel_res": hist[-1],
+             "factor": round(tune.gpu_factor(dim, n, p, device=dev, nu=nu, gamma=g), 5)}
+        if ref is not None:
+            d["err_vs_oracle"] = err_vs(u_last, ref)
+        out[key] = d
+        torch.cuda.empty_cache()
+    base = out["nu1_gamma1"]["ms_to_rtol"]
+    for k, d in out.items():
+        if k.startswith("nu"):
+            d["time_vs_nu1_gamma1"] = round(d["ms_to_rtol"] / base, 3)
+            d["time_vs_fused_v_cycle"] = round(d["ms_to_rtol"] / v_ms, 3)
+            log("  %dD %s: %.3f ms, %d cycles, factor %.4f" % (dim, k, d["ms_to_rtol"], d["cycles"], d["factor"]))
     return out
 
 
@@ -640,6 +717,12 @@ def main():
         modes[k]["speedup_vs_fp64"] = round(modes["fp64"]["ms_to_rtol"] / modes[k]["ms_to_rtol"], 3)
 
     extra = {}
+    log("conventional comparison cycle on the same workload")
+    extra["usual%d" % (n + 1)] = bench_usual(dmg, f, dev, torch, args,
+                                             {k: modes[k]["ms_to_rtol"] for k in ("fp64", "fp32_refined")},
+                                             refs.get("square"))
+    log("more sweeps per level and W-cycles on the same workload")
+    extra["cycles%d" % (n + 1)] = bench_cycles(dmg, f, dev, torch, args, modes["fp64"]["ms_to_rtol"], refs.get("square"))
     if not args.no_extra:
         log("fourth-order residual: direct and two-stage solves")
         extra["fourth_order%d" % (n + 1)] = bench_fourth_order(dmg, f, dev, torch, args, refs.get("square_o4"))
@@ -649,6 +732,15 @@ def main():
             log("learned coarse correction in 3D: pairs, training, held-out solves")
             extra["learned129_3d"] = bench_learned3d(dmg, learned, dev, torch, args, not args.no_cpu)
         extra["cube257"] = bench_cube(dmg, workloads, dev, torch, args, refs.get("cube"))
+        f3 = torch.from_numpy(workloads.cube_uniform(256, seed=3)).to(dev)
+        log("conventional comparison cycle on the cube")
+        extra["usual_cube257"] = bench_usual(dmg, f3, dev, torch, args,
+                                             {k: extra["cube257"][k]["ms_to_rtol"] for k in ("fp64", "fp32_refined")},
+                                             refs.get("cube"))
+        log("more sweeps per level and W-cycles on the cube")
+        extra["cycles_cube257"] = bench_cycles(dmg, f3, dev, torch, args, extra["cube257"]["fp64"]["ms_to_rtol"],
+                                               refs.get("cube"))
+        del f3
         log("fourth-order residual in 3D: direct and two-stage solves")
         f3 = torch.from_numpy(workloads.cube_uniform(256, seed=3)).to(dev)
         extra["fourth_order_cube257"] = bench_fourth_order(dmg, f3, dev, torch, args, refs.get("cube_o4"))
