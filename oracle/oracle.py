@@ -78,6 +78,8 @@ def lib():
         L.orc_net_forward.restype = ctypes.c_int
         L.orc_net_loss_grad.argtypes = [i, i, dp, dp, dp, dp]
         L.orc_net_loss_grad.restype = ctypes.c_double
+        L.orc_net_judge_loss_grad.argtypes = [i, i, dp, dp, d, dp]
+        L.orc_net_judge_loss_grad.restype = ctypes.c_double
         L.orc_net_adam.argtypes = [i, dp, dp, dp, dp, i, d, d, d, d]
         L.orc_net_adam.restype = None
         _lib = L
@@ -340,6 +342,21 @@ def net_loss_grad(inp, target, w):
     loss = lib().orc_net_loss_grad(dim, inp.shape[0], _ptr(inp), _ptr(target), _ptr(w), _ptr(grad))
     if not np.isfinite(loss):
         raise OracleError(-1, "orc_net_loss_grad")
+    return loss, grad
+
+
+def net_judge_loss_grad(inp, w, pj):
+    """(loss, dloss/dw) of the cut-level objective: the network output at the
+    even points goes through the cut level's own red-black Jacobi step (its
+    parameter pj) and the loss is the mean squared residual of that level's
+    equation, rho = x - L v (spacing 1, the network's units)."""
+    inp = np.ascontiguousarray(inp, dtype=np.float64)
+    dim = inp.ndim - 1
+    w = np.ascontiguousarray(w, dtype=np.float64).reshape(net_shape(dim))
+    grad = np.zeros(net_shape(dim))
+    loss = lib().orc_net_judge_loss_grad(dim, inp.shape[0], _ptr(inp), _ptr(w), float(pj), _ptr(grad))
+    if not np.isfinite(loss):
+        raise OracleError(-1, "orc_net_judge_loss_grad")
     return loss, grad
 
 

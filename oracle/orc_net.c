@@ -17,7 +17,8 @@
  *          layer 0 reads only cin 0, layer 3 writes only cout 0;
  *   y_{l+1}(p, co) = sum_t sum_ci y_l(p + off(t), ci) w[l][t][ci][co] at
  *          interior p, then ReLU for l < 3; y_0 = input in channel 0;
- *   loss = mean over samples and interior points of (y_4(p, 0) - target)^2.
+ *   loss = mean over samples and interior points of (y_4(p, 0) - target)^2,
+ *          or the cut-level objective of orc_net_judge_loss_grad.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -98,6 +99,28 @@ int orc_net_forward(int dim, int B, const double *in, const double *w, double *o
     return 0;
 }
 
+/* index-sum parity of grid point q */
+static int parity(const Geo *g, int q)
+{
+    int G = g->G;
+    return (q % G + (q / G) % G + q / (G * G)) & 1;
+}
+
+/* sum over the 2 dim axis neighbours of q of a[nb] (0 outside the interior) */
+static double axis_sum(const Geo *g, const double *a, int q)
+{
+    int st[3] = {1, g->G, g->G * g->G};
+    double s = 0;
+    for (int ax = 0; ax < g->dim; ax++)
+        for (int sg = -1; sg <= 1; sg += 2) {
+            int nb = q + sg * st[ax];
+            if (interior(g, nb)) s += a[nb];
+        }
+    return s;
+}
+
+static void backward(const Geo *g, int B, const double *act, const double *w, double *dY, double *grad);
+
 /* loss (mean squared error over samples and interior points) and its
  * gradient with respect to w (same layout); returns NaN on bad arguments */
 double orc_net_loss_grad(int dim, int B, const double *in, const double *target, const double *w,
@@ -106,11 +129,9 @@ double orc_net_loss_grad(int dim, int B, const double *in, const double *target,
     Geo g;
     if (geo(dim, &g) || B < 1) return NAN;
     size_t per = (size_t)B * g.pts * C;
-    size_t WL = (size_t)g.T * C * C;
     double *act = forward(&g, B, in, w);
     double *dY = (double *)calloc(per, sizeof(double));
-    double *dX = (double *)calloc(per, sizeof(double));
-    if (!act || !dY || !dX) { free(act); free(dY); free(dX); return NAN; }
+    if (!act || !dY) { free(act); free(dY); return NAN; }
     int G2 = g.G - 2;
     double cnt = (double)B * G2 * G2 * (dim == 3 ? G2 : 1);
     double loss = 0;
@@ -123,6 +144,93 @@ double orc_net_loss_grad(int dim, int B, const double *in, const double *target,
             dY[s * C] = 2 * e / cnt;
         }
     loss /= cnt;
+    backward(&g, B, act, w, dY, grad);
+    free(act);
+    free(dY);
+    return loss;
+}
+
+/* The objective the coarse kernel judges the network by: the network output
+ * y, taken at the points of the cut level that it shares with the level
+ * below (index sum even), goes through that level's own red-black Jacobi
+ * step for Lap v = x with the residual weighted by pj (its over-relaxation
+ * parameter; x the network input, all in the network's units, spacing 1):
+ * first the odd points v = (sum of the 2 dim neighbours' y - pj x) / (2 dim),
+ * then the even ones from the new odd values; the loss is the mean over
+ * samples and interior points of rho^2, rho = x - (sum of neighbours' v - 2 dim
+ * v), i.e. the squared reduction of the cut level's residual norm when x is
+ * normalised to unit rms.  Gradient by the chain rule through the step (a
+ * linear map) and the network. */
+double orc_net_judge_loss_grad(int dim, int B, const double *in, const double *w, double pj, double *grad)
+{
+    Geo g;
+    if (geo(dim, &g) || B < 1) return NAN;
+    size_t per = (size_t)B * g.pts * C;
+    double *act = forward(&g, B, in, w);
+    double *dY = (double *)calloc(per, sizeof(double));
+    double *y = (double *)calloc((size_t)g.pts, sizeof(double));
+    double *v = (double *)calloc((size_t)g.pts, sizeof(double));
+    double *rho = (double *)calloc((size_t)g.pts, sizeof(double));
+    double *dv = (double *)calloc((size_t)g.pts, sizeof(double));
+    double *dvf = (double *)calloc((size_t)g.pts, sizeof(double));
+    if (!act || !dY || !y || !v || !rho || !dv || !dvf) {
+        free(act); free(dY); free(y); free(v); free(rho); free(dv); free(dvf);
+        return NAN;
+    }
+    int G2 = g.G - 2;
+    double cnt = (double)B * G2 * G2 * (dim == 3 ? G2 : 1), d2 = 2.0 * dim;
+    double loss = 0;
+    for (int b = 0; b < B; b++) {
+        const double *x = in + (size_t)b * g.pts;
+        for (int q = 0; q < g.pts; q++) {
+            y[q] = (interior(&g, q) && !parity(&g, q)) ? act[per * NL + ((size_t)b * g.pts + q) * C] : 0.0;
+            v[q] = rho[q] = dv[q] = dvf[q] = 0.0;
+        }
+        for (int q = 0; q < g.pts; q++)   /* odd points from the network's even values */
+            if (interior(&g, q) && parity(&g, q)) v[q] = (axis_sum(&g, y, q) - pj * x[q]) / d2;
+        for (int q = 0; q < g.pts; q++)   /* even points from the new odd values */
+            if (interior(&g, q) && !parity(&g, q)) v[q] = (axis_sum(&g, v, q) - pj * x[q]) / d2;
+        for (int q = 0; q < g.pts; q++)
+            if (interior(&g, q)) {
+                rho[q] = x[q] - (axis_sum(&g, v, q) - d2 * v[q]);
+                loss += rho[q] * rho[q];
+            }
+        /* d loss / d v = -L (2 rho / cnt): L is symmetric with the zero boundary */
+        for (int q = 0; q < g.pts; q++)
+            if (interior(&g, q)) dv[q] = -(axis_sum(&g, rho, q) - d2 * rho[q]) * 2.0 / cnt;
+        /* through the even half-step: each odd point feeds its even neighbours */
+        for (int q = 0; q < g.pts; q++) {
+            if (!interior(&g, q) || !parity(&g, q)) continue;
+            double s = 0;
+            int st[3] = {1, g.G, g.G * g.G};
+            for (int ax = 0; ax < dim; ax++)
+                for (int sg = -1; sg <= 1; sg += 2) {
+                    int nb = q + sg * st[ax];
+                    if (interior(&g, nb)) s += dv[nb];
+                }
+            dvf[q] = dv[q] + s / d2;
+        }
+        /* through the odd half-step onto the network's even outputs */
+        for (int q = 0; q < g.pts; q++)
+            if (interior(&g, q) && !parity(&g, q)) dY[((size_t)b * g.pts + q) * C] = axis_sum(&g, dvf, q) / d2;
+    }
+    loss /= cnt;
+    backward(&g, B, act, w, dY, grad);
+    free(act); free(dY); free(y); free(v); free(rho); free(dv); free(dvf);
+    return loss;
+}
+
+/* gradient of the loss with respect to w from the gradient dY with respect
+ * to the last layer's output (channel 0); dY is overwritten */
+static void backward(const Geo *gp, int B, const double *act, const double *w, double *dY, double *grad)
+{
+    const Geo g = *gp;
+    const int dim = g.dim;
+    (void)dim;
+    size_t per = (size_t)B * g.pts * C;
+    size_t WL = (size_t)g.T * C * C;
+    double *dX = (double *)calloc(per, sizeof(double));
+    if (!dX) { for (size_t i = 0; i < NL * WL; i++) grad[i] = NAN; return; }
     memset(grad, 0, sizeof(double) * NL * WL);
     for (int l = NL - 1; l >= 0; l--) {
         /* dY: gradient with respect to the output of layer l (masked) */
@@ -166,10 +274,7 @@ double orc_net_loss_grad(int dim, int B, const double *in, const double *target,
                 if (ci != 0) grad[((size_t)t * C + ci) * C + co] = 0;
                 if (co != 0) grad[WL * 3 + ((size_t)t * C + ci) * C + co] = 0;
             }
-    free(act);
-    free(dY);
     free(dX);
-    return loss;
 }
 
 /* One Adam step (Kingma and Ba, Algorithm 1) on n parameters, bias-corrected
