@@ -364,6 +364,29 @@ def bench_batched(dmg, workloads, dev, torch, args, with_oracle=False):
     return res
 
 
+def train_pair_of_nets(L, torch, r, e, log):
+    """Trains one network towards the targets (mean squared error) and one on
+    the cut-level objective, the same schedule and seeds; reports the cut
+    objective of both over the pairs and returns the second one's weights."""
+    epochs = sum(k for k, _ in L.SCHEDULE)
+    info = {"epochs": epochs, "batch": 256, "lr_schedule": [list(x) for x in L.SCHEDULE], "loss": "cut"}
+    w = None
+    for loss in ("mse", "cut"):
+        t1 = time.perf_counter()
+        net, hist = L.train(r, e, batch=256, seed=7, schedule=L.SCHEDULE, loss=loss)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        w = net.weights().copy()
+        net.close()
+        obj = L.cut_objective(w, r)
+        info[loss] = {"train_seconds": round(t2 - t1, 3), "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1],
+                      "cut_objective": obj, "cut_ratio_rms": round(obj ** 0.5, 4)}
+        log("  net (%s loss): %d epochs in %.2f s, loss %.3e -> %.3e, cut-level ratio (rms over pairs) %.4f"
+            % (loss, epochs, t2 - t1, hist[0], hist[-1], obj ** 0.5))
+    info["train_seconds"] = info["cut"]["train_seconds"]
+    return w, info
+
+
 def train_net(dmg, L, torch, log):
     """10^4 (r_c, e_c) pairs from 1250 plain FP64 solves of 1025^2 problems
     (f seeds 1000..2249, 8 cycles each), then Adam on the GPU."""
@@ -371,18 +394,9 @@ def train_net(dmg, L, torch, log):
     r, e = L.make_pairs(n=1024, seeds=range(1000, 2250), cycles=8, log=log)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    epochs = sum(k for k, _ in L.SCHEDULE)
-    net, hist = L.train(r, e, batch=256, seed=7, schedule=L.SCHEDULE)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    w = net.weights().copy()
-    info = {"pairs": int(r.shape[0]), "pair_seconds": round(t1 - t0, 2), "epochs": epochs, "batch": 256,
-            "lr_schedule": [list(x) for x in L.SCHEDULE], "train_seconds": round(t2 - t1, 3),
-            "train_us_per_step": round(1e6 * (t2 - t1) / (epochs * (r.shape[0] // 256)), 1),
-            "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]}
-    log("  net: %d pairs in %.1f s, %d epochs in %.2f s, loss %.3e -> %.3e"
-        % (info["pairs"], t1 - t0, epochs, t2 - t1, hist[0], hist[-1]))
-    net.close()
+    w, info = train_pair_of_nets(L, torch, r, e, log)
+    info.update({"pairs": int(r.shape[0]), "pair_seconds": round(t1 - t0, 2)})
+    info["train_us_per_step"] = round(1e6 * info["train_seconds"] / (info["epochs"] * (r.shape[0] // 256)), 1)
     del r, e
     torch.cuda.empty_cache()
     return w, info
@@ -451,15 +465,8 @@ def bench_learned3d(dmg, L, dev, torch, args, with_oracle=False):
     r, e = L.make_pairs_3d(n=128, seeds=range(1000, 2250), cycles=8)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    epochs = sum(k for k, _ in L.SCHEDULE)
-    net, hist = L.train(r, e, batch=256, seed=7, schedule=L.SCHEDULE)
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    w = net.weights().copy()
-    net.close()
-    info = {"pairs": int(r.shape[0]), "pair_seconds": round(t1 - t0, 2), "epochs": epochs, "batch": 256,
-            "lr_schedule": [list(x) for x in L.SCHEDULE], "train_seconds": round(t2 - t1, 3),
-            "loss_first_epoch": hist[0], "loss_last_epoch": hist[-1]}
+    w, info = train_pair_of_nets(L, torch, r, e, lambda m: log(m.replace("net (", "net 3D (")))
+    info.update({"pairs": int(r.shape[0]), "pair_seconds": round(t1 - t0, 2)})
     del r, e
     fs = [torch.from_numpy(f).to(dev) for f in L.eval_problems(128, range(5000, 5008), dim=3)]
     ref = None

@@ -279,6 +279,20 @@ int mg_net_forward(mg_net *net, const double *in, double *out, int batch, int no
  * scaled like the output.  Synchronises the stream. */
 int mg_net_loss_grad(mg_net *net, const double *in, const double *target, int batch, int normalize,
                      float *grad, double *loss);
+/* Training objective of mg_net_loss_grad and mg_net_train.
+ * MG_NET_LOSS_MSE (the default): the mean squared error above.
+ * MG_NET_LOSS_CUT: what the plan's judge compares.  The output at the cut
+ * level's points with even index sum (those it shares with the level below)
+ * goes through the cut level's red-black Jacobi step for Lap v = x
+ * (Section 2.2; over-relaxed form of Section 2.4 with parameter pj, the
+ * cut level's p: 2D p, 3D p_g), odd points first, in the normalised units
+ * (x = r_c / s, spacing 1); the loss is the mean over interior points of
+ * (x - Lap v)^2, the square of the cut level's residual reduction.  The
+ * target is not read and may be NULL.  pj in (0, 1000); MG_ERR_ARG
+ * otherwise.  The setting stays until changed. */
+#define MG_NET_LOSS_MSE 0
+#define MG_NET_LOSS_CUT 1
+int mg_net_set_loss(mg_net *net, int kind, double pj);
 /* Adam (lr, beta1 0.9, beta2 0.999, eps 1e-8) on npairs normalised
  * (r_c, e_c) pairs (device, npairs x G^dim doubles each), `epochs` passes
  * of npairs / batch steps; the order of every pass is a seeded permutation.

@@ -53,9 +53,10 @@ __device__ inline int net_sample(int b, long long base, long long pa, long long 
 }
 
 // Loads sample s into X0 (channel 0) and tgt; returns the input scale.
+// judge: tgt receives the (scaled) input itself in single precision.
 template <int DIM>
 __device__ double net_load(const double* __restrict__ in, const double* __restrict__ target, int normalize,
-                           bf16_t* X0, float* tgt, double* red)
+                           bf16_t* X0, float* tgt, double* red, bool judge = false)
 {
     using N = NetGeo<DIM>;
     double ss = 0;
@@ -69,19 +70,96 @@ __device__ double net_load(const double* __restrict__ in, const double* __restri
     for (int q = threadIdx.x; q < N::NIN; q += blockDim.x) {
         int p = N::lin(q);
         X0[p * kNetCh] = f2bf((float)(in[p] * sc));
-        if (tgt) tgt[q] = (float)(target[p] * st);
+        if (tgt) tgt[q] = judge ? (float)(in[p] * sc) : (float)(target[p] * st);
     }
     return normalize ? rms * net_h2<DIM>() : 1.0;
 }
 
+// The cut-level objective (judge != 0): the network output y at the grid's
+// even points (the points the cut level shares with the level below) goes
+// through the cut level's own red-black Jacobi step for Lap v = x, with its
+// over-relaxation parameter pj on the residual (odd points first, then the
+// even ones from the new odd values; the network's units, spacing 1), and
+// the loss is the sum of rho^2 over the interior, rho = x - L v: the
+// squared reduction of the cut level's residual by the correction the coarse
+// kernel would use.  Its gradient with respect to y (the step is linear) goes
+// into d0 at the even points; d1 serves as scratch and is cleared again.
+template <int DIM>
+__device__ double net_judge_loss(const float* out0, const float* xin, const short* linq, float pj, float inv_cnt,
+                                 bf16_t* d0, bf16_t* d1, int grad, double* red)
+{
+    using N = NetGeo<DIM>;
+    constexpr int G = N::G, PTS = N::PTS;
+    constexpr float d2 = 2.f * DIM, inv2d = 1.f / (2.f * DIM);
+    float* Y = reinterpret_cast<float*>(d1);
+    float* X = Y + PTS;
+    float* V = X + PTS;
+    float* R = V + PTS;
+    float* F = R + PTS;
+    auto par = [](int p) { return (p % G + (p / G) % G + p / (G * G)) & 1; };
+    auto nsum = [](const float* a, int p) {
+        float s = a[p - 1] + a[p + 1] + a[p - G] + a[p + G];
+        if (DIM == 3) s += a[p - G * G] + a[p + G * G];
+        return s;
+    };
+    for (int p = threadIdx.x; p < 5 * PTS; p += blockDim.x) Y[p] = 0.f;
+    __syncthreads();
+    for (int q = threadIdx.x; q < N::NIN; q += blockDim.x) {
+        const int p = linq[q];
+        X[p] = xin[q];
+        if (!par(p)) Y[p] = out0[q];
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < N::NIN; q += blockDim.x) {
+        const int p = linq[q];
+        if (par(p)) V[p] = (nsum(Y, p) - pj * X[p]) * inv2d;
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < N::NIN; q += blockDim.x) {
+        const int p = linq[q];
+        if (!par(p)) V[p] = (nsum(V, p) - pj * X[p]) * inv2d;
+    }
+    __syncthreads();
+    double l = 0;
+    for (int q = threadIdx.x; q < N::NIN; q += blockDim.x) {
+        const int p = linq[q];
+        const float rho = X[p] - (nsum(V, p) - d2 * V[p]);
+        R[p] = rho;
+        l += (double)rho * rho;
+    }
+    l = block_sum(l, red);
+    if (grad) {
+        // d loss / d v = -L (2 rho inv_cnt) (L symmetric, zero boundary), into Y
+        for (int q = threadIdx.x; q < N::NIN; q += blockDim.x) {
+            const int p = linq[q];
+            Y[p] = -(nsum(R, p) - d2 * R[p]) * 2.f * inv_cnt;
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < N::NIN; q += blockDim.x) {   // odd points feed their even neighbours
+            const int p = linq[q];
+            if (par(p)) F[p] = Y[p] + nsum(Y, p) * inv2d;
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < N::NIN; q += blockDim.x) {   // onto the network's even outputs
+            const int p = linq[q];
+            if (!par(p)) d0[p * kNetCh] = f2bf(nsum(F, p) * inv2d);
+        }
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < 5 * PTS; p += blockDim.x) Y[p] = 0.f;   // d1 is zero again
+    __syncthreads();
+    return l;
+}
+
 // One sample per workgroup: forward, loss, and (grad != 0) the weight
-// gradient of this sample into gpart[block][NW].
+// gradient of this sample into gpart[block][NW].  judge: the cut-level
+// objective above instead of the mean squared error (e is not read).
 template <int DIM>
 __global__ void __launch_bounds__(kNetThreads) kn_train(const double* __restrict__ r, const double* __restrict__ e,
                                                         long long base, long long pa, long long pb, int npairs,
                                                         int normalize, float inv_cnt, const bf16_t* __restrict__ wf,
                                                         const bf16_t* __restrict__ wb, float* __restrict__ gpart,
-                                                        double* __restrict__ lpart, int grad)
+                                                        double* __restrict__ lpart, int grad, int judge, float pj)
 {
     using N = NetGeo<DIM>;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -97,7 +175,8 @@ __global__ void __launch_bounds__(kNetThreads) kn_train(const double* __restrict
     net_zero(act, 6 * N::ACT);
     net_fill_lin<DIM>(linq);
     __syncthreads();
-    net_load<DIM>(r + (size_t)s * N::PTS, e + (size_t)s * N::PTS, normalize, act, tgt, red);
+    net_load<DIM>(r + (size_t)s * N::PTS, judge ? nullptr : e + (size_t)s * N::PTS, normalize, act, tgt, red,
+                  judge != 0);
     __syncthreads();
     const int WLY = N::T * 256;
     net_conv_fwd<DIM, true>(act, act + N::ACT, nullptr, wf, linq);
@@ -109,12 +188,16 @@ __global__ void __launch_bounds__(kNetThreads) kn_train(const double* __restrict
     net_conv_fwd<DIM, false>(act + 3 * N::ACT, nullptr, out0, wf + 3 * WLY, linq);
     __syncthreads();
     double l = 0;
-    for (int q = threadIdx.x; q < N::NIN; q += blockDim.x) {
-        float d = out0[q] - tgt[q];
-        l += (double)d * d;
-        if (grad) d0[linq[q] * kNetCh] = f2bf(2.f * d * inv_cnt);
+    if (judge) {
+        l = net_judge_loss<DIM>(out0, tgt, linq, pj, inv_cnt, d0, d1, grad, red);
+    } else {
+        for (int q = threadIdx.x; q < N::NIN; q += blockDim.x) {
+            float d = out0[q] - tgt[q];
+            l += (double)d * d;
+            if (grad) d0[linq[q] * kNetCh] = f2bf(2.f * d * inv_cnt);
+        }
+        l = block_sum(l, red);
     }
-    l = block_sum(l, red);
     if (threadIdx.x == 0) lpart[blockIdx.x] = l;
     if (!grad) return;
     float* gw = gpart + (size_t)blockIdx.x * N::NW;
@@ -218,6 +301,8 @@ constexpr int kMaxEpochs = 4096;
 
 struct mg_net {
     int dim = 2, max_batch = 0, device = 0, nw = 0, step = 0;
+    int judge = 0;      // loss: 0 mean squared error to the target, 1 the cut-level objective
+    float pj = 1.f;     // the cut level's over-relaxation parameter (judge)
     hipStream_t stream = nullptr;
     char* ws = nullptr;
     size_t off_w = 0, off_m = 0, off_v = 0, off_wf = 0, off_wb = 0, off_gpart = 0, off_lpart = 0, off_gout = 0,
@@ -255,11 +340,11 @@ int launch_train(mg_net& N, const double* r, const double* e, int B, long long b
     if (N.dim == 2)
         hipLaunchKernelGGL(kn_train<2>, dim3(B), dim3(kNetThreads), net_lds_train<2>(), N.stream, r, e, base, pa, pb, npairs,
                            normalize, inv_cnt, N.at<bf16_t>(N.off_wf), N.at<bf16_t>(N.off_wb), N.at<float>(N.off_gpart),
-                           N.at<double>(N.off_lpart), grad);
+                           N.at<double>(N.off_lpart), grad, N.judge, N.pj);
     else
         hipLaunchKernelGGL(kn_train<3>, dim3(B), dim3(kNetThreads), net_lds_train<3>(), N.stream, r, e, base, pa, pb, npairs,
                            normalize, inv_cnt, N.at<bf16_t>(N.off_wf), N.at<bf16_t>(N.off_wb), N.at<float>(N.off_gpart),
-                           N.at<double>(N.off_lpart), grad);
+                           N.at<double>(N.off_lpart), grad, N.judge, N.pj);
     return last_launch();
 }
 
@@ -418,10 +503,19 @@ int mg_net_forward(mg_net* N, const double* in, double* out, int batch, int norm
     return last_launch();
 }
 
+int mg_net_set_loss(mg_net* N, int kind, double pj)
+{
+    if (!N || (kind != MG_NET_LOSS_MSE && kind != MG_NET_LOSS_CUT)) return MG_ERR_ARG;
+    if (kind == MG_NET_LOSS_CUT && !(pj > 0.0 && pj < 1e3)) return MG_ERR_ARG;
+    N->judge = kind == MG_NET_LOSS_CUT;
+    N->pj = kind == MG_NET_LOSS_CUT ? (float)pj : 1.f;
+    return MG_OK;
+}
+
 int mg_net_loss_grad(mg_net* N, const double* in, const double* target, int batch, int normalize, float* grad,
                      double* loss)
 {
-    if (!N || !in || !target || batch < 1 || batch > N->max_batch) return MG_ERR_ARG;
+    if (!N || !in || (!target && !N->judge) || batch < 1 || batch > N->max_batch) return MG_ERR_ARG;
     DevGuard g(N->device);
     double inv = 1.0 / ((double)batch * net_nin(N->dim));
     int e = launch_train(*N, in, target, batch, 0, 1, 0, 0, normalize, (float)inv, 1);
@@ -443,7 +537,7 @@ int mg_net_loss_grad(mg_net* N, const double* in, const double* target, int batc
 int mg_net_train(mg_net* N, const double* r, const double* e, int npairs, int epochs, int batch, float lr,
                  unsigned long long seed, double* epoch_loss)
 {
-    if (!N || !r || !e || npairs < 1 || epochs < 0 || epochs > kMaxEpochs || batch < 1 || batch > N->max_batch ||
+    if (!N || !r || (!e && !N->judge) || npairs < 1 || epochs < 0 || epochs > kMaxEpochs || batch < 1 || batch > N->max_batch ||
         batch > npairs || !(lr > 0.f))
         return MG_ERR_ARG;
     DevGuard g(N->device);

@@ -56,6 +56,7 @@ _lib.mg_net_forward.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int]
 _lib.mg_net_loss_grad.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _fp, _dp]
 _lib.mg_net_train.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_float, _ull, _dp]
 _lib.mg_net_destroy.argtypes = [_vp]
+_lib.mg_net_set_loss.argtypes = [_vp, ctypes.c_int, ctypes.c_double]
 _lib.mg_set_coarse_net.argtypes = [_vp, _fp, ctypes.c_int]
 _lib.mg_net_stats.argtypes = [_vp, _ip, _ip, _dp, _dp]
 _lib.mg_coarse_export.argtypes = [_vp, ctypes.c_int, _vp]
@@ -71,7 +72,7 @@ for _f in ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_solve_
            "mg_solve_batched", "mg_vcycle_batched", "mg_autotune", "mg_net_weight_count", "mg_net_workspace_bytes",
            "mg_net_create", "mg_net_set_weights", "mg_net_get_weights", "mg_net_init", "mg_net_forward",
            "mg_net_loss_grad", "mg_net_train", "mg_net_destroy", "mg_set_coarse_net", "mg_net_stats",
-           "mg_coarse_export", "mg_vcycle_static", "mg_cycle_workspace_bytes", "mg_setup_cycle"):
+           "mg_coarse_export", "mg_vcycle_static", "mg_cycle_workspace_bytes", "mg_setup_cycle", "mg_net_set_loss"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTS = ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_solve_two_stage", "mg_level_get", "mg_level_info",
@@ -79,9 +80,11 @@ EXPORTS = ("mg_workspace_bytes", "mg_setup", "mg_vcycle", "mg_solve", "mg_solve_
            "mg_setup_batched", "mg_solve_batched", "mg_vcycle_batched", "mg_autotune", "mg_net_weight_count",
            "mg_net_workspace_bytes", "mg_net_create", "mg_net_set_weights", "mg_net_get_weights", "mg_net_init",
            "mg_net_forward", "mg_net_loss_grad", "mg_net_train", "mg_net_destroy", "mg_set_coarse_net",
-           "mg_net_stats", "mg_coarse_export", "mg_vcycle_static", "mg_cycle_workspace_bytes", "mg_setup_cycle")
+           "mg_net_stats", "mg_coarse_export", "mg_vcycle_static", "mg_cycle_workspace_bytes", "mg_setup_cycle",
+           "mg_net_set_loss")
 
 MG_NET_CUT = 6
+MG_NET_LOSS_MSE, MG_NET_LOSS_CUT = 0, 1
 NET_G = {2: 17, 3: 9}
 
 # kernel families for mg_timing_enable
@@ -291,6 +294,10 @@ def mg_net_train(net, r_ptr, e_ptr, npairs, epochs, batch, lr, seed):
     h = (ctypes.c_double * max(epochs, 1))()
     _check(_lib.mg_net_train(net, r_ptr, e_ptr, npairs, epochs, batch, lr, seed, h), "mg_net_train")
     return list(h)[:epochs]
+
+
+def mg_net_set_loss(net, kind, pj=1.0):
+    _check(_lib.mg_net_set_loss(net, int(kind), float(pj)), "mg_net_set_loss")
 
 
 def mg_net_destroy(net):
@@ -555,16 +562,28 @@ class Net:
         mg_net_forward(self.net, x.data_ptr(), out.data_ptr(), x.shape[0], normalize)
         return out
 
-    def loss_grad(self, x, target, normalize=False):
+    def set_loss(self, kind, pj=1.0):
+        """MG_NET_LOSS_MSE, or MG_NET_LOSS_CUT with the cut level's
+        over-relaxation parameter pj (then no target is read)."""
+        mg_net_set_loss(self.net, kind, pj)
+        self.loss_kind = kind
+
+    def _target(self, t, name):
+        if t is None and getattr(self, "loss_kind", MG_NET_LOSS_MSE) == MG_NET_LOSS_CUT:
+            return None
+        self._grid(t, name)
+        return t.data_ptr()
+
+    def loss_grad(self, x, target=None, normalize=False):
         self._grid(x, "x")
-        self._grid(target, "target")
-        loss, g = mg_net_loss_grad(self.net, self.dim, x.data_ptr(), target.data_ptr(), x.shape[0], normalize)
+        tp = self._target(target, "target")
+        loss, g = mg_net_loss_grad(self.net, self.dim, x.data_ptr(), tp, x.shape[0], normalize)
         return loss, g.reshape(4, 3 ** self.dim, 16, 16)
 
     def train(self, r, e, epochs, batch=256, lr=1e-3, seed=0):
         self._grid(r, "r")
-        self._grid(e, "e")
-        return mg_net_train(self.net, r.data_ptr(), e.data_ptr(), r.shape[0], epochs, batch, lr, seed)
+        ep = self._target(e, "e")
+        return mg_net_train(self.net, r.data_ptr(), ep, r.shape[0], epochs, batch, lr, seed)
 
     def close(self):
         if getattr(self, "net", None) is not None:

@@ -9,7 +9,9 @@ Orchestration only: every arithmetic step runs in libdmg's kernels.
   the 17 x 17 Poisson problem with right-hand side r_c, solved by the same
   library (batched, FP64) to a relative residual of 1e-13.
 * Training: Adam on the normalised pairs (libdmg's bf16 forward/backward
-  kernels, FP32 master weights).
+  kernels, FP32 master weights), either towards e_c (mean squared error) or
+  on the cut-level objective the coarse kernel judges the network by: the
+  cut level's residual after its own Jacobi step from the network's output.
 """
 import concurrent.futures as cf
 
@@ -97,16 +99,50 @@ def make_pairs_3d(n=128, seeds=range(1000, 1250), cycles=8, device=None, target_
 SCHEDULE = ((120, 2e-3), (60, 5e-4), (60, 1.25e-4), (100, 3e-5))
 
 
-def train(r, e, epochs=30, batch=256, lr=2e-3, seed=7, init_seed=1, net=None, schedule=None):
+def cut_p(dim, p=None):
+    """the cut level's over-relaxation parameter: 2D p, 3D p_g (the green
+    level's); the library's defaults unless p is given"""
+    p = p if p is not None else (dmg.P2D_TUNED if dim == 2 else dmg.P3D_TUNED)
+    return float(p[0] if dim == 2 else p[3])
+
+
+def train(r, e, epochs=30, batch=256, lr=2e-3, seed=7, init_seed=1, net=None, schedule=None, loss="mse", pj=None):
     """Train (or continue training) a network on the pairs; returns (net,
     epoch losses).  schedule: ((epochs, lr), ...) run in order (Adam state
-    carried over), instead of epochs at one lr."""
+    carried over), instead of epochs at one lr.  loss "mse": towards the
+    targets e; "cut": the cut level's residual after its own Jacobi step from
+    the network's output (e is not used; pj defaults to cut_p)."""
+    dim = r.dim() - 1
     if net is None:
-        net = dmg.Net(dim=r.dim() - 1, max_batch=batch, seed=init_seed, device=r.device)
+        net = dmg.Net(dim=dim, max_batch=batch, seed=init_seed, device=r.device)
+    if loss == "cut":
+        net.set_loss(dmg.MG_NET_LOSS_CUT, cut_p(dim) if pj is None else pj)
+        e = None
+    elif loss == "mse":
+        net.set_loss(dmg.MG_NET_LOSS_MSE)
+    else:
+        raise ValueError("loss must be 'mse' or 'cut'")
     hist = []
     for k, (ep, rate) in enumerate(schedule or ((epochs, lr),)):
         hist += net.train(r, e, epochs=ep, batch=batch, lr=rate, seed=seed + 7919 * k)
     return net, hist
+
+
+def cut_objective(w, r, batch=256, pj=None):
+    """Mean over the pairs' residuals r of the cut-level objective for the
+    weights w (mean rho^2 with r normalised to unit rms: the square of the
+    cut level's residual reduction, averaged over samples)."""
+    dim = r.dim() - 1
+    net = dmg.Net(dim=dim, max_batch=batch, device=r.device)
+    net.set_weights(w)
+    net.set_loss(dmg.MG_NET_LOSS_CUT, cut_p(dim) if pj is None else pj)
+    tot, cnt = 0.0, 0
+    for i in range(0, r.shape[0], batch):
+        rb = r[i:i + batch]
+        tot += net.loss_grad(rb, None, normalize=True)[0] * rb.shape[0]
+        cnt += rb.shape[0]
+    net.close()
+    return tot / cnt
 
 
 def eval_problems(n=1024, seeds=range(5000, 5032), dim=2):

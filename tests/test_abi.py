@@ -107,6 +107,7 @@ def test_net_sizes_and_argument_errors(D):
     assert D._lib.mg_net_create(ctypes.byref(net), 2, 8, None, 0, None) == D.MG_ERR_WS
     assert D._lib.mg_net_create(ctypes.byref(net), 5, 8, None, 0, None) == D.MG_ERR_ARG
     assert D._lib.mg_net_destroy(None) == D.MG_OK
+    assert D._lib.mg_net_set_loss(None, D.MG_NET_LOSS_CUT, 1.0) == D.MG_ERR_ARG
     # a plan is required; checked before any GPU call
     assert D._lib.mg_set_coarse_net(None, None, 6) == D.MG_ERR_ARG
     assert D._lib.mg_net_stats(None, None, None, None, None) == D.MG_ERR_ARG

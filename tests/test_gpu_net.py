@@ -7,6 +7,10 @@
 * one Adam step against the oracle's Adam applied to the GPU gradient;
 * training on pairs from the plain solver lowers the loss, and the trained
   network estimates the cut level's correction better than the untrained one;
+* the cut-level objective (the level's residual after its own Jacobi step
+  from the output) and its gradient against the oracle; trained on it, the
+  network reduces the cut level's residual more than the one trained
+  towards the targets;
 * the judge: its per-problem decision on a first cycle matches the decision
   predicted from the stand-alone network and the oracle's plain sub-cycle;
   poisoned weights leave the solve bitwise equal to the plain one;
@@ -136,6 +140,43 @@ def test_gradient_exact_on_exact_data(dmg, orc, dim):
     net.close()
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_cut_objective_matches_oracle(dmg, orc, dim):
+    """The cut-level objective (the level's own Jacobi step from the output's
+    even points, then the residual) and its weight gradient against the
+    oracle on the same bf16-exact weights and inputs; same tolerance as the
+    mean-squared-error gradient (the step itself runs in fp32)."""
+    print("cut objective parity dim", dim, flush=True)
+    rng = np.random.default_rng(260 + dim)
+    w = bf(rand_weights(rng, dim))
+    x = bf(rand_grid(rng, dim, 5))
+    pj = float(np.float32(1.052 if dim == 2 else 0.99))
+    net = dmg.Net(dim=dim, max_batch=8)
+    net.set_weights(w.astype(np.float32))
+    net.set_loss(dmg.MG_NET_LOSS_CUT, pj)
+    loss, g = net.loss_grad(dev(x), None, normalize=False)
+    lo, go = O.net_judge_loss_grad(x, w, pj)
+    print("  loss gpu %.6e oracle %.6e" % (loss, lo))
+    assert abs(loss - lo) <= 1e-2 * lo
+    for l in range(4):
+        d = np.abs(g[l] - go[l]).max() / np.abs(go[l]).max()
+        cos = (g[l] * go[l]).sum() / np.sqrt((g[l] ** 2).sum() * (go[l] ** 2).sum())
+        print("  layer %d: max err / max |g| = %.2e, cosine %.6f" % (l, d, cos))
+        assert d <= 6e-2 and cos >= 0.998
+    assert not g[0, :, 1:, :].any() and not g[3, :, :, 1:].any()
+    # the target is not read: any target gives the same result
+    l2, g2 = net.loss_grad(dev(x), dev(rand_grid(rng, dim, 5)), normalize=False)
+    assert l2 == loss and np.array_equal(g2, g)
+    # back to the mean squared error
+    net.set_loss(dmg.MG_NET_LOSS_MSE)
+    t = rand_grid(rng, dim, 5)
+    lm, _ = net.loss_grad(dev(x), dev(t), normalize=False)
+    assert abs(lm - O.net_loss_grad(x, t, w)[0]) <= 1e-2 * lm
+    with pytest.raises(dmg.MGError):
+        net.set_loss(dmg.MG_NET_LOSS_CUT, -1.0)
+    net.close()
+
+
 def stencil_weights(dim):
     T = O.NET_TAPS[dim]
     c = T // 2
@@ -262,6 +303,37 @@ def test_trained_net_beats_untrained_at_the_cut(dmg, orc, trained):
           % tuple(np.median(rows, axis=0)))
     assert np.median(rows[:, 1]) < 0.5 * np.median(rows[:, 0])
     net.close()
+
+
+def test_cut_objective_training_beats_mse_at_the_cut(dmg, orc, trained):
+    """Trained on the cut-level objective (the fixture's pairs, epochs and
+    seeds), the network's cut-level residual reduction after the level's own
+    Jacobi step (the oracle's single-level step, on held-out pairs) is
+    smaller than that of the network trained towards the targets, and the
+    GPU's value of the objective agrees with the oracle's ratios."""
+    r, e, w_mse, hist = trained
+    from paper_math_9907190_amd import learned as L
+    net, h2 = L.train(r, None, epochs=60, batch=64, lr=2e-3, seed=5, loss="cut")
+    w_cut = net.weights().copy()
+    net.close()
+    print("cut-objective epoch losses: first %.4e, last %.4e" % (h2[0], h2[-1]))
+    assert np.all(np.isfinite(h2)) and h2[-1] < 0.5 * h2[0]
+    rh, _ = L.make_pairs(n=NT, seeds=range(5000, 5008), cycles=2, chunk=8)
+    med = {}
+    for name, w in (("mse", w_mse), ("cut", w_cut)):
+        net = dmg.Net(dim=2, max_batch=64)
+        net.set_weights(w)
+        y = net.forward(rh).cpu().numpy()
+        net.close()
+        rn = rh.cpu().numpy()
+        q = np.array([cut_ratio(rn[i], jacobi_cut(rn[i], y[i])) for i in range(rn.shape[0])])
+        obj = L.cut_objective(w, rh)
+        # the objective is the mean of the squared ratios (unit-rms inputs)
+        print("%s-trained: median cut ratio %.4f, rms %.4f, GPU objective rms %.4f"
+              % (name, np.median(q), np.sqrt((q ** 2).mean()), np.sqrt(obj)))
+        assert abs(np.sqrt(obj) - np.sqrt((q ** 2).mean())) <= 3e-2 * np.sqrt(obj)
+        med[name] = np.median(q)
+    assert med["cut"] < med["mse"]
 
 
 def test_judge_decisions_match_prediction(dmg, orc, trained):
