@@ -37,15 +37,16 @@ namespace dmg {
 
 // r = f - Lap_h(u) on rows [y0, y1) (stored as T, squared norm accumulated
 // in double), then Eq. (Erest2r) onto the first diagonal level at those rows.
-// FZ: also Eq. (Erest2b) onto the axis level below it, from the diagonal
-// values of three consecutive rows kept in registers (the strip then
-// computes one diagonal row past its end; strips start on odd rows).
+// FZ: Eq. (Erest2b) onto the axis level below it, from the diagonal values
+// of three consecutive rows kept in registers (the strip then computes one
+// diagonal row past its end; strips start on odd rows), and the diagonal
+// level itself is not stored: the finest Jacobi restricts it again from r.
 // Lane t owns the column pair (2t, 2t+1); a diagonal value needs the lanes
 // beside it, and an FZ value the lanes beside those: lanes 1 .. 61 write r
 // and r1, lanes 2 .. 62 write r2.
-// NT: non-temporal f, r0 and r1 accesses (r1 is next read by the finest
-// kernel, after the whole cycle: kept out of the caches, it leaves them to
-// the level arrays in between).  At most 128 VGPRs (four waves per
+// NT: non-temporal f, r0 and r1 accesses (r0 and r1 are next read by the
+// finest kernel, after the whole cycle: kept out of the caches, they leave
+// them to the level arrays in between).  At most 128 VGPRs (four waves per
 // SIMD keep enough loads in flight); the FP64 FZ variant needs a few more
 // and runs three waves rather than spill (measured faster than halving its
 // row chunk to stay at four).
@@ -169,7 +170,7 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
                 T rn = q ? r1j : r0j;
                 int a = 2 * t + q;
                 const T d1 = rs2_core(rc, rw, rs, re, rn);
-                if (useful && a >= 1 && a <= m - 1 && j - 1 < y1) {
+                if (!FZ && useful && a >= 1 && a <= m - 1 && j - 1 < y1) {
                     if (NT) __builtin_nontemporal_store(d1, rD + (size_t)(j - 1) * W + t);
                     else rD[(size_t)(j - 1) * W + t] = d1;
                 }
@@ -377,10 +378,15 @@ __global__ void __launch_bounds__(kRowBlock) kb_finest(int m, T cc, const Fin2<T
 // k is (2t + (k&1), k); F points (odd rows) come from two rows of the
 // coarser axis level v2 (columns t, t+1), C points (even rows) from the F
 // values of the rows above and below (lanes t-1, t), so the F row k+1 is
-// computed one row ahead.  These extra neighbour dependencies leave lanes
-// 2 .. 61 to write u (lanes 0, 1, 62, 63 are halo).  Same arithmetic cores
-// as the per-level kernels: the results are bit-identical to running the
-// diagonal Jacobi and then kb_finest.
+// computed one row ahead.  The diagonal level's residual is not read
+// either: it is restricted (Eq. Erest2r) from the axis residual rows the
+// march holds anyway (a window of three row pairs, loaded two rows ahead),
+// so the residual kernel and kb_rs_pair do not store it.  These extra
+// neighbour dependencies leave lanes 2 .. 61 to write u (lanes 0, 1, 62, 63
+// are halo; a restricted value at lane 0 of an even row or lane 63 of an
+// odd row lacks its outer neighbour and reaches no written point).  Same
+// arithmetic cores as the per-level kernels: the results are bit-identical
+// to restricting, running the diagonal Jacobi and then kb_finest.
 constexpr int kFusePairs = 60;
 
 // FINEST: add the axis values to u (else store them in vA).
@@ -391,9 +397,8 @@ constexpr int kFusePairs = 60;
 // neighbouring strips then reach the rows they share at the same time (both
 // at their start or both at their end), while those rows are still in L2.
 template <typename T, bool FINEST, bool NT, bool MIR>
-__device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, const T* __restrict__ r1,
-                                  const T* __restrict__ v2, T* __restrict__ vA, double* __restrict__ u, int wv,
-                                  int nwx, int rows)
+__device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, const T* __restrict__ v2,
+                                  T* __restrict__ vA, double* __restrict__ u, int wv, int nwx, int rows)
 {
     const int lane = threadIdx.x & 63;
     const int wx = wv % nwx, sy = wv / nwx;
@@ -401,7 +406,7 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
     const int ya = 1 + sy * rows, yb = min(ya + rows, m);   // the strip's rows [ya, yb)
     const int y0 = MIR ? m - yb + 1 : ya;                   // the same rows as marched
     const int y1 = MIR ? m - ya + 1 : yb;
-    const int h = m / 2, W = h + 1;   // row length of the diagonal level and of v2 (side m/2)
+    const int h = m / 2, W = h + 1;   // row length of v2 (side m/2)
     auto R = [&](int k) { return MIR ? m - k : k; };       // marched row -> grid row
     auto RB = [&](int B) { return MIR ? h - B : B; };      // the same on the level of side m/2
     const bool useful = lane >= 2 && lane < kFusePairs + 2 && t >= 0 && t <= h;
@@ -409,10 +414,27 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
     const bool c0 = t >= 1 && 2 * t <= m - 1, c1 = t >= 0 && 2 * t + 1 <= m - 1;
     const size_t w = (size_t)(m + 1);
     auto ld2 = [&](int B) -> T { return (colok && B >= 0 && B <= h) ? v2[(size_t)RB(B) * W + t] : T(0); };
-    auto ld1 = [&](int k) -> T {
-        if (!(colok && k >= 0 && k <= m)) return T(0);
-        const T* p = r1 + (size_t)R(k) * W + t;
-        return (FINEST && NT) ? __builtin_nontemporal_load(p) : *p;
+    // pair of an interior row: column m+1 is the next row's column 0 and never used
+    auto ldR = [&](int j, T& x, T& y) {
+        x = y = 0;
+        if (!colok || j < 1 || j > m - 1) return;
+        const T* p = rA + (size_t)R(j) * w + 2 * t;
+        P2<T> v = (FINEST && NT) ? ld_pair_nt(p) : *reinterpret_cast<const P2<T>*>(p);
+        x = c0 ? v.x : T(0);
+        y = c1 ? v.y : T(0);
+    };
+    // Eq. (Erest2r) at the lane's diagonal point (2t + (k&1), k) of marched
+    // row k from the axis residual pairs of marched rows k-1 (m), k (c), k+1
+    // (p), the operands in grid order (south = the lower grid row); the same
+    // bits as the stored restriction of the residual kernels
+    auto rs1 = [&](int k, T mx, T my, T cx, T cy, T px, T py) -> T {
+        const int q = k & 1;   // grid row R(k) has the parity of k (m is even)
+        const T sh = q ? __shfl_down(cx, 1) : __shfl_up(cy, 1);
+        const T rc = q ? cy : cx;
+        const T rw = q ? cx : sh;
+        const T re = q ? sh : cy;
+        const T rlo = q ? my : mx, rhi = q ? py : px;
+        return MIR ? rs2_core(rc, rw, rhi, re, rlo) : rs2_core(rc, rw, rlo, re, rhi);
     };
     // F point (2t+1, k), k odd, from v2 rows (k-1)/2 (vlo) and (k+1)/2 (vhi), as jac2_diagF
     auto f21 = [&](int k, T rF, T vlo, T vhi) -> T {
@@ -426,43 +448,49 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
         if (!(t >= 1 && t <= h - 1 && k >= 2 && k <= m - 2)) return T(0);
         return MIR ? jac2_sum(cd, rC, Fp_w, Fp, Fm, Fm_w) : jac2_sum(cd, rC, Fm_w, Fm, Fp, Fp_w);
     };
-    auto fs = [&](int k) -> T { return f21(k, ld1(k), ld2((k - 1) >> 1), ld2((k + 1) >> 1)); };
-    auto vs = [&](int k) -> T { return (k & 1) ? fs(k) : c21(k, ld1(k), fs(k - 1), fs(k + 1)); };
-    // pair of an interior row: column m+1 is the next row's column 0 and never used
-    auto ldR = [&](int j, T& x, T& y) {
-        x = y = 0;
-        if (!colok || j < 1 || j > m - 1) return;
-        const T* p = rA + (size_t)R(j) * w + 2 * t;
-        P2<T> v = (FINEST && NT) ? ld_pair_nt(p) : *reinterpret_cast<const P2<T>*>(p);
-        x = c0 ? v.x : T(0);
-        y = c1 ? v.y : T(0);
-    };
+    auto fsr = [&](int k, T r1k) -> T { return f21(k, r1k, ld2((k - 1) >> 1), ld2((k + 1) >> 1)); };
     // window entering row j: diagonal values of rows j-1 (dm), j (d0); at even
-    // j, Fn = F row j+1; at odd j, vlo = v2 row (j+1)/2
+    // j, Fn = F row j+1; at odd j, vlo = v2 row (j+1)/2.  The axis residual
+    // pairs of rows j-3 .. j+2 give the diagonal residuals of rows j-2 .. j+1.
     int j = y0 - 1;
-    T dm = vs(j - 1), d0 = vs(j);
-    T vlo, Fn = T(0);
+    T a0x, a0y, a1x, a1y, a2x, a2y, sx, sy_, nx, ny, xx, xy;
+    ldR(j - 3, a0x, a0y);
+    ldR(j - 2, a1x, a1y);
+    ldR(j - 1, a2x, a2y);
+    ldR(j, sx, sy_);
+    ldR(j + 1, nx, ny);
+    ldR(j + 2, xx, xy);
+    T dm, d0, vlo, Fn = T(0);
     if (j & 1) {
+        const T Fj = fsr(j, rs1(j, a2x, a2y, sx, sy_, nx, ny));
+        dm = c21(j - 1, rs1(j - 1, a1x, a1y, a2x, a2y, sx, sy_), fsr(j - 2, rs1(j - 2, a0x, a0y, a1x, a1y, a2x, a2y)), Fj);
+        d0 = Fj;
         vlo = ld2((j + 1) >> 1);
     } else {
-        Fn = fs(j + 1);
+        const T Fm = fsr(j - 1, rs1(j - 1, a1x, a1y, a2x, a2y, sx, sy_));
+        const T Fp = fsr(j + 1, rs1(j + 1, sx, sy_, nx, ny, xx, xy));
+        dm = Fm;
+        d0 = c21(j, rs1(j, a2x, a2y, sx, sy_, nx, ny), Fm, Fp);
+        Fn = Fp;
         vlo = ld2((j + 2) >> 1);
     }
-    // raw inputs of one row j, loaded a row ahead of their use
-    struct Ck { T rx, ry, r1c, r1f, vhi; double ux, uy; };
+    // raw inputs loaded a row ahead of their use: at odd jj the axis
+    // residual pairs of rows jj+2 (a) and jj+3 (b) and v2 row (jj+3)/2; u of
+    // row jj.  Entering row jj, (sx, sy_) holds the pair of row jj, (nx, ny)
+    // that of row jj+1 and, at even jj, (xx, xy) that of row jj+2.
+    struct Ck { T ax, ay, bx, by, vhi; double ux, uy; };
     auto load = [&](int jj, Ck& c) {
-        c.rx = c.ry = c.r1c = c.r1f = c.vhi = 0;
+        c.ax = c.ay = c.bx = c.by = c.vhi = 0;
         c.ux = c.uy = 0;
         if (jj > y1) return;
-        ldR(jj, c.rx, c.ry);
         if (FINEST && useful && jj >= y0 && jj < y1 && (c0 || c1)) {
             P2<double> v = *reinterpret_cast<const P2<double>*>(u + (size_t)R(jj) * w + 2 * t);
             c.ux = v.x;
             c.uy = v.y;
         }
         if (jj & 1) {
-            c.r1c = ld1(jj + 1);
-            c.r1f = ld1(jj + 2);
+            ldR(jj + 2, c.ax, c.ay);
+            ldR(jj + 3, c.bx, c.by);
             c.vhi = ld2((jj + 3) >> 1);
         }
     };
@@ -472,16 +500,18 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
         if (jj > y1) return;
         T dp;
         if (jj & 1) {   // row jj+1 even: its C points from F rows jj (= d0) and jj+2
-            const T F2 = f21(jj + 2, c.r1f, vlo, c.vhi);
-            dp = c21(jj + 1, c.r1c, d0, F2);
+            const T r1c = rs1(jj + 1, sx, sy_, nx, ny, c.ax, c.ay);
+            const T r1f = rs1(jj + 2, nx, ny, c.ax, c.ay, c.bx, c.by);
+            const T F2 = f21(jj + 2, r1f, vlo, c.vhi);
+            dp = c21(jj + 1, r1c, d0, F2);
             Fn = F2;
             vlo = c.vhi;
         } else {        // row jj+1 odd: its F points, computed one row ago
             dp = Fn;
         }
         const int q = jj & 1;
-        const T rF = q ? c.rx : c.ry;   // F at column 2t+1-q
-        const T rC = q ? c.ry : c.rx;   // C at column 2t+q
+        const T rF = q ? sx : sy_;   // F at column 2t+1-q
+        const T rC = q ? sy_ : sx;   // C at column 2t+q
         const T nb = q ? __shfl_up(d0, 1) : __shfl_down(d0, 1);
         const T vw = q ? nb : d0;
         const T ve = q ? d0 : nb;
@@ -517,6 +547,18 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
         d0 = dp;
         uxm1 = c.ux;
         uym1 = c.uy;
+        // slide the residual pairs one row
+        sx = nx;
+        sy_ = ny;
+        if (jj & 1) {
+            nx = c.ax;
+            ny = c.ay;
+            xx = c.bx;
+            xy = c.by;
+        } else {
+            nx = xx;
+            ny = xy;
+        }
     };
     rows_march<1, Ck>(j, y1, load, proc);
 }
@@ -529,8 +571,8 @@ __global__ void __launch_bounds__(kRowBlock) kb_finest_fused(int m, T cc, T cd, 
     ITEM_GATE(ctls, it.prob);
     const int wv = rows_wave_id(nwaves);
     if (wv >= nwaves) return;
-    if ((wv / nwx) & 1) fused_body<T, true, NT, true>(m, cc, cd, it.r0, it.r1, it.v2, nullptr, it.u, wv, nwx, rows);
-    else fused_body<T, true, NT, false>(m, cc, cd, it.r0, it.r1, it.v2, nullptr, it.u, wv, nwx, rows);
+    if ((wv / nwx) & 1) fused_body<T, true, NT, true>(m, cc, cd, it.r0, it.v2, nullptr, it.u, wv, nwx, rows);
+    else fused_body<T, true, NT, false>(m, cc, cd, it.r0, it.v2, nullptr, it.u, wv, nwx, rows);
 }
 
 // The Jacobi of an axis level L (side m, coefficient cc) with that of the
@@ -543,8 +585,8 @@ __global__ void __launch_bounds__(kRowBlock) kb_jac_pair(int m, T cc, T cd, cons
     ITEM_GATE(ctls, it.prob);
     const int wv = rows_wave_id(nwaves);
     if (wv >= nwaves) return;
-    if ((wv / nwx) & 1) fused_body<T, false, false, true>(m, cc, cd, it.rA, it.r1, it.v2, it.vA, nullptr, wv, nwx, rows);
-    else fused_body<T, false, false, false>(m, cc, cd, it.rA, it.r1, it.v2, it.vA, nullptr, wv, nwx, rows);
+    if ((wv / nwx) & 1) fused_body<T, false, false, true>(m, cc, cd, it.rA, it.v2, it.vA, nullptr, wv, nwx, rows);
+    else fused_body<T, false, false, false>(m, cc, cd, it.rA, it.v2, it.vA, nullptr, wv, nwx, rows);
 }
 
 // tiny finest grids: one thread per point (both half-sweeps recomputed)
@@ -623,11 +665,12 @@ __global__ void __launch_bounds__(kRowBlock) kb_a2d_rows(int m, const Item2<T>* 
 }
 
 // Eqs. (Erest2r) then (Erest2b) in one march: the residual of an axis level
-// L (side m) onto the diagonal level L-1 (stored) and from there onto the
-// axis level L-2 (side m/2), the diagonal values of three consecutive rows
-// kept in registers, as the residual kernel does below the finest level.
-// Lanes 1 .. 61 write r1, lanes 2 .. 62 write r2; strips start on odd rows
-// (rows is even) and compute one diagonal row past their end.
+// L (side m) onto the diagonal level L-1 and from there onto the axis level
+// L-2 (side m/2), the diagonal values of three consecutive rows kept in
+// registers, as the residual kernel does below the finest level.  Level
+// L-1's residual is not stored (kb_jac_pair restricts it again); lanes
+// 2 .. 62 write r2; strips start on odd rows (rows is even) and compute one
+// diagonal row past their end.
 template <typename T, int CH>
 __global__ void __launch_bounds__(kRowBlock) kb_rs_pair(int m, const RsPair2<T>* __restrict__ items, int nwx,
                                                         int nwaves, int rows, const Ctl* __restrict__ ctls)
@@ -635,7 +678,6 @@ __global__ void __launch_bounds__(kRowBlock) kb_rs_pair(int m, const RsPair2<T>*
     const RsPair2<T> it = items[blockIdx.y];
     ITEM_GATE(ctls, it.prob);
     const T* __restrict__ rA = it.rA;
-    T* __restrict__ rD = it.r1;
     T* __restrict__ rA2 = it.r2;
     const int lane = threadIdx.x & 63;
     const int wv = rows_wave_id(nwaves);
@@ -645,12 +687,10 @@ __global__ void __launch_bounds__(kRowBlock) kb_rs_pair(int m, const RsPair2<T>*
     const int y0 = 1 + sy * rows;
     const int y1 = min(y0 + rows, m);
     const int mc = m / 2;
-    const bool useful = lane >= 1 && lane <= kResidPairs && t >= 0 && t <= m / 2;
     const bool useful2 = lane >= 2 && lane <= kResidPairs + 1 && t >= 1 && t <= mc - 1;
     const bool colok = t >= 0 && t <= m / 2;
     const bool c0 = t >= 1 && 2 * t <= m - 1, c1 = t >= 0 && 2 * t + 1 <= m - 1;
     const size_t w = (size_t)(m + 1);
-    const int W = m / 2 + 1;
     auto ldr = [&](int j, T& x, T& y) {
         x = y = 0;
         if (!colok || j < 1 || j > m - 1) return;
@@ -682,9 +722,7 @@ __global__ void __launch_bounds__(kRowBlock) kb_rs_pair(int m, const RsPair2<T>*
             const T re = q ? sh : rc1;
             const T rs = q ? rm1 : rm0;
             const T rn = q ? c.y[i] : c.x[i];
-            const int a = 2 * t + q;
             const T d1 = rs2_core(rc, rw, rs, re, rn);
-            if (useful && a >= 1 && a <= m - 1 && j < y1) rD[(size_t)j * W + t] = d1;
             // axis point (t, B) of level L-2, B = (j-1)/2: diagonal rows 2B-1, 2B, 2B+1
             if (q && j - 1 >= y0 && j - 1 < y1) {
                 const int B = (j - 1) >> 1;

@@ -23,8 +23,7 @@ struct Item2 {
 // that of the diagonal level L-1 below it
 template <typename T>
 struct JPair2 {
-    const T* rA;   // residual of level L
-    const T* r1;   // residual of level L-1
+    const T* rA;   // residual of level L (level L-1's is restricted from it on the fly)
     const T* v2;   // correction of level L-2
     T* vA;         // correction of level L (output; level L-1's is not stored)
     int prob;
@@ -36,8 +35,7 @@ struct JPair2 {
 template <typename T>
 struct RsPair2 {
     const T* rA;   // residual of level L
-    T* r1;         // residual of level L-1 (output)
-    T* r2;         // residual of level L-2 (output)
+    T* r2;         // residual of level L-2 (output; level L-1's is not stored)
     int prob;
     int pad;
 };
@@ -48,7 +46,7 @@ struct Fin2 {
     double* u;
     const double* f;
     T* r0;         // finest residual (natural layout)
-    T* r1;         // residual of the first diagonal level (written by the fused residual)
+    T* r1;         // residual of the first diagonal level (written by the unfused residual only)
     const T* v1;   // correction of the first diagonal level (or a zero array)
     const T* v2;   // correction of the level below it (read when the finest kernel runs its Jacobi)
     T* r2;         // residual of that level (written by the residual kernel when fused)

@@ -101,7 +101,7 @@ int plan2_layout(Plan2& P, int nprob, const int* n, int prec, double p)
     P.off_fin = take(sizeof(Fin2<double>) * (size_t)nprob);
     P.off_coarse = take(sizeof(Coarse2B<double>) * (size_t)nprob);
     P.off_net = take(sizeof(bf16_t) * (size_t)NetGeo<2>::PACK);
-    P.off_lg_item = take(sizeof(Item2<double>));
+    P.off_lg_item = take(2 * sizeof(Item2<double>));
     P.off_rs_items.assign(P.Dmax + 1, 0);
     P.off_jac_items.assign(P.Dmax + 1, 0);
     P.n_rs_items.assign(P.Dmax + 1, 0);
@@ -241,15 +241,14 @@ int write_tables(Plan2& P)
         std::vector<RsPair2<T>> rsp;
         for (int i = 0; i < P.nprob; i++)
             if (pair_level(lam, P.D[i], P.pairs))
-                rsp.push_back(RsPair2<T>{at<T>(P, P.off_r[i][lam]), at<T>(P, P.off_r[i][lam - 1]),
-                                         at<T>(P, P.off_r[i][lam - 2]), i, 0});
+                rsp.push_back(RsPair2<T>{at<T>(P, P.off_r[i][lam]), at<T>(P, P.off_r[i][lam - 2]), i, 0});
         if (!rsp.empty() && put(P, P.off_rsp_items[lam], rsp.data(), rsp.size() * sizeof(RsPair2<T>)))
             return MG_ERR_HIP;
         std::vector<JPair2<T>> pairs;
         for (int i = 0; i < P.nprob; i++)
             if (pair_level(lam, P.D[i], P.pairs))
-                pairs.push_back(JPair2<T>{at<T>(P, P.off_r[i][lam]), at<T>(P, P.off_r[i][lam - 1]),
-                                          at<T>(P, P.off_v[i][lam - 2]), at<T>(P, P.off_v[i][lam]), i, 0});
+                pairs.push_back(JPair2<T>{at<T>(P, P.off_r[i][lam]), at<T>(P, P.off_v[i][lam - 2]),
+                                          at<T>(P, P.off_v[i][lam]), i, 0});
         if (!pairs.empty() && put(P, P.off_pair_items[lam], pairs.data(), pairs.size() * sizeof(JPair2<T>)))
             return MG_ERR_HIP;
     }
@@ -292,19 +291,22 @@ void enq_norm_f(Plan2& P, Ctl* ctls, int* nact, bool small_only = false)
     }
 }
 
-// fused: the restriction of r1 onto the level below ((n/2 - 1)^2 interior points) is written too
+// fused (n >= 8): the restriction onto the axis level below the first
+// diagonal level ((n/2 - 1)^2 interior points) is written instead of the
+// diagonal level itself (which the finest Jacobi restricts again)
 double bytes_resid(int n, size_t es, bool fused)
 {
     double inter = (double)(n - 1) * (n - 1), M = n / 2;
-    return 8 * (double)sizeA(n) + 8 * inter + es * inter + (n >= 4 ? es * (M * M + (M - 1) * (M - 1)) : 0) +
-           (fused ? es * (M - 1) * (M - 1) : 0);
+    const bool fz = fused && n >= 8;
+    return 8 * (double)sizeA(n) + 8 * inter + es * inter + (n >= 4 && !fz ? es * (M * M + (M - 1) * (M - 1)) : 0) +
+           (fz ? es * (M - 1) * (M - 1) : 0);
 }
-// fused: the first diagonal level's residual (half the finest points) and
-// the correction below it (a quarter) replace the read of its correction
+// fused: the correction of the level below the first diagonal level (a
+// quarter of the points) replaces the read of the diagonal level's correction
 double bytes_finest(int n, size_t es, bool fused)
 {
     double inter = (double)(n - 1) * (n - 1), M = n / 2;
-    double lev = fused ? (double)sizeD(n) + (M + 1) * (M + 1) : (double)sizeD(n);
+    double lev = fused ? (M + 1) * (M + 1) : (double)sizeD(n);
     return es * (inter + lev) + 16 * inter;
 }
 double bytes_rs(int diag_in, int m, size_t es)
@@ -367,7 +369,7 @@ void enq_cycle(Plan2& P, Ctl* ctls)
         if (int kp = lam + 1 <= P.Dmax ? P.n_rsp_items[lam + 1] : 0) {   // into lam and lam-1
             const int m = side_of(lam + 1);
             const double M = m / 2;
-            Timed t(&P.tm, MG_K_RESTRICT, (bytes_rs(0, m, es) + es * (M - 1) * (M - 1)) * kp);
+            Timed t(&P.tm, MG_K_RESTRICT, es * ((double)sizeA(m) + (M - 1) * (M - 1)) * kp);
             launch_b_rs_pair<T>(m, at<RsPair2<T>>(P, P.off_rsp_items[lam + 1]), kp, ctls, P.stream);
         }
         int k = P.n_rs_items[lam];
@@ -414,8 +416,8 @@ void enq_cycle(Plan2& P, Ctl* ctls)
         if (int kp = P.n_pair_items[lam]) {
             const int m = side_of(lam);
             const double M = m / 2;
-            // r of both levels, v of the level below the pair, v written
-            const double b = es * (2.0 * (double)sizeA(m) + (double)sizeD(m) + (M + 1) * (M + 1));
+            // r of the axis level, v of the level below the pair, v written
+            const double b = es * (2.0 * (double)sizeA(m) + (M + 1) * (M + 1));
             Timed t(&P.tm, MG_K_JACOBI, b * kp);
             launch_b_jac_pair<T>(m, (T)coef(P, lam), (T)coef(P, lam - 1), at<JPair2<T>>(P, P.off_pair_items[lam]), kp,
                                  ctls, P.stream);
@@ -711,15 +713,20 @@ int plan2_solve(Plan2& P, double* const* u, const double* const* f, double rtol,
 }
 
 template <typename T>
-int recompute_diag(Plan2& P, int lam)
+int recompute_diag(Plan2& P, int lam, size_t above, bool jacobi)
 {
-    Item2<T> it{at<T>(P, P.off_r[0][lam]), at<T>(P, P.off_v[0][lam]), at<T>(P, P.off_v[0][lam - 1]), 0, 0};
+    // restriction item (r <- Eq. Erest2r of `in`), then the Jacobi item
+    Item2<T> it[2] = {{at<T>(P, P.off_r[0][lam]), nullptr, at<T>(P, above), 0, 0},
+                      {at<T>(P, P.off_r[0][lam]), at<T>(P, P.off_v[0][lam]), at<T>(P, P.off_v[0][lam - 1]), 0, 0}};
     if (hipStreamSynchronize(P.stream) != hipSuccess ||
-        hipMemcpy(P.ws + P.off_lg_item, &it, sizeof(it), hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(P.ws + P.off_lg_item, it, sizeof(it), hipMemcpyHostToDevice) != hipSuccess)
         return MG_ERR_HIP;
     // the zero block serves as a control block that is never done
-    launch_b_jacobi<T>(1, side_of(lam), b_default_rows(2, side_of(lam)), (T)coef(P, lam),
-                       at<Item2<T>>(P, P.off_lg_item), 1, at<Ctl>(P, P.off_zero), P.stream);
+    Item2<T>* dit = at<Item2<T>>(P, P.off_lg_item);
+    launch_b_restrict<T>(0, side_of(lam), 0, dit, 1, at<Ctl>(P, P.off_zero), P.stream);
+    if (jacobi)
+        launch_b_jacobi<T>(1, side_of(lam), b_default_rows(2, side_of(lam)), (T)coef(P, lam), dit + 1, 1,
+                           at<Ctl>(P, P.off_zero), P.stream);
     return last_launch();
 }
 
@@ -732,12 +739,15 @@ int plan2_level_get(Plan2& P, int depth, int which, double* dst)
     int m = side_of(lam);
     int diag = lam & 1;
     size_t off = (which == 0) ? (depth == 0 ? P.off_r0[0] : P.off_r[0][lam]) : P.off_v[0][lam];
-    if (which == 1 && (lam & 1) && ((lam == D - 1 && fin_fused(D, P.lamc)) || pair_level(lam + 1, D, P.pairs))) {
-        // the cycle computed this diagonal level inside the Jacobi of the
-        // axis level above it without storing it: rerun its Jacobi (same
-        // arithmetic, so the same values) from the residual and the coarser
-        // correction the cycle left
-        int e = P.prec == MG_FP64 ? recompute_diag<double>(P, lam) : recompute_diag<float>(P, lam);
+    if ((lam & 1) && ((lam == D - 1 && fin_fused(D, P.lamc) && side_of(D) >= 8) || pair_level(lam + 1, D, P.pairs))) {
+        // the cycle restricted and relaxed this diagonal level inside the
+        // kernels of the axis level above it without storing either: rerun
+        // its restriction and its Jacobi (same arithmetic, so the same
+        // values) from the axis level's residual and the coarser correction
+        // the cycle left
+        const size_t above = lam == D - 1 ? P.off_r0[0] : P.off_r[0][lam + 1];
+        int e = P.prec == MG_FP64 ? recompute_diag<double>(P, lam, above, which == 1)
+                                  : recompute_diag<float>(P, lam, above, which == 1);
         if (e) return e;
     }
     if (P.prec == MG_FP64) launch_b_level_get<double>(diag, m, at<double>(P, off), dst, P.stream);
