@@ -50,8 +50,8 @@ FAMILY_KERNELS = {
         3: "kb_finest_fused (r1 by Eq. Erest2r, Jacobi of the first diagonal and the finest axis level, u += v)",
         4: "kb_coarse", 5: "kb_finalize"},
     3: {0: "k3_resid_planes (r0 and Eq. Erred onto the red level, norm partials)",
-        1: "k3_r2m_planes, k3_rs_r2m, k3_rs_m2b, k3_rs_g2r",
-        2: "k3_red_planes, k3_mag_planes, k3_green_planes, k3_jac_*",
+        1: "k3_r2m_planes, k3_rs_m2b, k3_down_group (a level group of side 16..64 per launch), k3_rs_*",
+        2: "k3_mag_planes, k3_red_planes, k3_green_planes, k3_up_group (a level group of side 16..64 per launch), k3_jac_mag",
         3: "k3_green_planes<finest> (green-red Jacobi, u += v)",
         4: "k3_coarse", 5: "k_finalize"},
 }

@@ -893,9 +893,10 @@ __global__ void __launch_bounds__(kPlThreads) k3_mag_planes(int m, T cc, const T
 constexpr int kPlMinSide = 128;   // smaller levels: one thread per point
 constexpr int kRdPlMinSide = 128, kGrPlMinSide = 128;   // the red and green steps
 
-// z planes per workgroup (measured on MI355X at 257^3: 8 is best, longer
-// chunks leave too few workgroups in flight)
-inline int pl_zchunk(int) { return 8; }
+// z planes per workgroup (measured on MI355X at 257^3: 8 at side 256,
+// longer chunks leave too few workgroups in flight; 4 at side 128, where 8
+// leaves two waves per SIMD)
+inline int pl_zchunk(int m) { return m >= 256 ? 8 : 4; }
 
 template <typename T>
 void launch_jac3(const Lev3<T>& L, const Lev3<T>& Cr, T* zero, const Ctl* ctl, hipStream_t s)
@@ -947,6 +948,366 @@ void launch_jac3_finest(int n, T c, const T* r0, const T* vR, double* u, const C
     }
     dim3 g((n / 2 + 1 + 255) / 256, n - 1, n - 1);
     hipLaunchKernelGGL(k3_jac_finest<T>, g, dim3(256), 0, s, n, c, r0, vR, u, ctl);
+}
+
+// ------------------------------------------------------ level-group kernels
+// One level group of side m (green m -> red m -> magenta m -> blue = green
+// m/2) in one launch each way, for the sides where the per-level launches
+// are too small to fill the chip (16 .. 64).  A workgroup owns the fine
+// points with every index in [8t, 8t+8) of its tile t = (tx, ty, tz) and
+// computes each intermediate level over the tile plus the halo the next
+// step needs, in LDS; every point is computed with the arithmetic and term
+// order of the per-point functions (rs3_*, jac3_*), so the values equal
+// theirs bit for bit.  Owned points of every level are stored.  All global
+// loads of a workgroup are issued at its start (into registers, a fixed
+// number per thread), so the level steps that follow wait on LDS only.
+constexpr int kGrpT = 8, kGrpThreads = 1024;
+// (at side 128 the per-level kernels are faster: 4096 tiles re-read their
+// halos from L2 more than the launches cost; measured on MI355X)
+constexpr int kGrpMinSide = 16, kGrpMaxDown = 64, kGrpMaxUp = 64;
+
+__device__ inline bool grp_in(int a, int m) { return a >= 1 && a <= m - 1; }
+constexpr int grp_per(int n) { return (n + kGrpThreads - 1) / kGrpThreads; }
+
+// restriction: green r (G, side m) -> red r, magenta r (E, O), blue r (G, side m/2)
+template <typename T>
+__global__ void __launch_bounds__(kGrpThreads) k3_down_group(int m, const T* __restrict__ rG, T* __restrict__ rR,
+                                                             T* __restrict__ rE, T* __restrict__ rO,
+                                                             T* __restrict__ rB, int nt, const Ctl* ctl)
+{
+    DMG_GATE(ctl);
+    // boxes (fine indices, per dimension): green [8t-3, 8t+9], red [8t-2, 8t+8],
+    // magenta [8t-1, 8t+7]; blue points 4t .. 4t+3
+    constexpr int GW = kGrpT + 5, RW = kGrpT + 3, MW = kGrpT + 1, NT = kGrpThreads;
+    constexpr int NG = GW * GW * GW, NR = RW * RW * RW, NM = MW * MW * MW, H = kGrpT / 2;
+    __shared__ T G[NG];
+    __shared__ T R[NR];
+    __shared__ T M[NM];
+    const int bid = xcd_block();
+    const int tx = bid % nt, ty = (bid / nt) % nt, tz = bid / (nt * nt);
+    const int ox = kGrpT * tx, oy = kGrpT * ty, oz = kGrpT * tz;   // first owned fine index
+    const int tid = threadIdx.x;
+    auto own = [&](int a, int b, int c) {
+        return a >= ox && a < ox + kGrpT && b >= oy && b < oy + kGrpT && c >= oz && c < oz + kGrpT;
+    };
+    {
+        T g[grp_per(NG)];
+#pragma unroll
+        for (int k = 0; k < grp_per(NG); k++) {
+            const int p = tid + k * NT;
+            const int a = ox - 3 + p % GW, b = oy - 3 + (p / GW) % GW, c = oz - 3 + p / (GW * GW);
+            g[k] = (p < NG && a >= 0 && a <= m && b >= 0 && b <= m && c >= 0 && c <= m) ? rG[idxG(m, a, b, c)] : T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < grp_per(NG); k++)
+            if (tid + k * NT < NG) G[tid + k * NT] = g[k];
+    }
+    __syncthreads();
+    // Eq. (Erred), as rs3_g2r
+#pragma unroll
+    for (int kk = 0; kk < grp_per(NR); kk++) {
+        const int p = tid + kk * NT;
+        if (p >= NR) break;
+        const int i = p % RW, j = (p / RW) % RW, k = p / (RW * RW);
+        const int a = ox - 2 + i, b = oy - 2 + j, c = oz - 2 + k;
+        T v = T(0);
+        if (!((a + b + c) & 1) && grp_in(a, m) && grp_in(b, m) && grp_in(c, m)) {
+            const int q = ((k + 1) * GW + (j + 1)) * GW + (i + 1), w = GW, w2 = GW * GW;
+            v = (6 * G[q] + G[q + 1] + G[q - 1] + G[q + w] + G[q - w] + G[q + w2] + G[q - w2]) * (T(1) / T(12));
+            if (own(a, b, c)) rR[idxR(m, a, b, c)] = v;
+        }
+        R[p] = v;
+    }
+    __syncthreads();
+    // Eqs. (Ermagc), (Ermagm), as rs3_r2mE / rs3_r2mO
+#pragma unroll
+    for (int kk = 0; kk < grp_per(NM); kk++) {
+        const int p = tid + kk * NT;
+        if (p >= NM) break;
+        const int i = p % MW, j = (p / MW) % MW, k = p / (MW * MW);
+        const int a = ox - 1 + i, b = oy - 1 + j, c = oz - 1 + k;
+        auto r = [&](int da, int db, int dc) { return R[((k + 1 + dc) * RW + (j + 1 + db)) * RW + (i + 1 + da)]; };
+        T v = T(0);
+        if (!((a | b | c) & 1) && grp_in(a, m) && grp_in(b, m) && grp_in(c, m)) {
+            v = (12 * r(0, 0, 0)
+                 + r(1, 1, 0) + r(1, -1, 0)
+                 + r(-1, -1, 0) + r(-1, 1, 0)
+                 + r(1, 0, 1) + r(1, 0, -1)
+                 + r(-1, 0, -1) + r(-1, 0, 1)
+                 + r(0, 1, 1) + r(0, 1, -1)
+                 + r(0, -1, -1) + r(0, -1, 1)) * (T(1) / T(24));
+            if (own(a, b, c)) rE[idxME(m, a, b, c)] = v;
+        } else if ((a & b & c & 1) && grp_in(a, m) && grp_in(b, m) && grp_in(c, m)) {
+            v = (r(1, 0, 0) + r(-1, 0, 0) + r(0, 1, 0) + r(0, -1, 0) + r(0, 0, 1) + r(0, 0, -1)) * (T(1) / T(6));
+            if (own(a, b, c)) rO[idxMO(m, a, b, c)] = v;
+        }
+        M[p] = v;
+    }
+    __syncthreads();
+    // Eq. (Erblu), as rs3_m2b
+    const int mc = m / 2;
+    if (tid < H * H * H) {
+        const int p = tid;
+        const int A = ox / 2 + p % H, B = oy / 2 + (p / H) % H, C = oz / 2 + p / (H * H);
+        if (grp_in(A, mc) && grp_in(B, mc) && grp_in(C, mc)) {
+            const int i = 2 * A - (ox - 1), j = 2 * B - (oy - 1), k = 2 * C - (oz - 1);
+            auto e = [&](int da, int db, int dc) { return M[((k + dc) * MW + (j + db)) * MW + (i + da)]; };
+            rB[idxG(mc, A, B, C)] = (8 * e(0, 0, 0)
+                                     + e(1, 1, 1) + e(1, 1, -1)
+                                     + e(1, -1, 1) + e(1, -1, -1)
+                                     + e(-1, 1, 1) + e(-1, 1, -1)
+                                     + e(-1, -1, 1) + e(-1, -1, -1)) * T(0.0625);
+        }
+    }
+}
+
+// Jacobi: magenta (Eqs. Emprolm, Emprolb) from the blue correction, red
+// (Eqs. Erprolr, Erprolm) from the new magenta values, green (Eqs. Egprolg,
+// Egprolr) from the new red values.  cm: magenta coefficient; c1, c2: red;
+// cg: green.
+template <typename T>
+struct GrpUp {
+    const T *rG, *rR, *rE, *rO, *vB;
+    T *vG, *vR, *vE, *vO;
+    T cm, c1, c2, cg;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kGrpThreads) k3_up_group(int m, GrpUp<T> L, int nt, const Ctl* ctl)
+{
+    DMG_GATE(ctl);
+    // boxes (fine indices): blue half indices [4t-3, 4t+6]; magenta centres
+    // (odd) [8t-5, 8t+11], corners (even) [8t-4, 8t+10]; red [8t-3, 8t+10]
+    // (corners over [8t-2, 8t+9]); green F [8t-1, 8t+8]; green C: the tile
+    constexpr int BW = kGrpT / 2 + 6, OW = kGrpT / 2 + 5, EW = kGrpT / 2 + 4, RW = kGrpT + 6, FW = kGrpT + 2;
+    constexpr int NT = kGrpThreads, NB = BW * BW * BW, NO = OW * OW * OW, NE = EW * EW * EW, NR = RW * RW * RW,
+                  NF = FW * FW * FW, NC = kGrpT * kGrpT * kGrpT;
+    __shared__ T Bv[NB];
+    __shared__ T Mo[NO];
+    __shared__ T Me[NE];
+    __shared__ T Rv[NR];
+    __shared__ T Gf[NF];
+    const int bid = xcd_block();
+    const int tx = bid % nt, ty = (bid / nt) % nt, tz = bid / (nt * nt);
+    const int ox = kGrpT * tx, oy = kGrpT * ty, oz = kGrpT * tz;
+    const int tid = threadIdx.x;
+    const int mc = m / 2;
+    auto own = [&](int a, int b, int c) {
+        return a >= ox && a < ox + kGrpT && b >= oy && b < oy + kGrpT && c >= oz && c < oz + kGrpT;
+    };
+    auto inside = [&](int a, int b, int c) { return grp_in(a, m) && grp_in(b, m) && grp_in(c, m); };
+    const int bx = ox / 2 - 3, by = oy / 2 - 3, bz = oz / 2 - 3;
+    // point p of each step's box
+    auto pO = [&](int p, int& a, int& b, int& c) {
+        a = ox - 5 + 2 * (p % OW); b = oy - 5 + 2 * ((p / OW) % OW); c = oz - 5 + 2 * (p / (OW * OW));
+    };
+    auto pE = [&](int p, int& a, int& b, int& c) {
+        a = ox - 4 + 2 * (p % EW); b = oy - 4 + 2 * ((p / EW) % EW); c = oz - 4 + 2 * (p / (EW * EW));
+    };
+    auto pR = [&](int p, int& a, int& b, int& c) {
+        a = ox - 3 + p % RW; b = oy - 3 + (p / RW) % RW; c = oz - 3 + p / (RW * RW);
+    };
+    auto pF = [&](int p, int& a, int& b, int& c) {
+        a = ox - 1 + p % FW; b = oy - 1 + (p / FW) % FW; c = oz - 1 + p / (FW * FW);
+    };
+    auto pC = [&](int p, int& a, int& b, int& c) {
+        a = ox + p % kGrpT; b = oy + (p / kGrpT) % kGrpT; c = oz + p / (kGrpT * kGrpT);
+    };
+    auto isface = [](int a, int b, int c) { return (a & 1) + (b & 1) + (c & 1) == 2; };
+    // every global input of the workgroup, loaded up front
+    T lb[grp_per(NB)], lo[grp_per(NO)], le[grp_per(NE)], lr[grp_per(NR)], lf[grp_per(NF)], lc[grp_per(NC)];
+#pragma unroll
+    for (int k = 0; k < grp_per(NB); k++) {
+        const int p = tid + k * NT;
+        const int A = bx + p % BW, B = by + (p / BW) % BW, C = bz + p / (BW * BW);
+        lb[k] = (p < NB && A >= 0 && A <= mc && B >= 0 && B <= mc && C >= 0 && C <= mc) ? L.vB[idxG(mc, A, B, C)] : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < grp_per(NO); k++) {
+        const int p = tid + k * NT;
+        int a, b, c;
+        pO(p, a, b, c);
+        lo[k] = (p < NO && inside(a, b, c)) ? L.rO[idxMO(m, a, b, c)] : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < grp_per(NE); k++) {
+        const int p = tid + k * NT;
+        int a, b, c;
+        pE(p, a, b, c);
+        le[k] = (p < NE && inside(a, b, c)) ? L.rE[idxME(m, a, b, c)] : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < grp_per(NR); k++) {   // face centres over the box, corners over the box less its border
+        const int p = tid + k * NT;
+        int a, b, c;
+        pR(p, a, b, c);
+        lr[k] = (p < NR && !((a + b + c) & 1) && inside(a, b, c)) ? L.rR[idxR(m, a, b, c)] : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < grp_per(NF); k++) {
+        const int p = tid + k * NT;
+        int a, b, c;
+        pF(p, a, b, c);
+        lf[k] = (p < NF && ((a + b + c) & 1) && inside(a, b, c)) ? L.rG[idxG(m, a, b, c)] : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < grp_per(NC); k++) {
+        const int p = tid + k * NT;
+        int a, b, c;
+        pC(p, a, b, c);
+        lc[k] = (p < NC && !((a + b + c) & 1) && inside(a, b, c)) ? L.rG[idxG(m, a, b, c)] : T(0);
+    }
+#pragma unroll
+    for (int k = 0; k < grp_per(NB); k++)
+        if (tid + k * NT < NB) Bv[tid + k * NT] = lb[k];
+    __syncthreads();
+    // magenta centres, as jac3_magF
+#pragma unroll
+    for (int kk = 0; kk < grp_per(NO); kk++) {
+        const int p = tid + kk * NT;
+        if (p >= NO) break;
+        int a, b, c;
+        pO(p, a, b, c);
+        T v = T(0);
+        if (inside(a, b, c)) {
+            const int q = ((((c - 1) >> 1) - bz) * BW + (((b - 1) >> 1) - by)) * BW + (((a - 1) >> 1) - bx);
+            const int w = BW, w2 = BW * BW;
+            v = (-L.cm * lo[kk]
+                 + Bv[q + 1 + w + w2] + Bv[q + 1 + w] + Bv[q + 1 + w2] + Bv[q + 1]
+                 + Bv[q + w + w2] + Bv[q + w] + Bv[q + w2] + Bv[q]) * T(0.125);
+            if (own(a, b, c)) L.vO[idxMO(m, a, b, c)] = v;
+        }
+        Mo[p] = v;
+    }
+    __syncthreads();
+    // magenta corners, as jac3_magC
+#pragma unroll
+    for (int kk = 0; kk < grp_per(NE); kk++) {
+        const int p = tid + kk * NT;
+        if (p >= NE) break;
+        const int i = p % EW, j = (p / EW) % EW, k = p / (EW * EW);
+        int a, b, c;
+        pE(p, a, b, c);
+        T v = T(0);
+        if (inside(a, b, c)) {
+            // centre (a+da, b+db, c+dc) of Mo: a+1 -> i+1, a-1 -> i
+            auto o = [&](int da, int db, int dc) {
+                return Mo[((k + (dc + 1) / 2) * OW + (j + (db + 1) / 2)) * OW + (i + (da + 1) / 2)];
+            };
+            T sm = o(1, 1, 1) + o(1, 1, -1) + o(1, -1, 1) + o(1, -1, -1) + o(-1, 1, 1) + o(-1, 1, -1) + o(-1, -1, 1) +
+                   o(-1, -1, -1);
+            v = (-L.cm * le[kk] + sm) * T(0.125);
+            if (own(a, b, c)) L.vE[idxME(m, a, b, c)] = v;
+        }
+        Me[p] = v;
+    }
+    __syncthreads();
+    // magenta value at fine (a, b, c): a corner (all even) or a centre (all odd)
+    auto mE = [&](int a, int b, int c) {
+        return Me[(((c - (oz - 4)) >> 1) * EW + ((b - (oy - 4)) >> 1)) * EW + ((a - (ox - 4)) >> 1)];
+    };
+    auto mO = [&](int a, int b, int c) {
+        return Mo[(((c - (oz - 5)) >> 1) * OW + ((b - (oy - 5)) >> 1)) * OW + ((a - (ox - 5)) >> 1)];
+    };
+    // red face centres, as jac3_redF (other slots: 0 for now)
+#pragma unroll
+    for (int kk = 0; kk < grp_per(NR); kk++) {
+        const int p = tid + kk * NT;
+        if (p >= NR) break;
+        int a, b, c;
+        pR(p, a, b, c);
+        T v = T(0);
+        if (isface(a, b, c) && inside(a, b, c)) {
+            T sm;
+            if (!(c & 1))
+                sm = 2 * (mO(a, b, c + 1) + mO(a, b, c - 1))
+                     + mE(a + 1, b + 1, c) + mE(a + 1, b - 1, c)
+                     + mE(a - 1, b - 1, c) + mE(a - 1, b + 1, c);
+            else if (!(a & 1))
+                sm = 2 * (mO(a + 1, b, c) + mO(a - 1, b, c))
+                     + mE(a, b + 1, c + 1) + mE(a, b + 1, c - 1)
+                     + mE(a, b - 1, c - 1) + mE(a, b - 1, c + 1);
+            else
+                sm = 2 * (mO(a, b + 1, c) + mO(a, b - 1, c))
+                     + mE(a + 1, b, c + 1) + mE(a - 1, b, c + 1)
+                     + mE(a - 1, b, c - 1) + mE(a + 1, b, c - 1);
+            v = (-L.c1 * lr[kk] + sm) * T(0.125);
+            if (own(a, b, c)) L.vR[idxR(m, a, b, c)] = v;
+        }
+        Rv[p] = v;
+    }
+    __syncthreads();
+    // red corners over [8t-2, 8t+9], as jac3_redC: they read face centres
+    // only, so they are written into the same array
+#pragma unroll
+    for (int kk = 0; kk < grp_per(NR); kk++) {
+        const int p = tid + kk * NT;
+        if (p >= NR) break;
+        const int i = p % RW, j = (p / RW) % RW, k = p / (RW * RW);
+        int a, b, c;
+        pR(p, a, b, c);
+        if (!((a | b | c) & 1) && i >= 1 && i < RW - 1 && j >= 1 && j < RW - 1 && k >= 1 && k < RW - 1 &&
+            inside(a, b, c)) {
+            auto f = [&](int da, int db, int dc) { return Rv[p + (dc * RW + db) * RW + da]; };
+            T sm = f(1, 1, 0) + f(1, -1, 0) + f(-1, -1, 0) + f(-1, 1, 0)
+                 + f(1, 0, 1) + f(1, 0, -1) + f(-1, 0, -1) + f(-1, 0, 1)
+                 + f(0, 1, 1) + f(0, 1, -1) + f(0, -1, -1) + f(0, -1, 1);
+            const T v = (-L.c2 * lr[kk] + sm) * (T(1) / T(12));
+            if (own(a, b, c)) L.vR[idxR(m, a, b, c)] = v;
+            Rv[p] = v;
+        }
+    }
+    __syncthreads();
+    // green F points (a+b+c odd) over [8t-1, 8t+8], as jac3_greenF
+#pragma unroll
+    for (int kk = 0; kk < grp_per(NF); kk++) {
+        const int p = tid + kk * NT;
+        if (p >= NF) break;
+        const int i = p % FW, j = (p / FW) % FW, k = p / (FW * FW);
+        int a, b, c;
+        pF(p, a, b, c);
+        T v = T(0);
+        if (((a + b + c) & 1) && inside(a, b, c)) {
+            const int q = ((k + 2) * RW + (j + 2)) * RW + (i + 2), w = RW, w2 = RW * RW;
+            T sm = Rv[q + 1] + Rv[q - 1] + Rv[q + w] + Rv[q - w] + Rv[q + w2] + Rv[q - w2];
+            v = (-L.cg * lf[kk] + sm) * (T(1) / T(6));
+            if (own(a, b, c)) L.vG[idxG(m, a, b, c)] = v;
+        }
+        Gf[p] = v;
+    }
+    __syncthreads();
+    // green C points of the tile, as jac3_greenC
+#pragma unroll
+    for (int kk = 0; kk < grp_per(NC); kk++) {
+        const int p = tid + kk * NT;
+        if (p >= NC) break;
+        int a, b, c;
+        pC(p, a, b, c);
+        if (((a + b + c) & 1) || !inside(a, b, c)) continue;
+        const int q = ((c - oz + 1) * FW + (b - oy + 1)) * FW + (a - ox + 1), w = FW, w2 = FW * FW;
+        T sm = Gf[q + 1] + Gf[q - 1] + Gf[q + w] + Gf[q - w] + Gf[q + w2] + Gf[q - w2];
+        L.vG[idxG(m, a, b, c)] = (-L.cg * lc[kk] + sm) * (T(1) / T(6));
+    }
+}
+
+bool group3_ok(int m, bool up) { return m >= kGrpMinSide && m <= (up ? kGrpMaxUp : kGrpMaxDown); }
+
+template <typename T>
+void launch_down_group3(const Lev3<T>& G, const Lev3<T>& R, const Lev3<T>& M, const Lev3<T>& B, const Ctl* ctl,
+                        hipStream_t s)
+{
+    const int nt = G.m / kGrpT;
+    hipLaunchKernelGGL(k3_down_group<T>, dim3(nt * nt * nt), dim3(kGrpThreads), 0, s, G.m, G.r, R.r, M.r, M.r2, B.r,
+                       nt, ctl);
+}
+
+template <typename T>
+void launch_up_group3(const Lev3<T>& G, const Lev3<T>& R, const Lev3<T>& M, const Lev3<T>& B, const Ctl* ctl,
+                      hipStream_t s)
+{
+    const int nt = G.m / kGrpT;
+    GrpUp<T> L{G.r, R.r, M.r, M.r2, B.v, G.v, R.v, M.v, M.v2, M.c, R.c, R.c2, G.c};
+    hipLaunchKernelGGL(k3_up_group<T>, dim3(nt * nt * nt), dim3(kGrpThreads), 0, s, G.m, L, nt, ctl);
 }
 
 // ------------------------------------------------- coarse persistent kernel
@@ -1341,6 +1702,10 @@ void launch_level_get3(int kind, int m, const T* src, const T* src2, double* dst
     template void launch_rs3<T>(const Lev3<T>&, const Lev3<T>&, const Ctl*, hipStream_t);                 \
     template void launch_jac3<T>(const Lev3<T>&, const Lev3<T>&, T*, const Ctl*, hipStream_t);            \
     template void launch_jac3_finest<T>(int, T, const T*, const T*, double*, const Ctl*, hipStream_t);    \
+    template void launch_down_group3<T>(const Lev3<T>&, const Lev3<T>&, const Lev3<T>&, const Lev3<T>&,      \
+                                        const Ctl*, hipStream_t);                                             \
+    template void launch_up_group3<T>(const Lev3<T>&, const Lev3<T>&, const Lev3<T>&, const Lev3<T>&,        \
+                                      const Ctl*, hipStream_t);                                               \
     template void launch_coarse3<T>(const Coarse3<T>&, const Ctl*, hipStream_t);                          \
     template void launch_coarse3_net<T>(const Coarse3<T>&, Ctl*, const bf16_t*, hipStream_t);             \
     template void launch_level_get3<T>(int, int, const T*, const T*, double*, hipStream_t);              \

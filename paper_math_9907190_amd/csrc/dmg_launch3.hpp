@@ -162,6 +162,16 @@ template <typename T>
 void launch_jac3(const Lev3<T>& L, const Lev3<T>& coarser, T* zero, const Ctl* ctl, hipStream_t s);
 template <typename T>
 void launch_jac3_finest(int n, T c, const T* r0, const T* vR, double* u, const Ctl* ctl, hipStream_t s);
+// one level group (green G -> red R -> magenta M -> blue B, side 16 .. 64)
+// in one launch each way: the three restrictions from G's residual, or the
+// three Jacobi steps from B's correction
+bool group3_ok(int m, bool up);
+template <typename T>
+void launch_down_group3(const Lev3<T>& G, const Lev3<T>& R, const Lev3<T>& M, const Lev3<T>& B, const Ctl* ctl,
+                        hipStream_t s);
+template <typename T>
+void launch_up_group3(const Lev3<T>& G, const Lev3<T>& R, const Lev3<T>& M, const Lev3<T>& B, const Ctl* ctl,
+                      hipStream_t s);
 template <typename T>
 void launch_coarse3(const Coarse3<T>& a, const Ctl* ctl, hipStream_t s);
 // the coarse kernel with the learned correction at the green level of side 8 (wf: packed forward weights)

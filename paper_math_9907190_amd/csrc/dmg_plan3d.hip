@@ -1,8 +1,10 @@
 // Host runtime of the 3D solver (Roberts, Section 3): level plan, workspace
 // carving and launch sequencing of one V-cycle: residual on the finest
-// green grid, restriction green -> red -> magenta -> blue group by group,
-// every level of side <= 8 in one persistent workgroup, Jacobi back up
-// (magenta-blue, red-magenta, green-red), the finest fused with u += v.
+// green grid, restriction green -> red -> magenta -> blue group by group
+// (a group of side 16 .. 64 in one launch), every level of side <= 8 in
+// one persistent workgroup, Jacobi back up (magenta-blue, red-magenta,
+// green-red; again one launch per group of side 16 .. 64), the finest fused
+// with u += v.
 #include "dmg_launch.hpp"
 #include "dmg_launch3.hpp"
 #include "dmg_net.hpp"
@@ -46,6 +48,32 @@ double bytes_finest3(int n, size_t es)
     return es * (inter + (double)sizeR(n)) + 16 * inter;
 }
 
+// A level group (green at depth g > 0, then red, magenta, and the blue =
+// green at g+3) runs each way in one launch when its side allows: down when
+// the restrictions into g+1 .. g+3 are launched here (g+3 <= last_rs), up
+// when the Jacobi steps of g+2 .. g are (g+2 <= first_jac).
+bool group_down(const Plan3& P, int g, int last_rs)
+{
+    return g >= 3 && g % 3 == 0 && g + 3 <= last_rs && group3_ok(P.lev[g].m, false);
+}
+bool group_up(const Plan3& P, int g, int first_jac)
+{
+    return g >= 3 && g % 3 == 0 && g + 2 <= first_jac && g + 3 <= P.D && group3_ok(P.lev[g].m, true);
+}
+// algorithmic bytes: green residual read; red, magenta and blue residuals written
+double bytes_down_group3(int m, size_t es)
+{
+    double M = m / 2, c = (double)(m - 1) * (m - 1) * (m - 1);
+    return (double)es * (c + c / 2 + (M - 1) * (M - 1) * (M - 1) + M * M * M + (M - 1) * (M - 1) * (M - 1));
+}
+// blue correction and the three residuals read; the three corrections written
+double bytes_up_group3(int m, size_t es)
+{
+    double M = m / 2, c = (double)(m - 1) * (m - 1) * (m - 1);
+    double mag = (M - 1) * (M - 1) * (M - 1) + M * M * M;
+    return (double)es * (sizeG(m / 2) + 2 * (c + c / 2 + mag));
+}
+
 template <typename T>
 void enqueue_cycle3(Plan3& P, double* u, const Ctl* ctl)
 {
@@ -68,6 +96,12 @@ void enqueue_cycle3(Plan3& P, double* u, const Ctl* ctl)
     };
     int last_rs = dc ? dc : D;
     for (int d = P.fused_resid ? 2 : 1; d <= last_rs; d++) {   // the fused residual produced level 1
+        if (group_down(P, d - 1, last_rs)) {   // the group's three restrictions in one launch
+            Timed t(&P.tm, MG_K_RESTRICT, bytes_down_group3(P.lev[d - 1].m, es));
+            launch_down_group3<T>(lv(d - 1), lv(d), lv(d + 1), lv(d + 2), ctl, s);
+            d += 2;
+            continue;
+        }
         Timed t(&P.tm, MG_K_RESTRICT, bytes_rs3(P.lev[d].kind, P.lev[d - 1].m, es));
         launch_rs3<T>(lv(d - 1), lv(d), ctl, s);
     }
@@ -84,7 +118,14 @@ void enqueue_cycle3(Plan3& P, double* u, const Ctl* ctl)
         if (P.has_net) launch_coarse3_net<T>(a, at<Ctl>(P, P.ctl), at<bf16_t>(P, P.net), s);
         else launch_coarse3<T>(a, ctl, s);
     }
-    for (int d = (dc ? dc - 1 : D); d >= 1; d--) {
+    const int first_jac = dc ? dc - 1 : D;
+    for (int d = first_jac; d >= 1; d--) {
+        if (d >= 2 && group_up(P, d - 2, first_jac)) {   // magenta d, red d-1, green d-2 in one launch
+            Timed t(&P.tm, MG_K_JACOBI, bytes_up_group3(P.lev[d - 2].m, es));
+            launch_up_group3<T>(lv(d - 2), lv(d - 1), lv(d), lv(d + 1), ctl, s);
+            d -= 2;
+            continue;
+        }
         Lev3<T> c = (d == D) ? Lev3<T>{} : lv(d + 1);
         Timed t(&P.tm, MG_K_JACOBI, bytes_jac3(P.lev[d].kind, P.lev[d].m, es));
         launch_jac3<T>(lv(d), c, at<T>(P, P.zero), ctl, s);
