@@ -573,7 +573,8 @@ def main():
                     help="kernel family for the roofline (-1: the single-kernel family that takes the most time)")
     ap.add_argument("--cpu-runs", type=int, default=3, help="oracle runs per CPU-baseline leg (median reported)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (CPU baseline and errors against it)")
-    ap.add_argument("--no-extra", action="store_true", help="skip the batched and 3D workloads")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="only the 4097^2 modes (no comparison cycles, batched, fourth-order or 3D workloads)")
     ap.add_argument("--no-learned", action="store_true", help="skip training and the learned modes")
     ap.add_argument("--cube-only", action="store_true", help="only the 3D 257^3 workload (for profiling)")
     ap.add_argument("--fourth-only", action="store_true", help="only the fourth-order solves of the 2D workload")
@@ -724,13 +725,14 @@ def main():
         modes[k]["speedup_vs_fp64"] = round(modes["fp64"]["ms_to_rtol"] / modes[k]["ms_to_rtol"], 3)
 
     extra = {}
-    log("conventional comparison cycle on the same workload")
-    extra["usual%d" % (n + 1)] = bench_usual(dmg, f, dev, torch, args,
-                                             {k: modes[k]["ms_to_rtol"] for k in ("fp64", "fp32_refined")},
-                                             refs.get("square"))
-    log("more sweeps per level and W-cycles on the same workload")
-    extra["cycles%d" % (n + 1)] = bench_cycles(dmg, f, dev, torch, args, modes["fp64"]["ms_to_rtol"], refs.get("square"))
     if not args.no_extra:
+        log("conventional comparison cycle on the same workload")
+        extra["usual%d" % (n + 1)] = bench_usual(dmg, f, dev, torch, args,
+                                                 {k: modes[k]["ms_to_rtol"] for k in ("fp64", "fp32_refined")},
+                                                 refs.get("square"))
+        log("more sweeps per level and W-cycles on the same workload")
+        extra["cycles%d" % (n + 1)] = bench_cycles(dmg, f, dev, torch, args, modes["fp64"]["ms_to_rtol"],
+                                                   refs.get("square"))
         log("fourth-order residual: direct and two-stage solves")
         extra["fourth_order%d" % (n + 1)] = bench_fourth_order(dmg, f, dev, torch, args, refs.get("square_o4"))
         extra["batched512"] = bench_batched(dmg, workloads, dev, torch, args, not args.no_cpu)

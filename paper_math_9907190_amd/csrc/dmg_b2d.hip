@@ -57,45 +57,51 @@ namespace dmg {
 // (its FZ variants run three waves per SIMD in both precisions).
 // WF: the partial sums of f^2 over the same interior points too (the first
 // evaluation of a solve, so that ||f|| needs no pass of its own).
+// MIR (FZ strips of odd index): the strip is marched from its last row to
+// its first, as the same march over the grid mirrored in y (rows m - j; m is
+// even, so parities are unchanged); the stencil operands are passed in the
+// unmirrored order, so every value has the same bits.  Two neighbouring
+// strips then reach the halo rows they share at the same time, while those
+// rows are still in L2.  A mirrored strip starts on an even row, so it
+// computes one diagonal row before its start instead of one past its end.
 constexpr int kResidPairs = 61;
-template <typename T, int CH, bool NT, bool FZ, bool M4, bool WF>
-__global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu((FZ && (sizeof(T) == 8 || M4)) || WF ? 3 : 4))) kb_resid(int m, double inv_h2, const Fin2<T>* __restrict__ items,
-                                                      int nwx, int nwaves, int rows, const Ctl* __restrict__ ctls)
+template <typename T, int CH, bool NT, bool FZ, bool M4, bool WF, bool MIR>
+__device__ inline void resid_body(int m, double inv_h2, const Fin2<T>& it, int wv, int nwx, int rows, double& acc,
+                                  double& accf)
 {
-    const Fin2<T> it = items[blockIdx.y];
-    ITEM_GATE(ctls, it.prob);
     const double* __restrict__ u = it.u;
     const double* __restrict__ f = it.f;
     T* __restrict__ r0 = it.r0;
     T* __restrict__ rD = it.r1;
     T* __restrict__ rA2 = it.r2;
     const int lane = threadIdx.x & 63;
-    const int wv = rows_wave_id(nwaves);
-    const bool live = wv < nwaves;
     const int wx = wv % nwx, sy = wv / nwx;
     const int t = wx * kResidPairs - 1 + lane;
-    const int y0 = 1 + sy * rows;
-    const int y1 = min(y0 + rows, m);
-    const int ylast = y1 + (FZ ? 1 : 0);   // last row of the march
+    const int ya = 1 + sy * rows, yb = min(ya + rows, m);   // the strip's grid rows [ya, yb)
+    const int y0 = MIR ? m - yb + 1 : ya;                   // the same rows as marched
+    const int y1 = MIR ? m - ya + 1 : yb;
+    const int dlo = MIR ? y0 - 1 : y0;                      // first diagonal row computed
+    const int ylast = FZ && !MIR ? y1 + 1 : y1;             // last row of the march
     const int mc = m / 2;
+    auto R = [&](int j) { return MIR ? m - j : j; };        // marched row -> grid row
     const bool useful = lane >= 1 && lane <= kResidPairs && t >= 0 && t <= m / 2;
     const bool useful2 = lane >= 2 && lane <= kResidPairs + 1 && t >= 1 && t <= mc - 1;
     const size_t w = (size_t)(m + 1);
     const int W = m / 2 + 1;
     const bool c0 = t >= 1 && 2 * t <= m - 1, c1 = t >= 0 && 2 * t + 1 <= m - 1;  // columns 2t, 2t+1 interior
-    const bool colok = live && t >= 0 && t <= m / 2;
-    // u at columns 2t, 2t+1 of row j (column m+1 does not exist)
+    const bool colok = t >= 0 && t <= m / 2;
+    // u at columns 2t, 2t+1 of marched row j (column m+1 does not exist)
     auto ldu = [&](int j, double& x, double& y) {
         x = y = 0;
         if (!colok || j < 0 || j > m) return;
-        const double* p = u + (size_t)j * w + 2 * t;
+        const double* p = u + (size_t)R(j) * w + 2 * t;
         if (t < m / 2) { P2<double> v = *reinterpret_cast<const P2<double>*>(p); x = v.x; y = v.y; }
         else x = p[0];
     };
     auto ldf = [&](int j, double& x, double& y) {
         x = y = 0;
         if (!colok || j < 1 || j > m - 1) return;
-        const double* q = f + (size_t)j * w + 2 * t;
+        const double* q = f + (size_t)R(j) * w + 2 * t;
         P2<double> v = NT ? ld_pair_nt(q) : *reinterpret_cast<const P2<double>*>(q);
         x = v.x; y = v.y;
     };
@@ -108,11 +114,11 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
             if (j <= ylast) { ldu(j + 2, c.ux[i], c.uy[i]); ldf(j, c.fx[i], c.fy[i]); }
         }
     };
-    double acc = 0, accf = 0;
-    double um0, um1, uc0, uc1, up0, up1;  // u rows j-1, j, j+1 of the lane's pair
-    ldu(y0 - 2, um0, um1);
-    ldu(y0 - 1, uc0, uc1);
-    ldu(y0, up0, up1);
+    const int jstart = dlo - 1;   // r rows from dlo - 1 on make the diagonal rows from dlo on
+    double um0, um1, uc0, uc1, up0, up1;  // u rows j-1, j, j+1 (marched) of the lane's pair
+    ldu(jstart - 1, um0, um1);
+    ldu(jstart, uc0, uc1);
+    ldu(jstart + 1, up0, up1);
     T rm2_0 = 0, rm2_1 = 0, rm1_0 = 0, rm1_1 = 0;  // r rows j-2, j-1 (as stored)
     T d3 = 0, d2 = 0;                               // FZ: diagonal values of rows j-3, j-2
     // P0: parity of jb (-1: not known at compile time).  With the vector
@@ -126,21 +132,26 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
             bool rowin = j >= 1 && j <= m - 1;
             double uW = __shfl_up(uc1, 1);   // u(2t-1, j)
             double uE = __shfl_down(uc0, 1); // u(2t+2, j)
+            // grid south / north rows of the lane's pair (marched j-1 / j+1 unless mirrored)
+            const double us0 = MIR ? up0 : um0, us1 = MIR ? up1 : um1;
+            const double un0 = MIR ? um0 : up0, un1 = MIR ? um1 : up1;
             double x0, x1;
             if constexpr (M4) {
                 // Eq. (Efos2): -20 centre, 4 x (S, N, W, E), then NE, NW, SW, SE
-                const double mW = __shfl_up(um1, 1), mE = __shfl_down(um0, 1);   // row j-1, columns 2t-1, 2t+2
-                const double pW = __shfl_up(up1, 1), pE = __shfl_down(up0, 1);   // row j+1
-                x0 = c.fx[i] - (-20 * uc0 + 4 * (um0 + up0 + uW + uc1) + up1 + pW + mW + um1) * inv_h2;
-                x1 = c.fy[i] - (-20 * uc1 + 4 * (um1 + up1 + uc0 + uE) + pE + up0 + um0 + mE) * inv_h2;
+                const double mW = __shfl_up(um1, 1), mE = __shfl_down(um0, 1);   // marched row j-1, columns 2t-1, 2t+2
+                const double pW = __shfl_up(up1, 1), pE = __shfl_down(up0, 1);   // marched row j+1
+                const double sW = MIR ? pW : mW, sE = MIR ? pE : mE;            // grid south row
+                const double nW = MIR ? mW : pW, nE = MIR ? mE : pE;            // grid north row
+                x0 = c.fx[i] - (-20 * uc0 + 4 * (us0 + un0 + uW + uc1) + un1 + nW + sW + us1) * inv_h2;
+                x1 = c.fy[i] - (-20 * uc1 + 4 * (us1 + un1 + uc0 + uE) + nE + un0 + us0 + sE) * inv_h2;
             } else {
-                x0 = c.fx[i] - (uW + um0 + uc1 + up0 - 4 * uc0) * inv_h2;
-                x1 = c.fy[i] - (uc0 + um1 + uE + up1 - 4 * uc1) * inv_h2;
+                x0 = c.fx[i] - (uW + us0 + uc1 + un0 - 4 * uc0) * inv_h2;
+                x1 = c.fy[i] - (uc0 + us1 + uE + un1 - 4 * uc1) * inv_h2;
             }
             T r0j = (rowin && c0) ? (T)x0 : T(0);
             T r1j = (rowin && c1) ? (T)x1 : T(0);
             if (j >= y0 && j < y1 && useful) {
-                T* p = r0 + (size_t)j * w + 2 * t;
+                T* p = r0 + (size_t)R(j) * w + 2 * t;
                 if (c0 && c1) {
                     if (NT) st_pair_nt(p, r0j, r1j);
                     else *reinterpret_cast<P2<T>*>(p) = P2<T>{r0j, r1j};
@@ -158,7 +169,7 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
                     if constexpr (WF) accf += c.fx[i] * c.fx[i];
                 }
             }
-            if (j - 1 >= y0) {
+            if (j - 1 >= dlo) {
                 // Eq. Erest2r at the diagonal point of row j-1 (a + j-1 even)
                 constexpr int p0 = decltype(P0)::value;
                 const int q = p0 >= 0 ? (p0 + i + 1) & 1 : (j - 1) & 1;
@@ -166,22 +177,24 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
                 T rc = q ? rm1_1 : rm1_0;
                 T rw = q ? rm1_0 : sh;
                 T re = q ? sh : rm1_1;
-                T rs = q ? rm2_1 : rm2_0;
-                T rn = q ? r1j : r0j;
+                T rlo = q ? rm2_1 : rm2_0;   // marched row j-2
+                T rhi = q ? r1j : r0j;       // marched row j
                 int a = 2 * t + q;
-                const T d1 = rs2_core(rc, rw, rs, re, rn);
+                const T d1 = MIR ? rs2_core(rc, rw, rhi, re, rlo) : rs2_core(rc, rw, rlo, re, rhi);
                 if (!FZ && useful && a >= 1 && a <= m - 1 && j - 1 < y1) {
-                    if (NT) __builtin_nontemporal_store(d1, rD + (size_t)(j - 1) * W + t);
-                    else rD[(size_t)(j - 1) * W + t] = d1;
+                    if (NT) __builtin_nontemporal_store(d1, rD + (size_t)R(j - 1) * W + t);
+                    else rD[(size_t)R(j - 1) * W + t] = d1;
                 }
                 if constexpr (FZ) {
                     // Eq. (Erest2b) at axis point (t, B) of the level below,
                     // B = (j-2)/2: diagonal rows 2B-1 (d3), 2B (d2), 2B+1 (d1)
+                    // as marched (mirrored: 2B+1, 2B, 2B-1 of the grid)
                     if (!(j & 1) && j - 2 >= y0 && j - 2 < y1) {
                         const int B = (j - 2) >> 1;
                         const T d3w = __shfl_up(d3, 1), d1w = __shfl_up(d1, 1);
                         if (useful2 && B >= 1 && B <= mc - 1)
-                            rA2[(size_t)B * (mc + 1) + t] = rs2_core(d2, d3w, d3, d1, d1w);
+                            rA2[(size_t)(MIR ? mc - B : B) * (mc + 1) + t] =
+                                MIR ? rs2_core(d2, d1w, d1, d3, d3w) : rs2_core(d2, d3w, d3, d1, d1w);
                     }
                     d3 = d2;
                     d2 = d1;
@@ -199,7 +212,21 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
             proc_p(jb, c, Int<-1>{});   // run-time parity (no vector stores here)
         }
     };
-    rows_march<CH, Ck>(y0 - 1, ylast, load, proc);
+    rows_march<CH, Ck>(jstart, ylast, load, proc);
+}
+
+template <typename T, int CH, bool NT, bool FZ, bool M4, bool WF>
+__global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu((FZ && (sizeof(T) == 8 || M4)) || WF ? 3 : 4))) kb_resid(int m, double inv_h2, const Fin2<T>* __restrict__ items,
+                                                      int nwx, int nwaves, int rows, const Ctl* __restrict__ ctls)
+{
+    const Fin2<T> it = items[blockIdx.y];
+    ITEM_GATE(ctls, it.prob);
+    const int wv = rows_wave_id(nwaves);
+    double acc = 0, accf = 0;
+    if (wv < nwaves) {
+        if (FZ && ((wv / nwx) & 1)) resid_body<T, CH, NT, FZ, M4, WF, true>(m, inv_h2, it, wv, nwx, rows, acc, accf);
+        else resid_body<T, CH, NT, FZ, M4, WF, false>(m, inv_h2, it, wv, nwx, rows, acc, accf);
+    }
     double sum = rows_block_sum(acc);
     if (threadIdx.x == 0) it.part[blockIdx.x] = sum;
     if constexpr (WF) {
