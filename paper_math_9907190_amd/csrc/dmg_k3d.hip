@@ -245,7 +245,8 @@ __global__ void __launch_bounds__(256) k3_jac_finest(int n, T cc, const T* __res
 constexpr int kPlTX = 64, kPlTY = 8, kPlThreads = 256;
 constexpr int kPlW = kPlTX + 2, kPlH = kPlTY + 2;   // tile plus a one-point halo
 constexpr int kRdTX = 32, kRdW = kRdTX + 2;        // red tiles: 32 slots (64 x positions) wide
-constexpr int kRdTY = 8, kRdH = kRdTY + 2;         // red tiles: rows (16 and 32 measured slower)
+constexpr int kRdTY = 16, kRdH = kRdTY + 2;        // red tiles: rows (with 512 threads; 8 rows and
+constexpr int kRdThreads = 512;                     // 256 threads measured slower)
 
 // ---- green: F points (a+b+c odd), Eq. (Egprolg).  The red grid is staged
 // plane by plane in LDS over the tile plus a two-point halo: row (b, c) of
@@ -253,12 +254,15 @@ constexpr int kRdTY = 8, kRdH = kRdTY + 2;         // red tiles: rows (16 and 32
 // s = (x0-3)/2 cover a in [x0-2, x0+65] for either parity and load as one
 // contiguous run; each red value is then loaded once instead of once per
 // F neighbour.
-constexpr int kGrRS = 35, kGrRH = kPlTY + 4;                    // red LDS plane: rows y0-2 .. y0+9
+// Green tiles: 64 x 16 points, 512 threads (the red halo rows of a plane are
+// 1.25 times the tile's instead of 1.5 for 64 x 8).
+constexpr int kGrTY = 16, kGrThreads = 512, kGrH = kGrTY + 2;
+constexpr int kGrRS = 35, kGrRH = kGrTY + 4;                    // red LDS plane: rows y0-2 .. y0+17
 constexpr int kGrRN = kGrRS * kGrRH;
-constexpr int kGrRP = (kGrRN + kPlThreads - 1) / kPlThreads;   // red slots per thread
+constexpr int kGrRP = (kGrRN + kGrThreads - 1) / kGrThreads;   // red slots per thread
 constexpr int kGrFR = kPlW / 2;                                  // F points per extended tile row
-constexpr int kGrFN = kPlH * kGrFR;
-constexpr int kGrFP = (kGrFN + kPlThreads - 1) / kPlThreads;   // F points per thread
+constexpr int kGrFN = kGrH * kGrFR;
+constexpr int kGrFP = (kGrFN + kGrThreads - 1) / kGrThreads;   // F points per thread
 
 // red value e of the staged plane c (0 outside the grid)
 template <typename T>
@@ -287,18 +291,18 @@ __device__ inline bool green_fpoint(int m, int x0, int y0, int c, int e, int& a,
 // one-point halo) into a second ring, and then the x pair (2t, 2t+1) of one
 // output row of plane c-1; the inputs of the next plane are loaded meanwhile.
 template <typename T, bool FINEST>
-__global__ void __launch_bounds__(kPlThreads) k3_green_planes(int m, T cc, const T* __restrict__ rG,
+__global__ void __launch_bounds__(kGrThreads) k3_green_planes(int m, T cc, const T* __restrict__ rG,
                                                                const T* __restrict__ vR, T* __restrict__ vG,
                                                                double* __restrict__ u, int ntx, int nty, int zc,
                                                                const Ctl* ctl)
 {
     DMG_GATE(ctl);
     constexpr int W = kPlW;
-    __shared__ T F[3][kPlH * kPlW];
+    __shared__ T F[3][kGrH * kPlW];
     __shared__ T R[3][kGrRN];
     const int bid = xcd_block();   // tiles of one die are neighbours
     const int tx = bid % ntx, ty = (bid / ntx) % nty, tz = bid / (ntx * nty);
-    const int x0 = 1 + tx * kPlTX, y0 = 1 + ty * kPlTY, z0 = 1 + tz * zc;
+    const int x0 = 1 + tx * kPlTX, y0 = 1 + ty * kGrTY, z0 = 1 + tz * zc;
     const int z1 = min(z0 + zc, m);   // output planes [z0, z1)
     const int tid = threadIdx.x;
     const int oly = tid / (kPlTX / 2), opr = tid % (kPlTX / 2);
@@ -309,7 +313,7 @@ __global__ void __launch_bounds__(kPlThreads) k3_green_planes(int m, T cc, const
     T rr[kGrRP], rf[kGrFP];
 #pragma unroll
     for (int i = 0; i < kGrRP; i++) {
-        const int e = tid + i * kPlThreads;
+        const int e = tid + i * kGrThreads;
         const T a0 = green_rload(vR, m, x0, y0, z0 - 2, e), a1 = green_rload(vR, m, x0, y0, z0 - 1, e);
         if (e < kGrRN) {
             R[(z0 + 1) % 3][e] = a0;
@@ -319,7 +323,7 @@ __global__ void __launch_bounds__(kPlThreads) k3_green_planes(int m, T cc, const
     }
 #pragma unroll
     for (int i = 0; i < kGrFP; i++) {
-        const int e = tid + i * kPlThreads;
+        const int e = tid + i * kGrThreads;
         int a, b;
         rf[i] = (e < kGrFN && green_fpoint(m, x0, y0, z0 - 1, e, a, b)) ? rG[idxG(m, a, b, z0 - 1)] : T(0);
     }
@@ -328,7 +332,7 @@ __global__ void __launch_bounds__(kPlThreads) k3_green_planes(int m, T cc, const
     for (int c = z0 - 1; c <= z1; c++) {
 #pragma unroll
         for (int i = 0; i < kGrRP; i++) {   // red plane c+1
-            const int e = tid + i * kPlThreads;
+            const int e = tid + i * kGrThreads;
             if (e < kGrRN) R[(c + 4) % 3][e] = rr[i];
         }
         T rfc[kGrFP];
@@ -338,10 +342,10 @@ __global__ void __launch_bounds__(kPlThreads) k3_green_planes(int m, T cc, const
         const T rc = rn;
         if (c + 1 <= z1) {   // next plane's inputs
 #pragma unroll
-            for (int i = 0; i < kGrRP; i++) rr[i] = green_rload(vR, m, x0, y0, c + 2, tid + i * kPlThreads);
+            for (int i = 0; i < kGrRP; i++) rr[i] = green_rload(vR, m, x0, y0, c + 2, tid + i * kGrThreads);
 #pragma unroll
             for (int i = 0; i < kGrFP; i++) {
-                const int e = tid + i * kPlThreads;
+                const int e = tid + i * kGrThreads;
                 int a, b;
                 rf[i] = (e < kGrFN && green_fpoint(m, x0, y0, c + 1, e, a, b)) ? rG[idxG(m, a, b, c + 1)] : T(0);
             }
@@ -362,7 +366,7 @@ __global__ void __launch_bounds__(kPlThreads) k3_green_planes(int m, T cc, const
             T* Fp = F[c % 3];
 #pragma unroll
             for (int i = 0; i < kGrFP; i++) {
-                const int e = tid + i * kPlThreads;
+                const int e = tid + i * kGrThreads;
                 if (e >= kGrFN) continue;
                 int a, b;
                 const bool ok = green_fpoint(m, x0, y0, c, e, a, b);
@@ -412,7 +416,7 @@ __global__ void __launch_bounds__(kPlThreads) k3_green_planes(int m, T cc, const
 // plus a one-point halo (36 x 7 values), so each magenta value is loaded
 // once; face centres read their six magenta neighbours from there.
 constexpr int kMsW = kRdTX + 4, kMsH = kRdTY / 2 + 3, kMsN = kMsW * kMsH;
-constexpr int kMsP = (kMsN + kPlThreads - 1) / kPlThreads;   // staged magenta values per thread
+constexpr int kMsP = (kMsN + kRdThreads - 1) / kRdThreads;   // staged magenta values per thread
 
 // staged magenta value e of plane c (0 outside the grid)
 template <typename T>
@@ -438,14 +442,14 @@ __device__ inline bool red_fpoint(int s0, int y0, int c, int p, int& a, int& b)
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kPlThreads) k3_red_planes(int m, T c1, T c2, const T* __restrict__ rR,
+__global__ void __launch_bounds__(kRdThreads) k3_red_planes(int m, T c1, T c2, const T* __restrict__ rR,
                                                              const T* __restrict__ vE, const T* __restrict__ vO,
                                                              T* __restrict__ vR, int ntx, int nty, int zc,
                                                              const Ctl* ctl)
 {
     DMG_GATE(ctl);
-    constexpr int W = kRdW, NP = (kRdH * kRdW + kPlThreads - 1) / kPlThreads;   // F slots per thread
-    constexpr int NO = kRdTY * kRdTX / kPlThreads;                              // outputs per thread
+    constexpr int W = kRdW, NP = (kRdH * kRdW + kRdThreads - 1) / kRdThreads;   // F slots per thread
+    constexpr int NO = kRdTY * kRdTX / kRdThreads;                              // outputs per thread
     __shared__ T F[3][kRdH * kRdW];
     __shared__ T M[3][kMsN];
     const int bid = xcd_block();   // tiles of one die are neighbours
@@ -458,7 +462,7 @@ __global__ void __launch_bounds__(kPlThreads) k3_red_planes(int m, T c1, T c2, c
     auto fload = [&](int c, T (&rf)[NP]) {
 #pragma unroll
         for (int k = 0; k < NP; k++) {
-            const int p = tid + k * kPlThreads;
+            const int p = tid + k * kRdThreads;
             int a, b;
             rf[k] = T(0);
             if (p < kRdH * kRdW && red_fpoint(s0, y0, c, p, a, b) && a >= 1 && a < m && b >= 1 && b < m && c >= 1 &&
@@ -470,7 +474,7 @@ __global__ void __launch_bounds__(kPlThreads) k3_red_planes(int m, T c1, T c2, c
     // (c+3)%3), plane z0 and the F residuals of plane z0-1 into registers
 #pragma unroll
     for (int k = 0; k < kMsP; k++) {
-        const int e = tid + k * kPlThreads;
+        const int e = tid + k * kRdThreads;
         const T a0 = red_mload(vE, vO, m, s0, y0, z0 - 2, e), a1 = red_mload(vE, vO, m, s0, y0, z0 - 1, e);
         if (e < kMsN) {
             M[(z0 + 1) % 3][e] = a0;
@@ -479,7 +483,7 @@ __global__ void __launch_bounds__(kPlThreads) k3_red_planes(int m, T c1, T c2, c
     }
     T mn[kMsP];
 #pragma unroll
-    for (int k = 0; k < kMsP; k++) mn[k] = red_mload(vE, vO, m, s0, y0, z0, tid + k * kPlThreads);
+    for (int k = 0; k < kMsP; k++) mn[k] = red_mload(vE, vO, m, s0, y0, z0, tid + k * kRdThreads);
     T rf[NP];
     fload(z0 - 1, rf);
     T rn[NO];
@@ -488,7 +492,7 @@ __global__ void __launch_bounds__(kPlThreads) k3_red_planes(int m, T c1, T c2, c
     for (int c = z0 - 1; c <= z1; c++) {
 #pragma unroll
         for (int k = 0; k < kMsP; k++) {   // magenta plane c+1
-            const int e = tid + k * kPlThreads;
+            const int e = tid + k * kRdThreads;
             if (e < kMsN) M[(c + 4) % 3][e] = mn[k];
         }
         T rfc[NP], rc[NO];
@@ -498,13 +502,13 @@ __global__ void __launch_bounds__(kPlThreads) k3_red_planes(int m, T c1, T c2, c
         for (int k = 0; k < NO; k++) rc[k] = rn[k];
         if (c + 1 <= z1) {
 #pragma unroll
-            for (int k = 0; k < kMsP; k++) mn[k] = red_mload(vE, vO, m, s0, y0, c + 2, tid + k * kPlThreads);
+            for (int k = 0; k < kMsP; k++) mn[k] = red_mload(vE, vO, m, s0, y0, c + 2, tid + k * kRdThreads);
             fload(c + 1, rf);
         }
         if (c >= z0 && c < z1) {   // corners of this plane need rR next iteration
 #pragma unroll
             for (int k = 0; k < NO; k++) {
-                const int e = tid + k * kPlThreads;
+                const int e = tid + k * kRdThreads;
                 const int b = y0 + e / kRdTX, sl = s0 + e % kRdTX;
                 const int a = 2 * sl + ((b + c) & 1);
                 if (b < m && a >= 1 && a < m && ((a | b | c) & 1) == 0) rn[k] = rR[idxR(m, a, b, c)];
@@ -518,7 +522,7 @@ __global__ void __launch_bounds__(kPlThreads) k3_red_planes(int m, T c1, T c2, c
             T* Fp = F[c % 3];
 #pragma unroll
             for (int k = 0; k < NP; k++) {
-                const int p = tid + k * kPlThreads;
+                const int p = tid + k * kRdThreads;
                 int a, b;
                 if (p >= kRdH * kRdW || !red_fpoint(s0, y0, c, p, a, b)) continue;
                 T v = T(0);
@@ -548,7 +552,7 @@ __global__ void __launch_bounds__(kPlThreads) k3_red_planes(int m, T c1, T c2, c
             const T* Fq = F[c % 3];
 #pragma unroll
             for (int k = 0; k < NO; k++) {
-                const int e = tid + k * kPlThreads;
+                const int e = tid + k * kRdThreads;
                 const int ly = e / kRdTX, ls = e % kRdTX;
                 const int b = y0 + ly, sl = s0 + ls;
                 const int a = 2 * sl + ((b + co) & 1);
@@ -582,13 +586,16 @@ __global__ void __launch_bounds__(kPlThreads) k3_red_planes(int m, T c1, T c2, c
 // one-point halo) through a second ring, and the red points of the plane
 // behind read their seven residuals from LDS.  The next plane's u and f are
 // loaded while the current one is processed.
-constexpr int kRsUW = kPlTX + 4, kRsUH = kPlTY + 4;   // u region
-constexpr int kRsRW = kPlTX + 2, kRsRH = kPlTY + 2;   // residual region
-constexpr int kRsUS = (kRsUW * kRsUH + kPlThreads - 1) / kPlThreads;
-constexpr int kRsFS = (kRsRW * kRsRH + kPlThreads - 1) / kPlThreads;
+// Tiles of 64 x 16 points and 512 threads: the u halo of a plane is then
+// 1.25 times the tile (1.5 for 64 x 8) at the same four waves per SIMD.
+constexpr int kRsTY = 16, kRsThreads = 512;
+constexpr int kRsUW = kPlTX + 4, kRsUH = kRsTY + 4;   // u region
+constexpr int kRsRW = kPlTX + 2, kRsRH = kRsTY + 2;   // residual region
+constexpr int kRsUS = (kRsUW * kRsUH + kRsThreads - 1) / kRsThreads;
+constexpr int kRsFS = (kRsRW * kRsRH + kRsThreads - 1) / kRsThreads;
 
 template <typename T, bool M4>
-__global__ void __launch_bounds__(kPlThreads) k3_resid_planes(int n, double inv_h2, const double* __restrict__ u,
+__global__ void __launch_bounds__(kRsThreads) k3_resid_planes(int n, double inv_h2, const double* __restrict__ u,
                                                                const double* __restrict__ f, T* __restrict__ r0,
                                                                T* __restrict__ rR, double* __restrict__ partial,
                                                                int ntx, int nty, int zc, const Ctl* ctl)
@@ -596,26 +603,49 @@ __global__ void __launch_bounds__(kPlThreads) k3_resid_planes(int n, double inv_
     DMG_GATE(ctl);
     __shared__ double U[3][kRsUW * kRsUH];
     __shared__ T Rr[3][kRsRW * kRsRH];
-    __shared__ double red[kPlThreads / 64];
+    __shared__ double red[kRsThreads / 64];
     const int bid = xcd_block();   // tiles of one die are neighbours
     const int tx = bid % ntx, ty = (bid / ntx) % nty, tz = bid / (ntx * nty);
-    const int x0 = 1 + tx * kPlTX, y0 = 1 + ty * kPlTY, z0 = 1 + tz * zc;
+    const int x0 = 1 + tx * kPlTX, y0 = 1 + ty * kRsTY, z0 = 1 + tz * zc;
     const int z1 = min(z0 + zc, n);
     const int tid = threadIdx.x;
-    auto uload = [&](int c, int i) -> double {
-        const int p = tid + i * kPlThreads;
-        if (p >= kRsUW * kRsUH) return 0.0;
+    const size_t NN = (size_t)(n + 1) * (n + 1);   // plane stride of the G layout
+    // Everything about a thread's points that does not depend on the plane is
+    // worked out once: the (x, y) offset within a plane of each staged u and
+    // f point (-1 off the grid or past the region) and, per residual point,
+    // its LDS position and whether it is owned.
+    int uoff[kRsUS], foff[kRsFS], rl[kRsFS];
+    bool rown[kRsFS];
+#pragma unroll
+    for (int i = 0; i < kRsUS; i++) {
+        const int p = tid + i * kRsThreads;
         const int a = x0 - 2 + p % kRsUW, b = y0 - 2 + p / kRsUW;
-        if (a < 0 || a > n || b < 0 || b > n || c < 0 || c > n) return 0.0;
-        return u[idxG(n, a, b, c)];
+        uoff[i] = (p < kRsUW * kRsUH && a >= 0 && a <= n && b >= 0 && b <= n) ? b * (n + 1) + a : -1;
+    }
+#pragma unroll
+    for (int i = 0; i < kRsFS; i++) {
+        const int p = tid + i * kRsThreads;
+        const int lx = p % kRsRW, ly = p / kRsRW;
+        const int a = x0 - 1 + lx, b = y0 - 1 + ly;
+        foff[i] = (p < kRsRW * kRsRH && a >= 1 && a < n && b >= 1 && b < n) ? b * (n + 1) + a : -1;
+        rl[i] = (ly + 1) * kRsUW + (lx + 1);
+        rown[i] = lx >= 1 && lx <= kPlTX && ly >= 1 && ly <= kRsTY;
+    }
+    auto uload = [&](int c, int i) -> double {
+        return (uoff[i] >= 0 && c >= 0 && c <= n) ? u[(size_t)c * NN + uoff[i]] : 0.0;
     };
     auto fload = [&](int c, int i) -> double {
-        const int p = tid + i * kPlThreads;
-        if (p >= kRsRW * kRsRH) return 0.0;
-        const int a = x0 - 1 + p % kRsRW, b = y0 - 1 + p / kRsRW;
-        if (a < 1 || a >= n || b < 1 || b >= n || c < 1 || c >= n) return 0.0;
-        return __builtin_nontemporal_load(f + idxG(n, a, b, c));
+        return (foff[i] >= 0 && c >= 1 && c < n) ? __builtin_nontemporal_load(f + (size_t)c * NN + foff[i]) : 0.0;
     };
+    // the thread's red output point: row ly of the tile, pair k; its column
+    // alternates with the plane's parity
+    const int oly = tid / (kPlTX / 2), ok = tid % (kPlTX / 2);
+    const int ob = y0 + oly;
+    // rings of LDS planes, rotated at the start of every step: in step c, Um,
+    // U0, Uq hold u of planes c-1, c, c+1 (Uq written in the step), and after
+    // its residual is written Rq, Rm, R0 hold the residual of planes c-2, c-1, c
+    double *Um = U[0], *U0 = U[1], *Uq = U[2];
+    T *Rm = Rr[0], *R0 = Rr[1], *Rq = Rr[2];
     // u planes z0-2 and z0-1 into LDS; registers: u of plane z0, f of plane z0-1
     {
         double a0[kRsUS], a1[kRsUS];
@@ -623,9 +653,12 @@ __global__ void __launch_bounds__(kPlThreads) k3_resid_planes(int n, double inv_
         for (int i = 0; i < kRsUS; i++) { a0[i] = uload(z0 - 2, i); a1[i] = uload(z0 - 1, i); }
 #pragma unroll
         for (int i = 0; i < kRsUS; i++) {
-            const int p = tid + i * kPlThreads;
-            if (p < kRsUW * kRsUH) { U[(z0 + 1) % 3][p] = a0[i]; U[(z0 + 2) % 3][p] = a1[i]; }
+            const int p = tid + i * kRsThreads;
+            if (p < kRsUW * kRsUH) { Um[p] = a0[i]; U0[p] = a1[i]; }
         }
+    }
+    {   // as after a step z0-2: U0 holds plane z0-2, Uq plane z0-1
+        double* t = Uq; Uq = U0; U0 = Um; Um = t;
     }
     // two register sets in turn, each holding the u plane and the f plane of
     // one step, so every load is issued two planes ahead of its use
@@ -638,11 +671,14 @@ __global__ void __launch_bounds__(kPlThreads) k3_resid_planes(int n, double inv_
     // plane c: u plane c+1 from the set into LDS, the residual of plane c, then
     // the red points of plane c-1; the set is refilled with planes c+3 and c+2
     auto step = [&](int c, double (&un)[kRsUS], double (&fn)[kRsFS]) {
-        double* Up = U[(c + 1) % 3];   // plane c+1
+        {   // rotate: plane c-1 <- c <- c+1, the oldest buffer takes plane c+1
+            double* t = Um; Um = U0; U0 = Uq; Uq = t;
+            T* r = Rm; Rm = R0; R0 = Rq; Rq = r;
+        }
 #pragma unroll
         for (int i = 0; i < kRsUS; i++) {
-            const int p = tid + i * kPlThreads;
-            if (p < kRsUW * kRsUH) Up[p] = un[i];
+            const int p = tid + i * kRsThreads;
+            if (p < kRsUW * kRsUH) Uq[p] = un[i];
         }
         double fc[kRsFS];
 #pragma unroll
@@ -654,20 +690,14 @@ __global__ void __launch_bounds__(kPlThreads) k3_resid_planes(int n, double inv_
             for (int i = 0; i < kRsFS; i++) fn[i] = fload(c + 2, i);
         }
         __syncthreads();
-        const double* Um = U[(c + 2) % 3];   // plane c-1
-        const double* U0 = U[c % 3];
-        const double* Uq = U[(c + 1) % 3];
-        T* Rp = Rr[c % 3];
+        const bool cin = c >= 1 && c < n, cown = c >= z0 && c < z1;
 #pragma unroll
         for (int i = 0; i < kRsFS; i++) {
-            const int p = tid + i * kPlThreads;
+            const int p = tid + i * kRsThreads;
             if (p >= kRsRW * kRsRH) continue;
-            const int lx = p % kRsRW, ly = p / kRsRW;
-            const int a = x0 - 1 + lx, b = y0 - 1 + ly;
-            const bool in = a >= 1 && a < n && b >= 1 && b < n && c >= 1 && c < n;
             T rt = T(0);
-            if (in) {
-                const int l = (ly + 1) * kRsUW + (lx + 1);
+            if (cin && foff[i] >= 0) {
+                const int l = rl[i];
                 double lap;
                 if constexpr (M4) {
                     // Eq. (Efos4): -24 centre, 2 x (6 faces), then the 12 edges
@@ -682,26 +712,24 @@ __global__ void __launch_bounds__(kPlThreads) k3_resid_planes(int n, double inv_
                 }
                 double r = fc[i] - lap;
                 rt = (T)r;
-                if (lx >= 1 && lx <= kPlTX && ly >= 1 && ly <= kPlTY && c >= z0 && c < z1) {
-                    __builtin_nontemporal_store(rt, r0 + idxG(n, a, b, c));
+                if (rown[i] && cown) {
+                    __builtin_nontemporal_store(rt, r0 + (size_t)c * NN + foff[i]);
                     acc += r * r;
                 }
             }
-            Rp[p] = rt;
+            R0[p] = rt;
         }
         __syncthreads();
         const int co = c - 1;
         if (co >= z0) {
-            const T* Rm = Rr[(co + 2) % 3];
-            const T* R0 = Rr[co % 3];
-            const T* Rq = Rr[c % 3];
-            const int ly = tid / (kPlTX / 2), k = tid % (kPlTX / 2);
-            const int b = y0 + ly;
-            const int a = x0 + ((x0 + b + co) & 1) + 2 * k;   // the red point (a+b+co even) of pair k
-            if (b < n && a < n) {
-                const int l = (ly + 1) * kRsRW + (a - x0 + 1);
-                T sum = 6 * R0[l] + R0[l + 1] + R0[l - 1] + R0[l + kRsRW] + R0[l - kRsRW] + Rq[l] + Rm[l];
-                rR[idxR(n, a, b, co)] = sum * (T(1) / T(12));
+            const T* Pm = Rq;   // residual plane co-1
+            const T* P0 = Rm;   // plane co
+            const T* Pq = R0;   // plane co+1 = c
+            const int a = x0 + ((x0 + ob + co) & 1) + 2 * ok;   // the red point (a+b+co even) of pair k
+            if (ob < n && a < n) {
+                const int l = (oly + 1) * kRsRW + (a - x0 + 1);
+                T sum = 6 * P0[l] + P0[l + 1] + P0[l - 1] + P0[l + kRsRW] + P0[l - kRsRW] + Pq[l] + Pm[l];
+                rR[idxR(n, a, ob, co)] = sum * (T(1) / T(12));
             }
         }
     };
@@ -715,7 +743,7 @@ __global__ void __launch_bounds__(kPlThreads) k3_resid_planes(int n, double inv_
     __syncthreads();
     if (tid == 0) {
         double t = 0;
-        for (int w = 0; w < kPlThreads / 64; w++) t += red[w];
+        for (int w = 0; w < kRsThreads / 64; w++) t += red[w];
         partial[blockIdx.x] = t;
     }
 }
@@ -723,8 +751,12 @@ __global__ void __launch_bounds__(kPlThreads) k3_resid_planes(int n, double inv_
 inline void resid3_grid(int n, int& ntx, int& nty, int& zc, int& nb)
 {
     ntx = (n - 1 + kPlTX - 1) / kPlTX;
-    nty = (n - 1 + kPlTY - 1) / kPlTY;
-    zc = 8;
+    nty = (n - 1 + kRsTY - 1) / kRsTY;
+    // the longest z chunk (the fewest halo planes read twice) that still
+    // gives 512 workgroups, two per CU (measured at 257^3: 32 planes, 99 us,
+    // against 102 for 16 and 108 for 8)
+    zc = 32;
+    while (zc > 4 && (long)ntx * nty * ((n - 1 + zc - 1) / zc) < 512) zc >>= 1;
     nb = ntx * nty * ((n - 1 + zc - 1) / zc);
 }
 
@@ -744,10 +776,10 @@ void launch_resid3_fused(int n, const double* u, const double* f, T* r0, T* rR, 
     int ntx, nty, zc, nb;
     resid3_grid(n, ntx, nty, zc, nb);
     if (order == 4)
-        hipLaunchKernelGGL((k3_resid_planes<T, true>), dim3(nb), dim3(kPlThreads), 0, s, n, (double)n * n / 6, u, f, r0,
+        hipLaunchKernelGGL((k3_resid_planes<T, true>), dim3(nb), dim3(kRsThreads), 0, s, n, (double)n * n / 6, u, f, r0,
                            rR, partial, ntx, nty, zc, ctl);
     else
-        hipLaunchKernelGGL((k3_resid_planes<T, false>), dim3(nb), dim3(kPlThreads), 0, s, n, (double)n * n, u, f, r0,
+        hipLaunchKernelGGL((k3_resid_planes<T, false>), dim3(nb), dim3(kRsThreads), 0, s, n, (double)n * n, u, f, r0,
                            rR, partial, ntx, nty, zc, ctl);
 }
 
@@ -897,6 +929,16 @@ constexpr int kRdPlMinSide = 128, kGrPlMinSide = 128;   // the red and green ste
 // longer chunks leave too few workgroups in flight; 4 at side 128, where 8
 // leaves two waves per SIMD)
 inline int pl_zchunk(int m) { return m >= 256 ? 8 : 4; }
+// green steps (64 x 16 tiles): the longest chunk that still gives 512
+// workgroups (measured at 257^3: 32 planes 109 us, 16 planes 110, 8 planes
+// with 64 x 8 tiles 118)
+inline int gr_zchunk(int m)
+{
+    const long tiles = (long)((m - 1 + kPlTX - 1) / kPlTX) * ((m - 1 + kGrTY - 1) / kGrTY);
+    int zc = 32;
+    while (zc > 4 && tiles * ((m - 1 + zc - 1) / zc) < 512) zc >>= 1;
+    return zc;
+}
 
 template <typename T>
 void launch_jac3(const Lev3<T>& L, const Lev3<T>& Cr, T* zero, const Ctl* ctl, hipStream_t s)
@@ -917,7 +959,7 @@ void launch_jac3(const Lev3<T>& L, const Lev3<T>& Cr, T* zero, const Ctl* ctl, h
         if (m >= kRdPlMinSide) {
             int ntx = (m / 2 + kRdTX - 1) / kRdTX, nty = (m - 1 + kRdTY - 1) / kRdTY, zc = pl_zchunk(m);
             int ntz = (m - 1 + zc - 1) / zc;
-            hipLaunchKernelGGL(k3_red_planes<T>, dim3(ntx * nty * ntz), dim3(kPlThreads), 0, s, m, L.c, L.c2, L.r,
+            hipLaunchKernelGGL(k3_red_planes<T>, dim3(ntx * nty * ntz), dim3(kRdThreads), 0, s, m, L.c, L.c2, L.r,
                                Cr.v, Cr.v2, L.v, ntx, nty, zc, ctl);
         } else {
             dim3 g((m / 2 + 255) / 256, m / 2, m / 2);
@@ -925,9 +967,9 @@ void launch_jac3(const Lev3<T>& L, const Lev3<T>& Cr, T* zero, const Ctl* ctl, h
         }
     } else {
         if (m >= kGrPlMinSide) {
-            int ntx = (m - 1 + kPlTX - 1) / kPlTX, nty = (m - 1 + kPlTY - 1) / kPlTY, zc = pl_zchunk(m);
+            int ntx = (m - 1 + kPlTX - 1) / kPlTX, nty = (m - 1 + kGrTY - 1) / kGrTY, zc = gr_zchunk(m);
             int ntz = (m - 1 + zc - 1) / zc;
-            hipLaunchKernelGGL((k3_green_planes<T, false>), dim3(ntx * nty * ntz), dim3(kPlThreads), 0, s, m, L.c, L.r,
+            hipLaunchKernelGGL((k3_green_planes<T, false>), dim3(ntx * nty * ntz), dim3(kGrThreads), 0, s, m, L.c, L.r,
                                vc, L.v, nullptr, ntx, nty, zc, ctl);
         } else {
             dim3 g((m / 2 + 1 + 255) / 256, m - 1, m - 1);
@@ -940,9 +982,9 @@ template <typename T>
 void launch_jac3_finest(int n, T c, const T* r0, const T* vR, double* u, const Ctl* ctl, hipStream_t s)
 {
     if (n >= kPlMinSide) {
-        int ntx = (n - 1 + kPlTX - 1) / kPlTX, nty = (n - 1 + kPlTY - 1) / kPlTY, zc = pl_zchunk(n);
+        int ntx = (n - 1 + kPlTX - 1) / kPlTX, nty = (n - 1 + kGrTY - 1) / kGrTY, zc = gr_zchunk(n);
         int ntz = (n - 1 + zc - 1) / zc;
-        hipLaunchKernelGGL((k3_green_planes<T, true>), dim3(ntx * nty * ntz), dim3(kPlThreads), 0, s, n, c, r0, vR,
+        hipLaunchKernelGGL((k3_green_planes<T, true>), dim3(ntx * nty * ntz), dim3(kGrThreads), 0, s, n, c, r0, vR,
                            nullptr, u, ntx, nty, zc, ctl);
         return;
     }
