@@ -243,7 +243,7 @@ __global__ void __launch_bounds__(256) k3_jac_finest(int n, T cc, const T* __res
 // results equal those of the one-thread-per-point kernels bit for bit.
 
 constexpr int kPlTX = 64, kPlTY = 8, kPlThreads = 256;
-constexpr int kPlW = kPlTX + 2, kPlH = kPlTY + 2;   // tile plus a one-point halo
+constexpr int kPlW = kPlTX + 2;   // tile width plus a one-point halo
 constexpr int kRdTX = 32, kRdW = kRdTX + 2;        // red tiles: 32 slots (64 x positions) wide
 constexpr int kRdTY = 16, kRdH = kRdTY + 2;        // red tiles: rows (with 512 threads; 8 rows and
 constexpr int kRdThreads = 512;                     // 256 threads measured slower)
@@ -263,26 +263,6 @@ constexpr int kGrRP = (kGrRN + kGrThreads - 1) / kGrThreads;   // red slots per 
 constexpr int kGrFR = kPlW / 2;                                  // F points per extended tile row
 constexpr int kGrFN = kGrH * kGrFR;
 constexpr int kGrFP = (kGrFN + kGrThreads - 1) / kGrThreads;   // F points per thread
-
-// red value e of the staged plane c (0 outside the grid)
-template <typename T>
-__device__ inline T green_rload(const T* __restrict__ vR, int m, int x0, int y0, int c, int e)
-{
-    if (e >= kGrRN) return T(0);
-    const int b = y0 - 2 + e / kGrRS, s = (x0 - 3) / 2 + e % kGrRS;
-    const int a = 2 * s + ((b + c) & 1);
-    if (a < 0 || a > m || b < 0 || b > m || c < 0 || c > m) return T(0);
-    return vR[idxR(m, a, b, c)];
-}
-
-// F point e of the extended tile plane c: (a, b) and whether it is interior
-__device__ inline bool green_fpoint(int m, int x0, int y0, int c, int e, int& a, int& b)
-{
-    const int ly = e / kGrFR, j = e % kGrFR;
-    b = y0 - 1 + ly;
-    a = x0 - 1 + ((x0 + b + c) & 1) + 2 * j;
-    return a > 0 && a < m && b > 0 && b < m && c > 0 && c < m;
-}
 
 // Green grid of side m, Eqs. (Egprolg), (Egprolr): F points from the red
 // grid vR, then C points (a+b+c even) from the six new F values.  FINEST
@@ -305,35 +285,86 @@ __global__ void __launch_bounds__(kGrThreads) k3_green_planes(int m, T cc, const
     const int x0 = 1 + tx * kPlTX, y0 = 1 + ty * kGrTY, z0 = 1 + tz * zc;
     const int z1 = min(z0 + zc, m);   // output planes [z0, z1)
     const int tid = threadIdx.x;
+    const int h = m / 2;
+    const size_t NN = (size_t)(m + 1) * (m + 1), PR = (size_t)(m + 1) * (h + 1);   // plane strides: G, R layouts
+    // What does not depend on the plane is worked out once per thread.
+    // Staged red slot e: row b = y0-2 + e / 35, slot s = (x0-3)/2 + e % 35,
+    // point a = 2 s + ((b+c) & 1) (inside iff 0 <= s < h, or s = h with a even).
+    int roff[kGrRP];
+    bool rok[kGrRP], rsh[kGrRP], rodd[kGrRP];
+#pragma unroll
+    for (int i = 0; i < kGrRP; i++) {
+        const int e = tid + i * kGrThreads;
+        const int b = y0 - 2 + e / kGrRS, sl = (x0 - 3) / 2 + e % kGrRS;
+        rok[i] = e < kGrRN && b >= 0 && b <= m && sl >= 0 && sl <= h;
+        rsh[i] = sl == h;
+        rodd[i] = b & 1;
+        roff[i] = b * (h + 1) + sl;
+    }
+    auto rload = [&](int c, int i) -> T {
+        const bool ok = rok[i] && c >= 0 && c <= m && !(rsh[i] && ((rodd[i] ^ c) & 1));
+        return ok ? vR[(size_t)c * PR + roff[i]] : T(0);
+    };
+    // F point e: row b = y0-1 + e / 33, a = x0-1 + ((x0+b+c) & 1) + 2j with j = e % 33
+    int foff[kGrFP], flb[kGrFP], fwp[kGrFP];
+    bool frow[kGrFP], fodd[kGrFP];
+    int fa0[kGrFP];
+#pragma unroll
+    for (int i = 0; i < kGrFP; i++) {
+        const int e = tid + i * kGrThreads;
+        const int ly = e / kGrFR, j = e % kGrFR;
+        const int b = y0 - 1 + ly;
+        frow[i] = e < kGrFN && b > 0 && b < m;
+        fodd[i] = (x0 + b) & 1;                     // parity of x0 + b
+        fa0[i] = x0 - 1 + 2 * j;                    // a for even x0+b+c
+        foff[i] = b * (m + 1) + x0 - 1 + 2 * j;     // in-plane G offset of that a
+        flb[i] = (ly + 1) * kGrRS + j;              // staged red position of slot a/2-ish (see below)
+        fwp[i] = ly * W + 2 * j;                    // F position of that a
+    }
+    // F point i of plane c: its parity offset (0/1) and whether it is interior
+    auto fpar = [&](int c, int i) { return (fodd[i] ^ c) & 1; };
+    auto fin = [&](int c, int i) {
+        const int a = fa0[i] + fpar(c, i);
+        return frow[i] && a > 0 && a < m && c > 0 && c < m;
+    };
+    // the thread's output pair (2t, 2t+1) of row ob
     const int oly = tid / (kPlTX / 2), opr = tid % (kPlTX / 2);
     const int ob = y0 + oly, oa = x0 + 2 * opr;
     const bool orow = ob < m;
-    // prologue: red planes z0-2 and z0-1 into LDS; red plane z0 and the F
-    // residuals of plane z0-1 into registers (ring slot of plane c: (c+3)%3)
+    const int ooff = ob * (m + 1) + oa;              // in-plane G offset of the pair
+    const int obpar = (oa + ob) & 1;
+    // rings rotated at the start of every plane step c: Rm, R0, Rq hold red
+    // planes c-1, c, c+1 (Rq written in the step); after the step's F values
+    // are written, Fa, Fb, Fc hold those of planes c-2, c-1, c
+    T *Rm = R[2], *R0 = R[0], *Rq = R[1];
+    T *Fa = F[0], *Fb = F[1], *Fc = F[2];
+    // prologue: red planes z0-2 (R0) and z0-1 (Rq) into LDS; red plane z0 and
+    // the F residuals of plane z0-1 into registers
     T rr[kGrRP], rf[kGrFP];
 #pragma unroll
     for (int i = 0; i < kGrRP; i++) {
         const int e = tid + i * kGrThreads;
-        const T a0 = green_rload(vR, m, x0, y0, z0 - 2, e), a1 = green_rload(vR, m, x0, y0, z0 - 1, e);
+        const T a0 = rload(z0 - 2, i), a1 = rload(z0 - 1, i);
         if (e < kGrRN) {
-            R[(z0 + 1) % 3][e] = a0;
-            R[(z0 + 2) % 3][e] = a1;
+            R0[e] = a0;
+            Rq[e] = a1;
         }
-        rr[i] = green_rload(vR, m, x0, y0, z0, e);
+        rr[i] = rload(z0, i);
     }
 #pragma unroll
-    for (int i = 0; i < kGrFP; i++) {
-        const int e = tid + i * kGrThreads;
-        int a, b;
-        rf[i] = (e < kGrFN && green_fpoint(m, x0, y0, z0 - 1, e, a, b)) ? rG[idxG(m, a, b, z0 - 1)] : T(0);
-    }
+    for (int i = 0; i < kGrFP; i++)
+        rf[i] = fin(z0 - 1, i) ? rG[(size_t)(z0 - 1) * NN + foff[i] + fpar(z0 - 1, i)] : T(0);
     double un0 = 0, un1 = 0;
     T rn = T(0);
     for (int c = z0 - 1; c <= z1; c++) {
+        {
+            T* t = Rm; Rm = R0; R0 = Rq; Rq = t;
+            T* f = Fa; Fa = Fb; Fb = Fc; Fc = f;
+        }
 #pragma unroll
         for (int i = 0; i < kGrRP; i++) {   // red plane c+1
             const int e = tid + i * kGrThreads;
-            if (e < kGrRN) R[(c + 4) % 3][e] = rr[i];
+            if (e < kGrRN) Rq[e] = rr[i];
         }
         T rfc[kGrFP];
 #pragma unroll
@@ -342,64 +373,57 @@ __global__ void __launch_bounds__(kGrThreads) k3_green_planes(int m, T cc, const
         const T rc = rn;
         if (c + 1 <= z1) {   // next plane's inputs
 #pragma unroll
-            for (int i = 0; i < kGrRP; i++) rr[i] = green_rload(vR, m, x0, y0, c + 2, tid + i * kGrThreads);
+            for (int i = 0; i < kGrRP; i++) rr[i] = rload(c + 2, i);
 #pragma unroll
-            for (int i = 0; i < kGrFP; i++) {
-                const int e = tid + i * kGrThreads;
-                int a, b;
-                rf[i] = (e < kGrFN && green_fpoint(m, x0, y0, c + 1, e, a, b)) ? rG[idxG(m, a, b, c + 1)] : T(0);
-            }
+            for (int i = 0; i < kGrFP; i++)
+                rf[i] = fin(c + 1, i) ? rG[(size_t)(c + 1) * NN + foff[i] + fpar(c + 1, i)] : T(0);
         }
         if (c >= z0 && c < z1 && orow) {   // this plane's output inputs, used next iteration
-            const int aC = oa + ((oa + ob + c) & 1);   // the C point of the pair
-            if (aC < m) rn = rG[idxG(m, aC, ob, c)];
+            const int pc = (obpar + c) & 1;   // the pair's C point is oa + pc
+            if (oa + pc < m) rn = rG[(size_t)c * NN + ooff + pc];
             if (FINEST) {
-                if (oa < m) un0 = u[idxG(m, oa, ob, c)];
-                if (oa + 1 < m) un1 = u[idxG(m, oa + 1, ob, c)];
+                if (oa < m) un0 = u[(size_t)c * NN + ooff];
+                if (oa + 1 < m) un1 = u[(size_t)c * NN + ooff + 1];
             }
         }
         __syncthreads();
-        {   // F values of plane c, same arithmetic and order as jac3_greenF
-            const T* Rm = R[(c + 2) % 3];
-            const T* R0 = R[c % 3];
-            const T* Rq = R[(c + 1) % 3];
-            T* Fp = F[c % 3];
+        // F values of plane c, same arithmetic and order as jac3_greenF: with
+        // par the parity offset of a, the red neighbours (a+1, b) and (a-1, b)
+        // sit at staged slots flb+1+par and flb+par, (a, b +- 1) at flb+1 +- 35
 #pragma unroll
-            for (int i = 0; i < kGrFP; i++) {
-                const int e = tid + i * kGrThreads;
-                if (e >= kGrFN) continue;
-                int a, b;
-                const bool ok = green_fpoint(m, x0, y0, c, e, a, b);
-                T v = T(0);
-                if (ok) {
-                    const int ly = b - y0 + 2, k = (a - x0 + 3) >> 1;   // red row and slot of (a, b)
-                    const int l = ly * kGrRS + k;
-                    const T n0 = R0[ly * kGrRS + ((a - x0 + 4) >> 1)];   // (a+1, b, c)
-                    const T n1 = R0[ly * kGrRS + ((a - x0 + 2) >> 1)];   // (a-1, b, c)
-                    T s = n0 + n1 + R0[l + kGrRS] + R0[l - kGrRS] + Rq[l] + Rm[l];
-                    v = (-cc * rfc[i] + s) * (T(1) / T(6));
-                }
-                Fp[(b - y0 + 1) * W + (a - x0 + 1)] = v;
+        for (int i = 0; i < kGrFP; i++) {
+            const int e = tid + i * kGrThreads;
+            if (e >= kGrFN) continue;
+            const int par = fpar(c, i);
+            T v = T(0);
+            if (fin(c, i)) {
+                const int l = flb[i] + 1;
+                const T n0 = R0[l + par];       // (a+1, b, c)
+                const T n1 = R0[l - 1 + par];   // (a-1, b, c)
+                T sm = n0 + n1 + R0[l + kGrRS] + R0[l - kGrRS] + Rq[l] + Rm[l];
+                v = (-cc * rfc[i] + sm) * (T(1) / T(6));
             }
+            Fc[fwp[i] + par] = v;
         }
         __syncthreads();
         const int co = c - 1;
         if (co >= z0 && orow) {
-            const T* Fm = F[(co + 2) % 3];   // plane co - 1
-            const T* F0 = F[co % 3];
-            const T* Fq = F[c % 3];          // plane co + 1
+            const T* Fm = Fa;   // plane co - 1
+            const T* F0 = Fb;
+            const T* Fq = Fc;   // plane co + 1
+            const int pco = (obpar + co) & 1;   // 1: the pair's first point is an F point
             for (int k = 0; k < 2; k++) {
                 const int a = oa + k;
                 if (a >= m) break;
-                const int l = (oly + 1) * W + (a - x0 + 1);
+                const int l = (oly + 1) * W + (2 * opr + 1 + k);
                 T v;
-                if ((a + ob + co) & 1) {
+                if ((pco + k) & 1) {
                     v = F0[l];
                 } else {
-                    T s = F0[l + 1] + F0[l - 1] + F0[l + W] + F0[l - W] + Fq[l] + Fm[l];
-                    v = (-cc * rc + s) * (T(1) / T(6));
+                    T sm = F0[l + 1] + F0[l - 1] + F0[l + W] + F0[l - W] + Fq[l] + Fm[l];
+                    v = (-cc * rc + sm) * (T(1) / T(6));
                 }
-                size_t q = idxG(m, a, ob, co);
+                const size_t q = (size_t)co * NN + ooff + k;
                 if (FINEST) u[q] = (k ? uc1 : uc0) + (double)v;
                 else vG[q] = v;
             }
@@ -418,29 +442,6 @@ __global__ void __launch_bounds__(kGrThreads) k3_green_planes(int m, T cc, const
 constexpr int kMsW = kRdTX + 4, kMsH = kRdTY / 2 + 3, kMsN = kMsW * kMsH;
 constexpr int kMsP = (kMsN + kRdThreads - 1) / kRdThreads;   // staged magenta values per thread
 
-// staged magenta value e of plane c (0 outside the grid)
-template <typename T>
-__device__ inline T red_mload(const T* __restrict__ vE, const T* __restrict__ vO, int m, int s0, int y0, int c, int e)
-{
-    if (e >= kMsN) return T(0);
-    const int h = m / 2;
-    const int i = s0 - 2 + e % kMsW, j = (y0 - 1) / 2 - 1 + e / kMsW;
-    if (c & 1) {
-        if (i < 0 || i >= h || j < 0 || j >= h || c < 1 || c >= m) return T(0);
-        return vO[idxMO(m, 2 * i + 1, 2 * j + 1, c)];
-    }
-    if (i < 0 || i > h || j < 0 || j > h || c < 0 || c > m) return T(0);
-    return vE[idxME(m, 2 * i, 2 * j, c)];
-}
-
-// face-centre slot p of the extended tile plane c: (a, b); false for corners
-__device__ inline bool red_fpoint(int s0, int y0, int c, int p, int& a, int& b)
-{
-    b = y0 - 1 + p / kRdW;
-    a = 2 * (s0 - 1 + p % kRdW) + ((b + c) & 1);
-    return (a & 1) + (b & 1) + (c & 1) == 2;
-}
-
 template <typename T>
 __global__ void __launch_bounds__(kRdThreads) k3_red_planes(int m, T c1, T c2, const T* __restrict__ rR,
                                                              const T* __restrict__ vE, const T* __restrict__ vO,
@@ -457,43 +458,99 @@ __global__ void __launch_bounds__(kRdThreads) k3_red_planes(int m, T c1, T c2, c
     const int s0 = tx * kRdTX, y0 = 1 + ty * kRdTY, z0 = 1 + tz * zc;
     const int z1 = min(z0 + zc, m);
     const int tid = threadIdx.x;
+    const int h = m / 2;
     const int iL = s0 - 2, jL = (y0 - 1) / 2 - 1;   // half indices of staged value 0
-    // F residuals of plane c (0 for corners and points off the interior)
-    auto fload = [&](int c, T (&rf)[NP]) {
-#pragma unroll
-        for (int k = 0; k < NP; k++) {
-            const int p = tid + k * kRdThreads;
-            int a, b;
-            rf[k] = T(0);
-            if (p < kRdH * kRdW && red_fpoint(s0, y0, c, p, a, b) && a >= 1 && a < m && b >= 1 && b < m && c >= 1 &&
-                c < m)
-                rf[k] = rR[idxR(m, a, b, c)];
-        }
-    };
-    // prologue: magenta planes z0-2 and z0-1 into LDS (ring slot of plane c:
-    // (c+3)%3), plane z0 and the F residuals of plane z0-1 into registers
+    const size_t PR = (size_t)(m + 1) * (h + 1);      // plane strides: R layout,
+    const size_t PE = (size_t)(h + 1) * (h + 1), PO = (size_t)h * h;   // magenta corners, centres
+    // What does not depend on the plane is worked out once per thread: the
+    // in-plane offsets of its staged magenta values (corner planes, centre
+    // planes), of its F slots (and their row parity, slot, staging base) and
+    // of its output points.
+    int meo[kMsP], moo[kMsP];
 #pragma unroll
     for (int k = 0; k < kMsP; k++) {
         const int e = tid + k * kRdThreads;
-        const T a0 = red_mload(vE, vO, m, s0, y0, z0 - 2, e), a1 = red_mload(vE, vO, m, s0, y0, z0 - 1, e);
+        const int i = iL + e % kMsW, j = jL + e / kMsW;
+        meo[k] = (e < kMsN && i >= 0 && i <= h && j >= 0 && j <= h) ? j * (h + 1) + i : -1;
+        moo[k] = (e < kMsN && i >= 0 && i < h && j >= 0 && j < h) ? j * h + i : -1;
+    }
+    auto mload = [&](int c, int k) -> T {
+        if (c & 1) return (moo[k] >= 0 && c >= 1 && c < m) ? vO[(size_t)(c >> 1) * PO + moo[k]] : T(0);
+        return (meo[k] >= 0 && c >= 0 && c <= m) ? vE[(size_t)(c >> 1) * PE + meo[k]] : T(0);
+    };
+    // F slot p: row b = y0-1 + p / W, slot sl = s0-1 + p % W, point a = 2 sl + ((b+c) & 1)
+    int foff[NP], fbase[NP];
+    bool fodd[NP], frow[NP], fsl0[NP], fslok[NP];
+#pragma unroll
+    for (int k = 0; k < NP; k++) {
+        const int p = tid + k * kRdThreads;
+        const int b = y0 - 1 + p / W, sl = s0 - 1 + p % W;
+        frow[k] = p < kRdH * kRdW && b >= 1 && b < m;
+        fodd[k] = b & 1;
+        fsl0[k] = sl == 0;
+        fslok[k] = sl >= 0 && sl <= h - 1;
+        foff[k] = b * (h + 1) + sl;
+        fbase[k] = ((b >> 1) - jL) * kMsW + (sl - iL);
+    }
+    // is F slot k a face centre of plane c, and an interior one (a in [1, m-1])
+    auto fface = [&](int c, int k) { return fodd[k] || (c & 1); };
+    auto finside = [&](int c, int k) {
+        const bool par = (fodd[k] ^ c) & 1;   // parity of a
+        return frow[k] && c >= 1 && c < m && fslok[k] && (!fsl0[k] || par);
+    };
+    auto fload = [&](int c, T (&rf)[NP]) {   // F residuals of plane c (0 for corners and points off the interior)
+#pragma unroll
+        for (int k = 0; k < NP; k++)
+            rf[k] = (fface(c, k) && finside(c, k)) ? rR[(size_t)c * PR + foff[k]] : T(0);
+    };
+    // output point k: row b = y0 + e / 32, slot sl = s0 + e % 32
+    int ooff[NO], ol[NO];
+    bool orow[NO], oodd[NO], osl0[NO], oslok[NO];
+#pragma unroll
+    for (int k = 0; k < NO; k++) {
+        const int e = tid + k * kRdThreads;
+        const int ly = e / kRdTX, ls = e % kRdTX;
+        const int b = y0 + ly, sl = s0 + ls;
+        orow[k] = b < m;
+        oodd[k] = b & 1;
+        osl0[k] = sl == 0;
+        oslok[k] = sl <= h - 1;
+        ooff[k] = b * (h + 1) + sl;
+        ol[k] = (ly + 1) * W + (ls + 1);
+    }
+    // rings of LDS planes, rotated at the start of every plane step c: Mm, M0,
+    // Mq hold magenta planes c-1, c, c+1 (Mq written in the step); after the
+    // step's F values are written, Fa, Fb, Fc hold those of planes c-2, c-1, c
+    T *Mm = M[2], *M0 = M[0], *Mq = M[1];
+    T *Fa = F[0], *Fb = F[1], *Fc = F[2];
+    // prologue: magenta planes z0-2 (M0) and z0-1 (Mq) into LDS, plane z0 and
+    // the F residuals of plane z0-1 into registers
+#pragma unroll
+    for (int k = 0; k < kMsP; k++) {
+        const int e = tid + k * kRdThreads;
+        const T a0 = mload(z0 - 2, k), a1 = mload(z0 - 1, k);
         if (e < kMsN) {
-            M[(z0 + 1) % 3][e] = a0;
-            M[(z0 + 2) % 3][e] = a1;
+            M0[e] = a0;
+            Mq[e] = a1;
         }
     }
     T mn[kMsP];
 #pragma unroll
-    for (int k = 0; k < kMsP; k++) mn[k] = red_mload(vE, vO, m, s0, y0, z0, tid + k * kRdThreads);
+    for (int k = 0; k < kMsP; k++) mn[k] = mload(z0, k);
     T rf[NP];
     fload(z0 - 1, rf);
     T rn[NO];
 #pragma unroll
     for (int k = 0; k < NO; k++) rn[k] = T(0);
     for (int c = z0 - 1; c <= z1; c++) {
+        {
+            T* t = Mm; Mm = M0; M0 = Mq; Mq = t;
+            T* f = Fa; Fa = Fb; Fb = Fc; Fc = f;
+        }
 #pragma unroll
         for (int k = 0; k < kMsP; k++) {   // magenta plane c+1
             const int e = tid + k * kRdThreads;
-            if (e < kMsN) M[(c + 4) % 3][e] = mn[k];
+            if (e < kMsN) Mq[e] = mn[k];
         }
         T rfc[NP], rc[NO];
 #pragma unroll
@@ -502,75 +559,59 @@ __global__ void __launch_bounds__(kRdThreads) k3_red_planes(int m, T c1, T c2, c
         for (int k = 0; k < NO; k++) rc[k] = rn[k];
         if (c + 1 <= z1) {
 #pragma unroll
-            for (int k = 0; k < kMsP; k++) mn[k] = red_mload(vE, vO, m, s0, y0, c + 2, tid + k * kRdThreads);
+            for (int k = 0; k < kMsP; k++) mn[k] = mload(c + 2, k);
             fload(c + 1, rf);
         }
-        if (c >= z0 && c < z1) {   // corners of this plane need rR next iteration
+        if (c >= z0 && c < z1 && !(c & 1)) {   // corners of this plane need rR next iteration
 #pragma unroll
-            for (int k = 0; k < NO; k++) {
-                const int e = tid + k * kRdThreads;
-                const int b = y0 + e / kRdTX, sl = s0 + e % kRdTX;
-                const int a = 2 * sl + ((b + c) & 1);
-                if (b < m && a >= 1 && a < m && ((a | b | c) & 1) == 0) rn[k] = rR[idxR(m, a, b, c)];
-            }
+            for (int k = 0; k < NO; k++)
+                if (orow[k] && !oodd[k] && !osl0[k] && oslok[k]) rn[k] = rR[(size_t)c * PR + ooff[k]];
         }
         __syncthreads();
-        {   // face centres of plane c, same arithmetic and order as jac3_redF
-            const T* Mm = M[(c + 2) % 3];   // plane c-1
-            const T* M0 = M[c % 3];
-            const T* Mq = M[(c + 1) % 3];   // plane c+1
-            T* Fp = F[c % 3];
+        // face centres of plane c, same arithmetic and order as jac3_redF
+        // (base: the staged position of the slot's own half indices)
 #pragma unroll
-            for (int k = 0; k < NP; k++) {
-                const int p = tid + k * kRdThreads;
-                int a, b;
-                if (p >= kRdH * kRdW || !red_fpoint(s0, y0, c, p, a, b)) continue;
-                T v = T(0);
-                if (a >= 1 && a < m && b >= 1 && b < m && c >= 1 && c < m) {
-                    // staged position of half indices (i, j): (j - jL) * kMsW + (i - iL)
-                    auto at = [&](int aa, int bb) { return ((bb >> 1) - jL) * kMsW + ((aa >> 1) - iL); };
-                    T s;
-                    if (!(c & 1))
-                        s = 2 * (Mq[at(a, b)] + Mm[at(a, b)]) + M0[at(a + 1, b + 1)] + M0[at(a + 1, b - 1)]
-                            + M0[at(a - 1, b - 1)] + M0[at(a - 1, b + 1)];
-                    else if (!(a & 1))
-                        s = 2 * (M0[at(a + 1, b)] + M0[at(a - 1, b)]) + Mq[at(a, b + 1)] + Mm[at(a, b + 1)]
-                            + Mm[at(a, b - 1)] + Mq[at(a, b - 1)];
-                    else
-                        s = 2 * (M0[at(a, b + 1)] + M0[at(a, b - 1)]) + Mq[at(a + 1, b)] + Mq[at(a - 1, b)]
-                            + Mm[at(a - 1, b)] + Mm[at(a + 1, b)];
-                    v = (-c1 * rfc[k] + s) * T(0.125);
-                }
-                Fp[p] = v;
+        for (int k = 0; k < NP; k++) {
+            const int p = tid + k * kRdThreads;
+            if (p >= kRdH * kRdW || !fface(c, k)) continue;
+            T v = T(0);
+            if (finside(c, k)) {
+                const int q = fbase[k];
+                T sm;
+                if (!(c & 1))        // a, b odd: centres above and below, corners around
+                    sm = 2 * (Mq[q] + Mm[q]) + M0[q + kMsW + 1] + M0[q + 1] + M0[q] + M0[q + kMsW];
+                else if (fodd[k])    // b odd, a even: centres at a +- 1, corners at b +- 1 above and below
+                    sm = 2 * (M0[q] + M0[q - 1]) + Mq[q + kMsW] + Mm[q + kMsW] + Mm[q] + Mq[q];
+                else                 // b even, a odd: centres at b +- 1, corners at a +- 1 above and below
+                    sm = 2 * (M0[q] + M0[q - kMsW]) + Mq[q + 1] + Mq[q] + Mm[q] + Mm[q + 1];
+                v = (-c1 * rfc[k] + sm) * T(0.125);
             }
+            Fc[p] = v;
         }
         __syncthreads();
         const int co = c - 1;
         if (co >= z0) {
-            const T* Fm = F[(co + 2) % 3];
-            const T* F0 = F[co % 3];
-            const T* Fq = F[c % 3];
+            const T* Fm = Fa;   // plane co-1
+            const T* F0 = Fb;   // plane co
+            const T* Fq = Fc;   // plane co+1
 #pragma unroll
             for (int k = 0; k < NO; k++) {
-                const int e = tid + k * kRdThreads;
-                const int ly = e / kRdTX, ls = e % kRdTX;
-                const int b = y0 + ly, sl = s0 + ls;
-                const int a = 2 * sl + ((b + co) & 1);
-                if (b >= m || a < 1 || a >= m) continue;
-                const int l = (ly + 1) * W + (ls + 1);
-                const int odd = (a & 1) + (b & 1) + (co & 1);
+                const bool par = (oodd[k] ^ co) & 1;   // parity of a
+                if (!orow[k] || !oslok[k] || (osl0[k] && !par)) continue;
+                const int l = ol[k];
+                const bool corner = !oodd[k] && !(co & 1);   // then a is even too
                 T v;
-                if (odd == 2) {
+                if (!corner) {
                     v = F0[l];
                 } else {
-                    // corner (no red point has one or three odd indices): slots a/2 (= l) and a/2 - 1 (= l - 1);
-                    // rows b +- 1 are l +- W; the twelve faces in the order of Eq. (Erprolm) as jac3_redC sums them
-                    T s = F0[l + W] + F0[l - W] + F0[l - W - 1] + F0[l + W - 1]
-                        + Fq[l] + Fm[l] + Fm[l - 1] + Fq[l - 1]
-                        + Fq[l + W] + Fm[l + W] + Fm[l - W] + Fq[l - W];
-                    v = (-c2 * rc[k] + s) * (T(1) / T(12));
+                    // corner: slots a/2 (= l) and a/2 - 1 (= l - 1); rows b +- 1 are l +- W; the
+                    // twelve faces in the order of Eq. (Erprolm) as jac3_redC sums them
+                    T sm = F0[l + W] + F0[l - W] + F0[l - W - 1] + F0[l + W - 1]
+                         + Fq[l] + Fm[l] + Fm[l - 1] + Fq[l - 1]
+                         + Fq[l + W] + Fm[l + W] + Fm[l - W] + Fq[l - W];
+                    v = (-c2 * rc[k] + sm) * (T(1) / T(12));
                 }
-                vR[idxR(m, a, b, co)] = v;
+                vR[(size_t)co * PR + ooff[k]] = v;
             }
         }
         __syncthreads();
