@@ -845,52 +845,12 @@ void launch_rhs4_3d(int n, const double* f, double* g, hipStream_t s)
 // cube centres (2A+1, 2B+1, 2C+1), 0 <= A,B,C < m/2, from the blue grid (the
 // green grid of side m/2), then interior corners (2A, 2B, 2C) from the eight
 // new centres around them.  A workgroup marches a tile of centres (plus one
-// centre of halo below in A and B) through a chunk of C planes; the corner
-// plane C reads centre planes C-1 and C from a ring of two LDS planes.
+// centre of halo below in A and B) through a chunk of C planes.  Each blue
+// plane is staged in LDS once (the tile's region plus one, a ring of two
+// planes: centre plane C reads blue planes C and C+1); the corner plane C
+// reads centre planes C-1 and C from a ring of two LDS planes.
 constexpr int kMgTX = 32, kMgW = kMgTX + 1, kMgH = kPlTY + 1;
-
-template <typename T>
-struct MgIn {
-    T r, b0, b1, b2, b3, b4, b5, b6, b7;
-    int pos;   // LDS position; -1: no centre
-    bool ok;
-};
-
-template <typename T>
-__device__ inline MgIn<T> mag_fload(const T* __restrict__ rO, const T* __restrict__ vB, int m, int A0, int B0, int C,
-                                    int p)
-{
-    MgIn<T> q;
-    q.pos = -1;
-    q.ok = false;
-    q.r = q.b0 = q.b1 = q.b2 = q.b3 = q.b4 = q.b5 = q.b6 = q.b7 = T(0);
-    if (p >= kMgW * kMgH) return q;
-    q.pos = p;
-    const int h = m / 2;
-    const int A = A0 - 1 + p % kMgW, B = B0 - 1 + p / kMgW;
-    if (A < 0 || A >= h || B < 0 || B >= h || C < 0 || C >= h) return q;
-    q.ok = true;
-    const size_t w = (size_t)(h + 1), w2 = w * w;
-    const size_t o = idxG(h, A, B, C);
-    q.r = rO[idxMO(m, 2 * A + 1, 2 * B + 1, 2 * C + 1)];
-    q.b0 = vB[o + 1 + w + w2];
-    q.b1 = vB[o + 1 + w];
-    q.b2 = vB[o + 1 + w2];
-    q.b3 = vB[o + 1];
-    q.b4 = vB[o + w + w2];
-    q.b5 = vB[o + w];
-    q.b6 = vB[o + w2];
-    q.b7 = vB[o];
-    return q;
-}
-
-// same arithmetic and order as jac3_magF
-template <typename T>
-__device__ inline T mag_fcomp(const MgIn<T>& q, T cc)
-{
-    if (!q.ok) return T(0);
-    return (-cc * q.r + q.b0 + q.b1 + q.b2 + q.b3 + q.b4 + q.b5 + q.b6 + q.b7) * T(0.125);
-}
+constexpr int kMgBW = kMgW + 1, kMgBH = kMgH + 1, kMgBN = kMgBW * kMgBH;   // staged blue region
 
 template <typename T>
 __global__ void __launch_bounds__(kPlThreads) k3_mag_planes(int m, T cc, const T* __restrict__ rE,
@@ -900,63 +860,117 @@ __global__ void __launch_bounds__(kPlThreads) k3_mag_planes(int m, T cc, const T
 {
     DMG_GATE(ctl);
     constexpr int W = kMgW, NP = (kMgW * kMgH + kPlThreads - 1) / kPlThreads, NO = kMgTX * kPlTY / kPlThreads;
+    constexpr int NB = (kMgBN + kPlThreads - 1) / kPlThreads;
     __shared__ T F[2][kMgW * kMgH];
+    __shared__ T Bs[2][kMgBN];
     const int h = m / 2;
     const int bid = xcd_block();   // tiles of one die are neighbours
     const int tx = bid % ntx, ty = (bid / ntx) % nty, tz = bid / (ntx * nty);
     const int A0 = tx * kMgTX, B0 = ty * kPlTY, C0 = tz * zc;
     const int C1 = min(C0 + zc, h);   // centre planes [C0, C1) and corner planes [C0, C1) are output
     const int tid = threadIdx.x;
-    MgIn<T> nx[NP];
+    const size_t PB = (size_t)(h + 1) * (h + 1), PO = (size_t)h * h, PE = (size_t)(h + 1) * (h + 1);
+    // plane-invariant per-thread data: staged blue offsets, centre slots, corner outputs
+    int boff[NB];
 #pragma unroll
-    for (int j = 0; j < NP; j++) nx[j] = mag_fload(rO, vB, m, A0, B0, C0 - 1, tid + j * kPlThreads);
+    for (int k = 0; k < NB; k++) {
+        const int e = tid + k * kPlThreads;
+        const int A = A0 - 1 + e % kMgBW, B = B0 - 1 + e / kMgBW;
+        boff[k] = (e < kMgBN && A >= 0 && A <= h && B >= 0 && B <= h) ? B * (h + 1) + A : -1;
+    }
+    auto bload = [&](int C, int k) -> T {
+        return (boff[k] >= 0 && C >= 0 && C <= h) ? vB[(size_t)C * PB + boff[k]] : T(0);
+    };
+    int poff[NP], pq[NP];
+    bool pok[NP], pown[NP];
+#pragma unroll
+    for (int j = 0; j < NP; j++) {
+        const int p = tid + j * kPlThreads;
+        const int A = A0 - 1 + p % W, B = B0 - 1 + p / W;
+        pok[j] = p < kMgW * kMgH && A >= 0 && A < h && B >= 0 && B < h;
+        pown[j] = pok[j] && A >= A0 && B >= B0;
+        poff[j] = B * h + A;
+        pq[j] = (p / W) * kMgBW + p % W;   // staged blue position of (A, B)
+    }
+    auto rload = [&](int C, int j) -> T { return (pok[j] && C >= 0 && C < h) ? rO[(size_t)C * PO + poff[j]] : T(0); };
+    int ooff[NO], ol[NO];
+    bool oin[NO];
+#pragma unroll
+    for (int k = 0; k < NO; k++) {
+        const int e = tid + k * kPlThreads;
+        const int A = A0 + e % kMgTX, B = B0 + e / kMgTX;
+        oin[k] = A >= 1 && A < h && B >= 1 && B < h;
+        ooff[k] = B * (h + 1) + A;
+        ol[k] = (B - B0 + 1) * W + (A - A0 + 1);   // centre (A, B); (A-1) is l-1, (B-1) is l-W
+    }
+    // prologue: blue plane C0-1 into LDS; registers: blue plane C0, the centre
+    // residuals of plane C0-1
+    T *Bm = Bs[0], *Bq = Bs[1];   // in step C: blue planes C (Bm) and C+1 (Bq)
+#pragma unroll
+    for (int k = 0; k < NB; k++) {
+        const int e = tid + k * kPlThreads;
+        const T v = bload(C0 - 1, k);
+        if (e < kMgBN) Bq[e] = v;
+    }
+    T bn[NB], rnx[NP];
+#pragma unroll
+    for (int k = 0; k < NB; k++) bn[k] = bload(C0, k);
+#pragma unroll
+    for (int j = 0; j < NP; j++) rnx[j] = rload(C0 - 1, j);
     T rn[NO];
 #pragma unroll
     for (int k = 0; k < NO; k++) rn[k] = T(0);
+    T *Fm = F[0], *F0 = F[1];   // in step C: centre planes C-1 (Fm) and C (F0)
     for (int C = C0 - 1; C < C1; C++) {
-        MgIn<T> cur[NP];
-        T rc[NO];
+        {
+            T* t = Bm; Bm = Bq; Bq = t;
+            T* f = Fm; Fm = F0; F0 = f;
+        }
 #pragma unroll
-        for (int j = 0; j < NP; j++) cur[j] = nx[j];
+        for (int k = 0; k < NB; k++) {   // blue plane C+1
+            const int e = tid + k * kPlThreads;
+            if (e < kMgBN) Bq[e] = bn[k];
+        }
+        T rr[NP], rc[NO];
+#pragma unroll
+        for (int j = 0; j < NP; j++) rr[j] = rnx[j];
 #pragma unroll
         for (int k = 0; k < NO; k++) rc[k] = rn[k];
         if (C + 1 < C1) {
 #pragma unroll
-            for (int j = 0; j < NP; j++) nx[j] = mag_fload(rO, vB, m, A0, B0, C + 1, tid + j * kPlThreads);
-        }
-        if (C + 1 >= C0 && C + 1 < C1) {   // corners of plane C+1 need rE next iteration
+            for (int k = 0; k < NB; k++) bn[k] = bload(C + 2, k);
 #pragma unroll
-            for (int k = 0; k < NO; k++) {
-                const int e = tid + k * kPlThreads;
-                const int A = A0 + e % kMgTX, B = B0 + e / kMgTX;
-                if (A >= 1 && A < h && B >= 1 && B < h && C + 1 >= 1 && C + 1 < h)
-                    rn[k] = rE[idxME(m, 2 * A, 2 * B, 2 * (C + 1))];
-            }
+            for (int j = 0; j < NP; j++) rnx[j] = rload(C + 1, j);
         }
-        T* Fp = F[(C + 2) & 1];   // plane C (C >= -1)
+        if (C + 1 >= C0 && C + 1 < C1 && C + 1 >= 1) {   // corners of plane C+1 need rE next iteration
+#pragma unroll
+            for (int k = 0; k < NO; k++)
+                if (oin[k]) rn[k] = rE[(size_t)(C + 1) * PE + ooff[k]];
+        }
+        __syncthreads();
+        // centres of plane C, same arithmetic and order as jac3_magF
 #pragma unroll
         for (int j = 0; j < NP; j++) {
-            if (cur[j].pos < 0) continue;
-            const T v = mag_fcomp(cur[j], cc);
-            Fp[cur[j].pos] = v;
-            const int p = cur[j].pos;
-            const int A = A0 - 1 + p % W, B = B0 - 1 + p / W;
-            if (cur[j].ok && C >= C0 && A >= A0 && A < A0 + kMgTX && B >= B0 && B < B0 + kPlTY)
-                vO[idxMO(m, 2 * A + 1, 2 * B + 1, 2 * C + 1)] = v;
+            const int p = tid + j * kPlThreads;
+            if (p >= kMgW * kMgH) continue;
+            T v = T(0);
+            if (pok[j] && C >= 0 && C < h) {
+                const int q = pq[j], w = kMgBW;
+                v = (-cc * rr[j] + Bq[q + 1 + w] + Bm[q + 1 + w] + Bq[q + 1] + Bm[q + 1] + Bq[q + w] + Bm[q + w] +
+                     Bq[q] + Bm[q]) * T(0.125);
+                if (pown[j] && C >= C0) vO[(size_t)C * PO + poff[j]] = v;
+            }
+            F0[p] = v;
         }
         __syncthreads();
         if (C >= C0 && C >= 1) {   // corner plane C from centre planes C-1 and C
-            const T* Fm = F[(C + 1) & 1];
-            const T* F0 = F[(C + 2) & 1];
 #pragma unroll
             for (int k = 0; k < NO; k++) {
-                const int e = tid + k * kPlThreads;
-                const int A = A0 + e % kMgTX, B = B0 + e / kMgTX;
-                if (A < 1 || A >= h || B < 1 || B >= h) continue;
-                const int l = (B - B0 + 1) * W + (A - A0 + 1);   // centre (A, B); (A-1) is l-1, (B-1) is l-W
+                if (!oin[k]) continue;
+                const int l = ol[k];
                 // the eight centres in the order of Eq. (Emprolb) as jac3_magC sums them
-                T s = F0[l] + Fm[l] + F0[l - W] + Fm[l - W] + F0[l - 1] + Fm[l - 1] + F0[l - W - 1] + Fm[l - W - 1];
-                vE[idxME(m, 2 * A, 2 * B, 2 * C)] = (-cc * rc[k] + s) * T(0.125);
+                T sm = F0[l] + Fm[l] + F0[l - W] + Fm[l - W] + F0[l - 1] + Fm[l - 1] + F0[l - W - 1] + Fm[l - W - 1];
+                vE[(size_t)C * PE + ooff[k]] = (-cc * rc[k] + sm) * T(0.125);
             }
         }
         __syncthreads();
@@ -987,7 +1001,7 @@ void launch_jac3(const Lev3<T>& L, const Lev3<T>& Cr, T* zero, const Ctl* ctl, h
     int m = L.m;
     const T* vc = Cr.v ? Cr.v : zero;
     if (L.kind == 2) {
-        if (m >= 2 * kPlMinSide) {   // at side 128 the 64^3 centres give too few workgroups (measured slower)
+        if (m >= kPlMinSide) {
             int h = m / 2, ntx = (h + kMgTX - 1) / kMgTX, nty = (h + kPlTY - 1) / kPlTY, zc = pl_zchunk(m);
             int ntz = (h + zc - 1) / zc;
             hipLaunchKernelGGL(k3_mag_planes<T>, dim3(ntx * nty * ntz), dim3(kPlThreads), 0, s, m, L.c, L.r, L.r2, vc,
