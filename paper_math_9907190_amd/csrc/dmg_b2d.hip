@@ -1393,7 +1393,7 @@ __device__ double net_cut_2d(const T* __restrict__ rc, T* __restrict__ vD, const
         A[p * kNetCh] = f2bf((float)((double)rc[p] * sc));
     }
     __syncthreads();
-    const int WLY = N::T * 256;
+    const int WLY = N::WLY;
     net_conv_fwd<2, true>(A, B, nullptr, wf, linq);
     __syncthreads();
     net_conv_fwd<2, true>(B, A, nullptr, wf + WLY, linq);
@@ -1437,7 +1437,7 @@ __global__ void __launch_bounds__(kCoarseThreadsB) kb_coarse_net(CoarseLev<T> L,
     __shared__ __align__(16) bf16_t A[N::ACT];
     __shared__ __align__(16) bf16_t B[N::ACT];
     __shared__ float out0[N::TILES * 16];
-    __shared__ short linq[N::TILES * 16];
+    __shared__ short linq[N::LQ];
     __shared__ double red[kCoarseThreadsB / 64];
     __shared__ T vsave[(N::G) * (N::G / 2 + 1)];
     const int m = L.l[cut].m;

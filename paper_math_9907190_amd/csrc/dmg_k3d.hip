@@ -1651,7 +1651,7 @@ __device__ double net_cut_3d(const T* rc, T* vR, const bf16_t* __restrict__ wf, 
         A[p * kNetCh] = f2bf((float)((double)rc[p] * sc));
     }
     __syncthreads();
-    const int WLY = N::T * 256;
+    const int WLY = N::WLY;
     net_conv_fwd<3, true>(A, B, nullptr, wf, linq);
     __syncthreads();
     net_conv_fwd<3, true>(B, A, nullptr, wf + WLY, linq);
@@ -1678,8 +1678,8 @@ template <typename T>
 constexpr size_t coarse3_net_save_off()
 {
     using N = NetGeo<3>;
-    return (coarse3_net_act_off<T>() + 2 * sizeof(bf16_t) * N::ACT + N::TILES * 16 * (sizeof(float) + sizeof(short)) +
-            15) / 16 * 16;
+    return (coarse3_net_act_off<T>() + 2 * sizeof(bf16_t) * N::ACT + N::TILES * 16 * sizeof(float) +
+            N::LQ * sizeof(short) + 15) / 16 * 16;
 }
 template <typename T>
 constexpr size_t coarse3_net_lds() { return coarse3_net_save_off<T>() + sizeof(T) * 405; }

@@ -25,13 +25,13 @@ template <int DIM>
 constexpr size_t net_lds_train()
 {
     using N = NetGeo<DIM>;
-    return 6 * (size_t)N::ACT * sizeof(bf16_t) + 2 * N::TILES * 16 * sizeof(float) + N::TILES * 16 * sizeof(short);
+    return 6 * (size_t)N::ACT * sizeof(bf16_t) + 2 * N::TILES * 16 * sizeof(float) + N::LQ * sizeof(short);
 }
 template <int DIM>
 constexpr size_t net_lds_fwd()
 {
     using N = NetGeo<DIM>;
-    return 2 * (size_t)N::ACT * sizeof(bf16_t) + N::TILES * 16 * sizeof(float) + N::TILES * 16 * sizeof(short);
+    return 2 * (size_t)N::ACT * sizeof(bf16_t) + N::TILES * 16 * sizeof(float) + N::LQ * sizeof(short);
 }
 
 __device__ inline double block_sum(double v, double* red)
@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(kNetThreads) kn_train(const double* __restrict
     net_load<DIM>(r + (size_t)s * N::PTS, judge ? nullptr : e + (size_t)s * N::PTS, normalize, act, tgt, red,
                   judge != 0);
     __syncthreads();
-    const int WLY = N::T * 256;
+    const int WLY = N::WLY, GLY = N::GLY;
     net_conv_fwd<DIM, true>(act, act + N::ACT, nullptr, wf, linq);
     __syncthreads();
     net_conv_fwd<DIM, true>(act + N::ACT, act + 2 * N::ACT, nullptr, wf + WLY, linq);
@@ -201,13 +201,13 @@ __global__ void __launch_bounds__(kNetThreads) kn_train(const double* __restrict
     if (threadIdx.x == 0) lpart[blockIdx.x] = l;
     if (!grad) return;
     float* gw = gpart + (size_t)blockIdx.x * N::NW;
-    net_conv_bwd_weight<DIM>(act + 3 * N::ACT, d0, gw + 3 * WLY, linq);
+    net_conv_bwd_weight<DIM>(act + 3 * N::ACT, d0, gw + 3 * GLY, linq);
     net_conv_bwd_data<DIM>(d0, act + 3 * N::ACT, d1, wb + 3 * WLY, linq);
     __syncthreads();
-    net_conv_bwd_weight<DIM>(act + 2 * N::ACT, d1, gw + 2 * WLY, linq);
+    net_conv_bwd_weight<DIM>(act + 2 * N::ACT, d1, gw + 2 * GLY, linq);
     net_conv_bwd_data<DIM>(d1, act + 2 * N::ACT, d0, wb + 2 * WLY, linq);
     __syncthreads();
-    net_conv_bwd_weight<DIM>(act + N::ACT, d0, gw + WLY, linq);
+    net_conv_bwd_weight<DIM>(act + N::ACT, d0, gw + GLY, linq);
     net_conv_bwd_data<DIM>(d0, act + N::ACT, d1, wb + WLY, linq);
     __syncthreads();
     net_conv_bwd_weight<DIM>(act, d1, gw, linq);
@@ -231,7 +231,7 @@ __global__ void __launch_bounds__(kNetThreads) kn_forward(const double* __restri
     __syncthreads();
     double back = net_load<DIM>(in + s * N::PTS, nullptr, normalize, A, nullptr, red);
     __syncthreads();
-    const int WLY = N::T * 256;
+    const int WLY = N::WLY;
     net_conv_fwd<DIM, true>(A, B, nullptr, wf, linq);
     __syncthreads();
     net_conv_fwd<DIM, true>(B, A, nullptr, wf + WLY, linq);
@@ -267,7 +267,7 @@ __global__ void __launch_bounds__(256) kn_adam(const float* __restrict__ gpart, 
     if (i >= N::NW) return;
     double gs = 0;
     for (int b = 0; b < B; b++) gs += gpart[(size_t)b * N::NW + i];
-    const int lt = i >> 8, ci = (i >> 4) & 15, co = i & 15, layer = lt / N::T;
+    const int lt = i >> 8, ci = (i >> 4) & 15, co = i & 15, layer = lt / N::T, tap = lt % N::T;
     if ((layer == 0 && ci != 0) || (layer == kNetLayers - 1 && co != 0)) gs = 0;
     const float g = (float)gs;
     if (gout) gout[i] = g;
@@ -280,8 +280,8 @@ __global__ void __launch_bounds__(256) kn_adam(const float* __restrict__ gpart, 
     v[i] = vi;
     w[i] = wi;
     bf16_t h = f2bf(wi);
-    wf[net_pack_fwd(lt, ci, co)] = h;
-    wb[net_pack_bwd(lt, ci, co)] = h;
+    wf[net_pack_fwd(N::T, layer, tap, ci, co)] = h;
+    wb[net_pack_bwd(N::T, layer, tap, ci, co)] = h;
 }
 
 template <int DIM>
@@ -316,6 +316,7 @@ namespace {
 int net_nw(int dim) { return dim == 2 ? NetGeo<2>::NW : NetGeo<3>::NW; }
 int net_nin(int dim) { return dim == 2 ? NetGeo<2>::NIN : NetGeo<3>::NIN; }
 int net_taps(int dim) { return dim == 2 ? 9 : 27; }
+int net_pack_len(int dim) { return dim == 2 ? NetGeo<2>::PACK : NetGeo<3>::PACK; }
 
 void net_layout(mg_net& N)
 {
@@ -325,8 +326,8 @@ void net_layout(mg_net& N)
     N.off_w = take(4 * nw);
     N.off_m = take(4 * nw);
     N.off_v = take(4 * nw);
-    N.off_wf = take(2 * nw);
-    N.off_wb = take(2 * nw);
+    N.off_wf = take(2 * (size_t)net_pack_len(N.dim));   // packed forms; odd tap counts pad with zeros
+    N.off_wb = take(2 * (size_t)net_pack_len(N.dim));
     N.off_gpart = take(4 * nw * (size_t)N.max_batch);
     N.off_lpart = take(8 * (size_t)N.max_batch);
     N.off_gout = take(4 * nw);
@@ -380,16 +381,20 @@ long long gcdll(long long a, long long b) { while (b) { long long t = a % b; a =
 namespace dmg {
 
 // host packing of fp32 weights [layer][tap][ci][co] into the two bf16 forms
+// (each of net_pack_len(dim) entries; the padding entries are set to zero)
 void net_pack_host(int dim, const float* w, bf16_t* wf, bf16_t* wb)
 {
-    int T = net_taps(dim);
-    for (int lt = 0; lt < kNetLayers * T; lt++)
-        for (int ci = 0; ci < kNetCh; ci++)
-            for (int co = 0; co < kNetCh; co++) {
-                bf16_t h = f2bf(w[(lt * kNetCh + ci) * kNetCh + co]);
-                if (wf) wf[net_pack_fwd(lt, ci, co)] = h;
-                if (wb) wb[net_pack_bwd(lt, ci, co)] = h;
-            }
+    const int T = net_taps(dim), len = net_pack_len(dim);
+    if (wf) memset(wf, 0, sizeof(bf16_t) * len);
+    if (wb) memset(wb, 0, sizeof(bf16_t) * len);
+    for (int layer = 0; layer < kNetLayers; layer++)
+        for (int tap = 0; tap < T; tap++)
+            for (int ci = 0; ci < kNetCh; ci++)
+                for (int co = 0; co < kNetCh; co++) {
+                    bf16_t h = f2bf(w[((layer * T + tap) * kNetCh + ci) * kNetCh + co]);
+                    if (wf) wf[net_pack_fwd(T, layer, tap, ci, co)] = h;
+                    if (wb) wb[net_pack_bwd(T, layer, tap, ci, co)] = h;
+                }
 }
 
 int net_weight_count(int dim) { return (dim == 2 || dim == 3) ? net_nw(dim) : 0; }
@@ -446,14 +451,15 @@ int mg_net_set_weights(mg_net* N, const float* w)
                 int layer = lt / T;
                 if ((layer == 0 && ci) || (layer == kNetLayers - 1 && co)) wm[(lt * kNetCh + ci) * kNetCh + co] = 0.f;
             }
-    std::vector<bf16_t> wf(N->nw), wb(N->nw);
+    const size_t np = (size_t)net_pack_len(N->dim);
+    std::vector<bf16_t> wf(np), wb(np);
     net_pack_host(N->dim, wm.data(), wf.data(), wb.data());
     size_t nb = sizeof(float) * N->nw;
     if (hipMemcpyAsync(N->at<float>(N->off_w), wm.data(), nb, hipMemcpyHostToDevice, N->stream) != hipSuccess ||
         hipMemsetAsync(N->at<float>(N->off_m), 0, nb, N->stream) != hipSuccess ||
         hipMemsetAsync(N->at<float>(N->off_v), 0, nb, N->stream) != hipSuccess ||
-        hipMemcpyAsync(N->at<bf16_t>(N->off_wf), wf.data(), 2 * (size_t)N->nw, hipMemcpyHostToDevice, N->stream) != hipSuccess ||
-        hipMemcpyAsync(N->at<bf16_t>(N->off_wb), wb.data(), 2 * (size_t)N->nw, hipMemcpyHostToDevice, N->stream) != hipSuccess ||
+        hipMemcpyAsync(N->at<bf16_t>(N->off_wf), wf.data(), sizeof(bf16_t) * np, hipMemcpyHostToDevice, N->stream) != hipSuccess ||
+        hipMemcpyAsync(N->at<bf16_t>(N->off_wb), wb.data(), sizeof(bf16_t) * np, hipMemcpyHostToDevice, N->stream) != hipSuccess ||
         hipStreamSynchronize(N->stream) != hipSuccess)
         return MG_ERR_HIP;
     N->step = 0;
