@@ -44,10 +44,10 @@ FAMILY_NAMES = {0: "residual", 1: "restriction", 2: "jacobi", 3: "finest jacobi 
 FAMILY_KERNELS = {
     "usual": {0: "k_residual", 1: "ku2_fw / ku3_fw (full weighting)", 2: "ku2_up / ku3_up (interpolation + red-black Jacobi)",
               3: "ku2_up / ku3_up, finest (u += v)", 4: "-", 5: "k_finalize"},
-    2: {0: "kb_resid (r0, Eqs. Erest2r then Erest2b onto r2, norm partials)",
+    2: {0: "kb_resid (r0 formed, not stored; Eqs. Erest2r then Erest2b onto r2, norm partials)",
         1: "kb_rs_pair, kb_mid_down, kb_rs_*",
         2: "kb_jac_pair, kb_mid_up, kb_jac_*",
-        3: "kb_finest_fused (r1 by Eq. Erest2r, Jacobi of the first diagonal and the finest axis level, u += v)",
+        3: "kb_finest_oop (r0 from u and f, r1 by Eq. Erest2r, Jacobi of the first diagonal and the finest axis level, u + v into the other iterate buffer)",
         4: "kb_coarse", 5: "kb_finalize"},
     3: {0: "k3_resid_planes (r0 and Eq. Erred onto the red level, norm partials)",
         1: "k3_r2m_planes, k3_rs_m2b, k3_down_group (a level group of side 16..64 per launch), k3_rs_*",
@@ -84,20 +84,27 @@ def err_vs(u, ref):
 
 
 def kernel_table(S, f, cycles, torch):
-    """Per kernel family: mean launch time, launches and algorithmic bytes per
-    cycle, from HIP events around every launch of the family on the solver's
-    stream over `cycles` V-cycles (mg_vcycle: every launch does its work)."""
+    """Per kernel family: time, launches and algorithmic bytes per cycle of a
+    solve (mg_solve, the path the timed solves take), from HIP events around
+    every launch of the family on the solver's stream.  Each figure is the
+    difference between a solve of 2 + `cycles` cycles and one of 2 cycles
+    (rtol 0, so every cycle runs): the cycles' own launches, without the
+    first residual evaluation and the set-up of a solve."""
     u = torch.zeros_like(f)
-    S.vcycle(u, f)
+    S.solve(u, f, rtol=0.0, max_cycles=2)
     torch.cuda.synchronize()
     rows = []
     for fam in range(6):
         S.timing(fam)
-        for _ in range(cycles):
-            S.vcycle(u, f)
-        ms, cnt, byt = S.timing_read()
+        tot = []
+        for k in (2, 2 + cycles):
+            u.zero_()
+            torch.cuda.synchronize()
+            S.solve(u, f, rtol=0.0, max_cycles=k)
+            tot.append(S.timing_read())
         S.timing(-1)
-        if cnt == 0:
+        ms, cnt, byt = (b - a for a, b in zip(*tot))
+        if cnt <= 0:
             continue
         gbs = byt / (ms * 1e-3) / 1e9
         key = "usual" if getattr(S, "scheme", "diagonal") == "usual" else f.dim()

@@ -64,12 +64,25 @@ namespace dmg {
 // strips then reach the halo rows they share at the same time, while those
 // rows are still in L2.  A mirrored strip starts on an even row, so it
 // computes one diagonal row before its start instead of one past its end.
+// st0 = false (out-of-place solves): r is formed, restricted and summed but
+// not stored.
 constexpr int kResidPairs = 61;
-template <typename T, int CH, bool NT, bool FZ, bool M4, bool WF, bool MIR>
-__device__ inline void resid_body(int m, double inv_h2, const Fin2<T>& it, int wv, int nwx, int rows, double& acc,
-                                  double& accf)
+
+// Eq. (Evpois): the residual at columns 2t, 2t+1 of one row from f there and
+// u at the lane's pair (c), the grid row south (s) and north (n) of it and the
+// columns 2t-1 (W) and 2t+2 (E); one expression for every kernel that forms
+// it, so that they all get the same bits
+__device__ inline void resid_pair(double inv_h2, double fx, double fy, double uW, double us0, double us1, double uc0,
+                                  double uc1, double un0, double un1, double uE, double& x0, double& x1)
 {
-    const double* __restrict__ u = it.u;
+    x0 = fx - (uW + us0 + uc1 + un0 - 4 * uc0) * inv_h2;
+    x1 = fy - (uc0 + us1 + uE + un1 - 4 * uc1) * inv_h2;
+}
+
+template <typename T, int CH, bool NT, bool FZ, bool M4, bool WF, bool MIR>
+__device__ inline void resid_body(int m, double inv_h2, const Fin2<T>& it, const double* __restrict__ u, bool st0,
+                                  int wv, int nwx, int rows, double& acc, double& accf)
+{
     const double* __restrict__ f = it.f;
     T* __restrict__ r0 = it.r0;
     T* __restrict__ rD = it.r1;
@@ -145,26 +158,27 @@ __device__ inline void resid_body(int m, double inv_h2, const Fin2<T>& it, int w
                 x0 = c.fx[i] - (-20 * uc0 + 4 * (us0 + un0 + uW + uc1) + un1 + nW + sW + us1) * inv_h2;
                 x1 = c.fy[i] - (-20 * uc1 + 4 * (us1 + un1 + uc0 + uE) + nE + un0 + us0 + sE) * inv_h2;
             } else {
-                x0 = c.fx[i] - (uW + us0 + uc1 + un0 - 4 * uc0) * inv_h2;
-                x1 = c.fy[i] - (uc0 + us1 + uE + un1 - 4 * uc1) * inv_h2;
+                resid_pair(inv_h2, c.fx[i], c.fy[i], uW, us0, us1, uc0, uc1, un0, un1, uE, x0, x1);
             }
             T r0j = (rowin && c0) ? (T)x0 : T(0);
             T r1j = (rowin && c1) ? (T)x1 : T(0);
             if (j >= y0 && j < y1 && useful) {
                 T* p = r0 + (size_t)R(j) * w + 2 * t;
                 if (c0 && c1) {
-                    if (NT) st_pair_nt(p, r0j, r1j);
-                    else *reinterpret_cast<P2<T>*>(p) = P2<T>{r0j, r1j};
+                    if (st0) {
+                        if (NT) st_pair_nt(p, r0j, r1j);
+                        else *reinterpret_cast<P2<T>*>(p) = P2<T>{r0j, r1j};
+                    }
                     acc += x0 * x0 + x1 * x1;
                     if constexpr (WF) accf += c.fx[i] * c.fx[i] + c.fy[i] * c.fy[i];
                 }
                 else if (c1) {
-                    p[1] = r1j;
+                    if (st0) p[1] = r1j;
                     acc += x1 * x1;
                     if constexpr (WF) accf += c.fy[i] * c.fy[i];
                 }
                 else if (c0) {
-                    p[0] = r0j;
+                    if (st0) p[0] = r0j;
                     acc += x0 * x0;
                     if constexpr (WF) accf += c.fx[i] * c.fx[i];
                 }
@@ -217,15 +231,19 @@ __device__ inline void resid_body(int m, double inv_h2, const Fin2<T>& it, int w
 
 template <typename T, int CH, bool NT, bool FZ, bool M4, bool WF>
 __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu((FZ && (sizeof(T) == 8 || M4)) || WF ? 3 : 4))) kb_resid(int m, double inv_h2, const Fin2<T>* __restrict__ items,
-                                                      int nwx, int nwaves, int rows, const Ctl* __restrict__ ctls)
+                                                      int nwx, int nwaves, int rows, const Ctl* __restrict__ ctls,
+                                                      int oop)
 {
     const Fin2<T> it = items[blockIdx.y];
     ITEM_GATE(ctls, it.prob);
     const int wv = rows_wave_id(nwaves);
+    // out of place: evaluation k reads the iterate of cycle k (u for even k, ub for odd k)
+    const bool pp = oop && it.ub;
+    const double* uk = pp && (ctls[it.prob].k & 1) ? it.ub : it.u;
     double acc = 0, accf = 0;
     if (wv < nwaves) {
-        if (FZ && ((wv / nwx) & 1)) resid_body<T, CH, NT, FZ, M4, WF, true>(m, inv_h2, it, wv, nwx, rows, acc, accf);
-        else resid_body<T, CH, NT, FZ, M4, WF, false>(m, inv_h2, it, wv, nwx, rows, acc, accf);
+        if (FZ && ((wv / nwx) & 1)) resid_body<T, CH, NT, FZ, M4, WF, true>(m, inv_h2, it, uk, !pp, wv, nwx, rows, acc, accf);
+        else resid_body<T, CH, NT, FZ, M4, WF, false>(m, inv_h2, it, uk, !pp, wv, nwx, rows, acc, accf);
     }
     double sum = rows_block_sum(acc);
     if (threadIdx.x == 0) it.part[blockIdx.x] = sum;
@@ -423,9 +441,17 @@ constexpr int kFusePairs = 60;
 // passed in the unmirrored order, so the values are the same bits.  Two
 // neighbouring strips then reach the rows they share at the same time (both
 // at their start or both at their end), while those rows are still in L2.
-template <typename T, bool FINEST, bool NT, bool MIR>
+// PP (FINEST, FP64; out-of-place solves): the axis residual rows are not read
+// but formed from the previous iterate uc and f (Eq. Evpois, the residual
+// kernel's expression: the same bits), and the new iterate uc + v goes to u,
+// another buffer, so no workgroup ever reads a value another one has
+// updated.  The lane's u pairs of the rows it has loaded stay in registers
+// (five rows) for the update; lanes 0 and 63 also load the one column beyond
+// the band that their residual needs.
+template <typename T, bool FINEST, bool NT, bool MIR, bool PP = false>
 __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, const T* __restrict__ v2,
-                                  T* __restrict__ vA, double* __restrict__ u, int wv, int nwx, int rows)
+                                  T* __restrict__ vA, double* __restrict__ u, int wv, int nwx, int rows,
+                                  const double* __restrict__ uc = nullptr, const double* __restrict__ fr = nullptr)
 {
     const int lane = threadIdx.x & 63;
     const int wx = wv % nwx, sy = wv / nwx;
@@ -476,17 +502,88 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
         return MIR ? jac2_sum(cd, rC, Fp_w, Fp, Fm, Fm_w) : jac2_sum(cd, rC, Fm_w, Fm, Fp, Fp_w);
     };
     auto fsr = [&](int k, T r1k) -> T { return f21(k, r1k, ld2((k - 1) >> 1), ld2((k + 1) >> 1)); };
+    // PP: the previous iterate's pair at marched row k, and in e the column
+    // beyond the band (lane 0: 2t-1, lane 63: 2t+2); column m+1 does not exist
+    const double inv_h2 = (double)m * (double)m;
+    auto ldU = [&](int k, double& x, double& y, double& e) {
+        x = y = e = 0;
+        if (!colok || k < 0 || k > m) return;
+        const double* p = uc + (size_t)R(k) * w + 2 * t;
+        if (t < h) {
+            P2<double> v = NT ? ld_pair_nt(p) : *reinterpret_cast<const P2<double>*>(p);
+            x = v.x;
+            y = v.y;
+        } else {
+            x = p[0];
+        }
+        if (lane == 0 && t >= 1) e = p[-1];
+        if (lane == 63 && 2 * t + 2 <= m) e = p[2];
+    };
+    auto ldF = [&](int k, double& x, double& y) {
+        x = y = 0;
+        if (!colok || k < 1 || k > m - 1) return;
+        const double* q = fr + (size_t)R(k) * w + 2 * t;
+        P2<double> v = NT ? ld_pair_nt(q) : *reinterpret_cast<const P2<double>*>(q);
+        x = v.x;
+        y = v.y;
+    };
+    // PP: the axis residual pair of marched row k from the u pairs of marched
+    // rows k-1 (a), k (b), k+1 (c), the outer column e of row k and f of row k,
+    // zero where ldR reads zero
+    auto r0row = [&](int k, double ax, double ay, double bx, double by, double cx, double cy, double e, double fx,
+                     double fy, T& x, T& y) {
+        double uW = __shfl_up(by, 1), uE = __shfl_down(bx, 1);
+        if (lane == 0) uW = e;
+        if (lane == 63) uE = e;
+        x = y = 0;
+        if (!colok || k < 1 || k > m - 1) return;
+        double x0, x1;
+        if (MIR) resid_pair(inv_h2, fx, fy, uW, cx, cy, bx, by, ax, ay, uE, x0, x1);
+        else resid_pair(inv_h2, fx, fy, uW, ax, ay, bx, by, cx, cy, uE, x0, x1);
+        x = c0 ? (T)x0 : T(0);
+        y = c1 ? (T)x1 : T(0);
+    };
     // window entering row j: diagonal values of rows j-1 (dm), j (d0); at even
     // j, Fn = F row j+1; at odd j, vlo = v2 row (j+1)/2.  The axis residual
     // pairs of rows j-3 .. j+2 give the diagonal residuals of rows j-2 .. j+1.
     int j = y0 - 1;
     T a0x, a0y, a1x, a1y, a2x, a2y, sx, sy_, nx, ny, xx, xy;
-    ldR(j - 3, a0x, a0y);
-    ldR(j - 2, a1x, a1y);
-    ldR(j - 1, a2x, a2y);
-    ldR(j, sx, sy_);
-    ldR(j + 1, nx, ny);
-    ldR(j + 2, xx, xy);
+    // PP: u pairs of rows jj-1 .. jj+2 (w0 .. w3) entering an odd row jj, of
+    // rows jj-1 .. jj+3 (w0 .. w4) entering an even one; eS: the outer column
+    // of the next odd row jj' plus 2
+    double w0x = 0, w0y = 0, w1x = 0, w1y = 0, w2x = 0, w2y = 0, w3x = 0, w3y = 0, w4x = 0, w4y = 0, eS = 0;
+    if constexpr (PP) {
+        double ux_[8], uy_[8], ue_[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++) ldU(j - 4 + i, ux_[i], uy_[i], ue_[i]);   // rows j-4 .. j+3
+        T rx_[6], ry_[6];
+#pragma unroll
+        for (int i = 0; i < 6; i++) {   // residual rows j-3 .. j+2
+            double fx, fy;
+            ldF(j - 3 + i, fx, fy);
+            r0row(j - 3 + i, ux_[i], uy_[i], ux_[i + 1], uy_[i + 1], ux_[i + 2], uy_[i + 2], ue_[i + 1], fx, fy, rx_[i],
+                  ry_[i]);
+        }
+        a0x = rx_[0]; a0y = ry_[0];
+        a1x = rx_[1]; a1y = ry_[1];
+        a2x = rx_[2]; a2y = ry_[2];
+        sx = rx_[3]; sy_ = ry_[3];
+        nx = rx_[4]; ny = ry_[4];
+        xx = rx_[5]; xy = ry_[5];
+        w0x = ux_[3]; w0y = uy_[3];
+        w1x = ux_[4]; w1y = uy_[4];
+        w2x = ux_[5]; w2y = uy_[5];
+        w3x = ux_[6]; w3y = uy_[6];
+        w4x = ux_[7]; w4y = uy_[7];
+        eS = (j & 1) ? ue_[6] : ue_[7];
+    } else {
+        ldR(j - 3, a0x, a0y);
+        ldR(j - 2, a1x, a1y);
+        ldR(j - 1, a2x, a2y);
+        ldR(j, sx, sy_);
+        ldR(j + 1, nx, ny);
+        ldR(j + 2, xx, xy);
+    }
     T dm, d0, vlo, Fn = T(0);
     if (j & 1) {
         const T Fj = fsr(j, rs1(j, a2x, a2y, sx, sy_, nx, ny));
@@ -505,8 +602,26 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
     // residual pairs of rows jj+2 (a) and jj+3 (b) and v2 row (jj+3)/2; u of
     // row jj.  Entering row jj, (sx, sy_) holds the pair of row jj, (nx, ny)
     // that of row jj+1 and, at even jj, (xx, xy) that of row jj+2.
-    struct Ck { T ax, ay, bx, by, vhi; double ux, uy; };
+    // PP, at odd jj: u of rows jj+3 (u3) and jj+4 (u4) with their outer
+    // columns, f of rows jj+2 and jj+3, instead of the residual pairs
+    struct Ck {
+        T ax, ay, bx, by, vhi;
+        double ux, uy;
+        double u3x, u3y, u4x, u4y, e3, e4, f2x, f2y, f3x, f3y;
+    };
     auto load = [&](int jj, Ck& c) {
+        if constexpr (PP) {
+            c.ax = c.ay = c.bx = c.by = c.vhi = 0;
+            c.ux = c.uy = 0;
+            c.u3x = c.u3y = c.u4x = c.u4y = c.e3 = c.e4 = c.f2x = c.f2y = c.f3x = c.f3y = 0;
+            if (jj > y1 || !(jj & 1)) return;
+            ldU(jj + 3, c.u3x, c.u3y, c.e3);
+            ldU(jj + 4, c.u4x, c.u4y, c.e4);
+            ldF(jj + 2, c.f2x, c.f2y);
+            ldF(jj + 3, c.f3x, c.f3y);
+            c.vhi = ld2((jj + 3) >> 1);
+            return;
+        }
         c.ax = c.ay = c.bx = c.by = c.vhi = 0;
         c.ux = c.uy = 0;
         if (jj > y1) return;
@@ -525,10 +640,17 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
     double uxm1 = 0, uym1 = 0;
     auto proc = [&](int jj, const Ck& c) {
         if (jj > y1) return;
+        T cax = c.ax, cay = c.ay, cbx = c.bx, cby = c.by;   // residual pairs of rows jj+2, jj+3 (odd jj)
+        if constexpr (PP) {
+            if (jj & 1) {
+                r0row(jj + 2, w2x, w2y, w3x, w3y, c.u3x, c.u3y, eS, c.f2x, c.f2y, cax, cay);
+                r0row(jj + 3, w3x, w3y, c.u3x, c.u3y, c.u4x, c.u4y, c.e3, c.f3x, c.f3y, cbx, cby);
+            }
+        }
         T dp;
         if (jj & 1) {   // row jj+1 even: its C points from F rows jj (= d0) and jj+2
-            const T r1c = rs1(jj + 1, sx, sy_, nx, ny, c.ax, c.ay);
-            const T r1f = rs1(jj + 2, nx, ny, c.ax, c.ay, c.bx, c.by);
+            const T r1c = rs1(jj + 1, sx, sy_, nx, ny, cax, cay);
+            const T r1f = rs1(jj + 2, nx, ny, cax, cay, cbx, cby);
             const T F2 = f21(jj + 2, r1f, vlo, c.vhi);
             dp = c21(jj + 1, r1c, d0, F2);
             Fn = F2;
@@ -555,11 +677,12 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
             const T vx = qq ? Fm1 : C;   // column 2t
             const T vy = qq ? C : Fm1;   // column 2t+1
             const size_t o = (size_t)R(jj - 1) * w + 2 * t;
+            const double ox = PP ? w0x : uxm1, oy = PP ? w0y : uym1;   // the iterate at row jj-1
             if (useful) {
                 if constexpr (FINEST) {
-                    if (c0 && c1) *reinterpret_cast<P2<double>*>(u + o) = P2<double>{uxm1 + (double)vx, uym1 + (double)vy};
-                    else if (c1) u[o + 1] = uym1 + (double)vy;
-                    else if (c0) u[o] = uxm1 + (double)vx;
+                    if (c0 && c1) *reinterpret_cast<P2<double>*>(u + o) = P2<double>{ox + (double)vx, oy + (double)vy};
+                    else if (c1) u[o + 1] = oy + (double)vy;
+                    else if (c0) u[o] = ox + (double)vx;
                 } else {
                     if (c0 && c1) *reinterpret_cast<P2<T>*>(vA + o) = P2<T>{vx, vy};
                     else if (c1) vA[o + 1] = vy;
@@ -578,13 +701,25 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
         sx = nx;
         sy_ = ny;
         if (jj & 1) {
-            nx = c.ax;
-            ny = c.ay;
-            xx = c.bx;
-            xy = c.by;
+            nx = cax;
+            ny = cay;
+            xx = cbx;
+            xy = cby;
         } else {
             nx = xx;
             ny = xy;
+        }
+        if constexpr (PP) {   // and the iterate's rows
+            w0x = w1x; w0y = w1y;
+            w1x = w2x; w1y = w2y;
+            w2x = w3x; w2y = w3y;
+            if (jj & 1) {
+                w3x = c.u3x; w3y = c.u3y;
+                w4x = c.u4x; w4y = c.u4y;
+                eS = c.e4;
+            } else {
+                w3x = w4x; w3y = w4y;
+            }
         }
     };
     rows_march<1, Ck>(j, y1, load, proc);
@@ -600,6 +735,27 @@ __global__ void __launch_bounds__(kRowBlock) kb_finest_fused(int m, T cc, T cd, 
     if (wv >= nwaves) return;
     if ((wv / nwx) & 1) fused_body<T, true, NT, true>(m, cc, cd, it.r0, it.v2, nullptr, it.u, wv, nwx, rows);
     else fused_body<T, true, NT, false>(m, cc, cd, it.r0, it.v2, nullptr, it.u, wv, nwx, rows);
+}
+
+// Out-of-place solve step (one FP64 problem): cycle k (the control block's
+// count when the cycle runs) reads the iterate of cycle k-1 and writes that of
+// cycle k; even k live in u, odd k in ub.
+template <bool NT>
+__global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(4))) kb_finest_oop(int m, double cc, double cd,
+                                                           const Fin2<double>* __restrict__ items, int nwx,
+                                                           int nwaves, int rows, const Ctl* __restrict__ ctls)
+{
+    const Fin2<double> it = items[blockIdx.y];
+    ITEM_GATE(ctls, it.prob);
+    const int wv = rows_wave_id(nwaves);
+    if (wv >= nwaves) return;
+    const bool odd = ctls[it.prob].k & 1;
+    const double* uc = odd ? it.u : it.ub;
+    double* un = odd ? it.ub : it.u;
+    if ((wv / nwx) & 1)
+        fused_body<double, true, NT, true, true>(m, cc, cd, nullptr, it.v2, nullptr, un, wv, nwx, rows, uc, it.f);
+    else
+        fused_body<double, true, NT, false, true>(m, cc, cd, nullptr, it.v2, nullptr, un, wv, nwx, rows, uc, it.f);
 }
 
 // The Jacobi of an axis level L (side m, coefficient cc) with that of the
@@ -1738,6 +1894,22 @@ static void launch_timed(K kern, dim3 g, dim3 b, hipStream_t s, Args... args)
     }
 }
 
+__global__ void kb_copy_ring(int n, const double* __restrict__ src, double* __restrict__ dst)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    const size_t w = (size_t)n + 1;
+    dst[i] = src ? src[i] : 0.0;                                     // row 0
+    dst[(size_t)n * w + i] = src ? src[(size_t)n * w + i] : 0.0;     // row n
+    dst[(size_t)i * w] = src ? src[(size_t)i * w] : 0.0;             // column 0
+    dst[(size_t)i * w + n] = src ? src[(size_t)i * w + n] : 0.0;     // column n
+}
+
+void launch_b_copy_ring(int n, const double* src, double* dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_copy_ring, dim3((n + 1 + 255) / 256), dim3(256), 0, s, n, src, dst);
+}
+
 void launch_b_rhs4(int n, const double* f, double* g, hipStream_t s)
 {
     hipLaunchKernelGGL(kb_rhs4, dim3((n - 1 + 255) / 256, n - 1), dim3(256), 0, s, n, f, g);
@@ -1745,7 +1917,7 @@ void launch_b_rhs4(int n, const double* f, double* g, hipStream_t s)
 
 template <typename T>
 void launch_b_resid(int n, int fused, int order, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s,
-                    int withf)
+                    int withf, int oop)
 {
     const bool m4 = order == 4;
     double inv_h2 = m4 ? (double)n * (double)n / 6 : (double)n * (double)n;
@@ -1757,7 +1929,10 @@ void launch_b_resid(int n, int fused, int order, const Fin2<T>* items, int nitem
     // rows is a power of two >= 4: every strip starts on an odd row
     int rows = pick_rows(n / 2 + 1, kResidPairs, n - 1, kTargetWavesResid);
     rows_grid(n / 2 + 1, kResidPairs, n - 1, rows, nwx, nw, nb);
-    auto go = [&](auto kern) { launch_timed(kern, dim3(nb, nitems), dim3(kRowBlock), s, n, inv_h2, items, nwx, nw, rows, ctls); };
+    const int pp = oop && fused && n >= 8 && !m4 && sizeof(T) == 8 ? 1 : 0;
+    auto go = [&](auto kern) {
+        launch_timed(kern, dim3(nb, nitems), dim3(kRowBlock), s, n, inv_h2, items, nwx, nw, rows, ctls, pp);
+    };
     const bool nt = nt_hint(n);
     auto pick = [&](auto M, auto F) {
         constexpr bool M4 = decltype(M)::value != 0, WF = decltype(F)::value != 0;
@@ -1780,13 +1955,27 @@ void launch_b_sumsq(int n, const Fin2<T>* items, int nitems, const Ctl* ctls, hi
 }
 
 template <typename T>
-void launch_b_finest(int n, T c, T c1, int fused, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s)
+void launch_b_finest(int n, T c, T c1, int fused, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s,
+                     int oop)
 {
     if (n < 8) {
         launch_timed(kb_finest_small<T>, dim3(1, nitems), dim3(kRowBlock), s, n, c, items, ctls);
         return;
     }
     int nwx, nw, nb;
+    if constexpr (sizeof(T) == 8) {
+        if (fused && oop && nitems == 1) {
+            auto go = [&](auto kern) {
+                const int rows = fill_rows((const void*)kern, n / 2 + 1, kFusePairs, n - 1);
+                rows_grid(n / 2 + 1, kFusePairs, n - 1, rows, nwx, nw, nb);
+                launch_timed(kern, dim3(nb, 1), dim3(kRowBlock), s, n, (double)c, (double)c1,
+                             reinterpret_cast<const Fin2<double>*>(items), nwx, nw, rows, ctls);
+            };
+            if (nt_hint(n)) go(kb_finest_oop<true>);
+            else go(kb_finest_oop<false>);
+            return;
+        }
+    }
     if (fused) {
         auto go = [&](auto kern) {
             const int rows = nitems == 1 ? fill_rows((const void*)kern, n / 2 + 1, kFusePairs, n - 1)
@@ -1922,9 +2111,9 @@ void launch_b_coarse_net(const LevInfo<T>* lev, const Coarse2B<T>* items, int ni
 }
 
 #define DMG_INSTB(T)                                                                                            \
-    template void launch_b_resid<T>(int, int, int, const Fin2<T>*, int, const Ctl*, hipStream_t, int);                   \
+    template void launch_b_resid<T>(int, int, int, const Fin2<T>*, int, const Ctl*, hipStream_t, int, int);                   \
     template void launch_b_sumsq<T>(int, const Fin2<T>*, int, const Ctl*, hipStream_t);                        \
-    template void launch_b_finest<T>(int, T, T, int, const Fin2<T>*, int, const Ctl*, hipStream_t);          \
+    template void launch_b_finest<T>(int, T, T, int, const Fin2<T>*, int, const Ctl*, hipStream_t, int);          \
     template void launch_b_restrict<T>(int, int, int, const Item2<T>*, int, const Ctl*, hipStream_t);          \
     template void launch_b_jac_pair<T>(int, T, T, const JPair2<T>*, int, const Ctl*, hipStream_t);              \
     template void launch_b_rs_pair<T>(int, const RsPair2<T>*, int, const Ctl*, hipStream_t);                    \

@@ -52,6 +52,7 @@ struct Fin2 {
     T* r2;         // residual of that level (written by the residual kernel when fused)
     double* part;  // norm partial sums of this problem
     double* partf; // partial sums of f^2 (first evaluation of a solve, made by the residual kernel)
+    double* ub;    // out-of-place solves: the second iterate buffer ((n+1)^2 doubles), else null
     int prob;
     int pad;
 };
@@ -75,17 +76,26 @@ struct LevInfo {
 };
 
 // fused = 1: the kernel also restricts r1 onto the axis level below it (r2)
-template <typename T>
 // withf: also the partial sums of f^2 (into partf), for finalize kind 2
+// oop (fused FP64 single problems with ub set): out-of-place solve step: the
+// residual of the iterate of evaluation k (the control block's count: u for
+// even k, ub for odd k) is formed, restricted and summed but not stored
+template <typename T>
 void launch_b_resid(int n, int fused, int order, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s,
-                    int withf = 0);
+                    int withf = 0, int oop = 0);
 // order 4: f of the items is the right-hand side combination made by launch_b_rhs4
 void launch_b_rhs4(int n, const double* f, double* g, hipStream_t s);
 int b_resid_parts(int n);
 // fused = 1: the kernel also runs the Jacobi of the first diagonal level
 // (coefficient c1) from r1 and v2 instead of reading v1
+// oop (fused, FP64, one item with ub set): the kernel of cycle k forms the
+// finest residual from the iterate of cycle k-1 and f itself and writes the
+// new iterate into the other buffer (cycle k writes u for even k, ub for odd k)
 template <typename T>
-void launch_b_finest(int n, T c, T c1, int fused, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s);
+void launch_b_finest(int n, T c, T c1, int fused, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s,
+                     int oop = 0);
+// the boundary entries of an (n+1)^2 array: dst <- src (src null: zeros)
+void launch_b_copy_ring(int n, const double* src, double* dst, hipStream_t s);
 // does a problem with finest level D run the first diagonal level's Jacobi in
 // the finest kernel, and the restriction into the level below it (D-2) in
 // the residual kernel (when both levels are above the coarse kernel's top lamc)

@@ -51,7 +51,7 @@ bool rs_one(const Plan2& P, int lam, int D, int top)
 
 }  // namespace
 
-int plan2_layout(Plan2& P, int nprob, const int* n, int prec, double p)
+int plan2_layout(Plan2& P, int nprob, const int* n, int prec, double p, bool allow_oop)
 {
     if (nprob < 1 || !n) return MG_ERR_ARG;
     P.rorder = (prec & MG_ORDER4) ? 4 : 2;
@@ -72,6 +72,8 @@ int plan2_layout(Plan2& P, int nprob, const int* n, int prec, double p)
     }
     P.lamc = 0;
     while (side_of(P.lamc + 1) <= kCoarseSide2) P.lamc++;
+    P.oop = allow_oop && nprob == 1 && prec == MG_FP64 && P.rorder == 2 && n[0] >= 8 && fin_fused(P.D[0], P.lamc);
+    P.r0_stale = false;
     size_t es = prec == MG_FP64 ? 8 : 4;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -207,6 +209,7 @@ Fin2<T> fin_item(Plan2& P, int i)
     x.r2 = fin_fused(P.D[i], P.lamc) ? at<T>(P, P.off_r[i][P.D[i] - 2]) : nullptr;
     x.part = at<double>(P, P.off_part[i]);
     x.partf = at<double>(P, P.off_partf[i]);
+    x.ub = P.oop ? at<double>(P, P.off_r0[i]) : nullptr;
     x.prob = i;
     return x;
 }
@@ -294,20 +297,22 @@ void enq_norm_f(Plan2& P, Ctl* ctls, int* nact, bool small_only = false)
 // fused (n >= 8): the restriction onto the axis level below the first
 // diagonal level ((n/2 - 1)^2 interior points) is written instead of the
 // diagonal level itself (which the finest Jacobi restricts again)
-double bytes_resid(int n, size_t es, bool fused)
+// oop: the finest residual is not stored
+double bytes_resid(int n, size_t es, bool fused, bool oop = false)
 {
     double inter = (double)(n - 1) * (n - 1), M = n / 2;
     const bool fz = fused && n >= 8;
-    return 8 * (double)sizeA(n) + 8 * inter + es * inter + (n >= 4 && !fz ? es * (M * M + (M - 1) * (M - 1)) : 0) +
-           (fz ? es * (M - 1) * (M - 1) : 0);
+    return 8 * (double)sizeA(n) + 8 * inter + (oop ? 0 : es * inter) +
+           (n >= 4 && !fz ? es * (M * M + (M - 1) * (M - 1)) : 0) + (fz ? es * (M - 1) * (M - 1) : 0);
 }
 // fused: the correction of the level below the first diagonal level (a
 // quarter of the points) replaces the read of the diagonal level's correction
-double bytes_finest(int n, size_t es, bool fused)
+// oop: f (8 bytes) is read instead of the stored residual
+double bytes_finest(int n, size_t es, bool fused, bool oop = false)
 {
     double inter = (double)(n - 1) * (n - 1), M = n / 2;
     double lev = fused ? (M + 1) * (M + 1) : (double)sizeD(n);
-    return es * (inter + lev) + 16 * inter;
+    return (oop ? 8 : es) * inter + es * lev + 16 * inter;
 }
 double bytes_rs(int diag_in, int m, size_t es)
 {
@@ -325,8 +330,9 @@ double bytes_jac(int diag, int m, size_t es)
 // withf: the first evaluation of a solve: the residual kernel of every size
 // class with n >= 4 also sums f^2, so that the norm of f needs no pass of its
 // own (the others have theirs from enq_norm_f(small_only))
+// oop: the out-of-place solve step (P.oop)
 template <typename T>
-void enq_resid(Plan2& P, Ctl* ctls, int* nact, bool withf_all = false)
+void enq_resid(Plan2& P, Ctl* ctls, int* nact, bool withf_all = false, bool oop = false)
 {
     size_t es = sizeof(T);
     for (size_t c = 0; c < P.cls_n.size(); c++) {
@@ -334,9 +340,9 @@ void enq_resid(Plan2& P, Ctl* ctls, int* nact, bool withf_all = false)
         {
             const int n = P.cls_n[c];
             const bool fz = fin_fused(2 * (ilog2(n) - 1), P.lamc);
-            Timed t(&P.tm, MG_K_RESIDUAL, bytes_resid(n, es, fz) * P.cls_count[c], true);
+            Timed t(&P.tm, MG_K_RESIDUAL, bytes_resid(n, es, fz, oop) * P.cls_count[c], true);
             launch_b_resid<T>(n, fz ? 1 : 0, P.rorder, fin_items<T>(P, (int)c), P.cls_count[c], ctls, P.stream,
-                              withf ? 1 : 0);
+                              withf ? 1 : 0, oop ? 1 : 0);
         }
         Timed t(&P.tm, MG_K_NORM, 8.0 * P.nparts[c] * P.cls_count[c] * (withf ? 2 : 1));
         launch_b_finalize<T>(withf ? 2 : 1, fin_items<T>(P, (int)c), P.cls_count[c], P.nparts[c], ctls, nact,
@@ -359,7 +365,7 @@ bool use_mid(const Plan2& P)
 }
 
 template <typename T>
-void enq_cycle(Plan2& P, Ctl* ctls)
+void enq_cycle(Plan2& P, Ctl* ctls, bool oop = false)
 {
     size_t es = sizeof(T);
     const bool mid = use_mid(P);
@@ -445,19 +451,19 @@ void enq_cycle(Plan2& P, Ctl* ctls)
         int n = P.cls_n[c];
         const int D = 2 * (ilog2(n) - 1);
         const bool fz = fin_fused(D, P.lamc);
-        Timed t(&P.tm, MG_K_FINEST, bytes_finest(n, es, fz) * P.cls_count[c], true);
+        Timed t(&P.tm, MG_K_FINEST, bytes_finest(n, es, fz, oop) * P.cls_count[c], true);
         double sh = 1.0 / n;
         launch_b_finest<T>(n, (T)(P.p * sh * sh), (T)(fz ? coef(P, D - 1) : 0.0), fz ? 1 : 0, fin_items<T>(P, (int)c),
-                           P.cls_count[c], ctls, P.stream);
+                           P.cls_count[c], ctls, P.stream, oop ? 1 : 0);
     }
 }
 
-// one outer iteration: cycle, the next residual, the stopping decision
+// one outer iteration of a solve: cycle, the next residual, the stopping decision
 void enq_iteration(Plan2& P)
 {
     Ctl* ctls = at<Ctl>(P, P.off_ctl);
     int* nact = at<int>(P, P.off_nactive);
-    if (P.prec == MG_FP64) { enq_cycle<double>(P, ctls); enq_resid<double>(P, ctls, nact); }
+    if (P.prec == MG_FP64) { enq_cycle<double>(P, ctls, P.oop); enq_resid<double>(P, ctls, nact, false, P.oop); }
     else { enq_cycle<float>(P, ctls); enq_resid<float>(P, ctls, nact); }
 }
 
@@ -616,6 +622,7 @@ int plan2_vcycle(Plan2& P, double* const* u, const double* const* f, double* rel
     int* nact = at<int>(P, P.off_nactive);
     int e = bind_uf(P, u, f);
     if (e) return e;
+    P.r0_stale = false;   // the cycle stores the finest residual
     if (P.rorder == 4) launch_b_rhs4(P.n[0], f[0], at<double>(P, P.off_g), P.stream);
     launch_b_ctl_reset(ctls, P.nprob, 0, 0, 0.0, nact, P.has_net ? 1 : 0, P.stream);
     const bool wf = relres != nullptr;
@@ -656,9 +663,13 @@ int plan2_solve(Plan2& P, double* const* u, const double* const* f, double rtol,
     if (e) return e;
     if (P.rorder == 4) launch_b_rhs4(P.n[0], f[0], at<double>(P, P.off_g), P.stream);
     launch_b_ctl_reset(ctls, P.nprob, 1, max_cycles, rtol, nact, P.has_net ? 1 : 0, P.stream);
+    if (P.oop) {   // the second iterate buffer takes u's boundary values
+        launch_b_copy_ring(P.n[0], u[0], at<double>(P, P.off_r0[0]), P.stream);
+        P.r0_stale = true;
+    }
     if (P.prec == MG_FP64) {
         enq_norm_f<double>(P, ctls, nact, true);
-        enq_resid<double>(P, ctls, nact, true);
+        enq_resid<double>(P, ctls, nact, true, P.oop);
     } else {
         enq_norm_f<float>(P, ctls, nact, true);
         enq_resid<float>(P, ctls, nact, true);
@@ -694,15 +705,26 @@ int plan2_solve(Plan2& P, double* const* u, const double* const* f, double rtol,
     if (history0 && hipMemcpyAsync(P.hctl, ctls, sizeof(Ctl), hipMemcpyDeviceToHost, P.stream) != hipSuccess)
         return MG_ERR_HIP;
     if (hipStreamSynchronize(P.stream) != hipSuccess) return MG_ERR_HIP;
-    int worst = MG_OK;
+    int worst = MG_OK, cy0 = 0;
     for (int i = 0; i < P.nprob; i++) {
         const Ctl* c = reinterpret_cast<const Ctl*>(P.hres + kCtlHead * (size_t)i);
         int st = c->done ? c->status : MG_ERR_NOT_CONVERGED;
         int cy = c->done ? c->cycles : max_cycles;
+        if (i == 0) cy0 = cy;
         if (cycles) cycles[i] = cy;
         if (relres) relres[i] = c->last;
         if (status) status[i] = st;
         if (st != MG_OK && (worst == MG_OK || st < worst)) worst = st;
+    }
+    // out of place: cycle k left its iterate in ub for odd k; the array's
+    // boundary then reads 0 again, as the cycles of mg_vcycle expect
+    if (P.oop) {
+        double* ub = at<double>(P, P.off_r0[0]);
+        if ((cy0 & 1) && hipMemcpyAsync(u[0], ub, sizeof(double) * sizeA(P.n[0]), hipMemcpyDeviceToDevice,
+                                        P.stream) != hipSuccess)
+            return MG_ERR_HIP;
+        launch_b_copy_ring(P.n[0], nullptr, ub, P.stream);
+        if (hipStreamSynchronize(P.stream) != hipSuccess) return MG_ERR_HIP;
     }
     if (history0) {
         const Ctl& H = *P.hctl;
@@ -738,6 +760,10 @@ int plan2_level_get(Plan2& P, int depth, int which, double* dst)
     int lam = D - depth;
     int m = side_of(lam);
     int diag = lam & 1;
+    // after an out-of-place solve the finest residual's array holds an
+    // iterate: the finest residual and the first diagonal level (made from it)
+    // are not available until the next mg_vcycle
+    if (P.r0_stale && depth <= 1) return MG_ERR_ARG;
     size_t off = (which == 0) ? (depth == 0 ? P.off_r0[0] : P.off_r[0][lam]) : P.off_v[0][lam];
     if ((lam & 1) && ((lam == D - 1 && fin_fused(D, P.lamc) && side_of(D) >= 8) || pair_level(lam + 1, D, P.pairs))) {
         // the cycle restricted and relaxed this diagonal level inside the

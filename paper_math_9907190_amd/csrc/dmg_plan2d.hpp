@@ -18,6 +18,10 @@ struct Plan2 {
     // workspace offsets
     size_t off_ctl = 0, off_nactive = 0, off_zero = 0, off_fin = 0, off_coarse = 0, off_net = 0, off_lg_item = 0, total = 0;
     bool has_net = false;     // learned coarse correction set (packed bf16 weights at off_net)
+    // single FP64 second-order problem with the fused finest kernels: solves
+    // update u out of place, alternating between u and the finest residual's
+    // array (which they then do not store); r0_stale: it holds an iterate
+    bool oop = false, r0_stale = false;
     std::vector<size_t> off_r0, off_part, off_partf;
     std::vector<std::vector<size_t>> off_r, off_v;   // [problem][aligned level]
     std::vector<size_t> off_rs_items, off_jac_items; // [aligned level]
@@ -52,7 +56,8 @@ struct Plan2 {
     size_t stage_lo = 0;                // lowest offset written into stage
 };
 
-int plan2_layout(Plan2& P, int nprob, const int* n, int prec, double p);
+// allow_oop = false: no out-of-place solves (plans that only run cycles)
+int plan2_layout(Plan2& P, int nprob, const int* n, int prec, double p, bool allow_oop = true);
 int plan2_setup(Plan2& P, void* ws, size_t ws_bytes, hipStream_t stream);
 void plan2_destroy(Plan2& P);
 // Single problem: bind the laid-out plan to workspace ws (P.total bytes,

@@ -56,7 +56,7 @@ extern "C" int mg_vcycle_static(int dim, int n, int precision, const double* p, 
     void* ws = nullptr;
     if (dim == 2) {
         Plan2 P;
-        int e = plan2_layout(P, 1, &n, precision, p[0]);
+        int e = plan2_layout(P, 1, &n, precision, p[0], false);
         if (e) return e;
         if (P.total > kScratchBytes) return MG_ERR_SCRATCH;
         if (hipGetDevice(&dev) != hipSuccess) return MG_ERR_HIP;

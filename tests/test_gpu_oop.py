@@ -1,0 +1,79 @@
+"""Out-of-place 2D solves (a single FP64 second-order problem with the fused
+finest kernels): the cycles alternate the iterate between u and a second
+buffer and form the finest residual inside the finest kernel instead of
+storing it.
+
+* u after 1 .. 5 cycles (odd counts end in the second buffer and are copied
+  back) is bitwise equal to the in-place path's (a batch of two copies of the
+  problem: per-level launches, residual stored), with the same relative
+  residuals, for grids whose strips and bands leave ragged edges;
+* nonzero Dirichlet values in u's boundary are used and left untouched;
+* after such a solve the finest residual is not available from
+  mg_level_get until the next mg_vcycle.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_math_9907190_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dmg():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_math_9907190_amd import dmg as D
+    return D
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def start(n, seed):
+    """f and a start u with random interior and boundary values."""
+    rng = np.random.default_rng(seed)
+    f = W.batch_problem(n, 0, base_seed=seed)
+    u = rng.uniform(-1, 1, (n + 1, n + 1))
+    return u, f
+
+
+@pytest.mark.parametrize("n", [256, 512, 1024])
+def test_out_of_place_equals_in_place_bitwise(dmg, n):
+    u0, f = start(n, 60 + n)
+    fd = dev(f)
+    S = dmg.Solver(2, n, p=(1.052,))
+    B = dmg.BatchSolver([n, n], precision=dmg.MG_FP64)
+    for k in range(1, 6):
+        print("out of place n=%d cycles=%d" % (n, k), flush=True)
+        u1 = dev(u0)
+        st1, c1, r1, h1 = S.solve(u1, fd, rtol=0.0, max_cycles=k)
+        ub = [dev(u0), dev(u0)]
+        st2, c2, r2, s2 = B.solve(ub, [fd, fd], rtol=0.0, max_cycles=k)
+        assert st1 == dmg.MG_ERR_NOT_CONVERGED and c1 == k and c2 == [k, k]
+        assert r1 == r2[0] == r2[1]
+        assert torch.equal(u1, ub[0]) and torch.equal(u1, ub[1]), k
+        b = u1.cpu().numpy()
+        assert np.array_equal(b[0], u0[0]) and np.array_equal(b[-1], u0[-1])
+        assert np.array_equal(b[:, 0], u0[:, 0]) and np.array_equal(b[:, -1], u0[:, -1])
+    S.close()
+
+
+def test_finest_residual_after_an_out_of_place_solve(dmg):
+    n = 256
+    u0, f = start(n, 7)
+    S = dmg.Solver(2, n, p=(1.052,))
+    u = dev(u0)
+    S.vcycle(u, dev(f))
+    r_before = S.level(0, 0)
+    S.solve(dev(u0), dev(f), rtol=1e-10, max_cycles=40)
+    for depth, which in ((0, 0), (1, 0), (1, 1)):
+        with pytest.raises(dmg.MGError) as ei:
+            S.level(depth, which)
+        assert ei.value.code == dmg.MG_ERR_ARG
+    S.level(2, 0)   # the other levels stay readable
+    u = dev(u0)
+    S.vcycle(u, dev(f))
+    assert torch.equal(S.level(0, 0), r_before)
+    S.close()
