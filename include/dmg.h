@@ -125,7 +125,10 @@ int mg_vcycle(mg_plan *plan, double *u, const double *f, double *rel_res_before)
  * nullable, max_cycles+1 doubles): relative residual after 0, 1, ...
  * cycles.  Returns MG_OK, MG_ERR_NOT_CONVERGED, MG_ERR_NONFINITE or
  * MG_ERR_DIVERGED (the last three still fill the outputs).  Synchronises
- * the stream. */
+ * the stream.  A 2D FP64 second-order plan of n >= 128 (mg_setup) runs the
+ * cycles out of place: the iterates alternate between u and a workspace
+ * array, u holds the result when the call returns, and u's boundary values
+ * are read, never written. */
 int mg_solve(mg_plan *plan, double *u, const double *f, double rtol, int max_cycles,
              int *cycles_out, double *rel_res_out, double *history);
 
@@ -174,7 +177,9 @@ int mg_setup_cycle(mg_plan **out, int dim, int n, int precision, const double *p
  * also the odd depths whose aligned level is >= 15).  which = 1 recomputes
  * such a level (same arithmetic, same values) from its residual and the
  * next coarser correction, so it is the last cycle's only right after
- * mg_vcycle (mg_solve ends with a fresh residual).  For parity tests. */
+ * mg_vcycle (mg_solve ends with a fresh residual).  After an out-of-place
+ * mg_solve (see there) the finest residual is not stored: depths 0 and 1
+ * return MG_ERR_ARG until the next mg_vcycle.  For parity tests. */
 int mg_level_get(mg_plan *plan, int depth, int which, double *dst);
 
 /* Number of levels D+1 and the side m of level `depth` (host-only). */
