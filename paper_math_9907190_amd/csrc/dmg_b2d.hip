@@ -740,7 +740,6 @@ __global__ void __launch_bounds__(kRowBlock) kb_finest_fused(int m, T cc, T cd, 
 // Out-of-place solve step (one FP64 problem): cycle k (the control block's
 // count when the cycle runs) reads the iterate of cycle k-1 and writes that of
 // cycle k; even k live in u, odd k in ub.
-template <bool NT>
 __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(4))) kb_finest_oop(int m, double cc, double cd,
                                                            const Fin2<double>* __restrict__ items, int nwx,
                                                            int nwaves, int rows, const Ctl* __restrict__ ctls)
@@ -753,9 +752,9 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
     const double* uc = odd ? it.u : it.ub;
     double* un = odd ? it.ub : it.u;
     if ((wv / nwx) & 1)
-        fused_body<double, true, NT, true, true>(m, cc, cd, nullptr, it.v2, nullptr, un, wv, nwx, rows, uc, it.f);
+        fused_body<double, true, false, true, true>(m, cc, cd, nullptr, it.v2, nullptr, un, wv, nwx, rows, uc, it.f);
     else
-        fused_body<double, true, NT, false, true>(m, cc, cd, nullptr, it.v2, nullptr, un, wv, nwx, rows, uc, it.f);
+        fused_body<double, true, false, false, true>(m, cc, cd, nullptr, it.v2, nullptr, un, wv, nwx, rows, uc, it.f);
 }
 
 // The Jacobi of an axis level L (side m, coefficient cc) with that of the
@@ -1644,11 +1643,13 @@ __global__ void __launch_bounds__(kCoarseThreadsB) kb_coarse_net(CoarseLev<T> L,
 // problem sums its partials in a fixed order.  kind 0: ||f|| into fnorm;
 // kind 1: relative residual of evaluation ctl.k, then stop when it is <= rtol,
 // not finite, grew three times in a row above the start, or after
-// max_cycles cycles.  A problem that stops decrements *nactive.
+// max_cycles cycles.  A problem that stops decrements *nactive.  host (a
+// single problem's solve): a pinned host copy of the control block that
+// receives the decision, the relative residual and its history entry.
 template <typename T>
 __global__ void __launch_bounds__(256) kb_finalize(int kind, const Fin2<T>* __restrict__ items, int nparts,
                                                    Ctl* __restrict__ ctls, int* __restrict__ nactive,
-                                                   int* __restrict__ host_active)
+                                                   Ctl* __restrict__ host)
 {
     const Fin2<T> it = items[blockIdx.x];
     Ctl* c = &ctls[it.prob];
@@ -1708,9 +1709,15 @@ __global__ void __launch_bounds__(256) kb_finalize(int kind, const Fin2<T>* __re
         c->cycles = k;
         atomicSub(nactive, 1);
     }
-    // a single problem's state straight into the host's pinned word (the
-    // host reads it after an event that follows this kernel)
-    if (host_active) *host_active = c->done ? 0 : 1;
+    // a single problem's state straight into host memory (read by the host
+    // after an event or a synchronisation that follows this kernel)
+    if (host) {
+        if (k <= kMaxCycles) host->hist[k] = rr;
+        host->last = rr;
+        host->status = c->status;
+        host->cycles = c->cycles;
+        host->done = c->done;
+    }
 }
 
 __global__ void kb_ctl_reset(Ctl* ctls, int nprob, int mode, int max_cycles, double rtol, int* nactive, int net)
@@ -1738,10 +1745,10 @@ __global__ void kb_ctl_reset(Ctl* ctls, int nprob, int mode, int max_cycles, dou
 
 template <typename T>
 void launch_b_finalize(int kind, const Fin2<T>* items, int nitems, int nparts, Ctl* ctls, int* nactive, hipStream_t s,
-                       int* host_active)
+                       Ctl* host)
 {
     hipLaunchKernelGGL(kb_finalize<T>, dim3(nitems), dim3(256), 0, s, kind, items, nparts, ctls, nactive,
-                       nitems == 1 ? host_active : nullptr);
+                       nitems == 1 ? host : nullptr);
 }
 
 void launch_b_ctl_reset(Ctl* ctls, int nprob, int mode, int max_cycles, double rtol, int* nactive, int net,
@@ -1910,6 +1917,27 @@ void launch_b_copy_ring(int n, const double* src, double* dst, hipStream_t s)
     hipLaunchKernelGGL(kb_copy_ring, dim3((n + 1 + 255) / 256), dim3(256), 0, s, n, src, dst);
 }
 
+// End of an out-of-place solve: the interior of the last iterate into u when
+// it is in ub (odd cycle count), and ub's boundary back to zero.
+__global__ void kb_oop_finish(int n, const Ctl* __restrict__ ctl, double* __restrict__ ub, double* __restrict__ u)
+{
+    const size_t w = (size_t)n + 1;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x) {
+        ub[i] = 0.0;
+        ub[(size_t)n * w + i] = 0.0;
+        ub[(size_t)i * w] = 0.0;
+        ub[(size_t)i * w + n] = 0.0;
+    }
+    if (!(ctl->cycles & 1)) return;
+    for (int b = blockIdx.x + 1; b < n; b += gridDim.x)
+        for (int a = threadIdx.x + 1; a < n; a += blockDim.x) u[(size_t)b * w + a] = ub[(size_t)b * w + a];
+}
+
+void launch_b_oop_finish(int n, const Ctl* ctl, double* ub, double* u, hipStream_t s)
+{
+    hipLaunchKernelGGL(kb_oop_finish, dim3(n - 1 < 2048 ? n - 1 : 2048), dim3(256), 0, s, n, ctl, ub, u);
+}
+
 void launch_b_rhs4(int n, const double* f, double* g, hipStream_t s)
 {
     hipLaunchKernelGGL(kb_rhs4, dim3((n - 1 + 255) / 256, n - 1), dim3(256), 0, s, n, f, g);
@@ -1971,8 +1999,10 @@ void launch_b_finest(int n, T c, T c1, int fused, const Fin2<T>* items, int nite
                 launch_timed(kern, dim3(nb, 1), dim3(kRowBlock), s, n, (double)c, (double)c1,
                              reinterpret_cast<const Fin2<double>*>(items), nwx, nw, rows, ctls);
             };
-            if (nt_hint(n)) go(kb_finest_oop<true>);
-            else go(kb_finest_oop<false>);
+            // plain loads: the iterate and f rows a strip shares with its
+            // neighbour are then still in L2 when the neighbour reads them
+            // (non-temporal ones measured 485.7 against 467.4 MB per launch)
+            go(kb_finest_oop);
             return;
         }
     }
@@ -2120,7 +2150,7 @@ void launch_b_coarse_net(const LevInfo<T>* lev, const Coarse2B<T>* items, int ni
     template void launch_b_jacobi<T>(int, int, int, T, const Item2<T>*, int, const Ctl*, hipStream_t);         \
     template void launch_b_coarse<T>(const LevInfo<T>*, const Coarse2B<T>*, int, const T*, const Ctl*, hipStream_t, \
                                      int);                                                                    \
-    template void launch_b_finalize<T>(int, const Fin2<T>*, int, int, Ctl*, int*, hipStream_t, int*);          \
+    template void launch_b_finalize<T>(int, const Fin2<T>*, int, int, Ctl*, int*, hipStream_t, Ctl*);          \
     template void launch_b_level_get<T>(int, int, const T*, double*, hipStream_t);                           \
     template void launch_b_coarse_net<T>(const LevInfo<T>*, const Coarse2B<T>*, int, const T*, Ctl*, const bf16_t*, \
                                          hipStream_t, int);                                                     \

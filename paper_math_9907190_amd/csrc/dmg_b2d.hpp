@@ -96,6 +96,8 @@ void launch_b_finest(int n, T c, T c1, int fused, const Fin2<T>* items, int nite
                      int oop = 0);
 // the boundary entries of an (n+1)^2 array: dst <- src (src null: zeros)
 void launch_b_copy_ring(int n, const double* src, double* dst, hipStream_t s);
+// end of an out-of-place solve (ctl: the problem's control block, done set)
+void launch_b_oop_finish(int n, const Ctl* ctl, double* ub, double* u, hipStream_t s);
 // does a problem with finest level D run the first diagonal level's Jacobi in
 // the finest kernel, and the restriction into the level below it (D-2) in
 // the residual kernel (when both levels are above the coarse kernel's top lamc)
@@ -124,11 +126,12 @@ void launch_b_coarse(const LevInfo<T>* lev, const Coarse2B<T>* items, int nitems
 // sum of f^2 over interior nodes per problem, into the problem's partials (b_resid_parts(n) of them)
 template <typename T>
 void launch_b_sumsq(int n, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s);
-// host_active (pinned host memory, single-item launches only): receives 1 while
-// the problem is active, 0 once it stopped
+// host (pinned host memory, single-item launches only): receives, for kind
+// 1 and 2 in a solve, the decision (done, status, cycles), the relative
+// residual (last) and its entry of hist
 template <typename T>
 void launch_b_finalize(int kind, const Fin2<T>* items, int nitems, int nparts, Ctl* ctls, int* nactive,
-                       hipStream_t s, int* host_active = nullptr);
+                       hipStream_t s, Ctl* host = nullptr);
 void launch_b_ctl_reset(Ctl* ctls, int nprob, int mode, int max_cycles, double rtol, int* nactive, int net,
                         hipStream_t s);
 // the coarse kernel with the learned correction at the cut level (wf: packed forward weights)

@@ -428,7 +428,9 @@ __global__ void __launch_bounds__(kGrThreads) k3_green_planes(int m, T cc, const
                 else vG[q] = v;
             }
         }
-        __syncthreads();
+        // no barrier here: the next step writes only Rq (the slot of plane
+        // c-1, last read before this step's second barrier) before its first
+        // barrier, and the F slot this step's outputs read only after it
     }
 }
 
@@ -614,7 +616,9 @@ __global__ void __launch_bounds__(kRdThreads) k3_red_planes(int m, T c1, T c2, c
                 vR[(size_t)co * PR + ooff[k]] = v;
             }
         }
-        __syncthreads();
+        // no barrier here: before its first barrier the next step writes only
+        // Mq (the slot of plane c-1, last read before this step's second
+        // barrier); the F slot it then writes is the one read here
     }
 }
 
@@ -973,7 +977,9 @@ __global__ void __launch_bounds__(kPlThreads) k3_mag_planes(int m, T cc, const T
                 vE[(size_t)C * PE + ooff[k]] = (-cc * rc[k] + sm) * T(0.125);
             }
         }
-        __syncthreads();
+        // no barrier here: before its first barrier the next step writes only
+        // Bq (the slot of blue plane C, last read before this step's second
+        // barrier); the centre slot it then writes is the one read here
     }
 }
 

@@ -346,7 +346,7 @@ void enq_resid(Plan2& P, Ctl* ctls, int* nact, bool withf_all = false, bool oop 
         }
         Timed t(&P.tm, MG_K_NORM, 8.0 * P.nparts[c] * P.cls_count[c] * (withf ? 2 : 1));
         launch_b_finalize<T>(withf ? 2 : 1, fin_items<T>(P, (int)c), P.cls_count[c], P.nparts[c], ctls, nact,
-                             P.stream, P.nprob == 1 ? P.hact : nullptr);
+                             P.stream, P.nprob == 1 && !P.stat ? P.hctl : nullptr);
     }
 }
 
@@ -676,10 +676,10 @@ int plan2_solve(Plan2& P, double* const* u, const double* const* f, double rtol,
     }
     if ((e = last_launch())) return e;
     // The active-problem count after evaluation it lands in host slot it & 1
-    // before event ev[it & 1]: copied, or for a single problem written by
-    // the finalize kernel itself into slot 0 (then the host may read the
-    // next evaluation's value; it never grows, and that evaluation is
-    // already queued, so stopping on it is right).
+    // before event ev[it & 1]: copied, or for a single problem the finalize
+    // kernel writes its decision into the pinned control block itself (then
+    // the host may read the next evaluation's; it never reverts, and that
+    // evaluation is already queued, so stopping on it is right).
     const bool direct = P.nprob == 1;
     auto mark = [&](int it1) -> int {
         const int k = it1 & 1;
@@ -688,43 +688,52 @@ int plan2_solve(Plan2& P, double* const* u, const double* const* f, double rtol,
         return hip_status(hipEventRecord(P.ev[k], P.stream));
     };
     if ((e = mark(0))) return e;
+    // Iteration it+1 is launched before the host looks at what iteration it
+    // left, so the GPU does not wait for the host between cycles -- unless a
+    // single problem's residual trend says iteration it is probably the last:
+    // then the host waits first, rather than queue a whole gated iteration
+    // that would only return.
+    double rr1 = -1, rr2 = -1;   // relative residuals of evaluations it-1, it-2 (single problem)
     for (int it = 0;; it++) {
-        // launch iteration it+1 before looking at what iteration it left
-        if (it < max_cycles) {
+        const bool likely_last = direct && rr1 > 0 && rr2 > 0 && rr1 * (rr1 / rr2) <= 2 * rtol;
+        bool ahead = false;
+        if (it < max_cycles && !likely_last) {
             if ((e = run_iteration(P)) || (e = mark(it + 1))) return e;
+            ahead = true;
         }
         if (hipEventSynchronize(P.ev[it & 1]) != hipSuccess) return MG_ERR_HIP;
-        const int active = direct ? *(volatile int*)&P.hact[0] : P.hact[it & 1];
+        const int active = direct ? (*(volatile int*)&P.hctl->done ? 0 : 1) : P.hact[it & 1];
         if (active <= 0 || it >= max_cycles) break;
+        if (direct) {
+            rr2 = rr1;
+            rr1 = *(volatile double*)&P.hctl->last;
+        }
+        if (!ahead && (e = run_iteration(P)) == MG_OK) e = mark(it + 1);
+        if (e) return e;
+    }
+    // out of place: cycle k left its iterate in ub for odd k (the kernel
+    // reads the count); the array's boundary then reads 0 again, as the
+    // cycles of mg_vcycle expect
+    if (P.oop) launch_b_oop_finish(P.n[0], ctls, at<double>(P, P.off_r0[0]), u[0], P.stream);
+    // per-problem outcome: the first fields of each control block (a single
+    // problem's are in the pinned copy already)
+    if (!direct) {
+        if (hipMemcpy2DAsync(P.hres, kCtlHead, ctls, sizeof(Ctl), kCtlHead, P.nprob, hipMemcpyDeviceToHost,
+                             P.stream) != hipSuccess)
+            return MG_ERR_HIP;
+        if (history0 && hipMemcpyAsync(P.hctl, ctls, sizeof(Ctl), hipMemcpyDeviceToHost, P.stream) != hipSuccess)
+            return MG_ERR_HIP;
     }
     if (hipStreamSynchronize(P.stream) != hipSuccess) return MG_ERR_HIP;
-    // per-problem outcome: the first fields of each control block
-    if (hipMemcpy2DAsync(P.hres, kCtlHead, ctls, sizeof(Ctl), kCtlHead, P.nprob,
-                         hipMemcpyDeviceToHost, P.stream) != hipSuccess)
-        return MG_ERR_HIP;
-    if (history0 && hipMemcpyAsync(P.hctl, ctls, sizeof(Ctl), hipMemcpyDeviceToHost, P.stream) != hipSuccess)
-        return MG_ERR_HIP;
-    if (hipStreamSynchronize(P.stream) != hipSuccess) return MG_ERR_HIP;
-    int worst = MG_OK, cy0 = 0;
+    int worst = MG_OK;
     for (int i = 0; i < P.nprob; i++) {
-        const Ctl* c = reinterpret_cast<const Ctl*>(P.hres + kCtlHead * (size_t)i);
+        const Ctl* c = direct ? P.hctl : reinterpret_cast<const Ctl*>(P.hres + kCtlHead * (size_t)i);
         int st = c->done ? c->status : MG_ERR_NOT_CONVERGED;
         int cy = c->done ? c->cycles : max_cycles;
-        if (i == 0) cy0 = cy;
         if (cycles) cycles[i] = cy;
         if (relres) relres[i] = c->last;
         if (status) status[i] = st;
         if (st != MG_OK && (worst == MG_OK || st < worst)) worst = st;
-    }
-    // out of place: cycle k left its iterate in ub for odd k; the array's
-    // boundary then reads 0 again, as the cycles of mg_vcycle expect
-    if (P.oop) {
-        double* ub = at<double>(P, P.off_r0[0]);
-        if ((cy0 & 1) && hipMemcpyAsync(u[0], ub, sizeof(double) * sizeA(P.n[0]), hipMemcpyDeviceToDevice,
-                                        P.stream) != hipSuccess)
-            return MG_ERR_HIP;
-        launch_b_copy_ring(P.n[0], nullptr, ub, P.stream);
-        if (hipStreamSynchronize(P.stream) != hipSuccess) return MG_ERR_HIP;
     }
     if (history0) {
         const Ctl& H = *P.hctl;

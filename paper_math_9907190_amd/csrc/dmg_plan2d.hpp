@@ -38,7 +38,7 @@ struct Plan2 {
     hipStream_t stream = nullptr;
     int device = 0;
     void* hfin = nullptr;     // pinned host image of the finest-item table
-    Ctl* hctl = nullptr;      // pinned: problem 0's control block (history)
+    Ctl* hctl = nullptr;      // pinned: problem 0's control block (a single problem's solve: written by its finalize kernel)
     int* hact = nullptr;      // pinned: active-problem counts of two iterations
     char* hres = nullptr;     // pinned: the first kCtlHead bytes of every control block
     hipEvent_t ev[2];

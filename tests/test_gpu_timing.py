@@ -59,7 +59,8 @@ def test_families_report_time_and_bytes(dmg, n):
         assert cnt > 0 and ms > 0 and by > 0, (fam, ms, cnt, by)
         assert ms < wall_ms, (fam, ms, wall_ms)
         if fam == dmg.MG_K_FINEST and n >= 128:
-            # one launch per cycle plus the gated one after the last
-            assert cnt == cyc + 1
+            # one launch per cycle, plus a gated one after the last unless the
+            # residual trend predicted that the last cycle was the last
+            assert cnt in (cyc, cyc + 1)
             assert by == pytest.approx(cnt * fused_finest_bytes(n), rel=1e-12)
     S.close()
