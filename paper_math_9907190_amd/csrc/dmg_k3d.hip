@@ -260,16 +260,20 @@ constexpr int kGrTY = 16, kGrThreads = 512, kGrH = kGrTY + 2;
 constexpr int kGrRS = 35, kGrRH = kGrTY + 4;                    // red LDS plane: rows y0-2 .. y0+17
 constexpr int kGrRN = kGrRS * kGrRH;
 constexpr int kGrRP = (kGrRN + kGrThreads - 1) / kGrThreads;   // red slots per thread
-constexpr int kGrFR = kPlW / 2;                                  // F points per extended tile row
-constexpr int kGrFN = kGrH * kGrFR;
-constexpr int kGrFP = (kGrFN + kGrThreads - 1) / kGrThreads;   // F points per thread
 
 // Green grid of side m, Eqs. (Egprolg), (Egprolr): F points from the red
 // grid vR, then C points (a+b+c even) from the six new F values.  FINEST
-// adds the correction to u instead of storing it.  Per plane c a thread
-// stages red slots of plane c+1, computes F values of plane c (tile plus a
-// one-point halo) into a second ring, and then the x pair (2t, 2t+1) of one
-// output row of plane c-1; the inputs of the next plane are loaded meanwhile.
+// adds the correction to u instead of storing it.  Thread (oly, opr) owns
+// the x pair (oa, oa+1) = (x0 + 2 opr, x0 + 2 opr + 1) of row y0 + oly: one
+// point of the pair is an F point of a plane and the other a C point, so the
+// thread reads the pair's residuals of a plane as one 16-byte access and
+// computes the F value of its own pair itself; 82 threads also compute one F
+// point of the one-point halo ring of the tile (rows y0-1 and y0+16, and the
+// one column of x0-1, x0+64 that holds an F point of the row).  Per plane c
+// a thread stages red slots of plane c+2 into registers, writes those of
+// plane c+1 into the red ring, computes F values of plane c into a second
+// ring, and then the pair of plane c-1 from them; the inputs of the next
+// plane are loaded meanwhile.
 template <typename T, bool FINEST>
 __global__ void __launch_bounds__(kGrThreads) k3_green_planes(int m, T cc, const T* __restrict__ rG,
                                                                const T* __restrict__ vR, T* __restrict__ vG,
@@ -278,6 +282,7 @@ __global__ void __launch_bounds__(kGrThreads) k3_green_planes(int m, T cc, const
 {
     DMG_GATE(ctl);
     constexpr int W = kPlW;
+    constexpr int NH = 2 * (kPlW / 2) + kGrTY;   // F points of the halo ring per plane
     __shared__ T F[3][kGrH * kPlW];
     __shared__ T R[3][kGrRN];
     const int bid = xcd_block();   // tiles of one die are neighbours
@@ -305,42 +310,61 @@ __global__ void __launch_bounds__(kGrThreads) k3_green_planes(int m, T cc, const
         const bool ok = rok[i] && c >= 0 && c <= m && !(rsh[i] && ((rodd[i] ^ c) & 1));
         return ok ? vR[(size_t)c * PR + roff[i]] : T(0);
     };
-    // F point e: row b = y0-1 + e / 33, a = x0-1 + ((x0+b+c) & 1) + 2j with j = e % 33
-    int foff[kGrFP], flb[kGrFP], fwp[kGrFP];
-    bool frow[kGrFP], fodd[kGrFP];
-    int fa0[kGrFP];
-#pragma unroll
-    for (int i = 0; i < kGrFP; i++) {
-        const int e = tid + i * kGrThreads;
-        const int ly = e / kGrFR, j = e % kGrFR;
-        const int b = y0 - 1 + ly;
-        frow[i] = e < kGrFN && b > 0 && b < m;
-        fodd[i] = (x0 + b) & 1;                     // parity of x0 + b
-        fa0[i] = x0 - 1 + 2 * j;                    // a for even x0+b+c
-        foff[i] = b * (m + 1) + x0 - 1 + 2 * j;     // in-plane G offset of that a
-        flb[i] = (ly + 1) * kGrRS + j;              // staged red position of slot a/2-ish (see below)
-        fwp[i] = ly * W + 2 * j;                    // F position of that a
-    }
-    // F point i of plane c: its parity offset (0/1) and whether it is interior
-    auto fpar = [&](int c, int i) { return (fodd[i] ^ c) & 1; };
-    auto fin = [&](int c, int i) {
-        const int a = fa0[i] + fpar(c, i);
-        return frow[i] && a > 0 && a < m && c > 0 && c < m;
-    };
-    // the thread's output pair (2t, 2t+1) of row ob
+    // the thread's pair (oa, oa+1) of row ob; ext position (oly+1, 2 opr+1)
     const int oly = tid / (kPlTX / 2), opr = tid % (kPlTX / 2);
     const int ob = y0 + oly, oa = x0 + 2 * opr;
     const bool orow = ob < m;
+    const bool pok = orow && oa < m;                 // the pair holds an interior point
     const int ooff = ob * (m + 1) + oa;              // in-plane G offset of the pair
     const int obpar = (oa + ob) & 1;
+    // halo F point (tid < NH): ext row hy, column hx(c); a = x0-1 + hx, b = y0-1 + hy
+    int hy = 0, hj = 0;
+    bool hside = false;
+    if (tid < NH) {
+        if (tid < 2 * (kPlW / 2)) {
+            hy = tid < kPlW / 2 ? 0 : kGrH - 1;
+            hj = tid % (kPlW / 2);
+        } else {
+            hy = 1 + tid - 2 * (kPlW / 2);
+            hside = true;
+        }
+    }
+    const int hb = y0 - 1 + hy;
+    // ext column of the halo point in plane c (an F point: a + b + c odd)
+    auto hcol = [&](int c) {
+        const int q = (hb + c) & 1;
+        return hside ? (q ? 0 : W - 1) : 2 * hj + 1 - q;
+    };
+    auto hin = [&](int c, int hx) {
+        const int a = x0 - 1 + hx;
+        return tid < NH && a > 0 && a < m && hb > 0 && hb < m && c > 0 && c < m;
+    };
+    auto hload = [&](int c) -> T {
+        const int hx = hcol(c);
+        return hin(c, hx) ? rG[(size_t)c * NN + hb * (m + 1) + x0 - 1 + hx] : T(0);
+    };
+    auto pload = [&](const T* p, int c) -> P2<T> {   // the thread's pair of plane c
+        if (!pok || c < 1 || c >= m) return P2<T>{T(0), T(0)};
+        return *reinterpret_cast<const P2<T>*>(p + (size_t)c * NN + ooff);
+    };
+    // F value at ext position (ly, lx) of plane c from the staged red planes
+    // Rm, R0, Rq (c-1, c, c+1), same arithmetic and order as jac3_greenF
+    auto fval = [&](const T* Rm, const T* R0, const T* Rq, int ly, int lx, T r) -> T {
+        const int par = lx & 1;
+        const int l = (ly + 1) * kGrRS + (lx >> 1) + 1;
+        const T n0 = R0[l + par];       // (a+1, b, c)
+        const T n1 = R0[l - 1 + par];   // (a-1, b, c)
+        const T sm = n0 + n1 + R0[l + kGrRS] + R0[l - kGrRS] + Rq[l] + Rm[l];
+        return (-cc * r + sm) * (T(1) / T(6));
+    };
     // rings rotated at the start of every plane step c: Rm, R0, Rq hold red
     // planes c-1, c, c+1 (Rq written in the step); after the step's F values
     // are written, Fa, Fb, Fc hold those of planes c-2, c-1, c
     T *Rm = R[2], *R0 = R[0], *Rq = R[1];
     T *Fa = F[0], *Fb = F[1], *Fc = F[2];
-    // prologue: red planes z0-2 (R0) and z0-1 (Rq) into LDS; red plane z0 and
-    // the F residuals of plane z0-1 into registers
-    T rr[kGrRP], rf[kGrFP];
+    // prologue: red planes z0-2 (R0) and z0-1 (Rq) into LDS; red plane z0,
+    // the residual pair and the halo residual of plane z0-1 into registers
+    T rr[kGrRP];
 #pragma unroll
     for (int i = 0; i < kGrRP; i++) {
         const int e = tid + i * kGrThreads;
@@ -351,11 +375,10 @@ __global__ void __launch_bounds__(kGrThreads) k3_green_planes(int m, T cc, const
         }
         rr[i] = rload(z0, i);
     }
-#pragma unroll
-    for (int i = 0; i < kGrFP; i++)
-        rf[i] = fin(z0 - 1, i) ? rG[(size_t)(z0 - 1) * NN + foff[i] + fpar(z0 - 1, i)] : T(0);
-    double un0 = 0, un1 = 0;
-    T rn = T(0);
+    P2<T> rpn = pload(rG, z0 - 1);           // residual pair of the next plane to take F values of
+    P2<T> rpc = P2<T>{T(0), T(0)};          // ... of plane c, then (next step) of the output plane
+    T rh = hload(z0 - 1);
+    P2<double> un = P2<double>{0.0, 0.0};
     for (int c = z0 - 1; c <= z1; c++) {
         {
             T* t = Rm; Rm = R0; R0 = Rq; Rq = t;
@@ -366,44 +389,28 @@ __global__ void __launch_bounds__(kGrThreads) k3_green_planes(int m, T cc, const
             const int e = tid + i * kGrThreads;
             if (e < kGrRN) Rq[e] = rr[i];
         }
-        T rfc[kGrFP];
-#pragma unroll
-        for (int i = 0; i < kGrFP; i++) rfc[i] = rf[i];
-        const double uc0 = un0, uc1 = un1;
-        const T rc = rn;
+        const P2<T> rpo = rpc;   // the output plane's pair (c-1)
+        rpc = rpn;
+        const T rhc = rh;
+        const P2<double> uo = un;
         if (c + 1 <= z1) {   // next plane's inputs
 #pragma unroll
             for (int i = 0; i < kGrRP; i++) rr[i] = rload(c + 2, i);
-#pragma unroll
-            for (int i = 0; i < kGrFP; i++)
-                rf[i] = fin(c + 1, i) ? rG[(size_t)(c + 1) * NN + foff[i] + fpar(c + 1, i)] : T(0);
+            rpn = pload(rG, c + 1);
+            rh = hload(c + 1);
         }
-        if (c >= z0 && c < z1 && orow) {   // this plane's output inputs, used next iteration
-            const int pc = (obpar + c) & 1;   // the pair's C point is oa + pc
-            if (oa + pc < m) rn = rG[(size_t)c * NN + ooff + pc];
-            if (FINEST) {
-                if (oa < m) un0 = u[(size_t)c * NN + ooff];
-                if (oa + 1 < m) un1 = u[(size_t)c * NN + ooff + 1];
-            }
-        }
+        if (FINEST && c >= z0 && c < z1 && pok) un = *reinterpret_cast<const P2<double>*>(u + (size_t)c * NN + ooff);
         __syncthreads();
-        // F values of plane c, same arithmetic and order as jac3_greenF: with
-        // par the parity offset of a, the red neighbours (a+1, b) and (a-1, b)
-        // sit at staged slots flb+1+par and flb+par, (a, b +- 1) at flb+1 +- 35
-#pragma unroll
-        for (int i = 0; i < kGrFP; i++) {
-            const int e = tid + i * kGrThreads;
-            if (e >= kGrFN) continue;
-            const int par = fpar(c, i);
-            T v = T(0);
-            if (fin(c, i)) {
-                const int l = flb[i] + 1;
-                const T n0 = R0[l + par];       // (a+1, b, c)
-                const T n1 = R0[l - 1 + par];   // (a-1, b, c)
-                T sm = n0 + n1 + R0[l + kGrRS] + R0[l - kGrRS] + Rq[l] + Rm[l];
-                v = (-cc * rfc[i] + sm) * (T(1) / T(6));
-            }
-            Fc[fwp[i] + par] = v;
+        {   // the pair's F point of plane c (pF: 0 if oa, 1 if oa+1)
+            const int pF = ((obpar + c) & 1) ^ 1;
+            const int a = oa + pF;
+            const bool in = orow && a < m && c > 0 && c < m;
+            Fc[(oly + 1) * W + 2 * opr + 1 + pF] = in ? fval(Rm, R0, Rq, oly + 1, 2 * opr + 1 + pF, pF ? rpc.y : rpc.x)
+                                                      : T(0);
+        }
+        if (tid < NH) {
+            const int hx = hcol(c);
+            Fc[hy * W + hx] = hin(c, hx) ? fval(Rm, R0, Rq, hy, hx, rhc) : T(0);
         }
         __syncthreads();
         const int co = c - 1;
@@ -412,20 +419,24 @@ __global__ void __launch_bounds__(kGrThreads) k3_green_planes(int m, T cc, const
             const T* F0 = Fb;
             const T* Fq = Fc;   // plane co + 1
             const int pco = (obpar + co) & 1;   // 1: the pair's first point is an F point
+            T v[2];
+#pragma unroll
             for (int k = 0; k < 2; k++) {
-                const int a = oa + k;
-                if (a >= m) break;
                 const int l = (oly + 1) * W + (2 * opr + 1 + k);
-                T v;
                 if ((pco + k) & 1) {
-                    v = F0[l];
+                    v[k] = F0[l];
                 } else {
-                    T sm = F0[l + 1] + F0[l - 1] + F0[l + W] + F0[l - W] + Fq[l] + Fm[l];
-                    v = (-cc * rc + sm) * (T(1) / T(6));
+                    const T sm = F0[l + 1] + F0[l - 1] + F0[l + W] + F0[l - W] + Fq[l] + Fm[l];
+                    v[k] = (-cc * (k ? rpo.y : rpo.x) + sm) * (T(1) / T(6));
                 }
-                const size_t q = (size_t)co * NN + ooff + k;
-                if (FINEST) u[q] = (k ? uc1 : uc0) + (double)v;
-                else vG[q] = v;
+            }
+            const size_t q = (size_t)co * NN + ooff;
+            if (oa + 1 < m) {
+                if (FINEST) *reinterpret_cast<P2<double>*>(u + q) = P2<double>{uo.x + (double)v[0], uo.y + (double)v[1]};
+                else *reinterpret_cast<P2<T>*>(vG + q) = P2<T>{v[0], v[1]};
+            } else if (oa < m) {
+                if (FINEST) u[q] = uo.x + (double)v[0];
+                else vG[q] = v[0];
             }
         }
         // no barrier here: the next step writes only Rq (the slot of plane
