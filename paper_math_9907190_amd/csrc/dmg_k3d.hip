@@ -15,14 +15,18 @@ namespace dmg {
 
 // ------------------------------------------------------------ restriction
 
+// The one-thread-per-point kernels below take blockDim.y rows of a plane per
+// workgroup (x: the row's points, blockDim.x of them at a time), so that a
+// short row does not leave most of a 256-thread workgroup idle.
+
 // green (side m) -> red (side m): one thread per R-layout slot
 template <typename T>
 __global__ void __launch_bounds__(256) k3_rs_g2r(int m, const T* __restrict__ rG, T* __restrict__ rR, const Ctl* ctl)
 {
     DMG_GATE(ctl);
     int col = blockIdx.x * blockDim.x + threadIdx.x;
-    int b = blockIdx.y + 1, c = blockIdx.z + 1;
-    if (col > m / 2) return;
+    int b = blockIdx.y * blockDim.y + threadIdx.y + 1, c = blockIdx.z + 1;
+    if (col > m / 2 || b >= m) return;
     int a = 2 * col + ((b + c) & 1);
     if (a < 1 || a >= m) return;
     rR[idxR(m, a, b, c)] = rs3_g2r(rG, m, a, b, c);
@@ -36,8 +40,8 @@ __global__ void __launch_bounds__(256) k3_rs_r2m(int m, const T* __restrict__ rR
     DMG_GATE(ctl);
     int h = m / 2;
     int A = blockIdx.x * blockDim.x + threadIdx.x;
-    int B = blockIdx.y, C = blockIdx.z;
-    if (A >= h) return;
+    int B = blockIdx.y * blockDim.y + threadIdx.y, C = blockIdx.z;
+    if (A >= h || B >= h) return;
     rO[idxMO(m, 2 * A + 1, 2 * B + 1, 2 * C + 1)] = rs3_r2mO(rR, m, 2 * A + 1, 2 * B + 1, 2 * C + 1);
     if (A >= 1 && B >= 1 && C >= 1) rE[idxME(m, 2 * A, 2 * B, 2 * C)] = rs3_r2mE(rR, m, 2 * A, 2 * B, 2 * C);
 }
@@ -50,8 +54,8 @@ __global__ void __launch_bounds__(256) k3_rs_m2b(int m, const T* __restrict__ rE
     DMG_GATE(ctl);
     int mc = m / 2;
     int A = blockIdx.x * blockDim.x + threadIdx.x + 1;
-    int B = blockIdx.y + 1, C = blockIdx.z + 1;
-    if (A >= mc) return;
+    int B = blockIdx.y * blockDim.y + threadIdx.y + 1, C = blockIdx.z + 1;
+    if (A >= mc || B >= mc) return;
     rB[idxG(mc, A, B, C)] = rs3_m2b(rE, rO, m, A, B, C);
 }
 
@@ -138,13 +142,24 @@ __global__ void __launch_bounds__(kRmThreads) k3_r2m_planes(int m, const T* __re
 // (half the bytes: the point kernel measured as fast), use one thread per point
 constexpr int kRmPlMinSide = 256;
 
+// a 256-thread block shape for rows of len points: x the row (a multiple of
+// 64, at most 256), y the rows per block; and the grid over rows x planes
+inline void row_blocks(int len, int rows, int planes, dim3& blk, dim3& grd)
+{
+    const int bx = len >= 256 ? 256 : (len + 63) / 64 * 64;
+    blk = dim3(bx, 256 / bx);
+    grd = dim3((len + bx - 1) / bx, (rows + blk.y - 1) / blk.y, planes);
+}
+
 template <typename T>
 void launch_rs3(const Lev3<T>& F, const Lev3<T>& Cc, const Ctl* ctl, hipStream_t s)
 {
     int m = F.m;
+    dim3 blk, g;
     if (Cc.kind == 1) {
-        dim3 g((m / 2 + 1 + 255) / 256, m - 1, m - 1);
-        hipLaunchKernelGGL(k3_rs_g2r<T>, g, dim3(256), 0, s, m, F.r, Cc.r, ctl);
+        // slot m/2 holds no interior point (a >= m): rows of m/2 slots
+        row_blocks(m / 2, m - 1, m - 1, blk, g);
+        hipLaunchKernelGGL(k3_rs_g2r<T>, g, blk, 0, s, m, F.r, Cc.r, ctl);
     } else if (Cc.kind == 2) {
         if (m >= kRmPlMinSide && sizeof(T) == 8) {
             const int h = m / 2, nta = (h + kRmTA - 1) / kRmTA, ntb = (h + kRmTB - 1) / kRmTB, zc = 8;
@@ -153,13 +168,13 @@ void launch_rs3(const Lev3<T>& F, const Lev3<T>& Cc, const Ctl* ctl, hipStream_t
                                nta, ntb, zc, ctl);
             return;
         }
-        dim3 g((m / 2 + 255) / 256, m / 2, m / 2);
-        hipLaunchKernelGGL(k3_rs_r2m<T>, g, dim3(256), 0, s, m, F.r, Cc.r, Cc.r2, ctl);
+        row_blocks(m / 2, m / 2, m / 2, blk, g);
+        hipLaunchKernelGGL(k3_rs_r2m<T>, g, blk, 0, s, m, F.r, Cc.r, Cc.r2, ctl);
     } else {
         int mc = m / 2;
         if (mc < 2) return;
-        dim3 g((mc - 1 + 255) / 256, mc - 1, mc - 1);
-        hipLaunchKernelGGL(k3_rs_m2b<T>, g, dim3(256), 0, s, m, F.r, F.r2, Cc.r, ctl);
+        row_blocks(mc - 1, mc - 1, mc - 1, blk, g);
+        hipLaunchKernelGGL(k3_rs_m2b<T>, g, blk, 0, s, m, F.r, F.r2, Cc.r, ctl);
     }
 }
 
