@@ -1539,7 +1539,12 @@ __device__ void coarse3_down(const Coarse3<T>& a, const S3<T>& S, int lo, int hi
     }
 }
 
-// Jacobi at d = hi down to lo (the coarsest from a zero correction)
+// Jacobi at d = hi down to lo (the coarsest from a zero correction).  Each
+// level takes two passes with a barrier between them: its first-half-sweep
+// points (magenta centres, red face centres, green F points) into LDS, then
+// its second-half-sweep points summed from those stored values in the order
+// of jac3_magC / jac3_redC / jac3_greenC (the same bits as recomputing them,
+// with a dependent chain of 7-9 LDS reads per thread instead of 37-85).
 template <typename T>
 __device__ void coarse3_up(const Coarse3<T>& a, const S3<T>& S, int lo, int hi)
 {
@@ -1558,7 +1563,15 @@ __device__ void coarse3_up(const Coarse3<T>& a, const S3<T>& S, int lo, int hi)
                 int A = q % h, B = (q / h) % h, Cc = q / (h * h);
                 int x = 2 * A + 1, y = 2 * B + 1, z = 2 * Cc + 1;
                 vO[idxMO(m, x, y, z)] = jac3_magF(rO, vB, m, L.c, x, y, z);
-                if (A >= 1 && B >= 1 && Cc >= 1) vE[idxME(m, x - 1, y - 1, z - 1)] = jac3_magC(rE, rO, vB, m, L.c, x - 1, y - 1, z - 1);
+            }
+            __syncthreads();
+            const int k = h - 1;   // interior corners (2A, 2B, 2C), A, B, C in [1, h-1]
+            for (int q = tid; q < k * k * k; q += nt) {
+                int x = 2 * (q % k + 1), y = 2 * ((q / k) % k + 1), z = 2 * (q / (k * k) + 1);
+                auto o = [&](int dx, int dy, int dz) { return vO[idxMO(m, x + dx, y + dy, z + dz)]; };
+                T sm = o(1, 1, 1) + o(1, 1, -1) + o(1, -1, 1) + o(1, -1, -1) + o(-1, 1, 1) + o(-1, 1, -1) +
+                       o(-1, -1, 1) + o(-1, -1, -1);
+                vE[idxME(m, x, y, z)] = (-L.c * rE[idxME(m, x, y, z)] + sm) * T(0.125);
             }
         } else if (L.kind == 1) {
             const T* mE = S.V(d + 1);
@@ -1572,7 +1585,15 @@ __device__ void coarse3_up(const Coarse3<T>& a, const S3<T>& S, int lo, int hi)
                 if (Cc >= 1) vR[idxR(m, x + 1, y + 1, z)] = jac3_redF(rR, mE, mO, m, L.c, x + 1, y + 1, z);
                 if (A >= 1) vR[idxR(m, x, y + 1, z + 1)] = jac3_redF(rR, mE, mO, m, L.c, x, y + 1, z + 1);
                 if (B >= 1) vR[idxR(m, x + 1, y, z + 1)] = jac3_redF(rR, mE, mO, m, L.c, x + 1, y, z + 1);
-                if (A >= 1 && B >= 1 && Cc >= 1) vR[idxR(m, x, y, z)] = jac3_redC(rR, mE, mO, m, L.c, L.c2, x, y, z);
+            }
+            __syncthreads();
+            const int k = h - 1;   // interior corners
+            for (int q = tid; q < k * k * k; q += nt) {
+                int x = 2 * (q % k + 1), y = 2 * ((q / k) % k + 1), z = 2 * (q / (k * k) + 1);
+                auto f = [&](int dx, int dy, int dz) { return vR[idxR(m, x + dx, y + dy, z + dz)]; };
+                T sm = f(1, 1, 0) + f(1, -1, 0) + f(-1, -1, 0) + f(-1, 1, 0) + f(1, 0, 1) + f(1, 0, -1) +
+                       f(-1, 0, -1) + f(-1, 0, 1) + f(0, 1, 1) + f(0, 1, -1) + f(0, -1, -1) + f(0, -1, 1);
+                vR[idxR(m, x, y, z)] = (-L.c2 * rR[idxR(m, x, y, z)] + sm) * (T(1) / T(12));
             }
         } else {
             const T* vR = (d == a.last) ? S.Z() : S.V(d + 1);
@@ -1582,10 +1603,19 @@ __device__ void coarse3_up(const Coarse3<T>& a, const S3<T>& S, int lo, int hi)
             int tot = w * (m - 1) * (m - 1);
             for (int q = tid; q < tot; q += nt) {
                 int t = q % w, b = (q / w) % (m - 1) + 1, c = q / (w * (m - 1)) + 1;
-                int par = (b + c) & 1;
-                int aC = 2 * t + par, aF = 2 * t + 1 - par;
+                int aF = 2 * t + 1 - ((b + c) & 1);
                 if (aF >= 1 && aF < m) vG[idxG(m, aF, b, c)] = jac3_greenF(rG, vR, m, L.c, aF, b, c);
-                if (aC >= 1 && aC < m) vG[idxG(m, aC, b, c)] = jac3_greenC(rG, vR, m, L.c, aC, b, c);
+            }
+            __syncthreads();
+            for (int q = tid; q < tot; q += nt) {
+                int t = q % w, b = (q / w) % (m - 1) + 1, c = q / (w * (m - 1)) + 1;
+                int aC = 2 * t + ((b + c) & 1);
+                if (aC >= 1 && aC < m) {
+                    // F neighbours off the interior are zero in LDS, as jac3_greenF returns there
+                    const size_t p = idxG(m, aC, b, c), W1 = (size_t)(m + 1), W2 = W1 * W1;
+                    T sm = vG[p + 1] + vG[p - 1] + vG[p + W1] + vG[p - W1] + vG[p + W2] + vG[p - W2];
+                    vG[p] = (-L.c * rG[p] + sm) * (T(1) / T(6));
+                }
             }
         }
         __syncthreads();
