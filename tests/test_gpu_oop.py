@@ -77,3 +77,30 @@ def test_finest_residual_after_an_out_of_place_solve(dmg):
     S.vcycle(u, dev(f))
     assert torch.equal(S.level(0, 0), r_before)
     S.close()
+
+
+def test_out_of_place_edge_cases(dmg):
+    """max_cycles = 0 runs no cycle and leaves u as it was; a NaN in f stops
+    at the first evaluation (MG_ERR_NONFINITE, 0 cycles) with u untouched;
+    a solve then still matches the in-place path bitwise."""
+    n = 256
+    u0, f = start(n, 9)
+    S = dmg.Solver(2, n, p=(1.052,))
+    u = dev(u0)
+    st, cyc, rr, hist = S.solve(u, dev(f), rtol=1e-10, max_cycles=0)
+    assert st == dmg.MG_ERR_NOT_CONVERGED and cyc == 0
+    assert torch.equal(u, dev(u0))
+    fn = f.copy()
+    fn[n // 2, n // 3] = np.nan
+    u = dev(u0)
+    st, cyc, rr, hist = S.solve(u, dev(fn), rtol=1e-10, max_cycles=40)
+    assert st == dmg.MG_ERR_NONFINITE and cyc == 0
+    assert torch.equal(u, dev(u0))
+    u1 = dev(u0)
+    st1, c1, r1, h1 = S.solve(u1, dev(f), rtol=1e-10, max_cycles=40)
+    B = dmg.BatchSolver([n, n], precision=dmg.MG_FP64)
+    ub = [dev(u0), dev(u0)]
+    st2, c2, r2, s2 = B.solve(ub, [dev(f), dev(f)], rtol=1e-10, max_cycles=40)
+    assert st1 == dmg.MG_OK and c2 == [c1, c1] and r2[0] == r1
+    assert torch.equal(u1, ub[0])
+    S.close()
