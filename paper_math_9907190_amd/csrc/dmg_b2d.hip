@@ -1717,6 +1717,7 @@ __global__ void __launch_bounds__(256) kb_finalize(int kind, const Fin2<T>* __re
         host->status = c->status;
         host->cycles = c->cycles;
         host->done = c->done;
+        host->k = k + 1;   // evaluations done: what the host loop polls
     }
 }
 

@@ -90,7 +90,7 @@ constexpr size_t kCtlHead = offsetof(Ctl, hist);
 // finalize kernel into pinned host memory
 struct HostState {
     int done;
-    int pad;
+    int k;         // evaluations done
     double last;
 };
 

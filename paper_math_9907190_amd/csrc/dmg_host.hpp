@@ -4,9 +4,27 @@
 #include "../../include/dmg.h"
 #include "dmg_common.hpp"
 
+#include <chrono>
+
 namespace dmg {
 
 constexpr int kTimedMax = 64;
+
+// Host side of a solve loop: wait until the finalize kernel has written
+// evaluation it (its count of evaluations done exceeds it) or a stop into the
+// pinned state h, by polling it -- no event between iterations, whose
+// system-scope release would stall the queue every cycle.  Should nothing
+// show within 50 ms, a stream synchronisation settles it.  The caller
+// zeroes h->k and h->done before it queues the solve's first kernel.
+inline int wait_evaluation(const volatile HostState* h, int it, hipStream_t s)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    for (unsigned spin = 0; h->k < it + 1 && !h->done; spin++) {
+        if ((spin & 1023) == 1023 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(50))
+            return hipStreamSynchronize(s) == hipSuccess ? MG_OK : MG_ERR_HIP;
+    }
+    return MG_OK;
+}
 
 // Timing of one kernel family (mg_timing_enable / mg_timing_read): every
 // launch of that family is bracketed by two events on the plan's stream.

@@ -21,6 +21,7 @@
 #include "dmg_plan2d.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -661,6 +662,10 @@ int plan2_solve(Plan2& P, double* const* u, const double* const* f, double rtol,
     int* nact = at<int>(P, P.off_nactive);
     int e = bind_uf(P, u, f);
     if (e) return e;
+    if (P.nprob == 1) {   // a fresh pinned count before any kernel of this solve can write it
+        P.hctl->k = 0;
+        P.hctl->done = 0;
+    }
     if (P.rorder == 4) launch_b_rhs4(P.n[0], f[0], at<double>(P, P.off_g), P.stream);
     launch_b_ctl_reset(ctls, P.nprob, 1, max_cycles, rtol, nact, P.has_net ? 1 : 0, P.stream);
     if (P.oop) {   // the second iterate buffer takes u's boundary values
@@ -682,11 +687,28 @@ int plan2_solve(Plan2& P, double* const* u, const double* const* f, double rtol,
     // evaluation is already queued, so stopping on it is right).
     const bool direct = P.nprob == 1;
     auto mark = [&](int it1) -> int {
+        if (direct) return MG_OK;   // the host polls the pinned count instead (see wait)
         const int k = it1 & 1;
-        if (!direct && hipMemcpyAsync(&P.hact[k], nact, sizeof(int), hipMemcpyDeviceToHost, P.stream) != hipSuccess)
+        if (hipMemcpyAsync(&P.hact[k], nact, sizeof(int), hipMemcpyDeviceToHost, P.stream) != hipSuccess)
             return MG_ERR_HIP;
         return hip_status(hipEventRecord(P.ev[k], P.stream));
     };
+    // wait for evaluation it: a single problem's finalize kernel writes the
+    // count of evaluations done (and the decision) into the pinned control
+    // block, which the host polls -- no event between iterations, whose
+    // system-scope release would stall the queue every cycle.  Should the
+    // count not show within 50 ms, a stream synchronisation settles it.
+    auto wait = [&](int it) -> int {
+        if (!direct) return hipEventSynchronize(P.ev[it & 1]) == hipSuccess ? MG_OK : MG_ERR_HIP;
+        const volatile Ctl* h = P.hctl;
+        const auto t0 = std::chrono::steady_clock::now();
+        for (unsigned spin = 0; h->k < it + 1 && !h->done; spin++) {
+            if ((spin & 1023) == 1023 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(50))
+                return hipStreamSynchronize(P.stream) == hipSuccess ? MG_OK : MG_ERR_HIP;
+        }
+        return MG_OK;
+    };
+
     if ((e = mark(0))) return e;
     // Iteration it+1 is launched before the host looks at what iteration it
     // left, so the GPU does not wait for the host between cycles -- unless a
@@ -701,7 +723,7 @@ int plan2_solve(Plan2& P, double* const* u, const double* const* f, double rtol,
             if ((e = run_iteration(P)) || (e = mark(it + 1))) return e;
             ahead = true;
         }
-        if (hipEventSynchronize(P.ev[it & 1]) != hipSuccess) return MG_ERR_HIP;
+        if ((e = wait(it))) return e;
         const int active = direct ? (*(volatile int*)&P.hctl->done ? 0 : 1) : P.hact[it & 1];
         if (active <= 0 || it >= max_cycles) break;
         if (direct) {

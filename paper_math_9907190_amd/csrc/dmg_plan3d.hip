@@ -313,6 +313,8 @@ int plan3_solve(Plan3& P, double* u, const double* f, double rtol, int max_cycle
         launch_rhs4_3d(P.n, f, at<double>(P, P.g), s);
         f = at<double>(P, P.g);
     }
+    P.hstate->k = 0;   // the pinned evaluation count the loop polls, fresh before any kernel
+    P.hstate->done = 0;
     launch_ctl_reset(ctl, 1, max_cycles, rtol, s, P.has_net ? 1 : 0);
     launch_sumsq(3, P.n, f, part, P.nparts, ctl, s);
     enqueue_finalize(P, 0, ctl);
@@ -331,11 +333,9 @@ int plan3_solve(Plan3& P, double* u, const double* f, double rtol, int max_cycle
         enqueue_cycle_any(P, u, ctl);
         enqueue_residual(P, u, f, ctl);
         enqueue_finalize(P, 1, ctl, P.hstate);
-        int e = last_launch();
-        if (e) return e;
-        return hip_status(hipEventRecord(P.ev[it1 & 1], s));
+        (void)it1;
+        return last_launch();
     };
-    if (hipEventRecord(P.ev[0], s) != hipSuccess) return MG_ERR_HIP;
     double rr1 = -1, rr2 = -1;   // relative residuals of evaluations it-1, it-2
     for (int it = 0;; it++) {
         const bool likely_last = rr1 > 0 && rr2 > 0 && rr1 * (rr1 / rr2) <= 2 * rtol;
@@ -345,7 +345,7 @@ int plan3_solve(Plan3& P, double* u, const double* f, double rtol, int max_cycle
             if (e) return e;
             ahead = true;
         }
-        if (hipEventSynchronize(P.ev[it & 1]) != hipSuccess) return MG_ERR_HIP;
+        if (int e = wait_evaluation(P.hstate, it, s)) return e;
         const volatile HostState* h = P.hstate;
         if (h->done || it >= max_cycles) break;
         rr2 = rr1;

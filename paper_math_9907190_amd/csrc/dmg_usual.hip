@@ -487,6 +487,8 @@ int planu_solve(PlanU& P, double* u, const double* f, double rtol, int max_cycle
     Ctl* ctl = at<Ctl>(P, P.ctl);
     hipStream_t s = P.stream;
     f = rhs(P, f);
+    P.hstate->k = 0;   // the pinned evaluation count the loop polls, fresh before any kernel
+    P.hstate->done = 0;
     launch_ctl_reset(ctl, 1, max_cycles, rtol, s);
     launch_sumsq(P.dim, P.n, f, at<double>(P, P.partial), P.nparts, ctl, s);
     enq_finalize(P, 0, ctl);
@@ -498,11 +500,9 @@ int planu_solve(PlanU& P, double* u, const double* f, double rtol, int max_cycle
         enq_cycle_any(P, u, ctl);
         enq_residual(P, u, f, ctl);
         enq_finalize(P, 1, ctl, P.hstate);
-        int e = last_launch();
-        if (e) return e;
-        return hip_status(hipEventRecord(P.ev[it1 & 1], s));
+        (void)it1;
+        return last_launch();
     };
-    if (hipEventRecord(P.ev[0], s) != hipSuccess) return MG_ERR_HIP;
     double rr1 = -1, rr2 = -1;
     for (int it = 0;; it++) {
         const bool likely_last = rr1 > 0 && rr2 > 0 && rr1 * (rr1 / rr2) <= 2 * rtol;
@@ -512,7 +512,7 @@ int planu_solve(PlanU& P, double* u, const double* f, double rtol, int max_cycle
             if (e) return e;
             ahead = true;
         }
-        if (hipEventSynchronize(P.ev[it & 1]) != hipSuccess) return MG_ERR_HIP;
+        if (int e = wait_evaluation(P.hstate, it, s)) return e;
         const volatile HostState* h = P.hstate;
         if (h->done || it >= max_cycles) break;
         rr2 = rr1;

@@ -176,6 +176,7 @@ __global__ void __launch_bounds__(1024) k_finalize(int kind, const double* __res
     if (host) {   // pinned host memory, read by the host after an event that follows this kernel
         host->last = rr;
         host->done = ctl->done;
+        host->k = k + 1;   // written last: what the host loop polls
     }
 }
 
