@@ -454,19 +454,14 @@ int plang_setup(PlanG& P, void* ws, size_t ws_bytes, hipStream_t stream)
     if (hipGetDevice(&P.device) != hipSuccess) return MG_ERR_HIP;
     if (hipHostMalloc((void**)&P.hctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) return MG_ERR_HIP;
     if (hipHostMalloc((void**)&P.hstate, sizeof(HostState), hipHostMallocDefault) != hipSuccess) return MG_ERR_HIP;
-    for (int k = 0; k < 2; k++)
-        if (hipEventCreateWithFlags(&P.ev[k], hipEventDisableTiming) != hipSuccess) return MG_ERR_HIP;
-    P.evs = true;
+    P.live = true;
     return hip_status(hipMemsetAsync(P.ws, 0, P.total, P.stream));
 }
 
 void plang_destroy(PlanG& P)
 {
     P.tm.destroy();
-    if (P.evs) {
-        (void)hipStreamSynchronize(P.stream);
-        for (int k = 0; k < 2; k++) (void)hipEventDestroy(P.ev[k]);
-    }
+    if (P.live) (void)hipStreamSynchronize(P.stream);
     if (P.hctl) (void)hipHostFree(P.hctl);
     if (P.hstate) (void)hipHostFree(P.hstate);
 }

@@ -261,7 +261,7 @@ constexpr int kPlTX = 64, kPlTY = 8, kPlThreads = 256;
 constexpr int kPlW = kPlTX + 2;   // tile width plus a one-point halo
 constexpr int kRdTX = 32, kRdW = kRdTX + 2;        // red tiles: 32 slots (64 x positions) wide
 constexpr int kRdTY = 16, kRdH = kRdTY + 2;        // red tiles: rows (with 512 threads; 8 rows and
-constexpr int kRdThreads = 512;                     // 256 threads measured slower)
+constexpr int kRdThreads = 512;                     // 256 threads, or 32 rows and 1024, measured slower)
 
 // ---- green: F points (a+b+c odd), Eq. (Egprolg).  The red grid is staged
 // plane by plane in LDS over the tile plus a two-point halo: row (b, c) of

@@ -240,9 +240,7 @@ int plan3_setup(Plan3& P, void* ws, size_t ws_bytes, hipStream_t stream)
     if (hipGetDevice(&P.device) != hipSuccess) return MG_ERR_HIP;
     if (hipHostMalloc((void**)&P.hctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) return MG_ERR_HIP;
     if (hipHostMalloc((void**)&P.hstate, sizeof(HostState), hipHostMallocDefault) != hipSuccess) return MG_ERR_HIP;
-    for (int k = 0; k < 2; k++)
-        if (hipEventCreateWithFlags(&P.ev[k], hipEventDisableTiming) != hipSuccess) return MG_ERR_HIP;
-    P.evs = true;
+    P.live = true;
     // zero the whole workspace once: boundary entries of every level stay 0
     return hip_status(hipMemsetAsync(P.ws, 0, P.total, P.stream));
 }
@@ -263,10 +261,7 @@ int plan3_bind_static(Plan3& P, void* ws, hipStream_t stream)
 void plan3_destroy(Plan3& P)
 {
     P.tm.destroy();
-    if (P.evs) {
-        (void)hipStreamSynchronize(P.stream);
-        for (int k = 0; k < 2; k++) (void)hipEventDestroy(P.ev[k]);
-    }
+    if (P.live) (void)hipStreamSynchronize(P.stream);
     if (P.hctl) (void)hipHostFree(P.hctl);
     if (P.hstate) (void)hipHostFree(P.hstate);
 }

@@ -30,8 +30,7 @@ struct Plan3 {
     int device = 0;
     Ctl* hctl = nullptr;
     HostState* hstate = nullptr;   // pinned: written by the finalize kernel of a solve
-    hipEvent_t ev[2];
-    bool evs = false;
+    bool live = false;   // set up: destroy synchronises the stream before freeing the pinned state
     Timing tm;
 };
 

@@ -19,8 +19,7 @@ struct PlanU {
     int device = 0;
     Ctl* hctl = nullptr;
     HostState* hstate = nullptr;
-    hipEvent_t ev[2];
-    bool evs = false;
+    bool live = false;   // set up: destroy synchronises the stream before freeing the pinned state
     Timing tm;
 };
 
