@@ -558,7 +558,8 @@ int plan2_setup(Plan2& P, void* ws, size_t ws_bytes, hipStream_t stream)
     if (hipGetDevice(&P.device) != hipSuccess) return MG_ERR_HIP;
     size_t fb = sizeof(Fin2<double>) * (size_t)P.nprob;
     if (hipHostMalloc(&P.hfin, fb, hipHostMallocDefault) != hipSuccess) return MG_ERR_HIP;
-    if (hipHostMalloc((void**)&P.hctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) return MG_ERR_HIP;
+    // coherent: the finalize kernel's writes reach the polling host without a release
+    if (hipHostMalloc((void**)&P.hctl, sizeof(Ctl), hipHostMallocCoherent) != hipSuccess) return MG_ERR_HIP;
     if (hipHostMalloc((void**)&P.hact, 4 * sizeof(int), hipHostMallocDefault) != hipSuccess) return MG_ERR_HIP;
     if (hipHostMalloc((void**)&P.hres, kCtlHead * (size_t)P.nprob, hipHostMallocDefault) != hipSuccess)
         return MG_ERR_HIP;

@@ -439,7 +439,8 @@ int planu_setup(PlanU& P, void* ws, size_t ws_bytes, hipStream_t stream)
     P.tm.stream = stream;
     if (hipGetDevice(&P.device) != hipSuccess) return MG_ERR_HIP;
     if (hipHostMalloc((void**)&P.hctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) return MG_ERR_HIP;
-    if (hipHostMalloc((void**)&P.hstate, sizeof(HostState), hipHostMallocDefault) != hipSuccess) return MG_ERR_HIP;
+    // coherent: the finalize kernel's writes reach the polling host without a release
+    if (hipHostMalloc((void**)&P.hstate, sizeof(HostState), hipHostMallocCoherent) != hipSuccess) return MG_ERR_HIP;
     P.live = true;
     // boundary entries of every level stay 0
     return hip_status(hipMemsetAsync(P.ws, 0, P.total, P.stream));
