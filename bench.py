@@ -44,10 +44,13 @@ FAMILY_NAMES = {0: "residual", 1: "restriction", 2: "jacobi", 3: "finest jacobi 
 FAMILY_KERNELS = {
     "usual": {0: "k_residual", 1: "ku2_fw / ku3_fw (full weighting)", 2: "ku2_up / ku3_up (interpolation + red-black Jacobi)",
               3: "ku2_up / ku3_up, finest (u += v)", 4: "-", 5: "k_finalize"},
-    2: {0: "kb_resid (r0 formed, not stored; Eqs. Erest2r then Erest2b onto r2, norm partials)",
+    2: {0: "kb_resid (a solve's first evaluation: r0 formed, not stored; Eqs. Erest2r then Erest2b onto r2, "
+           "norm partials)",
         1: "kb_rs_pair, kb_mid_down, kb_rs_*",
         2: "kb_jac_pair, kb_mid_up, kb_jac_*",
-        3: "kb_finest_oop (r0 from u and f, r1 by Eq. Erest2r, Jacobi of the first diagonal and the finest axis level, u + v into the other iterate buffer)",
+        3: "kb_finest_res (r0 from u and f, r1 by Eq. Erest2r, Jacobi of the first diagonal and the finest axis "
+           "level, u + v into the other iterate buffer; the next evaluation's residual of u + v, its norm partials "
+           "and Eqs. Erest2r then Erest2b onto r2)",
         4: "kb_coarse", 5: "kb_finalize"},
     3: {0: "k3_resid_planes (r0 and Eq. Erred onto the red level, norm partials)",
         1: "k3_r2m_planes, k3_rs_m2b, k3_down_group (a level group of side 16..64 per launch), k3_rs_*",

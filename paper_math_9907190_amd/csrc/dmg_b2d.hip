@@ -143,16 +143,16 @@ __device__ inline void resid_body(int m, double inv_h2, const Fin2<T>& it, const
             const int j = jb + i;
             if (j > ylast) return;
             bool rowin = j >= 1 && j <= m - 1;
-            double uW = __shfl_up(uc1, 1);   // u(2t-1, j)
-            double uE = __shfl_down(uc0, 1); // u(2t+2, j)
+            double uW = lane_up(uc1);   // u(2t-1, j)
+            double uE = lane_down(uc0); // u(2t+2, j)
             // grid south / north rows of the lane's pair (marched j-1 / j+1 unless mirrored)
             const double us0 = MIR ? up0 : um0, us1 = MIR ? up1 : um1;
             const double un0 = MIR ? um0 : up0, un1 = MIR ? um1 : up1;
             double x0, x1;
             if constexpr (M4) {
                 // Eq. (Efos2): -20 centre, 4 x (S, N, W, E), then NE, NW, SW, SE
-                const double mW = __shfl_up(um1, 1), mE = __shfl_down(um0, 1);   // marched row j-1, columns 2t-1, 2t+2
-                const double pW = __shfl_up(up1, 1), pE = __shfl_down(up0, 1);   // marched row j+1
+                const double mW = lane_up(um1), mE = lane_down(um0);   // marched row j-1, columns 2t-1, 2t+2
+                const double pW = lane_up(up1), pE = lane_down(up0);   // marched row j+1
                 const double sW = MIR ? pW : mW, sE = MIR ? pE : mE;            // grid south row
                 const double nW = MIR ? mW : pW, nE = MIR ? mE : pE;            // grid north row
                 x0 = c.fx[i] - (-20 * uc0 + 4 * (us0 + un0 + uW + uc1) + un1 + nW + sW + us1) * inv_h2;
@@ -187,7 +187,7 @@ __device__ inline void resid_body(int m, double inv_h2, const Fin2<T>& it, const
                 // Eq. Erest2r at the diagonal point of row j-1 (a + j-1 even)
                 constexpr int p0 = decltype(P0)::value;
                 const int q = p0 >= 0 ? (p0 + i + 1) & 1 : (j - 1) & 1;
-                T sh = q ? __shfl_down(rm1_0, 1) : __shfl_up(rm1_1, 1);
+                T sh = q ? lane_down(rm1_0) : lane_up(rm1_1);
                 T rc = q ? rm1_1 : rm1_0;
                 T rw = q ? rm1_0 : sh;
                 T re = q ? sh : rm1_1;
@@ -205,7 +205,7 @@ __device__ inline void resid_body(int m, double inv_h2, const Fin2<T>& it, const
                     // as marched (mirrored: 2B+1, 2B, 2B-1 of the grid)
                     if (!(j & 1) && j - 2 >= y0 && j - 2 < y1) {
                         const int B = (j - 2) >> 1;
-                        const T d3w = __shfl_up(d3, 1), d1w = __shfl_up(d1, 1);
+                        const T d3w = lane_up(d3), d1w = lane_up(d1);
                         if (useful2 && B >= 1 && B <= mc - 1)
                             rA2[(size_t)(MIR ? mc - B : B) * (mc + 1) + t] =
                                 MIR ? rs2_core(d2, d1w, d1, d3, d3w) : rs2_core(d2, d3w, d3, d1, d1w);
@@ -448,21 +448,42 @@ constexpr int kFusePairs = 60;
 // updated.  The lane's u pairs of the rows it has loaded stay in registers
 // (five rows) for the update; lanes 0 and 63 also load the one column beyond
 // the band that their residual needs.
-template <typename T, bool FINEST, bool NT, bool MIR, bool PP = false>
-__device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, const T* __restrict__ v2,
-                                  T* __restrict__ vA, double* __restrict__ u, int wv, int nwx, int rows,
-                                  const double* __restrict__ uc = nullptr, const double* __restrict__ fr = nullptr)
+// RES (with PP): the kernel also forms the new iterate's residual, its norm
+// partials and its two restrictions (Eqs. Erest2r, Erest2b) onto the axis
+// level below the first diagonal one (rA2), as the residual kernel does for
+// the next evaluation, from the new iterate's rows while they are still in
+// registers.  The residual rows trail the Jacobi rows by two, the march
+// starts three or four rows before the strip's first row and ends three or
+// four rows past its last (the new iterate is formed, not written, there), and a wave owns 57 column
+// pairs, lanes 4 .. 60: the new iterate is right in lanes 2 .. 61, its
+// residual in 3 .. 60, the diagonal restriction in 3 .. 60 and the axis one,
+// which takes the diagonal values of the lane to the west, in 4 .. 60.
+// Strips must start on odd rows (an even strip length), as in the residual
+// kernel.  Returns the lane's part of the squared norm.
+constexpr int kResPairs = 57;
+template <typename T, bool FINEST, bool NT, bool MIR, bool PP = false, bool RES = false>
+__device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA, const T* __restrict__ v2,
+                                    T* __restrict__ vA, double* __restrict__ u, int wv, int nwx, int rows,
+                                    const double* __restrict__ uc = nullptr, const double* __restrict__ fr = nullptr,
+                                    T* __restrict__ rA2 = nullptr)
 {
+    static_assert(!RES || (PP && FINEST), "the residual of the new iterate needs the out-of-place finest step");
+    constexpr int kStride = RES ? kResPairs : kFusePairs, kLane0 = RES ? 4 : 2;
     const int lane = threadIdx.x & 63;
     const int wx = wv % nwx, sy = wv / nwx;
-    const int t = wx * kFusePairs - 2 + lane;
+    const int t = wx * kStride - kLane0 + lane;
     const int ya = 1 + sy * rows, yb = min(ya + rows, m);   // the strip's rows [ya, yb)
     const int y0 = MIR ? m - yb + 1 : ya;                   // the same rows as marched
     const int y1 = MIR ? m - ya + 1 : yb;
     const int h = m / 2, W = h + 1;   // row length of v2 (side m/2)
     auto R = [&](int k) { return MIR ? m - k : k; };       // marched row -> grid row
     auto RB = [&](int B) { return MIR ? h - B : B; };      // the same on the level of side m/2
-    const bool useful = lane >= 2 && lane < kFusePairs + 2 && t >= 0 && t <= h;
+    const bool useful = lane >= kLane0 && lane < kStride + kLane0 && t >= 0 && t <= h;
+    // RES: the residual rows [jstart, ylast] and the first diagonal row dlo, as
+    // the residual kernel takes them (strips start on odd grid rows); the march
+    // rows [jbeg, jend]
+    const int dlo = MIR ? y0 - 1 : y0, jstart = dlo - 1, ylast = MIR ? y1 : y1 + 1;
+    const int jbeg = RES ? jstart - 2 : y0 - 1, jend = RES ? ylast + 2 : y1;
     const bool colok = t >= 0 && t <= h;
     const bool c0 = t >= 1 && 2 * t <= m - 1, c1 = t >= 0 && 2 * t + 1 <= m - 1;
     const size_t w = (size_t)(m + 1);
@@ -476,28 +497,29 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
         x = c0 ? v.x : T(0);
         y = c1 ? v.y : T(0);
     };
-    // Eq. (Erest2r) at the lane's diagonal point (2t + (k&1), k) of marched
-    // row k from the axis residual pairs of marched rows k-1 (m), k (c), k+1
-    // (p), the operands in grid order (south = the lower grid row); the same
-    // bits as the stored restriction of the residual kernels
-    auto rs1 = [&](int k, T mx, T my, T cx, T cy, T px, T py) -> T {
-        const int q = k & 1;   // grid row R(k) has the parity of k (m is even)
-        const T sh = q ? __shfl_down(cx, 1) : __shfl_up(cy, 1);
-        const T rc = q ? cy : cx;
-        const T rw = q ? cx : sh;
-        const T re = q ? sh : cy;
-        const T rlo = q ? my : mx, rhi = q ? py : px;
-        return MIR ? rs2_core(rc, rw, rhi, re, rlo) : rs2_core(rc, rw, rlo, re, rhi);
+    // Eq. (Erest2r) at the lane's diagonal point (2t + q, k) of marched row k
+    // (Q: Int<q>, q = k & 1; grid row R(k) has the parity of k, m being even)
+    // from the axis residual pairs of marched rows k-1 (m), k (c), k+1 (p),
+    // the operands in grid order (south = the lower grid row); the same bits
+    // as the stored restriction of the residual kernels
+    auto rs1 = [&](auto Q, T mx, T my, T cx, T cy, T px, T py) -> T {
+        if constexpr (decltype(Q)::value) {
+            const T e = lane_down(cx);
+            return MIR ? rs2_core(cy, cx, py, e, my) : rs2_core(cy, cx, my, e, py);
+        } else {
+            const T w_ = lane_up(cy);
+            return MIR ? rs2_core(cx, w_, px, cy, mx) : rs2_core(cx, w_, mx, cy, px);
+        }
     };
     // F point (2t+1, k), k odd, from v2 rows (k-1)/2 (vlo) and (k+1)/2 (vhi), as jac2_diagF
     auto f21 = [&](int k, T rF, T vlo, T vhi) -> T {
-        const T vlo_e = __shfl_down(vlo, 1), vhi_e = __shfl_down(vhi, 1);
+        const T vlo_e = lane_down(vlo), vhi_e = lane_down(vhi);
         if (!(t >= 0 && t <= h - 1 && k >= 1 && k <= m - 1)) return T(0);
         return MIR ? jac2_chain(cd, rF, vhi, vhi_e, vlo_e, vlo) : jac2_chain(cd, rF, vlo, vlo_e, vhi_e, vhi);
     };
     // C point (2t, k), k even, from the F rows k-1 (Fm) and k+1 (Fp), as jac2_diagC
     auto c21 = [&](int k, T rC, T Fm, T Fp) -> T {
-        const T Fm_w = __shfl_up(Fm, 1), Fp_w = __shfl_up(Fp, 1);
+        const T Fm_w = lane_up(Fm), Fp_w = lane_up(Fp);
         if (!(t >= 1 && t <= h - 1 && k >= 2 && k <= m - 2)) return T(0);
         return MIR ? jac2_sum(cd, rC, Fp_w, Fp, Fm, Fm_w) : jac2_sum(cd, rC, Fm_w, Fm, Fp, Fp_w);
     };
@@ -532,7 +554,7 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
     // zero where ldR reads zero
     auto r0row = [&](int k, double ax, double ay, double bx, double by, double cx, double cy, double e, double fx,
                      double fy, T& x, T& y) {
-        double uW = __shfl_up(by, 1), uE = __shfl_down(bx, 1);
+        double uW = lane_up(by), uE = lane_down(bx);
         if (lane == 0) uW = e;
         if (lane == 63) uE = e;
         x = y = 0;
@@ -543,10 +565,12 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
         x = c0 ? (T)x0 : T(0);
         y = c1 ? (T)x1 : T(0);
     };
-    // window entering row j: diagonal values of rows j-1 (dm), j (d0); at even
-    // j, Fn = F row j+1; at odd j, vlo = v2 row (j+1)/2.  The axis residual
-    // pairs of rows j-3 .. j+2 give the diagonal residuals of rows j-2 .. j+1.
-    int j = y0 - 1;
+    // The march starts on the even row j at or before jbeg, so that every
+    // row's parity is known at compile time.  Window entering row j:
+    // diagonal values of rows j-1 (dm), j (d0), Fn = F row j+1.  The axis
+    // residual pairs of rows j-3 .. j+2 give the diagonal residuals of rows
+    // j-2 .. j+1.
+    const int j = jbeg & ~1;
     T a0x, a0y, a1x, a1y, a2x, a2y, sx, sy_, nx, ny, xx, xy;
     // PP: u pairs of rows jj-1 .. jj+2 (w0 .. w3) entering an odd row jj, of
     // rows jj-1 .. jj+3 (w0 .. w4) entering an even one; eS: the outer column
@@ -575,7 +599,7 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
         w2x = ux_[5]; w2y = uy_[5];
         w3x = ux_[6]; w3y = uy_[6];
         w4x = ux_[7]; w4y = uy_[7];
-        eS = (j & 1) ? ue_[6] : ue_[7];
+        eS = ue_[7];
     } else {
         ldR(j - 3, a0x, a0y);
         ldR(j - 2, a1x, a1y);
@@ -584,17 +608,12 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
         ldR(j + 1, nx, ny);
         ldR(j + 2, xx, xy);
     }
-    T dm, d0, vlo, Fn = T(0);
-    if (j & 1) {
-        const T Fj = fsr(j, rs1(j, a2x, a2y, sx, sy_, nx, ny));
-        dm = c21(j - 1, rs1(j - 1, a1x, a1y, a2x, a2y, sx, sy_), fsr(j - 2, rs1(j - 2, a0x, a0y, a1x, a1y, a2x, a2y)), Fj);
-        d0 = Fj;
-        vlo = ld2((j + 1) >> 1);
-    } else {
-        const T Fm = fsr(j - 1, rs1(j - 1, a1x, a1y, a2x, a2y, sx, sy_));
-        const T Fp = fsr(j + 1, rs1(j + 1, sx, sy_, nx, ny, xx, xy));
+    T dm, d0, vlo, Fn;
+    {
+        const T Fm = fsr(j - 1, rs1(Int<1>{}, a1x, a1y, a2x, a2y, sx, sy_));
+        const T Fp = fsr(j + 1, rs1(Int<1>{}, sx, sy_, nx, ny, xx, xy));
         dm = Fm;
-        d0 = c21(j, rs1(j, a2x, a2y, sx, sy_, nx, ny), Fm, Fp);
+        d0 = c21(j, rs1(Int<0>{}, a2x, a2y, sx, sy_, nx, ny), Fm, Fp);
         Fn = Fp;
         vlo = ld2((j + 2) >> 1);
     }
@@ -609,12 +628,15 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
         double ux, uy;
         double u3x, u3y, u4x, u4y, e3, e4, f2x, f2y, f3x, f3y;
     };
-    auto load = [&](int jj, Ck& c) {
+    // Pc: Int<jj & 1>; an even row's buffer holds at most the u pair (FINEST
+    // without PP) and is otherwise constant zero
+    auto load = [&](auto Pc, int jj, Ck& c) {
+        constexpr int P = decltype(Pc)::value;
         if constexpr (PP) {
             c.ax = c.ay = c.bx = c.by = c.vhi = 0;
             c.ux = c.uy = 0;
             c.u3x = c.u3y = c.u4x = c.u4y = c.e3 = c.e4 = c.f2x = c.f2y = c.f3x = c.f3y = 0;
-            if (jj > y1 || !(jj & 1)) return;
+            if (jj > jend || !P) return;
             ldU(jj + 3, c.u3x, c.u3y, c.e3);
             ldU(jj + 4, c.u4x, c.u4y, c.e4);
             ldF(jj + 2, c.f2x, c.f2y);
@@ -624,13 +646,14 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
         }
         c.ax = c.ay = c.bx = c.by = c.vhi = 0;
         c.ux = c.uy = 0;
+        c.u3x = c.u3y = c.u4x = c.u4y = c.e3 = c.e4 = c.f2x = c.f2y = c.f3x = c.f3y = 0;
         if (jj > y1) return;
         if (FINEST && useful && jj >= y0 && jj < y1 && (c0 || c1)) {
             P2<double> v = *reinterpret_cast<const P2<double>*>(u + (size_t)R(jj) * w + 2 * t);
             c.ux = v.x;
             c.uy = v.y;
         }
-        if (jj & 1) {
+        if constexpr (P) {
             ldR(jj + 2, c.ax, c.ay);
             ldR(jj + 3, c.bx, c.by);
             c.vhi = ld2((jj + 3) >> 1);
@@ -638,19 +661,29 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
     };
     T Fm2 = 0, Fm1 = 0, rCm1 = 0;
     double uxm1 = 0, uym1 = 0;
-    auto proc = [&](int jj, const Ck& c) {
-        if (jj > y1) return;
+    // RES: the new iterate's pairs of rows k-1 (q_m) and k (q_c) entering the
+    // residual of row k = jj-2; the residual pairs of rows k-1, k-2 and the
+    // diagonal values of rows k-3, k-2, as in the residual kernel; the norm
+    double qmx = 0, qmy = 0, qcx = 0, qcy = 0;
+    T rm1_0 = 0, rm1_1 = 0, rm2_0 = 0, rm2_1 = 0, d3 = 0, d2 = 0;
+    double acc = 0;
+    const bool useful2 = useful && t >= 1 && t <= h - 1;
+    double gfx = 0, gfy = 0;   // f of the next residual row, loaded one row ahead
+    if constexpr (RES) ldF(jstart, gfx, gfy);
+    auto proc = [&](auto Pc, int jj, const Ck& c) {
+        constexpr int P = decltype(Pc)::value;   // jj & 1
+        if (jj > jend) return;
         T cax = c.ax, cay = c.ay, cbx = c.bx, cby = c.by;   // residual pairs of rows jj+2, jj+3 (odd jj)
         if constexpr (PP) {
-            if (jj & 1) {
+            if constexpr (P) {
                 r0row(jj + 2, w2x, w2y, w3x, w3y, c.u3x, c.u3y, eS, c.f2x, c.f2y, cax, cay);
                 r0row(jj + 3, w3x, w3y, c.u3x, c.u3y, c.u4x, c.u4y, c.e3, c.f3x, c.f3y, cbx, cby);
             }
         }
         T dp;
-        if (jj & 1) {   // row jj+1 even: its C points from F rows jj (= d0) and jj+2
-            const T r1c = rs1(jj + 1, sx, sy_, nx, ny, cax, cay);
-            const T r1f = rs1(jj + 2, nx, ny, cax, cay, cbx, cby);
+        if constexpr (P) {   // row jj+1 even: its C points from F rows jj (= d0) and jj+2
+            const T r1c = rs1(Int<0>{}, sx, sy_, nx, ny, cax, cay);
+            const T r1f = rs1(Int<1>{}, nx, ny, cax, cay, cbx, cby);
             const T F2 = f21(jj + 2, r1f, vlo, c.vhi);
             dp = c21(jj + 1, r1c, d0, F2);
             Fn = F2;
@@ -658,19 +691,23 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
         } else {        // row jj+1 odd: its F points, computed one row ago
             dp = Fn;
         }
-        const int q = jj & 1;
+        constexpr int q = P;
         const T rF = q ? sx : sy_;   // F at column 2t+1-q
         const T rC = q ? sy_ : sx;   // C at column 2t+q
-        const T nb = q ? __shfl_up(d0, 1) : __shfl_down(d0, 1);
+        T nb;
+        if constexpr (q) nb = lane_up(d0);
+        else nb = lane_down(d0);
         const T vw = q ? nb : d0;
         const T ve = q ? d0 : nb;
         const int aF = 2 * t + 1 - q;
         const T Fj = (aF >= 1 && aF <= m - 1 && jj >= 1 && jj <= m - 1)
                          ? (MIR ? jac2_sum(cc, rF, vw, dp, ve, dm) : jac2_sum(cc, rF, vw, dm, ve, dp))
                          : T(0);
-        if (jj - 1 >= y0) {
-            const int qq = (jj - 1) & 1;
-            const T sb = qq ? __shfl_down(Fm1, 1) : __shfl_up(Fm1, 1);
+        if (jj - 1 >= (RES ? jbeg + 1 : y0)) {
+            constexpr int qq = 1 - P;
+            T sb;
+            if constexpr (qq) sb = lane_down(Fm1);
+            else sb = lane_up(Fm1);
             const T cw = qq ? Fm1 : sb;
             const T ce = qq ? sb : Fm1;
             const T C = MIR ? jac2_sum(cc, rCm1, cw, Fj, ce, Fm2) : jac2_sum(cc, rCm1, cw, Fm2, ce, Fj);
@@ -678,7 +715,61 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
             const T vy = qq ? C : Fm1;   // column 2t+1
             const size_t o = (size_t)R(jj - 1) * w + 2 * t;
             const double ox = PP ? w0x : uxm1, oy = PP ? w0y : uym1;   // the iterate at row jj-1
-            if (useful) {
+            if constexpr (RES) {
+                // the new iterate's pair of row jj-1 (the old values off the interior)
+                const bool rin = jj - 1 >= 1 && jj - 1 <= m - 1;
+                const double npx = (rin && c0) ? ox + (double)vx : ox, npy = (rin && c1) ? oy + (double)vy : oy;
+                const int k = jj - 2;   // its residual row: u' rows k-1 (q_m), k (q_c), k+1 (np)
+                if (k >= jstart && k <= ylast) {
+                    const double fx = gfx, fy = gfy;
+                    ldF(k + 1, gfx, gfy);
+                    const double uW = lane_up(qcy), uE = lane_down(qcx);
+                    const bool rowin = k >= 1 && k <= m - 1;
+                    double x0 = 0, x1 = 0;
+                    if (rowin && colok) {
+                        if (MIR) resid_pair(inv_h2, fx, fy, uW, npx, npy, qcx, qcy, qmx, qmy, uE, x0, x1);
+                        else resid_pair(inv_h2, fx, fy, uW, qmx, qmy, qcx, qcy, npx, npy, uE, x0, x1);
+                    }
+                    const T r0j = (rowin && c0) ? (T)x0 : T(0), r1j = (rowin && c1) ? (T)x1 : T(0);
+                    if (k >= y0 && k < y1 && useful) {
+                        if (c0 && c1) acc += x0 * x0 + x1 * x1;
+                        else if (c1) acc += x1 * x1;
+                        else if (c0) acc += x0 * x0;
+                    }
+                    if (k - 1 >= dlo) {
+                        // Eq. (Erest2r) at the diagonal point of row k-1, then
+                        // Eq. (Erest2b) onto the axis level below it at even k
+                        constexpr int q = 1 - P;   // (k - 1) & 1, k = jj - 2
+                        T sh;
+                        if constexpr (q) sh = lane_down(rm1_0);
+                        else sh = lane_up(rm1_1);
+                        const T rc = q ? rm1_1 : rm1_0;
+                        const T rw = q ? rm1_0 : sh;
+                        const T re = q ? sh : rm1_1;
+                        const T rlo = q ? rm2_1 : rm2_0;
+                        const T rhi = q ? r1j : r0j;
+                        const T d1 = MIR ? rs2_core(rc, rw, rhi, re, rlo) : rs2_core(rc, rw, rlo, re, rhi);
+                        if (!P && k - 2 >= y0 && k - 2 < y1) {
+                            const int B = (k - 2) >> 1;
+                            const T d3w = lane_up(d3), d1w = lane_up(d1);
+                            if (useful2 && B >= 1 && B <= h - 1)
+                                rA2[(size_t)(MIR ? h - B : B) * (h + 1) + t] =
+                                    MIR ? rs2_core(d2, d1w, d1, d3, d3w) : rs2_core(d2, d3w, d3, d1, d1w);
+                        }
+                        d3 = d2;
+                        d2 = d1;
+                    }
+                    rm2_0 = rm1_0;
+                    rm2_1 = rm1_1;
+                    rm1_0 = r0j;
+                    rm1_1 = r1j;
+                }
+                qmx = qcx;
+                qmy = qcy;
+                qcx = npx;
+                qcy = npy;
+            }
+            if (useful && (!RES || jj - 1 < y1) && jj - 1 >= y0) {
                 if constexpr (FINEST) {
                     if (c0 && c1) *reinterpret_cast<P2<double>*>(u + o) = P2<double>{ox + (double)vx, oy + (double)vy};
                     else if (c1) u[o + 1] = oy + (double)vy;
@@ -700,7 +791,7 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
         // slide the residual pairs one row
         sx = nx;
         sy_ = ny;
-        if (jj & 1) {
+        if constexpr (P) {
             nx = cax;
             ny = cay;
             xx = cbx;
@@ -713,7 +804,7 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
             w0x = w1x; w0y = w1y;
             w1x = w2x; w1y = w2y;
             w2x = w3x; w2y = w3y;
-            if (jj & 1) {
+            if constexpr (P) {
                 w3x = c.u3x; w3y = c.u3y;
                 w4x = c.u4x; w4y = c.u4y;
                 eS = c.e4;
@@ -722,7 +813,8 @@ __device__ inline void fused_body(int m, T cc, T cd, const T* __restrict__ rA, c
             }
         }
     };
-    rows_march<1, Ck>(j, y1, load, proc);
+    rows_march_parity<Ck>(j, jend, load, proc);
+    return acc;
 }
 
 template <typename T, bool NT>
@@ -755,6 +847,36 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
         fused_body<double, true, false, true, true>(m, cc, cd, nullptr, it.v2, nullptr, un, wv, nwx, rows, uc, it.f);
     else
         fused_body<double, true, false, false, true>(m, cc, cd, nullptr, it.v2, nullptr, un, wv, nwx, rows, uc, it.f);
+}
+
+// The same step, which also evaluates the new iterate (the residual kernel's
+// work for the next evaluation, see RES above): each block's norm partial
+// goes to part[blockIdx.x], and block 0 clears part[gridDim.x .. nparts), so
+// the finalize kernel sums as many partials as after the residual kernel.
+__global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(3))) kb_finest_res(int m, double cc, double cd,
+                                                           const Fin2<double>* __restrict__ items, int nwx,
+                                                           int nwaves, int rows, const Ctl* __restrict__ ctls,
+                                                           int nparts)
+{
+    const Fin2<double> it = items[blockIdx.y];
+    ITEM_GATE(ctls, it.prob);
+    const int wv = rows_wave_id(nwaves);
+    const bool odd = ctls[it.prob].k & 1;
+    const double* uc = odd ? it.u : it.ub;
+    double* un = odd ? it.ub : it.u;
+    double acc = 0;
+    if (wv < nwaves) {   // no early return: the block sum below synchronises the block
+        if ((wv / nwx) & 1)
+            acc = fused_body<double, true, false, true, true, true>(m, cc, cd, nullptr, it.v2, nullptr, un, wv, nwx,
+                                                                    rows, uc, it.f, it.r2);
+        else
+            acc = fused_body<double, true, false, false, true, true>(m, cc, cd, nullptr, it.v2, nullptr, un, wv, nwx,
+                                                                     rows, uc, it.f, it.r2);
+    }
+    const double sum = rows_block_sum(acc);
+    if (threadIdx.x == 0) it.part[blockIdx.x] = sum;
+    if (blockIdx.x == 0)
+        for (int i = (int)gridDim.x + (int)threadIdx.x; i < nparts; i += blockDim.x) it.part[i] = 0.0;
 }
 
 // The Jacobi of an axis level L (side m, coefficient cc) with that of the
@@ -2026,6 +2148,30 @@ void launch_b_finest(int n, T c, T c1, int fused, const Fin2<T>* items, int nite
     else
         launch_timed((kb_finest<T, kChunkJAxis, false>), dim3(nb, nitems), dim3(kRowBlock), s, n, c, items, nwx,
                      nw, rows, ctls);
+}
+
+// the grid of kb_finest_res: one round of waves, strips of even length
+static void finest_res_grid(int n, int& rows, int& nwx, int& nw, int& nb)
+{
+    rows = fill_rows((const void*)kb_finest_res, n / 2 + 1, kResPairs, n - 1);
+    rows += rows & 1;
+    rows_grid(n / 2 + 1, kResPairs, n - 1, rows, nwx, nw, nb);
+}
+
+bool b_finest_res_fits(int n, int nparts)
+{
+    if (n < 8) return false;
+    int rows, nwx, nw, nb;
+    finest_res_grid(n, rows, nwx, nw, nb);
+    return nb <= nparts;
+}
+
+void launch_b_finest_res(int n, double c, double c1, const Fin2<double>* items, const Ctl* ctls, int nparts,
+                         hipStream_t s)
+{
+    int rows, nwx, nw, nb;
+    finest_res_grid(n, rows, nwx, nw, nb);
+    launch_timed(kb_finest_res, dim3(nb, 1), dim3(kRowBlock), s, n, c, c1, items, nwx, nw, rows, ctls, nparts);
 }
 
 template <typename T>

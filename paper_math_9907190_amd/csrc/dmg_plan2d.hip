@@ -332,13 +332,15 @@ double bytes_jac(int diag, int m, size_t es)
 // class with n >= 4 also sums f^2, so that the norm of f needs no pass of its
 // own (the others have theirs from enq_norm_f(small_only))
 // oop: the out-of-place solve step (P.oop)
+// formed: the finest kernel of the cycle has formed the residual already
+// (kb_finest_res); only the stopping decision is left
 template <typename T>
-void enq_resid(Plan2& P, Ctl* ctls, int* nact, bool withf_all = false, bool oop = false)
+void enq_resid(Plan2& P, Ctl* ctls, int* nact, bool withf_all = false, bool oop = false, bool formed = false)
 {
     size_t es = sizeof(T);
     for (size_t c = 0; c < P.cls_n.size(); c++) {
         const bool withf = withf_all && P.cls_n[c] >= 4;
-        {
+        if (!formed) {
             const int n = P.cls_n[c];
             const bool fz = fin_fused(2 * (ilog2(n) - 1), P.lamc);
             Timed t(&P.tm, MG_K_RESIDUAL, bytes_resid(n, es, fz, oop) * P.cls_count[c], true);
@@ -365,8 +367,10 @@ bool use_mid(const Plan2& P)
     return true;
 }
 
+// res (with oop): the finest kernel also forms the next evaluation's residual
+// where its grid allows (kb_finest_res); returns whether it did
 template <typename T>
-void enq_cycle(Plan2& P, Ctl* ctls, bool oop = false)
+bool enq_cycle(Plan2& P, Ctl* ctls, bool oop = false, bool res = false)
 {
     size_t es = sizeof(T);
     const bool mid = use_mid(P);
@@ -448,15 +452,27 @@ void enq_cycle(Plan2& P, Ctl* ctls, bool oop = false)
         launch_b_jacobi<T>(lam & 1, side_of(lam), P.rows_jac[lam], (T)coef(P, lam), at<Item2<T>>(P, P.off_jac_items[lam]),
                            k, ctls, P.stream);
     }
+    bool formed = false;
     for (size_t c = 0; c < P.cls_n.size(); c++) {
         int n = P.cls_n[c];
         const int D = 2 * (ilog2(n) - 1);
         const bool fz = fin_fused(D, P.lamc);
-        Timed t(&P.tm, MG_K_FINEST, bytes_finest(n, es, fz, oop) * P.cls_count[c], true);
         double sh = 1.0 / n;
+        if constexpr (sizeof(T) == 8) {
+            if (res && oop && fz && P.cls_count[c] == 1 && b_finest_res_fits(n, P.nparts[c])) {
+                const double M = n / 2;
+                Timed t(&P.tm, MG_K_FINEST, bytes_finest(n, es, fz, oop) + es * (M - 1) * (M - 1), true);
+                launch_b_finest_res(n, P.p * sh * sh, coef(P, D - 1), fin_items<double>(P, (int)c), ctls, P.nparts[c],
+                                    P.stream);
+                formed = true;
+                continue;
+            }
+        }
+        Timed t(&P.tm, MG_K_FINEST, bytes_finest(n, es, fz, oop) * P.cls_count[c], true);
         launch_b_finest<T>(n, (T)(P.p * sh * sh), (T)(fz ? coef(P, D - 1) : 0.0), fz ? 1 : 0, fin_items<T>(P, (int)c),
                            P.cls_count[c], ctls, P.stream, oop ? 1 : 0);
     }
+    return formed;
 }
 
 // one outer iteration of a solve: cycle, the next residual, the stopping decision
@@ -464,7 +480,10 @@ void enq_iteration(Plan2& P)
 {
     Ctl* ctls = at<Ctl>(P, P.off_ctl);
     int* nact = at<int>(P, P.off_nactive);
-    if (P.prec == MG_FP64) { enq_cycle<double>(P, ctls, P.oop); enq_resid<double>(P, ctls, nact, false, P.oop); }
+    if (P.prec == MG_FP64) {
+        const bool formed = enq_cycle<double>(P, ctls, P.oop, P.res);
+        enq_resid<double>(P, ctls, nact, false, P.oop, formed);
+    }
     else { enq_cycle<float>(P, ctls); enq_resid<float>(P, ctls, nact); }
 }
 
@@ -570,6 +589,11 @@ int plan2_setup(Plan2& P, void* ws, size_t ws_bytes, hipStream_t stream)
     if (e) return e;
     const char* ng = getenv("DMG_NO_GRAPH");
     P.use_graph = !(ng && ng[0] == '1');
+    // out-of-place solves form each evaluation's residual in the finest
+    // kernel of the cycle before it unless DMG_NO_FUSED_RESIDUAL=1 (then the
+    // residual kernel runs after it, as for the first evaluation)
+    const char* nr = getenv("DMG_NO_FUSED_RESIDUAL");
+    P.res = P.oop && !(nr && nr[0] == '1');
     for (int k = 0; k < 2; k++)
         if (hipEventCreateWithFlags(&P.ev[k], hipEventDisableTiming) != hipSuccess) return MG_ERR_HIP;
     if (hipEventCreateWithFlags(&P.evu, hipEventDisableTiming) != hipSuccess) return MG_ERR_HIP;

@@ -48,6 +48,7 @@ struct Plan2 {
     Timing tm;
     hipGraphExec_t gexec = nullptr;
     bool gready = false, use_graph = true;
+    bool res = false;   // out of place: the finest kernel also forms the next residual
     hipStream_t cap = nullptr;
     // bound by plan2_bind_static: no pinned host memory, events or graph; the
     // tables are written by stream-ordered kernels

@@ -40,6 +40,30 @@ struct alignas(sizeof(T)) P2 {
     T x, y;
 };
 
+// Neighbour-lane reads as DPP moves across the whole wave (wave_shr:1 and
+// wave_shl:1 of the GFX9 DPP controls): lane i takes lane i-1's value
+// (lane_up) or lane i+1's (lane_down), and lane 0, resp. lane 63, reads 0
+// (bound_ctrl).  One VALU move instead of an LDS permute: no LDS round trip
+// in the dependent chains of the row kernels.  The kernels that use them
+// never take a value at lane 0 or 63 that came from beyond the wave (their
+// halo lanes).
+constexpr int kDppWaveShl1 = 0x130, kDppWaveShr1 = 0x138;
+template <int CTRL>
+__device__ inline float lane_dpp(float x)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL>
+__device__ inline double lane_dpp(double x)
+{
+    return __hiloint2double(__builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, true),
+                            __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, true));
+}
+template <typename T>
+__device__ inline T lane_up(T x) { return lane_dpp<kDppWaveShr1>(x); }
+template <typename T>
+__device__ inline T lane_down(T x) { return lane_dpp<kDppWaveShl1>(x); }
+
 // Sum over the block (fixed order: wave shuffle tree, then waves in order).
 __device__ inline double rows_block_sum(double x)
 {
@@ -85,6 +109,26 @@ __device__ inline void static_for(F&& f)
     if constexpr (I < N) {
         f(Int<I>{});
         static_for<I + 1, N>(f);
+    }
+}
+
+// rows_march<1> over jbeg (even), jbeg+1, ... <= jlast with the row's parity
+// as a compile-time argument (Int<0> or Int<1>) of load and proc: even and
+// odd rows keep buffers of their own, so that what one parity never loads
+// folds away.
+template <typename Ck, typename Load, typename Proc>
+__device__ inline void rows_march_parity(int jbeg, int jlast, Load&& load, Proc&& proc)
+{
+    Ck E, O;
+    int jj = jbeg;
+    load(Int<0>{}, jj, E);
+    while (true) {
+        load(Int<1>{}, jj + 1, O);
+        proc(Int<0>{}, jj, E);
+        if (++jj > jlast) break;
+        load(Int<0>{}, jj + 1, E);
+        proc(Int<1>{}, jj, O);
+        if (++jj > jlast) break;
     }
 }
 

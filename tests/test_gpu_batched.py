@@ -58,7 +58,9 @@ def test_batched_equals_single_bitwise(dmg):
         st1, c1, r1, h1 = S.solve(u1, dev(f), rtol=1e-10, max_cycles=40)
         assert st1 == dmg.MG_OK and c1 == cyc[i]
         assert torch.equal(u1, us[i]), i
-        assert r1 == rr[i]
+        # a single FP64 problem sums its residual norm in the finest kernel's
+        # blocks: the same squares, added in another order
+        assert r1 == pytest.approx(rr[i], rel=1e-12)
 
 
 def test_batched_fp64_matches_oracle(dmg, orc):
@@ -159,5 +161,5 @@ def test_paired_levels_equal_per_level_bitwise(dmg):
     S = dmg.Solver(2, 2048, p=(1.052,))
     u1 = dev(np.zeros_like(fs[0]))
     st1, c1, r1, h1 = S.solve(u1, dev(fs[0]), rtol=1e-10, max_cycles=40)
-    assert st1 == dmg.MG_OK and c1 == cyc[0] and r1 == rr[0]
+    assert st1 == dmg.MG_OK and c1 == cyc[0] and r1 == pytest.approx(rr[0], rel=1e-12)
     assert torch.equal(u1, us[0])

@@ -5,12 +5,20 @@ storing it.
 
 * u after 1 .. 5 cycles (odd counts end in the second buffer and are copied
   back) is bitwise equal to the in-place path's (a batch of two copies of the
-  problem: per-level launches, residual stored), with the same relative
-  residuals, for grids whose strips and bands leave ragged edges;
+  problem: per-level launches, residual stored), for grids whose strips and
+  bands leave ragged edges; the finest kernel also forms the next
+  evaluation's residual and its restriction (bitwise the residual kernel's,
+  or u would differ after the next cycle) and the norm partials, whose sum
+  matches to rounding (another order of the same squares);
 * nonzero Dirichlet values in u's boundary are used and left untouched;
 * after such a solve the finest residual is not available from
-  mg_level_get until the next mg_vcycle.
+  mg_level_get until the next mg_vcycle;
+* the residual formed in the finest kernel gives the iterates of the
+  residual kernel (DMG_NO_FUSED_RESIDUAL=1) to the bit, the same cycle count
+  and the same residual history to rounding.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -39,7 +47,7 @@ def start(n, seed):
     return u, f
 
 
-@pytest.mark.parametrize("n", [256, 512, 1024])
+@pytest.mark.parametrize("n", [256, 512, 1024, 2048, 4096])
 def test_out_of_place_equals_in_place_bitwise(dmg, n):
     u0, f = start(n, 60 + n)
     fd = dev(f)
@@ -52,7 +60,7 @@ def test_out_of_place_equals_in_place_bitwise(dmg, n):
         ub = [dev(u0), dev(u0)]
         st2, c2, r2, s2 = B.solve(ub, [fd, fd], rtol=0.0, max_cycles=k)
         assert st1 == dmg.MG_ERR_NOT_CONVERGED and c1 == k and c2 == [k, k]
-        assert r1 == r2[0] == r2[1]
+        assert r2[0] == r2[1] and r1 == pytest.approx(r2[0], rel=1e-12)
         assert torch.equal(u1, ub[0]) and torch.equal(u1, ub[1]), k
         b = u1.cpu().numpy()
         assert np.array_equal(b[0], u0[0]) and np.array_equal(b[-1], u0[-1])
@@ -101,6 +109,30 @@ def test_out_of_place_edge_cases(dmg):
     B = dmg.BatchSolver([n, n], precision=dmg.MG_FP64)
     ub = [dev(u0), dev(u0)]
     st2, c2, r2, s2 = B.solve(ub, [dev(f), dev(f)], rtol=1e-10, max_cycles=40)
-    assert st1 == dmg.MG_OK and c2 == [c1, c1] and r2[0] == r1
+    assert st1 == dmg.MG_OK and c2 == [c1, c1] and r1 == pytest.approx(r2[0], rel=1e-12)
     assert torch.equal(u1, ub[0])
     S.close()
+
+
+@pytest.mark.parametrize("n", [128, 1024, 4096])
+def test_fused_residual_equals_residual_kernel(dmg, n):
+    u0, f = start(n, 90 + n)
+    fd = dev(f)
+    S = dmg.Solver(2, n, p=(1.052,))
+    os.environ["DMG_NO_FUSED_RESIDUAL"] = "1"
+    try:
+        Sr = dmg.Solver(2, n, p=(1.052,))
+    finally:
+        del os.environ["DMG_NO_FUSED_RESIDUAL"]
+    for k in (1, 2, 3, 40):
+        print("fused residual n=%d max_cycles=%d" % (n, k), flush=True)
+        rtol = 0.0 if k < 40 else 1e-10
+        u1, u2 = dev(u0), dev(u0)
+        st1, c1, r1, h1 = S.solve(u1, fd, rtol=rtol, max_cycles=k)
+        st2, c2, r2, h2 = Sr.solve(u2, fd, rtol=rtol, max_cycles=k)
+        assert st1 == st2 and c1 == c2
+        assert r1 == pytest.approx(r2, rel=1e-12)
+        np.testing.assert_allclose(h1, h2, rtol=1e-12, atol=0)
+        assert torch.equal(u1, u2), k
+    S.close()
+    Sr.close()

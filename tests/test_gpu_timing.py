@@ -3,8 +3,9 @@ bench.py's roofline figure.
 
 * every family that a 2D solve launches reports launches, a positive
   duration and the algorithmic bytes of those launches;
-* the finest family's bytes per launch are the fused kernel's (r0, v2,
-  u read, u written) at the sizes where that kernel runs;
+* the finest family's bytes per launch are the out-of-place kernel's (f,
+  v2 and the previous iterate read; the new iterate and the next
+  evaluation's restricted residual written) at the sizes where it runs;
 * summed kernel time stays below the solve's wall time, and timing does not
   change the result.
 """
@@ -26,11 +27,13 @@ def dmg():
 
 
 def fused_finest_bytes(n, es=8):
-    """r0 and u read, u written at the interior points, the correction of the
-    level below the first diagonal level read; the diagonal level's residual
-    is restricted inside the kernel, not read"""
+    """A single FP64 problem's out-of-place step: f and the previous iterate
+    read, the new one written at the interior points, the correction of the
+    level below the first diagonal level read (the diagonal level's residual
+    is restricted inside the kernel, not read), and the next evaluation's
+    residual restricted onto that lower level written ((n/2 - 1)^2 points)"""
     inter, M = (n - 1) ** 2, n // 2
-    return es * (inter + (M + 1) ** 2) + 16 * inter
+    return es * (inter + (M + 1) ** 2) + 16 * inter + es * (M - 1) ** 2
 
 
 @pytest.mark.parametrize("n", [64, 512])
