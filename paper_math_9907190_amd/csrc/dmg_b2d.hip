@@ -83,10 +83,11 @@ template <typename T, int CH, bool NT, bool FZ, bool M4, bool WF, bool MIR>
 __device__ inline void resid_body(int m, double inv_h2, const Fin2<T>& it, const double* __restrict__ u, bool st0,
                                   int wv, int nwx, int rows, double& acc, double& accf)
 {
-    const double* __restrict__ f = it.f;
-    T* __restrict__ r0 = it.r0;
-    T* __restrict__ rD = it.r1;
-    T* __restrict__ rA2 = it.r2;
+    const auto f = gmem(it.f);
+    const auto r0 = gmem(it.r0);
+    const auto rD = gmem(it.r1);
+    const auto rA2 = gmem(it.r2);
+    const auto ug = gmem(u);
     const int lane = threadIdx.x & 63;
     const int wx = wv % nwx, sy = wv / nwx;
     const int t = wx * kResidPairs - 1 + lane;
@@ -107,15 +108,15 @@ __device__ inline void resid_body(int m, double inv_h2, const Fin2<T>& it, const
     auto ldu = [&](int j, double& x, double& y) {
         x = y = 0;
         if (!colok || j < 0 || j > m) return;
-        const double* p = u + (size_t)R(j) * w + 2 * t;
-        if (t < m / 2) { P2<double> v = *reinterpret_cast<const P2<double>*>(p); x = v.x; y = v.y; }
+        const auto p = ug + (size_t)R(j) * w + 2 * t;
+        if (t < m / 2) { P2<double> v = ld_pair(p); x = v.x; y = v.y; }
         else x = p[0];
     };
     auto ldf = [&](int j, double& x, double& y) {
         x = y = 0;
         if (!colok || j < 1 || j > m - 1) return;
-        const double* q = f + (size_t)R(j) * w + 2 * t;
-        P2<double> v = NT ? ld_pair_nt(q) : *reinterpret_cast<const P2<double>*>(q);
+        const auto q = f + (size_t)R(j) * w + 2 * t;
+        P2<double> v = NT ? ld_pair_nt(q) : ld_pair(q);
         x = v.x; y = v.y;
     };
     struct Ck { double ux[CH], uy[CH], fx[CH], fy[CH]; };
@@ -163,11 +164,11 @@ __device__ inline void resid_body(int m, double inv_h2, const Fin2<T>& it, const
             T r0j = (rowin && c0) ? (T)x0 : T(0);
             T r1j = (rowin && c1) ? (T)x1 : T(0);
             if (j >= y0 && j < y1 && useful) {
-                T* p = r0 + (size_t)R(j) * w + 2 * t;
+                const auto p = r0 + (size_t)R(j) * w + 2 * t;
                 if (c0 && c1) {
                     if (st0) {
                         if (NT) st_pair_nt(p, r0j, r1j);
-                        else *reinterpret_cast<P2<T>*>(p) = P2<T>{r0j, r1j};
+                        else st_pair(p, r0j, r1j);
                     }
                     acc += x0 * x0 + x1 * x1;
                     if constexpr (WF) accf += c.fx[i] * c.fx[i] + c.fy[i] * c.fy[i];
@@ -487,13 +488,17 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
     const bool colok = t >= 0 && t <= h;
     const bool c0 = t >= 1 && 2 * t <= m - 1, c1 = t >= 0 && 2 * t + 1 <= m - 1;
     const size_t w = (size_t)(m + 1);
-    auto ld2 = [&](int B) -> T { return (colok && B >= 0 && B <= h) ? v2[(size_t)RB(B) * W + t] : T(0); };
+    const auto rAg = gmem(rA), v2g = gmem(v2);
+    const auto ucg = gmem(uc), frg = gmem(fr);
+    const auto vAg = gmem(vA), rA2g = gmem(rA2);
+    const auto ug = gmem(u);
+    auto ld2 = [&](int B) -> T { return (colok && B >= 0 && B <= h) ? v2g[(size_t)RB(B) * W + t] : T(0); };
     // pair of an interior row: column m+1 is the next row's column 0 and never used
     auto ldR = [&](int j, T& x, T& y) {
         x = y = 0;
         if (!colok || j < 1 || j > m - 1) return;
-        const T* p = rA + (size_t)R(j) * w + 2 * t;
-        P2<T> v = (FINEST && NT) ? ld_pair_nt(p) : *reinterpret_cast<const P2<T>*>(p);
+        const auto p = rAg + (size_t)R(j) * w + 2 * t;
+        P2<T> v = (FINEST && NT) ? ld_pair_nt(p) : ld_pair(p);
         x = c0 ? v.x : T(0);
         y = c1 ? v.y : T(0);
     };
@@ -530,9 +535,9 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
     auto ldU = [&](int k, double& x, double& y, double& e) {
         x = y = e = 0;
         if (!colok || k < 0 || k > m) return;
-        const double* p = uc + (size_t)R(k) * w + 2 * t;
+        const auto p = ucg + (size_t)R(k) * w + 2 * t;
         if (t < h) {
-            P2<double> v = NT ? ld_pair_nt(p) : *reinterpret_cast<const P2<double>*>(p);
+            P2<double> v = NT ? ld_pair_nt(p) : ld_pair(p);
             x = v.x;
             y = v.y;
         } else {
@@ -544,8 +549,8 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
     auto ldF = [&](int k, double& x, double& y) {
         x = y = 0;
         if (!colok || k < 1 || k > m - 1) return;
-        const double* q = fr + (size_t)R(k) * w + 2 * t;
-        P2<double> v = NT ? ld_pair_nt(q) : *reinterpret_cast<const P2<double>*>(q);
+        const auto q = frg + (size_t)R(k) * w + 2 * t;
+        P2<double> v = NT ? ld_pair_nt(q) : ld_pair(q);
         x = v.x;
         y = v.y;
     };
@@ -576,6 +581,11 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
     // rows jj-1 .. jj+3 (w0 .. w4) entering an even one; eS: the outer column
     // of the next odd row jj' plus 2
     double w0x = 0, w0y = 0, w1x = 0, w1y = 0, w2x = 0, w2y = 0, w3x = 0, w3y = 0, w4x = 0, w4y = 0, eS = 0;
+    // RES: f pairs of rows jj-2 .. jj+2 (F0 .. F4) entering an even row jj,
+    // of rows jj-2 .. jj+1 (F0 .. F3) entering an odd one: the residual of the
+    // new iterate at row jj-2 takes f from F0, the pair the Jacobi's residual
+    // loaded four or five rows earlier (no second load of f)
+    double F0x = 0, F0y = 0, F1x = 0, F1y = 0, F2x = 0, F2y = 0, F3x = 0, F3y = 0, F4x = 0, F4y = 0;
     if constexpr (PP) {
         double ux_[8], uy_[8], ue_[8];
 #pragma unroll
@@ -587,6 +597,11 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
             ldF(j - 3 + i, fx, fy);
             r0row(j - 3 + i, ux_[i], uy_[i], ux_[i + 1], uy_[i + 1], ux_[i + 2], uy_[i + 2], ue_[i + 1], fx, fy, rx_[i],
                   ry_[i]);
+            if (i == 1) { F0x = fx; F0y = fy; }
+            if (i == 2) { F1x = fx; F1y = fy; }
+            if (i == 3) { F2x = fx; F2y = fy; }
+            if (i == 4) { F3x = fx; F3y = fy; }
+            if (i == 5) { F4x = fx; F4y = fy; }
         }
         a0x = rx_[0]; a0y = ry_[0];
         a1x = rx_[1]; a1y = ry_[1];
@@ -649,7 +664,7 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
         c.u3x = c.u3y = c.u4x = c.u4y = c.e3 = c.e4 = c.f2x = c.f2y = c.f3x = c.f3y = 0;
         if (jj > y1) return;
         if (FINEST && useful && jj >= y0 && jj < y1 && (c0 || c1)) {
-            P2<double> v = *reinterpret_cast<const P2<double>*>(u + (size_t)R(jj) * w + 2 * t);
+            P2<double> v = ld_pair(ug + (size_t)R(jj) * w + 2 * t);
             c.ux = v.x;
             c.uy = v.y;
         }
@@ -668,8 +683,6 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
     T rm1_0 = 0, rm1_1 = 0, rm2_0 = 0, rm2_1 = 0, d3 = 0, d2 = 0;
     double acc = 0;
     const bool useful2 = useful && t >= 1 && t <= h - 1;
-    double gfx = 0, gfy = 0;   // f of the next residual row, loaded one row ahead
-    if constexpr (RES) ldF(jstart, gfx, gfy);
     auto proc = [&](auto Pc, int jj, const Ck& c) {
         constexpr int P = decltype(Pc)::value;   // jj & 1
         if (jj > jend) return;
@@ -721,8 +734,7 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
                 const double npx = (rin && c0) ? ox + (double)vx : ox, npy = (rin && c1) ? oy + (double)vy : oy;
                 const int k = jj - 2;   // its residual row: u' rows k-1 (q_m), k (q_c), k+1 (np)
                 if (k >= jstart && k <= ylast) {
-                    const double fx = gfx, fy = gfy;
-                    ldF(k + 1, gfx, gfy);
+                    const double fx = F0x, fy = F0y;
                     const double uW = lane_up(qcy), uE = lane_down(qcx);
                     const bool rowin = k >= 1 && k <= m - 1;
                     double x0 = 0, x1 = 0;
@@ -753,7 +765,7 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
                             const int B = (k - 2) >> 1;
                             const T d3w = lane_up(d3), d1w = lane_up(d1);
                             if (useful2 && B >= 1 && B <= h - 1)
-                                rA2[(size_t)(MIR ? h - B : B) * (h + 1) + t] =
+                                rA2g[(size_t)(MIR ? h - B : B) * (h + 1) + t] =
                                     MIR ? rs2_core(d2, d1w, d1, d3, d3w) : rs2_core(d2, d3w, d3, d1, d1w);
                         }
                         d3 = d2;
@@ -771,13 +783,13 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
             }
             if (useful && (!RES || jj - 1 < y1) && jj - 1 >= y0) {
                 if constexpr (FINEST) {
-                    if (c0 && c1) *reinterpret_cast<P2<double>*>(u + o) = P2<double>{ox + (double)vx, oy + (double)vy};
-                    else if (c1) u[o + 1] = oy + (double)vy;
-                    else if (c0) u[o] = ox + (double)vx;
+                    if (c0 && c1) st_pair(ug + o, ox + (double)vx, oy + (double)vy);
+                    else if (c1) ug[o + 1] = oy + (double)vy;
+                    else if (c0) ug[o] = ox + (double)vx;
                 } else {
-                    if (c0 && c1) *reinterpret_cast<P2<T>*>(vA + o) = P2<T>{vx, vy};
-                    else if (c1) vA[o + 1] = vy;
-                    else if (c0) vA[o] = vx;
+                    if (c0 && c1) st_pair(vAg + o, vx, vy);
+                    else if (c1) vAg[o + 1] = vy;
+                    else if (c0) vAg[o] = vx;
                 }
             }
         }
@@ -810,6 +822,17 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
                 eS = c.e4;
             } else {
                 w3x = w4x; w3y = w4y;
+            }
+        }
+        if constexpr (RES) {   // and f
+            F0x = F1x; F0y = F1y;
+            F1x = F2x; F1y = F2y;
+            F2x = F3x; F2y = F3y;
+            if constexpr (P) {
+                F3x = c.f2x; F3y = c.f2y;
+                F4x = c.f3x; F4y = c.f3y;
+            } else {
+                F3x = F4x; F3y = F4y;
             }
         }
     };
@@ -981,8 +1004,8 @@ __global__ void __launch_bounds__(kRowBlock) kb_rs_pair(int m, const RsPair2<T>*
 {
     const RsPair2<T> it = items[blockIdx.y];
     ITEM_GATE(ctls, it.prob);
-    const T* __restrict__ rA = it.rA;
-    T* __restrict__ rA2 = it.r2;
+    const auto rA = gmem(it.rA);
+    const auto rA2 = gmem(it.r2);
     const int lane = threadIdx.x & 63;
     const int wv = rows_wave_id(nwaves);
     if (wv >= nwaves) return;
@@ -998,7 +1021,7 @@ __global__ void __launch_bounds__(kRowBlock) kb_rs_pair(int m, const RsPair2<T>*
     auto ldr = [&](int j, T& x, T& y) {
         x = y = 0;
         if (!colok || j < 1 || j > m - 1) return;
-        P2<T> v = *reinterpret_cast<const P2<T>*>(rA + (size_t)j * w + 2 * t);
+        P2<T> v = ld_pair(rA + (size_t)j * w + 2 * t);
         x = c0 ? v.x : T(0);
         y = c1 ? v.y : T(0);
     };
@@ -1020,7 +1043,7 @@ __global__ void __launch_bounds__(kRowBlock) kb_rs_pair(int m, const RsPair2<T>*
             const int j = jb + i;
             if (j > y1) break;
             const int q = j & 1;
-            const T sh = q ? __shfl_down(rc0, 1) : __shfl_up(rc1, 1);
+            const T sh = q ? lane_down(rc0) : lane_up(rc1);
             const T rc = q ? rc1 : rc0;
             const T rw = q ? rc0 : sh;
             const T re = q ? sh : rc1;
@@ -1030,7 +1053,7 @@ __global__ void __launch_bounds__(kRowBlock) kb_rs_pair(int m, const RsPair2<T>*
             // axis point (t, B) of level L-2, B = (j-1)/2: diagonal rows 2B-1, 2B, 2B+1
             if (q && j - 1 >= y0 && j - 1 < y1) {
                 const int B = (j - 1) >> 1;
-                const T d3w = __shfl_up(d3, 1), d1w = __shfl_up(d1, 1);
+                const T d3w = lane_up(d3), d1w = lane_up(d1);
                 if (useful2 && B >= 1 && B <= mc - 1) rA2[(size_t)B * (mc + 1) + t] = rs2_core(d2, d3w, d3, d1, d1w);
             }
             d3 = d2;

@@ -132,6 +132,36 @@ __device__ inline void rows_march_parity(int jbeg, int jlast, Load&& load, Proc&
     }
 }
 
+// Global-memory views.  Pointers that reach a kernel through an item table
+// in memory are generic addresses, which the compiler can only access with
+// FLAT instructions; those count against both the vector-memory and the LDS
+// counters and may complete out of order, so every wait for one load is a
+// wait for all of them (vmcnt(0) lgkmcnt(0)), and a row kernel's loads of
+// the next rows are never in flight during the current row's arithmetic.
+// Accesses through gmem() pointers are global loads and stores: they count
+// in order and a wait covers only the load it needs.
+#define DMG_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ inline DMG_GLOBAL T* gmem(T* p)
+{
+    return (DMG_GLOBAL T*)p;
+}
+// a pair as one vector access (element-aligned, like P2)
+template <typename T>
+__device__ inline P2<T> ld_pair(const DMG_GLOBAL T* p)
+{
+    typedef T V __attribute__((ext_vector_type(2), aligned(sizeof(T))));
+    const V v = *(const DMG_GLOBAL V*)p;
+    return P2<T>{v.x, v.y};
+}
+template <typename T>
+__device__ inline void st_pair(DMG_GLOBAL T* p, T x, T y)
+{
+    typedef T V __attribute__((ext_vector_type(2), aligned(sizeof(T))));
+    const V v = {x, y};
+    *(DMG_GLOBAL V*)p = v;
+}
+
 // Streaming pair accesses for arrays that are not reused before the cache
 // would evict them anyway (f, and r0 between the residual and the finest
 // Jacobi): non-temporal hints keep them from displacing u and the level
@@ -149,6 +179,20 @@ __device__ inline void st_pair_nt(T* p, T x, T y)
     typedef T V __attribute__((ext_vector_type(2)));
     V v = {x, y};
     __builtin_nontemporal_store(v, reinterpret_cast<V*>(p));
+}
+template <typename T>
+__device__ inline P2<T> ld_pair_nt(const DMG_GLOBAL T* p)
+{
+    typedef T V __attribute__((ext_vector_type(2)));
+    V v = __builtin_nontemporal_load((const DMG_GLOBAL V*)p);
+    return P2<T>{v.x, v.y};
+}
+template <typename T>
+__device__ inline void st_pair_nt(DMG_GLOBAL T* p, T x, T y)
+{
+    typedef T V __attribute__((ext_vector_type(2)));
+    V v = {x, y};
+    __builtin_nontemporal_store(v, (DMG_GLOBAL V*)p);
 }
 
 }  // namespace dmg
