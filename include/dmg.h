@@ -351,8 +351,11 @@ const char *mg_strerror(int code);
  *
  * The array holds MG_STATIC_SCRATCH_BYTES (64 MiB) on every device the
  * library runs on, from the first call there until the process ends.
- * Problems whose workspace (mg_workspace_bytes) is larger return
- * MG_ERR_SCRATCH and enqueue nothing; 64 MiB covers 2D n <= 1024 in every
+ * Problems whose workspace is larger return MG_ERR_SCRATCH and enqueue
+ * nothing.  That workspace is mg_workspace_bytes, except for 2D
+ * MG_FP32_REFINED, where it is (n+1)^2 * 4 bytes less: the cycle here runs
+ * in place, without the second double iterate of mg_solve's out-of-place
+ * cycles; 64 MiB covers 2D n <= 1024 in every
  * precision (n = 2048 with single-precision levels) and 3D n <= 128
  * (second-order residual).  Every call on one device uses the same array
  * and leaves its contents behind; the next call zeroes it first.  Calls

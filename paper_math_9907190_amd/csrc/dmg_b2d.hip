@@ -855,11 +855,14 @@ __global__ void __launch_bounds__(kRowBlock) kb_finest_fused(int m, T cc, T cd, 
 // Out-of-place solve step (one FP64 problem): cycle k (the control block's
 // count when the cycle runs) reads the iterate of cycle k-1 and writes that of
 // cycle k; even k live in u, odd k in ub.
-__global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(4))) kb_finest_oop(int m, double cc, double cd,
-                                                           const Fin2<double>* __restrict__ items, int nwx,
+// (T: the type of the levels and the correction; FP32-refined solves use
+// float, the residual and the iterate staying double)
+template <typename T>
+__global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(4))) kb_finest_oop(int m, T cc, T cd,
+                                                           const Fin2<T>* __restrict__ items, int nwx,
                                                            int nwaves, int rows, const Ctl* __restrict__ ctls)
 {
-    const Fin2<double> it = items[blockIdx.y];
+    const Fin2<T> it = items[blockIdx.y];
     ITEM_GATE(ctls, it.prob);
     const int wv = rows_wave_id(nwaves);
     if (wv >= nwaves) return;
@@ -867,21 +870,22 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
     const double* uc = odd ? it.u : it.ub;
     double* un = odd ? it.ub : it.u;
     if ((wv / nwx) & 1)
-        fused_body<double, true, false, true, true>(m, cc, cd, nullptr, it.v2, nullptr, un, wv, nwx, rows, uc, it.f);
+        fused_body<T, true, false, true, true>(m, cc, cd, nullptr, it.v2, nullptr, un, wv, nwx, rows, uc, it.f);
     else
-        fused_body<double, true, false, false, true>(m, cc, cd, nullptr, it.v2, nullptr, un, wv, nwx, rows, uc, it.f);
+        fused_body<T, true, false, false, true>(m, cc, cd, nullptr, it.v2, nullptr, un, wv, nwx, rows, uc, it.f);
 }
 
 // The same step, which also evaluates the new iterate (the residual kernel's
 // work for the next evaluation, see RES above): each block's norm partial
 // goes to part[blockIdx.x], and block 0 clears part[gridDim.x .. nparts), so
 // the finalize kernel sums as many partials as after the residual kernel.
-__global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(3))) kb_finest_res(int m, double cc, double cd,
-                                                           const Fin2<double>* __restrict__ items, int nwx,
+template <typename T>
+__global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(3))) kb_finest_res(int m, T cc, T cd,
+                                                           const Fin2<T>* __restrict__ items, int nwx,
                                                            int nwaves, int rows, const Ctl* __restrict__ ctls,
                                                            int nparts)
 {
-    const Fin2<double> it = items[blockIdx.y];
+    const Fin2<T> it = items[blockIdx.y];
     ITEM_GATE(ctls, it.prob);
     const int wv = rows_wave_id(nwaves);
     const bool odd = ctls[it.prob].k & 1;
@@ -890,11 +894,11 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
     double acc = 0;
     if (wv < nwaves) {   // no early return: the block sum below synchronises the block
         if ((wv / nwx) & 1)
-            acc = fused_body<double, true, false, true, true, true>(m, cc, cd, nullptr, it.v2, nullptr, un, wv, nwx,
-                                                                    rows, uc, it.f, it.r2);
+            acc = fused_body<T, true, false, true, true, true>(m, cc, cd, nullptr, it.v2, nullptr, un, wv, nwx, rows,
+                                                               uc, it.f, it.r2);
         else
-            acc = fused_body<double, true, false, false, true, true>(m, cc, cd, nullptr, it.v2, nullptr, un, wv, nwx,
-                                                                     rows, uc, it.f, it.r2);
+            acc = fused_body<T, true, false, false, true, true>(m, cc, cd, nullptr, it.v2, nullptr, un, wv, nwx, rows,
+                                                                uc, it.f, it.r2);
     }
     const double sum = rows_block_sum(acc);
     if (threadIdx.x == 0) it.part[blockIdx.x] = sum;
@@ -2103,7 +2107,7 @@ void launch_b_resid(int n, int fused, int order, const Fin2<T>* items, int nitem
     // rows is a power of two >= 4: every strip starts on an odd row
     int rows = pick_rows(n / 2 + 1, kResidPairs, n - 1, kTargetWavesResid);
     rows_grid(n / 2 + 1, kResidPairs, n - 1, rows, nwx, nw, nb);
-    const int pp = oop && fused && n >= 8 && !m4 && sizeof(T) == 8 ? 1 : 0;
+    const int pp = oop && fused && n >= 8 && !m4 ? 1 : 0;
     auto go = [&](auto kern) {
         launch_timed(kern, dim3(nb, nitems), dim3(kRowBlock), s, n, inv_h2, items, nwx, nw, rows, ctls, pp);
     };
@@ -2137,20 +2141,17 @@ void launch_b_finest(int n, T c, T c1, int fused, const Fin2<T>* items, int nite
         return;
     }
     int nwx, nw, nb;
-    if constexpr (sizeof(T) == 8) {
-        if (fused && oop && nitems == 1) {
-            auto go = [&](auto kern) {
-                const int rows = fill_rows((const void*)kern, n / 2 + 1, kFusePairs, n - 1);
-                rows_grid(n / 2 + 1, kFusePairs, n - 1, rows, nwx, nw, nb);
-                launch_timed(kern, dim3(nb, 1), dim3(kRowBlock), s, n, (double)c, (double)c1,
-                             reinterpret_cast<const Fin2<double>*>(items), nwx, nw, rows, ctls);
-            };
-            // plain loads: the iterate and f rows a strip shares with its
-            // neighbour are then still in L2 when the neighbour reads them
-            // (non-temporal ones measured 485.7 against 467.4 MB per launch)
-            go(kb_finest_oop);
-            return;
-        }
+    if (fused && oop && nitems == 1) {
+        auto go = [&](auto kern) {
+            const int rows = fill_rows((const void*)kern, n / 2 + 1, kFusePairs, n - 1);
+            rows_grid(n / 2 + 1, kFusePairs, n - 1, rows, nwx, nw, nb);
+            launch_timed(kern, dim3(nb, 1), dim3(kRowBlock), s, n, c, c1, items, nwx, nw, rows, ctls);
+        };
+        // plain loads: the iterate and f rows a strip shares with its
+        // neighbour are then still in L2 when the neighbour reads them
+        // (non-temporal ones measured 485.7 against 467.4 MB per launch)
+        go(kb_finest_oop<T>);
+        return;
     }
     if (fused) {
         auto go = [&](auto kern) {
@@ -2174,27 +2175,29 @@ void launch_b_finest(int n, T c, T c1, int fused, const Fin2<T>* items, int nite
 }
 
 // the grid of kb_finest_res: one round of waves, strips of even length
+template <typename T>
 static void finest_res_grid(int n, int& rows, int& nwx, int& nw, int& nb)
 {
-    rows = fill_rows((const void*)kb_finest_res, n / 2 + 1, kResPairs, n - 1);
+    rows = fill_rows((const void*)kb_finest_res<T>, n / 2 + 1, kResPairs, n - 1);
     rows += rows & 1;
     rows_grid(n / 2 + 1, kResPairs, n - 1, rows, nwx, nw, nb);
 }
 
+template <typename T>
 bool b_finest_res_fits(int n, int nparts)
 {
     if (n < 8) return false;
     int rows, nwx, nw, nb;
-    finest_res_grid(n, rows, nwx, nw, nb);
+    finest_res_grid<T>(n, rows, nwx, nw, nb);
     return nb <= nparts;
 }
 
-void launch_b_finest_res(int n, double c, double c1, const Fin2<double>* items, const Ctl* ctls, int nparts,
-                         hipStream_t s)
+template <typename T>
+void launch_b_finest_res(int n, T c, T c1, const Fin2<T>* items, const Ctl* ctls, int nparts, hipStream_t s)
 {
     int rows, nwx, nw, nb;
-    finest_res_grid(n, rows, nwx, nw, nb);
-    launch_timed(kb_finest_res, dim3(nb, 1), dim3(kRowBlock), s, n, c, c1, items, nwx, nw, rows, ctls, nparts);
+    finest_res_grid<T>(n, rows, nwx, nw, nb);
+    launch_timed(kb_finest_res<T>, dim3(nb, 1), dim3(kRowBlock), s, n, c, c1, items, nwx, nw, rows, ctls, nparts);
 }
 
 template <typename T>
@@ -2314,6 +2317,8 @@ void launch_b_coarse_net(const LevInfo<T>* lev, const Coarse2B<T>* items, int ni
     template void launch_b_resid<T>(int, int, int, const Fin2<T>*, int, const Ctl*, hipStream_t, int, int);                   \
     template void launch_b_sumsq<T>(int, const Fin2<T>*, int, const Ctl*, hipStream_t);                        \
     template void launch_b_finest<T>(int, T, T, int, const Fin2<T>*, int, const Ctl*, hipStream_t, int);          \
+    template bool b_finest_res_fits<T>(int, int);                                                              \
+    template void launch_b_finest_res<T>(int, T, T, const Fin2<T>*, const Ctl*, int, hipStream_t);            \
     template void launch_b_restrict<T>(int, int, int, const Item2<T>*, int, const Ctl*, hipStream_t);          \
     template void launch_b_jac_pair<T>(int, T, T, const JPair2<T>*, int, const Ctl*, hipStream_t);              \
     template void launch_b_rs_pair<T>(int, const RsPair2<T>*, int, const Ctl*, hipStream_t);                    \

@@ -94,15 +94,16 @@ int b_resid_parts(int n);
 template <typename T>
 void launch_b_finest(int n, T c, T c1, int fused, const Fin2<T>* items, int nitems, const Ctl* ctls, hipStream_t s,
                      int oop = 0);
-// The out-of-place step (one FP64 problem, fused, n >= 8) that also forms
+// The out-of-place step (one problem, fused, n >= 8) that also forms
 // the residual of the iterate it writes, its norm partials (nparts of them,
 // as the residual kernel's) and its restriction onto the level below the
 // first diagonal one, as the residual kernel would for the next evaluation.
 // b_finest_res_fits: whether its grid has at most nparts blocks (else the
 // separate residual kernel stays in use).
+template <typename T>
 bool b_finest_res_fits(int n, int nparts);
-void launch_b_finest_res(int n, double c, double c1, const Fin2<double>* items, const Ctl* ctls, int nparts,
-                         hipStream_t s);
+template <typename T>
+void launch_b_finest_res(int n, T c, T c1, const Fin2<T>* items, const Ctl* ctls, int nparts, hipStream_t s);
 // the boundary entries of an (n+1)^2 array: dst <- src (src null: zeros)
 void launch_b_copy_ring(int n, const double* src, double* dst, hipStream_t s);
 // end of an out-of-place solve (ctl: the problem's control block, done set)

@@ -73,7 +73,8 @@ int plan2_layout(Plan2& P, int nprob, const int* n, int prec, double p, bool all
     }
     P.lamc = 0;
     while (side_of(P.lamc + 1) <= kCoarseSide2) P.lamc++;
-    P.oop = allow_oop && nprob == 1 && prec == MG_FP64 && P.rorder == 2 && n[0] >= 8 && fin_fused(P.D[0], P.lamc);
+    P.oop = allow_oop && nprob == 1 && (prec == MG_FP64 || prec == MG_FP32_REFINED) && P.rorder == 2 && n[0] >= 8 &&
+            fin_fused(P.D[0], P.lamc);
     P.r0_stale = false;
     size_t es = prec == MG_FP64 ? 8 : 4;
     size_t off = 0;
@@ -144,7 +145,7 @@ int plan2_layout(Plan2& P, int nprob, const int* n, int prec, double p, bool all
         int i = ord[s];
         int m = n[i];
         size_t cnt = sizeA(m);
-        P.off_r0[i] = take(es * cnt);
+        P.off_r0[i] = take((P.oop ? sizeof(double) : es) * cnt);   // out of place: the second iterate
         int cls = (int)(std::lower_bound(P.cls_n.begin(), P.cls_n.end(), m) - P.cls_n.begin());
         P.off_part[i] = take(sizeof(double) * (size_t)P.nparts[cls]);
         P.off_partf[i] = take(sizeof(double) * (size_t)P.nparts[cls]);
@@ -458,15 +459,13 @@ bool enq_cycle(Plan2& P, Ctl* ctls, bool oop = false, bool res = false)
         const int D = 2 * (ilog2(n) - 1);
         const bool fz = fin_fused(D, P.lamc);
         double sh = 1.0 / n;
-        if constexpr (sizeof(T) == 8) {
-            if (res && oop && fz && P.cls_count[c] == 1 && b_finest_res_fits(n, P.nparts[c])) {
-                const double M = n / 2;
-                Timed t(&P.tm, MG_K_FINEST, bytes_finest(n, es, fz, oop) + es * (M - 1) * (M - 1), true);
-                launch_b_finest_res(n, P.p * sh * sh, coef(P, D - 1), fin_items<double>(P, (int)c), ctls, P.nparts[c],
-                                    P.stream);
-                formed = true;
-                continue;
-            }
+        if (res && oop && fz && P.cls_count[c] == 1 && b_finest_res_fits<T>(n, P.nparts[c])) {
+            const double M = n / 2;
+            Timed t(&P.tm, MG_K_FINEST, bytes_finest(n, es, fz, oop) + es * (M - 1) * (M - 1), true);
+            launch_b_finest_res<T>(n, (T)(P.p * sh * sh), (T)coef(P, D - 1), fin_items<T>(P, (int)c), ctls,
+                                   P.nparts[c], P.stream);
+            formed = true;
+            continue;
         }
         Timed t(&P.tm, MG_K_FINEST, bytes_finest(n, es, fz, oop) * P.cls_count[c], true);
         launch_b_finest<T>(n, (T)(P.p * sh * sh), (T)(fz ? coef(P, D - 1) : 0.0), fz ? 1 : 0, fin_items<T>(P, (int)c),
@@ -483,8 +482,10 @@ void enq_iteration(Plan2& P)
     if (P.prec == MG_FP64) {
         const bool formed = enq_cycle<double>(P, ctls, P.oop, P.res);
         enq_resid<double>(P, ctls, nact, false, P.oop, formed);
+    } else {
+        const bool formed = enq_cycle<float>(P, ctls, P.oop, P.res);
+        enq_resid<float>(P, ctls, nact, false, P.oop, formed);
     }
-    else { enq_cycle<float>(P, ctls); enq_resid<float>(P, ctls, nact); }
 }
 
 int build_graph(Plan2& P)
@@ -702,7 +703,7 @@ int plan2_solve(Plan2& P, double* const* u, const double* const* f, double rtol,
         enq_resid<double>(P, ctls, nact, true, P.oop);
     } else {
         enq_norm_f<float>(P, ctls, nact, true);
-        enq_resid<float>(P, ctls, nact, true);
+        enq_resid<float>(P, ctls, nact, true, P.oop);
     }
     if ((e = last_launch())) return e;
     // The active-problem count after evaluation it lands in host slot it & 1

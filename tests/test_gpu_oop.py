@@ -1,7 +1,7 @@
-"""Out-of-place 2D solves (a single FP64 second-order problem with the fused
-finest kernels): the cycles alternate the iterate between u and a second
-buffer and form the finest residual inside the finest kernel instead of
-storing it.
+"""Out-of-place 2D solves (a single second-order problem with the fused
+finest kernels, FP64 or FP32-refined): the cycles alternate the iterate
+between u and a second buffer and form the finest residual inside the
+finest kernel instead of storing it.
 
 * u after 1 .. 5 cycles (odd counts end in the second buffer and are copied
   back) is bitwise equal to the in-place path's (a batch of two copies of the
@@ -15,7 +15,9 @@ storing it.
   mg_level_get until the next mg_vcycle;
 * the residual formed in the finest kernel gives the iterates of the
   residual kernel (DMG_NO_FUSED_RESIDUAL=1) to the bit, the same cycle count
-  and the same residual history to rounding.
+  and the same residual history to rounding;
+* all of this also holds for FP32-refined solves (levels in float, the
+  residual, the iterate and the update in double).
 """
 import os
 
@@ -47,14 +49,16 @@ def start(n, seed):
     return u, f
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("n", [256, 512, 1024, 2048, 4096])
-def test_out_of_place_equals_in_place_bitwise(dmg, n):
+def test_out_of_place_equals_in_place_bitwise(dmg, n, prec):
+    pr = dmg.MG_FP64 if prec == "fp64" else dmg.MG_FP32_REFINED
     u0, f = start(n, 60 + n)
     fd = dev(f)
-    S = dmg.Solver(2, n, p=(1.052,))
-    B = dmg.BatchSolver([n, n], precision=dmg.MG_FP64)
+    S = dmg.Solver(2, n, precision=pr, p=(1.052,))
+    B = dmg.BatchSolver([n, n], precision=pr)
     for k in range(1, 6):
-        print("out of place n=%d cycles=%d" % (n, k), flush=True)
+        print("out of place %s n=%d cycles=%d" % (prec, n, k), flush=True)
         u1 = dev(u0)
         st1, c1, r1, h1 = S.solve(u1, fd, rtol=0.0, max_cycles=k)
         ub = [dev(u0), dev(u0)]
@@ -114,18 +118,20 @@ def test_out_of_place_edge_cases(dmg):
     S.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("n", [128, 1024, 4096])
-def test_fused_residual_equals_residual_kernel(dmg, n):
+def test_fused_residual_equals_residual_kernel(dmg, n, prec):
+    pr = dmg.MG_FP64 if prec == "fp64" else dmg.MG_FP32_REFINED
     u0, f = start(n, 90 + n)
     fd = dev(f)
-    S = dmg.Solver(2, n, p=(1.052,))
+    S = dmg.Solver(2, n, precision=pr, p=(1.052,))
     os.environ["DMG_NO_FUSED_RESIDUAL"] = "1"
     try:
-        Sr = dmg.Solver(2, n, p=(1.052,))
+        Sr = dmg.Solver(2, n, precision=pr, p=(1.052,))
     finally:
         del os.environ["DMG_NO_FUSED_RESIDUAL"]
     for k in (1, 2, 3, 40):
-        print("fused residual n=%d max_cycles=%d" % (n, k), flush=True)
+        print("fused residual %s n=%d max_cycles=%d" % (prec, n, k), flush=True)
         rtol = 0.0 if k < 40 else 1e-10
         u1, u2 = dev(u0), dev(u0)
         st1, c1, r1, h1 = S.solve(u1, fd, rtol=rtol, max_cycles=k)
