@@ -1041,13 +1041,18 @@ __global__ void __launch_bounds__(kRowBlock) kb_rs_pair(int m, const RsPair2<T>*
     ldr(y0 - 1, rm0, rm1);
     ldr(y0, rc0, rc1);
     T d3 = 0, d2 = 0;   // diagonal values of rows j-2, j-1
+    // the march starts on the strip's first row, which is odd (rows is a
+    // power of two), and CH is even: row jb + i has the parity of i + 1
+    static_assert(CH % 2 == 0, "row parities are fixed by the chunk position");
     auto proc = [&](int jb, const Ck& c) {
-#pragma unroll
-        for (int i = 0; i < CH; i++) {
+        static_for<0, CH>([&](auto I) {
+            constexpr int i = decltype(I)::value;
             const int j = jb + i;
-            if (j > y1) break;
-            const int q = j & 1;
-            const T sh = q ? lane_down(rc0) : lane_up(rc1);
+            if (j > y1) return;
+            constexpr int q = (i + 1) & 1;
+            T sh;
+            if constexpr (q) sh = lane_down(rc0);
+            else sh = lane_up(rc1);
             const T rc = q ? rc1 : rc0;
             const T rw = q ? rc0 : sh;
             const T re = q ? sh : rc1;
@@ -1063,7 +1068,7 @@ __global__ void __launch_bounds__(kRowBlock) kb_rs_pair(int m, const RsPair2<T>*
             d3 = d2;
             d2 = d1;
             rm0 = rc0; rm1 = rc1; rc0 = c.x[i]; rc1 = c.y[i];
-        }
+        });
     };
     rows_march<CH, Ck>(y0, y1, load, proc);
 }
