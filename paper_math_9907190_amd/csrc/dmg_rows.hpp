@@ -25,11 +25,16 @@ __device__ inline int xcd_block()
     return x * per + (x < rem ? x : rem) + b / kXcds;
 }
 
-// consecutive waves march neighbouring column bands of the same strip
+// consecutive waves march neighbouring column bands of the same strip.  The
+// id is the same in every lane of a wave, which the compiler cannot see from
+// threadIdx.x; reading it from the first lane makes it (and the strip, band
+// and row indices derived from it) scalar, so the per-row range checks of a
+// march are scalar compares and branches instead of vector compares and
+// execution-mask updates.
 __device__ inline int rows_wave_id(int nwaves)
 {
     (void)nwaves;
-    return xcd_block() * kWavesPerBlock + (threadIdx.x >> 6);
+    return __builtin_amdgcn_readfirstlane(xcd_block() * kWavesPerBlock + (int)(threadIdx.x >> 6));
 }
 
 // Two adjacent elements (columns 2t, 2t+1 of a row) moved as one access.
