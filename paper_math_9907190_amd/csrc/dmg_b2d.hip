@@ -462,7 +462,9 @@ constexpr int kFusePairs = 60;
 // Strips must start on odd rows (an even strip length), as in the residual
 // kernel.  Returns the lane's part of the squared norm.
 constexpr int kResPairs = 57;
-template <typename T, bool FINEST, bool NT, bool MIR, bool PP = false, bool RES = false>
+// INNER: every lane's column pair t lies in 1 .. m/2 - 1 (a band away from
+// both boundary columns), so every column check holds and folds away.
+template <typename T, bool FINEST, bool NT, bool MIR, bool PP = false, bool RES = false, bool INNER = false>
 __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA, const T* __restrict__ v2,
                                     T* __restrict__ vA, double* __restrict__ u, int wv, int nwx, int rows,
                                     const double* __restrict__ uc = nullptr, const double* __restrict__ fr = nullptr,
@@ -479,14 +481,14 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
     const int h = m / 2, W = h + 1;   // row length of v2 (side m/2)
     auto R = [&](int k) { return MIR ? m - k : k; };       // marched row -> grid row
     auto RB = [&](int B) { return MIR ? h - B : B; };      // the same on the level of side m/2
-    const bool useful = lane >= kLane0 && lane < kStride + kLane0 && t >= 0 && t <= h;
+    const bool useful = lane >= kLane0 && lane < kStride + kLane0 && (INNER || (t >= 0 && t <= h));
     // RES: the residual rows [jstart, ylast] and the first diagonal row dlo, as
     // the residual kernel takes them (strips start on odd grid rows); the march
     // rows [jbeg, jend]
     const int dlo = MIR ? y0 - 1 : y0, jstart = dlo - 1, ylast = MIR ? y1 : y1 + 1;
     const int jbeg = RES ? jstart - 2 : y0 - 1, jend = RES ? ylast + 2 : y1;
-    const bool colok = t >= 0 && t <= h;
-    const bool c0 = t >= 1 && 2 * t <= m - 1, c1 = t >= 0 && 2 * t + 1 <= m - 1;
+    const bool colok = INNER || (t >= 0 && t <= h);
+    const bool c0 = INNER || (t >= 1 && 2 * t <= m - 1), c1 = INNER || (t >= 0 && 2 * t + 1 <= m - 1);
     const size_t w = (size_t)(m + 1);
     const auto rAg = gmem(rA), v2g = gmem(v2);
     const auto ucg = gmem(uc), frg = gmem(fr);
@@ -519,13 +521,13 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
     // F point (2t+1, k), k odd, from v2 rows (k-1)/2 (vlo) and (k+1)/2 (vhi), as jac2_diagF
     auto f21 = [&](int k, T rF, T vlo, T vhi) -> T {
         const T vlo_e = lane_down(vlo), vhi_e = lane_down(vhi);
-        if (!(t >= 0 && t <= h - 1 && k >= 1 && k <= m - 1)) return T(0);
+        if (!((INNER || (t >= 0 && t <= h - 1)) && k >= 1 && k <= m - 1)) return T(0);
         return MIR ? jac2_chain(cd, rF, vhi, vhi_e, vlo_e, vlo) : jac2_chain(cd, rF, vlo, vlo_e, vhi_e, vhi);
     };
     // C point (2t, k), k even, from the F rows k-1 (Fm) and k+1 (Fp), as jac2_diagC
     auto c21 = [&](int k, T rC, T Fm, T Fp) -> T {
         const T Fm_w = lane_up(Fm), Fp_w = lane_up(Fp);
-        if (!(t >= 1 && t <= h - 1 && k >= 2 && k <= m - 2)) return T(0);
+        if (!((INNER || (t >= 1 && t <= h - 1)) && k >= 2 && k <= m - 2)) return T(0);
         return MIR ? jac2_sum(cd, rC, Fp_w, Fp, Fm, Fm_w) : jac2_sum(cd, rC, Fm_w, Fm, Fp, Fp_w);
     };
     auto fsr = [&](int k, T r1k) -> T { return f21(k, r1k, ld2((k - 1) >> 1), ld2((k + 1) >> 1)); };
@@ -536,15 +538,15 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
         x = y = e = 0;
         if (!colok || k < 0 || k > m) return;
         const auto p = ucg + (size_t)R(k) * w + 2 * t;
-        if (t < h) {
+        if (INNER || t < h) {
             P2<double> v = NT ? ld_pair_nt(p) : ld_pair(p);
             x = v.x;
             y = v.y;
         } else {
             x = p[0];
         }
-        if (lane == 0 && t >= 1) e = p[-1];
-        if (lane == 63 && 2 * t + 2 <= m) e = p[2];
+        if (lane == 0 && (INNER || t >= 1)) e = p[-1];
+        if (lane == 63 && (INNER || 2 * t + 2 <= m)) e = p[2];
     };
     auto ldF = [&](int k, double& x, double& y) {
         x = y = 0;
@@ -682,7 +684,7 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
     double qmx = 0, qmy = 0, qcx = 0, qcy = 0;
     T rm1_0 = 0, rm1_1 = 0, rm2_0 = 0, rm2_1 = 0, d3 = 0, d2 = 0;
     double acc = 0;
-    const bool useful2 = useful && t >= 1 && t <= h - 1;
+    const bool useful2 = useful && (INNER || (t >= 1 && t <= h - 1));
     auto proc = [&](auto Pc, int jj, const Ck& c) {
         constexpr int P = decltype(Pc)::value;   // jj & 1
         if (jj > jend) return;
@@ -713,10 +715,10 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
         const T vw = q ? nb : d0;
         const T ve = q ? d0 : nb;
         const int aF = 2 * t + 1 - q;
-        const T Fj = (aF >= 1 && aF <= m - 1 && jj >= 1 && jj <= m - 1)
+        const T Fj = ((INNER || (aF >= 1 && aF <= m - 1)) && jj >= 1 && jj <= m - 1)
                          ? (MIR ? jac2_sum(cc, rF, vw, dp, ve, dm) : jac2_sum(cc, rF, vw, dm, ve, dp))
                          : T(0);
-        if (jj - 1 >= (RES ? jbeg + 1 : y0)) {
+        {   // the C points of row jj-1 and the update there (written from row y0 on)
             constexpr int qq = 1 - P;
             T sb;
             if constexpr (qq) sb = lane_down(Fm1);
@@ -732,50 +734,48 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
                 // the new iterate's pair of row jj-1 (the old values off the interior)
                 const bool rin = jj - 1 >= 1 && jj - 1 <= m - 1;
                 const double npx = (rin && c0) ? ox + (double)vx : ox, npy = (rin && c1) ? oy + (double)vy : oy;
-                const int k = jj - 2;   // its residual row: u' rows k-1 (q_m), k (q_c), k+1 (np)
-                if (k >= jstart && k <= ylast) {
-                    const double fx = F0x, fy = F0y;
-                    const double uW = lane_up(qcy), uE = lane_down(qcx);
-                    const bool rowin = k >= 1 && k <= m - 1;
-                    double x0 = 0, x1 = 0;
-                    if (rowin && colok) {
-                        if (MIR) resid_pair(inv_h2, fx, fy, uW, npx, npy, qcx, qcy, qmx, qmy, uE, x0, x1);
-                        else resid_pair(inv_h2, fx, fy, uW, qmx, qmy, qcx, qcy, npx, npy, uE, x0, x1);
+                // its residual row k = jj-2 from u' rows k-1 (q_m), k (q_c), k+1 (np).
+                // The pipeline runs from the march's first row on: the rows before
+                // jstart (and after ylast) only pass through its registers and reach
+                // no output (the norm and the stores are guarded), so its state needs
+                // no branch per row.
+                const int k = jj - 2;
+                const double fx = F0x, fy = F0y;
+                const double uW = lane_up(qcy), uE = lane_down(qcx);
+                const bool rowin = k >= 1 && k <= m - 1;
+                double x0, x1;
+                if (MIR) resid_pair(inv_h2, fx, fy, uW, npx, npy, qcx, qcy, qmx, qmy, uE, x0, x1);
+                else resid_pair(inv_h2, fx, fy, uW, qmx, qmy, qcx, qcy, npx, npy, uE, x0, x1);
+                const T r0j = (rowin && c0) ? (T)x0 : T(0), r1j = (rowin && c1) ? (T)x1 : T(0);
+                // the residual kernel's sums: x0^2 + x1^2, or the one interior column's
+                const double s2 = (c0 ? x0 * x0 : 0.0) + (c1 ? x1 * x1 : 0.0);
+                if (k >= y0 && k < y1 && useful) acc += s2;
+                {   // Eq. (Erest2r) at the diagonal point of row k-1, then Eq.
+                    // (Erest2b) onto the axis level below it at even k
+                    constexpr int q = 1 - P;   // (k - 1) & 1, k = jj - 2
+                    T sh;
+                    if constexpr (q) sh = lane_down(rm1_0);
+                    else sh = lane_up(rm1_1);
+                    const T rc = q ? rm1_1 : rm1_0;
+                    const T rw = q ? rm1_0 : sh;
+                    const T re = q ? sh : rm1_1;
+                    const T rlo = q ? rm2_1 : rm2_0;
+                    const T rhi = q ? r1j : r0j;
+                    const T d1 = MIR ? rs2_core(rc, rw, rhi, re, rlo) : rs2_core(rc, rw, rlo, re, rhi);
+                    if (!P && k - 2 >= y0 && k - 2 < y1) {
+                        const int B = (k - 2) >> 1;
+                        const T d3w = lane_up(d3), d1w = lane_up(d1);
+                        if (useful2 && B >= 1 && B <= h - 1)
+                            rA2g[(size_t)(MIR ? h - B : B) * (h + 1) + t] =
+                                MIR ? rs2_core(d2, d1w, d1, d3, d3w) : rs2_core(d2, d3w, d3, d1, d1w);
                     }
-                    const T r0j = (rowin && c0) ? (T)x0 : T(0), r1j = (rowin && c1) ? (T)x1 : T(0);
-                    if (k >= y0 && k < y1 && useful) {
-                        if (c0 && c1) acc += x0 * x0 + x1 * x1;
-                        else if (c1) acc += x1 * x1;
-                        else if (c0) acc += x0 * x0;
-                    }
-                    if (k - 1 >= dlo) {
-                        // Eq. (Erest2r) at the diagonal point of row k-1, then
-                        // Eq. (Erest2b) onto the axis level below it at even k
-                        constexpr int q = 1 - P;   // (k - 1) & 1, k = jj - 2
-                        T sh;
-                        if constexpr (q) sh = lane_down(rm1_0);
-                        else sh = lane_up(rm1_1);
-                        const T rc = q ? rm1_1 : rm1_0;
-                        const T rw = q ? rm1_0 : sh;
-                        const T re = q ? sh : rm1_1;
-                        const T rlo = q ? rm2_1 : rm2_0;
-                        const T rhi = q ? r1j : r0j;
-                        const T d1 = MIR ? rs2_core(rc, rw, rhi, re, rlo) : rs2_core(rc, rw, rlo, re, rhi);
-                        if (!P && k - 2 >= y0 && k - 2 < y1) {
-                            const int B = (k - 2) >> 1;
-                            const T d3w = lane_up(d3), d1w = lane_up(d1);
-                            if (useful2 && B >= 1 && B <= h - 1)
-                                rA2g[(size_t)(MIR ? h - B : B) * (h + 1) + t] =
-                                    MIR ? rs2_core(d2, d1w, d1, d3, d3w) : rs2_core(d2, d3w, d3, d1, d1w);
-                        }
-                        d3 = d2;
-                        d2 = d1;
-                    }
-                    rm2_0 = rm1_0;
-                    rm2_1 = rm1_1;
-                    rm1_0 = r0j;
-                    rm1_1 = r1j;
+                    d3 = d2;
+                    d2 = d1;
                 }
+                rm2_0 = rm1_0;
+                rm2_1 = rm1_1;
+                rm1_0 = r0j;
+                rm1_1 = r1j;
                 qmx = qcx;
                 qmy = qcy;
                 qcx = npx;
@@ -893,12 +893,14 @@ __global__ void __launch_bounds__(kRowBlock) __attribute__((amdgpu_waves_per_eu(
     double* un = odd ? it.ub : it.u;
     double acc = 0;
     if (wv < nwaves) {   // no early return: the block sum below synchronises the block
-        if ((wv / nwx) & 1)
-            acc = fused_body<T, true, false, true, true, true>(m, cc, cd, nullptr, it.v2, nullptr, un, wv, nwx, rows,
-                                                               uc, it.f, it.r2);
-        else
-            acc = fused_body<T, true, false, false, true, true>(m, cc, cd, nullptr, it.v2, nullptr, un, wv, nwx, rows,
-                                                                uc, it.f, it.r2);
+        const int t0 = (wv % nwx) * kResPairs - 4;   // the column pair of lane 0
+        const bool inner = t0 >= 1 && t0 + 63 <= m / 2 - 1;
+        auto run = [&](auto Mc, auto Ic) {
+            return fused_body<T, true, false, decltype(Mc)::value != 0, true, true, decltype(Ic)::value != 0>(
+                m, cc, cd, nullptr, it.v2, nullptr, un, wv, nwx, rows, uc, it.f, it.r2);
+        };
+        if ((wv / nwx) & 1) acc = inner ? run(Int<1>{}, Int<1>{}) : run(Int<1>{}, Int<0>{});
+        else acc = inner ? run(Int<0>{}, Int<1>{}) : run(Int<0>{}, Int<0>{});
     }
     const double sum = rows_block_sum(acc);
     if (threadIdx.x == 0) it.part[blockIdx.x] = sum;
