@@ -686,8 +686,7 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
     double acc = 0;
     const bool useful2 = useful && (INNER || (t >= 1 && t <= h - 1));
     auto proc = [&](auto Pc, int jj, const Ck& c) {
-        constexpr int P = decltype(Pc)::value;   // jj & 1
-        if (jj > jend) return;
+        constexpr int P = decltype(Pc)::value;   // jj & 1 (the march calls it for jj <= jend only)
         T cax = c.ax, cay = c.ay, cbx = c.bx, cby = c.by;   // residual pairs of rows jj+2, jj+3 (odd jj)
         if constexpr (PP) {
             if constexpr (P) {
