@@ -462,6 +462,9 @@ constexpr int kFusePairs = 60;
 // Strips must start on odd rows (an even strip length), as in the residual
 // kernel.  Returns the lane's part of the squared norm.
 constexpr int kResPairs = 57;
+// s_waitcnt operand of a wait for every vector-memory access (vmcnt 0, the
+// export and LDS counts at their maxima; the GFX9 field layout)
+constexpr int kWaitVmem0 = 0xF70;
 // INNER: every lane's column pair t lies in 1 .. m/2 - 1 (a band away from
 // both boundary columns), so every column check holds and folds away.
 template <typename T, bool FINEST, bool NT, bool MIR, bool PP = false, bool RES = false, bool INNER = false>
@@ -685,11 +688,38 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
     T rm1_0 = 0, rm1_1 = 0, rm2_0 = 0, rm2_1 = 0, d3 = 0, d2 = 0;
     double acc = 0;
     const bool useful2 = useful && (INNER || (t >= 1 && t <= h - 1));
+    // The stores of an even row step wait in registers and are issued at the
+    // end of the odd row step that follows.  The odd step's loads go out before
+    // the even step; a store issued after them would have to complete before
+    // the odd step can use them (a wait on the vector-memory count covers
+    // every access issued before the one it needs), so the even step's
+    // arithmetic would no longer hide their latency.  No wave reads what these
+    // stores write while the kernel runs.
+    bool pw = false, pr = false;   // a pending row store / restriction store
+    size_t po = 0, pro = 0;
+    double pux = 0, puy = 0;
+    T pvx = 0, pvy = 0, prv = 0;
+    auto store_row = [&](bool ok, size_t o, double ux, double uy, T vx, T vy) {
+        if (!ok) return;
+        if constexpr (FINEST) {
+            if (c0 && c1) st_pair(ug + o, ux, uy);
+            else if (c1) ug[o + 1] = uy;
+            else if (c0) ug[o] = ux;
+        } else {
+            if (c0 && c1) st_pair(vAg + o, vx, vy);
+            else if (c1) vAg[o + 1] = vy;
+            else if (c0) vAg[o] = vx;
+        }
+    };
     auto proc = [&](auto Pc, int jj, const Ck& c) {
         constexpr int P = decltype(Pc)::value;   // jj & 1 (the march calls it for jj <= jend only)
         T cax = c.ax, cay = c.ay, cbx = c.bx, cby = c.by;   // residual pairs of rows jj+2, jj+3 (odd jj)
         if constexpr (PP) {
             if constexpr (P) {
+                // every load of this row step is needed right here; waiting for
+                // all of them at once, ahead of the step's stores, spares the
+                // loop a wait that would also cover those stores
+                __builtin_amdgcn_s_waitcnt(kWaitVmem0);
                 r0row(jj + 2, w2x, w2y, w3x, w3y, c.u3x, c.u3y, eS, c.f2x, c.f2y, cax, cay);
                 r0row(jj + 3, w3x, w3y, c.u3x, c.u3y, c.u4x, c.u4y, c.e3, c.f3x, c.f3y, cbx, cby);
             }
@@ -761,12 +791,12 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
                     const T rlo = q ? rm2_1 : rm2_0;
                     const T rhi = q ? r1j : r0j;
                     const T d1 = MIR ? rs2_core(rc, rw, rhi, re, rlo) : rs2_core(rc, rw, rlo, re, rhi);
-                    if (!P && k - 2 >= y0 && k - 2 < y1) {
+                    if constexpr (!P) {   // a restriction store, pending (see above)
                         const int B = (k - 2) >> 1;
                         const T d3w = lane_up(d3), d1w = lane_up(d1);
-                        if (useful2 && B >= 1 && B <= h - 1)
-                            rA2g[(size_t)(MIR ? h - B : B) * (h + 1) + t] =
-                                MIR ? rs2_core(d2, d1w, d1, d3, d3w) : rs2_core(d2, d3w, d3, d1, d1w);
+                        pr = k - 2 >= y0 && k - 2 < y1 && useful2 && B >= 1 && B <= h - 1;
+                        pro = (size_t)(MIR ? h - B : B) * (h + 1) + t;
+                        prv = MIR ? rs2_core(d2, d1w, d1, d3, d3w) : rs2_core(d2, d3w, d3, d1, d1w);
                     }
                     d3 = d2;
                     d2 = d1;
@@ -780,16 +810,21 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
                 qcx = npx;
                 qcy = npy;
             }
-            if (useful && (!RES || jj - 1 < y1) && jj - 1 >= y0) {
-                if constexpr (FINEST) {
-                    if (c0 && c1) st_pair(ug + o, ox + (double)vx, oy + (double)vy);
-                    else if (c1) ug[o + 1] = oy + (double)vy;
-                    else if (c0) ug[o] = ox + (double)vx;
-                } else {
-                    if (c0 && c1) st_pair(vAg + o, vx, vy);
-                    else if (c1) vAg[o + 1] = vy;
-                    else if (c0) vAg[o] = vx;
+            const bool wr = useful && (!RES || jj - 1 < y1) && jj - 1 >= y0;
+            if constexpr (!P) {   // pending until the next row step
+                pw = wr;
+                po = o;
+                pux = ox + (double)vx;
+                puy = oy + (double)vy;
+                pvx = vx;
+                pvy = vy;
+            } else {
+                store_row(pw, po, pux, puy, pvx, pvy);
+                store_row(wr, o, ox + (double)vx, oy + (double)vy, vx, vy);
+                if constexpr (RES) {
+                    if (pr) rA2g[pro] = prv;
                 }
+                pw = pr = false;
             }
         }
         Fm2 = Fm1;
@@ -836,6 +871,10 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
         }
     };
     rows_march_parity<Ck>(j, jend, load, proc);
+    store_row(pw, po, pux, puy, pvx, pvy);   // a march that ended on an even row
+    if constexpr (RES) {
+        if (pr) rA2g[pro] = prv;
+    }
     return acc;
 }
 
