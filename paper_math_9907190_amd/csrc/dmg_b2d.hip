@@ -688,17 +688,19 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
     T rm1_0 = 0, rm1_1 = 0, rm2_0 = 0, rm2_1 = 0, d3 = 0, d2 = 0;
     double acc = 0;
     const bool useful2 = useful && (INNER || (t >= 1 && t <= h - 1));
-    // The stores of an even row step wait in registers and are issued at the
-    // end of the odd row step that follows.  The odd step's loads go out before
-    // the even step; a store issued after them would have to complete before
-    // the odd step can use them (a wait on the vector-memory count covers
-    // every access issued before the one it needs), so the even step's
-    // arithmetic would no longer hide their latency.  No wave reads what these
-    // stores write while the kernel runs.
-    bool pw = false, pr = false;   // a pending row store / restriction store
-    size_t po = 0, pro = 0;
-    double pux = 0, puy = 0;
-    T pvx = 0, pvy = 0, prv = 0;
+    // A row step's stores wait in registers and are issued at the start of
+    // the next odd row step, right after its loads have arrived.  The odd
+    // step's loads go out before the even step; a store issued after them
+    // would have to complete before the odd step can use them (a wait on the
+    // vector-memory count covers every access issued before the one it
+    // needs), so the even step's arithmetic would no longer hide their
+    // latency; and stores issued early in the odd step are done before the
+    // loop's next wait.  No wave reads what these stores write while the
+    // kernel runs.
+    bool pw = false, pr = false, qw = false;   // pending: even row, restriction, odd row
+    size_t po = 0, pro = 0, qo = 0;
+    double pux = 0, puy = 0, qux = 0, quy = 0;
+    T pvx = 0, pvy = 0, prv = 0, qvx = 0, qvy = 0;
     auto store_row = [&](bool ok, size_t o, double ux, double uy, T vx, T vy) {
         if (!ok) return;
         if constexpr (FINEST) {
@@ -711,6 +713,14 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
             else if (c0) vAg[o] = vx;
         }
     };
+    auto flush = [&]() {
+        store_row(qw, qo, qux, quy, qvx, qvy);
+        store_row(pw, po, pux, puy, pvx, pvy);
+        if constexpr (RES) {
+            if (pr) rA2g[pro] = prv;
+        }
+        qw = pw = pr = false;
+    };
     auto proc = [&](auto Pc, int jj, const Ck& c) {
         constexpr int P = decltype(Pc)::value;   // jj & 1 (the march calls it for jj <= jend only)
         T cax = c.ax, cay = c.ay, cbx = c.bx, cby = c.by;   // residual pairs of rows jj+2, jj+3 (odd jj)
@@ -720,6 +730,7 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
                 // all of them at once, ahead of the step's stores, spares the
                 // loop a wait that would also cover those stores
                 __builtin_amdgcn_s_waitcnt(kWaitVmem0);
+                flush();
                 r0row(jj + 2, w2x, w2y, w3x, w3y, c.u3x, c.u3y, eS, c.f2x, c.f2y, cax, cay);
                 r0row(jj + 3, w3x, w3y, c.u3x, c.u3y, c.u4x, c.u4y, c.e3, c.f3x, c.f3y, cbx, cby);
             }
@@ -819,12 +830,13 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
                 pvx = vx;
                 pvy = vy;
             } else {
-                store_row(pw, po, pux, puy, pvx, pvy);
-                store_row(wr, o, ox + (double)vx, oy + (double)vy, vx, vy);
-                if constexpr (RES) {
-                    if (pr) rA2g[pro] = prv;
-                }
-                pw = pr = false;
+                if constexpr (!PP) flush();
+                qw = wr;
+                qo = o;
+                qux = ox + (double)vx;
+                quy = oy + (double)vy;
+                qvx = vx;
+                qvy = vy;
             }
         }
         Fm2 = Fm1;
@@ -871,10 +883,7 @@ __device__ inline double fused_body(int m, T cc, T cd, const T* __restrict__ rA,
         }
     };
     rows_march_parity<Ck>(j, jend, load, proc);
-    store_row(pw, po, pux, puy, pvx, pvy);   // a march that ended on an even row
-    if constexpr (RES) {
-        if (pr) rA2g[pro] = prv;
-    }
+    flush();   // the last row steps' stores
     return acc;
 }
 
