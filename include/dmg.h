@@ -125,10 +125,14 @@ int mg_vcycle(mg_plan *plan, double *u, const double *f, double *rel_res_before)
  * nullable, max_cycles+1 doubles): relative residual after 0, 1, ...
  * cycles.  Returns MG_OK, MG_ERR_NOT_CONVERGED, MG_ERR_NONFINITE or
  * MG_ERR_DIVERGED (the last three still fill the outputs).  Synchronises
- * the stream.  A 2D FP64 second-order plan of n >= 128 (mg_setup) runs the
- * cycles out of place: the iterates alternate between u and a workspace
- * array, u holds the result when the call returns, and u's boundary values
- * are read, never written. */
+ * the stream.  A 2D second-order plan of one problem, n >= 128, FP64 or
+ * MG_FP32_REFINED (mg_setup), runs the cycles out of place: the iterates
+ * alternate between u and a workspace array, u holds the result when the call
+ * returns, and u's boundary values are read, never written.  Its finest
+ * kernel also forms the next residual evaluation (the relative residuals then
+ * equal the in-place path's to rounding: the norm's partial sums are grouped
+ * differently); with the environment variable DMG_NO_FUSED_RESIDUAL=1 at
+ * mg_setup the residual kernel runs after each cycle instead. */
 int mg_solve(mg_plan *plan, double *u, const double *f, double rtol, int max_cycles,
              int *cycles_out, double *rel_res_out, double *history);
 
