@@ -53,8 +53,8 @@ namespace dmg {
 // M4: the fourth-order residual of Section 2.3, Eq. (Efos2): f holds the
 // right-hand side combination (8f + 4 neighbours)/12, made once per solve by
 // kb_rhs4, and inv_h2 is 1/(6h^2) for the 9-point operator; the extra
-// diagonal neighbours come from the rows already held, by lane shuffles
-// (its FZ variants run three waves per SIMD in both precisions).
+// diagonal neighbours come from the rows already held, by neighbour-lane
+// reads (its FZ variants run three waves per SIMD in both precisions).
 // WF: the partial sums of f^2 over the same interior points too (the first
 // evaluation of a solve, so that ||f|| needs no pass of its own).
 // MIR (FZ strips of odd index): the strip is marched from its last row to
@@ -442,9 +442,10 @@ constexpr int kFusePairs = 60;
 // passed in the unmirrored order, so the values are the same bits.  Two
 // neighbouring strips then reach the rows they share at the same time (both
 // at their start or both at their end), while those rows are still in L2.
-// PP (FINEST, FP64; out-of-place solves): the axis residual rows are not read
-// but formed from the previous iterate uc and f (Eq. Evpois, the residual
-// kernel's expression: the same bits), and the new iterate uc + v goes to u,
+// PP (FINEST; out-of-place solves, levels of type T, the residual formed in
+// double): the axis residual rows are not read but formed from the previous
+// iterate uc and f (Eq. Evpois, the residual kernel's expression: the same
+// bits, rounded to T as it rounds them), and the new iterate uc + v goes to u,
 // another buffer, so no workgroup ever reads a value another one has
 // updated.  The lane's u pairs of the rows it has loaded stay in registers
 // (five rows) for the update; lanes 0 and 63 also load the one column beyond
@@ -455,10 +456,11 @@ constexpr int kFusePairs = 60;
 // the next evaluation, from the new iterate's rows while they are still in
 // registers.  The residual rows trail the Jacobi rows by two, the march
 // starts three or four rows before the strip's first row and ends three or
-// four rows past its last (the new iterate is formed, not written, there), and a wave owns 57 column
-// pairs, lanes 4 .. 60: the new iterate is right in lanes 2 .. 61, its
-// residual in 3 .. 60, the diagonal restriction in 3 .. 60 and the axis one,
-// which takes the diagonal values of the lane to the west, in 4 .. 60.
+// four rows past its last (the new iterate is formed, not written, there),
+// and a wave owns 57 column pairs, lanes 4 .. 60: the new iterate is right in
+// lanes 2 .. 61, its residual in 3 .. 60, the diagonal restriction in 3 .. 60
+// and the axis one, which takes the diagonal values of the lane to the west,
+// in 4 .. 60.
 // Strips must start on odd rows (an even strip length), as in the residual
 // kernel.  Returns the lane's part of the squared norm.
 constexpr int kResPairs = 57;
