@@ -141,8 +141,11 @@ __device__ inline void resid_body(int m, double inv_h2, const Fin2<T>& it, const
     auto proc_p = [&](int jb, const Ck& c, auto P0) {
         static_for<0, CH>([&](auto I) {
             constexpr int i = decltype(I)::value;
+            // rows of the last chunk past ylast are computed too: every output
+            // below is guarded by its row range, and without an early exit per
+            // row the compiler keeps the row window in place instead of
+            // copying it on every row
             const int j = jb + i;
-            if (j > ylast) return;
             bool rowin = j >= 1 && j <= m - 1;
             double uW = lane_up(uc1);   // u(2t-1, j)
             double uE = lane_down(uc0); // u(2t+2, j)
