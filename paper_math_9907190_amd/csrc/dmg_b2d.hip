@@ -1101,8 +1101,7 @@ __global__ void __launch_bounds__(kRowBlock) kb_rs_pair(int m, const RsPair2<T>*
     auto proc = [&](int jb, const Ck& c) {
         static_for<0, CH>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            const int j = jb + i;
-            if (j > y1) return;
+            const int j = jb + i;   // past y1 too (the store below is guarded)
             constexpr int q = (i + 1) & 1;
             T sh;
             if constexpr (q) sh = lane_down(rc0);
