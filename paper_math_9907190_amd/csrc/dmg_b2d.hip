@@ -900,8 +900,19 @@ __global__ void __launch_bounds__(kRowBlock) kb_finest_fused(int m, T cc, T cd, 
     ITEM_GATE(ctls, it.prob);
     const int wv = rows_wave_id(nwaves);
     if (wv >= nwaves) return;
-    if ((wv / nwx) & 1) fused_body<T, true, NT, true>(m, cc, cd, it.r0, it.v2, nullptr, it.u, wv, nwx, rows);
-    else fused_body<T, true, NT, false>(m, cc, cd, it.r0, it.v2, nullptr, it.u, wv, nwx, rows);
+    const int t0 = (wv % nwx) * kFusePairs - 2;   // the column pair of lane 0
+    const bool inner = t0 >= 1 && t0 + 63 <= m / 2 - 1;
+    auto run = [&](auto Mc, auto Ic) {
+        fused_body<T, true, NT, decltype(Mc)::value != 0, false, false, decltype(Ic)::value != 0>(
+            m, cc, cd, it.r0, it.v2, nullptr, it.u, wv, nwx, rows);
+    };
+    if ((wv / nwx) & 1) {
+        if (inner) run(Int<1>{}, Int<1>{});
+        else run(Int<1>{}, Int<0>{});
+    } else {
+        if (inner) run(Int<0>{}, Int<1>{});
+        else run(Int<0>{}, Int<0>{});
+    }
 }
 
 // Out-of-place solve step (one FP64 problem): cycle k (the control block's
